@@ -1,0 +1,466 @@
+"""FP64 CPU oracle for lAIR (arXiv:1708.06065).
+
+TEST INFRASTRUCTURE ONLY: this module is the reference the GPU library is
+checked against.  Only tests, the smoke check and the benchmark's CPU-baseline
+leg may import it; the solver library never does, and the two share no code.
+
+The heavy per-row loops (strength, Ruge-Stueben split, neighbourhoods, local
+solves, interpolation, sparse products) are in ``lair_oracle.c``; this module
+strings them together in the paper's order and adds the parts that are plain
+library calls (SciPy sparse products with vectors, a dense LU for the
+coarsest grid, minimal-norm least squares for singular local systems).
+
+Steps and where the paper defines them:
+  strength          Sec. 4 (strong neighbourhood with a hard minimum)
+  rs_split          Sec. 4 (classical CF splitting, first pass only)
+  neighbourhoods    Sec. 3.1 (distance-one or -two strong F-neighbours) and
+                    Sec. 4 (F-F-C paths only at distance two)
+  local_solves      Sec. 3.1, Eq. (johnair) / Eq. (system) and its footnote
+  restriction       Eq. (PR): R = [Z I]
+  interp_one_point  Sec. 4 (one-point interpolation)
+  interp_direct     classical direct interpolation (Stueben 2001) as a
+                    stand-in for the classical formulas cited in Sec. 4
+  galerkin          Sec. 2.1: K = R A P
+  block_scale       Sec. 4.2.1: D_B^{-1} A with the element block diagonal
+  cycle             Sec. 2.1 coarse-grid correction followed by F-F-C Jacobi
+                    (Sec. 4, relaxation paragraph; Eq. (jacobi_err))
+  solve             stationary iteration on the V-cycle to a relative
+                    residual tolerance
+  cycle_transpose   the exact adjoint of ``cycle`` (for gradients)
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import build as _build
+
+SOC_ABS, SOC_NEG = 0, 1
+DIST_ALL_F = 0
+INTERP_ONE_POINT, INTERP_DIRECT = 0, 1
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.orc_strength.argtypes = [i64, P, P, P, f64, i32, P]
+        L.orc_strength.restype = None
+        L.orc_rs_split.argtypes = [i64, P, P, P, P]
+        L.orc_rs_split.restype = i32
+        L.orc_nbr_count.argtypes = [i64, P, P, P, P, i32, i64, P, P]
+        L.orc_nbr_count.restype = i32
+        L.orc_nbr_fill.argtypes = [i64, P, P, P, P, i32, i64, P, P, P]
+        L.orc_nbr_fill.restype = i32
+        L.orc_local_solves.argtypes = [P, P, P, i64, P, P, P, P, P]
+        L.orc_local_solves.restype = i32
+        L.orc_interp_one_point.argtypes = [i64, P, P, P, P, P, P, P]
+        L.orc_interp_one_point.restype = None
+        L.orc_interp_direct.argtypes = [i64, P, P, P, P, P, P, i32, P, P, P]
+        L.orc_interp_direct.restype = None
+        L.orc_spgemm_count.argtypes = [i64, i64, P, P, P, P, P]
+        L.orc_spgemm_count.restype = i32
+        L.orc_spgemm_fill.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P]
+        L.orc_spgemm_fill.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def csr(rowptr, col, val, shape=None):
+    """scipy CSR from raw arrays, keeping every stored entry (even zeros)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    n = rowptr.shape[0] - 1
+    if shape is None:
+        shape = (n, n)
+    m = sp.csr_matrix((np.ascontiguousarray(val, dtype=np.float64),
+                       np.ascontiguousarray(col, dtype=np.int32), rowptr),
+                      shape=shape)
+    return m
+
+
+def _arrays(A):
+    return (np.ascontiguousarray(A.indptr, dtype=np.int32),
+            np.ascontiguousarray(A.indices, dtype=np.int32),
+            np.ascontiguousarray(A.data, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Setup steps
+# --------------------------------------------------------------------------
+
+def strength(A, theta=0.25, kind=SOC_ABS):
+    """Strong-connection mask over A's stored entries (uint8[nnz])."""
+    rp, cj, vx = _arrays(A)
+    smask = np.zeros(cj.shape[0], dtype=np.uint8)
+    lib().orc_strength(A.shape[0], _p(rp), _p(cj), _p(vx), float(theta),
+                       int(kind), _p(smask))
+    return smask
+
+
+def rs_split(A, smask):
+    """Classical Ruge-Stueben first pass: int8[n], 1 = C, 0 = F."""
+    rp, cj, _ = _arrays(A)
+    cf = np.zeros(A.shape[0], dtype=np.int8)
+    st = lib().orc_rs_split(A.shape[0], _p(rp), _p(cj),
+                            _p(np.ascontiguousarray(smask, dtype=np.uint8)),
+                            _p(cf))
+    if st != 0:
+        raise MemoryError("rs_split")
+    return cf
+
+
+def coarse_index(cf):
+    """C-points numbered in increasing fine index; -1 for F-points."""
+    cf = np.asarray(cf)
+    cidx = np.full(cf.shape[0], -1, dtype=np.int32)
+    cpts = np.flatnonzero(cf == 1).astype(np.int32)
+    cidx[cpts] = np.arange(cpts.shape[0], dtype=np.int32)
+    return cidx, cpts
+
+
+def neighbourhoods(A, smask, cf, distance=1):
+    """Sorted restriction neighbourhoods N_i of every C-point.
+
+    Returns (cpts, nptr int64[nc+1], nbr int32[sum S_i]).
+    """
+    rp, cj, _ = _arrays(A)
+    cf = np.ascontiguousarray(cf, dtype=np.int8)
+    smask = np.ascontiguousarray(smask, dtype=np.uint8)
+    _, cpts = coarse_index(cf)
+    nc = cpts.shape[0]
+    cnt = np.zeros(nc, dtype=np.int64)
+    L = lib()
+    L.orc_nbr_count(A.shape[0], _p(rp), _p(cj), _p(smask), _p(cf),
+                    int(distance), nc, _p(cpts), _p(cnt))
+    nptr = np.zeros(nc + 1, dtype=np.int64)
+    np.cumsum(cnt, out=nptr[1:])
+    nbr = np.zeros(max(int(nptr[-1]), 1), dtype=np.int32)
+    L.orc_nbr_fill(A.shape[0], _p(rp), _p(cj), _p(smask), _p(cf),
+                   int(distance), nc, _p(cpts), _p(nptr), _p(nbr))
+    return cpts, nptr, nbr[:nptr[-1]]
+
+
+def local_system(A, i, nb):
+    """Dense M = A(N,N)^T and f = -A(i,N)^T of Eq. (system) for one C-point."""
+    sub = A[nb][:, nb].toarray()
+    M = sub.T.copy()
+    f = -A[i][:, nb].toarray().ravel()
+    return M, f
+
+
+def local_solves(A, cpts, nptr, nbr):
+    """Solve every local system; singular ones by minimal-norm least squares.
+
+    Returns (z float64[sum S_i], flags int8[nc]) with flag 1 where the
+    least-squares fallback was taken.
+    """
+    rp, cj, vx = _arrays(A)
+    nc = cpts.shape[0]
+    z = np.zeros(max(int(nptr[-1]), 1), dtype=np.float64)
+    flag = np.zeros(max(nc, 1), dtype=np.int8)
+    nb = np.ascontiguousarray(nbr if nbr.shape[0] else np.zeros(1, np.int32),
+                              dtype=np.int32)
+    st = lib().orc_local_solves(_p(rp), _p(cj), _p(vx), nc,
+                                _p(np.ascontiguousarray(cpts, np.int32)),
+                                _p(np.ascontiguousarray(nptr, np.int64)),
+                                _p(nb), _p(z), _p(flag))
+    if st != 0:
+        raise MemoryError("local_solves")
+    flag = flag[:nc]
+    for c in np.flatnonzero(flag):
+        nbc = nbr[nptr[c]:nptr[c + 1]]
+        M, f = local_system(A, int(cpts[c]), nbc)
+        z[nptr[c]:nptr[c + 1]] = np.linalg.lstsq(M, f, rcond=None)[0]
+    return z[:nptr[-1]], flag
+
+
+def restriction(n, cpts, nptr, nbr, z):
+    """R = [Z I]: row c holds z on N_c and 1 at the C-point, sorted columns."""
+    nc = cpts.shape[0]
+    rows = np.concatenate([np.repeat(np.arange(nc), np.diff(nptr)),
+                           np.arange(nc)])
+    cols = np.concatenate([nbr.astype(np.int64), cpts.astype(np.int64)])
+    vals = np.concatenate([z, np.ones(nc)])
+    order = np.lexsort((cols, rows))
+    rowptr = np.zeros(nc + 1, dtype=np.int32)
+    np.cumsum(np.bincount(rows, minlength=nc), out=rowptr[1:])
+    return csr(rowptr, cols[order], vals[order], shape=(nc, n))
+
+
+def interp_one_point(A, smask, cf):
+    rp, cj, vx = _arrays(A)
+    cidx, cpts = coarse_index(cf)
+    n = A.shape[0]
+    pcol = np.zeros(n, dtype=np.int32)
+    lib().orc_interp_one_point(n, _p(rp), _p(cj), _p(vx),
+                               _p(np.ascontiguousarray(smask, np.uint8)),
+                               _p(np.ascontiguousarray(cf, np.int8)),
+                               _p(cidx), _p(pcol))
+    has = pcol >= 0
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(has, out=rowptr[1:])
+    return csr(rowptr, pcol[has], np.ones(int(has.sum())),
+               shape=(n, cpts.shape[0]))
+
+
+def interp_direct(A, smask, cf):
+    rp, cj, vx = _arrays(A)
+    cidx, cpts = coarse_index(cf)
+    n = A.shape[0]
+    L = lib()
+    args = (n, _p(rp), _p(cj), _p(vx),
+            _p(np.ascontiguousarray(smask, np.uint8)),
+            _p(np.ascontiguousarray(cf, np.int8)), _p(cidx))
+    pptr = np.zeros(n + 1, dtype=np.int64)
+    dummy_i = np.zeros(1, np.int32)
+    dummy_d = np.zeros(1, np.float64)
+    L.orc_interp_direct(*args, 0, _p(pptr), _p(dummy_i), _p(dummy_d))
+    np.cumsum(pptr, out=pptr)
+    nnz = int(pptr[-1])
+    pcol = np.zeros(max(nnz, 1), np.int32)
+    pval = np.zeros(max(nnz, 1), np.float64)
+    L.orc_interp_direct(*args, 1, _p(pptr), _p(pcol), _p(pval))
+    return csr(pptr.astype(np.int32), pcol[:nnz], pval[:nnz],
+               shape=(n, cpts.shape[0]))
+
+
+def spgemm(A, B):
+    """C = A B with the symbolic pattern (no value-based dropping)."""
+    m = A.shape[0]
+    nb = B.shape[1]
+    ap = np.ascontiguousarray(A.indptr, np.int64)
+    aj = np.ascontiguousarray(A.indices, np.int32)
+    ax = np.ascontiguousarray(A.data, np.float64)
+    bp = np.ascontiguousarray(B.indptr, np.int64)
+    bj = np.ascontiguousarray(B.indices, np.int32)
+    bx = np.ascontiguousarray(B.data, np.float64)
+    if aj.shape[0] == 0:
+        aj = np.zeros(1, np.int32); ax = np.zeros(1)
+    if bj.shape[0] == 0:
+        bj = np.zeros(1, np.int32); bx = np.zeros(1)
+    cnt = np.zeros(m, np.int64)
+    L = lib()
+    L.orc_spgemm_count(m, nb, _p(ap), _p(aj), _p(bp), _p(bj), _p(cnt))
+    cp = np.zeros(m + 1, np.int64)
+    np.cumsum(cnt, out=cp[1:])
+    nnz = int(cp[-1])
+    cj = np.zeros(max(nnz, 1), np.int32)
+    cx = np.zeros(max(nnz, 1), np.float64)
+    L.orc_spgemm_fill(m, nb, _p(ap), _p(aj), _p(ax), _p(bp), _p(bj), _p(bx),
+                      _p(cp), _p(cj), _p(cx))
+    return csr(cp.astype(np.int32), cj[:nnz], cx[:nnz], shape=(m, nb))
+
+
+def galerkin(R, A, P):
+    """K = R (A P), symbolic pattern."""
+    return spgemm(R, spgemm(A, P))
+
+
+def block_scale(A, b, k):
+    """D_B^{-1} A and D_B^{-1} b for the k x k diagonal blocks (Sec. 4.2.1).
+
+    Each block row is multiplied by the inverse of its diagonal block; the
+    product keeps the symbolic pattern, so every row of a block carries the
+    union of that block row's columns.
+    """
+    n = A.shape[0]
+    assert n % k == 0
+    nb = n // k
+    D = np.zeros((nb, k, k))
+    Ac = A.tocoo()
+    r, c = Ac.row, Ac.col
+    inblk = (r // k) == (c // k)
+    D[r[inblk] // k, r[inblk] % k, c[inblk] % k] = Ac.data[inblk]
+    Dinv = np.linalg.inv(D)
+    rowptr = np.arange(0, n * k + 1, k, dtype=np.int32)
+    col = (np.repeat(np.arange(nb) * k, k * k) +
+           np.tile(np.arange(k), nb * k)).astype(np.int32)
+    Bd = csr(rowptr, col, Dinv.reshape(-1), shape=(n, n))
+    bs = np.einsum("eij,ej->ei", Dinv, np.asarray(b).reshape(nb, k)).ravel()
+    return spgemm(Bd, A), bs
+
+
+# --------------------------------------------------------------------------
+# Hierarchy
+# --------------------------------------------------------------------------
+
+class Level:
+    pass
+
+
+class Hierarchy:
+    def __init__(self):
+        self.levels = []
+        self.coarse_lu = None
+
+    @property
+    def nlevels(self):
+        return len(self.levels)
+
+    def op_complexity(self):
+        return sum(l.A.nnz for l in self.levels) / self.levels[0].A.nnz
+
+    def cycle_complexity(self):
+        """Work units per V-cycle; one WU = one SpMV with A_0 (2 nnz flops)."""
+        wu = 2.0 * self.levels[0].A.nnz
+        flops = 0.0
+        for l in self.levels[:-1]:
+            nf = l.A.indptr[1:] - l.A.indptr[:-1]
+            nnz_f = float(nf[l.cf == 0].sum())
+            nnz_c = float(nf[l.cf == 1].sum())
+            flops += 2.0 * l.A.nnz                    # residual
+            flops += 2.0 * l.R.nnz + 2.0 * l.P.nnz    # restrict, interpolate
+            flops += 2.0 * (2.0 * nnz_f + nnz_c)      # F, F, C Jacobi
+        nL = self.levels[-1].A.shape[0]
+        flops += 2.0 * nL * nL                        # coarsest triangular solves
+        return flops / wu
+
+
+def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
+          distance=1, interp=INTERP_ONE_POINT, max_levels=25, max_coarse=128,
+          stall=0.9):
+    """Build the lAIR hierarchy.
+
+    cf_levels: optional list of per-level CF splits (int8 arrays, 1 = C);
+    levels beyond the list use the Ruge-Stueben first pass.
+    Coarsening stops when n <= max_coarse, when max_levels is reached, when
+    no C-point is found, or when n_c > stall * n.
+    """
+    if theta_c is None:
+        theta_c = theta
+    H = Hierarchy()
+    Al = A.tocsr()
+    lvl = 0
+    while True:
+        L = Level()
+        L.A = Al
+        n = Al.shape[0]
+        H.levels.append(L)
+        if n <= max_coarse or lvl + 1 >= max_levels:
+            break
+        L.smask = strength(Al, theta, kind)
+        if cf_levels is not None and lvl < len(cf_levels):
+            cf = np.ascontiguousarray(cf_levels[lvl], dtype=np.int8)
+        else:
+            sm_c = L.smask if theta_c == theta else strength(Al, theta_c, kind)
+            cf = rs_split(Al, sm_c)
+        nc = int((cf == 1).sum())
+        if nc == 0 or nc > stall * n:
+            del L.smask
+            break
+        L.cf = cf
+        L.cidx, L.cpts = coarse_index(cf)
+        cpts, L.nptr, L.nbr = neighbourhoods(Al, L.smask, cf, distance)
+        L.z, L.flags = local_solves(Al, cpts, L.nptr, L.nbr)
+        L.R = restriction(n, cpts, L.nptr, L.nbr, L.z)
+        if interp == INTERP_ONE_POINT:
+            L.P = interp_one_point(Al, L.smask, cf)
+        else:
+            L.P = interp_direct(Al, L.smask, cf)
+        L.AP = spgemm(Al, L.P)
+        Al = spgemm(L.R, L.AP)
+        lvl += 1
+    last = H.levels[-1]
+    last.cf = None
+    H.coarse_lu = sla.lu_factor(last.A.toarray())
+    return H
+
+
+def _jacobi(A, diag, b, x, rows, omega=1.0):
+    """One Jacobi sweep restricted to ``rows``; every row reads the old x."""
+    r = b[rows] - A[rows] @ x
+    y = x.copy()
+    y[rows] = x[rows] + omega * r / diag[rows]
+    return y
+
+
+def cycle(H, b, x, lvl=0, omega=1.0):
+    """One V-cycle: coarse-grid correction, then F, F, C Jacobi sweeps."""
+    L = H.levels[lvl]
+    if lvl == H.nlevels - 1:
+        return sla.lu_solve(H.coarse_lu, b)
+    A = L.A
+    r = b - A @ x
+    bc = L.R @ r
+    xc = cycle(H, bc, np.zeros(bc.shape[0]), lvl + 1, omega)
+    x = x + L.P @ xc
+    diag = A.diagonal()
+    F = np.flatnonzero(L.cf == 0)
+    C = np.flatnonzero(L.cf == 1)
+    x = _jacobi(A, diag, b, x, F, omega)
+    x = _jacobi(A, diag, b, x, F, omega)
+    x = _jacobi(A, diag, b, x, C, omega)
+    return x
+
+
+def solve(H, b, x0=None, rtol=1e-10, maxit=200, omega=1.0):
+    """Stationary V-cycle iteration until ||b - A x|| <= rtol ||b||.
+
+    Returns (x, iterations, residual-norm history).
+    """
+    A = H.levels[0].A
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    nb = np.linalg.norm(b)
+    hist = [np.linalg.norm(b - A @ x)]
+    it = 0
+    while hist[-1] > rtol * nb and it < maxit:
+        x = cycle(H, b, x, 0, omega)
+        it += 1
+        hist.append(np.linalg.norm(b - A @ x))
+    return x, it, np.array(hist)
+
+
+# --------------------------------------------------------------------------
+# Adjoint: the exact transpose of the V-cycle map x <- x + B (b - A x).
+# B^T applies, per level, Jacobi C, F, F on A^T (same diagonal), restricts
+# with P^T, recurses on K^T and interpolates with R^T.
+# --------------------------------------------------------------------------
+
+def cycle_transpose(H, g, lam, lvl=0, omega=1.0):
+    L = H.levels[lvl]
+    if lvl == H.nlevels - 1:
+        return sla.lu_solve(H.coarse_lu, g, trans=1)
+    At = L.A.T.tocsr()
+    diag = L.A.diagonal()
+    F = np.flatnonzero(L.cf == 0)
+    C = np.flatnonzero(L.cf == 1)
+    lam = _jacobi(At, diag, g, lam, C, omega)
+    lam = _jacobi(At, diag, g, lam, F, omega)
+    lam = _jacobi(At, diag, g, lam, F, omega)
+    r = g - At @ lam
+    gc = L.P.T @ r
+    lc = cycle_transpose(H, gc, np.zeros(gc.shape[0]), lvl + 1, omega)
+    return lam + L.R.T @ lc
+
+
+def solve_transpose(H, g, rtol=1e-10, maxit=200, omega=1.0):
+    At = H.levels[0].A.T.tocsr()
+    lam = np.zeros_like(g)
+    ng = np.linalg.norm(g)
+    hist = [np.linalg.norm(g - At @ lam)]
+    it = 0
+    while hist[-1] > rtol * ng and it < maxit:
+        lam = cycle_transpose(H, g, lam, 0, omega)
+        it += 1
+        hist.append(np.linalg.norm(g - At @ lam))
+    return lam, it, np.array(hist)
+
+
+def convergence_factor(hist):
+    """Geometric mean residual reduction per iteration."""
+    k = len(hist) - 1
+    if k <= 0 or hist[0] == 0:
+        return 0.0
+    return float((hist[-1] / hist[0]) ** (1.0 / k))

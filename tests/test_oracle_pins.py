@@ -1,0 +1,563 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: every expected value
+comes from a hand trace, a closed form, a dense re-derivation with NumPy, or
+an independent brute-force implementation written here.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import lair as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.split()
+    return out
+
+
+def _mat(w):
+    return O.csr(w["rowptr"], w["col"], w["val"])
+
+
+# ---------------------------------------------------------------- brute force
+
+def brute_strength(A, theta, kind):
+    """Strong sets from a dense copy, written independently of the oracle."""
+    D = A.toarray()
+    n = D.shape[0]
+    S = []
+    for i in range(n):
+        off = [abs(D[i, k]) for k in range(n) if k != i]
+        m = max(off) if off else 0.0
+        s = set()
+        for j in range(n):
+            if j == i or D[i, j] == 0.0 or m <= 0.0:
+                continue
+            a = -D[i, j] if kind == O.SOC_NEG else abs(D[i, j])
+            if a >= theta * m:
+                s.add(j)
+        S.append(s)
+    return S
+
+
+def brute_rs(S):
+    """Ruge-Stueben first pass by linear scans over sets (no tree)."""
+    n = len(S)
+    ST = [set() for _ in range(n)]
+    for i in range(n):
+        for j in S[i]:
+            ST[j].add(i)
+    lam = [len(ST[i]) for i in range(n)]
+    state = [None] * n
+    for i in range(n):
+        if not S[i] and not ST[i]:
+            state[i] = 0
+    while True:
+        U = [i for i in range(n) if state[i] is None]
+        if not U:
+            break
+        best = max(U, key=lambda i: (lam[i], -i))
+        if lam[best] == 0:
+            for i in U:
+                state[i] = 0
+            break
+        state[best] = 1
+        for j in sorted(ST[best]):
+            if state[j] is None:
+                state[j] = 0
+                for k in S[j]:
+                    if state[k] is None:
+                        lam[k] += 1
+        for j in S[best]:
+            if state[j] is None:
+                lam[j] -= 1
+    return np.array(state, dtype=np.int8)
+
+
+def brute_nbr(S, cf, i, distance):
+    F = {j for j in range(len(cf)) if cf[j] == 0}
+    if distance == 0:
+        return sorted(F)
+    d1 = S[i] & F
+    out = set(d1)
+    if distance == 2:
+        for j in d1:
+            out |= S[j] & F
+    return sorted(out)
+
+
+def smask_to_sets(A, smask):
+    S = []
+    for i in range(A.shape[0]):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        S.append({int(A.indices[p]) for p in range(lo, hi) if smask[p]})
+    return S
+
+
+# ---------------------------------------------------------------- O1 strength
+
+def test_strength_c1_hand_values():
+    """C1 interior rows: |a_W|/max = 1 and |a_S|/max = tan(3pi/16) >= 0.25."""
+    w = W.workload_c1()
+    A = _mat(w)
+    sm = O.strength(A, 0.25, O.SOC_ABS)
+    cnt = np.add.reduceat(sm.astype(np.int64), A.indptr[:-1]) * (np.diff(A.indptr) > 0)
+    m = 64
+    i = np.arange(m * m) % m
+    j = np.arange(m * m) // m
+    assert math.tan(3 * math.pi / 16) >= 0.25
+    assert cnt[0] == 0
+    assert np.all(cnt[(i > 0) & (j > 0)] == 2)
+    assert np.all(cnt[(i == 0) & (j > 0)] == 1)
+    assert np.all(cnt[(i > 0) & (j == 0)] == 1)
+
+
+@pytest.mark.parametrize("kind", [O.SOC_ABS, O.SOC_NEG])
+@pytest.mark.parametrize("theta", [0.1, 0.25, 0.6])
+def test_strength_vs_bruteforce(kind, theta):
+    rng = np.random.default_rng(7)
+    D = rng.standard_normal((30, 30)) * (rng.uniform(size=(30, 30)) < 0.2)
+    D[np.arange(30), np.arange(30)] = 5.0
+    D[3, :] = 0.0
+    D[3, 3] = 1.0                      # a row with no off-diagonal: no strong
+    A = sp.csr_matrix(D)
+    A.sort_indices()
+    sm = O.strength(A, theta, kind)
+    assert smask_to_sets(A, sm) == brute_strength(A, theta, kind)
+
+
+def test_strength_keeps_explicit_zero_weak():
+    A = O.csr(np.array([0, 2, 4]), np.array([0, 1, 0, 1]),
+              np.array([2.0, 0.0, -1.0, 3.0]))
+    sm = O.strength(A, 0.25)
+    assert sm.tolist() == [0, 0, 1, 0]
+
+
+# ---------------------------------------------------------------- O2 RS split
+
+def test_rs_chain_hand_trace():
+    g = _read_golden("chain5.txt")
+    A = _mat(W.chain_1d(5))
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    assert cf.tolist() == [int(v) for v in g["cf"]]
+    cnt = [int(sm[A.indptr[i]:A.indptr[i + 1]].sum()) for i in range(5)]
+    assert cnt == [int(v) for v in g["strong_per_row"]]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_rs_vs_bruteforce(seed):
+    w = W.random_ff_digraph(40, 3, seed)
+    A = _mat(w)
+    sm = O.strength(A, 0.25)
+    S = smask_to_sets(A, sm)
+    assert O.rs_split(A, sm).tolist() == brute_rs(S).tolist()
+
+
+def test_rs_small_grid_vs_bruteforce():
+    w = W.adr_2d(9, 1e-2, 0.3, 0.5)
+    A = _mat(w)
+    sm = O.strength(A, 0.25)
+    assert O.rs_split(A, sm).tolist() == brute_rs(smask_to_sets(A, sm)).tolist()
+
+
+# ---------------------------------------------------------------- O3 N_i
+
+@pytest.mark.parametrize("distance", [0, 1, 2])
+@pytest.mark.parametrize("seed", range(5))
+def test_neighbourhoods_vs_bruteforce(distance, seed):
+    w = W.random_ff_digraph(35, 4, seed + 100)
+    A = _mat(w)
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, distance)
+    S = smask_to_sets(A, sm)
+    for c, i in enumerate(cpts):
+        got = nbr[nptr[c]:nptr[c + 1]].tolist()
+        assert got == brute_nbr(S, cf, int(i), distance)
+
+
+def test_neighbourhoods_chain():
+    g = _read_golden("chain5.txt")
+    A = _mat(W.chain_1d(5))
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, 1)
+    assert nptr.tolist() == [int(v) for v in g["nbr_ptr"]]
+    assert nbr.tolist() == [int(v) for v in g["nbr"]]
+
+
+# ---------------------------------------------------------------- O4-O5 Z
+
+def _ideal_Z(A, cf):
+    D = A.toarray()
+    F = np.flatnonzero(cf == 0)
+    C = np.flatnonzero(cf == 1)
+    return -D[np.ix_(C, F)] @ np.linalg.inv(D[np.ix_(F, F)]), F, C
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_all_f_neighbourhood_gives_ideal_restriction(seed):
+    """N_i = all F-points makes Z = -A_cf A_ff^{-1} exactly (Eq. r_ideal)."""
+    w = W.random_ff_digraph(60, 4, seed + 200)
+    A = _mat(w)
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, O.DIST_ALL_F)
+    z, flags = O.local_solves(A, cpts, nptr, nbr)
+    R = O.restriction(A.shape[0], cpts, nptr, nbr, z).toarray()
+    Zi, F, C = _ideal_Z(A, cf)
+    assert flags.sum() == 0
+    assert np.abs(R[:, F] - Zi).max() <= 1e-12 * max(1.0, np.abs(Zi).max())
+    assert np.array_equal(R[:, C], np.eye(C.shape[0]))
+
+
+def test_ideal_restriction_on_small_transport():
+    w = W.upwind_transport_2d(12)
+    A = _mat(w)
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, O.DIST_ALL_F)
+    z, _ = O.local_solves(A, cpts, nptr, nbr)
+    R = O.restriction(A.shape[0], cpts, nptr, nbr, z).toarray()
+    Zi, F, C = _ideal_Z(A, cf)
+    assert np.abs(R[:, F] - Zi).max() <= 1e-12 * np.abs(Zi).max()
+
+
+@pytest.mark.parametrize("distance", [1, 2])
+@pytest.mark.parametrize("case", ["adr", "dg"])
+def test_RA_vanishes_on_neighbourhood(distance, case):
+    """Eq. (johnair): (Z A_ff + A_cf)(i, N_i) = 0, i.e. (R A)(i, N_i) = 0."""
+    if case == "adr":
+        A = _mat(W.adr_2d(14, 1e-2, 0.7, 0.3))
+    else:
+        w = W.upwind_dg_p2(6)
+        A, _ = O.block_scale(_mat(w), w["rhs"], 6)
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, distance)
+    z, flags = O.local_solves(A, cpts, nptr, nbr)
+    R = O.restriction(A.shape[0], cpts, nptr, nbr, z)
+    RA = (R @ A).toarray()
+    scale = (abs(R) @ abs(A)).toarray()
+    for c in range(cpts.shape[0]):
+        nb = nbr[nptr[c]:nptr[c + 1]]
+        if nb.shape[0]:
+            assert np.all(np.abs(RA[c, nb]) <= 1e-12 * scale[c, nb] + 1e-300)
+
+
+def test_local_solves_vs_numpy():
+    A = _mat(W.adr_2d(12, 1e-1, 2.0, 0.1))
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, 2)
+    z, flags = O.local_solves(A, cpts, nptr, nbr)
+    D = A.toarray()
+    for c, i in enumerate(cpts):
+        nb = nbr[nptr[c]:nptr[c + 1]]
+        if not nb.shape[0]:
+            continue
+        M = D[np.ix_(nb, nb)].T
+        f = -D[i, nb]
+        ref = np.linalg.solve(M, f)
+        assert np.abs(z[nptr[c]:nptr[c + 1]] - ref).max() <= 1e-12 * max(1, np.abs(ref).max())
+
+
+def test_singular_local_system_takes_min_norm_lstsq():
+    """Footnote of Sec. 3.1: a singular local system is solved as a
+    minimal-norm least-squares problem.  Rows 1 and 2 are identical, so the
+    local matrix of C-point 0 (N = {1, 2}) is singular; a_22 is a stored
+    zero."""
+    A = O.csr(np.array([0, 3, 5, 8, 9]), np.array([0, 1, 2, 1, 3, 1, 2, 3, 3]),
+              np.array([4.0, -1.0, -1.0, 1.0, -1.0, 1.0, 0.0, -1.0, 2.0]))
+    cf = np.array([1, 0, 0, 1], dtype=np.int8)
+    cpts = np.array([0, 3], dtype=np.int32)
+    nptr = np.array([0, 2, 2], dtype=np.int64)
+    nbr = np.array([1, 2], dtype=np.int32)
+    z, flags = O.local_solves(A, cpts, nptr, nbr)
+    assert flags.tolist() == [1, 0]
+    M = np.array([[1.0, 1.0], [0.0, 0.0]])      # A(N,N)^T
+    f = np.array([1.0, 1.0])
+    assert np.allclose(z, np.linalg.pinv(M) @ f, rtol=0, atol=1e-14)
+
+
+def test_chain_z_is_one():
+    g = _read_golden("chain5.txt")
+    A = _mat(W.chain_1d(5))
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, 1)
+    z, _ = O.local_solves(A, cpts, nptr, nbr)
+    assert z.tolist() == [float(v) for v in g["z"]]
+    R = O.restriction(5, cpts, nptr, nbr, z)
+    assert R.indptr.tolist() == [int(v) for v in g["R_rowptr"]]
+    assert R.indices.tolist() == [int(v) for v in g["R_col"]]
+    assert R.data.tolist() == [float(v) for v in g["R_val"]]
+
+
+# ---------------------------------------------------------------- O6-O8 P, K
+
+def test_one_point_interp_chain_and_strongest():
+    g = _read_golden("chain5.txt")
+    A = _mat(W.chain_1d(5))
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    P = O.interp_one_point(A, sm, cf)
+    want = [int(v) for v in g["P_one_point_col"]]
+    for i in range(5):
+        cols = P.indices[P.indptr[i]:P.indptr[i + 1]].tolist()
+        assert cols == ([] if want[i] < 0 else [want[i]])
+    # strongest C-neighbour, ties to the smallest index
+    A2 = O.csr(np.array([0, 4, 5, 6, 7]), np.array([0, 1, 2, 3, 1, 2, 3]),
+               np.array([3.0, -1.0, -2.0, 2.0, 1.0, 1.0, 1.0]))
+    cf2 = np.array([0, 1, 1, 1], dtype=np.int8)
+    sm2 = O.strength(A2, 0.25)
+    P2 = O.interp_one_point(A2, sm2, cf2)
+    assert P2.indices[P2.indptr[0]:P2.indptr[1]].tolist() == [1]   # col 2 -> c1
+
+
+def test_direct_interp_reproduces_constants():
+    """Zero row sums: sum_k w_ik = -(sum_{j != i} a_ij)/a_ii = 1."""
+    w = W.adr_2d(15, 1.0, 0.4, 0.0)
+    A = _mat(w)
+    rs = np.asarray(A.sum(axis=1)).ravel()
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    P = O.interp_direct(A, sm, cf)
+    p1 = P @ np.ones(P.shape[1])
+    rows = (np.abs(rs) < 1e-12 * np.abs(A.diagonal())) & (np.diff(P.indptr) > 0)
+    assert rows.sum() > 10
+    assert np.allclose(p1[rows], 1.0, rtol=0, atol=1e-12)
+
+
+def test_galerkin_matches_dense_products():
+    A = _mat(W.adr_2d(10, 1e-2, 1.1, 0.2))
+    H = O.setup(A, interp=O.INTERP_DIRECT, max_coarse=10)
+    L0 = H.levels[0]
+    K = H.levels[1].A.toarray()
+    Kd = L0.R.toarray() @ L0.A.toarray() @ L0.P.toarray()
+    assert np.abs(K - Kd).max() <= 1e-12 * np.abs(Kd).max()
+
+
+def test_galerkin_pattern_is_symbolic():
+    """Entries that cancel to zero stay in K's pattern (chain: R A has an
+    exact 0 in every F column, Eq. (johnair))."""
+    g = _read_golden("chain5.txt")
+    A = _mat(W.chain_1d(5))
+    H = O.setup(A, max_coarse=1, max_levels=2)
+    K = H.levels[1].A
+    assert K.indptr.tolist() == [int(v) for v in g["K_rowptr"]]
+    assert K.indices.tolist() == [int(v) for v in g["K_col"]]
+    assert K.data.tolist() == [float(v) for v in g["K_val"]]
+    AP = H.levels[0].AP
+    assert 0.0 in AP.data.tolist()        # the kept cancellation
+
+
+def test_ideal_R_gives_schur_complement():
+    """With ideal R, R A P = A_cc - A_cf A_ff^{-1} A_fc for any P."""
+    w = W.random_ff_digraph(50, 4, 321)
+    A = _mat(w)
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, O.DIST_ALL_F)
+    z, _ = O.local_solves(A, cpts, nptr, nbr)
+    R = O.restriction(A.shape[0], cpts, nptr, nbr, z)
+    D = A.toarray()
+    F = np.flatnonzero(cf == 0)
+    C = np.flatnonzero(cf == 1)
+    S = D[np.ix_(C, C)] - D[np.ix_(C, F)] @ np.linalg.solve(D[np.ix_(F, F)], D[np.ix_(F, C)])
+    for P in (O.interp_one_point(A, sm, cf), O.interp_direct(A, sm, cf)):
+        K = O.galerkin(R, A, P).toarray()
+        assert np.abs(K - S).max() <= 1e-11 * np.abs(S).max()
+
+
+def test_row_scaling_invariance():
+    """Remark (row scaling): A -> D A keeps the splitting and patterns,
+    Z -> D_c Z D_f^{-1}, K -> D_c K (same P)."""
+    w = W.adr_2d(12, 1e-2, 0.9, 0.3)
+    A = _mat(w)
+    d = np.random.default_rng(5).uniform(0.5, 4.0, A.shape[0])
+    DA = (sp.diags(d) @ A).tocsr()
+    DA.sort_indices()
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    smd = O.strength(DA, 0.25)
+    assert np.array_equal(sm, smd)
+    assert np.array_equal(cf, O.rs_split(DA, smd))
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, 2)
+    z, _ = O.local_solves(A, cpts, nptr, nbr)
+    zd, _ = O.local_solves(DA, cpts, nptr, nbr)
+    rows = np.repeat(cpts, np.diff(nptr))
+    assert np.allclose(zd, d[rows] * z / d[nbr], rtol=1e-12, atol=0)
+    P = O.interp_one_point(A, sm, cf)
+    R = O.restriction(A.shape[0], cpts, nptr, nbr, z)
+    Rd = O.restriction(A.shape[0], cpts, nptr, nbr, zd)
+    K = O.galerkin(R, A, P).toarray()
+    Kd = O.galerkin(Rd, DA, P).toarray()
+    assert np.abs(Kd - d[cpts][:, None] * K).max() <= 1e-12 * np.abs(Kd).max()
+
+
+# ---------------------------------------------------------------- O10 cycle
+
+def test_chain_one_cycle_is_exact():
+    """F-F-C Jacobi after the distance-one lAIR correction solves the upwind
+    chain in one V-cycle, for any length and depth."""
+    for n in (5, 64, 257):
+        A = _mat(W.chain_1d(n))
+        H = O.setup(A, max_coarse=2)
+        b = np.random.default_rng(n).standard_normal(n)
+        x = O.cycle(H, b, np.zeros(n))
+        xs = spla.spsolve(A.tocsc(), b)
+        assert np.abs(x - xs).max() <= 1e-12 * np.abs(xs).max()
+        for l in H.levels[1:]:
+            K = l.A
+            assert np.all(np.diff(K.indptr)[1:] == 2)
+
+
+def _two_grid_error_operator(H):
+    """E = (I - Pi_C D^-1 A)(I - Pi_F D^-1 A)^2 (I - P K^-1 R A), written from
+    Eq. (err_prop) and Eq. (jacobi_err) with Delta = D_ff^{-1}."""
+    L = H.levels[0]
+    A = L.A.toarray()
+    n = A.shape[0]
+    R, P = L.R.toarray(), L.P.toarray()
+    K = R @ A @ P
+    Dinv = np.diag(1.0 / np.diag(A))
+    PiF = np.diag((L.cf == 0).astype(float))
+    PiC = np.diag((L.cf == 1).astype(float))
+    I = np.eye(n)
+    cgc = I - P @ np.linalg.solve(K, R @ A)
+    fr = I - PiF @ Dinv @ A
+    cr = I - PiC @ Dinv @ A
+    return cr @ fr @ fr @ cgc
+
+
+def test_two_grid_cycle_matches_error_propagation():
+    A = _mat(W.adr_2d(9, 1e-2, 0.6, 0.2))
+    H = O.setup(A, max_levels=2, max_coarse=10, distance=2)
+    assert H.nlevels == 2
+    E = _two_grid_error_operator(H)
+    rng = np.random.default_rng(3)
+    xs = rng.standard_normal(A.shape[0])
+    b = A @ xs
+    x0 = rng.standard_normal(A.shape[0])
+    x1 = O.cycle(H, b, x0)
+    assert np.abs((xs - x1) - E @ (xs - x0)).max() <= 1e-11 * np.abs(xs - x0).max()
+
+
+def test_exact_f_solve_and_ideal_R_converge_in_one_step():
+    """Eq. (cgc_rho): exact F-solve with ideal restriction gives rho = 0."""
+    w = W.random_ff_digraph(40, 3, 11)
+    A = _mat(w)
+    D = A.toarray()
+    sm = O.strength(A, 0.25)
+    cf = O.rs_split(A, sm)
+    cpts, nptr, nbr = O.neighbourhoods(A, sm, cf, O.DIST_ALL_F)
+    z, _ = O.local_solves(A, cpts, nptr, nbr)
+    R = O.restriction(A.shape[0], cpts, nptr, nbr, z).toarray()
+    P = O.interp_one_point(A, sm, cf).toarray()
+    F = np.flatnonzero(cf == 0)
+    n = A.shape[0]
+    Delta = np.zeros((n, n))
+    Delta[np.ix_(F, F)] = np.linalg.inv(D[np.ix_(F, F)])
+    K = R @ D @ P
+    E = (np.eye(n) - Delta @ D) @ (np.eye(n) - P @ np.linalg.solve(K, R @ D))
+    assert np.abs(np.linalg.eigvals(E)).max() <= 1e-10
+
+
+def test_row_scaling_gives_same_iterates():
+    w = W.adr_2d(16, 1e-2, 2.5, 0.1)
+    A = _mat(w)
+    d = np.random.default_rng(8).uniform(0.3, 3.0, A.shape[0])
+    DA = (sp.diags(d) @ A).tocsr()
+    DA.sort_indices()
+    H = O.setup(A, interp=O.INTERP_ONE_POINT)
+    Hd = O.setup(DA, interp=O.INTERP_ONE_POINT)
+    b = np.ones(A.shape[0])
+    x = O.cycle(H, b, np.zeros_like(b))
+    xd = O.cycle(Hd, d * b, np.zeros_like(b))
+    x2 = O.cycle(H, b, x)
+    xd2 = O.cycle(Hd, d * b, xd)
+    assert np.abs(x2 - xd2).max() <= 1e-11 * np.abs(x2).max()
+
+
+# ---------------------------------------------------------------- O11 solve
+
+@pytest.mark.parametrize("case", ["c1", "c4", "euler3d"])
+def test_solve_matches_direct_solution(case):
+    if case == "c1":
+        w = W.workload_c1(32)
+        A = _mat(w)
+        kw = {}
+    elif case == "c4":
+        w = W.workload_c4(32)
+        A = (_mat(w) + sp.diags(w["c"])).tocsr()
+        A.sort_indices()
+        kw = dict(interp=O.INTERP_DIRECT)
+    else:
+        w = W.implicit_euler_adr_3d(m=14, nrhs=1)
+        A = _mat(w)
+        kw = dict(interp=O.INTERP_DIRECT)
+    H = O.setup(A, **kw)
+    x, it, hist = O.solve(H, w["rhs"], rtol=1e-10)
+    assert hist[-1] <= 1e-10 * np.linalg.norm(w["rhs"])
+    xs = spla.spsolve(A.tocsc(), w["rhs"])
+    cond_est = np.linalg.cond(A.toarray()) if A.shape[0] <= 3000 else 1e4
+    assert np.linalg.norm(x - xs) <= 2e-10 * cond_est * np.linalg.norm(xs)
+
+
+# ---------------------------------------------------------------- adjoint
+
+def test_transpose_cycle_is_adjoint():
+    """<B u, v> = <u, B^T v> for one cycle from zero (x = B b)."""
+    w = W.workload_c4(24)
+    A = (_mat(w) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    H = O.setup(A, interp=O.INTERP_DIRECT, max_coarse=20)
+    assert H.nlevels >= 3
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal(A.shape[0])
+    v = rng.standard_normal(A.shape[0])
+    Bu = O.cycle(H, u, np.zeros_like(u))
+    Btv = O.cycle_transpose(H, v, np.zeros_like(v))
+    assert abs(Bu @ v - u @ Btv) <= 1e-13 * np.linalg.norm(Bu) * np.linalg.norm(v) * 10
+
+
+def test_transpose_solve_matches_dense():
+    w = W.workload_c4(20)
+    A = (_mat(w) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    H = O.setup(A, interp=O.INTERP_DIRECT)
+    g = np.random.default_rng(4).standard_normal(A.shape[0])
+    lam, it, hist = O.solve_transpose(H, g, rtol=1e-12)
+    ref = np.linalg.solve(A.toarray().T, g)
+    assert np.linalg.norm(lam - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- DG / block
+
+def test_dg_reproduces_constants_and_block_scaling():
+    w = W.upwind_dg_p2(5)
+    A = _mat(w)
+    assert np.abs(A @ np.ones(A.shape[0]) - w["rhs"]).max() <= 1e-14
+    As, bs = O.block_scale(A, w["rhs"], 6)
+    D = As.toarray()
+    for e in range(A.shape[0] // 6):
+        blk = D[6 * e:6 * e + 6, 6 * e:6 * e + 6]
+        assert np.abs(blk - np.eye(6)).max() <= 1e-12
+    assert np.abs(As @ np.ones(A.shape[0]) - bs).max() <= 1e-12
