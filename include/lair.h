@@ -1,0 +1,199 @@
+/*
+ * lair.h -- C ABI of liblair, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of lAIR: nonsymmetric algebraic multigrid with
+ * local approximate ideal restriction and F-relaxation (Manteuffel, Ruge,
+ * Southworth, arXiv:1708.06065).
+ *
+ * The library builds a multigrid hierarchy on the GPU from a square sparse
+ * matrix A (CSR) and a CF splitting, and runs V-cycles with F-F-C Jacobi
+ * relaxation:
+ *   setup  (per level)  strength of connection (Sec. 4), restriction
+ *                        neighbourhoods (Sec. 3.1 / Sec. 4), one dense local
+ *                        solve per C-point (Eq. (system)) giving R = [Z I]
+ *                        (Eq. (PR)), interpolation P, Galerkin K = R A P
+ *                        (Sec. 2.1);
+ *   cycle               coarse-grid correction x += P K^{-1} R (b - A x)
+ *                        (Sec. 2.1) followed by Jacobi on F, F, then C points
+ *                        (Sec. 4, relaxation paragraph).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are CSR with int32 row pointers and column indices and double
+ *    values; each row's columns are strictly increasing and the diagonal is
+ *    stored.  Vectors are double.  Several right-hand sides are interleaved:
+ *    element (i, k) of an n x nrhs block is at [i * nrhs + k].
+ *  - Pointers named "device" are HIP device pointers on the current device.
+ *    The caller owns every buffer it passes; the library never keeps a
+ *    caller pointer beyond the call (lair_setup copies A).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  All device work of
+ *    a call is ordered on it; calls that report results to the host
+ *    synchronise it before returning.
+ *  - Errors are returned as lair_status codes; no exception or abort crosses
+ *    the ABI.  Arguments are validated before any device work.  A message for
+ *    the last failure on the calling thread is available from
+ *    lair_last_error().
+ *  - One hierarchy may be used by one stream at a time; distinct hierarchies
+ *    are independent.
+ */
+#ifndef LAIR_H
+#define LAIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lair_status;
+
+#define LAIR_OK             0
+#define LAIR_EINVAL        -1   /* invalid argument or malformed input      */
+#define LAIR_ENOMEM        -2   /* device or host allocation failed         */
+#define LAIR_EDEVICE       -3   /* HIP runtime error / no device            */
+#define LAIR_ESINGULAR     -4   /* coarsest-grid matrix is singular         */
+#define LAIR_ENOCONV       -5   /* tolerance not reached within maxit       */
+#define LAIR_EUNSUPPORTED  -6   /* a size limit of this build was exceeded  */
+
+/* strength-of-connection kinds (Sec. 4) */
+#define LAIR_SOC_ABS 0   /* |a_ij| >= theta max_{k!=i} |a_ik|                */
+#define LAIR_SOC_NEG 1   /* -a_ij  >= theta max_{k!=i} |a_ik|  (paper's form) */
+
+/* neighbourhood distance for R (Sec. 3.1): 1, 2, or every F-point */
+#define LAIR_DIST_ALL_F 0
+
+/* interpolation */
+#define LAIR_P_ONE_POINT 0  /* value of the strongest C-neighbour (Sec. 4) */
+#define LAIR_P_DIRECT    1  /* classical direct interpolation              */
+
+/* precision of the setup's local solves and of the cycle */
+#define LAIR_FP64        0  /* everything in double                        */
+#define LAIR_MIXED       1  /* float local LU + one double refinement step
+                               per row of Z; float cycle under a double outer
+                               iteration (residual, update, norms in double) */
+
+/* A square CSR matrix handed to lair_setup. */
+typedef struct lair_csr {
+    int64_t n;               /* rows = columns, 1 <= n < 2^31               */
+    int64_t nnz;             /* stored entries, nnz < 2^31                  */
+    const int32_t *rowptr;   /* n + 1 offsets, rowptr[0] = 0                */
+    const int32_t *col;      /* nnz column indices, sorted, unique per row  */
+    const double *val;       /* nnz values, finite                          */
+    int32_t on_device;       /* 1: the three arrays are device pointers     */
+} lair_csr;
+
+/* Strength of connection and neighbourhood (Sec. 3.1, Sec. 4). */
+typedef struct lair_strength {
+    double theta;            /* threshold for neighbourhoods and P  (0.25)  */
+    double theta_c;          /* threshold for the library's own CF split    */
+    int32_t kind;            /* LAIR_SOC_ABS or LAIR_SOC_NEG                */
+    int32_t distance;        /* 1, 2 or LAIR_DIST_ALL_F                     */
+} lair_strength;
+
+/* Optional per-level CF splittings (host memory).  Level l uses
+ * cf[offs[l] .. offs[l+1]) with 1 = C-point, 0 = F-point; its length must
+ * equal that level's size.  Levels beyond nlevels use the library's own
+ * classical first-pass splitting on the host. */
+typedef struct lair_cf_levels {
+    int32_t nlevels;
+    const int64_t *offs;     /* nlevels + 1 entries                          */
+    const int8_t *cf;
+} lair_cf_levels;
+
+typedef struct lair_options {
+    int32_t interp;          /* LAIR_P_ONE_POINT or LAIR_P_DIRECT           */
+    int32_t precision;       /* LAIR_FP64 or LAIR_MIXED                     */
+    double omega;            /* Jacobi weight (1.0)                         */
+    int32_t max_levels;      /* at most this many levels (25)               */
+    int32_t max_coarse;      /* stop coarsening at n <= max_coarse (128)    */
+    double stall;            /* stop when n_c > stall * n (0.9)             */
+    int32_t block_size;      /* 0, or k: solve D_B^{-1} A x = D_B^{-1} b with
+                                D_B the k x k diagonal blocks (Sec. 4.2.1) */
+    int32_t reserved;
+} lair_options;
+
+typedef struct lair_info {
+    int32_t iters;           /* V-cycles done                               */
+    int32_t nlevels;
+    double relres;           /* max over right-hand sides of
+                                ||b - A x||_2 / ||b||_2 at return          */
+    double rho;              /* geometric-mean residual reduction / cycle   */
+    double cycle_complexity; /* work units per cycle (1 WU = SpMV with A_0) */
+    double op_complexity;    /* sum_l nnz(A_l) / nnz(A_0)                   */
+    int64_t n_singular_local;/* local systems solved by least squares       */
+    double setup_ms;         /* wall time of lair_setup                     */
+    double solve_ms;         /* wall time of the last solve                 */
+} lair_info;
+
+/* Per-level statistics (host copy). */
+typedef struct lair_level_stats {
+    int64_t n, nnz_A, nc, nnz_R, nnz_P;
+    int32_t s_min, s_max;    /* neighbourhood sizes over C-points            */
+    double s_mean;
+    int64_t n_singular;
+} lair_level_stats;
+
+typedef struct lair_hierarchy lair_hierarchy;   /* opaque */
+
+/* Fill the defaults: theta = theta_c = 0.25, ABS, distance 1, one-point P,
+ * FP64, omega 1, 25 levels, max_coarse 128, stall 0.9, no block scaling. */
+void lair_default_options(lair_strength *s, lair_options *o);
+
+/* Build a hierarchy for A (copied).  cf may be NULL.  On success *out owns
+ * all device memory of the hierarchy until lair_free.
+ * Errors: EINVAL (bad CSR, non-finite values, bad cf length or values, bad
+ * options), ENOMEM, EDEVICE, ESINGULAR (coarsest matrix singular),
+ * EUNSUPPORTED (neighbourhood or product row beyond this build's limits). */
+lair_status lair_setup(const lair_csr *A, const lair_cf_levels *cf,
+                       const lair_strength *s, const lair_options *o,
+                       void *stream, lair_hierarchy **out);
+
+/* One V-cycle on device vectors: x <- x + B (b - A x), nrhs interleaved
+ * right-hand sides (nrhs in 1, 2, 4, 8, 16, 32).  With block scaling, b is
+ * the unscaled right-hand side.  Asynchronous on `stream`. */
+lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
+                       int32_t nrhs, void *stream);
+
+/* Stationary V-cycle iteration from the given x (device, in/out) until
+ * every right-hand side has ||b - A x||_2 <= rtol ||b||_2, or maxit cycles.
+ * info may be NULL.  Returns ENOCONV (info filled, x = last iterate) when
+ * maxit is reached first. */
+lair_status lair_solve(lair_hierarchy *h, const double *b, double *x,
+                       int32_t nrhs, double rtol, int32_t maxit,
+                       lair_info *info, void *stream);
+
+/* Same for the transposed system A^T lam = g with the transposed cycle
+ * (pre-relaxation C, F, F on A^T; restriction P^T; interpolation R^T), the
+ * exact adjoint of lair_cycle.  Used for gradients. */
+lair_status lair_solve_transpose(lair_hierarchy *h, const double *g,
+                                 double *lam, int32_t nrhs, double rtol,
+                                 int32_t maxit, lair_info *info,
+                                 void *stream);
+
+/* One transposed cycle (the adjoint of lair_cycle). */
+lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g,
+                                 double *lam, int32_t nrhs, void *stream);
+
+/* Number of levels and per-level statistics. */
+int32_t lair_num_levels(const lair_hierarchy *h);
+lair_status lair_level_stats_get(const lair_hierarchy *h, int32_t level,
+                                 lair_level_stats *st);
+
+/* Copy one array of a level to host memory.  `what` selects:
+ *   0 A.rowptr (int32, n+1)   1 A.col (int32)    2 A.val (double)
+ *   3 cf (int8, n)            4 strength mask (uint8, nnz_A)
+ *   5 R.rowptr  6 R.col  7 R.val     8 P.rowptr  9 P.col  10 P.val
+ *   11 neighbourhood offsets (int32, nc+1)  12 neighbourhood list (int32)
+ *   13 local-solve fallback flags (int8, nc)
+ * *bytes is the capacity of host_buf on input and the size needed on
+ * output; host_buf may be NULL to query the size.  EINVAL on a bad level or
+ * `what`, or when the buffer is too small. */
+lair_status lair_export(const lair_hierarchy *h, int32_t level, int32_t what,
+                        void *host_buf, int64_t *bytes);
+
+void lair_free(lair_hierarchy *h);
+const char *lair_status_string(lair_status s);
+const char *lair_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAIR_H */

@@ -1,0 +1,220 @@
+"""lAIR on MI355X: Python binding of liblair (argument marshalling only).
+
+Every step of the setup and of the cycles runs in the HIP kernels of
+liblair.so (include/lair.h).  PyTorch supplies device memory and the current
+HIP stream.  There is no CPU fallback: if the library is not built or no GPU
+is visible, the calls raise.
+
+    import paper_1708_06065_amd as lair
+    h = lair.setup(rowptr, col, val, distance=2, interp="one_point")
+    x, info = h.solve(b)                 # b: torch tensor on the GPU
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import LairError  # noqa: F401
+
+__all__ = ["setup", "Hierarchy", "LairError", "load_library"]
+
+_KINDS = {"abs": L.SOC_ABS, "neg": L.SOC_NEG}
+_INTERP = {"one_point": L.P_ONE_POINT, "direct": L.P_DIRECT}
+_PREC = {"fp64": L.FP64, "mixed": L.MIXED}
+_DIST = {1: 1, 2: 2, "all_f": L.DIST_ALL_F, 0: L.DIST_ALL_F}
+
+EXPORT_WHAT = {
+    "A.rowptr": (0, np.int32), "A.col": (1, np.int32), "A.val": (2, np.float64),
+    "cf": (3, np.int8), "smask": (4, np.uint8),
+    "R.rowptr": (5, np.int32), "R.col": (6, np.int32), "R.val": (7, np.float64),
+    "P.rowptr": (8, np.int32), "P.col": (9, np.int32), "P.val": (10, np.float64),
+    "nbr_ptr": (11, np.int32), "nbr": (12, np.int32), "flags": (13, np.int8),
+}
+
+
+def load_library():
+    return L.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be contiguous %s" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Hierarchy:
+    """An lAIR hierarchy living on the GPU (owns liblair's handle)."""
+
+    def __init__(self, handle, n, options):
+        self._h = handle
+        self.n = n
+        self.options = options
+
+    # -- lifetime ---------------------------------------------------------
+    def free(self):
+        if self._h:
+            L.load().lair_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("hierarchy has been freed")
+        return self._h
+
+    # -- introspection ----------------------------------------------------
+    @property
+    def nlevels(self):
+        return L.load().lair_num_levels(self.handle)
+
+    def level_stats(self, level):
+        st = L.LevelStats()
+        L.check(L.load().lair_level_stats_get(self.handle, level, ctypes.byref(st)),
+                "lair_level_stats_get")
+        return st.as_dict()
+
+    def export(self, level, what):
+        code, dt = EXPORT_WHAT[what]
+        nb = ctypes.c_int64(0)
+        lib = L.load()
+        L.check(lib.lair_export(self.handle, level, code, None, ctypes.byref(nb)),
+                "lair_export")
+        out = np.zeros(nb.value // np.dtype(dt).itemsize, dtype=dt)
+        if nb.value:
+            L.check(lib.lair_export(self.handle, level, code,
+                                    out.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(nb)), "lair_export")
+        return out
+
+    # -- cycles and solves --------------------------------------------------
+    def _nrhs(self, b):
+        if b.dim() == 1:
+            return 1
+        return b.shape[1]
+
+    def cycle(self, b, x, stream=None):
+        """x <- x + B (b - A x): one V-cycle, in place on device tensors."""
+        torch = _torch()
+        nr = self._nrhs(b)
+        L.check(L.load().lair_cycle(self.handle, _dev_ptr(b, torch.float64, "b"),
+                                    _dev_ptr(x, torch.float64, "x"), nr,
+                                    _stream_ptr(stream)), "lair_cycle")
+        return x
+
+    def cycle_transpose(self, g, lam, stream=None):
+        torch = _torch()
+        nr = self._nrhs(g)
+        L.check(L.load().lair_cycle_transpose(self.handle, _dev_ptr(g, torch.float64, "g"),
+                                              _dev_ptr(lam, torch.float64, "lam"), nr,
+                                              _stream_ptr(stream)),
+                "lair_cycle_transpose")
+        return lam
+
+    def solve(self, b, x=None, rtol=1e-10, maxit=200, stream=None,
+              raise_on_noconv=False):
+        """Stationary V-cycle iteration.  Returns (x, info dict)."""
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        info = L.Info()
+        st = L.load().lair_solve(self.handle, _dev_ptr(b, torch.float64, "b"),
+                                 _dev_ptr(x, torch.float64, "x"), self._nrhs(b),
+                                 float(rtol), int(maxit), ctypes.byref(info),
+                                 _stream_ptr(stream))
+        if st != L.LAIR_OK and (st != L.LAIR_ENOCONV or raise_on_noconv):
+            L.check(st, "lair_solve")
+        d = info.as_dict()
+        d["converged"] = st == L.LAIR_OK
+        return x, d
+
+    def solve_transpose(self, g, lam=None, rtol=1e-10, maxit=200, stream=None,
+                        raise_on_noconv=False):
+        torch = _torch()
+        if lam is None:
+            lam = torch.zeros_like(g)
+        info = L.Info()
+        st = L.load().lair_solve_transpose(self.handle, _dev_ptr(g, torch.float64, "g"),
+                                           _dev_ptr(lam, torch.float64, "lam"),
+                                           self._nrhs(g), float(rtol), int(maxit),
+                                           ctypes.byref(info), _stream_ptr(stream))
+        if st != L.LAIR_OK and (st != L.LAIR_ENOCONV or raise_on_noconv):
+            L.check(st, "lair_solve_transpose")
+        d = info.as_dict()
+        d["converged"] = st == L.LAIR_OK
+        return lam, d
+
+
+def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
+          kind="abs", distance=1, interp="one_point", precision="fp64",
+          omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
+          stream=None):
+    """Build a hierarchy for the CSR matrix (rowptr, col, val).
+
+    The arrays may be NumPy arrays (host) or contiguous CUDA tensors
+    (int32, int32, float64).  cf_levels is an optional list of per-level
+    int8 CF splittings (1 = C) in host memory.
+    """
+    torch = _torch()
+    lib = L.load()
+    keep = []
+    on_dev = isinstance(val, torch.Tensor) and val.is_cuda
+    if on_dev:
+        rp = _dev_ptr(rowptr, torch.int32, "rowptr")
+        cj = _dev_ptr(col, torch.int32, "col")
+        vx = _dev_ptr(val, torch.float64, "val")
+        n = rowptr.shape[0] - 1
+        nnz = col.shape[0]
+    else:
+        a = np.ascontiguousarray(rowptr, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        keep += [a, c, v]
+        rp, cj, vx = (x.ctypes.data_as(ctypes.c_void_p) for x in (a, c, v))
+        n = a.shape[0] - 1
+        nnz = c.shape[0]
+    A = L.Csr(n, nnz, rp, cj, vx, 1 if on_dev else 0)
+    s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
+                   _KINDS[kind], _DIST[distance])
+    o = L.Options(_INTERP[interp], _PREC[precision], float(omega), int(max_levels),
+                  int(max_coarse), float(stall), int(block_size), 0)
+    cfp = None
+    if cf_levels is not None:
+        arrs = [np.ascontiguousarray(x, dtype=np.int8) for x in cf_levels]
+        offs = np.zeros(len(arrs) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum([x.shape[0] for x in arrs])
+        flat = np.concatenate(arrs) if arrs else np.zeros(1, np.int8)
+        keep += [offs, flat]
+        cfl = L.CfLevels(len(arrs), offs.ctypes.data_as(ctypes.c_void_p),
+                         flat.ctypes.data_as(ctypes.c_void_p))
+        keep.append(cfl)
+        cfp = ctypes.byref(cfl)
+    out = ctypes.c_void_p()
+    st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),
+                        _stream_ptr(stream), ctypes.byref(out))
+    L.check(st, "lair_setup")
+    opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
+                interp=interp, precision=precision, omega=omega,
+                max_levels=max_levels, max_coarse=max_coarse, stall=stall,
+                block_size=block_size)
+    return Hierarchy(out, n, opts)

@@ -1,0 +1,108 @@
+"""ctypes declarations of liblair's C ABI (include/lair.h)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblair.so")
+
+c_i32, c_i64, c_f64, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+LAIR_OK = 0
+LAIR_EINVAL = -1
+LAIR_ENOMEM = -2
+LAIR_EDEVICE = -3
+LAIR_ESINGULAR = -4
+LAIR_ENOCONV = -5
+LAIR_EUNSUPPORTED = -6
+
+SOC_ABS, SOC_NEG = 0, 1
+DIST_ALL_F = 0
+P_ONE_POINT, P_DIRECT = 0, 1
+FP64, MIXED = 0, 1
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("nnz", c_i64), ("rowptr", c_vp), ("col", c_vp),
+                ("val", c_vp), ("on_device", c_i32)]
+
+
+class Strength(ctypes.Structure):
+    _fields_ = [("theta", c_f64), ("theta_c", c_f64), ("kind", c_i32),
+                ("distance", c_i32)]
+
+
+class CfLevels(ctypes.Structure):
+    _fields_ = [("nlevels", c_i32), ("offs", c_vp), ("cf", c_vp)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("interp", c_i32), ("precision", c_i32), ("omega", c_f64),
+                ("max_levels", c_i32), ("max_coarse", c_i32), ("stall", c_f64),
+                ("block_size", c_i32), ("reserved", c_i32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("nlevels", c_i32), ("relres", c_f64),
+                ("rho", c_f64), ("cycle_complexity", c_f64),
+                ("op_complexity", c_f64), ("n_singular_local", c_i64),
+                ("setup_ms", c_f64), ("solve_ms", c_f64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("nnz_A", c_i64), ("nc", c_i64), ("nnz_R", c_i64),
+                ("nnz_P", c_i64), ("s_min", c_i32), ("s_max", c_i32),
+                ("s_mean", c_f64), ("n_singular", c_i64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "lair_default_options": (None, [c_vp, c_vp]),
+    "lair_setup": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lair_cycle": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "lair_solve": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
+    "lair_solve_transpose": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
+    "lair_cycle_transpose": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "lair_num_levels": (c_i32, [c_vp]),
+    "lair_level_stats_get": (c_i32, [c_vp, c_i32, c_vp]),
+    "lair_export": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp]),
+    "lair_free": (None, [c_vp]),
+    "lair_status_string": (ctypes.c_char_p, [c_i32]),
+    "lair_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load liblair.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            "liblair.so is not built (%s); run `python -m "
+            "paper_1708_06065_amd.build` first" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class LairError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (msg, status, load().lair_last_error().decode()))
+        self.status = status
+
+
+def check(status, what):
+    if status != LAIR_OK:
+        raise LairError(status, what)

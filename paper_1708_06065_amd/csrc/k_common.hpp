@@ -1,0 +1,79 @@
+// Device-side helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+namespace lair {
+
+constexpr int WAVE = 64;
+
+// Butterfly reductions over a team of T consecutive lanes (T a power of two
+// dividing 64).  Every lane of the team receives the result; the order of
+// the additions is fixed, so results are reproducible run to run.
+template <int T>
+__device__ __forceinline__ double team_sum(double v) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
+    return v;
+}
+template <int T>
+__device__ __forceinline__ float team_sum(float v) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
+    return v;
+}
+template <int T>
+__device__ __forceinline__ double team_max(double v) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, T));
+    return v;
+}
+template <int T>
+__device__ __forceinline__ int team_min(int v) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, T));
+    return v;
+}
+template <int T>
+__device__ __forceinline__ int team_sum_int(int v) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, T);
+    return v;
+}
+
+// Bits of a wave ballot that belong to the calling lane's team of T lanes.
+template <int T>
+__device__ __forceinline__ uint64_t team_bits(bool pred) {
+    uint64_t b = __ballot(pred);
+    int first = (threadIdx.x & (WAVE - 1)) & ~(T - 1);
+    uint64_t mask = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
+    return (b >> first) & mask;
+}
+
+// Arg-max of |value| over a team, ties to the smallest index.
+template <int T>
+__device__ __forceinline__ void team_argmax(double &v, int &idx) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) {
+        double ov = __shfl_xor(v, o, T);
+        int oi = __shfl_xor(idx, o, T);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+}
+
+// Position of `key` in the sorted list a[0..n), or -1.
+__device__ __forceinline__ int bsearch_i32(const int32_t *a, int n, int key) {
+    int lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int v = a[mid];
+        if (v == key) return mid;
+        if (v < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+}  // namespace lair

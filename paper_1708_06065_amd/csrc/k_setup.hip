@@ -1,0 +1,1367 @@
+// Setup kernels of the lAIR hierarchy on gfx950 (wave64).
+//
+//   validate / strength     one team of lanes per row
+//   scan                    three-phase tile scan (counts -> offsets)
+//   neighbourhoods          one team per C-point; distance 2 is a k-way
+//                           merge of sorted strong-F lists (F-F-C paths)
+//   local solves            Eq. (system): M = A(N,N)^T, f = -A(i,N)^T,
+//                           partial-pivot LU; small systems one lane each in
+//                           registers, larger ones one wave each in LDS (or
+//                           global scratch beyond the LDS limit); singular
+//                           systems take the minimal-norm least-squares
+//                           solution by one-sided Jacobi SVD
+//   interpolation           one-point and classical direct, one lane per row
+//   sparse product          row-merge: one team per output row merges the
+//                           sorted rows of B selected by a row of A
+//   transpose, coarsest LU  support for the cycle and its adjoint
+#include <cfloat>
+#include <cmath>
+#include <type_traits>
+
+#include "k_common.hpp"
+#include "lair_internal.hpp"
+
+namespace lair {
+
+// ===========================================================================
+// Scan: out[i] = sum_{j<i} f(j), out[n] = total.
+// ===========================================================================
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_IPT = 4;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_IPT;
+
+struct CountsF {
+    const int32_t *c;
+    __device__ int64_t operator()(int64_t i) const { return c[i]; }
+};
+struct FlagsF {
+    const int8_t *f;
+    int8_t want;
+    __device__ int64_t operator()(int64_t i) const { return f[i] == want ? 1 : 0; }
+};
+
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) {
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_BS; o <<= 1) {
+        int64_t add = (t >= o) ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[SCAN_BS - 1];
+    int64_t r = sh[t] - v;
+    __syncthreads();
+    return r;
+}
+
+template <class F>
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_tile(F f, int64_t n, int32_t *out, int64_t *blocksum) {
+    __shared__ int64_t sh[SCAN_BS];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int64_t v[SCAN_IPT];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t i = base + j;
+        v[j] = (i < n) ? f(i) : 0;
+        s += v[j];
+    }
+    int64_t total;
+    int64_t pre = block_exclusive_scan(s, sh, total);
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = (int32_t)pre;
+        pre += v[j];
+    }
+    if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_sums(int64_t *bs, int64_t nb, int64_t *total) {
+    __shared__ int64_t sh[SCAN_BS];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_BS) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = (i < nb) ? bs[i] : 0;
+        int64_t tot;
+        int64_t pre = block_exclusive_scan(v, sh, tot);
+        if (i < nb) bs[i] = pre + carry;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int32_t *out, int64_t n, const int64_t *bs,
+                           const int64_t *total) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)((int64_t)out[i] + bs[i / SCAN_TILE]);
+    if (i == 0) out[n] = (int32_t)(*total);
+}
+
+template <class F>
+static int64_t scan_impl(F f, int32_t *out, int64_t n, hipStream_t s,
+                         DevArr<int64_t> &tmp) {
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb < 1) nb = 1;
+    tmp.ensure((size_t)nb + 1, s);
+    int64_t *bs = tmp.get();
+    int64_t *tot = bs + nb;
+    hipLaunchKernelGGL(k_scan_tile<F>, dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
+                       f, n, out, bs);
+    LAIR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, nb, tot);
+    LAIR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
+                       0, s, out, n, bs, tot);
+    LAIR_LAUNCH_CHECK();
+    int64_t total = 0;
+    LAIR_HIP(hipMemcpyAsync(&total, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    if (total > INT32_MAX)
+        fail(LAIR_EUNSUPPORTED, "offset array exceeds 2^31 entries (%lld)",
+             (long long)total);
+    return total;
+}
+
+int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
+                        hipStream_t s, DevArr<int64_t> &tmp) {
+    return scan_impl(CountsF{cnt}, out, n, s, tmp);
+}
+
+int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
+                      hipStream_t s, DevArr<int64_t> &tmp) {
+    return scan_impl(FlagsF{flags, want}, out, n, s, tmp);
+}
+
+// ===========================================================================
+// CSR validation.  Error bits: 1 bad row pointers, 2 column out of range,
+// 4 columns not strictly increasing, 8 non-finite value, 16 zero diagonal,
+// 32 missing diagonal.  stat[1] receives the longest row.
+// ===========================================================================
+__global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp,
+                           const int32_t *cj, const double *v, int32_t *stat) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(stat, 1);
+    if (i >= n) return;
+    int64_t lo = rp[i], hi = rp[i + 1];
+    if (lo < 0 || hi < lo || hi > nnz) { atomicOr(stat, 1); return; }
+    int err = 0;
+    bool diag = false;
+    for (int64_t p = lo; p < hi; ++p) {
+        int c = cj[p];
+        if (c < 0 || c >= n) err |= 2;
+        if (p > lo && c <= cj[p - 1]) err |= 4;
+        double a = v[p];
+        if (!isfinite(a)) err |= 8;
+        if (c == i) { diag = true; if (a == 0.0) err |= 16; }
+    }
+    if (!diag) err |= 32;
+    if (err) atomicOr(stat, err);
+    atomicMax(stat + 1, (int32_t)(hi - lo));
+}
+
+int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
+                     const int32_t *cj, const double *v, hipStream_t s) {
+    DevArr<int32_t> st;
+    st.alloc(2, s);
+    LAIR_HIP(hipMemsetAsync(st.get(), 0, 2 * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       n, nnz, rp, cj, v, st.get());
+    LAIR_LAUNCH_CHECK();
+    int32_t h[2];
+    LAIR_HIP(hipMemcpyAsync(h, st.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    if (h[0]) {
+        fail(LAIR_EINVAL, "invalid CSR matrix (error bits 0x%x: %s%s%s%s%s%s)", h[0],
+             (h[0] & 1) ? "row pointers " : "", (h[0] & 2) ? "column range " : "",
+             (h[0] & 4) ? "unsorted/duplicate columns " : "",
+             (h[0] & 8) ? "non-finite values " : "",
+             (h[0] & 16) ? "zero diagonal " : "",
+             (h[0] & 32) ? "missing diagonal" : "");
+    }
+    return h[1];
+}
+
+// ===========================================================================
+// Strength of connection (Sec. 4).  j is strong for i iff j != i, a_ij != 0,
+// m_i = max_{k!=i} |a_ik| > 0 and |a_ij| (ABS) or -a_ij (NEG) >= theta m_i.
+// ===========================================================================
+template <int T>
+__global__ void k_strength(int32_t n, const int32_t *rp, const int32_t *cj,
+                           const double *v, double theta, int32_t kind,
+                           uint8_t *smask) {
+    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)(gt / T);
+    int lane = (int)(gt % T);
+    if (i >= n) return;
+    int lo = rp[i], hi = rp[i + 1];
+    double m = 0.0;
+    for (int p = lo + lane; p < hi; p += T)
+        if (cj[p] != i) m = fmax(m, fabs(v[p]));
+    m = team_max<T>(m);
+    double thr = theta * m;
+    for (int p = lo + lane; p < hi; p += T) {
+        double a = v[p];
+        bool s = (cj[p] != i) && (a != 0.0) && (m > 0.0) &&
+                 (((kind == LAIR_SOC_NEG) ? -a : fabs(a)) >= thr);
+        smask[p] = s ? 1 : 0;
+    }
+}
+
+template <int T>
+static void strength_t(int32_t n, const int32_t *rp, const int32_t *cj,
+                       const double *v, double theta, int32_t kind,
+                       uint8_t *smask, hipStream_t s) {
+    hipLaunchKernelGGL(k_strength<T>, dim3(blocks_for((int64_t)n * T, 256)),
+                       dim3(256), 0, s, n, rp, cj, v, theta, kind, smask);
+    LAIR_LAUNCH_CHECK();
+}
+
+void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
+                     const double *v, double theta, int32_t kind,
+                     uint8_t *smask, double mean_len, hipStream_t s) {
+    int t = team_for_mean(mean_len);
+    switch (t) {
+        case 2: strength_t<2>(n, rp, cj, v, theta, kind, smask, s); break;
+        case 4: strength_t<4>(n, rp, cj, v, theta, kind, smask, s); break;
+        case 8: strength_t<8>(n, rp, cj, v, theta, kind, smask, s); break;
+        case 16: strength_t<16>(n, rp, cj, v, theta, kind, smask, s); break;
+        case 32: strength_t<32>(n, rp, cj, v, theta, kind, smask, s); break;
+        default: strength_t<64>(n, rp, cj, v, theta, kind, smask, s); break;
+    }
+}
+
+// ===========================================================================
+// Coarse numbering (C-points in increasing fine index) and row lists.
+// ===========================================================================
+__global__ void k_cf_lists(int32_t n, const int8_t *cf, const int32_t *scan,
+                           int32_t *cidx, int32_t *clist, int32_t *flist) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = scan[i];
+    if (cf[i] == 1) {
+        cidx[i] = c;
+        clist[c] = i;
+    } else {
+        cidx[i] = -1;
+        flist[i - c] = i;
+    }
+}
+
+void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
+                     int32_t *cidx, int32_t *clist, int32_t *flist,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_cf_lists, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       n, cf, cidx_scan, cidx, clist, flist);
+    LAIR_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Restriction neighbourhoods N_i (Sec. 3.1; F-F-C paths at distance two,
+// Sec. 4).  One team of T lanes per C-point.  Distance 1 compacts the strong
+// F entries of row i (already sorted).  Distance 2 merges the sorted lists
+// {row i} and {row j : j strong F-neighbour of i}, each filtered to strong
+// F entries; list k belongs to lane k % T, slot k / T (LPL slots per lane).
+// ===========================================================================
+constexpr int NBR_LPL = 4;
+
+__device__ __forceinline__ bool nbr_ok(const uint8_t *sm, const int8_t *cf,
+                                       const int32_t *cj, int p) {
+    return sm[p] && cf[cj[p]] == 0;
+}
+
+template <int T>
+__global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
+                      const int32_t *cj, const uint8_t *sm, const int8_t *cf,
+                      int32_t distance, const int32_t *flist, int32_t nf,
+                      bool fill, int32_t *cnt, const int32_t *nptr,
+                      int32_t *nbr, int32_t *overflow) {
+    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t c = (int32_t)(gt / T);
+    int lane = (int)(gt % T);
+    if (c >= nc) return;
+    int32_t base = fill ? nptr[c] : 0;
+    if (distance == LAIR_DIST_ALL_F) {
+        if (fill)
+            for (int q = lane; q < nf; q += T) nbr[base + q] = flist[q];
+        else if (lane == 0)
+            cnt[c] = nf;
+        return;
+    }
+    int32_t i = clist[c];
+    int lo = rp[i], hi = rp[i + 1];
+    if (distance == 1) {
+        int o = 0;
+        for (int p0 = lo; p0 < hi; p0 += T) {
+            int p = p0 + lane;
+            bool q = (p < hi) && nbr_ok(sm, cf, cj, p);
+            uint64_t bits = team_bits<T>(q);
+            int before = __popcll(bits & ((1ull << lane) - 1ull));
+            if (fill && q) nbr[base + o + before] = cj[p];
+            o += __popcll(bits);
+        }
+        if (!fill && lane == 0) cnt[c] = o;
+        return;
+    }
+    // distance 2: assign lists to (lane, slot)
+    int pos[NBR_LPL], end[NBR_LPL], head[NBR_LPL];
+#pragma unroll
+    for (int m = 0; m < NBR_LPL; ++m) { pos[m] = 0; end[m] = 0; head[m] = INT_MAX; }
+    int k = 1;                // list 0 is row i itself
+    bool over = false;
+    if (lane == 0) { pos[0] = lo; end[0] = hi; }
+    for (int p = lo; p < hi; ++p) {
+        if (!nbr_ok(sm, cf, cj, p)) continue;
+        if ((k % T) == lane) {
+            int m = k / T;
+            if (m >= NBR_LPL) {
+                over = true;
+            } else {
+                int j = cj[p];
+#pragma unroll
+                for (int mm = 0; mm < NBR_LPL; ++mm)
+                    if (mm == m) { pos[mm] = rp[j]; end[mm] = rp[j + 1]; }
+            }
+        }
+        ++k;
+    }
+    if (k > T * NBR_LPL) {
+        if (lane == 0) atomicOr(overflow, 1);
+        if (!fill && lane == 0) cnt[c] = 0;
+        return;
+    }
+    (void)over;
+#pragma unroll
+    for (int m = 0; m < NBR_LPL; ++m) {
+        while (pos[m] < end[m] && !nbr_ok(sm, cf, cj, pos[m])) ++pos[m];
+        head[m] = (pos[m] < end[m]) ? cj[pos[m]] : INT_MAX;
+    }
+    int o = 0;
+    for (;;) {
+        int h = INT_MAX;
+#pragma unroll
+        for (int m = 0; m < NBR_LPL; ++m) h = min(h, head[m]);
+        int mn = team_min<T>(h);
+        if (mn == INT_MAX) break;
+        if (fill && lane == 0) nbr[base + o] = mn;
+        ++o;
+#pragma unroll
+        for (int m = 0; m < NBR_LPL; ++m) {
+            if (head[m] == mn) {
+                ++pos[m];
+                while (pos[m] < end[m] && !nbr_ok(sm, cf, cj, pos[m])) ++pos[m];
+                head[m] = (pos[m] < end[m]) ? cj[pos[m]] : INT_MAX;
+            }
+        }
+    }
+    if (!fill && lane == 0) cnt[c] = o;
+}
+
+template <int T>
+static void nbr_t(int32_t nc, const int32_t *clist, const int32_t *rp,
+                  const int32_t *cj, const uint8_t *sm, const int8_t *cf,
+                  int32_t distance, const int32_t *flist, int32_t nf, bool fill,
+                  int32_t *cnt, const int32_t *nptr, int32_t *nbr,
+                  int32_t *overflow, hipStream_t s) {
+    hipLaunchKernelGGL(k_nbr<T>, dim3(blocks_for((int64_t)nc * T, 256)), dim3(256),
+                       0, s, nc, clist, rp, cj, sm, cf, distance, flist, nf, fill,
+                       cnt, nptr, nbr, overflow);
+    LAIR_LAUNCH_CHECK();
+}
+
+void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
+                           const int32_t *rp, const int32_t *cj,
+                           const uint8_t *smask, const int8_t *cf,
+                           int32_t distance, const int32_t *flist, int32_t nf,
+                           int32_t *cnt, const int32_t *nptr, int32_t *nbr,
+                           int32_t *overflow, int32_t max_row,
+                           hipStream_t s) {
+    (void)n;
+    if (nc == 0) return;
+    bool fill = (nbr != nullptr);
+    int t;
+    if (distance == 2) {
+        int need = (max_row + 1 + NBR_LPL - 1) / NBR_LPL;
+        t = 4;
+        while (t < 64 && t < need) t <<= 1;
+    } else {
+        t = team_for_mean(distance == 1 ? (double)max_row : 64.0);
+        if (t > 16 && distance == 1) t = 16;
+    }
+    switch (t) {
+        case 2: nbr_t<2>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+        case 4: nbr_t<4>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+        case 8: nbr_t<8>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+        case 16: nbr_t<16>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+        case 32: nbr_t<32>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+        default: nbr_t<64>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+    }
+}
+
+// ===========================================================================
+// Local lAIR solves, Eq. (system): for C-point i with N = (l_0 .. l_{s-1})
+//   M[p][q] = a(l_q, l_p),   f[p] = -a(i, l_p),   M z = f.
+// Row c of R is written in place: sorted N with z, and 1 at column i.
+// Singular systems (|pivot| <= 1e-14 ||M||_inf) are listed for the
+// least-squares kernel.
+// ===========================================================================
+constexpr double SING_TOL = 1e-14;
+
+__device__ __forceinline__ void write_r_row(int32_t rbase, int s, int32_t i,
+                                            const int32_t *l, const double *z,
+                                            int32_t *r_cj, double *r_v) {
+    // position of the C-point among the sorted columns
+    int ip = 0;
+    for (int q = 0; q < s; ++q) ip += (l[q] < i);
+    for (int q = 0; q < s; ++q) {
+        int o = rbase + q + (q >= ip ? 1 : 0);
+        r_cj[o] = l[q];
+        r_v[o] = z[q];
+    }
+    r_cj[rbase + ip] = i;
+    r_v[rbase + ip] = 1.0;
+}
+
+// One lane per system, s <= SM, everything in registers.  MIXED factorises
+// in float and refines once in double: r = f - M z is -(R_i A)(N) computed
+// from the rows of A, then z += LU^{-1} r.
+template <int SM, bool MIXED>
+__global__ void __launch_bounds__(256)
+k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
+              const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+              const double *v, int32_t *r_cj, double *r_v, int8_t *flags,
+              int32_t *big, int32_t *nbig, int32_t *sing, int32_t *nsing) {
+    using FT = typename std::conditional<MIXED, float, double>::type;
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int32_t i = clist[c];
+    int32_t n0 = nptr[c];
+    int s = nptr[c + 1] - n0;
+    int32_t rbase = n0 + c;
+    flags[c] = 0;
+    if (s == 0) {
+        r_cj[rbase] = i;
+        r_v[rbase] = 1.0;
+        return;
+    }
+    if (s > SM) {
+        big[atomicAdd(nbig, 1)] = c;
+        return;
+    }
+    int li[SM];
+#pragma unroll
+    for (int q = 0; q < SM; ++q) li[q] = (q < s) ? nbr[n0 + q] : -1;
+    FT M[SM][SM];
+    double f[SM];
+#pragma unroll
+    for (int p = 0; p < SM; ++p) {
+        f[p] = 0.0;
+#pragma unroll
+        for (int q = 0; q < SM; ++q) M[p][q] = (FT)0;
+    }
+    // column p of M comes from row l_p of A: M[q][p] = a(l_p, l_q)
+#pragma unroll
+    for (int p = 0; p < SM; ++p) {
+        if (p < s) {
+            int r = li[p];
+            for (int e = rp[r]; e < rp[r + 1]; ++e) {
+                int col = cj[e];
+                double a = v[e];
+#pragma unroll
+                for (int q = 0; q < SM; ++q)
+                    if (li[q] == col) M[q][p] = (FT)a;
+            }
+        }
+    }
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int col = cj[e];
+        double a = v[e];
+#pragma unroll
+        for (int p = 0; p < SM; ++p)
+            if (li[p] == col) f[p] = -a;
+    }
+    double mnorm = 0.0;
+#pragma unroll
+    for (int p = 0; p < SM; ++p) {
+        double rs = 0.0;
+#pragma unroll
+        for (int q = 0; q < SM; ++q) rs += fabs((double)M[p][q]);
+        mnorm = fmax(mnorm, rs);
+    }
+    double tol = SING_TOL * mnorm;
+    int perm[SM];
+#pragma unroll
+    for (int p = 0; p < SM; ++p) perm[p] = p;
+    bool singular = false;
+    FT fw[SM];
+#pragma unroll
+    for (int p = 0; p < SM; ++p) fw[p] = (FT)f[p];
+#pragma unroll
+    for (int k = 0; k < SM; ++k) {
+        if (k < s && !singular) {
+            int pr = k;
+            double pv = fabs((double)M[k][k]);
+#pragma unroll
+            for (int r = k + 1; r < SM; ++r)
+                if (r < s && fabs((double)M[r][k]) > pv) { pv = fabs((double)M[r][k]); pr = r; }
+            if (pv <= tol) {
+                singular = true;
+            } else {
+#pragma unroll
+                for (int r = k + 1; r < SM; ++r) {
+                    if (r == pr) {
+#pragma unroll
+                        for (int q = 0; q < SM; ++q) {
+                            FT t = M[k][q]; M[k][q] = M[r][q]; M[r][q] = t;
+                        }
+                        FT t = fw[k]; fw[k] = fw[r]; fw[r] = t;
+                        int tp = perm[k]; perm[k] = perm[r]; perm[r] = tp;
+                    }
+                }
+                FT inv = (FT)1 / M[k][k];
+#pragma unroll
+                for (int r = k + 1; r < SM; ++r) {
+                    if (r < s) {
+                        FT mult = M[r][k] * inv;
+                        M[r][k] = mult;               // keep L for refinement
+#pragma unroll
+                        for (int q = k + 1; q < SM; ++q) M[r][q] -= mult * M[k][q];
+                        fw[r] -= mult * fw[k];
+                    }
+                }
+            }
+        }
+    }
+    if (singular) {
+        flags[c] = 1;
+        sing[atomicAdd(nsing, 1)] = c;
+        return;
+    }
+    double z[SM];
+#pragma unroll
+    for (int k = SM - 1; k >= 0; --k) {
+        if (k < s) {
+            FT acc = fw[k];
+#pragma unroll
+            for (int q = k + 1; q < SM; ++q)
+                if (q < s) acc -= M[k][q] * (FT)z[q];
+            z[k] = (double)(acc / M[k][k]);
+        } else {
+            z[k] = 0.0;
+        }
+    }
+    if (MIXED) {
+        // residual r_p = f_p - sum_q a(l_q, l_p) z_q in double
+        double res[SM];
+#pragma unroll
+        for (int p = 0; p < SM; ++p) res[p] = f[p];
+#pragma unroll
+        for (int q = 0; q < SM; ++q) {
+            if (q < s) {
+                int r = li[q];
+                double zq = z[q];
+                for (int e = rp[r]; e < rp[r + 1]; ++e) {
+                    int col = cj[e];
+                    double a = v[e];
+#pragma unroll
+                    for (int p = 0; p < SM; ++p)
+                        if (li[p] == col) res[p] -= a * zq;
+                }
+            }
+        }
+        // solve with the float factors: apply the row permutation, L, U
+        FT w[SM];
+#pragma unroll
+        for (int k = 0; k < SM; ++k) {
+            FT acc = (FT)0;
+#pragma unroll
+            for (int p = 0; p < SM; ++p)
+                if (perm[k] == p) acc = (FT)res[p];
+            w[k] = acc;
+        }
+#pragma unroll
+        for (int k = 0; k < SM; ++k)
+#pragma unroll
+            for (int r = k + 1; r < SM; ++r)
+                if (r < s) w[r] -= M[r][k] * w[k];
+#pragma unroll
+        for (int k = SM - 1; k >= 0; --k) {
+            if (k < s) {
+                FT acc = w[k];
+#pragma unroll
+                for (int q = k + 1; q < SM; ++q)
+                    if (q < s) acc -= M[k][q] * w[q];
+                w[k] = acc / M[k][k];
+                z[k] += (double)w[k];
+            }
+        }
+    }
+    int32_t lw[SM];
+#pragma unroll
+    for (int q = 0; q < SM; ++q) lw[q] = li[q];
+    // sorted write of the R row
+    int ip = 0;
+#pragma unroll
+    for (int q = 0; q < SM; ++q) ip += (q < s && lw[q] < i) ? 1 : 0;
+#pragma unroll
+    for (int q = 0; q < SM; ++q) {
+        if (q < s) {
+            int o = rbase + q + (q >= ip ? 1 : 0);
+            r_cj[o] = lw[q];
+            r_v[o] = z[q];
+        }
+    }
+    r_cj[rbase + ip] = i;
+    r_v[rbase + ip] = 1.0;
+}
+
+// One wave per system (blockDim = 64).  M lives in LDS when s <= WSMAX, else
+// in a global scratch slab of smax^2 doubles per block.
+constexpr int WSMAX = 48;
+
+template <bool MIXED>
+__global__ void __launch_bounds__(64)
+k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
+             const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
+             const int32_t *cj, const double *v, int32_t *r_cj, double *r_v,
+             int8_t *flags, int32_t *sing, int32_t *nsing, double *gscratch,
+             int32_t smax) {
+    using FT = typename std::conditional<MIXED, float, double>::type;
+    __shared__ FT sM[WSMAX * WSMAX];
+    __shared__ double sf[WSMAX];
+    __shared__ FT sw[WSMAX];
+    __shared__ int32_t sl[WSMAX];
+    __shared__ int32_t sperm[WSMAX];
+    __shared__ double sz[WSMAX];
+    int lane = threadIdx.x;
+    int32_t b = blockIdx.x;
+    if (b >= nlist) return;
+    int32_t c = list[b];
+    int32_t i = clist[c];
+    int32_t n0 = nptr[c];
+    int s = nptr[c + 1] - n0;
+    int32_t rbase = n0 + c;
+    const int32_t *l = nbr + n0;
+    bool in_lds = (s <= WSMAX);
+    FT *M = in_lds ? sM : (FT *)(gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3);
+    double *f = in_lds ? sf : (double *)(gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3 + (size_t)smax * smax);
+    FT *w = in_lds ? sw : (FT *)(f + smax);
+    int32_t *ln = in_lds ? sl : (int32_t *)(w + smax);
+    int32_t *perm = in_lds ? sperm : (ln + smax);
+    double *z = in_lds ? sz : (double *)(gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3 + 2 * (size_t)smax * smax);
+    for (int idx = lane; idx < s * s; idx += 64) M[idx] = (FT)0;
+    for (int p = lane; p < s; p += 64) { f[p] = 0.0; ln[p] = l[p]; perm[p] = p; }
+    __syncthreads();
+    for (int p = lane; p < s; p += 64) {
+        int r = ln[p];
+        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+            int q = bsearch_i32(ln, s, cj[e]);
+            if (q >= 0) M[q * s + p] = (FT)v[e];
+        }
+    }
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+        int p = bsearch_i32(ln, s, cj[e]);
+        if (p >= 0) f[p] = -v[e];
+    }
+    __syncthreads();
+    double rs = 0.0;
+    for (int p = lane; p < s; p += 64) {
+        double a = 0.0;
+        for (int q = 0; q < s; ++q) a += fabs((double)M[p * s + q]);
+        rs = fmax(rs, a);
+    }
+    double tol = SING_TOL * team_max<64>(rs);
+    for (int p = lane; p < s; p += 64) w[p] = (FT)f[p];
+    __syncthreads();
+    bool singular = false;
+    for (int k = 0; k < s; ++k) {
+        double pv = -1.0;
+        int pr = INT_MAX;
+        for (int r = k + lane; r < s; r += 64) {
+            double a = fabs((double)M[r * s + k]);
+            if (a > pv) { pv = a; pr = r; }
+        }
+        team_argmax<64>(pv, pr);
+        if (pv <= tol) { singular = true; break; }
+        if (pr != k) {
+            for (int q = lane; q < s; q += 64) {
+                FT t = M[k * s + q]; M[k * s + q] = M[pr * s + q]; M[pr * s + q] = t;
+            }
+            if (lane == 0) {
+                FT t = w[k]; w[k] = w[pr]; w[pr] = t;
+                int tp = perm[k]; perm[k] = perm[pr]; perm[pr] = tp;
+            }
+        }
+        __syncthreads();
+        FT inv = (FT)1 / M[k * s + k];
+        for (int r = k + 1 + lane; r < s; r += 64) {
+            FT mult = M[r * s + k] * inv;
+            M[r * s + k] = mult;
+            w[r] -= mult * w[k];
+        }
+        __syncthreads();
+        int wdt = s - k - 1;
+        for (int idx = lane; idx < wdt * wdt; idx += 64) {
+            int r = k + 1 + idx / wdt;
+            int q = k + 1 + idx % wdt;
+            M[r * s + q] -= M[r * s + k] * M[k * s + q];
+        }
+        __syncthreads();
+    }
+    if (singular) {
+        if (lane == 0) {
+            flags[c] = 1;
+            sing[atomicAdd(nsing, 1)] = c;
+        }
+        return;
+    }
+    // back substitution, column oriented: z_k = w_k / u_kk; w_r -= u_rk z_k
+    for (int k = s - 1; k >= 0; --k) {
+        FT zk = w[k] / M[k * s + k];
+        __syncthreads();
+        if (lane == 0) z[k] = (double)zk;
+        for (int r = lane; r < k; r += 64) w[r] -= M[r * s + k] * zk;
+        __syncthreads();
+    }
+    if (MIXED) {
+        // r = f - M z in double via the rows of A, then z += LU^{-1} r
+        __syncthreads();
+        double *res = f;      // f is not needed after this point
+        // lane p owns res[p] = f[p] - sum_q a(l_q, l_p) z_q and searches
+        // column l_p in every row l_q (no two lanes write the same entry)
+        for (int p = lane; p < s; p += 64) {
+            double acc = res[p];
+            int lp = ln[p];
+            for (int q = 0; q < s; ++q) {
+                int r = ln[q];
+                // a(l_q, l_p): search column l_p in row l_q
+                int lo = rp[r], hi = rp[r + 1] - 1;
+                while (lo <= hi) {
+                    int mid = (lo + hi) >> 1;
+                    int cc = cj[mid];
+                    if (cc == lp) { acc -= v[mid] * z[q]; break; }
+                    if (cc < lp) lo = mid + 1; else hi = mid - 1;
+                }
+            }
+            w[p] = (FT)0;
+            res[p] = acc;
+        }
+        __syncthreads();
+        for (int k = lane; k < s; k += 64) w[k] = (FT)res[perm[k]];
+        __syncthreads();
+        for (int k = 0; k < s; ++k) {
+            FT wk = w[k];
+            for (int r = k + 1 + lane; r < s; r += 64) w[r] -= M[r * s + k] * wk;
+            __syncthreads();
+        }
+        for (int k = s - 1; k >= 0; --k) {
+            FT zk = w[k] / M[k * s + k];
+            __syncthreads();
+            if (lane == 0) z[k] += (double)zk;
+            for (int r = lane; r < k; r += 64) w[r] -= M[r * s + k] * zk;
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    int ip = 0;
+    for (int q = lane; q < s; q += 64) ip += (ln[q] < i) ? 1 : 0;
+    ip = team_sum_int<64>(ip);
+    for (int q = lane; q < s; q += 64) {
+        int o = rbase + q + (q >= ip ? 1 : 0);
+        r_cj[o] = ln[q];
+        r_v[o] = z[q];
+    }
+    if (lane == 0) {
+        r_cj[rbase + ip] = i;
+        r_v[rbase + ip] = 1.0;
+    }
+}
+
+// Minimal-norm least squares for flagged systems (footnote of Sec. 3.1):
+// one-sided Jacobi SVD, W = M V with orthogonal columns, then
+// z = sum_{sigma_j > cut} (w_j . f / sigma_j^2) v_j, cut = eps s sigma_max.
+// One wave per system, W and V column-major in global scratch.
+__global__ void __launch_bounds__(64)
+k_local_lstsq(const int32_t *list, int32_t nlist, const int32_t *clist,
+              const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
+              const int32_t *cj, const double *v, int32_t *r_cj, double *r_v,
+              double *gscratch, int32_t smax) {
+    int lane = threadIdx.x;
+    int32_t b = blockIdx.x;
+    if (b >= nlist) return;
+    int32_t c = list[b];
+    int32_t i = clist[c];
+    int32_t n0 = nptr[c];
+    int s = nptr[c + 1] - n0;
+    int32_t rbase = n0 + c;
+    const int32_t *l = nbr + n0;
+    size_t ss = (size_t)smax * smax;
+    double *W = gscratch + (size_t)b * (2 * ss + 2 * (size_t)smax);
+    double *V = W + ss;
+    double *f = V + ss;
+    double *z = f + smax;
+    for (int idx = lane; idx < s * s; idx += 64) {
+        W[idx] = 0.0;
+        V[idx] = ((idx % s) == (idx / s)) ? 1.0 : 0.0;
+    }
+    for (int p = lane; p < s; p += 64) { f[p] = 0.0; z[p] = 0.0; }
+    __syncthreads();
+    // W column p, row q = M[q][p] = a(l_p, l_q)  (column-major: W[p*s + q])
+    for (int p = lane; p < s; p += 64) {
+        int r = l[p];
+        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+            int q = bsearch_i32(l, s, cj[e]);
+            if (q >= 0) W[p * s + q] = v[e];
+        }
+    }
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+        int p = bsearch_i32(l, s, cj[e]);
+        if (p >= 0) f[p] = -v[e];
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        int rotated = 0;
+        for (int j = 0; j < s - 1; ++j) {
+            for (int k = j + 1; k < s; ++k) {
+                double a = 0.0, bb = 0.0, g = 0.0;
+                for (int q = lane; q < s; q += 64) {
+                    double wj = W[j * s + q], wk = W[k * s + q];
+                    a += wj * wj; bb += wk * wk; g += wj * wk;
+                }
+                a = team_sum<64>(a); bb = team_sum<64>(bb); g = team_sum<64>(g);
+                if (fabs(g) <= DBL_EPSILON * sqrt(a * bb) || g == 0.0) continue;
+                rotated = 1;
+                double zeta = (bb - a) / (2.0 * g);
+                double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                for (int q = lane; q < s; q += 64) {
+                    double wj = W[j * s + q], wk = W[k * s + q];
+                    W[j * s + q] = cs * wj - sn * wk;
+                    W[k * s + q] = sn * wj + cs * wk;
+                    double vj = V[j * s + q], vk = V[k * s + q];
+                    V[j * s + q] = cs * vj - sn * vk;
+                    V[k * s + q] = sn * vj + cs * vk;
+                }
+                __syncthreads();
+            }
+        }
+        if (!rotated) break;
+    }
+    double smx = 0.0;
+    for (int j = 0; j < s; ++j) {
+        double a = 0.0;
+        for (int q = lane; q < s; q += 64) a += W[j * s + q] * W[j * s + q];
+        a = team_sum<64>(a);
+        smx = fmax(smx, sqrt(a));
+    }
+    double cut = DBL_EPSILON * (double)s * smx;
+    for (int j = 0; j < s; ++j) {
+        double a = 0.0, d = 0.0;
+        for (int q = lane; q < s; q += 64) {
+            double wj = W[j * s + q];
+            a += wj * wj;
+            d += wj * f[q];
+        }
+        a = team_sum<64>(a);
+        d = team_sum<64>(d);
+        if (sqrt(a) <= cut) continue;
+        double coef = d / a;
+        for (int q = lane; q < s; q += 64) z[q] += coef * V[j * s + q];
+        __syncthreads();
+    }
+    __syncthreads();
+    int ip = 0;
+    for (int q = lane; q < s; q += 64) ip += (l[q] < i) ? 1 : 0;
+    ip = team_sum_int<64>(ip);
+    for (int q = lane; q < s; q += 64) {
+        int o = rbase + q + (q >= ip ? 1 : 0);
+        r_cj[o] = l[q];
+        r_v[o] = z[q];
+    }
+    if (lane == 0) {
+        r_cj[rbase + ip] = i;
+        r_v[rbase + ip] = 1.0;
+    }
+}
+
+constexpr int SMALL_SM = 8;
+
+int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
+                     const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+                     const double *v, int32_t precision, int32_t smax,
+                     LocalSolveOut out, hipStream_t s) {
+    if (nc == 0) return 0;
+    DevArr<int32_t> big, sing, counters;
+    big.alloc((size_t)nc, s);
+    sing.alloc((size_t)nc, s);
+    counters.alloc(2, s);
+    LAIR_HIP(hipMemsetAsync(counters.get(), 0, 2 * sizeof(int32_t), s));
+    bool mixed = (precision == LAIR_MIXED);
+    if (smax <= 4) {
+        if (mixed)
+            hipLaunchKernelGGL((k_local_small<4, true>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
+                               big.get(), counters.get(), sing.get(), counters.get() + 1);
+        else
+            hipLaunchKernelGGL((k_local_small<4, false>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
+                               big.get(), counters.get(), sing.get(), counters.get() + 1);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_local_small<SMALL_SM, true>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
+                               big.get(), counters.get(), sing.get(), counters.get() + 1);
+        else
+            hipLaunchKernelGGL((k_local_small<SMALL_SM, false>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
+                               big.get(), counters.get(), sing.get(), counters.get() + 1);
+    }
+    LAIR_LAUNCH_CHECK();
+    int32_t h[2];
+    LAIR_HIP(hipMemcpyAsync(h, counters.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    int32_t nbig = h[0];
+    if (nbig > 0) {
+        DevArr<double> scratch;
+        if (smax > WSMAX) scratch.alloc((size_t)nbig * (size_t)smax * smax * 3 + 16, s);
+        if (mixed)
+            hipLaunchKernelGGL((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), 0, s,
+                               big.get(), nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
+                               out.flags, sing.get(), counters.get() + 1, scratch.get(), smax);
+        else
+            hipLaunchKernelGGL((k_local_wave<false>), dim3((unsigned)nbig), dim3(64), 0, s,
+                               big.get(), nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
+                               out.flags, sing.get(), counters.get() + 1, scratch.get(), smax);
+        LAIR_LAUNCH_CHECK();
+        LAIR_HIP(hipMemcpyAsync(h, counters.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+    }
+    int32_t nsing = h[1];
+    if (nsing > 0) {
+        DevArr<double> scratch;
+        scratch.alloc((size_t)nsing * (2 * (size_t)smax * smax + 2 * (size_t)smax), s);
+        hipLaunchKernelGGL(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
+                           sing.get(), nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
+                           out.r_v, scratch.get(), smax);
+        LAIR_LAUNCH_CHECK();
+        LAIR_HIP(hipStreamSynchronize(s));
+    }
+    return nsing;
+}
+
+// ===========================================================================
+// Interpolation.
+// ===========================================================================
+// One-point (Sec. 4): F-point i takes the value at its strongest C-neighbour
+// (largest |a_ij| over strong C entries, smallest j on a tie); C-points
+// inject.  pcol[i] = coarse column or -1.
+__global__ void k_interp_1p(int32_t n, const int32_t *rp, const int32_t *cj,
+                            const double *v, const uint8_t *sm,
+                            const int8_t *cf, const int32_t *cidx,
+                            int32_t *pcol) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == 1) { pcol[i] = cidx[i]; return; }
+    int best = -1;
+    double bv = -1.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = cj[p];
+        if (!sm[p] || cf[j] != 1) continue;
+        double a = fabs(v[p]);
+        if (a > bv) { bv = a; best = j; }
+    }
+    pcol[i] = best >= 0 ? cidx[best] : -1;
+}
+
+void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
+                             const double *v, const uint8_t *smask,
+                             const int8_t *cf, const int32_t *cidx,
+                             int32_t *pcol, hipStream_t s) {
+    hipLaunchKernelGGL(k_interp_1p, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       n, rp, cj, v, smask, cf, cidx, pcol);
+    LAIR_LAUNCH_CHECK();
+}
+
+__global__ void k_compact_1p(int32_t n, const int32_t *pcol, const int32_t *prp,
+                             int32_t *pcj, double *pv) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (pcol[i] >= 0) {
+        pcj[prp[i]] = pcol[i];
+        pv[prp[i]] = 1.0;
+    }
+}
+
+void launch_compact_one_point(int32_t n, const int32_t *pcol,
+                              const int32_t *prp, int32_t *pcj, double *pv,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_1p, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       n, pcol, prp, pcj, pv);
+    LAIR_LAUNCH_CHECK();
+}
+
+// Classical direct interpolation (Stueben 2001): for F-point i with
+// P_i = S_i n C, alpha = sum_{j!=i} a_ij^- / sum_{P_i} a_ik^-, beta likewise
+// for positive entries, w_ik = -(alpha or beta) a_ik / a_ii; a sign class
+// missing from P_i is lumped into the diagonal.  Columns follow A's order,
+// which is increasing in coarse index.
+__global__ void k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
+                                const double *v, const uint8_t *sm,
+                                const int8_t *cf, const int32_t *cidx,
+                                bool fill, int32_t *cnt, const int32_t *prp,
+                                int32_t *pcj, double *pv) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == 1) {
+        if (!fill) cnt[i] = 1;
+        else { pcj[prp[i]] = cidx[i]; pv[prp[i]] = 1.0; }
+        return;
+    }
+    double diag = 0.0, sn = 0.0, sp = 0.0, pn = 0.0, pp = 0.0;
+    int k = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = cj[p];
+        double a = v[p];
+        if (j == i) { diag = a; continue; }
+        if (a < 0.0) sn += a; else sp += a;
+        if (sm[p] && cf[j] == 1) {
+            if (a < 0.0) pn += a; else pp += a;
+            ++k;
+        }
+    }
+    double d = diag;
+    if (pn == 0.0) d += sn;
+    if (pp == 0.0) d += sp;
+    if (k == 0 || d == 0.0) {
+        if (!fill) cnt[i] = 0;
+        return;
+    }
+    if (!fill) { cnt[i] = k; return; }
+    double alpha = (pn != 0.0) ? sn / pn : 0.0;
+    double beta = (pp != 0.0) ? sp / pp : 0.0;
+    int o = prp[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = cj[p];
+        if (j == i || !sm[p] || cf[j] != 1) continue;
+        double a = v[p];
+        pcj[o] = cidx[j];
+        pv[o] = -(a < 0.0 ? alpha : beta) * a / d;
+        ++o;
+    }
+}
+
+void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
+                          const double *v, const uint8_t *smask,
+                          const int8_t *cf, const int32_t *cidx, bool fill,
+                          int32_t *cnt, const int32_t *prp, int32_t *pcj,
+                          double *pv, hipStream_t s) {
+    hipLaunchKernelGGL(k_interp_direct, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       n, rp, cj, v, smask, cf, cidx, fill, cnt, prp, pcj, pv);
+    LAIR_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Row-merge sparse product C = A B, symbolic pattern.  One team of T lanes
+// per row of A; the row's entries select rows of B (sorted lists) that are
+// merged in increasing column order.  List k belongs to lane k % T, slot
+// k / T (LPL slots per lane).  The value of each output column is a
+// fixed-order team sum.
+// ===========================================================================
+template <int T, int LPL, bool FILL>
+__global__ void k_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
+                         const double *ax, const int32_t *bp,
+                         const int32_t *bj, const double *bx, int32_t *cnt,
+                         const int32_t *cp, int32_t *cj, double *cx,
+                         int32_t *overflow) {
+    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)(gt / T);
+    int lane = (int)(gt % T);
+    if (i >= m) return;
+    int lo = ap[i], ka = ap[i + 1] - lo;
+    if (ka > T * LPL) {
+        if (lane == 0) { atomicOr(overflow, 1); if (!FILL) cnt[i] = 0; }
+        return;
+    }
+    int pos[LPL], end[LPL], head[LPL];
+    double mul[LPL];
+#pragma unroll
+    for (int s = 0; s < LPL; ++s) {
+        int k = lane + s * T;
+        if (k < ka) {
+            int r = aj[lo + k];
+            pos[s] = bp[r];
+            end[s] = bp[r + 1];
+            mul[s] = FILL ? ax[lo + k] : 0.0;
+        } else {
+            pos[s] = 0; end[s] = 0; mul[s] = 0.0;
+        }
+        head[s] = (pos[s] < end[s]) ? bj[pos[s]] : INT_MAX;
+    }
+    int o = FILL ? cp[i] : 0;
+    for (;;) {
+        int h = INT_MAX;
+#pragma unroll
+        for (int s = 0; s < LPL; ++s) h = min(h, head[s]);
+        int mn = team_min<T>(h);
+        if (mn == INT_MAX) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < LPL; ++s) {
+            if (head[s] == mn) {
+                if (FILL) acc += mul[s] * bx[pos[s]];
+                ++pos[s];
+                head[s] = (pos[s] < end[s]) ? bj[pos[s]] : INT_MAX;
+            }
+        }
+        if (FILL) {
+            acc = team_sum<T>(acc);
+            if (lane == 0) { cj[o] = mn; cx[o] = acc; }
+        }
+        ++o;
+    }
+    if (!FILL && lane == 0) cnt[i] = o;
+}
+
+template <int T, int LPL>
+static void spgemm_t(int32_t m, const int32_t *ap, const int32_t *aj,
+                     const double *ax, const int32_t *bp, const int32_t *bj,
+                     const double *bx, bool fill, int32_t *cnt,
+                     const int32_t *cp, int32_t *cj, double *cx,
+                     int32_t *overflow, hipStream_t s) {
+    dim3 g(blocks_for((int64_t)m * T, 256)), b(256);
+    if (fill)
+        hipLaunchKernelGGL((k_spgemm<T, LPL, true>), g, b, 0, s, m, ap, aj, ax, bp, bj, bx,
+                           cnt, cp, cj, cx, overflow);
+    else
+        hipLaunchKernelGGL((k_spgemm<T, LPL, false>), g, b, 0, s, m, ap, aj, ax, bp, bj, bx,
+                           cnt, cp, cj, cx, overflow);
+    LAIR_LAUNCH_CHECK();
+}
+
+// Rows of A with more than 64 * 16 = 1024 entries are rejected (overflow).
+void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
+                   const double *ax, const int32_t *bp, const int32_t *bj,
+                   const double *bx, int32_t max_row_a, bool fill,
+                   int32_t *cnt, const int32_t *cp, int32_t *cj, double *cx,
+                   int32_t *overflow, hipStream_t s) {
+    if (m == 0) return;
+    if (max_row_a <= 16) spgemm_t<4, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    else if (max_row_a <= 32) spgemm_t<8, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    else if (max_row_a <= 64) spgemm_t<16, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    else if (max_row_a <= 128) spgemm_t<32, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    else if (max_row_a <= 256) spgemm_t<64, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    else if (max_row_a <= 512) spgemm_t<64, 8>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    else spgemm_t<64, 16>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+}
+
+// ===========================================================================
+// Transpose (deterministic): count per column, scan, scatter with atomic
+// cursors, then sort each output row by column (the source row index).
+// ===========================================================================
+__global__ void k_tcount(int32_t nrows, const int32_t *rp, const int32_t *cj,
+                         int32_t *tcount) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(&tcount[cj[p]], 1);
+}
+
+__global__ void k_tscatter(int32_t nrows, const int32_t *rp, const int32_t *cj,
+                           const double *v, const int32_t *trp,
+                           int32_t *cursor, int32_t *tcj, double *tv) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int c = cj[p];
+        int o = trp[c] + atomicAdd(&cursor[c], 1);
+        tcj[o] = i;
+        tv[o] = v[p];
+    }
+}
+
+__global__ void k_tsort(int32_t ncols, const int32_t *trp, int32_t *tcj,
+                        double *tv) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ncols) return;
+    int lo = trp[r], hi = trp[r + 1];
+    for (int a = lo + 1; a < hi; ++a) {
+        int kc = tcj[a];
+        double kv = tv[a];
+        int b = a - 1;
+        while (b >= lo && tcj[b] > kc) {
+            tcj[b + 1] = tcj[b];
+            tv[b + 1] = tv[b];
+            --b;
+        }
+        tcj[b + 1] = kc;
+        tv[b + 1] = kv;
+    }
+}
+
+void launch_transpose(int32_t nrows, int32_t ncols, int64_t nnz,
+                      const int32_t *rp, const int32_t *cj, const double *v,
+                      int32_t *tcount, int32_t *trp, int32_t *tcj, double *tv,
+                      int32_t *cursor, hipStream_t s, DevArr<int64_t> &tmp) {
+    (void)nnz;
+    LAIR_HIP(hipMemsetAsync(tcount, 0, sizeof(int32_t) * (size_t)ncols, s));
+    LAIR_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (size_t)ncols, s));
+    hipLaunchKernelGGL(k_tcount, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+                       nrows, rp, cj, tcount);
+    LAIR_LAUNCH_CHECK();
+    scan_counts_i32(tcount, trp, ncols, s, tmp);
+    hipLaunchKernelGGL(k_tscatter, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+                       nrows, rp, cj, v, trp, cursor, tcj, tv);
+    LAIR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_tsort, dim3(blocks_for(ncols, 256)), dim3(256), 0, s,
+                       ncols, trp, tcj, tv);
+    LAIR_LAUNCH_CHECK();
+}
+
+__global__ void k_to_float(const double *in, float *out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_to_float, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       in, out, n);
+    LAIR_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Block-diagonal inverse (Sec. 4.2.1): one lane per k x k diagonal block,
+// Gauss-Jordan with partial pivoting.  bad = 1 for a singular block.
+// ===========================================================================
+constexpr int BLK_MAX = 8;
+
+__global__ void k_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
+                                const int32_t *cj, const double *v,
+                                double *dinv, int32_t *bad) {
+    int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nblk) return;
+    double a[BLK_MAX][2 * BLK_MAX];
+    for (int r = 0; r < k; ++r)
+        for (int q = 0; q < 2 * k; ++q) a[r][q] = (q == k + r) ? 1.0 : 0.0;
+    int b0 = e * k;
+    for (int r = 0; r < k; ++r) {
+        int row = b0 + r;
+        for (int p = rp[row]; p < rp[row + 1]; ++p) {
+            int c = cj[p] - b0;
+            if (c >= 0 && c < k) a[r][c] = v[p];
+        }
+    }
+    for (int col = 0; col < k; ++col) {
+        int pr = col;
+        double pv = fabs(a[col][col]);
+        for (int r = col + 1; r < k; ++r)
+            if (fabs(a[r][col]) > pv) { pv = fabs(a[r][col]); pr = r; }
+        if (pv == 0.0) { atomicOr(bad, 1); return; }
+        if (pr != col)
+            for (int q = 0; q < 2 * k; ++q) { double t = a[col][q]; a[col][q] = a[pr][q]; a[pr][q] = t; }
+        double inv = 1.0 / a[col][col];
+        for (int q = 0; q < 2 * k; ++q) a[col][q] *= inv;
+        for (int r = 0; r < k; ++r) {
+            if (r == col) continue;
+            double f = a[r][col];
+            if (f == 0.0) continue;
+            for (int q = 0; q < 2 * k; ++q) a[r][q] -= f * a[col][q];
+        }
+    }
+    for (int r = 0; r < k; ++r)
+        for (int q = 0; q < k; ++q) dinv[(size_t)e * k * k + r * k + q] = a[r][k + q];
+}
+
+void launch_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
+                          const int32_t *cj, const double *v, double *dinv,
+                          int32_t *bad, hipStream_t s) {
+    if (k > BLK_MAX) fail(LAIR_EUNSUPPORTED, "block size %d > %d", k, BLK_MAX);
+    hipLaunchKernelGGL(k_block_inverse, dim3(blocks_for(nblk, 64)), dim3(64), 0, s,
+                       nblk, k, rp, cj, v, dinv, bad);
+    LAIR_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Coarsest grid: dense copy and LU with partial pivoting (one block).
+// ===========================================================================
+__global__ void k_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj,
+                                 const double *v, double *dense) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double *row = dense + (size_t)i * n;
+    for (int q = 0; q < n; ++q) row[q] = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) row[cj[p]] = v[p];
+}
+
+void launch_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj,
+                           const double *v, double *dense, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_from_csr, dim3(blocks_for(n, 64)), dim3(64), 0, s,
+                       n, rp, cj, v, dense);
+    LAIR_LAUNCH_CHECK();
+}
+
+__global__ void __launch_bounds__(1024)
+k_dense_lu(int32_t n, double *a, int32_t *piv, int32_t *info) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    int t = threadIdx.x;
+    int nt = blockDim.x;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = INT_MAX;
+        for (int r = k + t; r < n; r += nt) {
+            double x = fabs(a[(size_t)r * n + k]);
+            if (x > best || (x == best && r < bi)) { best = x; bi = r; }
+        }
+        sv[t] = best;
+        si[t] = bi;
+        __syncthreads();
+        for (int o = nt / 2; o > 0; o >>= 1) {
+            if (t < o) {
+                double ov = sv[t + o];
+                int oi = si[t + o];
+                if (ov > sv[t] || (ov == sv[t] && oi < si[t])) { sv[t] = ov; si[t] = oi; }
+            }
+            __syncthreads();
+        }
+        int pr = si[0];
+        double pv = sv[0];
+        __syncthreads();
+        if (pv == 0.0) {
+            if (t == 0) *info = k + 1;
+            return;
+        }
+        if (t == 0) piv[k] = pr;
+        if (pr != k)
+            for (int q = t; q < n; q += nt) {
+                double x = a[(size_t)k * n + q];
+                a[(size_t)k * n + q] = a[(size_t)pr * n + q];
+                a[(size_t)pr * n + q] = x;
+            }
+        __syncthreads();
+        double inv = 1.0 / a[(size_t)k * n + k];
+        for (int r = k + 1 + t; r < n; r += nt) a[(size_t)r * n + k] *= inv;
+        __syncthreads();
+        int w = n - k - 1;
+        for (int64_t idx = t; idx < (int64_t)w * w; idx += nt) {
+            int r = k + 1 + (int)(idx / w);
+            int q = k + 1 + (int)(idx % w);
+            a[(size_t)r * n + q] -= a[(size_t)r * n + k] * a[(size_t)k * n + q];
+        }
+        __syncthreads();
+    }
+    if (t == 0) *info = 0;
+}
+
+void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,
+                     hipStream_t s) {
+    int bs = 64;
+    while (bs < 1024 && bs < n) bs <<= 1;
+    hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(bs), 0, s, n, lu, piv, info);
+    LAIR_LAUNCH_CHECK();
+}
+
+}  // namespace lair

@@ -1,0 +1,970 @@
+// liblair host side: argument checking, the level loop of the setup, the
+// V-cycle schedule and the outer iteration.  Every arithmetic step runs in
+// the HIP kernels of k_setup.hip and k_cycle.hip; the host only sizes
+// buffers, launches, and (for the classical CF splitting, a sequential
+// greedy algorithm) runs rs_first_pass on a host copy of the strength mask.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "lair_internal.hpp"
+
+namespace lair {
+
+void rs_first_pass(int64_t n, const int32_t *rp, const int32_t *cj,
+                   const uint8_t *sm, int8_t *cf);
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+void fail(lair_status st, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    throw Error{st, std::string(buf)};
+}
+
+// ---------------------------------------------------------------------------
+// Hierarchy storage
+// ---------------------------------------------------------------------------
+struct Level {
+    DevCSR A, R, P;            // A_l (n x n), R_l (nc x n), P_l (n x nc)
+    DevCSR At, Rt, Pt;         // transposes for the adjoint cycle
+    int32_t n = 0, nc = 0, nf = 0;
+    int32_t max_row = 0;
+    int32_t team_A = 8, team_R = 8, team_P = 2;
+    int32_t team_At = 8, team_Rt = 2, team_Pt = 8;
+    DevArr<int8_t> cf;
+    DevArr<uint8_t> smask;
+    DevArr<int32_t> cidx, clist, flist, nptr, nbr;
+    DevArr<int8_t> flags;
+    lair_level_stats st{};
+    // cycle work vectors (capacity h->nrhs_cap right-hand sides)
+    DevArr<double> b, x, t, r;
+    DevArr<float> b32, x32, t32, r32;
+};
+
+}  // namespace lair
+
+struct lair_hierarchy {
+    std::vector<std::unique_ptr<lair::Level>> L;
+    lair_strength str{};
+    lair_options opt{};
+    hipStream_t stream = nullptr;
+    int32_t nL = 0;                          // coarsest size
+    lair::DevArr<double> lu;
+    lair::DevArr<int32_t> piv;
+    lair::DevArr<double> dinv;               // block scaling (block_size > 0)
+    int32_t nrhs_cap = 0;
+    lair::DevArr<double> bscaled, r0, partial, norms;
+    lair::DevArr<float> r0_32, e32;
+    bool have_transpose = false;
+    int64_t n_singular = 0;
+    double setup_ms = 0.0;
+    double cc = 0.0, oc = 0.0;
+};
+
+namespace lair {
+
+using Clock = std::chrono::steady_clock;
+
+static double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+static int32_t team_of(const DevCSR &M) {
+    double mean = M.nrows ? (double)M.nnz / (double)M.nrows : 1.0;
+    int t = 1;
+    while (t < 64 && t < mean) t <<= 1;
+    return t;
+}
+
+template <class VT>
+static CsrView<VT> view(const DevCSR &M, int32_t team) {
+    CsrView<VT> v;
+    v.nrows = M.nrows;
+    v.ncols = M.ncols;
+    v.rp = M.rp.get();
+    v.cj = M.cj.get();
+    if constexpr (std::is_same<VT, double>::value) v.v = M.v.get();
+    else v.v = M.v32.get();
+    v.team = team;
+    return v;
+}
+
+static const int32_t NPARTIAL = 1024;
+
+// max over an int32 device array (small helper kernel)
+__global__ void k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(out, a[i]);
+}
+
+__global__ void k_nonneg_flag(int32_t n, const int32_t *pc, int32_t *hs) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) hs[i] = pc[i] >= 0 ? 1 : 0;
+}
+
+__global__ void k_add(double *x, const double *e, int64_t m) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) x[i] += e[i];
+}
+
+__global__ void k_r_rowptr(int32_t nc, const int32_t *nptr, int32_t *rrp) {
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c <= nc) rrp[c] = nptr[c] + c;
+}
+
+__global__ void k_block_diag_csr(int32_t nblk, int32_t k, const double *dinv,
+                                 int32_t *rp, int32_t *cj, double *v) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)nblk * k;
+    if (g <= n) rp[g] = (int32_t)(g * k);
+    if (g >= n * k) return;
+    int64_t row = g / k;
+    int c = (int)(g % k);
+    cj[g] = (int32_t)((row / k) * k + c);
+    v[g] = dinv[(row / k) * k * k + (row % k) * k + c];
+}
+
+static int32_t device_max(const int32_t *a, int64_t n, hipStream_t s) {
+    if (n == 0) return 0;
+    DevArr<int32_t> m;
+    m.alloc(1, s);
+    LAIR_HIP(hipMemsetAsync(m.get(), 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_max_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, n, m.get());
+    LAIR_LAUNCH_CHECK();
+    int32_t h = 0;
+    LAIR_HIP(hipMemcpyAsync(&h, m.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// C = A B with the symbolic pattern.
+static void spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
+                   DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
+    C.nrows = A.nrows;
+    C.ncols = B.ncols;
+    DevArr<int32_t> cnt, over;
+    cnt.alloc((size_t)A.nrows + 1, s);
+    over.alloc(1, s);
+    LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
+    launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
+                  B.v.get(), max_row_a, false, cnt.get(), nullptr, nullptr, nullptr,
+                  over.get(), s);
+    C.rp.alloc((size_t)A.nrows + 1, s);
+    C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), A.nrows, s, tmp);
+    int32_t ov = 0;
+    LAIR_HIP(hipMemcpyAsync(&ov, over.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
+    C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
+    C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
+    launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
+                  B.v.get(), max_row_a, true, nullptr, C.rp.get(), C.cj.get(), C.v.get(),
+                  over.get(), s);
+}
+
+static void transpose(const DevCSR &M, DevCSR &T, hipStream_t s,
+                      DevArr<int64_t> &tmp) {
+    T.nrows = M.ncols;
+    T.ncols = M.nrows;
+    T.nnz = M.nnz;
+    DevArr<int32_t> cnt, cur;
+    cnt.alloc((size_t)M.ncols + 1, s);
+    cur.alloc((size_t)M.ncols + 1, s);
+    T.rp.alloc((size_t)M.ncols + 1, s);
+    T.cj.alloc((size_t)std::max<int64_t>(M.nnz, 1), s);
+    T.v.alloc((size_t)std::max<int64_t>(M.nnz, 1), s);
+    launch_transpose(M.nrows, M.ncols, M.nnz, M.rp.get(), M.cj.get(), M.v.get(),
+                     cnt.get(), T.rp.get(), T.cj.get(), T.v.get(), cur.get(), s, tmp);
+    if (M.v32.get()) {
+        T.v32.alloc((size_t)std::max<int64_t>(M.nnz, 1), s);
+        launch_to_float(T.v.get(), T.v32.get(), T.nnz, s);
+    }
+}
+
+static void check_options(const lair_strength *s, const lair_options *o) {
+    if (!s || !o) fail(LAIR_EINVAL, "strength and options must not be NULL");
+    if (!(s->theta >= 0.0 && s->theta <= 1.0) || !(s->theta_c >= 0.0 && s->theta_c <= 1.0))
+        fail(LAIR_EINVAL, "strength thresholds must lie in [0, 1]");
+    if (s->kind != LAIR_SOC_ABS && s->kind != LAIR_SOC_NEG)
+        fail(LAIR_EINVAL, "unknown strength kind %d", s->kind);
+    if (s->distance != 1 && s->distance != 2 && s->distance != LAIR_DIST_ALL_F)
+        fail(LAIR_EINVAL, "distance must be 1, 2 or LAIR_DIST_ALL_F");
+    if (o->interp != LAIR_P_ONE_POINT && o->interp != LAIR_P_DIRECT)
+        fail(LAIR_EINVAL, "unknown interpolation %d", o->interp);
+    if (o->precision != LAIR_FP64 && o->precision != LAIR_MIXED)
+        fail(LAIR_EINVAL, "unknown precision %d", o->precision);
+    if (!(o->omega > 0.0 && o->omega <= 2.0)) fail(LAIR_EINVAL, "omega must lie in (0, 2]");
+    if (o->max_levels < 1 || o->max_levels > 64) fail(LAIR_EINVAL, "max_levels must lie in [1, 64]");
+    if (o->max_coarse < 1) fail(LAIR_EINVAL, "max_coarse must be >= 1");
+    if (!(o->stall > 0.0 && o->stall <= 1.0)) fail(LAIR_EINVAL, "stall must lie in (0, 1]");
+    if (o->block_size < 0 || o->block_size > 8) fail(LAIR_EINVAL, "block_size must lie in [0, 8]");
+}
+
+static const int32_t MAX_DENSE = 4096;
+
+// ---------------------------------------------------------------------------
+// Setup
+// ---------------------------------------------------------------------------
+static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
+                                 const lair_cf_levels *cfl, bool &coarsest,
+                                 DevArr<int64_t> &tmp) {
+    hipStream_t s = h->stream;
+    const int32_t n = Lv.n;
+    const DevCSR &A = Lv.A;
+    double mean = n ? (double)A.nnz / n : 1.0;
+    Lv.smask.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
+    launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta, h->str.kind,
+                    Lv.smask.get(), mean, s);
+    Lv.cf.alloc((size_t)n, s);
+    if (cfl && lvl < cfl->nlevels) {
+        int64_t lo = cfl->offs[lvl], hi = cfl->offs[lvl + 1];
+        if (hi - lo != n)
+            fail(LAIR_EINVAL, "CF splitting of level %d has %lld entries, level size is %d",
+                 lvl, (long long)(hi - lo), n);
+        for (int64_t k = lo; k < hi; ++k)
+            if (cfl->cf[k] != 0 && cfl->cf[k] != 1)
+                fail(LAIR_EINVAL, "CF splitting of level %d holds a value other than 0/1", lvl);
+        LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), cfl->cf + lo, (size_t)n, hipMemcpyHostToDevice, s));
+    } else {
+        // library's own classical first pass on a host copy of the pattern
+        const uint8_t *sm_dev = Lv.smask.get();
+        DevArr<uint8_t> smc;
+        if (h->str.theta_c != h->str.theta) {
+            smc.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
+            launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
+                            h->str.kind, smc.get(), mean, s);
+            sm_dev = smc.get();
+        }
+        std::vector<int32_t> hrp((size_t)n + 1), hcj((size_t)A.nnz);
+        std::vector<uint8_t> hsm((size_t)A.nnz);
+        std::vector<int8_t> hcf((size_t)n);
+        LAIR_HIP(hipMemcpyAsync(hrp.data(), A.rp.get(), sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        if (A.nnz) {
+            LAIR_HIP(hipMemcpyAsync(hcj.data(), A.cj.get(), sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, s));
+            LAIR_HIP(hipMemcpyAsync(hsm.data(), sm_dev, (size_t)A.nnz, hipMemcpyDeviceToHost, s));
+        }
+        LAIR_HIP(hipStreamSynchronize(s));
+        rs_first_pass(n, hrp.data(), hcj.data(), hsm.data(), hcf.data());
+        LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), hcf.data(), (size_t)n, hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+    }
+    DevArr<int32_t> scan;
+    scan.alloc((size_t)n + 1, s);
+    int64_t nc = scan_flags_i8(Lv.cf.get(), 1, scan.get(), n, s, tmp);
+    if (nc == 0 || (double)nc > h->opt.stall * (double)n) {
+        coarsest = true;
+        Lv.smask.release();
+        Lv.cf.release();
+        return;
+    }
+    Lv.nc = (int32_t)nc;
+    Lv.nf = n - Lv.nc;
+    Lv.cidx.alloc((size_t)n, s);
+    Lv.clist.alloc((size_t)Lv.nc, s);
+    Lv.flist.alloc((size_t)std::max(Lv.nf, 1), s);
+    launch_cf_lists(n, Lv.cf.get(), scan.get(), Lv.cidx.get(), Lv.clist.get(),
+                    Lv.flist.get(), s);
+
+    // neighbourhoods
+    DevArr<int32_t> cnt, over;
+    cnt.alloc((size_t)Lv.nc + 1, s);
+    over.alloc(1, s);
+    LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
+    launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
+                          Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, cnt.get(),
+                          nullptr, nullptr, over.get(), Lv.max_row, s);
+    Lv.nptr.alloc((size_t)Lv.nc + 1, s);
+    int64_t nn = scan_counts_i32(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp);
+    int32_t ov = 0;
+    LAIR_HIP(hipMemcpyAsync(&ov, over.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    if (ov) fail(LAIR_EUNSUPPORTED, "level %d: a distance-2 neighbourhood merges more than 256 rows", lvl);
+    Lv.nbr.alloc((size_t)std::max<int64_t>(nn, 1), s);
+    launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
+                          Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, nullptr,
+                          Lv.nptr.get(), Lv.nbr.get(), over.get(), Lv.max_row, s);
+    // sizes of the local systems
+    {
+        // cnt still holds the per-C-point sizes
+        int32_t smax = device_max(cnt.get(), Lv.nc, s);
+        Lv.st.s_max = smax;
+        std::vector<int32_t> hn((size_t)Lv.nc + 1);
+        LAIR_HIP(hipMemcpyAsync(hn.data(), Lv.nptr.get(), sizeof(int32_t) * (Lv.nc + 1), hipMemcpyDeviceToHost, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+        int32_t smin = INT_MAX;
+        for (int32_t c = 0; c < Lv.nc; ++c) smin = std::min(smin, hn[c + 1] - hn[c]);
+        Lv.st.s_min = Lv.nc ? smin : 0;
+        Lv.st.s_mean = Lv.nc ? (double)nn / Lv.nc : 0.0;
+    }
+
+    // R = [Z I]
+    DevCSR &R = Lv.R;
+    R.nrows = Lv.nc;
+    R.ncols = n;
+    R.nnz = nn + Lv.nc;
+    R.rp.alloc((size_t)Lv.nc + 1, s);
+    R.cj.alloc((size_t)R.nnz, s);
+    R.v.alloc((size_t)R.nnz, s);
+    hipLaunchKernelGGL(k_r_rowptr, dim3(blocks_for(Lv.nc + 1, 256)), dim3(256), 0, s,
+                       Lv.nc, Lv.nptr.get(), R.rp.get());
+    LAIR_LAUNCH_CHECK();
+    Lv.flags.alloc((size_t)Lv.nc, s);
+    LocalSolveOut out{R.rp.get(), R.cj.get(), R.v.get(), Lv.flags.get()};
+    int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
+                                 A.rp.get(), A.cj.get(), A.v.get(), h->opt.precision,
+                                 Lv.st.s_max, out, s);
+    Lv.st.n_singular = nsing;
+    h->n_singular += nsing;
+
+    // P
+    DevCSR &P = Lv.P;
+    P.nrows = n;
+    P.ncols = Lv.nc;
+    P.rp.alloc((size_t)n + 1, s);
+    if (h->opt.interp == LAIR_P_ONE_POINT) {
+        DevArr<int32_t> pcol;
+        pcol.alloc((size_t)n, s);
+        launch_interp_one_point(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
+        DevArr<int32_t> has;
+        has.alloc((size_t)n, s);
+        hipLaunchKernelGGL(k_nonneg_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                           n, pcol.get(), has.get());
+        LAIR_LAUNCH_CHECK();
+        P.nnz = scan_counts_i32(has.get(), P.rp.get(), n, s, tmp);
+        P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
+        P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
+        launch_compact_one_point(n, pcol.get(), P.rp.get(), P.cj.get(), P.v.get(), s);
+    } else {
+        DevArr<int32_t> pc;
+        pc.alloc((size_t)n, s);
+        launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(), Lv.cf.get(),
+                             Lv.cidx.get(), false, pc.get(), nullptr, nullptr, nullptr, s);
+        P.nnz = scan_counts_i32(pc.get(), P.rp.get(), n, s, tmp);
+        P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
+        P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
+        launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(), Lv.cf.get(),
+                             Lv.cidx.get(), true, nullptr, P.rp.get(), P.cj.get(), P.v.get(), s);
+    }
+}
+
+static void finish_coarsest(lair_hierarchy *h) {
+    hipStream_t s = h->stream;
+    Level &Lc = *h->L.back();
+    int32_t n = Lc.n;
+    if (n > MAX_DENSE)
+        fail(LAIR_EUNSUPPORTED, "coarsest level has %d rows (> %d) after coarsening stalled",
+             n, MAX_DENSE);
+    h->nL = n;
+    h->lu.alloc((size_t)n * n, s);
+    h->piv.alloc((size_t)std::max(n, 1), s);
+    DevArr<int32_t> info;
+    info.alloc(1, s);
+    launch_dense_from_csr(n, Lc.A.rp.get(), Lc.A.cj.get(), Lc.A.v.get(), h->lu.get(), s);
+    launch_dense_lu(n, h->lu.get(), h->piv.get(), info.get(), s);
+    int32_t hinfo = 0;
+    LAIR_HIP(hipMemcpyAsync(&hinfo, info.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) fail(LAIR_ESINGULAR, "coarsest matrix (n = %d) is singular at pivot %d", n, hinfo);
+}
+
+// nnz of the F rows and C rows of each level (for the cycle complexity)
+__global__ void k_rowset_nnz(int32_t nx, const int32_t *rows, const int32_t *rp,
+                             unsigned long long *acc) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nx) return;
+    int32_t i = rows[k];
+    atomicAdd(acc, (unsigned long long)(rp[i + 1] - rp[i]));
+}
+
+static void level_stats_and_cc(lair_hierarchy *h) {
+    hipStream_t s = h->stream;
+    double nnz0 = (double)h->L[0]->A.nnz;
+    double flops = 0.0, sum = 0.0;
+    DevArr<unsigned long long> acc;
+    acc.alloc(2, s);
+    for (size_t l = 0; l < h->L.size(); ++l) {
+        Level &Lv = *h->L[l];
+        Lv.st.n = Lv.n;
+        Lv.st.nnz_A = Lv.A.nnz;
+        Lv.st.nc = Lv.nc;
+        Lv.st.nnz_R = Lv.R.nnz;
+        Lv.st.nnz_P = Lv.P.nnz;
+        sum += (double)Lv.A.nnz;
+        if (l + 1 == h->L.size()) break;
+        LAIR_HIP(hipMemsetAsync(acc.get(), 0, 2 * sizeof(unsigned long long), s));
+        if (Lv.nf)
+            hipLaunchKernelGGL(k_rowset_nnz, dim3(blocks_for(Lv.nf, 256)), dim3(256), 0, s,
+                               Lv.nf, Lv.flist.get(), Lv.A.rp.get(), acc.get());
+        if (Lv.nc)
+            hipLaunchKernelGGL(k_rowset_nnz, dim3(blocks_for(Lv.nc, 256)), dim3(256), 0, s,
+                               Lv.nc, Lv.clist.get(), Lv.A.rp.get(), acc.get() + 1);
+        LAIR_LAUNCH_CHECK();
+        unsigned long long hacc[2];
+        LAIR_HIP(hipMemcpyAsync(hacc, acc.get(), sizeof(hacc), hipMemcpyDeviceToHost, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+        flops += 2.0 * Lv.A.nnz + 2.0 * Lv.R.nnz + 2.0 * Lv.P.nnz;
+        flops += 2.0 * (2.0 * (double)hacc[0] + (double)hacc[1]);
+    }
+    double nl = (double)h->L.back()->n;
+    flops += 2.0 * nl * nl;
+    h->cc = flops / (2.0 * nnz0);
+    h->oc = sum / nnz0;
+}
+
+static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
+                                  const lair_strength *str, const lair_options *opt,
+                                  hipStream_t s) {
+    auto t0 = Clock::now();
+    if (!Ain) fail(LAIR_EINVAL, "A must not be NULL");
+    check_options(str, opt);
+    if (Ain->n < 1 || Ain->n >= INT32_MAX) fail(LAIR_EINVAL, "n = %lld out of range", (long long)Ain->n);
+    if (Ain->nnz < Ain->n || Ain->nnz >= INT32_MAX)
+        fail(LAIR_EINVAL, "nnz = %lld out of range (needs n <= nnz < 2^31)", (long long)Ain->nnz);
+    if (!Ain->rowptr || !Ain->col || !Ain->val) fail(LAIR_EINVAL, "CSR arrays must not be NULL");
+    if (cfl && cfl->nlevels > 0 && (!cfl->offs || !cfl->cf))
+        fail(LAIR_EINVAL, "cf levels given without arrays");
+    if (cfl && cfl->nlevels < 0) fail(LAIR_EINVAL, "negative number of CF levels");
+    if (opt->block_size > 0 && Ain->n % opt->block_size != 0)
+        fail(LAIR_EINVAL, "n is not a multiple of block_size");
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
+        fail(LAIR_EDEVICE, "no HIP device available");
+    {
+        // keep freed hierarchy memory in the stream-ordered pool
+        int dev = 0;
+        LAIR_HIP(hipGetDevice(&dev));
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    }
+    std::unique_ptr<lair_hierarchy> h(new lair_hierarchy());
+    h->str = *str;
+    h->opt = *opt;
+    h->stream = s;
+    DevArr<int64_t> tmp;
+
+    const int32_t n = (int32_t)Ain->n;
+    const int64_t nnz = Ain->nnz;
+    std::unique_ptr<Level> L0(new Level());
+    L0->n = n;
+    DevCSR &A = L0->A;
+    A.nrows = A.ncols = n;
+    A.nnz = nnz;
+    A.rp.alloc((size_t)n + 1, s);
+    A.cj.alloc((size_t)nnz, s);
+    A.v.alloc((size_t)nnz, s);
+    hipMemcpyKind kind = Ain->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    LAIR_HIP(hipMemcpyAsync(A.rp.get(), Ain->rowptr, sizeof(int32_t) * (n + 1), kind, s));
+    LAIR_HIP(hipMemcpyAsync(A.cj.get(), Ain->col, sizeof(int32_t) * nnz, kind, s));
+    LAIR_HIP(hipMemcpyAsync(A.v.get(), Ain->val, sizeof(double) * nnz, kind, s));
+    L0->max_row = validate_csr(n, nnz, A.rp.get(), A.cj.get(), A.v.get(), s);
+
+    if (opt->block_size > 0) {
+        int32_t k = opt->block_size;
+        int32_t nblk = n / k;
+        h->dinv.alloc((size_t)nblk * k * k, s);
+        DevArr<int32_t> bad;
+        bad.alloc(1, s);
+        LAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int32_t), s));
+        launch_block_inverse(nblk, k, A.rp.get(), A.cj.get(), A.v.get(), h->dinv.get(),
+                             bad.get(), s);
+        int32_t hb = 0;
+        LAIR_HIP(hipMemcpyAsync(&hb, bad.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+        if (hb) fail(LAIR_ESINGULAR, "a %dx%d diagonal block is singular", k, k);
+        DevCSR D;
+        D.nrows = D.ncols = n;
+        D.nnz = (int64_t)n * k;
+        D.rp.alloc((size_t)n + 1, s);
+        D.cj.alloc((size_t)D.nnz, s);
+        D.v.alloc((size_t)D.nnz, s);
+        hipLaunchKernelGGL(k_block_diag_csr, dim3(blocks_for(D.nnz + 1, 256)), dim3(256), 0, s,
+                           nblk, k, h->dinv.get(), D.rp.get(), D.cj.get(), D.v.get());
+        LAIR_LAUNCH_CHECK();
+        DevCSR As;
+        spgemm(D, k, A, As, s, tmp);
+        L0->A = std::move(As);
+        L0->max_row = validate_csr(n, L0->A.nnz, L0->A.rp.get(), L0->A.cj.get(), L0->A.v.get(), s);
+    }
+    h->L.push_back(std::move(L0));
+
+    for (int32_t lvl = 0;; ++lvl) {
+        Level &Lv = *h->L.back();
+        if (Lv.n <= opt->max_coarse || lvl + 1 >= opt->max_levels) break;
+        bool coarsest = false;
+        build_level_transfer(h.get(), Lv, lvl, cfl, coarsest, tmp);
+        if (coarsest) break;
+        // Galerkin product K = R (A P)
+        DevCSR AP;
+        spgemm(Lv.A, Lv.max_row, Lv.P, AP, s, tmp);
+        std::unique_ptr<Level> nx(new Level());
+        nx->n = Lv.nc;
+        int32_t rmax = Lv.st.s_max + 1;
+        spgemm(Lv.R, rmax, AP, nx->A, s, tmp);
+        nx->max_row = validate_csr(nx->n, nx->A.nnz, nx->A.rp.get(), nx->A.cj.get(),
+                                   nx->A.v.get(), s);
+        h->L.push_back(std::move(nx));
+    }
+    finish_coarsest(h.get());
+    for (auto &lp : h->L) {
+        Level &Lv = *lp;
+        Lv.team_A = team_of(Lv.A);
+        Lv.team_R = team_of(Lv.R);
+        Lv.team_P = team_of(Lv.P);
+        if (opt->precision == LAIR_MIXED) {
+            Lv.A.v32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+            launch_to_float(Lv.A.v.get(), Lv.A.v32.get(), Lv.A.nnz, s);
+            if (Lv.R.nnz) {
+                Lv.R.v32.alloc((size_t)Lv.R.nnz, s);
+                launch_to_float(Lv.R.v.get(), Lv.R.v32.get(), Lv.R.nnz, s);
+            }
+            if (Lv.P.nnz) {
+                Lv.P.v32.alloc((size_t)Lv.P.nnz, s);
+                launch_to_float(Lv.P.v.get(), Lv.P.v32.get(), Lv.P.nnz, s);
+            }
+        }
+    }
+    level_stats_and_cc(h.get());
+    LAIR_HIP(hipStreamSynchronize(s));
+    h->setup_ms = ms_since(t0);
+    return h.release();
+}
+
+// ---------------------------------------------------------------------------
+// Cycle
+// ---------------------------------------------------------------------------
+static void ensure_vectors(lair_hierarchy *h, int32_t nrhs, hipStream_t s) {
+    if (nrhs <= h->nrhs_cap) return;
+    bool mixed = h->opt.precision == LAIR_MIXED;
+    for (size_t l = 0; l < h->L.size(); ++l) {
+        Level &Lv = *h->L[l];
+        size_t n = (size_t)Lv.n * nrhs;
+        size_t tn = (size_t)std::max(std::max(Lv.nf, Lv.nc), 1) * nrhs;
+        Lv.b.alloc(n, s);
+        Lv.x.alloc(n, s);
+        Lv.r.alloc(n, s);
+        Lv.t.alloc(tn, s);
+        if (mixed) {
+            Lv.b32.alloc(n, s);
+            Lv.x32.alloc(n, s);
+            Lv.r32.alloc(n, s);
+            Lv.t32.alloc(tn, s);
+        }
+    }
+    size_t n0 = (size_t)h->L[0]->n * nrhs;
+    h->r0.alloc(n0, s);
+    if (h->opt.block_size > 0) h->bscaled.alloc(n0, s);
+    if (mixed) {
+        h->r0_32.alloc(n0, s);
+        h->e32.alloc(n0, s);
+    }
+    h->partial.alloc((size_t)NPARTIAL * nrhs, s);
+    h->norms.alloc((size_t)nrhs, s);
+    h->nrhs_cap = nrhs;
+}
+
+template <class VT>
+static VT *vec(DevArr<double> &d, DevArr<float> &f) {
+    if constexpr (std::is_same<VT, double>::value) { (void)f; return d.get(); }
+    else { (void)d; return f.get(); }
+}
+
+// F, F, C Jacobi sweeps on level l.
+template <class VT>
+static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
+                hipStream_t s) {
+    CsrView<VT> A = view<VT>(Lv.A, Lv.team_A);
+    VT *t = vec<VT>(Lv.t, Lv.t32);
+    double om = h->opt.omega;
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        const int32_t *rows = sweep < 2 ? Lv.flist.get() : Lv.clist.get();
+        int32_t nx = sweep < 2 ? Lv.nf : Lv.nc;
+        op_jacobi<VT>(A, rows, nx, b, x, t, om, nrhs, s);
+        op_scatter<VT>(rows, nx, t, x, nrhs, s);
+    }
+}
+
+// V-cycle from level l.  With x_zero the incoming iterate is zero: the
+// residual is b itself and the interpolated correction is assigned.  When
+// r is non-null it already holds b - A x.
+template <class VT>
+static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
+                   const VT *r, int32_t nrhs, hipStream_t s) {
+    Level &Lv = *h->L[l];
+    if (l + 1 == h->L.size()) {
+        if constexpr (std::is_same<VT, double>::value) {
+            op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), b, x, nrhs, false, s);
+        } else {
+            // the coarsest solve stays in double
+            int64_t m = (int64_t)h->nL * nrhs;
+            op_cast_f64(b, Lv.r.get(), m, s);
+            op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), Lv.r.get(), Lv.x.get(),
+                                   nrhs, false, s);
+            op_cast_f32(Lv.x.get(), x, m, s);
+        }
+        return;
+    }
+    Level &Nx = *h->L[l + 1];
+    const VT *res = b;
+    if (!x_zero) {
+        if (r) {
+            res = r;
+        } else {
+            VT *rr = vec<VT>(Lv.r, Lv.r32);
+            op_residual<VT>(view<VT>(Lv.A, Lv.team_A), b, x, rr, nrhs, s);
+            res = rr;
+        }
+    }
+    VT *bc = vec<VT>(Nx.b, Nx.b32);
+    VT *xc = vec<VT>(Nx.x, Nx.x32);
+    op_spmv<VT>(view<VT>(Lv.R, Lv.team_R), res, bc, nrhs, false, s);
+    vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s);
+    op_spmv<VT>(view<VT>(Lv.P, Lv.team_P), xc, x, nrhs, !x_zero, s);
+    ffc<VT>(h, Lv, b, x, nrhs, s);
+}
+
+// Transposed cycle: C, F, F Jacobi on A^T, restriction with P^T, recursion
+// on K^T, interpolation with R^T.
+static void ensure_transposes(lair_hierarchy *h) {
+    if (h->have_transpose) return;
+    hipStream_t s = h->stream;
+    DevArr<int64_t> tmp;
+    for (size_t l = 0; l < h->L.size(); ++l) {
+        Level &Lv = *h->L[l];
+        transpose(Lv.A, Lv.At, s, tmp);
+        Lv.team_At = team_of(Lv.At);
+        if (l + 1 == h->L.size()) break;
+        transpose(Lv.R, Lv.Rt, s, tmp);
+        transpose(Lv.P, Lv.Pt, s, tmp);
+        Lv.team_Rt = team_of(Lv.Rt);
+        Lv.team_Pt = team_of(Lv.Pt);
+    }
+    LAIR_HIP(hipStreamSynchronize(s));
+    h->have_transpose = true;
+}
+
+static void vcycle_t(lair_hierarchy *h, size_t l, const double *g, double *lam,
+                     bool lam_zero, int32_t nrhs, hipStream_t s) {
+    Level &Lv = *h->L[l];
+    if (l + 1 == h->L.size()) {
+        op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), g, lam, nrhs, true, s);
+        return;
+    }
+    if (lam_zero) op_fill<double>(lam, 0.0, (int64_t)Lv.n * nrhs, s);
+    CsrView<double> At = view<double>(Lv.At, Lv.team_At);
+    double om = h->opt.omega;
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        const int32_t *rows = sweep == 0 ? Lv.clist.get() : Lv.flist.get();
+        int32_t nx = sweep == 0 ? Lv.nc : Lv.nf;
+        op_jacobi<double>(At, rows, nx, g, lam, Lv.t.get(), om, nrhs, s);
+        op_scatter<double>(rows, nx, Lv.t.get(), lam, nrhs, s);
+    }
+    op_residual<double>(At, g, lam, Lv.r.get(), nrhs, s);
+    Level &Nx = *h->L[l + 1];
+    op_spmv<double>(view<double>(Lv.Pt, Lv.team_Pt), Lv.r.get(), Nx.b.get(), nrhs, false, s);
+    vcycle_t(h, l + 1, Nx.b.get(), Nx.x.get(), true, nrhs, s);
+    op_spmv<double>(view<double>(Lv.Rt, Lv.team_Rt), Nx.x.get(), lam, nrhs, true, s);
+}
+
+static bool valid_nrhs(int32_t nrhs) {
+    return nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8 || nrhs == 16 || nrhs == 32;
+}
+
+static void norms_host(lair_hierarchy *h, const double *r, int32_t nrhs,
+                       hipStream_t s, std::vector<double> &out) {
+    op_sumsq(r, h->L[0]->n, nrhs, h->partial.get(), NPARTIAL, h->norms.get(), s);
+    out.resize((size_t)nrhs);
+    LAIR_HIP(hipMemcpyAsync(out.data(), h->norms.get(), sizeof(double) * nrhs,
+                            hipMemcpyDeviceToHost, s));
+    LAIR_HIP(hipStreamSynchronize(s));
+    for (auto &v : out) v = std::sqrt(v);
+}
+
+static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
+                              int32_t nrhs, double rtol, int32_t maxit,
+                              lair_info *info, hipStream_t s, bool transpose) {
+    auto t0 = Clock::now();
+    if (!h) fail(LAIR_EINVAL, "hierarchy is NULL");
+    if (!b || !x) fail(LAIR_EINVAL, "b and x must not be NULL");
+    if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
+    if (!(rtol > 0.0) || maxit < 0) fail(LAIR_EINVAL, "need rtol > 0 and maxit >= 0");
+    ensure_vectors(h, nrhs, s);
+    if (transpose) ensure_transposes(h);
+    Level &L0 = *h->L[0];
+    const int64_t n = L0.n;
+    const double *bb = b;
+    if (h->opt.block_size > 0 && !transpose) {
+        op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
+                       h->bscaled.get(), nrhs, s);
+        bb = h->bscaled.get();
+    }
+    std::vector<double> nb, rn, r_first;
+    norms_host(h, bb, nrhs, s, nb);
+    CsrView<double> A0 = transpose ? view<double>(L0.At, L0.team_At)
+                                   : view<double>(L0.A, L0.team_A);
+    bool mixed = h->opt.precision == LAIR_MIXED && !transpose;
+    int32_t it = 0;
+    double relmax = 0.0;
+    for (;;) {
+        op_residual<double>(A0, bb, x, h->r0.get(), nrhs, s);
+        norms_host(h, h->r0.get(), nrhs, s, rn);
+        if (it == 0) r_first = rn;
+        relmax = 0.0;
+        bool done = true;
+        for (int32_t q = 0; q < nrhs; ++q) {
+            double rel = nb[q] > 0 ? rn[q] / nb[q] : rn[q];
+            relmax = std::max(relmax, rel);
+            if (!(rel <= rtol)) done = false;
+        }
+        if (done || it >= maxit) break;
+        if (transpose) {
+            // lambda <- lambda + B^T (g - A^T lambda): cycle on the residual
+            DevArr<double> &e = L0.b;
+            vcycle_t(h, 0, h->r0.get(), e.get(), true, nrhs, s);
+            hipLaunchKernelGGL(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
+                               x, e.get(), n * nrhs);
+            LAIR_LAUNCH_CHECK();
+        } else if (!mixed) {
+            vcycle<double>(h, 0, bb, x, false, h->r0.get(), nrhs, s);
+        } else {
+            op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
+            vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, s);
+            op_axpy_f32(x, h->e32.get(), n * nrhs, s);
+        }
+        ++it;
+    }
+    LAIR_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->iters = it;
+        info->nlevels = (int32_t)h->L.size();
+        info->relres = relmax;
+        double rho = 0.0;
+        if (it > 0 && !r_first.empty()) {
+            for (int32_t q = 0; q < nrhs; ++q)
+                if (r_first[q] > 0) rho = std::max(rho, std::pow(rn[q] / r_first[q], 1.0 / it));
+        }
+        info->rho = rho;
+        info->cycle_complexity = h->cc;
+        info->op_complexity = h->oc;
+        info->n_singular_local = h->n_singular;
+        info->setup_ms = h->setup_ms;
+        info->solve_ms = ms_since(t0);
+    }
+    return relmax <= rtol ? LAIR_OK : LAIR_ENOCONV;
+}
+
+}  // namespace lair
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace lair;
+
+template <class F>
+static lair_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return LAIR_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return LAIR_EDEVICE;
+    } catch (...) {
+        set_last_error("unknown error");
+        return LAIR_EDEVICE;
+    }
+}
+
+extern "C" {
+
+void lair_default_options(lair_strength *s, lair_options *o) {
+    if (s) {
+        s->theta = 0.25;
+        s->theta_c = 0.25;
+        s->kind = LAIR_SOC_ABS;
+        s->distance = 1;
+    }
+    if (o) {
+        o->interp = LAIR_P_ONE_POINT;
+        o->precision = LAIR_FP64;
+        o->omega = 1.0;
+        o->max_levels = 25;
+        o->max_coarse = 128;
+        o->stall = 0.9;
+        o->block_size = 0;
+        o->reserved = 0;
+    }
+}
+
+lair_status lair_setup(const lair_csr *A, const lair_cf_levels *cf,
+                       const lair_strength *s, const lair_options *o,
+                       void *stream, lair_hierarchy **out) {
+    return guarded([&]() -> lair_status {
+        if (!out) fail(LAIR_EINVAL, "out must not be NULL");
+        *out = nullptr;
+        *out = setup_impl(A, cf, s, o, (hipStream_t)stream);
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
+                       int32_t nrhs, void *stream) {
+    return guarded([&]() -> lair_status {
+        if (!h || !b || !x) fail(LAIR_EINVAL, "NULL argument");
+        if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
+        hipStream_t s = (hipStream_t)stream;
+        ensure_vectors(h, nrhs, s);
+        const double *bb = b;
+        int64_t n = h->L[0]->n;
+        if (h->opt.block_size > 0) {
+            op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
+                           h->bscaled.get(), nrhs, s);
+            bb = h->bscaled.get();
+        }
+        if (h->opt.precision == LAIR_MIXED) {
+            op_residual<double>(view<double>(h->L[0]->A, h->L[0]->team_A), bb, x,
+                                h->r0.get(), nrhs, s);
+            op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
+            vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, s);
+            op_axpy_f32(x, h->e32.get(), n * nrhs, s);
+        } else {
+            vcycle<double>(h, 0, bb, x, false, nullptr, nrhs, s);
+        }
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g, double *lam,
+                                 int32_t nrhs, void *stream) {
+    return guarded([&]() -> lair_status {
+        if (!h || !g || !lam) fail(LAIR_EINVAL, "NULL argument");
+        if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
+        hipStream_t s = (hipStream_t)stream;
+        ensure_vectors(h, nrhs, s);
+        ensure_transposes(h);
+        // lam <- lam + B^T (g - A^T lam)
+        Level &L0 = *h->L[0];
+        int64_t n = L0.n;
+        op_residual<double>(view<double>(L0.At, L0.team_At), g, lam, h->r0.get(), nrhs, s);
+        vcycle_t(h, 0, h->r0.get(), L0.b.get(), true, nrhs, s);
+        hipLaunchKernelGGL(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
+                           lam, L0.b.get(), n * nrhs);
+        LAIR_LAUNCH_CHECK();
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_solve(lair_hierarchy *h, const double *b, double *x, int32_t nrhs,
+                       double rtol, int32_t maxit, lair_info *info, void *stream) {
+    return guarded([&]() -> lair_status {
+        return solve_impl(h, b, x, nrhs, rtol, maxit, info, (hipStream_t)stream, false);
+    });
+}
+
+lair_status lair_solve_transpose(lair_hierarchy *h, const double *g, double *lam,
+                                 int32_t nrhs, double rtol, int32_t maxit,
+                                 lair_info *info, void *stream) {
+    return guarded([&]() -> lair_status {
+        if (h && h->opt.block_size > 0)
+            fail(LAIR_EUNSUPPORTED, "transposed solve with block scaling");
+        return solve_impl(h, g, lam, nrhs, rtol, maxit, info, (hipStream_t)stream, true);
+    });
+}
+
+int32_t lair_num_levels(const lair_hierarchy *h) { return h ? (int32_t)h->L.size() : 0; }
+
+lair_status lair_level_stats_get(const lair_hierarchy *h, int32_t level,
+                                 lair_level_stats *st) {
+    return guarded([&]() -> lair_status {
+        if (!h || !st) fail(LAIR_EINVAL, "NULL argument");
+        if (level < 0 || level >= (int32_t)h->L.size()) fail(LAIR_EINVAL, "bad level %d", level);
+        *st = h->L[level]->st;
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_export(const lair_hierarchy *h, int32_t level, int32_t what,
+                        void *host_buf, int64_t *bytes) {
+    return guarded([&]() -> lair_status {
+        if (!h || !bytes) fail(LAIR_EINVAL, "NULL argument");
+        if (level < 0 || level >= (int32_t)h->L.size()) fail(LAIR_EINVAL, "bad level %d", level);
+        const Level &Lv = *h->L[level];
+        const void *src = nullptr;
+        int64_t nb = 0;
+        switch (what) {
+            case 0: src = Lv.A.rp.get(); nb = 4 * ((int64_t)Lv.n + 1); break;
+            case 1: src = Lv.A.cj.get(); nb = 4 * Lv.A.nnz; break;
+            case 2: src = Lv.A.v.get(); nb = 8 * Lv.A.nnz; break;
+            case 3: src = Lv.cf.get(); nb = Lv.cf.get() ? Lv.n : 0; break;
+            case 4: src = Lv.smask.get(); nb = Lv.smask.get() ? Lv.A.nnz : 0; break;
+            case 5: src = Lv.R.rp.get(); nb = Lv.R.rp.get() ? 4 * ((int64_t)Lv.nc + 1) : 0; break;
+            case 6: src = Lv.R.cj.get(); nb = 4 * Lv.R.nnz; break;
+            case 7: src = Lv.R.v.get(); nb = 8 * Lv.R.nnz; break;
+            case 8: src = Lv.P.rp.get(); nb = Lv.P.rp.get() ? 4 * ((int64_t)Lv.n + 1) : 0; break;
+            case 9: src = Lv.P.cj.get(); nb = 4 * Lv.P.nnz; break;
+            case 10: src = Lv.P.v.get(); nb = 8 * Lv.P.nnz; break;
+            case 11: src = Lv.nptr.get(); nb = Lv.nptr.get() ? 4 * ((int64_t)Lv.nc + 1) : 0; break;
+            case 12: src = Lv.nbr.get(); nb = Lv.nptr.get() ? 4 * (Lv.R.nnz - Lv.nc) : 0; break;
+            case 13: src = Lv.flags.get(); nb = Lv.flags.get() ? Lv.nc : 0; break;
+            default: fail(LAIR_EINVAL, "unknown export selector %d", what);
+        }
+        int64_t cap = *bytes;
+        *bytes = nb;
+        if (!host_buf) return LAIR_OK;
+        if (cap < nb) fail(LAIR_EINVAL, "export buffer too small (%lld < %lld)",
+                           (long long)cap, (long long)nb);
+        if (nb > 0) {
+            LAIR_HIP(hipStreamSynchronize(h->stream));
+            LAIR_HIP(hipMemcpy(host_buf, src, (size_t)nb, hipMemcpyDeviceToHost));
+        }
+        return LAIR_OK;
+    });
+}
+
+void lair_free(lair_hierarchy *h) {
+    if (!h) return;
+    try {
+        delete h;
+    } catch (...) {
+    }
+}
+
+const char *lair_status_string(lair_status s) {
+    switch (s) {
+        case LAIR_OK: return "LAIR_OK";
+        case LAIR_EINVAL: return "LAIR_EINVAL: invalid argument";
+        case LAIR_ENOMEM: return "LAIR_ENOMEM: out of memory";
+        case LAIR_EDEVICE: return "LAIR_EDEVICE: HIP device error";
+        case LAIR_ESINGULAR: return "LAIR_ESINGULAR: singular coarsest matrix";
+        case LAIR_ENOCONV: return "LAIR_ENOCONV: tolerance not reached";
+        case LAIR_EUNSUPPORTED: return "LAIR_EUNSUPPORTED: size limit exceeded";
+        default: return "unknown status";
+    }
+}
+
+const char *lair_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// Internal declarations shared by the liblair translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lair.h"
+
+namespace lair {
+
+// ---------------------------------------------------------------------------
+// Errors: thrown inside the library, turned into a status at the ABI.
+// ---------------------------------------------------------------------------
+struct Error {
+    lair_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(lair_status st, const char *fmt, ...);
+void set_last_error(const std::string &m);
+
+#define LAIR_HIP(call)                                                         \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            ::lair::fail(e_ == hipErrorOutOfMemory ? LAIR_ENOMEM : LAIR_EDEVICE,\
+                         "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),\
+                         __FILE__, __LINE__);                                  \
+    } while (0)
+
+#define LAIR_LAUNCH_CHECK() LAIR_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Stream-ordered device array, freed on the stream it was allocated on.
+// ---------------------------------------------------------------------------
+template <class T>
+struct DevArr {
+    T *p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+
+    DevArr() = default;
+    DevArr(const DevArr &) = delete;
+    DevArr &operator=(const DevArr &) = delete;
+    DevArr(DevArr &&o) noexcept { swap(o); }
+    DevArr &operator=(DevArr &&o) noexcept {
+        if (this != &o) { release(); swap(o); }
+        return *this;
+    }
+    ~DevArr() { release(); }
+
+    void swap(DevArr &o) noexcept {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+        std::swap(s, o.s);
+    }
+    void release() noexcept {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count, hipStream_t stream) {
+        release();
+        s = stream;
+        n = count;
+        if (count == 0) return;
+        hipError_t e = hipMallocAsync((void **)&p, count * sizeof(T), stream);
+        if (e != hipSuccess) {
+            p = nullptr;
+            n = 0;
+            fail(e == hipErrorOutOfMemory ? LAIR_ENOMEM : LAIR_EDEVICE,
+                 "device allocation of %zu bytes failed: %s",
+                 count * sizeof(T), hipGetErrorString(e));
+        }
+    }
+    void ensure(size_t count, hipStream_t stream) {
+        if (count > n || p == nullptr) alloc(count, stream);
+    }
+    T *get() const { return p; }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// A square or rectangular CSR matrix on the device (int32 indices).
+struct DevCSR {
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    DevArr<int32_t> rp, cj;
+    DevArr<double> v;
+    DevArr<float> v32;    // float copy of the values (mixed precision)
+};
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+inline unsigned blocks_for(int64_t threads, int bs) {
+    int64_t b = (threads + bs - 1) / bs;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Team size for row-parallel kernels from the mean row length.
+inline int team_for_mean(double mean_len) {
+    int t = 2;
+    while (t < 64 && t < mean_len) t <<= 1;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Setup kernels (k_setup.hip)
+// ---------------------------------------------------------------------------
+// exclusive scan of f(i) for i < n into out[0..n], returns out[n]
+int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
+                        hipStream_t s, DevArr<int64_t> &tmp);
+int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
+                      hipStream_t s, DevArr<int64_t> &tmp);
+
+int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
+                     const int32_t *cj, const double *v, hipStream_t s);
+void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
+                     const double *v, double theta, int32_t kind,
+                     uint8_t *smask, double mean_len, hipStream_t s);
+void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
+                     int32_t *cidx, int32_t *clist, int32_t *flist,
+                     hipStream_t s);
+// neighbourhood sizes (fill = false) or lists (fill = true)
+void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
+                           const int32_t *rp, const int32_t *cj,
+                           const uint8_t *smask, const int8_t *cf,
+                           int32_t distance, const int32_t *flist, int32_t nf,
+                           int32_t *cnt, const int32_t *nptr, int32_t *nbr,
+                           int32_t *overflow, int32_t max_row_strong,
+                           hipStream_t s);
+struct LocalSolveOut {
+    int32_t *r_rp, *r_cj;
+    double *r_v;
+    int8_t *flags;
+};
+// returns the number of systems solved by least squares
+int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
+                     const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+                     const double *v, int32_t precision, int32_t smax,
+                     LocalSolveOut out, hipStream_t s);
+void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
+                             const double *v, const uint8_t *smask,
+                             const int8_t *cf, const int32_t *cidx,
+                             int32_t *pcol, hipStream_t s);
+void launch_compact_one_point(int32_t n, const int32_t *pcol,
+                              const int32_t *prp, int32_t *pcj, double *pv,
+                              hipStream_t s);
+void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
+                          const double *v, const uint8_t *smask,
+                          const int8_t *cf, const int32_t *cidx, bool fill,
+                          int32_t *cnt, const int32_t *prp, int32_t *pcj,
+                          double *pv, hipStream_t s);
+// C = A B (symbolic pattern).  Count pass when fill is false.
+void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
+                   const double *ax, const int32_t *bp, const int32_t *bj,
+                   const double *bx, int32_t max_row_a, bool fill,
+                   int32_t *cnt, const int32_t *cp, int32_t *cj, double *cx,
+                   int32_t *overflow, hipStream_t s);
+void launch_transpose(int32_t nrows, int32_t ncols, int64_t nnz,
+                      const int32_t *rp, const int32_t *cj, const double *v,
+                      int32_t *tcount, int32_t *trp, int32_t *tcj, double *tv,
+                      int32_t *cursor, hipStream_t s, DevArr<int64_t> &tmp);
+void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s);
+void launch_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
+                          const int32_t *cj, const double *v, double *dinv,
+                          int32_t *bad, hipStream_t s);
+// dense coarsest factorisation
+void launch_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj,
+                           const double *v, double *dense, hipStream_t s);
+void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,
+                     hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Cycle kernels (k_cycle.hip)
+// ---------------------------------------------------------------------------
+template <class VT>
+struct CsrView {
+    int32_t nrows, ncols;
+    const int32_t *rp, *cj;
+    const VT *v;
+    int32_t team;      // lanes per row for single right-hand sides
+};
+
+template <class VT>
+void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
+                 int32_t nrhs, hipStream_t s);
+template <class VT>
+void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
+             bool accumulate, hipStream_t s);
+template <class VT>
+void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nrows,
+               const VT *b, const VT *x, VT *t, double omega, int32_t nrhs,
+               hipStream_t s);
+template <class VT>
+void op_scatter(const int32_t *rows, int32_t nrows, const VT *t, VT *x,
+                int32_t nrhs, hipStream_t s);
+template <class VT>
+void op_fill(VT *x, VT val, int64_t n, hipStream_t s);
+template <class VT>
+void op_copy(const VT *x, VT *y, int64_t n, hipStream_t s);
+template <class VT>
+void op_dense_solve(int32_t n, const double *lu, const int32_t *piv,
+                    const VT *b, VT *x, int32_t nrhs, bool transpose,
+                    hipStream_t s);
+// per right-hand side sum of squares into out[0..nrhs) (double, fixed order)
+void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
+              int32_t npartial, double *out, hipStream_t s);
+void op_axpy_f32(double *x, const float *e, int64_t n, hipStream_t s);
+void op_cast_f32(const double *in, float *out, int64_t n, hipStream_t s);
+void op_cast_f64(const float *in, double *out, int64_t n, hipStream_t s);
+void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
+                    const double *b, double *out, int32_t nrhs, hipStream_t s);
+
+}  // namespace lair
