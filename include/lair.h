@@ -189,6 +189,21 @@ lair_status lair_level_stats_get(const lair_hierarchy *h, int32_t level,
 lair_status lair_export(const lair_hierarchy *h, int32_t level, int32_t what,
                         void *host_buf, int64_t *bytes);
 
+/* Kernel profiler (measurement aid, not part of the method).  Between
+ * lair_profile_begin and lair_profile_end every launch whose category is in
+ * the comma-separated list `categories` (NULL or "" = all) is bracketed by
+ * HIP events recorded on the stream it runs on, and tagged with its
+ * algorithmic bytes and flops (the data the operation must read or write at
+ * least once).  lair_profile_end waits for those events and writes a JSON
+ * object {category: {launches, ms, ms_max, alg_bytes, alg_flops}} into
+ * json (capacity *len bytes; *len returns the size needed, json may be NULL
+ * to query).  Categories: strength, cf_lists, nbr, local_small, local_wave,
+ * local_lstsq, interp, spgemm_count, spgemm_fill, validate, coarse_setup,
+ * residual, restrict, interpolate, jacobi, scatter, norm, coarse_solve,
+ * cast.  Process-wide; not for concurrent use from several host threads. */
+lair_status lair_profile_begin(const char *categories);
+lair_status lair_profile_end(char *json, int64_t *len);
+
 void lair_free(lair_hierarchy *h);
 const char *lair_status_string(lair_status s);
 const char *lair_last_error(void);

@@ -16,7 +16,8 @@ import numpy as np
 from . import _lib as L
 from ._lib import LairError  # noqa: F401
 
-__all__ = ["setup", "Hierarchy", "LairError", "load_library"]
+__all__ = ["setup", "Hierarchy", "LairError", "load_library", "profile_begin",
+           "profile_end"]
 
 _KINDS = {"abs": L.SOC_ABS, "neg": L.SOC_NEG}
 _INTERP = {"one_point": L.P_ONE_POINT, "direct": L.P_DIRECT}
@@ -163,6 +164,28 @@ class Hierarchy:
         d = info.as_dict()
         d["converged"] = st == L.LAIR_OK
         return lam, d
+
+
+def profile_begin(categories=None):
+    """Start the library's kernel profiler (HIP events per launch) for the
+    given categories (list or comma-separated string; None = all)."""
+    if isinstance(categories, (list, tuple)):
+        categories = ",".join(categories)
+    L.check(L.load().lair_profile_begin(None if categories is None else categories.encode()),
+            "lair_profile_begin")
+
+
+def profile_end():
+    """Stop profiling; returns {category: {launches, ms, ms_max, alg_bytes,
+    alg_flops}} summed over the profiled launches."""
+    import json
+    lib = L.load()
+    n = ctypes.c_int64(0)
+    lib.lair_profile_end(None, ctypes.byref(n))
+    buf = ctypes.create_string_buffer(int(n.value) + 16)
+    n2 = ctypes.c_int64(len(buf))
+    L.check(lib.lair_profile_end(buf, ctypes.byref(n2)), "lair_profile_end")
+    return json.loads(buf.value.decode() or "{}")
 
 
 def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,

@@ -12,9 +12,74 @@
 namespace lair {
 
 // ---------------------------------------------------------------------------
-// y = b - A x   (or y = A x, y += A x), one right-hand side, T lanes per row
+// Row products.  Source vectors may be split by point type: with SEL the
+// value of neighbour c is read from xC when cf[c] = 1 (C-point) and from xF
+// otherwise, which lets two Jacobi sweeps read and write without a copy.
 // ---------------------------------------------------------------------------
 enum { MODE_RESID = 0, MODE_SET = 1, MODE_ADD = 2 };
+
+template <class VT, bool SEL>
+__device__ __forceinline__ VT src_val(const VT *xF, const VT *xC, const int8_t *cf,
+                                      int64_t idx, int c) {
+    if (SEL) return cf[c] ? xC[idx] : xF[idx];
+    return xF[idx];
+}
+
+// One right-hand side, a team of T lanes per row (lanes take every T-th
+// entry of the row).
+template <class VT, int T, bool SEL>
+__device__ __forceinline__ void row_acc1(int lo, int hi, int lane, int diag_col,
+                                         const int32_t *cj, const VT *v,
+                                         const VT *xF, const VT *xC,
+                                         const int8_t *cf, VT &acc, VT &d) {
+    for (int p = lo + lane; p < hi; p += T) {
+        int c = cj[p];
+        VT a = v[p];
+        acc += a * src_val<VT, SEL>(xF, xC, cf, c, c);
+        if (c == diag_col) d = a;
+    }
+}
+
+// NR interleaved right-hand sides, one lane per right-hand side.  The team
+// loads NR consecutive entries of the row (one per lane) and broadcasts them
+// by shuffles in chunks of CH, so the gathers of a chunk are independent
+// loads issued together.  Padding entries use column 0 with value 0.
+template <class VT, int NR, bool SEL>
+__device__ __forceinline__ void row_accM(int lo, int hi, int q, int diag_col,
+                                         const int32_t *cj, const VT *v,
+                                         const VT *xF, const VT *xC,
+                                         const int8_t *cf, VT &acc, VT &d) {
+    constexpr int CH = NR < 8 ? NR : 8;
+    for (int base = lo; base < hi; base += NR) {
+        int p = base + q;
+        int c = -1;
+        VT a = (VT)0;
+        if (p < hi) { c = cj[p]; a = v[p]; }
+        int cnt = hi - base;
+#pragma unroll
+        for (int ch = 0; ch < NR; ch += CH) {
+            if (ch < cnt) {
+                int ce[CH];
+                VT ae[CH], xe[CH];
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    ce[e] = __shfl(c, ch + e, NR);
+                    ae[e] = __shfl(a, ch + e, NR);
+                }
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    int cc = ce[e] < 0 ? 0 : ce[e];
+                    xe[e] = src_val<VT, SEL>(xF, xC, cf, (int64_t)cc * NR + q, cc);
+                }
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    acc += ae[e] * xe[e];
+                    if (ce[e] == diag_col) d = ae[e];
+                }
+            }
+        }
+    }
+}
 
 template <class VT, int T, int MODE>
 __global__ void __launch_bounds__(256)
@@ -24,8 +89,8 @@ k_rowdot1(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
     int32_t i = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (i >= nrows) return;
-    VT acc = (VT)0;
-    for (int p = rp[i] + lane; p < rp[i + 1]; p += T) acc += v[p] * x[cj[p]];
+    VT acc = (VT)0, d = (VT)0;
+    row_acc1<VT, T, false>(rp[i], rp[i + 1], lane, -1, cj, v, x, x, nullptr, acc, d);
     acc = team_sum<T>(acc);
     if (lane == 0) {
         if (MODE == MODE_RESID) y[i] = b[i] - acc;
@@ -34,18 +99,17 @@ k_rowdot1(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
     }
 }
 
-// one lane per (row, right-hand side), nrhs interleaved
-template <class VT, int MODE>
+template <class VT, int NR, int MODE>
 __global__ void __launch_bounds__(256)
-k_rowdotM(int32_t nrows, int32_t nrhs, const int32_t *rp, const int32_t *cj,
-          const VT *v, const VT *x, const VT *b, VT *y) {
+k_rowdotM(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
+          const VT *x, const VT *b, VT *y) {
     int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t i = (int32_t)(gt / nrhs);
-    int q = (int)(gt % nrhs);
+    int32_t i = (int32_t)(gt / NR);
+    int q = (int)(gt % NR);
     if (i >= nrows) return;
-    VT acc = (VT)0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += v[p] * x[(int64_t)cj[p] * nrhs + q];
-    int64_t o = (int64_t)i * nrhs + q;
+    VT acc = (VT)0, d = (VT)0;
+    row_accM<VT, NR, false>(rp[i], rp[i + 1], q, -1, cj, v, x, x, nullptr, acc, d);
+    int64_t o = (int64_t)i * NR + q;
     if (MODE == MODE_RESID) y[o] = b[o] - acc;
     else if (MODE == MODE_SET) y[o] = acc;
     else y[o] += acc;
@@ -56,9 +120,18 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
                    int32_t nrhs, hipStream_t s) {
     if (A.nrows == 0) return;
     if (nrhs > 1) {
-        hipLaunchKernelGGL((k_rowdotM<VT, MODE>),
-                           dim3(blocks_for((int64_t)A.nrows * nrhs, 256)), dim3(256),
-                           0, s, A.nrows, nrhs, A.rp, A.cj, A.v, x, b, y);
+#define LAIR_RM(NN)                                                               \
+    hipLaunchKernelGGL((k_rowdotM<VT, NN, MODE>),                                 \
+                       dim3(blocks_for((int64_t)A.nrows * NN, 256)), dim3(256), 0, s, \
+                       A.nrows, A.rp, A.cj, A.v, x, b, y)
+        switch (nrhs) {
+            case 2: LAIR_RM(2); break;
+            case 4: LAIR_RM(4); break;
+            case 8: LAIR_RM(8); break;
+            case 16: LAIR_RM(16); break;
+            default: LAIR_RM(32); break;
+        }
+#undef LAIR_RM
         LAIR_LAUNCH_CHECK();
         return;
     }
@@ -93,66 +166,71 @@ void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi on a row set X:  t[k] = x_i + omega (b_i - (A x)_i) / a_ii, i = X[k].
-// The diagonal is found while streaming the row.
+// Jacobi on a row set X:  new_i = x_i + omega (b_i - (A x)_i) / a_ii for
+// i = X[k], written to out[k] (compact) or out[i].  Every row reads the
+// previous iterate; the diagonal is found while streaming the row.
 // ---------------------------------------------------------------------------
-template <class VT, int T>
+template <class VT, int T, bool SEL>
 __global__ void __launch_bounds__(256)
 k_jacobi1(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
-          const VT *v, const VT *b, const VT *x, VT *t, VT omega) {
+          const VT *v, const VT *b, const VT *xF, const VT *xC,
+          const int8_t *cf, VT *out, int compact, VT omega) {
     int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t k = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (k >= nx) return;
     int32_t i = rows[k];
     VT acc = (VT)0, d = (VT)0;
-    for (int p = rp[i] + lane; p < rp[i + 1]; p += T) {
-        int c = cj[p];
-        VT a = v[p];
-        acc += a * x[c];
-        if (c == i) d = a;
-    }
+    row_acc1<VT, T, SEL>(rp[i], rp[i + 1], lane, i, cj, v, xF, xC, cf, acc, d);
     acc = team_sum<T>(acc);
     d = team_sum<T>(d);
-    if (lane == 0) t[k] = x[i] + omega * (b[i] - acc) / d;
+    if (lane == 0) {
+        VT xi = src_val<VT, SEL>(xF, xC, cf, i, i);
+        out[compact ? k : i] = xi + omega * (b[i] - acc) / d;
+    }
 }
 
-template <class VT>
+template <class VT, int NR, bool SEL>
 __global__ void __launch_bounds__(256)
-k_jacobiM(int32_t nx, int32_t nrhs, const int32_t *rows, const int32_t *rp,
-          const int32_t *cj, const VT *v, const VT *b, const VT *x, VT *t,
-          VT omega) {
+k_jacobiM(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
+          const VT *v, const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
+          VT *out, int compact, VT omega) {
     int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t k = (int32_t)(gt / nrhs);
-    int q = (int)(gt % nrhs);
+    int32_t k = (int32_t)(gt / NR);
+    int q = (int)(gt % NR);
     if (k >= nx) return;
     int32_t i = rows[k];
     VT acc = (VT)0, d = (VT)0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int c = cj[p];
-        VT a = v[p];
-        acc += a * x[(int64_t)c * nrhs + q];
-        if (c == i) d = a;
-    }
-    int64_t oi = (int64_t)i * nrhs + q;
-    t[(int64_t)k * nrhs + q] = x[oi] + omega * (b[oi] - acc) / d;
+    row_accM<VT, NR, SEL>(rp[i], rp[i + 1], q, i, cj, v, xF, xC, cf, acc, d);
+    int64_t oi = (int64_t)i * NR + q;
+    VT xi = src_val<VT, SEL>(xF, xC, cf, oi, i);
+    out[(compact ? (int64_t)k * NR : oi - q) + q] = xi + omega * (b[oi] - acc) / d;
 }
 
-template <class VT>
-void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
-               const VT *b, const VT *x, VT *t, double omega, int32_t nrhs,
-               hipStream_t s) {
-    if (nx == 0) return;
-    VT om = (VT)omega;
+template <class VT, bool SEL>
+static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
+                          const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
+                          VT *out, int compact, VT om, int32_t nrhs, hipStream_t s) {
     if (nrhs > 1) {
-        hipLaunchKernelGGL((k_jacobiM<VT>), dim3(blocks_for((int64_t)nx * nrhs, 256)),
-                           dim3(256), 0, s, nx, nrhs, rows, A.rp, A.cj, A.v, b, x, t, om);
+#define LAIR_JM(NN)                                                               \
+    hipLaunchKernelGGL((k_jacobiM<VT, NN, SEL>),                                  \
+                       dim3(blocks_for((int64_t)nx * NN, 256)), dim3(256), 0, s,  \
+                       nx, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
+        switch (nrhs) {
+            case 2: LAIR_JM(2); break;
+            case 4: LAIR_JM(4); break;
+            case 8: LAIR_JM(8); break;
+            case 16: LAIR_JM(16); break;
+            default: LAIR_JM(32); break;
+        }
+#undef LAIR_JM
         LAIR_LAUNCH_CHECK();
         return;
     }
-#define LAIR_JC(TT)                                                             \
-    hipLaunchKernelGGL((k_jacobi1<VT, TT>), dim3(blocks_for((int64_t)nx * TT, 256)), \
-                       dim3(256), 0, s, nx, rows, A.rp, A.cj, A.v, b, x, t, om)
+#define LAIR_JC(TT)                                                              \
+    hipLaunchKernelGGL((k_jacobi1<VT, TT, SEL>),                                 \
+                       dim3(blocks_for((int64_t)nx * TT, 256)), dim3(256), 0, s, \
+                       nx, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
     switch (A.team) {
         case 1: LAIR_JC(1); break;
         case 2: LAIR_JC(2); break;
@@ -164,6 +242,19 @@ void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
     }
 #undef LAIR_JC
     LAIR_LAUNCH_CHECK();
+}
+
+template <class VT>
+void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
+               const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
+               VT *out, bool compact, double omega, int32_t nrhs,
+               hipStream_t s) {
+    if (nx == 0) return;
+    VT om = (VT)omega;
+    if (cf)
+        jacobi_launch<VT, true>(A, rows, nx, b, xF, xC, cf, out, compact ? 1 : 0, om, nrhs, s);
+    else
+        jacobi_launch<VT, false>(A, rows, nx, b, xF, xF, nullptr, out, compact ? 1 : 0, om, nrhs, s);
 }
 
 template <class VT>
@@ -299,6 +390,32 @@ void op_dense_solve(int32_t n, const double *lu, const int32_t *piv,
     LAIR_LAUNCH_CHECK();
 }
 
+// Coarsest grid through its explicit inverse (small grids): x = Kinv b or
+// Kinv^T b, accumulated in double whatever the vector type.
+template <class VT>
+__global__ void __launch_bounds__(256)
+k_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x, int32_t nrhs,
+               int transpose) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)n * nrhs) return;
+    int32_t i = (int32_t)(g / nrhs);
+    int q = (int)(g % nrhs);
+    double acc = 0.0;
+    if (!transpose)
+        for (int j = 0; j < n; ++j) acc += kinv[(size_t)i * n + j] * (double)b[(int64_t)j * nrhs + q];
+    else
+        for (int j = 0; j < n; ++j) acc += kinv[(size_t)j * n + i] * (double)b[(int64_t)j * nrhs + q];
+    x[g] = (VT)acc;
+}
+
+template <class VT>
+void op_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x,
+                     int32_t nrhs, bool transpose, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_apply<VT>), dim3(blocks_for((int64_t)n * nrhs, 256)),
+                       dim3(256), 0, s, n, kinv, b, x, nrhs, transpose ? 1 : 0);
+    LAIR_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------
 // Sum of squares per right-hand side, fixed reduction order.
 // ---------------------------------------------------------------------------
@@ -322,13 +439,21 @@ k_sumsq_partial(const double *r, int64_t total, int32_t nrhs, int64_t chunk,
     if (t < nrhs) partial[(int64_t)blockIdx.x * nrhs + t] = sh[t];
 }
 
-__global__ void k_sumsq_final(const double *partial, int32_t nblk, int32_t nrhs,
-                              double *out) {
-    int q = threadIdx.x;
-    if (q >= nrhs) return;
+// one block per right-hand side; strided partial sums then a fixed tree
+__global__ void __launch_bounds__(NRM_BS)
+k_sumsq_final(const double *partial, int32_t nblk, int32_t nrhs, double *out) {
+    __shared__ double sh[NRM_BS];
+    int q = blockIdx.x;
+    int t = threadIdx.x;
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * nrhs + q];
-    out[q] = acc;
+    for (int b = t; b < nblk; b += NRM_BS) acc += partial[(int64_t)b * nrhs + q];
+    sh[t] = acc;
+    __syncthreads();
+    for (int o = NRM_BS / 2; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    if (t == 0) out[q] = sh[0];
 }
 
 void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
@@ -343,7 +468,7 @@ void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
     hipLaunchKernelGGL(k_sumsq_partial, dim3(nblk), dim3(NRM_BS), 0, s, r, total,
                        nrhs, chunk, partial);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, partial, nblk, nrhs, out);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, nblk, nrhs, out);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -411,8 +536,10 @@ template void op_residual<double>(const CsrView<double> &, const double *, const
 template void op_residual<float>(const CsrView<float> &, const float *, const float *, float *, int32_t, hipStream_t);
 template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t);
 template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t);
-template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, double *, double, int32_t, hipStream_t);
-template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, float *, double, int32_t, hipStream_t);
+template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t);
+template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t);
+template void op_coarse_apply<double>(int32_t, const double *, const double *, double *, int32_t, bool, hipStream_t);
+template void op_coarse_apply<float>(int32_t, const double *, const float *, float *, int32_t, bool, hipStream_t);
 template void op_scatter<double>(const int32_t *, int32_t, const double *, double *, int32_t, hipStream_t);
 template void op_scatter<float>(const int32_t *, int32_t, const float *, float *, int32_t, hipStream_t);
 template void op_fill<double>(double *, double, int64_t, hipStream_t);

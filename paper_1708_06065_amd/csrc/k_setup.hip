@@ -142,26 +142,45 @@ int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
 // 4 columns not strictly increasing, 8 non-finite value, 16 zero diagonal,
 // 32 missing diagonal.  stat[1] receives the longest row.
 // ===========================================================================
-__global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp,
-                           const int32_t *cj, const double *v, int32_t *stat) {
+__global__ void __launch_bounds__(256)
+k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cj,
+           const double *v, int32_t *stat) {
+    __shared__ int se[256], sm[256];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(stat, 1);
-    if (i >= n) return;
-    int64_t lo = rp[i], hi = rp[i + 1];
-    if (lo < 0 || hi < lo || hi > nnz) { atomicOr(stat, 1); return; }
-    int err = 0;
-    bool diag = false;
-    for (int64_t p = lo; p < hi; ++p) {
-        int c = cj[p];
-        if (c < 0 || c >= n) err |= 2;
-        if (p > lo && c <= cj[p - 1]) err |= 4;
-        double a = v[p];
-        if (!isfinite(a)) err |= 8;
-        if (c == i) { diag = true; if (a == 0.0) err |= 16; }
+    int err = 0, len = 0;
+    if (i < n) {
+        int64_t lo = rp[i], hi = rp[i + 1];
+        if (lo < 0 || hi < lo || hi > nnz) {
+            err = 1;
+        } else {
+            bool diag = false;
+            for (int64_t p = lo; p < hi; ++p) {
+                int c = cj[p];
+                if (c < 0 || c >= n) err |= 2;
+                if (p > lo && c <= cj[p - 1]) err |= 4;
+                double a = v[p];
+                if (!isfinite(a)) err |= 8;
+                if (c == i) { diag = true; if (a == 0.0) err |= 16; }
+            }
+            if (!diag) err |= 32;
+            len = (int)(hi - lo);
+        }
     }
-    if (!diag) err |= 32;
-    if (err) atomicOr(stat, err);
-    atomicMax(stat + 1, (int32_t)(hi - lo));
+    se[threadIdx.x] = err;
+    sm[threadIdx.x] = len;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            se[threadIdx.x] |= se[threadIdx.x + o];
+            sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (se[0]) atomicOr(stat, se[0]);
+        atomicMax(stat + 1, sm[0]);
+    }
 }
 
 int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
@@ -169,6 +188,7 @@ int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
     DevArr<int32_t> st;
     st.alloc(2, s);
     LAIR_HIP(hipMemsetAsync(st.get(), 0, 2 * sizeof(int32_t), s));
+    ProfScope ps("validate", s, 12.0 * nnz + 4.0 * (n + 1));
     hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        n, nnz, rp, cj, v, st.get());
     LAIR_LAUNCH_CHECK();
@@ -225,6 +245,8 @@ void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
                      const double *v, double theta, int32_t kind,
                      uint8_t *smask, double mean_len, hipStream_t s) {
     int t = team_for_mean(mean_len);
+    double nnz = mean_len * n;
+    ProfScope ps("strength", s, 13.0 * nnz + 4.0 * (n + 1));
     switch (t) {
         case 2: strength_t<2>(n, rp, cj, v, theta, kind, smask, s); break;
         case 4: strength_t<4>(n, rp, cj, v, theta, kind, smask, s); break;
@@ -238,25 +260,47 @@ void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
 // ===========================================================================
 // Coarse numbering (C-points in increasing fine index) and row lists.
 // ===========================================================================
-__global__ void k_cf_lists(int32_t n, const int8_t *cf, const int32_t *scan,
-                           int32_t *cidx, int32_t *clist, int32_t *flist) {
+__global__ void __launch_bounds__(256)
+k_cf_lists(int32_t n, const int8_t *cf, const int32_t *scan, const int32_t *rp,
+           int32_t *cidx, int32_t *clist, int32_t *flist,
+           unsigned long long *acc) {
+    __shared__ unsigned long long sf[256], sc[256];
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t c = scan[i];
-    if (cf[i] == 1) {
-        cidx[i] = c;
-        clist[c] = i;
-    } else {
-        cidx[i] = -1;
-        flist[i - c] = i;
+    unsigned long long nf = 0, ncc = 0;
+    if (i < n) {
+        int32_t c = scan[i];
+        unsigned long long len = (unsigned long long)(rp[i + 1] - rp[i]);
+        if (cf[i] == 1) {
+            cidx[i] = c;
+            clist[c] = i;
+            ncc = len;
+        } else {
+            cidx[i] = -1;
+            flist[i - c] = i;
+            nf = len;
+        }
+    }
+    sf[threadIdx.x] = nf;
+    sc[threadIdx.x] = ncc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sf[threadIdx.x] += sf[threadIdx.x + o];
+            sc[threadIdx.x] += sc[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(acc, sf[0]);
+        atomicAdd(acc + 1, sc[0]);
     }
 }
 
 void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
-                     int32_t *cidx, int32_t *clist, int32_t *flist,
-                     hipStream_t s) {
+                     const int32_t *rp, int32_t *cidx, int32_t *clist,
+                     int32_t *flist, unsigned long long *acc, hipStream_t s) {
     hipLaunchKernelGGL(k_cf_lists, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       n, cf, cidx_scan, cidx, clist, flist);
+                       n, cf, cidx_scan, rp, cidx, clist, flist, acc);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -383,6 +427,7 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
     (void)n;
     if (nc == 0) return;
     bool fill = (nbr != nullptr);
+    ProfScope ps("nbr", s, 4.0 * nc);
     int t;
     if (distance == 2) {
         int need = (max_row + 1 + NBR_LPL - 1) / NBR_LPL;
@@ -890,6 +935,39 @@ k_local_lstsq(const int32_t *list, int32_t nlist, const int32_t *clist,
 
 constexpr int SMALL_SM = 8;
 
+// Algorithmic cost of the local solves, split at s <= lim / s > lim:
+// bytes = (|row i| + sum_{j in N_i} |row j|) 12 + (s + 1) 12 (gather and R
+// row), flops = 2 s^3 / 3 + 2 s^2 (LU and triangular solves).
+__global__ void __launch_bounds__(256)
+k_local_cost(int32_t nc, const int32_t *clist, const int32_t *nptr,
+             const int32_t *nbr, const int32_t *rp, int32_t lim, double *acc) {
+    __shared__ double sh[4][256];
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c < nc) {
+        int32_t i = clist[c];
+        int s = nptr[c + 1] - nptr[c];
+        double rows = (double)(rp[i + 1] - rp[i]);
+        for (int q = 0; q < s; ++q) {
+            int j = nbr[nptr[c] + q];
+            rows += (double)(rp[j + 1] - rp[j]);
+        }
+        double ds = (double)s;
+        int k = (s <= lim) ? 0 : 2;
+        v[k] = 12.0 * rows + 12.0 * (s + 1);
+        v[k + 1] = 2.0 * ds * ds * ds / 3.0 + 2.0 * ds * ds;
+    }
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) atomicAdd(acc + k, sh[k][0]);
+}
+
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax,
@@ -901,6 +979,19 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     counters.alloc(2, s);
     LAIR_HIP(hipMemsetAsync(counters.get(), 0, 2 * sizeof(int32_t), s));
     bool mixed = (precision == LAIR_MIXED);
+    double cost[4] = {0, 0, 0, 0};
+    if (prof_selected("local_small") || prof_selected("local_wave")) {
+        DevArr<double> acc;
+        acc.alloc(4, s);
+        LAIR_HIP(hipMemsetAsync(acc.get(), 0, 4 * sizeof(double), s));
+        hipLaunchKernelGGL(k_local_cost, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+                           nc, clist, nptr, nbr, rp, smax <= 4 ? 4 : SMALL_SM, acc.get());
+        LAIR_LAUNCH_CHECK();
+        LAIR_HIP(hipMemcpyAsync(cost, acc.get(), sizeof(cost), hipMemcpyDeviceToHost, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+    }
+    {
+    ProfScope ps_small("local_small", s, cost[0], cost[1]);
     if (smax <= 4) {
         if (mixed)
             hipLaunchKernelGGL((k_local_small<4, true>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
@@ -921,6 +1012,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                                big.get(), counters.get(), sing.get(), counters.get() + 1);
     }
     LAIR_LAUNCH_CHECK();
+    }
     int32_t h[2];
     LAIR_HIP(hipMemcpyAsync(h, counters.get(), sizeof(h), hipMemcpyDeviceToHost, s));
     LAIR_HIP(hipStreamSynchronize(s));
@@ -928,6 +1020,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     if (nbig > 0) {
         DevArr<double> scratch;
         if (smax > WSMAX) scratch.alloc((size_t)nbig * (size_t)smax * smax * 3 + 16, s);
+        ProfScope ps_wave("local_wave", s, cost[2], cost[3]);
         if (mixed)
             hipLaunchKernelGGL((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), 0, s,
                                big.get(), nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
@@ -944,6 +1037,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     if (nsing > 0) {
         DevArr<double> scratch;
         scratch.alloc((size_t)nsing * (2 * (size_t)smax * smax + 2 * (size_t)smax), s);
+        ProfScope ps_ls("local_lstsq", s, 0.0);
         hipLaunchKernelGGL(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
                            sing.get(), nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
                            out.r_v, scratch.get(), smax);

@@ -44,6 +44,7 @@ struct Level {
     DevCSR A, R, P;            // A_l (n x n), R_l (nc x n), P_l (n x nc)
     DevCSR At, Rt, Pt;         // transposes for the adjoint cycle
     int32_t n = 0, nc = 0, nf = 0;
+    int64_t nnzF = 0, nnzC = 0;     // stored entries in the F rows / C rows
     int32_t max_row = 0;
     int32_t team_A = 8, team_R = 8, team_P = 2;
     int32_t team_At = 8, team_Rt = 2, team_Pt = 8;
@@ -67,6 +68,7 @@ struct lair_hierarchy {
     int32_t nL = 0;                          // coarsest size
     lair::DevArr<double> lu;
     lair::DevArr<int32_t> piv;
+    lair::DevArr<double> kinv;               // explicit inverse when nL <= 512
     lair::DevArr<double> dinv;               // block scaling (block_size > 0)
     int32_t nrhs_cap = 0;
     lair::DevArr<double> bscaled, r0, partial, norms;
@@ -123,6 +125,11 @@ __global__ void k_add(double *x, const double *e, int64_t m) {
     if (i < m) x[i] += e[i];
 }
 
+__global__ void k_set_diag(int32_t n, double *a) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[(size_t)i * n + i] = 1.0;
+}
+
 __global__ void k_r_rowptr(int32_t nc, const int32_t *nptr, int32_t *rrp) {
     int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c <= nc) rrp[c] = nptr[c] + c;
@@ -162,9 +169,14 @@ static void spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
     cnt.alloc((size_t)A.nrows + 1, s);
     over.alloc(1, s);
     LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
-    launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                  B.v.get(), max_row_a, false, cnt.get(), nullptr, nullptr, nullptr,
-                  over.get(), s);
+    {
+        // symbolic pass: indices of A and of the rows of B, counts out
+        ProfScope ps("spgemm_count", s, 4.0 * (A.nnz + B.nnz) + 8.0 * (A.nrows + 1) +
+                                            4.0 * (B.nrows + 1));
+        launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
+                      B.v.get(), max_row_a, false, cnt.get(), nullptr, nullptr, nullptr,
+                      over.get(), s);
+    }
     C.rp.alloc((size_t)A.nrows + 1, s);
     C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), A.nrows, s, tmp);
     int32_t ov = 0;
@@ -173,9 +185,14 @@ static void spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
     if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
     C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
-    launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                  B.v.get(), max_row_a, true, nullptr, C.rp.get(), C.cj.get(), C.v.get(),
-                  over.get(), s);
+    {
+        // numeric pass: A, the rows of B and C each touched once
+        ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz + C.nnz) +
+                                           8.0 * (A.nrows + 1) + 4.0 * (B.nrows + 1));
+        launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
+                      B.v.get(), max_row_a, true, nullptr, C.rp.get(), C.cj.get(), C.v.get(),
+                      over.get(), s);
+    }
 }
 
 static void transpose(const DevCSR &M, DevCSR &T, hipStream_t s,
@@ -278,8 +295,19 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.cidx.alloc((size_t)n, s);
     Lv.clist.alloc((size_t)Lv.nc, s);
     Lv.flist.alloc((size_t)std::max(Lv.nf, 1), s);
-    launch_cf_lists(n, Lv.cf.get(), scan.get(), Lv.cidx.get(), Lv.clist.get(),
-                    Lv.flist.get(), s);
+    {
+        DevArr<unsigned long long> acc;
+        acc.alloc(2, s);
+        LAIR_HIP(hipMemsetAsync(acc.get(), 0, 2 * sizeof(unsigned long long), s));
+        ProfScope ps("cf_lists", s, 13.0 * n + 4.0 * n);
+        launch_cf_lists(n, Lv.cf.get(), scan.get(), A.rp.get(), Lv.cidx.get(), Lv.clist.get(),
+                        Lv.flist.get(), acc.get(), s);
+        unsigned long long hacc[2];
+        LAIR_HIP(hipMemcpyAsync(hacc, acc.get(), sizeof(hacc), hipMemcpyDeviceToHost, s));
+        LAIR_HIP(hipStreamSynchronize(s));
+        Lv.nnzF = (int64_t)hacc[0];
+        Lv.nnzC = (int64_t)hacc[1];
+    }
 
     // neighbourhoods
     DevArr<int32_t> cnt, over;
@@ -340,8 +368,11 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     if (h->opt.interp == LAIR_P_ONE_POINT) {
         DevArr<int32_t> pcol;
         pcol.alloc((size_t)n, s);
-        launch_interp_one_point(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
-                                Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
+        {
+            ProfScope ps("interp", s, 13.0 * A.nnz + 9.0 * n);
+            launch_interp_one_point(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                    Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
+        }
         DevArr<int32_t> has;
         has.alloc((size_t)n, s);
         hipLaunchKernelGGL(k_nonneg_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s,
@@ -354,15 +385,25 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     } else {
         DevArr<int32_t> pc;
         pc.alloc((size_t)n, s);
-        launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(), Lv.cf.get(),
-                             Lv.cidx.get(), false, pc.get(), nullptr, nullptr, nullptr, s);
+        {
+            ProfScope ps("interp", s, 6.0 * A.nnz + 9.0 * n);
+            launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                 Lv.cf.get(), Lv.cidx.get(), false, pc.get(), nullptr, nullptr,
+                                 nullptr, s);
+        }
         P.nnz = scan_counts_i32(pc.get(), P.rp.get(), n, s, tmp);
         P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
-        launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(), Lv.cf.get(),
-                             Lv.cidx.get(), true, nullptr, P.rp.get(), P.cj.get(), P.v.get(), s);
+        {
+            ProfScope ps("interp", s, 14.0 * A.nnz + 13.0 * n + 12.0 * P.nnz);
+            launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                 Lv.cf.get(), Lv.cidx.get(), true, nullptr, P.rp.get(),
+                                 P.cj.get(), P.v.get(), s);
+        }
     }
 }
+
+static const int32_t MAX_INVERSE = 512;
 
 static void finish_coarsest(lair_hierarchy *h) {
     hipStream_t s = h->stream;
@@ -371,6 +412,7 @@ static void finish_coarsest(lair_hierarchy *h) {
     if (n > MAX_DENSE)
         fail(LAIR_EUNSUPPORTED, "coarsest level has %d rows (> %d) after coarsening stalled",
              n, MAX_DENSE);
+    ProfScope ps("coarse_setup", s, 8.0 * n * (double)n, 2.0 / 3.0 * n * (double)n * n);
     h->nL = n;
     h->lu.alloc((size_t)n * n, s);
     h->piv.alloc((size_t)std::max(n, 1), s);
@@ -382,23 +424,23 @@ static void finish_coarsest(lair_hierarchy *h) {
     LAIR_HIP(hipMemcpyAsync(&hinfo, info.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LAIR_HIP(hipStreamSynchronize(s));
     if (hinfo != 0) fail(LAIR_ESINGULAR, "coarsest matrix (n = %d) is singular at pivot %d", n, hinfo);
-}
-
-// nnz of the F rows and C rows of each level (for the cycle complexity)
-__global__ void k_rowset_nnz(int32_t nx, const int32_t *rows, const int32_t *rp,
-                             unsigned long long *acc) {
-    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nx) return;
-    int32_t i = rows[k];
-    atomicAdd(acc, (unsigned long long)(rp[i + 1] - rp[i]));
+    if (n <= MAX_INVERSE) {
+        // K^{-1} from the LU factors applied to the identity (columns
+        // interleaved, so row i of the result is row i of K^{-1})
+        DevArr<double> eye;
+        eye.alloc((size_t)n * n, s);
+        op_fill<double>(eye.get(), 0.0, (int64_t)n * n, s);
+        hipLaunchKernelGGL(k_set_diag, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, eye.get());
+        LAIR_LAUNCH_CHECK();
+        h->kinv.alloc((size_t)n * n, s);
+        op_dense_solve<double>(n, h->lu.get(), h->piv.get(), eye.get(), h->kinv.get(), n,
+                               false, s);
+    }
 }
 
 static void level_stats_and_cc(lair_hierarchy *h) {
-    hipStream_t s = h->stream;
     double nnz0 = (double)h->L[0]->A.nnz;
     double flops = 0.0, sum = 0.0;
-    DevArr<unsigned long long> acc;
-    acc.alloc(2, s);
     for (size_t l = 0; l < h->L.size(); ++l) {
         Level &Lv = *h->L[l];
         Lv.st.n = Lv.n;
@@ -408,19 +450,9 @@ static void level_stats_and_cc(lair_hierarchy *h) {
         Lv.st.nnz_P = Lv.P.nnz;
         sum += (double)Lv.A.nnz;
         if (l + 1 == h->L.size()) break;
-        LAIR_HIP(hipMemsetAsync(acc.get(), 0, 2 * sizeof(unsigned long long), s));
-        if (Lv.nf)
-            hipLaunchKernelGGL(k_rowset_nnz, dim3(blocks_for(Lv.nf, 256)), dim3(256), 0, s,
-                               Lv.nf, Lv.flist.get(), Lv.A.rp.get(), acc.get());
-        if (Lv.nc)
-            hipLaunchKernelGGL(k_rowset_nnz, dim3(blocks_for(Lv.nc, 256)), dim3(256), 0, s,
-                               Lv.nc, Lv.clist.get(), Lv.A.rp.get(), acc.get() + 1);
-        LAIR_LAUNCH_CHECK();
-        unsigned long long hacc[2];
-        LAIR_HIP(hipMemcpyAsync(hacc, acc.get(), sizeof(hacc), hipMemcpyDeviceToHost, s));
-        LAIR_HIP(hipStreamSynchronize(s));
+        // residual, restriction, interpolation, then F, F, C Jacobi sweeps
         flops += 2.0 * Lv.A.nnz + 2.0 * Lv.R.nnz + 2.0 * Lv.P.nnz;
-        flops += 2.0 * (2.0 * (double)hacc[0] + (double)hacc[1]);
+        flops += 2.0 * (2.0 * (double)Lv.nnzF + (double)Lv.nnzC);
     }
     double nl = (double)h->L.back()->n;
     flops += 2.0 * nl * nl;
@@ -558,7 +590,7 @@ static void ensure_vectors(lair_hierarchy *h, int32_t nrhs, hipStream_t s) {
     for (size_t l = 0; l < h->L.size(); ++l) {
         Level &Lv = *h->L[l];
         size_t n = (size_t)Lv.n * nrhs;
-        size_t tn = (size_t)std::max(std::max(Lv.nf, Lv.nc), 1) * nrhs;
+        size_t tn = (size_t)std::max(Lv.n, 1) * nrhs;
         Lv.b.alloc(n, s);
         Lv.x.alloc(n, s);
         Lv.r.alloc(n, s);
@@ -588,18 +620,71 @@ static VT *vec(DevArr<double> &d, DevArr<float> &f) {
     else { (void)d; return f.get(); }
 }
 
-// F, F, C Jacobi sweeps on level l.
+// Algorithmic bytes of the cycle operations (w = value size, R = number of
+// right-hand sides): every matrix entry (index + value), row pointer, source
+// vector entry and destination entry counted once.
+static double ab_rowdot(const DevCSR &M, int w, int R, int vec_in_out) {
+    return (4.0 + w) * (double)M.nnz + 4.0 * (M.nrows + 1) + (double)w * R * M.ncols +
+           (double)w * R * M.nrows * vec_in_out;
+}
+static double ab_jacobi(int64_t nnz_x, int32_t nx, int32_t n, int w, int R, bool sel) {
+    return (4.0 + w) * (double)nnz_x + 12.0 * nx + (double)w * R * n + 2.0 * w * R * nx +
+           (sel ? (double)n : 0.0);
+}
+
+template <class VT>
+static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
+                         bool transpose, hipStream_t s) {
+    const int w = sizeof(VT);
+    ProfScope ps("coarse_solve", s, 8.0 * h->nL * (double)h->nL + 2.0 * w * nrhs * h->nL,
+                 2.0 * h->nL * (double)h->nL * nrhs);
+    if (h->kinv.get()) {
+        op_coarse_apply<VT>(h->nL, h->kinv.get(), b, x, nrhs, transpose, s);
+        return;
+    }
+    Level &Lc = *h->L.back();
+    if constexpr (std::is_same<VT, double>::value) {
+        op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), b, x, nrhs, transpose, s);
+    } else {
+        int64_t m = (int64_t)h->nL * nrhs;
+        op_cast_f64(b, Lc.r.get(), m, s);
+        op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), Lc.r.get(), Lc.x.get(),
+                               nrhs, transpose, s);
+        op_cast_f32(Lc.x.get(), x, m, s);
+    }
+}
+
+// F, F, C Jacobi sweeps on a level, every sweep reading the previous iterate.
+// X is the iterate, Y a level-sized buffer:
+//   F sweep 1 reads X, writes Y at the F rows;
+//   F sweep 2 reads Y at F-points and X at C-points, writes X at the F rows
+//     (X's F entries are not read by this sweep);
+//   C sweep reads X, writes a compact buffer that is then scattered to X.
 template <class VT>
 static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
                 hipStream_t s) {
     CsrView<VT> A = view<VT>(Lv.A, Lv.team_A);
-    VT *t = vec<VT>(Lv.t, Lv.t32);
+    VT *y = vec<VT>(Lv.t, Lv.t32);
     double om = h->opt.omega;
-    for (int sweep = 0; sweep < 3; ++sweep) {
-        const int32_t *rows = sweep < 2 ? Lv.flist.get() : Lv.clist.get();
-        int32_t nx = sweep < 2 ? Lv.nf : Lv.nc;
-        op_jacobi<VT>(A, rows, nx, b, x, t, om, nrhs, s);
-        op_scatter<VT>(rows, nx, t, x, nrhs, s);
+    const int w = sizeof(VT);
+    {
+        ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, false),
+                     2.0 * Lv.nnzF * nrhs);
+        op_jacobi<VT>(A, Lv.flist.get(), Lv.nf, b, x, x, nullptr, y, false, om, nrhs, s);
+    }
+    {
+        ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, true),
+                     2.0 * Lv.nnzF * nrhs);
+        op_jacobi<VT>(A, Lv.flist.get(), Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s);
+    }
+    {
+        ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, Lv.nc, Lv.n, w, nrhs, false),
+                     2.0 * Lv.nnzC * nrhs);
+        op_jacobi<VT>(A, Lv.clist.get(), Lv.nc, b, x, x, nullptr, y, true, om, nrhs, s);
+    }
+    {
+        ProfScope ps("scatter", s, 4.0 * Lv.nc + 2.0 * w * nrhs * Lv.nc);
+        op_scatter<VT>(Lv.clist.get(), Lv.nc, y, x, nrhs, s);
     }
 }
 
@@ -610,17 +695,9 @@ template <class VT>
 static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
                    const VT *r, int32_t nrhs, hipStream_t s) {
     Level &Lv = *h->L[l];
+    const int w = sizeof(VT);
     if (l + 1 == h->L.size()) {
-        if constexpr (std::is_same<VT, double>::value) {
-            op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), b, x, nrhs, false, s);
-        } else {
-            // the coarsest solve stays in double
-            int64_t m = (int64_t)h->nL * nrhs;
-            op_cast_f64(b, Lv.r.get(), m, s);
-            op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), Lv.r.get(), Lv.x.get(),
-                                   nrhs, false, s);
-            op_cast_f32(Lv.x.get(), x, m, s);
-        }
+        coarse_solve<VT>(h, b, x, nrhs, false, s);
         return;
     }
     Level &Nx = *h->L[l + 1];
@@ -630,15 +707,23 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
             res = r;
         } else {
             VT *rr = vec<VT>(Lv.r, Lv.r32);
+            ProfScope ps("residual", s, ab_rowdot(Lv.A, w, nrhs, 2), 2.0 * Lv.A.nnz * nrhs);
             op_residual<VT>(view<VT>(Lv.A, Lv.team_A), b, x, rr, nrhs, s);
             res = rr;
         }
     }
     VT *bc = vec<VT>(Nx.b, Nx.b32);
     VT *xc = vec<VT>(Nx.x, Nx.x32);
-    op_spmv<VT>(view<VT>(Lv.R, Lv.team_R), res, bc, nrhs, false, s);
+    {
+        ProfScope ps("restrict", s, ab_rowdot(Lv.R, w, nrhs, 1), 2.0 * Lv.R.nnz * nrhs);
+        op_spmv<VT>(view<VT>(Lv.R, Lv.team_R), res, bc, nrhs, false, s);
+    }
     vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s);
-    op_spmv<VT>(view<VT>(Lv.P, Lv.team_P), xc, x, nrhs, !x_zero, s);
+    {
+        ProfScope ps("interpolate", s, ab_rowdot(Lv.P, w, nrhs, x_zero ? 1 : 2),
+                     2.0 * Lv.P.nnz * nrhs);
+        op_spmv<VT>(view<VT>(Lv.P, Lv.team_P), xc, x, nrhs, !x_zero, s);
+    }
     ffc<VT>(h, Lv, b, x, nrhs, s);
 }
 
@@ -666,7 +751,7 @@ static void vcycle_t(lair_hierarchy *h, size_t l, const double *g, double *lam,
                      bool lam_zero, int32_t nrhs, hipStream_t s) {
     Level &Lv = *h->L[l];
     if (l + 1 == h->L.size()) {
-        op_dense_solve<double>(h->nL, h->lu.get(), h->piv.get(), g, lam, nrhs, true, s);
+        coarse_solve<double>(h, g, lam, nrhs, true, s);
         return;
     }
     if (lam_zero) op_fill<double>(lam, 0.0, (int64_t)Lv.n * nrhs, s);
@@ -675,7 +760,7 @@ static void vcycle_t(lair_hierarchy *h, size_t l, const double *g, double *lam,
     for (int sweep = 0; sweep < 3; ++sweep) {
         const int32_t *rows = sweep == 0 ? Lv.clist.get() : Lv.flist.get();
         int32_t nx = sweep == 0 ? Lv.nc : Lv.nf;
-        op_jacobi<double>(At, rows, nx, g, lam, Lv.t.get(), om, nrhs, s);
+        op_jacobi<double>(At, rows, nx, g, lam, lam, nullptr, Lv.t.get(), true, om, nrhs, s);
         op_scatter<double>(rows, nx, Lv.t.get(), lam, nrhs, s);
     }
     op_residual<double>(At, g, lam, Lv.r.get(), nrhs, s);
@@ -691,7 +776,10 @@ static bool valid_nrhs(int32_t nrhs) {
 
 static void norms_host(lair_hierarchy *h, const double *r, int32_t nrhs,
                        hipStream_t s, std::vector<double> &out) {
-    op_sumsq(r, h->L[0]->n, nrhs, h->partial.get(), NPARTIAL, h->norms.get(), s);
+    {
+        ProfScope ps("norm", s, 8.0 * nrhs * h->L[0]->n, 2.0 * nrhs * h->L[0]->n);
+        op_sumsq(r, h->L[0]->n, nrhs, h->partial.get(), NPARTIAL, h->norms.get(), s);
+    }
     out.resize((size_t)nrhs);
     LAIR_HIP(hipMemcpyAsync(out.data(), h->norms.get(), sizeof(double) * nrhs,
                             hipMemcpyDeviceToHost, s));
@@ -725,7 +813,11 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     int32_t it = 0;
     double relmax = 0.0;
     for (;;) {
-        op_residual<double>(A0, bb, x, h->r0.get(), nrhs, s);
+        {
+            const DevCSR &M0 = transpose ? L0.At : L0.A;
+            ProfScope ps("residual", s, ab_rowdot(M0, 8, nrhs, 2), 2.0 * M0.nnz * nrhs);
+            op_residual<double>(A0, bb, x, h->r0.get(), nrhs, s);
+        }
         norms_host(h, h->r0.get(), nrhs, s, rn);
         if (it == 0) r_first = rn;
         relmax = 0.0;
@@ -746,9 +838,15 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
         } else if (!mixed) {
             vcycle<double>(h, 0, bb, x, false, h->r0.get(), nrhs, s);
         } else {
-            op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
+            {
+                ProfScope ps("cast", s, 12.0 * n * nrhs);
+                op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
+            }
             vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, s);
-            op_axpy_f32(x, h->e32.get(), n * nrhs, s);
+            {
+                ProfScope ps("cast", s, 20.0 * n * nrhs);
+                op_axpy_f32(x, h->e32.get(), n * nrhs, s);
+            }
         }
         ++it;
     }

@@ -96,6 +96,23 @@ struct DevCSR {
 };
 
 // ---------------------------------------------------------------------------
+// Kernel profiler: when enabled (lair_profile_begin), launches of the
+// selected categories are bracketed by HIP events on their own stream and
+// tagged with their algorithmic bytes and flops.  Disabled it costs one
+// branch per launch.
+// ---------------------------------------------------------------------------
+struct ProfScope {
+    ProfScope(const char *category, hipStream_t s, double bytes, double flops = 0.0);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+    int slot = -1;
+    hipStream_t stream = nullptr;
+};
+// true while profiling is on and `category` is selected
+bool prof_selected(const char *category);
+
+// ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
 inline unsigned blocks_for(int64_t threads, int bs) {
@@ -124,9 +141,10 @@ int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
 void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
                      const double *v, double theta, int32_t kind,
                      uint8_t *smask, double mean_len, hipStream_t s);
+// cidx, C and F row lists; acc[0] += nnz of F rows, acc[1] += nnz of C rows
 void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
-                     int32_t *cidx, int32_t *clist, int32_t *flist,
-                     hipStream_t s);
+                     const int32_t *rp, int32_t *cidx, int32_t *clist,
+                     int32_t *flist, unsigned long long *acc, hipStream_t s);
 // neighbourhood sizes (fill = false) or lists (fill = true)
 void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
                            const int32_t *rp, const int32_t *cj,
@@ -194,10 +212,17 @@ void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
 template <class VT>
 void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
              bool accumulate, hipStream_t s);
+// Jacobi on rows X: out[k] (compact) or out[i] = x_i + omega (b - A x)_i / a_ii.
+// With cf non-null, neighbour values come from xC at C-points and from xF
+// at F-points; otherwise everything is read from xF.
 template <class VT>
 void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nrows,
-               const VT *b, const VT *x, VT *t, double omega, int32_t nrhs,
+               const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
+               VT *out, bool compact, double omega, int32_t nrhs,
                hipStream_t s);
+template <class VT>
+void op_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x,
+                     int32_t nrhs, bool transpose, hipStream_t s);
 template <class VT>
 void op_scatter(const int32_t *rows, int32_t nrows, const VT *t, VT *x,
                 int32_t nrhs, hipStream_t s);

@@ -1,0 +1,152 @@
+// Kernel profiler behind lair_profile_begin / lair_profile_end.
+//
+// Each profiled launch records a pair of HIP events on the stream the kernel
+// runs on, so the elapsed time is that of the launch itself as the stream
+// executes it.  Records carry the algorithmic bytes and flops of the launch
+// (the data the operation must touch at least once), from which the caller
+// derives achieved bandwidth.  Process-wide; not for concurrent use from
+// several host threads.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lair_internal.hpp"
+
+namespace lair {
+
+namespace {
+struct Rec {
+    std::string cat;
+    hipEvent_t e0, e1;
+    double bytes, flops;
+};
+struct Prof {
+    bool on = false;
+    std::string filter;            // empty: every category
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    std::mutex mu;
+};
+Prof &prof() {
+    static Prof p;
+    return p;
+}
+hipEvent_t take_event(Prof &p) {
+    if (!p.pool.empty()) {
+        hipEvent_t e = p.pool.back();
+        p.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+bool selected(const Prof &p, const char *cat) {
+    if (p.filter.empty()) return true;
+    // comma-separated list of category names
+    size_t pos = 0;
+    while (pos <= p.filter.size()) {
+        size_t c = p.filter.find(',', pos);
+        std::string tok = p.filter.substr(pos, c == std::string::npos ? std::string::npos : c - pos);
+        if (tok == cat) return true;
+        if (c == std::string::npos) break;
+        pos = c + 1;
+    }
+    return false;
+}
+}  // namespace
+
+bool prof_selected(const char *category) {
+    Prof &p = prof();
+    if (!p.on) return false;
+    std::lock_guard<std::mutex> g(p.mu);
+    return selected(p, category);
+}
+
+ProfScope::ProfScope(const char *category, hipStream_t s, double bytes, double flops) {
+    Prof &p = prof();
+    if (!p.on) return;
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!selected(p, category)) return;
+    Rec r{category, take_event(p), take_event(p), bytes, flops};
+    if (!r.e0 || !r.e1) return;
+    if (hipEventRecord(r.e0, s) != hipSuccess) return;
+    stream = s;
+    slot = (int)p.recs.size();
+    p.recs.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+    if (slot < 0) return;
+    Prof &p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    if (slot < (int)p.recs.size()) (void)hipEventRecord(p.recs[slot].e1, stream);
+}
+
+}  // namespace lair
+
+using namespace lair;
+
+extern "C" {
+
+lair_status lair_profile_begin(const char *categories) {
+    Prof &p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    for (auto &r : p.recs) {
+        p.pool.push_back(r.e0);
+        p.pool.push_back(r.e1);
+    }
+    p.recs.clear();
+    p.filter = categories ? categories : "";
+    p.on = true;
+    return LAIR_OK;
+}
+
+lair_status lair_profile_end(char *json, int64_t *len) {
+    Prof &p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.on = false;
+    struct Agg { long n = 0; double ms = 0, bytes = 0, flops = 0, ms_max = 0; };
+    std::map<std::string, Agg> agg;
+    lair_status st = LAIR_OK;
+    for (auto &r : p.recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) {
+            st = LAIR_EDEVICE;
+            continue;
+        }
+        Agg &a = agg[r.cat];
+        a.n += 1;
+        a.ms += ms;
+        a.bytes += r.bytes;
+        a.flops += r.flops;
+        if (ms > a.ms_max) a.ms_max = ms;
+    }
+    std::string out = "{";
+    bool first = true;
+    for (auto &kv : agg) {
+        char buf[512];
+        snprintf(buf, sizeof(buf),
+                 "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"ms_max\": %.6f, "
+                 "\"alg_bytes\": %.1f, \"alg_flops\": %.1f}",
+                 first ? "" : ", ", kv.first.c_str(), kv.second.n, kv.second.ms,
+                 kv.second.ms_max, kv.second.bytes, kv.second.flops);
+        out += buf;
+        first = false;
+    }
+    out += "}";
+    if (len) {
+        int64_t cap = *len;
+        *len = (int64_t)out.size() + 1;
+        if (json && cap >= (int64_t)out.size() + 1) memcpy(json, out.c_str(), out.size() + 1);
+        else if (json) st = LAIR_EINVAL;
+    }
+    return st;
+}
+
+}  // extern "C"
