@@ -1,0 +1,64 @@
+"""Differentiable lAIR solve: x = A(c)^{-1} b with A(c) = A0 + diag(c).
+
+The forward pass builds an lAIR hierarchy for A(c) and runs the stationary
+V-cycle iteration; the backward pass solves the adjoint system
+A(c)^T lam = dJ/dx with the transposed cycle of the same hierarchy
+(pre-relaxation C, F, F on A^T, restriction with P^T, interpolation with
+R^T).  Then dJ/db = lam and dJ/dc_k = -lam_k x_k, because
+dA/dc_k = e_k e_k^T.  Both solves run in liblair's kernels.
+"""
+import torch
+
+from . import setup as _setup
+
+
+def _diag_positions(rowptr, col):
+    """Index of the diagonal entry of each row (CSR on the device)."""
+    n = rowptr.shape[0] - 1
+    rows = torch.repeat_interleave(torch.arange(n, device=col.device),
+                                   (rowptr[1:] - rowptr[:-1]).long())
+    pos = torch.nonzero(col.long() == rows, as_tuple=False).squeeze(1)
+    if pos.shape[0] != n:
+        raise ValueError("every row needs a stored diagonal entry")
+    return pos
+
+
+class LairSolve(torch.autograd.Function):
+    """x = LairSolve.apply(b, c, rowptr, col, val0, opts)
+
+    b: (n,) or (n, nrhs) float64 CUDA tensor; c: (n,) float64 CUDA tensor
+    added to the diagonal of the CSR matrix (rowptr, col, val0);
+    opts: dict of lair.setup keyword arguments plus rtol and maxit.
+    """
+
+    @staticmethod
+    def forward(ctx, b, c, rowptr, col, val0, opts):
+        opts = dict(opts or {})
+        rtol = opts.pop("rtol", 1e-10)
+        maxit = opts.pop("maxit", 200)
+        pos = _diag_positions(rowptr, col)
+        val = val0.clone()
+        val[pos] += c
+        h = _setup(rowptr, col, val, **opts)
+        x, info = h.solve(b.contiguous(), rtol=rtol, maxit=maxit)
+        if not info["converged"]:
+            raise RuntimeError("lAIR forward solve did not converge: %r" % info)
+        ctx.h = h
+        ctx.rtol, ctx.maxit = rtol, maxit
+        ctx.save_for_backward(x)
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        lam, info = ctx.h.solve_transpose(gx.contiguous(), rtol=ctx.rtol * 1e-2,
+                                          maxit=ctx.maxit)
+        if not info["converged"]:
+            raise RuntimeError("lAIR adjoint solve did not converge: %r" % info)
+        gb = lam if ctx.needs_input_grad[0] else None
+        gc = None
+        if ctx.needs_input_grad[1]:
+            gc = -(lam * x) if lam.dim() == 1 else -(lam * x).sum(dim=1)
+        ctx.h.free()
+        return gb, gc, None, None, None, None

@@ -9,6 +9,19 @@
 namespace lair {
 
 constexpr int WAVE = 64;
+constexpr int NXCD = 8;
+
+// The hardware hands workgroups to the 8 XCDs round-robin, and each XCD has
+// its own L2.  Remap the workgroup id so that every XCD runs one contiguous
+// range of logical blocks: consecutive rows, which share matrix and vector
+// cache lines, then share an L2 instead of being striped over eight.  The
+// map is a bijection on [0, gridDim.x) for any grid size.
+__device__ __forceinline__ int64_t xcd_block_id() {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t x = b % NXCD, k = b / NXCD;
+    const int64_t q = nb / NXCD, r = nb % NXCD;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
 
 // Butterfly reductions over a team of T consecutive lanes (T a power of two
 // dividing 64).  Every lane of the team receives the result; the order of
@@ -62,6 +75,14 @@ __device__ __forceinline__ void team_argmax(double &v, int &idx) {
         int oi = __shfl_xor(idx, o, T);
         if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
     }
+}
+
+// Make the LDS writes of the calling wave visible to its later LDS reads
+// (lanes of one wave run in lockstep; only memory ordering is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Position of `key` in the sorted list a[0..n), or -1.

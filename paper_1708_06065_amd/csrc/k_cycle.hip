@@ -85,7 +85,7 @@ template <class VT, int T, int MODE>
 __global__ void __launch_bounds__(256)
 k_rowdot1(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
           const VT *x, const VT *b, VT *y) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (i >= nrows) return;
@@ -103,7 +103,7 @@ template <class VT, int NR, int MODE>
 __global__ void __launch_bounds__(256)
 k_rowdotM(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
           const VT *x, const VT *b, VT *y) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / NR);
     int q = (int)(gt % NR);
     if (i >= nrows) return;
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256)
 k_jacobi1(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
           const VT *v, const VT *b, const VT *xF, const VT *xC,
           const int8_t *cf, VT *out, int compact, VT omega) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t k = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (k >= nx) return;
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256)
 k_jacobiM(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
           const VT *v, const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
           VT *out, int compact, VT omega) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t k = (int32_t)(gt / NR);
     int q = (int)(gt % NR);
     if (k >= nx) return;

@@ -58,8 +58,9 @@ __device__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) 
 
 template <class F>
 __global__ void __launch_bounds__(SCAN_BS)
-k_scan_tile(F f, int64_t n, int32_t *out, int64_t *blocksum) {
+k_scan_tile(F f, int64_t n, int32_t *out, int64_t *blocksum, int64_t *blockmax) {
     __shared__ int64_t sh[SCAN_BS];
+    __shared__ int64_t smx[SCAN_BS];
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int64_t v[SCAN_IPT];
     int64_t s = 0;
@@ -71,19 +72,40 @@ k_scan_tile(F f, int64_t n, int32_t *out, int64_t *blocksum) {
     }
     int64_t total;
     int64_t pre = block_exclusive_scan(s, sh, total);
+    int64_t m = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
         int64_t i = base + j;
         if (i < n) out[i] = (int32_t)pre;
         pre += v[j];
+        m = v[j] > m ? v[j] : m;
     }
     if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+    smx[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = SCAN_BS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o && smx[threadIdx.x + o] > smx[threadIdx.x])
+            smx[threadIdx.x] = smx[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blockmax[blockIdx.x] = smx[0];
 }
 
 __global__ void __launch_bounds__(SCAN_BS)
-k_scan_sums(int64_t *bs, int64_t nb, int64_t *total) {
+k_scan_sums(int64_t *bs, const int64_t *bmax, int64_t nb, int64_t *total) {
     __shared__ int64_t sh[SCAN_BS];
     int64_t carry = 0;
+    int64_t m = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += SCAN_BS) m = bmax[i] > m ? bmax[i] : m;
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = SCAN_BS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o && sh[threadIdx.x + o] > sh[threadIdx.x])
+            sh[threadIdx.x] = sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) total[1] = sh[0];
+    __syncthreads();
     for (int64_t base = 0; base < nb; base += SCAN_BS) {
         int64_t i = base + threadIdx.x;
         int64_t v = (i < nb) ? bs[i] : 0;
@@ -104,37 +126,43 @@ __global__ void k_scan_add(int32_t *out, int64_t n, const int64_t *bs,
 
 template <class F>
 static int64_t scan_impl(F f, int32_t *out, int64_t n, hipStream_t s,
-                         DevArr<int64_t> &tmp) {
+                         DevArr<int64_t> &tmp, int64_t *max_out,
+                         const int32_t *flag, int32_t *flag_out) {
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
-    tmp.ensure((size_t)nb + 1, s);
+    tmp.ensure((size_t)2 * nb + 2, s);
     int64_t *bs = tmp.get();
-    int64_t *tot = bs + nb;
+    int64_t *bmax = bs + nb;
+    int64_t *tot = bmax + nb;      // tot[0] = total, tot[1] = largest value
     hipLaunchKernelGGL(k_scan_tile<F>, dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
-                       f, n, out, bs);
+                       f, n, out, bs, bmax);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, nb, tot);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, bmax, nb, tot);
     LAIR_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
                        0, s, out, n, bs, tot);
     LAIR_LAUNCH_CHECK();
-    int64_t total = 0;
-    LAIR_HIP(hipMemcpyAsync(&total, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
-    if (total > INT32_MAX)
+    int64_t h[2] = {0, 0};
+    Readback rb(s);
+    rb.add(h, tot, sizeof(h));
+    if (flag && flag_out) rb.add(flag_out, flag, sizeof(int32_t));
+    rb.run();
+    if (h[0] > INT32_MAX)
         fail(LAIR_EUNSUPPORTED, "offset array exceeds 2^31 entries (%lld)",
-             (long long)total);
-    return total;
+             (long long)h[0]);
+    if (max_out) *max_out = h[1];
+    return h[0];
 }
 
 int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
-                        hipStream_t s, DevArr<int64_t> &tmp) {
-    return scan_impl(CountsF{cnt}, out, n, s, tmp);
+                        hipStream_t s, DevArr<int64_t> &tmp, int64_t *max_out,
+                        const int32_t *flag, int32_t *flag_out) {
+    return scan_impl(CountsF{cnt}, out, n, s, tmp, max_out, flag, flag_out);
 }
 
 int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
                       hipStream_t s, DevArr<int64_t> &tmp) {
-    return scan_impl(FlagsF{flags, want}, out, n, s, tmp);
+    return scan_impl(FlagsF{flags, want}, out, n, s, tmp, nullptr, nullptr, nullptr);
 }
 
 // ===========================================================================
@@ -146,7 +174,7 @@ __global__ void __launch_bounds__(256)
 k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cj,
            const double *v, int32_t *stat) {
     __shared__ int se[256], sm[256];
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = xcd_block_id() * blockDim.x + threadIdx.x;
     if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(stat, 1);
     int err = 0, len = 0;
     if (i < n) {
@@ -193,8 +221,11 @@ int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
                        n, nnz, rp, cj, v, st.get());
     LAIR_LAUNCH_CHECK();
     int32_t h[2];
-    LAIR_HIP(hipMemcpyAsync(h, st.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
+    {
+        Readback rb(s);
+        rb.add(h, st.get(), sizeof(h));
+        rb.run();
+    }
     if (h[0]) {
         fail(LAIR_EINVAL, "invalid CSR matrix (error bits 0x%x: %s%s%s%s%s%s)", h[0],
              (h[0] & 1) ? "row pointers " : "", (h[0] & 2) ? "column range " : "",
@@ -214,7 +245,7 @@ template <int T>
 __global__ void k_strength(int32_t n, const int32_t *rp, const int32_t *cj,
                            const double *v, double theta, int32_t kind,
                            uint8_t *smask) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (i >= n) return;
@@ -324,7 +355,7 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
                       int32_t distance, const int32_t *flist, int32_t nf,
                       bool fill, int32_t *cnt, const int32_t *nptr,
                       int32_t *nbr, int32_t *overflow) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t c = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (c >= nc) return;
@@ -476,13 +507,17 @@ __device__ __forceinline__ void write_r_row(int32_t rbase, int s, int32_t i,
 // from the rows of A, then z += LU^{-1} r.
 template <int SM, bool MIXED>
 __global__ void __launch_bounds__(256)
-k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
-              const int32_t *nbr, const int32_t *rp, const int32_t *cj,
-              const double *v, int32_t *r_cj, double *r_v, int8_t *flags,
-              int32_t *big, int32_t *nbig, int32_t *sing, int32_t *nsing) {
+k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
+              const int32_t *clist,
+              const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
+              const int32_t *cj, const double *v, int32_t *r_cj, double *r_v,
+              int8_t *flags, int32_t *big, int32_t *nbig, int32_t *sing,
+              int32_t *nsing) {
     using FT = typename std::conditional<MIXED, float, double>::type;
-    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+    int32_t tid = (int32_t)xcd_block_id() * blockDim.x + threadIdx.x;
+    if (tid >= nlist) return;
+    if (list_count && tid >= *list_count) return;
+    int32_t c = list ? list[tid] : tid;
     int32_t i = clist[c];
     int32_t n0 = nptr[c];
     int s = nptr[c + 1] - n0;
@@ -500,13 +535,16 @@ k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
     int li[SM];
 #pragma unroll
     for (int q = 0; q < SM; ++q) li[q] = (q < s) ? nbr[n0 + q] : -1;
+    // Md holds M in double (kept for the refinement residual in MIXED);
+    // M is the copy that gets factorised (float in MIXED)
+    double Md[SM][SM];
     FT M[SM][SM];
     double f[SM];
 #pragma unroll
     for (int p = 0; p < SM; ++p) {
         f[p] = 0.0;
 #pragma unroll
-        for (int q = 0; q < SM; ++q) M[p][q] = (FT)0;
+        for (int q = 0; q < SM; ++q) Md[p][q] = 0.0;
     }
     // column p of M comes from row l_p of A: M[q][p] = a(l_p, l_q)
 #pragma unroll
@@ -518,10 +556,14 @@ k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
                 double a = v[e];
 #pragma unroll
                 for (int q = 0; q < SM; ++q)
-                    if (li[q] == col) M[q][p] = (FT)a;
+                    if (li[q] == col) Md[q][p] = a;
             }
         }
     }
+#pragma unroll
+    for (int p = 0; p < SM; ++p)
+#pragma unroll
+        for (int q = 0; q < SM; ++q) M[p][q] = (FT)Md[p][q];
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         int col = cj[e];
         double a = v[e];
@@ -534,7 +576,7 @@ k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
     for (int p = 0; p < SM; ++p) {
         double rs = 0.0;
 #pragma unroll
-        for (int q = 0; q < SM; ++q) rs += fabs((double)M[p][q]);
+        for (int q = 0; q < SM; ++q) rs += fabs(Md[p][q]);
         mnorm = fmax(mnorm, rs);
     }
     double tol = SING_TOL * mnorm;
@@ -600,23 +642,14 @@ k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
         }
     }
     if (MIXED) {
-        // residual r_p = f_p - sum_q a(l_q, l_p) z_q in double
+        // residual r = f - M z in double from the unfactorised copy
         double res[SM];
 #pragma unroll
-        for (int p = 0; p < SM; ++p) res[p] = f[p];
+        for (int p = 0; p < SM; ++p) {
+            double acc = f[p];
 #pragma unroll
-        for (int q = 0; q < SM; ++q) {
-            if (q < s) {
-                int r = li[q];
-                double zq = z[q];
-                for (int e = rp[r]; e < rp[r + 1]; ++e) {
-                    int col = cj[e];
-                    double a = v[e];
-#pragma unroll
-                    for (int p = 0; p < SM; ++p)
-                        if (li[p] == col) res[p] -= a * zq;
-                }
-            }
+            for (int q = 0; q < SM; ++q) acc -= Md[p][q] * z[q];
+            res[p] = acc;
         }
         // solve with the float factors: apply the row permutation, L, U
         FT w[SM];
@@ -664,9 +697,185 @@ k_local_small(int32_t nc, const int32_t *clist, const int32_t *nptr,
     r_v[rbase + ip] = 1.0;
 }
 
-// One wave per system (blockDim = 64).  M lives in LDS when s <= WSMAX, else
-// in a global scratch slab of smax^2 doubles per block.
-constexpr int WSMAX = 48;
+// One team of T lanes per system with s <= T (T = 8, 16, 32; a team is part
+// of one wave).  The gather writes M into the team's LDS tile (lane q scans
+// row l_q of A, so M[p][q] = a(l_q, l_p) lands in row p); lane p then holds
+// row p of M in registers.  Gaussian elimination with partial pivoting
+// keeps the rows in place: at step k the pivot is the not-yet-used row with
+// the largest |M[r][k]| (smallest r on ties), its row is broadcast by
+// shuffles and the other unused rows eliminate column k.  Back substitution
+// runs over the pivots in reverse order.  MIXED factorises a float copy and
+// refines once with the double rows kept in registers.
+template <int T, bool MIXED>
+__global__ void __launch_bounds__(T >= 32 ? 128 : 256)
+k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
+             const int32_t *clist, const int32_t *nptr, const int32_t *nbr,
+             const int32_t *rp, const int32_t *cj, const double *v, int32_t *r_cj,
+             double *r_v, int8_t *flags, int32_t *defer, int32_t *ndefer,
+             int32_t *sing, int32_t *nsing) {
+    using FT = typename std::conditional<MIXED, float, double>::type;
+    constexpr int BS = (T >= 32) ? 128 : 256;
+    constexpr int TEAMS = BS / T;
+    __shared__ double sM[TEAMS][T * T];
+    __shared__ double sf[TEAMS][T];
+    __shared__ int32_t sl[TEAMS][T];
+    const int team = threadIdx.x / T;
+    const int p = threadIdx.x % T;                  // this lane's row / column
+    int64_t gt = xcd_block_id() * BS + threadIdx.x;
+    int32_t tid = (int32_t)(gt / T);
+    if (tid >= nlist) return;
+    if (list_count && tid >= *list_count) return;
+    const int32_t c = list[tid];
+    const int32_t i = clist[c];
+    const int32_t n0 = nptr[c];
+    const int s = nptr[c + 1] - n0;
+    const int32_t rbase = n0 + c;
+    if (s > T) {
+        if (p == 0) defer[atomicAdd(ndefer, 1)] = c;
+        return;
+    }
+    if (p == 0) flags[c] = 0;
+    double *M = sM[team];
+    double *f = sf[team];
+    int32_t *ln = sl[team];
+    const int32_t lp = (p < s) ? nbr[n0 + p] : INT_MAX;
+    ln[p] = lp;
+    f[p] = 0.0;
+#pragma unroll
+    for (int j = 0; j < T; ++j) M[j * T + p] = 0.0;
+    wave_lds_sync();
+    if (p < s) {
+        for (int e = rp[lp]; e < rp[lp + 1]; ++e) {
+            int q = bsearch_i32(ln, s, cj[e]);
+            if (q >= 0) M[q * T + p] = v[e];
+        }
+    }
+    for (int e = rp[i] + p; e < rp[i + 1]; e += T) {
+        int q = bsearch_i32(ln, s, cj[e]);
+        if (q >= 0) f[q] = -v[e];
+    }
+    wave_lds_sync();
+    double Md[T];
+    FT Mr[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        Md[j] = M[p * T + j];
+        Mr[j] = (FT)Md[j];
+    }
+    const double f0 = f[p];
+    double rs = 0.0;
+#pragma unroll
+    for (int j = 0; j < T; ++j) rs += fabs(Md[j]);
+    const double tol = SING_TOL * team_max<T>(p < s ? rs : 0.0);
+    FT fr = (FT)f0;
+    FT Lr[T];
+    int piv[T];
+    bool used = (p >= s);
+    bool singular = false;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        Lr[k] = (FT)0;
+        piv[k] = 0;
+        if (k < s && !singular) {
+            double cand = used ? -1.0 : fabs((double)Mr[k]);
+            int who = p;
+            team_argmax<T>(cand, who);
+            if (cand <= tol) {
+                singular = true;
+            } else {
+                piv[k] = who;
+                FT pk = __shfl(Mr[k], who, T);
+                FT fk = __shfl(fr, who, T);
+                if (p == who) used = true;
+                FT mult = used ? (FT)0 : Mr[k] / pk;
+                Lr[k] = mult;
+#pragma unroll
+                for (int j = k + 1; j < T; ++j) {
+                    FT pj = __shfl(Mr[j], who, T);
+                    Mr[j] -= mult * pj;
+                }
+                fr -= mult * fk;
+            }
+        }
+    }
+    if (singular) {
+        if (p == 0) {
+            flags[c] = 1;
+            sing[atomicAdd(nsing, 1)] = c;
+        }
+        return;
+    }
+    // back substitution over the pivot rows, last pivot first
+    double z[T];
+#pragma unroll
+    for (int k = T - 1; k >= 0; --k) {
+        z[k] = 0.0;
+        if (k < s) {
+            FT acc = fr;
+#pragma unroll
+            for (int j = k + 1; j < T; ++j) acc -= Mr[j] * (FT)z[j];
+            FT zk = acc / Mr[k];
+            z[k] = (double)__shfl(zk, piv[k], T);
+        }
+    }
+    if (MIXED) {
+        // r_p = f_p - sum_j M[p][j] z_j in double, then the same eliminations
+        // and back substitution on r
+        double r = f0;
+#pragma unroll
+        for (int j = 0; j < T; ++j) r -= Md[j] * z[j];
+        FT rr = (FT)r;
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            if (k < s) {
+                FT rk = __shfl(rr, piv[k], T);
+                rr -= Lr[k] * rk;
+            }
+        }
+        double d[T];
+#pragma unroll
+        for (int k = T - 1; k >= 0; --k) {
+            d[k] = 0.0;
+            if (k < s) {
+                FT acc = rr;
+#pragma unroll
+                for (int j = k + 1; j < T; ++j) acc -= Mr[j] * (FT)d[j];
+                FT dk = acc / Mr[k];
+                d[k] = (double)__shfl(dk, piv[k], T);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < T; ++k) z[k] += d[k];
+    }
+    // sorted write of the R row: lane q writes entry q
+    int ip = team_sum_int<T>((p < s && lp < i) ? 1 : 0);
+    double zq = 0.0;
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+        if (k == p) zq = z[k];
+    if (p < s) {
+        int o = rbase + p + (p >= ip ? 1 : 0);
+        r_cj[o] = lp;
+        r_v[o] = zq;
+    }
+    if (p == 0) {
+        r_cj[rbase + ip] = i;
+        r_v[rbase + ip] = 1.0;
+    }
+}
+
+// One wave per system (blockDim = 64).  M lives in dynamic LDS sized for
+// the level's largest system up to WSMAX, beyond that in a global scratch
+// slab of 3 smax^2 doubles per block.  The gather walks the rows l_p one at
+// a time with all lanes on consecutive entries (coalesced), each lane
+// locating its column in the sorted N by binary search.
+constexpr int WSMAX = 64;
+
+template <class FT>
+__host__ __device__ constexpr size_t wave_lds_bytes(int cap) {
+    return (size_t)cap * cap * sizeof(FT) + (size_t)cap * (2 * sizeof(double) + sizeof(FT) +
+                                                           2 * sizeof(int32_t)) + 64;
+}
 
 template <bool MIXED>
 __global__ void __launch_bounds__(64)
@@ -674,14 +883,9 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
              const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
              const int32_t *cj, const double *v, int32_t *r_cj, double *r_v,
              int8_t *flags, int32_t *sing, int32_t *nsing, double *gscratch,
-             int32_t smax) {
+             int32_t smax, int32_t cap) {
     using FT = typename std::conditional<MIXED, float, double>::type;
-    __shared__ FT sM[WSMAX * WSMAX];
-    __shared__ double sf[WSMAX];
-    __shared__ FT sw[WSMAX];
-    __shared__ int32_t sl[WSMAX];
-    __shared__ int32_t sperm[WSMAX];
-    __shared__ double sz[WSMAX];
+    extern __shared__ double dyn[];
     int lane = threadIdx.x;
     int32_t b = blockIdx.x;
     if (b >= nlist) return;
@@ -691,19 +895,34 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
     int s = nptr[c + 1] - n0;
     int32_t rbase = n0 + c;
     const int32_t *l = nbr + n0;
-    bool in_lds = (s <= WSMAX);
-    FT *M = in_lds ? sM : (FT *)(gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3);
-    double *f = in_lds ? sf : (double *)(gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3 + (size_t)smax * smax);
-    FT *w = in_lds ? sw : (FT *)(f + smax);
-    int32_t *ln = in_lds ? sl : (int32_t *)(w + smax);
-    int32_t *perm = in_lds ? sperm : (ln + smax);
-    double *z = in_lds ? sz : (double *)(gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3 + 2 * (size_t)smax * smax);
+    bool in_lds = (s <= cap);
+    // layout: z, f (double), M (FT), w (FT), ln, perm (int)
+    double *z, *f;
+    FT *M, *w;
+    int32_t *ln, *perm;
+    if (in_lds) {
+        z = dyn;
+        f = z + cap;
+        M = (FT *)(f + cap);
+        w = M + (size_t)cap * cap;
+        ln = (int32_t *)(w + cap);
+        perm = ln + cap;
+    } else {
+        double *g = gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3;
+        z = g;
+        f = z + smax;
+        M = (FT *)(f + smax);
+        w = (FT *)(g + (size_t)smax * smax + 2 * (size_t)smax);
+        ln = (int32_t *)(g + (size_t)smax * smax * 2);
+        perm = ln + smax;
+    }
     for (int idx = lane; idx < s * s; idx += 64) M[idx] = (FT)0;
     for (int p = lane; p < s; p += 64) { f[p] = 0.0; ln[p] = l[p]; perm[p] = p; }
     __syncthreads();
-    for (int p = lane; p < s; p += 64) {
+    // column p of M is row l_p of A restricted to N: M[q][p] = a(l_p, l_q)
+    for (int p = 0; p < s; ++p) {
         int r = ln[p];
-        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        for (int e = rp[r] + lane; e < rp[r + 1]; e += 64) {
             int q = bsearch_i32(ln, s, cj[e]);
             if (q >= 0) M[q * s + p] = (FT)v[e];
         }
@@ -773,17 +992,15 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
         __syncthreads();
     }
     if (MIXED) {
-        // r = f - M z in double via the rows of A, then z += LU^{-1} r
-        __syncthreads();
-        double *res = f;      // f is not needed after this point
-        // lane p owns res[p] = f[p] - sum_q a(l_q, l_p) z_q and searches
-        // column l_p in every row l_q (no two lanes write the same entry)
+        // one refinement in double: r = f - M z from the rows of A (lane p
+        // owns r_p and searches column l_p in every row l_q), then
+        // z += LU^{-1} r with the float factors
+        double *res = f;
         for (int p = lane; p < s; p += 64) {
             double acc = res[p];
             int lp = ln[p];
             for (int q = 0; q < s; ++q) {
                 int r = ln[q];
-                // a(l_q, l_p): search column l_p in row l_q
                 int lo = rp[r], hi = rp[r + 1] - 1;
                 while (lo <= hi) {
                     int mid = (lo + hi) >> 1;
@@ -792,7 +1009,6 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
                     if (cc < lp) lo = mid + 1; else hi = mid - 1;
                 }
             }
-            w[p] = (FT)0;
             res[p] = acc;
         }
         __syncthreads();
@@ -968,16 +1184,69 @@ k_local_cost(int32_t nc, const int32_t *clist, const int32_t *nptr,
         for (int k = 0; k < 4; ++k) atomicAdd(acc + k, sh[k][0]);
 }
 
+// nlist bounds the grid; with list_count the pass reads the number of
+// listed systems on the device (no host synchronisation between passes).
+template <int SM>
+static void small_pass(bool mixed, int32_t nlist, const int32_t *list,
+                       const int32_t *list_count, const int32_t *clist,
+                       const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
+                       const int32_t *cj, const double *v, LocalSolveOut out,
+                       int32_t *defer, int32_t *ndefer, int32_t *sing, int32_t *nsing,
+                       hipStream_t s) {
+    if (nlist == 0) return;
+    if (mixed)
+        hipLaunchKernelGGL((k_local_small<SM, true>), dim3(blocks_for(nlist, 256)), dim3(256),
+                           0, s, nlist, list, list_count, clist, nptr, nbr, rp, cj, v, out.r_cj,
+                           out.r_v, out.flags, defer, ndefer, sing, nsing);
+    else
+        hipLaunchKernelGGL((k_local_small<SM, false>), dim3(blocks_for(nlist, 256)), dim3(256),
+                           0, s, nlist, list, list_count, clist, nptr, nbr, rp, cj, v, out.r_cj,
+                           out.r_v, out.flags, defer, ndefer, sing, nsing);
+    LAIR_LAUNCH_CHECK();
+}
+
+template <int T>
+static void team_pass(bool mixed, int32_t nlist, const int32_t *list,
+                      const int32_t *list_count, const int32_t *clist,
+                      const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
+                      const int32_t *cj, const double *v, LocalSolveOut out,
+                      int32_t *defer, int32_t *ndefer, int32_t *sing, int32_t *nsing,
+                      hipStream_t s) {
+    if (nlist == 0) return;
+    constexpr int BS = (T >= 32) ? 128 : 256;
+    dim3 g(blocks_for((int64_t)nlist * T, BS)), b(BS);
+    if constexpr (T <= 16) {
+        if (mixed) {
+            hipLaunchKernelGGL((k_local_team<T, true>), g, b, 0, s, nlist, list, list_count,
+                               clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer,
+                               ndefer, sing, nsing);
+            LAIR_LAUNCH_CHECK();
+            return;
+        }
+    }
+    if (mixed) fail(LAIR_EUNSUPPORTED, "mixed 32-lane local solve");
+    else
+        hipLaunchKernelGGL((k_local_team<T, false>), g, b, 0, s, nlist, list, list_count, clist,
+                           nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer, ndefer,
+                           sing, nsing);
+    LAIR_LAUNCH_CHECK();
+}
+
+// Size buckets: s <= 4 one lane per system (registers); s <= 8, 16, 32 one
+// team of 8, 16, 32 lanes per system; larger systems one wave each.  Each
+// pass defers the systems too large for it to a list for the next one.
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax,
                      LocalSolveOut out, hipStream_t s) {
     if (nc == 0) return 0;
-    DevArr<int32_t> big, sing, counters;
-    big.alloc((size_t)nc, s);
-    sing.alloc((size_t)nc, s);
-    counters.alloc(2, s);
-    LAIR_HIP(hipMemsetAsync(counters.get(), 0, 2 * sizeof(int32_t), s));
+    DevArr<int32_t> lists, counters;
+    lists.alloc((size_t)nc * 5, s);
+    int32_t *listA = lists.get(), *listB = listA + nc, *listC = listB + nc,
+            *listD = listC + nc, *sing = listD + nc;
+    counters.alloc(5, s);
+    LAIR_HIP(hipMemsetAsync(counters.get(), 0, 5 * sizeof(int32_t), s));
+    int32_t *nA = counters.get(), *nB = nA + 1, *nC = nA + 2, *nD = nA + 3, *nS = nA + 4;
     bool mixed = (precision == LAIR_MIXED);
     double cost[4] = {0, 0, 0, 0};
     if (prof_selected("local_small") || prof_selected("local_wave")) {
@@ -985,61 +1254,67 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         acc.alloc(4, s);
         LAIR_HIP(hipMemsetAsync(acc.get(), 0, 4 * sizeof(double), s));
         hipLaunchKernelGGL(k_local_cost, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
-                           nc, clist, nptr, nbr, rp, smax <= 4 ? 4 : SMALL_SM, acc.get());
+                           nc, clist, nptr, nbr, rp, 32, acc.get());
         LAIR_LAUNCH_CHECK();
-        LAIR_HIP(hipMemcpyAsync(cost, acc.get(), sizeof(cost), hipMemcpyDeviceToHost, s));
-        LAIR_HIP(hipStreamSynchronize(s));
+        Readback rb(s);
+        rb.add(cost, acc.get(), sizeof(cost));
+        rb.run();
+    }
+    int32_t h[5] = {0, 0, 0, 0, 0};
+    {
+        ProfScope ps_small("local_small", s, cost[0], cost[1]);
+        small_pass<4>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
+                      listA, nA, sing, nS, s);
+        if (smax > 4) {
+            Readback rb(s);
+            rb.add(h, counters.get(), sizeof(h));
+            rb.run();
+            int32_t na = h[0];
+            team_pass<8>(mixed, na, listA, nullptr, clist, nptr, nbr, rp, cj, v, out,
+                         listB, nB, sing, nS, s);
+            if (smax > 8)
+                team_pass<16>(mixed, na, listB, nB, clist, nptr, nbr, rp, cj, v, out,
+                              listC, nC, sing, nS, s);
+            // the mixed 32-lane variant needs too many registers; in mixed
+            // mode systems above 16 go to the one-wave kernel
+            if (smax > 16 && !mixed)
+                team_pass<32>(mixed, na, listC, nC, clist, nptr, nbr, rp, cj, v, out,
+                              listD, nD, sing, nS, s);
+        }
     }
     {
-    ProfScope ps_small("local_small", s, cost[0], cost[1]);
-    if (smax <= 4) {
-        if (mixed)
-            hipLaunchKernelGGL((k_local_small<4, true>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
-                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
-                               big.get(), counters.get(), sing.get(), counters.get() + 1);
-        else
-            hipLaunchKernelGGL((k_local_small<4, false>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
-                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
-                               big.get(), counters.get(), sing.get(), counters.get() + 1);
-    } else {
-        if (mixed)
-            hipLaunchKernelGGL((k_local_small<SMALL_SM, true>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
-                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
-                               big.get(), counters.get(), sing.get(), counters.get() + 1);
-        else
-            hipLaunchKernelGGL((k_local_small<SMALL_SM, false>), dim3(blocks_for(nc, 256)), dim3(256), 0, s,
-                               nc, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
-                               big.get(), counters.get(), sing.get(), counters.get() + 1);
+        Readback rb(s);
+        rb.add(h, counters.get(), sizeof(h));
+        rb.run();
     }
-    LAIR_LAUNCH_CHECK();
-    }
-    int32_t h[2];
-    LAIR_HIP(hipMemcpyAsync(h, counters.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
-    int32_t nbig = h[0];
+    const int32_t *wave_list = mixed ? listC : listD;
+    int32_t nbig = mixed ? h[2] : h[3];
     if (nbig > 0) {
+        int32_t cap = smax < WSMAX ? smax : WSMAX;
         DevArr<double> scratch;
-        if (smax > WSMAX) scratch.alloc((size_t)nbig * (size_t)smax * smax * 3 + 16, s);
+        if (smax > cap) scratch.alloc((size_t)nbig * (size_t)smax * smax * 3 + 16, s);
         ProfScope ps_wave("local_wave", s, cost[2], cost[3]);
+        size_t lds = mixed ? wave_lds_bytes<float>(cap) : wave_lds_bytes<double>(cap);
         if (mixed)
-            hipLaunchKernelGGL((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), 0, s,
-                               big.get(), nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
-                               out.flags, sing.get(), counters.get() + 1, scratch.get(), smax);
+            hipLaunchKernelGGL((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), lds, s,
+                               wave_list, nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
+                               out.flags, sing, nS, scratch.get(), smax, cap);
         else
-            hipLaunchKernelGGL((k_local_wave<false>), dim3((unsigned)nbig), dim3(64), 0, s,
-                               big.get(), nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
-                               out.flags, sing.get(), counters.get() + 1, scratch.get(), smax);
+            hipLaunchKernelGGL((k_local_wave<false>), dim3((unsigned)nbig), dim3(64), lds, s,
+                               wave_list, nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
+                               out.flags, sing, nS, scratch.get(), smax, cap);
         LAIR_LAUNCH_CHECK();
-        LAIR_HIP(hipMemcpyAsync(h, counters.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-        LAIR_HIP(hipStreamSynchronize(s));
+        Readback rb(s);
+        rb.add(h, counters.get(), sizeof(h));
+        rb.run();
     }
-    int32_t nsing = h[1];
+    int32_t nsing = h[4];
     if (nsing > 0) {
         DevArr<double> scratch;
         scratch.alloc((size_t)nsing * (2 * (size_t)smax * smax + 2 * (size_t)smax), s);
         ProfScope ps_ls("local_lstsq", s, 0.0);
         hipLaunchKernelGGL(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
-                           sing.get(), nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
+                           sing, nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
                            out.r_v, scratch.get(), smax);
         LAIR_LAUNCH_CHECK();
         LAIR_HIP(hipStreamSynchronize(s));
@@ -1057,7 +1332,7 @@ __global__ void k_interp_1p(int32_t n, const int32_t *rp, const int32_t *cj,
                             const double *v, const uint8_t *sm,
                             const int8_t *cf, const int32_t *cidx,
                             int32_t *pcol) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)xcd_block_id() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (cf[i] == 1) { pcol[i] = cidx[i]; return; }
     int best = -1;
@@ -1082,7 +1357,7 @@ void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
 
 __global__ void k_compact_1p(int32_t n, const int32_t *pcol, const int32_t *prp,
                              int32_t *pcj, double *pv) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)xcd_block_id() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (pcol[i] >= 0) {
         pcj[prp[i]] = pcol[i];
@@ -1102,22 +1377,29 @@ void launch_compact_one_point(int32_t n, const int32_t *pcol,
 // P_i = S_i n C, alpha = sum_{j!=i} a_ij^- / sum_{P_i} a_ik^-, beta likewise
 // for positive entries, w_ik = -(alpha or beta) a_ik / a_ii; a sign class
 // missing from P_i is lumped into the diagonal.  Columns follow A's order,
-// which is increasing in coarse index.
-__global__ void k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
-                                const double *v, const uint8_t *sm,
-                                const int8_t *cf, const int32_t *cidx,
-                                bool fill, int32_t *cnt, const int32_t *prp,
-                                int32_t *pcj, double *pv) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// which is increasing in coarse index.  One team of T lanes per row: the
+// sums are team reductions and the fill compacts in order with a ballot.
+template <int T>
+__global__ void __launch_bounds__(256)
+k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
+                const double *v, const uint8_t *sm, const int8_t *cf,
+                const int32_t *cidx, bool fill, int32_t *cnt,
+                const int32_t *prp, int32_t *pcj, double *pv) {
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)(gt / T);
+    int lane = (int)(gt % T);
     if (i >= n) return;
     if (cf[i] == 1) {
-        if (!fill) cnt[i] = 1;
-        else { pcj[prp[i]] = cidx[i]; pv[prp[i]] = 1.0; }
+        if (lane == 0) {
+            if (!fill) cnt[i] = 1;
+            else { pcj[prp[i]] = cidx[i]; pv[prp[i]] = 1.0; }
+        }
         return;
     }
+    const int lo = rp[i], hi = rp[i + 1];
     double diag = 0.0, sn = 0.0, sp = 0.0, pn = 0.0, pp = 0.0;
     int k = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    for (int p = lo + lane; p < hi; p += T) {
         int j = cj[p];
         double a = v[p];
         if (j == i) { diag = a; continue; }
@@ -1127,24 +1409,41 @@ __global__ void k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
             ++k;
         }
     }
+    diag = team_sum<T>(diag);
+    sn = team_sum<T>(sn);
+    sp = team_sum<T>(sp);
+    pn = team_sum<T>(pn);
+    pp = team_sum<T>(pp);
+    k = team_sum_int<T>(k);
     double d = diag;
     if (pn == 0.0) d += sn;
     if (pp == 0.0) d += sp;
-    if (k == 0 || d == 0.0) {
-        if (!fill) cnt[i] = 0;
+    bool empty = (k == 0 || d == 0.0);
+    if (!fill) {
+        if (lane == 0) cnt[i] = empty ? 0 : k;
         return;
     }
-    if (!fill) { cnt[i] = k; return; }
+    if (empty) return;
     double alpha = (pn != 0.0) ? sn / pn : 0.0;
     double beta = (pp != 0.0) ? sp / pp : 0.0;
     int o = prp[i];
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = cj[p];
-        if (j == i || !sm[p] || cf[j] != 1) continue;
-        double a = v[p];
-        pcj[o] = cidx[j];
-        pv[o] = -(a < 0.0 ? alpha : beta) * a / d;
-        ++o;
+    for (int p0 = lo; p0 < hi; p0 += T) {
+        int p = p0 + lane;
+        int j = -1;
+        double a = 0.0;
+        bool take = false;
+        if (p < hi) {
+            j = cj[p];
+            a = v[p];
+            take = (j != i) && sm[p] && cf[j] == 1;
+        }
+        uint64_t bits = team_bits<T>(take);
+        int before = __popcll(bits & ((1ull << lane) - 1ull));
+        if (take) {
+            pcj[o + before] = cidx[j];
+            pv[o + before] = -(a < 0.0 ? alpha : beta) * a / d;
+        }
+        o += __popcll(bits);
     }
 }
 
@@ -1152,9 +1451,20 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
                           const double *v, const uint8_t *smask,
                           const int8_t *cf, const int32_t *cidx, bool fill,
                           int32_t *cnt, const int32_t *prp, int32_t *pcj,
-                          double *pv, hipStream_t s) {
-    hipLaunchKernelGGL(k_interp_direct, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       n, rp, cj, v, smask, cf, cidx, fill, cnt, prp, pcj, pv);
+                          double *pv, double mean_len, hipStream_t s) {
+    int t = team_for_mean(mean_len);
+    if (t > 16) t = 16;
+#define LAIR_ID(TT)                                                              \
+    hipLaunchKernelGGL(k_interp_direct<TT>, dim3(blocks_for((int64_t)n * TT, 256)), \
+                       dim3(256), 0, s, n, rp, cj, v, smask, cf, cidx, fill, cnt, prp, \
+                       pcj, pv)
+    switch (t) {
+        case 2: LAIR_ID(2); break;
+        case 4: LAIR_ID(4); break;
+        case 8: LAIR_ID(8); break;
+        default: LAIR_ID(16); break;
+    }
+#undef LAIR_ID
     LAIR_LAUNCH_CHECK();
 }
 
@@ -1165,13 +1475,14 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 // k / T (LPL slots per lane).  The value of each output column is a
 // fixed-order team sum.
 // ===========================================================================
+constexpr int GEMM_PF = 4;   // entries of each merge list held in registers
+
 template <int T, int LPL, bool FILL>
-__global__ void k_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
-                         const double *ax, const int32_t *bp,
-                         const int32_t *bj, const double *bx, int32_t *cnt,
-                         const int32_t *cp, int32_t *cj, double *cx,
-                         int32_t *overflow) {
-    int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256)
+k_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
+         const int32_t *bp, const int32_t *bj, const double *bx, int32_t *cnt,
+         const int32_t *cp, int32_t *cj, double *cx, int32_t *overflow) {
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (i >= m) return;
@@ -1180,35 +1491,62 @@ __global__ void k_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
         if (lane == 0) { atomicOr(overflow, 1); if (!FILL) cnt[i] = 0; }
         return;
     }
-    int pos[LPL], end[LPL], head[LPL];
+    // Each slot holds the next GEMM_PF entries of its list (columns and
+    // scaled values) as a shift register: the merge consumes from registers
+    // and reloads GEMM_PF independent entries when the window is empty.
+    int pos[LPL], end[LPL];
+    int hb[LPL][GEMM_PF];
+    double vb[LPL][GEMM_PF];
     double mul[LPL];
 #pragma unroll
     for (int s = 0; s < LPL; ++s) {
         int k = lane + s * T;
+        pos[s] = 0;
+        end[s] = 0;
+        mul[s] = 0.0;
         if (k < ka) {
             int r = aj[lo + k];
             pos[s] = bp[r];
             end[s] = bp[r + 1];
-            mul[s] = FILL ? ax[lo + k] : 0.0;
-        } else {
-            pos[s] = 0; end[s] = 0; mul[s] = 0.0;
+            if (FILL) mul[s] = ax[lo + k];
         }
-        head[s] = (pos[s] < end[s]) ? bj[pos[s]] : INT_MAX;
+#pragma unroll
+        for (int d = 0; d < GEMM_PF; ++d) {
+            int idx = pos[s] + d;
+            bool ok = idx < end[s];
+            hb[s][d] = ok ? bj[idx] : INT_MAX;
+            if (FILL) vb[s][d] = ok ? mul[s] * bx[idx] : 0.0;
+        }
+        pos[s] += GEMM_PF;
     }
     int o = FILL ? cp[i] : 0;
     for (;;) {
         int h = INT_MAX;
 #pragma unroll
-        for (int s = 0; s < LPL; ++s) h = min(h, head[s]);
+        for (int s = 0; s < LPL; ++s) h = min(h, hb[s][0]);
         int mn = team_min<T>(h);
         if (mn == INT_MAX) break;
         double acc = 0.0;
 #pragma unroll
         for (int s = 0; s < LPL; ++s) {
-            if (head[s] == mn) {
-                if (FILL) acc += mul[s] * bx[pos[s]];
-                ++pos[s];
-                head[s] = (pos[s] < end[s]) ? bj[pos[s]] : INT_MAX;
+            if (hb[s][0] == mn) {
+                if (FILL) acc += vb[s][0];
+#pragma unroll
+                for (int d = 0; d + 1 < GEMM_PF; ++d) {
+                    hb[s][d] = hb[s][d + 1];
+                    if (FILL) vb[s][d] = vb[s][d + 1];
+                }
+                hb[s][GEMM_PF - 1] = INT_MAX;
+                if (hb[s][0] == INT_MAX && pos[s] < end[s]) {
+#pragma unroll
+                    for (int d = 0; d < GEMM_PF; ++d) {
+                        int idx = pos[s] + d;
+                        bool ok = idx < end[s];
+                        hb[s][d] = ok ? bj[idx] : INT_MAX;
+                        if (FILL) vb[s][d] = ok ? mul[s] * bx[idx] : 0.0;
+                    }
+                    pos[s] += GEMM_PF;
+                }
             }
         }
         if (FILL) {
@@ -1450,11 +1788,137 @@ k_dense_lu(int32_t n, double *a, int32_t *piv, int32_t *info) {
     if (t == 0) *info = 0;
 }
 
+// Small coarsest grids (n <= 128): the whole factorisation in LDS, pivot
+// search by the first wave with shuffles (largest |a|, smallest row on ties).
+__global__ void __launch_bounds__(256)
+k_dense_lu_lds(int32_t n, double *lu, int32_t *piv, int32_t *info) {
+    extern __shared__ double a[];
+    __shared__ int s_piv;
+    __shared__ double s_val;
+    int t = threadIdx.x, nt = blockDim.x;
+    for (int idx = t; idx < n * n; idx += nt) a[idx] = lu[idx];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (t < 64) {
+            double best = -1.0;
+            int bi = INT_MAX;
+            for (int r = k + t; r < n; r += 64) {
+                double x = fabs(a[r * n + k]);
+                if (x > best) { best = x; bi = r; }
+            }
+            team_argmax<64>(best, bi);
+            if (t == 0) { s_piv = bi; s_val = best; }
+        }
+        __syncthreads();
+        int pr = s_piv;
+        if (s_val == 0.0) {
+            if (t == 0) *info = k + 1;
+            return;
+        }
+        if (t == 0) piv[k] = pr;
+        if (pr != k)
+            for (int q = t; q < n; q += nt) {
+                double x = a[k * n + q];
+                a[k * n + q] = a[pr * n + q];
+                a[pr * n + q] = x;
+            }
+        __syncthreads();
+        double inv = 1.0 / a[k * n + k];
+        for (int r = k + 1 + t; r < n; r += nt) a[r * n + k] *= inv;
+        __syncthreads();
+        int w = n - k - 1;
+        for (int idx = t; idx < w * w; idx += nt) {
+            int r = k + 1 + idx / w;
+            int q = k + 1 + idx % w;
+            a[r * n + q] -= a[r * n + k] * a[k * n + q];
+        }
+        __syncthreads();
+    }
+    for (int idx = t; idx < n * n; idx += nt) lu[idx] = a[idx];
+    if (t == 0) *info = 0;
+}
+
+static size_t max_lds_per_block() {
+    static size_t cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            v > 0)
+            cached = (size_t)v;
+        else
+            cached = 65536;
+    }
+    return cached;
+}
+
 void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,
                      hipStream_t s) {
+    if (n <= 128 && (size_t)n * n * sizeof(double) + 64 <= max_lds_per_block()) {
+        hipLaunchKernelGGL(k_dense_lu_lds, dim3(1), dim3(256), (size_t)n * n * sizeof(double),
+                           s, n, lu, piv, info);
+        LAIR_LAUNCH_CHECK();
+        return;
+    }
     int bs = 64;
     while (bs < 1024 && bs < n) bs <<= 1;
     hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(bs), 0, s, n, lu, piv, info);
+    LAIR_LAUNCH_CHECK();
+}
+
+// Explicit inverse from P K = L U: block b solves for identity columns
+// 8b .. 8b+7 (one wave per block, the columns kept in LDS).
+constexpr int INV_COLS = 8;
+
+__global__ void __launch_bounds__(64)
+k_dense_inverse(int32_t n, const double *lu, const int32_t *piv, double *inv) {
+    extern __shared__ double xs[];
+    const int c0 = blockIdx.x * INV_COLS;
+    const int t = threadIdx.x;
+    for (int idx = t; idx < n * INV_COLS; idx += 64) {
+        int r = idx / INV_COLS, q = idx % INV_COLS;
+        xs[idx] = (r == c0 + q) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (t < INV_COLS)
+        for (int k = 0; k < n; ++k) {
+            int p = piv[k];
+            if (p != k) {
+                double x = xs[k * INV_COLS + t];
+                xs[k * INV_COLS + t] = xs[p * INV_COLS + t];
+                xs[p * INV_COLS + t] = x;
+            }
+        }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        int w = (n - k - 1) * INV_COLS;
+        for (int idx = t; idx < w; idx += 64) {
+            int r = k + 1 + idx / INV_COLS, q = idx % INV_COLS;
+            xs[r * INV_COLS + q] -= lu[(size_t)r * n + k] * xs[k * INV_COLS + q];
+        }
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        if (t < INV_COLS) xs[k * INV_COLS + t] /= lu[(size_t)k * n + k];
+        __syncthreads();
+        int w = k * INV_COLS;
+        for (int idx = t; idx < w; idx += 64) {
+            int r = idx / INV_COLS, q = idx % INV_COLS;
+            xs[r * INV_COLS + q] -= lu[(size_t)r * n + k] * xs[k * INV_COLS + q];
+        }
+        __syncthreads();
+    }
+    for (int idx = t; idx < n * INV_COLS; idx += 64) {
+        int r = idx / INV_COLS, q = idx % INV_COLS;
+        if (c0 + q < n) inv[(size_t)r * n + c0 + q] = xs[idx];
+    }
+}
+
+void launch_dense_inverse(int32_t n, const double *lu, const int32_t *piv,
+                          double *inv, hipStream_t s) {
+    int nb = (n + INV_COLS - 1) / INV_COLS;
+    hipLaunchKernelGGL(k_dense_inverse, dim3(nb), dim3(64),
+                       (size_t)n * INV_COLS * sizeof(double), s, n, lu, piv, inv);
     LAIR_LAUNCH_CHECK();
 }
 

@@ -69,6 +69,7 @@ struct lair_hierarchy {
     lair::DevArr<double> lu;
     lair::DevArr<int32_t> piv;
     lair::DevArr<double> kinv;               // explicit inverse when nL <= 512
+    lair::DevArr<int8_t> cf_dev;             // caller's CF splittings (all levels)
     lair::DevArr<double> dinv;               // block scaling (block_size > 0)
     int32_t nrhs_cap = 0;
     lair::DevArr<double> bscaled, r0, partial, norms;
@@ -109,12 +110,6 @@ static CsrView<VT> view(const DevCSR &M, int32_t team) {
 
 static const int32_t NPARTIAL = 1024;
 
-// max over an int32 device array (small helper kernel)
-__global__ void k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax(out, a[i]);
-}
-
 __global__ void k_nonneg_flag(int32_t n, const int32_t *pc, int32_t *hs) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) hs[i] = pc[i] >= 0 ? 1 : 0;
@@ -123,11 +118,6 @@ __global__ void k_nonneg_flag(int32_t n, const int32_t *pc, int32_t *hs) {
 __global__ void k_add(double *x, const double *e, int64_t m) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) x[i] += e[i];
-}
-
-__global__ void k_set_diag(int32_t n, double *a) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[(size_t)i * n + i] = 1.0;
 }
 
 __global__ void k_r_rowptr(int32_t nc, const int32_t *nptr, int32_t *rrp) {
@@ -147,22 +137,9 @@ __global__ void k_block_diag_csr(int32_t nblk, int32_t k, const double *dinv,
     v[g] = dinv[(row / k) * k * k + (row % k) * k + c];
 }
 
-static int32_t device_max(const int32_t *a, int64_t n, hipStream_t s) {
-    if (n == 0) return 0;
-    DevArr<int32_t> m;
-    m.alloc(1, s);
-    LAIR_HIP(hipMemsetAsync(m.get(), 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_max_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, n, m.get());
-    LAIR_LAUNCH_CHECK();
-    int32_t h = 0;
-    LAIR_HIP(hipMemcpyAsync(&h, m.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
-    return h;
-}
-
-// C = A B with the symbolic pattern.
-static void spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
-                   DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
+// C = A B with the symbolic pattern.  Returns the longest row of C.
+static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
+                      DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
     C.nrows = A.nrows;
     C.ncols = B.ncols;
     DevArr<int32_t> cnt, over;
@@ -178,10 +155,9 @@ static void spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
                       over.get(), s);
     }
     C.rp.alloc((size_t)A.nrows + 1, s);
-    C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), A.nrows, s, tmp);
+    int64_t mx = 0;
     int32_t ov = 0;
-    LAIR_HIP(hipMemcpyAsync(&ov, over.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
+    C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), A.nrows, s, tmp, &mx, over.get(), &ov);
     if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
     C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
@@ -193,6 +169,7 @@ static void spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
                       B.v.get(), max_row_a, true, nullptr, C.rp.get(), C.cj.get(), C.v.get(),
                       over.get(), s);
     }
+    return (int32_t)mx;
 }
 
 static void transpose(const DevCSR &M, DevCSR &T, hipStream_t s,
@@ -254,10 +231,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         if (hi - lo != n)
             fail(LAIR_EINVAL, "CF splitting of level %d has %lld entries, level size is %d",
                  lvl, (long long)(hi - lo), n);
-        for (int64_t k = lo; k < hi; ++k)
-            if (cfl->cf[k] != 0 && cfl->cf[k] != 1)
-                fail(LAIR_EINVAL, "CF splitting of level %d holds a value other than 0/1", lvl);
-        LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), cfl->cf + lo, (size_t)n, hipMemcpyHostToDevice, s));
+        // the splittings were uploaded (and checked) at the start of setup
+        LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), h->cf_dev.get() + lo, (size_t)n,
+                                hipMemcpyDeviceToDevice, s));
     } else {
         // library's own classical first pass on a host copy of the pattern
         const uint8_t *sm_dev = Lv.smask.get();
@@ -303,8 +279,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         launch_cf_lists(n, Lv.cf.get(), scan.get(), A.rp.get(), Lv.cidx.get(), Lv.clist.get(),
                         Lv.flist.get(), acc.get(), s);
         unsigned long long hacc[2];
-        LAIR_HIP(hipMemcpyAsync(hacc, acc.get(), sizeof(hacc), hipMemcpyDeviceToHost, s));
-        LAIR_HIP(hipStreamSynchronize(s));
+        Readback rb(s);
+        rb.add(hacc, acc.get(), sizeof(hacc));
+        rb.run();
         Lv.nnzF = (int64_t)hacc[0];
         Lv.nnzC = (int64_t)hacc[1];
     }
@@ -318,28 +295,18 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, cnt.get(),
                           nullptr, nullptr, over.get(), Lv.max_row, s);
     Lv.nptr.alloc((size_t)Lv.nc + 1, s);
-    int64_t nn = scan_counts_i32(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp);
+    int64_t smax64 = 0;
     int32_t ov = 0;
-    LAIR_HIP(hipMemcpyAsync(&ov, over.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
+    int64_t nn = scan_counts_i32(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp, &smax64, over.get(),
+                                 &ov);
     if (ov) fail(LAIR_EUNSUPPORTED, "level %d: a distance-2 neighbourhood merges more than 256 rows", lvl);
     Lv.nbr.alloc((size_t)std::max<int64_t>(nn, 1), s);
     launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, nullptr,
                           Lv.nptr.get(), Lv.nbr.get(), over.get(), Lv.max_row, s);
-    // sizes of the local systems
-    {
-        // cnt still holds the per-C-point sizes
-        int32_t smax = device_max(cnt.get(), Lv.nc, s);
-        Lv.st.s_max = smax;
-        std::vector<int32_t> hn((size_t)Lv.nc + 1);
-        LAIR_HIP(hipMemcpyAsync(hn.data(), Lv.nptr.get(), sizeof(int32_t) * (Lv.nc + 1), hipMemcpyDeviceToHost, s));
-        LAIR_HIP(hipStreamSynchronize(s));
-        int32_t smin = INT_MAX;
-        for (int32_t c = 0; c < Lv.nc; ++c) smin = std::min(smin, hn[c + 1] - hn[c]);
-        Lv.st.s_min = Lv.nc ? smin : 0;
-        Lv.st.s_mean = Lv.nc ? (double)nn / Lv.nc : 0.0;
-    }
+    Lv.st.s_max = (int32_t)smax64;
+    Lv.st.s_mean = Lv.nc ? (double)nn / Lv.nc : 0.0;
+    Lv.st.s_min = -1;   // filled on demand by lair_level_stats_get
 
     // R = [Z I]
     DevCSR &R = Lv.R;
@@ -389,7 +356,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
             ProfScope ps("interp", s, 6.0 * A.nnz + 9.0 * n);
             launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
                                  Lv.cf.get(), Lv.cidx.get(), false, pc.get(), nullptr, nullptr,
-                                 nullptr, s);
+                                 nullptr, mean, s);
         }
         P.nnz = scan_counts_i32(pc.get(), P.rp.get(), n, s, tmp);
         P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
@@ -398,7 +365,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
             ProfScope ps("interp", s, 14.0 * A.nnz + 13.0 * n + 12.0 * P.nnz);
             launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
                                  Lv.cf.get(), Lv.cidx.get(), true, nullptr, P.rp.get(),
-                                 P.cj.get(), P.v.get(), s);
+                                 P.cj.get(), P.v.get(), mean, s);
         }
     }
 }
@@ -421,20 +388,16 @@ static void finish_coarsest(lair_hierarchy *h) {
     launch_dense_from_csr(n, Lc.A.rp.get(), Lc.A.cj.get(), Lc.A.v.get(), h->lu.get(), s);
     launch_dense_lu(n, h->lu.get(), h->piv.get(), info.get(), s);
     int32_t hinfo = 0;
-    LAIR_HIP(hipMemcpyAsync(&hinfo, info.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
+    {
+        Readback rb(s);
+        rb.add(&hinfo, info.get(), sizeof(int32_t));
+        rb.run();
+    }
     if (hinfo != 0) fail(LAIR_ESINGULAR, "coarsest matrix (n = %d) is singular at pivot %d", n, hinfo);
     if (n <= MAX_INVERSE) {
-        // K^{-1} from the LU factors applied to the identity (columns
-        // interleaved, so row i of the result is row i of K^{-1})
-        DevArr<double> eye;
-        eye.alloc((size_t)n * n, s);
-        op_fill<double>(eye.get(), 0.0, (int64_t)n * n, s);
-        hipLaunchKernelGGL(k_set_diag, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, eye.get());
-        LAIR_LAUNCH_CHECK();
+        // K^{-1} from the LU factors, eight columns of the identity per block
         h->kinv.alloc((size_t)n * n, s);
-        op_dense_solve<double>(n, h->lu.get(), h->piv.get(), eye.get(), h->kinv.get(), n,
-                               false, s);
+        launch_dense_inverse(n, h->lu.get(), h->piv.get(), h->kinv.get(), s);
     }
 }
 
@@ -496,6 +459,25 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
 
     const int32_t n = (int32_t)Ain->n;
     const int64_t nnz = Ain->nnz;
+    if (cfl && cfl->nlevels > 0) {
+        // check the caller's splittings and upload them in one pinned copy
+        int64_t total = cfl->offs[cfl->nlevels];
+        if (cfl->offs[0] != 0 || total < 0) fail(LAIR_EINVAL, "bad CF level offsets");
+        for (int32_t l = 0; l < cfl->nlevels; ++l)
+            if (cfl->offs[l + 1] < cfl->offs[l]) fail(LAIR_EINVAL, "bad CF level offsets");
+        uint8_t bad = 0;
+        const uint8_t *cfb = (const uint8_t *)cfl->cf;
+        for (int64_t k = 0; k < total; ++k) bad |= cfb[k] & 0xFE;
+        if (bad) fail(LAIR_EINVAL, "a CF splitting holds a value other than 0/1");
+        if (total > 0) {
+            int8_t *stage = (int8_t *)pinned_staging((size_t)total);
+            memcpy(stage, cfl->cf, (size_t)total);
+            h->cf_dev.alloc((size_t)total, s);
+            LAIR_HIP(hipMemcpyAsync(h->cf_dev.get(), stage, (size_t)total,
+                                    hipMemcpyHostToDevice, s));
+            LAIR_HIP(hipStreamSynchronize(s));   // the staging buffer is reused
+        }
+    }
     std::unique_ptr<Level> L0(new Level());
     L0->n = n;
     DevCSR &A = L0->A;
@@ -520,8 +502,11 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         launch_block_inverse(nblk, k, A.rp.get(), A.cj.get(), A.v.get(), h->dinv.get(),
                              bad.get(), s);
         int32_t hb = 0;
-        LAIR_HIP(hipMemcpyAsync(&hb, bad.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        LAIR_HIP(hipStreamSynchronize(s));
+        {
+            Readback rb(s);
+            rb.add(&hb, bad.get(), sizeof(int32_t));
+            rb.run();
+        }
         if (hb) fail(LAIR_ESINGULAR, "a %dx%d diagonal block is singular", k, k);
         DevCSR D;
         D.nrows = D.ncols = n;
@@ -533,9 +518,8 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
                            nblk, k, h->dinv.get(), D.rp.get(), D.cj.get(), D.v.get());
         LAIR_LAUNCH_CHECK();
         DevCSR As;
-        spgemm(D, k, A, As, s, tmp);
+        L0->max_row = spgemm(D, k, A, As, s, tmp);
         L0->A = std::move(As);
-        L0->max_row = validate_csr(n, L0->A.nnz, L0->A.rp.get(), L0->A.cj.get(), L0->A.v.get(), s);
     }
     h->L.push_back(std::move(L0));
 
@@ -551,9 +535,8 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         std::unique_ptr<Level> nx(new Level());
         nx->n = Lv.nc;
         int32_t rmax = Lv.st.s_max + 1;
-        spgemm(Lv.R, rmax, AP, nx->A, s, tmp);
-        nx->max_row = validate_csr(nx->n, nx->A.nnz, nx->A.rp.get(), nx->A.cj.get(),
-                                   nx->A.v.get(), s);
+        // rows of K are sorted and unique by construction of the product
+        nx->max_row = spgemm(Lv.R, rmax, AP, nx->A, s, tmp);
         h->L.push_back(std::move(nx));
     }
     finish_coarsest(h.get());
@@ -781,9 +764,11 @@ static void norms_host(lair_hierarchy *h, const double *r, int32_t nrhs,
         op_sumsq(r, h->L[0]->n, nrhs, h->partial.get(), NPARTIAL, h->norms.get(), s);
     }
     out.resize((size_t)nrhs);
-    LAIR_HIP(hipMemcpyAsync(out.data(), h->norms.get(), sizeof(double) * nrhs,
-                            hipMemcpyDeviceToHost, s));
-    LAIR_HIP(hipStreamSynchronize(s));
+    {
+        Readback rb(s);
+        rb.add(out.data(), h->norms.get(), sizeof(double) * nrhs);
+        rb.run();
+    }
     for (auto &v : out) v = std::sqrt(v);
 }
 
@@ -1000,6 +985,18 @@ lair_status lair_level_stats_get(const lair_hierarchy *h, int32_t level,
         if (!h || !st) fail(LAIR_EINVAL, "NULL argument");
         if (level < 0 || level >= (int32_t)h->L.size()) fail(LAIR_EINVAL, "bad level %d", level);
         *st = h->L[level]->st;
+        const Level &Lv = *h->L[level];
+        if (Lv.nptr.get() && Lv.nc > 0) {
+            std::vector<int32_t> hn((size_t)Lv.nc + 1);
+            LAIR_HIP(hipStreamSynchronize(h->stream));
+            LAIR_HIP(hipMemcpy(hn.data(), Lv.nptr.get(), sizeof(int32_t) * (Lv.nc + 1),
+                               hipMemcpyDeviceToHost));
+            int32_t smin = INT_MAX;
+            for (int32_t c = 0; c < Lv.nc; ++c) smin = std::min(smin, hn[c + 1] - hn[c]);
+            st->s_min = smin;
+        } else {
+            st->s_min = 0;
+        }
         return LAIR_OK;
     });
 }

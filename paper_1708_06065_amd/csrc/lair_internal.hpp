@@ -86,6 +86,25 @@ struct DevArr {
     size_t bytes() const { return n * sizeof(T); }
 };
 
+// ---------------------------------------------------------------------------
+// Small device-to-host readbacks through a pinned host buffer (per host
+// thread): reads never go through pageable memory.  Every readback waits
+// for the stream.
+// ---------------------------------------------------------------------------
+struct Readback {
+    explicit Readback(hipStream_t s) : stream(s) {}
+    // queue a copy of `bytes` from device pointer `src` into host `dst`
+    void add(void *dst, const void *src, size_t bytes);
+    // issue the copies, wait for the stream, deliver to the destinations
+    void run();
+    hipStream_t stream;
+    std::vector<std::pair<void *, size_t>> dst;   // destination, offset
+    std::vector<std::pair<const void *, size_t>> src;
+    size_t used = 0;
+};
+// pinned host staging buffer of at least `bytes` (reused; per host thread)
+void *pinned_staging(size_t bytes);
+
 // A square or rectangular CSR matrix on the device (int32 indices).
 struct DevCSR {
     int32_t nrows = 0, ncols = 0;
@@ -131,8 +150,12 @@ inline int team_for_mean(double mean_len) {
 // Setup kernels (k_setup.hip)
 // ---------------------------------------------------------------------------
 // exclusive scan of f(i) for i < n into out[0..n], returns out[n]
+// optionally also returns the largest count and copies a device flag back
+// in the same synchronisation
 int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
-                        hipStream_t s, DevArr<int64_t> &tmp);
+                        hipStream_t s, DevArr<int64_t> &tmp,
+                        int64_t *max_out = nullptr, const int32_t *flag = nullptr,
+                        int32_t *flag_out = nullptr);
 int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
                       hipStream_t s, DevArr<int64_t> &tmp);
 
@@ -174,7 +197,7 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
                           const double *v, const uint8_t *smask,
                           const int8_t *cf, const int32_t *cidx, bool fill,
                           int32_t *cnt, const int32_t *prp, int32_t *pcj,
-                          double *pv, hipStream_t s);
+                          double *pv, double mean_len, hipStream_t s);
 // C = A B (symbolic pattern).  Count pass when fill is false.
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
                    const double *ax, const int32_t *bp, const int32_t *bj,
@@ -194,6 +217,9 @@ void launch_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj,
                            const double *v, double *dense, hipStream_t s);
 void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,
                      hipStream_t s);
+// inv = K^{-1} from the factors of launch_dense_lu (n <= 4096)
+void launch_dense_inverse(int32_t n, const double *lu, const int32_t *piv,
+                          double *inv, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Cycle kernels (k_cycle.hip)

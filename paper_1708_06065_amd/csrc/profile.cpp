@@ -87,6 +87,52 @@ ProfScope::~ProfScope() {
     if (slot < (int)p.recs.size()) (void)hipEventRecord(p.recs[slot].e1, stream);
 }
 
+namespace {
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+}  // namespace
+
+void *pinned_staging(size_t bytes) {
+    static thread_local PinnedBuf buf;
+    if (bytes > buf.n) {
+        if (buf.p) (void)hipHostFree(buf.p);
+        buf.p = nullptr;
+        buf.n = 0;
+        size_t want = bytes < 65536 ? 65536 : bytes;
+        if (hipHostMalloc(&buf.p, want, hipHostMallocDefault) != hipSuccess) {
+            buf.p = nullptr;
+            fail(LAIR_ENOMEM, "pinned host allocation of %zu bytes failed", want);
+        }
+        buf.n = want;
+    }
+    return buf.p;
+}
+
+void Readback::add(void *d, const void *sp, size_t bytes) {
+    size_t off = (used + 15) & ~(size_t)15;
+    dst.push_back({d, off});
+    src.push_back({sp, bytes});
+    used = off + bytes;
+}
+
+void Readback::run() {
+    char *stage = (char *)pinned_staging(used);
+    for (size_t k = 0; k < src.size(); ++k)
+        LAIR_HIP(hipMemcpyAsync(stage + dst[k].second, src[k].first, src[k].second,
+                                hipMemcpyDeviceToHost, stream));
+    LAIR_HIP(hipStreamSynchronize(stream));
+    for (size_t k = 0; k < src.size(); ++k)
+        memcpy(dst[k].first, stage + dst[k].second, src[k].second);
+    dst.clear();
+    src.clear();
+    used = 0;
+}
+
 }  // namespace lair
 
 using namespace lair;
