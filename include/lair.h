@@ -107,8 +107,16 @@ typedef struct lair_options {
     double stall;            /* stop when n_c > stall * n (0.9)             */
     int32_t block_size;      /* 0, or k: solve D_B^{-1} A x = D_B^{-1} b with
                                 D_B the k x k diagonal blocks (Sec. 4.2.1) */
-    int32_t reserved;
+    int32_t flags;           /* 0, or LAIR_FLAG_NO_GRAPH                     */
 } lair_options;
+
+/* Solves capture one iteration (cycle, residual, norms) in a HIP graph the
+ * first time a (b, x, nrhs) combination is seen, on a private stream of
+ * default priority, and replay it on the caller's stream afterwards; the
+ * results are bitwise those of eager launches.  This flag launches every
+ * kernel eagerly instead.  Iterations are also eager while the profiler
+ * times a cycle category. */
+#define LAIR_FLAG_NO_GRAPH 1
 
 typedef struct lair_info {
     int32_t iters;           /* V-cycles done                               */
@@ -134,7 +142,8 @@ typedef struct lair_level_stats {
 typedef struct lair_hierarchy lair_hierarchy;   /* opaque */
 
 /* Fill the defaults: theta = theta_c = 0.25, ABS, distance 1, one-point P,
- * FP64, omega 1, 25 levels, max_coarse 128, stall 0.9, no block scaling. */
+ * FP64, omega 1, 25 levels, max_coarse 128, stall 0.9, no block scaling,
+ * graph capture on. */
 void lair_default_options(lair_strength *s, lair_options *o);
 
 /* Build a hierarchy for A (copied).  cf may be NULL.  On success *out owns
@@ -171,6 +180,45 @@ lair_status lair_solve_transpose(lair_hierarchy *h, const double *g,
 /* One transposed cycle (the adjoint of lair_cycle). */
 lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g,
                                  double *lam, int32_t nrhs, void *stream);
+
+/* Batch of independent systems (each one the problem of Sec. 2 on its own).
+ * lair_setup_batch builds one hierarchy for the block-diagonal union of the
+ * nsys matrices A[0..nsys): system q owns union rows [o_q, o_q + n_q) with
+ * o_q = n_0 + ... + n_{q-1}.  Every phase of the setup and of the cycle is
+ * one launch over all systems.  Each system follows the single-system rules
+ * on its own: it stops coarsening when its size is <= max_coarse, at
+ * max_levels, or when its splitting has no C-point or more than stall * n_q
+ * of them; a stopped system passes through the remaining levels unchanged
+ * (all its points are C-points, R and P are the identity on them and they
+ * are not relaxed) and is solved directly at the union's coarsest level,
+ * one dense LU per system (at most 4096 rows each).  The CF splittings are
+ * the library's own (cf must be NULL or describe the union's levels).
+ * The A[q] must all be host arrays or all device arrays (on_device); each
+ * is copied.  Errors: as lair_setup, and EINVAL for nsys < 1, mixed
+ * locations, a union of 2^31 rows or entries or more, or a member whose
+ * rowptr does not run from 0 to nnz or whose columns leave its rows.
+ * Only one right-hand side per system (nrhs = 1) is supported on a batch. */
+lair_status lair_setup_batch(int32_t nsys, const lair_csr *A, const lair_cf_levels *cf,
+                             const lair_strength *s, const lair_options *o, void *stream,
+                             lair_hierarchy **out);
+
+/* Stationary iteration x += B (b - A x) on the union (b, x: device vectors
+ * of the union's length, system q at rows [o_q, o_q + n_q)), each system
+ * stopping on its own when ||b_q - A_q x_q||_2 <= rtol ||b_q||_2; the
+ * residuals of stopped systems are zeroed so that their corrections vanish.
+ * iters[q] and relres[q] (host arrays of nsys entries, may be NULL) return
+ * the cycles spent on system q and its final relative residual; info (may
+ * be NULL) gets the maximum of both.  ENOCONV when a system has not
+ * converged within maxit cycles.  EINVAL for a hierarchy not built by
+ * lair_setup_batch. */
+lair_status lair_solve_batch(lair_hierarchy *h, const double *b, double *x, double rtol,
+                             int32_t maxit, int32_t *iters, double *relres, lair_info *info,
+                             void *stream);
+
+/* Number of systems of a hierarchy (1 for lair_setup), and for a batch the
+ * number of levels each system has on its own (levels: nsys entries). */
+int32_t lair_num_systems(const lair_hierarchy *h);
+lair_status lair_system_levels(const lair_hierarchy *h, int32_t *levels);
 
 /* Number of levels and per-level statistics. */
 int32_t lair_num_levels(const lair_hierarchy *h);

@@ -16,8 +16,8 @@ import numpy as np
 from . import _lib as L
 from ._lib import LairError  # noqa: F401
 
-__all__ = ["setup", "Hierarchy", "LairError", "load_library", "profile_begin",
-           "profile_end"]
+__all__ = ["setup", "setup_batch", "Hierarchy", "LairError", "load_library",
+           "profile_begin", "profile_end"]
 
 _KINDS = {"abs": L.SOC_ABS, "neg": L.SOC_NEG}
 _INTERP = {"one_point": L.P_ONE_POINT, "direct": L.P_DIRECT}
@@ -149,6 +149,41 @@ class Hierarchy:
         d["converged"] = st == L.LAIR_OK
         return x, d
 
+    @property
+    def nsys(self):
+        return L.load().lair_num_systems(self.handle)
+
+    def system_levels(self):
+        """Levels of each system of a batch on its own (int32 array)."""
+        out = np.zeros(self.nsys, dtype=np.int32)
+        L.check(L.load().lair_system_levels(self.handle, out.ctypes.data_as(ctypes.c_void_p)),
+                "lair_system_levels")
+        return out
+
+    def solve_batch(self, b, x=None, rtol=1e-10, maxit=200, stream=None,
+                    raise_on_noconv=False):
+        """Per-system stationary iteration on a batch's union vectors.
+        Returns (x, info dict with per-system 'iters' and 'relres' arrays)."""
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        ns = self.nsys
+        its = np.zeros(ns, dtype=np.int32)
+        rel = np.zeros(ns, dtype=np.float64)
+        info = L.Info()
+        st = L.load().lair_solve_batch(self.handle, _dev_ptr(b, torch.float64, "b"),
+                                       _dev_ptr(x, torch.float64, "x"), float(rtol), int(maxit),
+                                       its.ctypes.data_as(ctypes.c_void_p),
+                                       rel.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(info), _stream_ptr(stream))
+        if st != L.LAIR_OK and (st != L.LAIR_ENOCONV or raise_on_noconv):
+            L.check(st, "lair_solve_batch")
+        d = info.as_dict()
+        d["converged"] = st == L.LAIR_OK
+        d["sys_iters"] = its
+        d["sys_relres"] = rel
+        return x, d
+
     def solve_transpose(self, g, lam=None, rtol=1e-10, maxit=200, stream=None,
                         raise_on_noconv=False):
         torch = _torch()
@@ -188,19 +223,9 @@ def profile_end():
     return json.loads(buf.value.decode() or "{}")
 
 
-def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
-          kind="abs", distance=1, interp="one_point", precision="fp64",
-          omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
-          stream=None):
-    """Build a hierarchy for the CSR matrix (rowptr, col, val).
-
-    The arrays may be NumPy arrays (host) or contiguous CUDA tensors
-    (int32, int32, float64).  cf_levels is an optional list of per-level
-    int8 CF splittings (1 = C) in host memory.
-    """
+def _csr(rowptr, col, val, keep):
+    """lair_csr for NumPy (host) or CUDA-tensor (device) arrays."""
     torch = _torch()
-    lib = L.load()
-    keep = []
     on_dev = isinstance(val, torch.Tensor) and val.is_cuda
     if on_dev:
         rp = _dev_ptr(rowptr, torch.int32, "rowptr")
@@ -216,11 +241,64 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
         rp, cj, vx = (x.ctypes.data_as(ctypes.c_void_p) for x in (a, c, v))
         n = a.shape[0] - 1
         nnz = c.shape[0]
-    A = L.Csr(n, nnz, rp, cj, vx, 1 if on_dev else 0)
+    return L.Csr(n, nnz, rp, cj, vx, 1 if on_dev else 0), n
+
+
+def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels,
+            max_coarse, stall, block_size, graphs):
     s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
                    _KINDS[kind], _DIST[distance])
     o = L.Options(_INTERP[interp], _PREC[precision], float(omega), int(max_levels),
-                  int(max_coarse), float(stall), int(block_size), 0)
+                  int(max_coarse), float(stall), int(block_size),
+                  0 if graphs else L.FLAG_NO_GRAPH)
+    opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
+                interp=interp, precision=precision, omega=omega,
+                max_levels=max_levels, max_coarse=max_coarse, stall=stall,
+                block_size=block_size, graphs=graphs)
+    return s, o, opts
+
+
+def setup_batch(systems, theta=0.25, theta_c=None, kind="abs", distance=1,
+                interp="one_point", precision="fp64", omega=1.0, max_levels=25,
+                max_coarse=128, stall=0.9, block_size=0, graphs=True, stream=None):
+    """One hierarchy for a batch of independent systems.
+
+    systems: list of (rowptr, col, val), all NumPy (host) or all CUDA
+    tensors.  Vectors of the returned hierarchy are the concatenation of the
+    systems' vectors in list order.
+    """
+    lib = L.load()
+    keep = []
+    mats = []
+    for (rp, cj, v) in systems:
+        A, _ = _csr(rp, cj, v, keep)
+        mats.append(A)
+    arr = (L.Csr * len(mats))(*mats)
+    s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
+                         max_levels, max_coarse, stall, block_size, graphs)
+    out = ctypes.c_void_p()
+    st = lib.lair_setup_batch(len(mats), arr, None, ctypes.byref(s), ctypes.byref(o),
+                              _stream_ptr(stream), ctypes.byref(out))
+    L.check(st, "lair_setup_batch")
+    return Hierarchy(out, int(sum(m.n for m in mats)), opts)
+
+
+def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
+          kind="abs", distance=1, interp="one_point", precision="fp64",
+          omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
+          graphs=True, stream=None):
+    """Build a hierarchy for the CSR matrix (rowptr, col, val).
+
+    The arrays may be NumPy arrays (host) or contiguous CUDA tensors
+    (int32, int32, float64).  cf_levels is an optional list of per-level
+    int8 CF splittings (1 = C) in host memory.  graphs=False launches the
+    solve's kernels eagerly instead of replaying captured iterations.
+    """
+    lib = L.load()
+    keep = []
+    A, n = _csr(rowptr, col, val, keep)
+    s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
+                         max_levels, max_coarse, stall, block_size, graphs)
     cfp = None
     if cf_levels is not None:
         arrs = [np.ascontiguousarray(x, dtype=np.int8) for x in cf_levels]
@@ -236,8 +314,4 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
     st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),
                         _stream_ptr(stream), ctypes.byref(out))
     L.check(st, "lair_setup")
-    opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
-                interp=interp, precision=precision, omega=omega,
-                max_levels=max_levels, max_coarse=max_coarse, stall=stall,
-                block_size=block_size)
     return Hierarchy(out, n, opts)

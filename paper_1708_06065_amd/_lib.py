@@ -19,6 +19,7 @@ SOC_ABS, SOC_NEG = 0, 1
 DIST_ALL_F = 0
 P_ONE_POINT, P_DIRECT = 0, 1
 FP64, MIXED = 0, 1
+FLAG_NO_GRAPH = 1
 
 
 class Csr(ctypes.Structure):
@@ -38,7 +39,7 @@ class CfLevels(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("interp", c_i32), ("precision", c_i32), ("omega", c_f64),
                 ("max_levels", c_i32), ("max_coarse", c_i32), ("stall", c_f64),
-                ("block_size", c_i32), ("reserved", c_i32)]
+                ("block_size", c_i32), ("flags", c_i32)]
 
 
 class Info(ctypes.Structure):
@@ -68,6 +69,10 @@ EXPORTS = {
     "lair_solve": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
     "lair_solve_transpose": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
     "lair_cycle_transpose": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "lair_setup_batch": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lair_solve_batch": (c_i32, [c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "lair_num_systems": (c_i32, [c_vp]),
+    "lair_system_levels": (c_i32, [c_vp, c_vp]),
     "lair_num_levels": (c_i32, [c_vp]),
     "lair_level_stats_get": (c_i32, [c_vp, c_i32, c_vp]),
     "lair_export": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp]),

@@ -53,6 +53,15 @@ struct Level {
     DevArr<int32_t> cidx, clist, flist, nptr, nbr;
     DevArr<int8_t> flags;
     lair_level_stats st{};
+    // batch of systems: row offsets of every system at this level, the
+    // systems that no longer coarsen (pass-through rows), and the C rows
+    // that are relaxed (C-points of systems still coarsening)
+    std::vector<int64_t> seg, next_seg;
+    DevArr<int64_t> seg_dev;
+    std::vector<uint8_t> stopped;
+    DevArr<uint8_t> stopped_dev;
+    DevArr<int32_t> rclist;
+    int32_t nrc = -1;                 // -1: relax every C row (clist)
     // cycle work vectors (capacity h->nrhs_cap right-hand sides)
     DevArr<double> b, x, t, r;
     DevArr<float> b32, x32, t32, r32;
@@ -75,6 +84,31 @@ struct lair_hierarchy {
     lair::DevArr<double> bscaled, r0, partial, norms;
     lair::DevArr<float> r0_32, e32;
     bool have_transpose = false;
+    // batch of independent systems (nsys > 1): per-system coarsest blocks
+    int32_t nsys = 1;
+    lair::DevArr<int64_t> dense_off;
+    std::vector<int32_t> sys_levels;
+    lair::DevArr<uint8_t> active_dev;
+    lair::DevArr<double> seg_norm;
+    lair::DevArr<double> e64;
+    // captured correction cycles, keyed by (precision, nrhs); replayed on a
+    // private stream ordered against the caller's stream with events
+    bool batch = false;                      // built by lair_setup_batch
+    std::vector<uint8_t> active;             // systems still iterated
+    // captured solve iterations (cycle + residual + norms), keyed by the
+    // iteration kind, the number of right-hand sides and the caller's b and
+    // x; captured on a private stream, replayed on the caller's stream
+    struct Graph { int kind; int32_t nrhs; const void *b; void *x; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
+    hipStream_t gstream = nullptr;
+    void drop_graphs() {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
+    ~lair_hierarchy() {
+        drop_graphs();
+        if (gstream) (void)hipStreamDestroy(gstream);
+    }
     int64_t n_singular = 0;
     double setup_ms = 0.0;
     double cc = 0.0, oc = 0.0;
@@ -208,6 +242,7 @@ static void check_options(const lair_strength *s, const lair_options *o) {
     if (o->max_coarse < 1) fail(LAIR_EINVAL, "max_coarse must be >= 1");
     if (!(o->stall > 0.0 && o->stall <= 1.0)) fail(LAIR_EINVAL, "stall must lie in (0, 1]");
     if (o->block_size < 0 || o->block_size > 8) fail(LAIR_EINVAL, "block_size must lie in [0, 8]");
+    if (o->flags & ~LAIR_FLAG_NO_GRAPH) fail(LAIR_EINVAL, "unknown option flags 0x%x", o->flags);
 }
 
 static const int32_t MAX_DENSE = 4096;
@@ -257,10 +292,55 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), hcf.data(), (size_t)n, hipMemcpyHostToDevice, s));
         LAIR_HIP(hipStreamSynchronize(s));
     }
+    std::vector<int64_t> seg_next;
+    if (h->nsys > 1) {
+        // systems that stopped coarsening keep all their points as C-points;
+        // a system whose splitting has no C-point or stalls stops here
+        const int32_t ns = h->nsys;
+        Lv.stopped_dev.alloc((size_t)ns, s);
+        LAIR_HIP(hipMemcpyAsync(Lv.stopped_dev.get(), Lv.stopped.data(), (size_t)ns,
+                                hipMemcpyHostToDevice, s));
+        launch_force_c(ns, Lv.seg_dev.get(), Lv.stopped_dev.get(), Lv.cf.get(), n, s);
+        DevArr<int32_t> cnt;
+        cnt.alloc((size_t)ns, s);
+        launch_seg_count_c(ns, Lv.seg_dev.get(), Lv.cf.get(), cnt.get(), s);
+        std::vector<int32_t> ncs((size_t)ns);
+        {
+            Readback rb(s);
+            rb.add(ncs.data(), cnt.get(), sizeof(int32_t) * ns);
+            rb.run();
+        }
+        bool newly = false, all = true;
+        for (int32_t q = 0; q < ns; ++q) {
+            int64_t nq = Lv.seg[q + 1] - Lv.seg[q];
+            if (!Lv.stopped[q] && (ncs[q] == 0 || (double)ncs[q] > h->opt.stall * (double)nq)) {
+                Lv.stopped[q] = 1;
+                h->sys_levels[q] = lvl + 1;
+                newly = true;
+            }
+            all = all && Lv.stopped[q];
+        }
+        if (all) {
+            coarsest = true;
+            Lv.smask.release();
+            Lv.cf.release();
+            return;
+        }
+        if (newly) {
+            LAIR_HIP(hipMemcpyAsync(Lv.stopped_dev.get(), Lv.stopped.data(), (size_t)ns,
+                                    hipMemcpyHostToDevice, s));
+            launch_force_c(ns, Lv.seg_dev.get(), Lv.stopped_dev.get(), Lv.cf.get(), n, s);
+        }
+        seg_next.assign((size_t)ns + 1, 0);
+        for (int32_t q = 0; q < ns; ++q) {
+            int64_t nq = Lv.seg[q + 1] - Lv.seg[q];
+            seg_next[q + 1] = seg_next[q] + (Lv.stopped[q] ? nq : (int64_t)ncs[q]);
+        }
+    }
     DevArr<int32_t> scan;
     scan.alloc((size_t)n + 1, s);
     int64_t nc = scan_flags_i8(Lv.cf.get(), 1, scan.get(), n, s, tmp);
-    if (nc == 0 || (double)nc > h->opt.stall * (double)n) {
+    if (h->nsys == 1 && (nc == 0 || (double)nc > h->opt.stall * (double)n)) {
         coarsest = true;
         Lv.smask.release();
         Lv.cf.release();
@@ -268,6 +348,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     }
     Lv.nc = (int32_t)nc;
     Lv.nf = n - Lv.nc;
+    Lv.next_seg = std::move(seg_next);
     Lv.cidx.alloc((size_t)n, s);
     Lv.clist.alloc((size_t)Lv.nc, s);
     Lv.flist.alloc((size_t)std::max(Lv.nf, 1), s);
@@ -284,6 +365,13 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         rb.run();
         Lv.nnzF = (int64_t)hacc[0];
         Lv.nnzC = (int64_t)hacc[1];
+    }
+    if (h->nsys > 1) {
+        bool any = false;
+        for (auto q : Lv.stopped) any = any || q;
+        if (any)
+            Lv.nrc = relax_list(h->nsys, Lv.seg_dev.get(), Lv.stopped_dev.get(), Lv.clist.get(),
+                                Lv.nc, Lv.rclist, s, tmp);
     }
 
     // neighbourhoods
@@ -372,7 +460,47 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
 
 static const int32_t MAX_INVERSE = 512;
 
+static void finish_coarsest_batch(lair_hierarchy *h) {
+    hipStream_t s = h->stream;
+    Level &Lc = *h->L.back();
+    const int32_t ns = h->nsys;
+    std::vector<int64_t> doff((size_t)ns + 1, 0);
+    for (int32_t q = 0; q < ns; ++q) {
+        int64_t m = Lc.seg[q + 1] - Lc.seg[q];
+        if (m > MAX_DENSE)
+            fail(LAIR_EUNSUPPORTED, "system %d has a coarsest level of %lld rows (> %d)", q,
+                 (long long)m, MAX_DENSE);
+        doff[q + 1] = doff[q] + m * m;
+    }
+    ProfScope ps("coarse_setup", s, 8.0 * (double)doff[ns], 0.0);
+    h->nL = Lc.n;
+    h->dense_off.alloc((size_t)ns + 1, s);
+    LAIR_HIP(hipMemcpyAsync(h->dense_off.get(), doff.data(), sizeof(int64_t) * (ns + 1),
+                            hipMemcpyHostToDevice, s));
+    h->lu.alloc((size_t)std::max<int64_t>(doff[ns], 1), s);
+    h->piv.alloc((size_t)std::max(Lc.n, 1), s);
+    DevArr<int32_t> info;
+    info.alloc(1, s);
+    LAIR_HIP(hipMemsetAsync(info.get(), 0, sizeof(int32_t), s));
+    launch_dense_blocks(ns, Lc.seg_dev.get(), h->dense_off.get(), Lc.A.rp.get(), Lc.A.cj.get(),
+                        Lc.A.v.get(), h->lu.get(), Lc.n, s);
+    launch_block_lu(ns, Lc.seg_dev.get(), h->dense_off.get(), h->lu.get(), h->piv.get(),
+                    info.get(), s);
+    int32_t hinfo = 0;
+    {
+        Readback rb(s);
+        rb.add(&hinfo, info.get(), sizeof(int32_t));
+        rb.run();
+    }
+    if (hinfo != 0)
+        fail(LAIR_ESINGULAR, "the coarsest matrix of system %d is singular", hinfo - 1);
+}
+
 static void finish_coarsest(lair_hierarchy *h) {
+    if (h->nsys > 1) {
+        finish_coarsest_batch(h);
+        return;
+    }
     hipStream_t s = h->stream;
     Level &Lc = *h->L.back();
     int32_t n = Lc.n;
@@ -423,9 +551,16 @@ static void level_stats_and_cc(lair_hierarchy *h) {
     h->oc = sum / nnz0;
 }
 
+static void upload_seg(Level &Lv, hipStream_t s) {
+    Lv.seg_dev.alloc(Lv.seg.size(), s);
+    LAIR_HIP(hipMemcpyAsync(Lv.seg_dev.get(), Lv.seg.data(), sizeof(int64_t) * Lv.seg.size(),
+                            hipMemcpyHostToDevice, s));
+}
+
+// seg: row offsets of the systems of a batch (nsys + 1 entries), or NULL.
 static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
                                   const lair_strength *str, const lair_options *opt,
-                                  hipStream_t s) {
+                                  hipStream_t s, const std::vector<int64_t> *seg = nullptr) {
     auto t0 = Clock::now();
     if (!Ain) fail(LAIR_EINVAL, "A must not be NULL");
     check_options(str, opt);
@@ -480,6 +615,14 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
     }
     std::unique_ptr<Level> L0(new Level());
     L0->n = n;
+    if (seg) {
+        h->batch = true;
+        h->nsys = (int32_t)seg->size() - 1;
+        h->sys_levels.assign((size_t)h->nsys, 0);
+        L0->seg = *seg;
+        L0->stopped.assign((size_t)h->nsys, 0);
+        upload_seg(*L0, s);
+    }
     DevCSR &A = L0->A;
     A.nrows = A.ncols = n;
     A.nnz = nnz;
@@ -525,7 +668,21 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
 
     for (int32_t lvl = 0;; ++lvl) {
         Level &Lv = *h->L.back();
-        if (Lv.n <= opt->max_coarse || lvl + 1 >= opt->max_levels) break;
+        if (h->nsys == 1) {
+            if (Lv.n <= opt->max_coarse || lvl + 1 >= opt->max_levels) break;
+        } else {
+            // each system stops under the single-system rules
+            bool all = true;
+            for (int32_t q = 0; q < h->nsys; ++q) {
+                int64_t nq = Lv.seg[q + 1] - Lv.seg[q];
+                if (!Lv.stopped[q] && (nq <= opt->max_coarse || lvl + 1 >= opt->max_levels)) {
+                    Lv.stopped[q] = 1;
+                    h->sys_levels[q] = lvl + 1;
+                }
+                all = all && Lv.stopped[q];
+            }
+            if (all) break;
+        }
         bool coarsest = false;
         build_level_transfer(h.get(), Lv, lvl, cfl, coarsest, tmp);
         if (coarsest) break;
@@ -537,6 +694,11 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         int32_t rmax = Lv.st.s_max + 1;
         // rows of K are sorted and unique by construction of the product
         nx->max_row = spgemm(Lv.R, rmax, AP, nx->A, s, tmp);
+        if (h->nsys > 1) {
+            nx->seg = Lv.next_seg;
+            nx->stopped = Lv.stopped;
+            upload_seg(*nx, s);
+        }
         h->L.push_back(std::move(nx));
     }
     finish_coarsest(h.get());
@@ -569,6 +731,7 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
 // ---------------------------------------------------------------------------
 static void ensure_vectors(lair_hierarchy *h, int32_t nrhs, hipStream_t s) {
     if (nrhs <= h->nrhs_cap) return;
+    h->drop_graphs();     // captured iterations refer to the old buffers
     bool mixed = h->opt.precision == LAIR_MIXED;
     for (size_t l = 0; l < h->L.size(); ++l) {
         Level &Lv = *h->L[l];
@@ -621,6 +784,19 @@ static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
     const int w = sizeof(VT);
     ProfScope ps("coarse_solve", s, 8.0 * h->nL * (double)h->nL + 2.0 * w * nrhs * h->nL,
                  2.0 * h->nL * (double)h->nL * nrhs);
+    if (h->nsys > 1) {
+        Level &Lb = *h->L.back();
+        if constexpr (std::is_same<VT, double>::value) {
+            launch_block_solve(h->nsys, Lb.seg_dev.get(), h->dense_off.get(), h->lu.get(),
+                               h->piv.get(), b, x, transpose, s);
+        } else {
+            op_cast_f64(b, Lb.r.get(), h->nL, s);
+            launch_block_solve(h->nsys, Lb.seg_dev.get(), h->dense_off.get(), h->lu.get(),
+                               h->piv.get(), Lb.r.get(), Lb.x.get(), transpose, s);
+            op_cast_f32(Lb.x.get(), x, h->nL, s);
+        }
+        return;
+    }
     if (h->kinv.get()) {
         op_coarse_apply<VT>(h->nL, h->kinv.get(), b, x, nrhs, transpose, s);
         return;
@@ -660,14 +836,16 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
                      2.0 * Lv.nnzF * nrhs);
         op_jacobi<VT>(A, Lv.flist.get(), Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s);
     }
+    const int32_t *crows = Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get();
+    const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
     {
-        ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, Lv.nc, Lv.n, w, nrhs, false),
+        ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, ncr, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzC * nrhs);
-        op_jacobi<VT>(A, Lv.clist.get(), Lv.nc, b, x, x, nullptr, y, true, om, nrhs, s);
+        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, true, om, nrhs, s);
     }
     {
-        ProfScope ps("scatter", s, 4.0 * Lv.nc + 2.0 * w * nrhs * Lv.nc);
-        op_scatter<VT>(Lv.clist.get(), Lv.nc, y, x, nrhs, s);
+        ProfScope ps("scatter", s, 4.0 * ncr + 2.0 * w * nrhs * ncr);
+        op_scatter<VT>(crows, ncr, y, x, nrhs, s);
     }
 }
 
@@ -740,9 +918,11 @@ static void vcycle_t(lair_hierarchy *h, size_t l, const double *g, double *lam,
     if (lam_zero) op_fill<double>(lam, 0.0, (int64_t)Lv.n * nrhs, s);
     CsrView<double> At = view<double>(Lv.At, Lv.team_At);
     double om = h->opt.omega;
+    const int32_t *crows = Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get();
+    const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
     for (int sweep = 0; sweep < 3; ++sweep) {
-        const int32_t *rows = sweep == 0 ? Lv.clist.get() : Lv.flist.get();
-        int32_t nx = sweep == 0 ? Lv.nc : Lv.nf;
+        const int32_t *rows = sweep == 0 ? crows : Lv.flist.get();
+        int32_t nx = sweep == 0 ? ncr : Lv.nf;
         op_jacobi<double>(At, rows, nx, g, lam, lam, nullptr, Lv.t.get(), true, om, nrhs, s);
         op_scatter<double>(rows, nx, Lv.t.get(), lam, nrhs, s);
     }
@@ -757,29 +937,103 @@ static bool valid_nrhs(int32_t nrhs) {
     return nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8 || nrhs == 16 || nrhs == 32;
 }
 
-static void norms_host(lair_hierarchy *h, const double *r, int32_t nrhs,
-                       hipStream_t s, std::vector<double> &out) {
-    {
-        ProfScope ps("norm", s, 8.0 * nrhs * h->L[0]->n, 2.0 * nrhs * h->L[0]->n);
-        op_sumsq(r, h->L[0]->n, nrhs, h->partial.get(), NPARTIAL, h->norms.get(), s);
-    }
-    out.resize((size_t)nrhs);
+static void check_nrhs(const lair_hierarchy *h, int32_t nrhs) {
+    if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
+    if (h->nsys > 1 && nrhs != 1)
+        fail(LAIR_EINVAL, "a hierarchy of a batch takes one right-hand side per system");
+}
+
+static void sumsq_dev(lair_hierarchy *h, const double *r, int32_t nrhs, hipStream_t s) {
+    ProfScope ps("norm", s, 8.0 * nrhs * h->L[0]->n, 2.0 * nrhs * h->L[0]->n);
+    op_sumsq(r, h->L[0]->n, nrhs, h->partial.get(), NPARTIAL, h->norms.get(), s);
+}
+
+// Square roots of the m sums of squares at dev (synchronises s).
+static void read_norms(const double *dev, int32_t m, hipStream_t s, std::vector<double> &out) {
+    out.resize((size_t)m);
     {
         Readback rb(s);
-        rb.add(out.data(), h->norms.get(), sizeof(double) * nrhs);
+        rb.add(out.data(), dev, sizeof(double) * m);
         rb.run();
     }
     for (auto &v : out) v = std::sqrt(v);
+}
+
+static void norms_host(lair_hierarchy *h, const double *r, int32_t nrhs,
+                       hipStream_t s, std::vector<double> &out) {
+    sumsq_dev(h, r, nrhs, s);
+    read_norms(h->norms.get(), nrhs, s, out);
+}
+
+// Kinds of captured iterations.
+enum { IT_FP64 = 0, IT_MIXED = 1, IT_BATCH_FP64 = 2, IT_BATCH_MIXED = 3 };
+
+static const char *const CYCLE_CATEGORIES[] = {
+    "jacobi", "scatter", "residual", "restrict", "interpolate", "coarse_solve", "norm", "cast"};
+
+// Iterations are captured unless the caller asked for eager launches or the
+// profiler times one of the cycle's categories (its events would have to be
+// recorded launch by launch).
+static bool use_graphs(const lair_hierarchy *h) {
+    if (h->opt.flags & LAIR_FLAG_NO_GRAPH) return false;
+    for (const char *c : CYCLE_CATEGORIES)
+        if (prof_selected(c)) return false;
+    return true;
+}
+
+static const size_t MAX_GRAPHS = 8;
+
+// Run body(stream) on s: replay its captured graph, capturing it first on
+// the hierarchy's private stream.  body must launch kernels only (no
+// allocation, no host synchronisation, no memset).
+template <class Body>
+static void run_iteration(lair_hierarchy *h, int kind, int32_t nrhs, const void *b, void *x,
+                          hipStream_t s, Body &&body) {
+    if (!use_graphs(h)) {
+        body(s);
+        return;
+    }
+    for (auto &g : h->graphs)
+        if (g.kind == kind && g.nrhs == nrhs && g.b == b && g.x == x) {
+            LAIR_HIP(hipGraphLaunch(g.exec, s));
+            return;
+        }
+    if (!h->gstream) LAIR_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    LAIR_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    try {
+        body(h->gstream);
+    } catch (...) {
+        if (hipStreamEndCapture(h->gstream, &graph) == hipSuccess && graph)
+            (void)hipGraphDestroy(graph);
+        throw;
+    }
+    LAIR_HIP(hipStreamEndCapture(h->gstream, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) fail(LAIR_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    if (h->graphs.size() >= MAX_GRAPHS) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back({kind, nrhs, b, x, exec});
+    LAIR_HIP(hipGraphLaunch(exec, s));
+}
+
+static void check_solve_args(lair_hierarchy *h, const double *b, double *x, double rtol,
+                             int32_t maxit) {
+    if (!h) fail(LAIR_EINVAL, "hierarchy is NULL");
+    if (!b || !x) fail(LAIR_EINVAL, "b and x must not be NULL");
+    if (!(rtol > 0.0) || maxit < 0) fail(LAIR_EINVAL, "need rtol > 0 and maxit >= 0");
 }
 
 static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
                               int32_t nrhs, double rtol, int32_t maxit,
                               lair_info *info, hipStream_t s, bool transpose) {
     auto t0 = Clock::now();
-    if (!h) fail(LAIR_EINVAL, "hierarchy is NULL");
-    if (!b || !x) fail(LAIR_EINVAL, "b and x must not be NULL");
-    if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
-    if (!(rtol > 0.0) || maxit < 0) fail(LAIR_EINVAL, "need rtol > 0 and maxit >= 0");
+    check_solve_args(h, b, x, rtol, maxit);
+    check_nrhs(h, nrhs);
     ensure_vectors(h, nrhs, s);
     if (transpose) ensure_transposes(h);
     Level &L0 = *h->L[0];
@@ -794,17 +1048,21 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     norms_host(h, bb, nrhs, s, nb);
     CsrView<double> A0 = transpose ? view<double>(L0.At, L0.team_At)
                                    : view<double>(L0.A, L0.team_A);
+    const DevCSR &M0 = transpose ? L0.At : L0.A;
+    auto residual_and_norms = [&](hipStream_t st) {
+        {
+            ProfScope ps("residual", st, ab_rowdot(M0, 8, nrhs, 2), 2.0 * M0.nnz * nrhs);
+            op_residual<double>(A0, bb, x, h->r0.get(), nrhs, st);
+        }
+        sumsq_dev(h, h->r0.get(), nrhs, st);
+    };
     bool mixed = h->opt.precision == LAIR_MIXED && !transpose;
+    residual_and_norms(s);
+    read_norms(h->norms.get(), nrhs, s, rn);
+    r_first = rn;
     int32_t it = 0;
     double relmax = 0.0;
     for (;;) {
-        {
-            const DevCSR &M0 = transpose ? L0.At : L0.A;
-            ProfScope ps("residual", s, ab_rowdot(M0, 8, nrhs, 2), 2.0 * M0.nnz * nrhs);
-            op_residual<double>(A0, bb, x, h->r0.get(), nrhs, s);
-        }
-        norms_host(h, h->r0.get(), nrhs, s, rn);
-        if (it == 0) r_first = rn;
         relmax = 0.0;
         bool done = true;
         for (int32_t q = 0; q < nrhs; ++q) {
@@ -820,19 +1078,27 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
             hipLaunchKernelGGL(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
                                x, e.get(), n * nrhs);
             LAIR_LAUNCH_CHECK();
+            residual_and_norms(s);
         } else if (!mixed) {
-            vcycle<double>(h, 0, bb, x, false, h->r0.get(), nrhs, s);
+            run_iteration(h, IT_FP64, nrhs, bb, x, s, [&](hipStream_t st) {
+                vcycle<double>(h, 0, bb, x, false, h->r0.get(), nrhs, st);
+                residual_and_norms(st);
+            });
         } else {
-            {
-                ProfScope ps("cast", s, 12.0 * n * nrhs);
-                op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
-            }
-            vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, s);
-            {
-                ProfScope ps("cast", s, 20.0 * n * nrhs);
-                op_axpy_f32(x, h->e32.get(), n * nrhs, s);
-            }
+            run_iteration(h, IT_MIXED, nrhs, bb, x, s, [&](hipStream_t st) {
+                {
+                    ProfScope ps("cast", st, 12.0 * n * nrhs);
+                    op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, st);
+                }
+                vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, st);
+                {
+                    ProfScope ps("cast", st, 20.0 * n * nrhs);
+                    op_axpy_f32(x, h->e32.get(), n * nrhs, st);
+                }
+                residual_and_norms(st);
+            });
         }
+        read_norms(h->norms.get(), nrhs, s, rn);
         ++it;
     }
     LAIR_HIP(hipStreamSynchronize(s));
@@ -853,6 +1119,212 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
         info->solve_ms = ms_since(t0);
     }
     return relmax <= rtol ? LAIR_OK : LAIR_ENOCONV;
+}
+
+// Batch of independent systems (one right-hand side each): the correction
+// form x += B (b - A x) on the union, with the residual rows of converged
+// systems zeroed so that their corrections vanish.  Each system stops at its
+// own relative residual.
+static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *x,
+                                    double rtol, int32_t maxit, int32_t *iters,
+                                    double *relres, lair_info *info, hipStream_t s) {
+    auto t0 = Clock::now();
+    check_solve_args(h, b, x, rtol, maxit);
+    if (!h->batch) fail(LAIR_EINVAL, "the hierarchy was not built by lair_setup_batch");
+    ensure_vectors(h, 1, s);
+    Level &L0 = *h->L[0];
+    const int32_t ns = h->nsys;
+    const int64_t n = L0.n;
+    bool mixed = h->opt.precision == LAIR_MIXED;
+    h->seg_norm.alloc((size_t)ns, s);
+    h->active_dev.alloc((size_t)ns, s);
+    if (!mixed) h->e64.alloc((size_t)n, s);
+    const double *bb = b;
+    if (h->opt.block_size > 0) {
+        op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
+                       h->bscaled.get(), 1, s);
+        bb = h->bscaled.get();
+    }
+    std::vector<double> nb, rn, rfirst;
+    {
+        ProfScope ps("norm", s, 8.0 * n, 2.0 * n);
+        launch_seg_sumsq(ns, L0.seg_dev.get(), bb, h->seg_norm.get(), s);
+    }
+    read_norms(h->seg_norm.get(), ns, s, nb);
+    CsrView<double> A0 = view<double>(L0.A, L0.team_A);
+    auto residual_and_norms = [&](hipStream_t st) {
+        {
+            ProfScope ps("residual", st, ab_rowdot(L0.A, 8, 1, 2), 2.0 * L0.A.nnz);
+            op_residual<double>(A0, bb, x, h->r0.get(), 1, st);
+        }
+        ProfScope ps("norm", st, 8.0 * n, 2.0 * n);
+        launch_seg_sumsq(ns, L0.seg_dev.get(), h->r0.get(), h->seg_norm.get(), st);
+    };
+    residual_and_norms(s);
+    read_norms(h->seg_norm.get(), ns, s, rn);
+    rfirst = rn;
+    h->active.assign((size_t)ns, 1);
+    std::vector<int32_t> its((size_t)ns, 0);
+    std::vector<double> rel((size_t)ns, 0.0);
+    bool upload = true;
+    int32_t it = 0;
+    for (;;) {
+        int32_t nact = 0;
+        for (int32_t q = 0; q < ns; ++q) {
+            if (!h->active[q]) continue;
+            rel[q] = nb[q] > 0 ? rn[q] / nb[q] : rn[q];
+            its[q] = it;
+            if (rel[q] <= rtol) {
+                h->active[q] = 0;
+                upload = true;
+            } else {
+                ++nact;
+            }
+        }
+        if (nact == 0 || it >= maxit) break;
+        if (upload) {
+            LAIR_HIP(hipMemcpyAsync(h->active_dev.get(), h->active.data(), (size_t)ns,
+                                    hipMemcpyHostToDevice, s));
+            upload = false;
+        }
+        run_iteration(h, mixed ? IT_BATCH_MIXED : IT_BATCH_FP64, 1, bb, x, s,
+                      [&](hipStream_t st) {
+            launch_mask_rows(ns, L0.seg_dev.get(), h->active_dev.get(), h->r0.get(), n, st);
+            if (mixed) {
+                {
+                    ProfScope ps("cast", st, 12.0 * n);
+                    op_cast_f32(h->r0.get(), h->r0_32.get(), n, st);
+                }
+                vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, 1, st);
+                ProfScope ps("cast", st, 20.0 * n);
+                op_axpy_f32(x, h->e32.get(), n, st);
+            } else {
+                vcycle<double>(h, 0, h->r0.get(), h->e64.get(), true, nullptr, 1, st);
+                hipLaunchKernelGGL(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, x,
+                                   h->e64.get(), n);
+                LAIR_LAUNCH_CHECK();
+            }
+            residual_and_norms(st);
+        });
+        read_norms(h->seg_norm.get(), ns, s, rn);
+        ++it;
+    }
+    LAIR_HIP(hipStreamSynchronize(s));
+    double relmax = 0.0;
+    int32_t itmax = 0;
+    bool conv = true;
+    for (int32_t q = 0; q < ns; ++q) {
+        if (iters) iters[q] = its[q];
+        if (relres) relres[q] = rel[q];
+        relmax = std::max(relmax, rel[q]);
+        itmax = std::max(itmax, its[q]);
+        conv = conv && rel[q] <= rtol;
+    }
+    if (info) {
+        info->iters = itmax;
+        info->nlevels = (int32_t)h->L.size();
+        info->relres = relmax;
+        double rho = 0.0;
+        for (int32_t q = 0; q < ns; ++q)
+            if (its[q] > 0 && rfirst[q] > 0)
+                rho = std::max(rho, std::pow(rel[q] * nb[q] / rfirst[q], 1.0 / its[q]));
+        info->rho = rho;
+        info->cycle_complexity = h->cc;
+        info->op_complexity = h->oc;
+        info->n_singular_local = h->n_singular;
+        info->setup_ms = h->setup_ms;
+        info->solve_ms = ms_since(t0);
+    }
+    return conv ? LAIR_OK : LAIR_ENOCONV;
+}
+
+// Union of a batch: the systems' matrices placed block-diagonally, rows of
+// system q at [seg[q], seg[q+1]).
+static lair_hierarchy *setup_batch_impl(int32_t nsys, const lair_csr *sys,
+                                        const lair_cf_levels *cfl, const lair_strength *str,
+                                        const lair_options *opt, hipStream_t s) {
+    if (nsys < 1) fail(LAIR_EINVAL, "nsys must be >= 1");
+    if (!sys) fail(LAIR_EINVAL, "the system array must not be NULL");
+    check_options(str, opt);
+    std::vector<int64_t> seg((size_t)nsys + 1, 0), nzo((size_t)nsys + 1, 0);
+    const int32_t dev = sys[0].on_device;
+    for (int32_t q = 0; q < nsys; ++q) {
+        const lair_csr &M = sys[q];
+        if (M.n < 1 || M.nnz < M.n) fail(LAIR_EINVAL, "system %d: need n >= 1 and nnz >= n", q);
+        if (!M.rowptr || !M.col || !M.val) fail(LAIR_EINVAL, "system %d: NULL CSR array", q);
+        if ((M.on_device != 0) != (dev != 0))
+            fail(LAIR_EINVAL, "all systems must be on the host or all on the device");
+        if (opt->block_size > 0 && M.n % opt->block_size != 0)
+            fail(LAIR_EINVAL, "system %d: n is not a multiple of block_size", q);
+        seg[q + 1] = seg[q] + M.n;
+        nzo[q + 1] = nzo[q] + M.nnz;
+    }
+    if (seg[nsys] >= INT32_MAX || nzo[nsys] >= INT32_MAX)
+        fail(LAIR_EINVAL, "the union has %lld rows and %lld entries (each must be < 2^31)",
+             (long long)seg[nsys], (long long)nzo[nsys]);
+    const int64_t n = seg[nsys], nnz = nzo[nsys];
+    lair_csr U{n, nnz, nullptr, nullptr, nullptr, 0};
+    std::vector<int32_t> hrp, hcj;
+    std::vector<double> hv;
+    DevArr<int32_t> drp, dcj;
+    DevArr<double> dv;
+    if (!dev) {
+        hrp.resize((size_t)n + 1);
+        hcj.resize((size_t)nnz);
+        hv.resize((size_t)nnz);
+        for (int32_t q = 0; q < nsys; ++q) {
+            const lair_csr &M = sys[q];
+            if (M.rowptr[0] != 0 || M.rowptr[M.n] != M.nnz)
+                fail(LAIR_EINVAL, "system %d: rowptr must run from 0 to nnz", q);
+            for (int64_t i = 0; i < M.n; ++i) hrp[seg[q] + i] = (int32_t)(nzo[q] + M.rowptr[i]);
+            for (int64_t p = 0; p < M.nnz; ++p) {
+                int32_t c = M.col[p];
+                if (c < 0 || c >= M.n) fail(LAIR_EINVAL, "system %d: column %d out of range", q, c);
+                hcj[nzo[q] + p] = (int32_t)(c + seg[q]);
+            }
+            memcpy(hv.data() + nzo[q], M.val, sizeof(double) * M.nnz);
+        }
+        hrp[n] = (int32_t)nnz;
+        U.rowptr = hrp.data();
+        U.col = hcj.data();
+        U.val = hv.data();
+    } else {
+        std::vector<SysCsr> hs((size_t)nsys);
+        for (int32_t q = 0; q < nsys; ++q)
+            hs[q] = SysCsr{sys[q].rowptr, sys[q].col, sys[q].val, sys[q].n, sys[q].nnz};
+        DevArr<SysCsr> ds;
+        DevArr<int64_t> dseg, dnzo;
+        DevArr<int32_t> bad;
+        ds.alloc((size_t)nsys, s);
+        dseg.alloc((size_t)nsys + 1, s);
+        dnzo.alloc((size_t)nsys + 1, s);
+        bad.alloc(1, s);
+        drp.alloc((size_t)n + 1, s);
+        dcj.alloc((size_t)nnz, s);
+        dv.alloc((size_t)nnz, s);
+        LAIR_HIP(hipMemcpyAsync(ds.get(), hs.data(), sizeof(SysCsr) * nsys,
+                                hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipMemcpyAsync(dseg.get(), seg.data(), sizeof(int64_t) * (nsys + 1),
+                                hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipMemcpyAsync(dnzo.get(), nzo.data(), sizeof(int64_t) * (nsys + 1),
+                                hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int32_t), s));
+        launch_union_gather(nsys, ds.get(), dseg.get(), dnzo.get(), drp.get(), dcj.get(),
+                            dv.get(), bad.get(), s);
+        int32_t hb = 0;
+        {
+            Readback rb(s);
+            rb.add(&hb, bad.get(), sizeof(int32_t));
+            rb.run();
+        }
+        if (hb) fail(LAIR_EINVAL, "a system's rowptr does not run from 0 to nnz or a column "
+                                  "lies outside its rows");
+        U.rowptr = drp.get();
+        U.col = dcj.get();
+        U.val = dv.get();
+        U.on_device = 1;
+    }
+    return setup_impl(&U, cfl, str, opt, s, &seg);
 }
 
 }  // namespace lair
@@ -898,7 +1370,7 @@ void lair_default_options(lair_strength *s, lair_options *o) {
         o->max_coarse = 128;
         o->stall = 0.9;
         o->block_size = 0;
-        o->reserved = 0;
+        o->flags = 0;
     }
 }
 
@@ -913,11 +1385,43 @@ lair_status lair_setup(const lair_csr *A, const lair_cf_levels *cf,
     });
 }
 
+lair_status lair_setup_batch(int32_t nsys, const lair_csr *A, const lair_cf_levels *cf,
+                             const lair_strength *s, const lair_options *o, void *stream,
+                             lair_hierarchy **out) {
+    return guarded([&]() -> lair_status {
+        if (!out) fail(LAIR_EINVAL, "out must not be NULL");
+        *out = nullptr;
+        *out = setup_batch_impl(nsys, A, cf, s, o, (hipStream_t)stream);
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_solve_batch(lair_hierarchy *h, const double *b, double *x, double rtol,
+                             int32_t maxit, int32_t *iters, double *relres, lair_info *info,
+                             void *stream) {
+    return guarded([&]() -> lair_status {
+        return solve_batch_impl(h, b, x, rtol, maxit, iters, relres, info,
+                                (hipStream_t)stream);
+    });
+}
+
+int32_t lair_num_systems(const lair_hierarchy *h) { return h ? h->nsys : 0; }
+
+lair_status lair_system_levels(const lair_hierarchy *h, int32_t *levels) {
+    return guarded([&]() -> lair_status {
+        if (!h || !levels) fail(LAIR_EINVAL, "hierarchy and levels must not be NULL");
+        if (!h->batch) fail(LAIR_EINVAL, "the hierarchy was not built by lair_setup_batch");
+        for (int32_t q = 0; q < h->nsys; ++q)
+            levels[q] = h->nsys > 1 ? h->sys_levels[q] : (int32_t)h->L.size();
+        return LAIR_OK;
+    });
+}
+
 lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
                        int32_t nrhs, void *stream) {
     return guarded([&]() -> lair_status {
         if (!h || !b || !x) fail(LAIR_EINVAL, "NULL argument");
-        if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
+        check_nrhs(h, nrhs);
         hipStream_t s = (hipStream_t)stream;
         ensure_vectors(h, nrhs, s);
         const double *bb = b;
@@ -944,7 +1448,7 @@ lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g, double *lam
                                  int32_t nrhs, void *stream) {
     return guarded([&]() -> lair_status {
         if (!h || !g || !lam) fail(LAIR_EINVAL, "NULL argument");
-        if (!valid_nrhs(nrhs)) fail(LAIR_EINVAL, "nrhs must be 1, 2, 4, 8, 16 or 32");
+        check_nrhs(h, nrhs);
         hipStream_t s = (hipStream_t)stream;
         ensure_vectors(h, nrhs, s);
         ensure_transposes(h);

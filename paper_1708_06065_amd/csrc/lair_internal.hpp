@@ -269,4 +269,36 @@ void op_cast_f64(const float *in, double *out, int64_t n, hipStream_t s);
 void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
                     const double *b, double *out, int32_t nrhs, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batch kernels (k_batch.hip)
+// ---------------------------------------------------------------------------
+struct SysCsr {
+    const int32_t *rp;
+    const int32_t *cj;
+    const double *v;
+    int64_t n, nnz;
+};
+void launch_union_gather(int32_t nsys, const SysCsr *sys, const int64_t *seg,
+                         const int64_t *nzo, int32_t *rp, int32_t *cj, double *v, int32_t *bad,
+                         hipStream_t s);
+void launch_seg_count_c(int32_t nsys, const int64_t *seg, const int8_t *cf, int32_t *count,
+                        hipStream_t s);
+void launch_force_c(int32_t nsys, const int64_t *seg, const uint8_t *stopped, int8_t *cf,
+                    int64_t nrows, hipStream_t s);
+int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
+                   const int32_t *clist, int32_t nc, DevArr<int32_t> &out,
+                   hipStream_t s, DevArr<int64_t> &tmp);
+void launch_seg_sumsq(int32_t nsys, const int64_t *seg, const double *r, double *out,
+                      hipStream_t s);
+void launch_mask_rows(int32_t nsys, const int64_t *seg, const uint8_t *active, double *r,
+                      int64_t nrows, hipStream_t s);
+void launch_dense_blocks(int32_t nsys, const int64_t *seg, const int64_t *doff,
+                         const int32_t *rp, const int32_t *cj, const double *v,
+                         double *dense, int64_t nrows, hipStream_t s);
+void launch_block_lu(int32_t nsys, const int64_t *seg, const int64_t *doff, double *dense,
+                     int32_t *piv, int32_t *info, hipStream_t s);
+void launch_block_solve(int32_t nsys, const int64_t *seg, const int64_t *doff,
+                        const double *dense, const int32_t *piv, const double *b, double *x,
+                        bool transpose, hipStream_t s);
+
 }  // namespace lair

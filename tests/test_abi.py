@@ -70,3 +70,42 @@ def test_host_side_validation_without_gpu():
     assert lib.lair_cycle(None, None, None, 1, None) == L.LAIR_EINVAL
     assert lib.lair_num_levels(None) == 0
     lib.lair_free(None)
+
+
+def test_batch_host_validation_without_gpu():
+    import numpy as np
+    lib = L.load()
+    out = ctypes.c_void_p()
+    s, o = L.Strength(), L.Options()
+    lib.lair_default_options(ctypes.byref(s), ctypes.byref(o))
+    rp = np.array([0, 2, 4], np.int32)
+    cj = np.array([0, 1, 0, 1], np.int32)
+    v = np.array([2.0, -1.0, -1.0, 2.0])
+    p = [x.ctypes.data_as(ctypes.c_void_p) for x in (rp, cj, v)]
+    good = L.Csr(2, 4, *p, 0)
+    arr = (L.Csr * 2)(good, good)
+    assert lib.lair_setup_batch(0, arr, None, ctypes.byref(s), ctypes.byref(o), None,
+                                ctypes.byref(out)) == L.LAIR_EINVAL
+    assert lib.lair_setup_batch(2, None, None, ctypes.byref(s), ctypes.byref(o), None,
+                                ctypes.byref(out)) == L.LAIR_EINVAL
+    # host and device members mixed
+    arr = (L.Csr * 2)(good, L.Csr(2, 4, *p, 1))
+    assert lib.lair_setup_batch(2, arr, None, ctypes.byref(s), ctypes.byref(o), None,
+                                ctypes.byref(out)) == L.LAIR_EINVAL
+    assert b"host or all on the device" in lib.lair_last_error()
+    # a column outside the member's own rows
+    cj_bad = np.array([0, 2, 0, 1], np.int32)
+    bad = L.Csr(2, 4, p[0], cj_bad.ctypes.data_as(ctypes.c_void_p), p[2], 0)
+    arr = (L.Csr * 2)(good, bad)
+    assert lib.lair_setup_batch(2, arr, None, ctypes.byref(s), ctypes.byref(o), None,
+                                ctypes.byref(out)) == L.LAIR_EINVAL
+    assert b"system 1" in lib.lair_last_error()
+    # unknown option flags
+    o.flags = 6
+    arr = (L.Csr * 2)(good, good)
+    assert lib.lair_setup_batch(2, arr, None, ctypes.byref(s), ctypes.byref(o), None,
+                                ctypes.byref(out)) == L.LAIR_EINVAL
+    assert out.value is None
+    assert lib.lair_solve_batch(None, None, None, 1e-10, 10, None, None, None,
+                                None) == L.LAIR_EINVAL
+    assert lib.lair_num_systems(None) == 0
