@@ -16,7 +16,13 @@ During the timed steps the library's profiler brackets every launch of the
 dominant kernel category with HIP events on its stream; the roofline entry is
 that category's algorithmic bytes divided by its measured time.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c5|c4|c1]
+Workload c3: a batch of 512 independent 2-D advection-diffusion-reaction
+systems of uneven size (N x N grids, N log-uniform in [32, 320], 10.8 M
+unknowns in all), set up and solved as one block-diagonal union with
+per-system convergence; one step = lair_setup_batch (union CF splittings
+given) + lair_solve_batch to 1e-10 for every system.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c5|c3|c4|c1]
 """
 import argparse
 import json
@@ -45,6 +51,12 @@ def make_workload(name):
             {"workload": "implicit_euler_adr3d_128^3_16rhs", "n": w["n"], "nnz": w["nnz"],
              "nrhs": 16, "grid": "128^3", "eps": 1e-4, "dt": "h", "distance": 1,
              "interp": "direct", "relaxation": "FFC-Jacobi", "rtol": 1e-10}
+    if name == "c3":
+        w = W.workload_c3()
+        return w, dict(interp="direct", distance=1), \
+            {"workload": "adr2d_batch_512_systems", "n": w["n"], "nnz": w["nnz"],
+             "nsys": 512, "grid": "N x N, N log-uniform in [32, 320]", "nrhs": 1,
+             "distance": 1, "interp": "direct", "relaxation": "FFC-Jacobi", "rtol": 1e-10}
     if name == "c1":
         w = W.workload_c1()
         return w, dict(interp="one_point", distance=1), \
@@ -62,6 +74,42 @@ def make_workload(name):
             {"workload": "adr_reaction_64x64", "n": w["n"], "nnz": w["nnz"], "nrhs": 1,
              "distance": 1, "interp": "direct", "rtol": 1e-10}
     raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline_batch(kw, budget_s=15.0):
+    """Oracle on a bounded sample of the batch: setup + solve of the systems
+    in order until budget_s seconds have been spent, scaled to the whole
+    batch by stored entries.  Child process, one OpenMP thread."""
+    code = r'''
+import json, sys, time
+sys.path.insert(0, %r)
+import workloads as W
+from oracle import lair as O
+systems = W.adr_batch(512, seed=3)
+tot = sum(w["nnz"] for w in systems)
+t0 = time.perf_counter(); done = 0; nz = 0; its = []
+for w in systems:
+    A = O.csr(w["rowptr"], w["col"], w["val"])
+    H = O.setup(A, interp=O.INTERP_DIRECT)
+    x, it, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=100)
+    done += 1; nz += w["nnz"]; its.append(it)
+    if time.perf_counter() - t0 > %r:
+        break
+el = time.perf_counter() - t0
+print(json.dumps({"s": el, "done": done, "nnz": nz, "tot": tot, "iters_max": max(its)}))
+''' % (ROOT, budget_s)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        log("cpu baseline failed:", r.stderr[-2000:])
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    scale = d["tot"] / d["nnz"]
+    return {"value": 1e3 * d["s"] * scale, "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": "oracle setup + solve to 1e-10 of the first %d of 512 systems "
+                      "(%.1f s, %.1f%% of the stored entries), scaled x%.1f by stored entries"
+                      % (d["done"], d["s"], 100.0 / scale, scale)}
 
 
 def cpu_baseline(workload, kw):
@@ -139,16 +187,26 @@ def main():
     w, kw, cfg = make_workload(args.workload)
     log("workload %s generated in %.1fs (n=%d nnz=%d)" % (cfg["workload"], time.time() - t0,
                                                           w["n"], w["nnz"]))
+    batch = "systems" in w
     rp = torch.as_tensor(w["rowptr"], device=dev)
     cj = torch.as_tensor(w["col"], device=dev)
     vv = torch.as_tensor(w["val"], device=dev)
     B = torch.as_tensor(np.ascontiguousarray(np.asarray(w["rhs"], dtype=np.float64)),
                         device=dev)
+    if batch:
+        members = [(torch.as_tensor(q["rowptr"], device=dev),
+                    torch.as_tensor(q["col"], device=dev),
+                    torch.as_tensor(q["val"], device=dev)) for q in w["systems"]]
     torch.cuda.synchronize()
+
+    def build(cf_levels=None, precision="fp64"):
+        if batch:
+            return lair.setup_batch(members, cf_levels=cf_levels, precision=precision, **kw)
+        return lair.setup(rp, cj, vv, cf_levels=cf_levels, precision=precision, **kw)
 
     # CF splitting per level by the library's own first pass (untimed)
     t0 = time.perf_counter()
-    h0 = lair.setup(rp, cj, vv, **kw)
+    h0 = build()
     torch.cuda.synchronize()
     t_full_setup = (time.perf_counter() - t0) * 1e3
     cfl = [h0.export(l, "cf") for l in range(h0.nlevels - 1)]
@@ -157,8 +215,11 @@ def main():
     log("library CF split + setup: %.1f ms, %d levels" % (t_full_setup, nlev))
 
     def step(precision):
-        h = lair.setup(rp, cj, vv, cf_levels=cfl, precision=precision, **kw)
-        X, info = h.solve(B, rtol=1e-10, maxit=100)
+        h = build(cfl, precision)
+        if batch:
+            X, info = h.solve_batch(B, rtol=1e-10, maxit=100)
+        else:
+            X, info = h.solve(B, rtol=1e-10, maxit=100)
         return h, X, info
 
     # which kernel category dominates a step (one profiled, untimed step)
@@ -248,7 +309,7 @@ def main():
         out["speedup_mixed_vs_fp64"] = results["fp64"]["ms"] / r["ms"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        cb = cpu_baseline(args.workload, kw)
+        cb = cpu_baseline_batch(kw) if batch else cpu_baseline(args.workload, kw)
         if cb:
             out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

@@ -252,7 +252,15 @@ lair_status lair_export(const lair_hierarchy *h, int32_t level, int32_t what,
 lair_status lair_profile_begin(const char *categories);
 lair_status lair_profile_end(char *json, int64_t *len);
 
+/* Release a hierarchy (NULL is ignored).  Waits for the device to finish
+ * the launches that may still use its memory, which goes back to the
+ * library's cache of device blocks. */
 void lair_free(lair_hierarchy *h);
+
+/* Return every cached, unused device block to the HIP runtime (after a
+ * device synchronisation).  The library keeps released blocks for reuse by
+ * later calls on the same stream; this call gives the memory back. */
+void lair_trim(void);
 const char *lair_status_string(lair_status s);
 const char *lair_last_error(void);
 

@@ -244,6 +244,21 @@ def _csr(rowptr, col, val, keep):
     return L.Csr(n, nnz, rp, cj, vx, 1 if on_dev else 0), n
 
 
+def _cf_levels(cf_levels, keep):
+    """lair_cf_levels pointer (or None) for a list of per-level splittings."""
+    if cf_levels is None:
+        return None
+    arrs = [np.ascontiguousarray(x, dtype=np.int8) for x in cf_levels]
+    offs = np.zeros(len(arrs) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([x.shape[0] for x in arrs])
+    flat = np.concatenate(arrs) if arrs else np.zeros(1, np.int8)
+    keep += [offs, flat]
+    cfl = L.CfLevels(len(arrs), offs.ctypes.data_as(ctypes.c_void_p),
+                     flat.ctypes.data_as(ctypes.c_void_p))
+    keep.append(cfl)
+    return ctypes.byref(cfl)
+
+
 def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels,
             max_coarse, stall, block_size, graphs):
     s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
@@ -258,14 +273,16 @@ def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels
     return s, o, opts
 
 
-def setup_batch(systems, theta=0.25, theta_c=None, kind="abs", distance=1,
-                interp="one_point", precision="fp64", omega=1.0, max_levels=25,
-                max_coarse=128, stall=0.9, block_size=0, graphs=True, stream=None):
+def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
+                distance=1, interp="one_point", precision="fp64", omega=1.0,
+                max_levels=25, max_coarse=128, stall=0.9, block_size=0, graphs=True,
+                stream=None):
     """One hierarchy for a batch of independent systems.
 
     systems: list of (rowptr, col, val), all NumPy (host) or all CUDA
     tensors.  Vectors of the returned hierarchy are the concatenation of the
-    systems' vectors in list order.
+    systems' vectors in list order.  cf_levels: optional per-level
+    splittings of the union (as exported by a previous batch setup).
     """
     lib = L.load()
     keep = []
@@ -277,7 +294,8 @@ def setup_batch(systems, theta=0.25, theta_c=None, kind="abs", distance=1,
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
                          max_levels, max_coarse, stall, block_size, graphs)
     out = ctypes.c_void_p()
-    st = lib.lair_setup_batch(len(mats), arr, None, ctypes.byref(s), ctypes.byref(o),
+    cfp = _cf_levels(cf_levels, keep)
+    st = lib.lair_setup_batch(len(mats), arr, cfp, ctypes.byref(s), ctypes.byref(o),
                               _stream_ptr(stream), ctypes.byref(out))
     L.check(st, "lair_setup_batch")
     return Hierarchy(out, int(sum(m.n for m in mats)), opts)
@@ -299,17 +317,7 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
     A, n = _csr(rowptr, col, val, keep)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
                          max_levels, max_coarse, stall, block_size, graphs)
-    cfp = None
-    if cf_levels is not None:
-        arrs = [np.ascontiguousarray(x, dtype=np.int8) for x in cf_levels]
-        offs = np.zeros(len(arrs) + 1, dtype=np.int64)
-        offs[1:] = np.cumsum([x.shape[0] for x in arrs])
-        flat = np.concatenate(arrs) if arrs else np.zeros(1, np.int8)
-        keep += [offs, flat]
-        cfl = L.CfLevels(len(arrs), offs.ctypes.data_as(ctypes.c_void_p),
-                         flat.ctypes.data_as(ctypes.c_void_p))
-        keep.append(cfl)
-        cfp = ctypes.byref(cfl)
+    cfp = _cf_levels(cf_levels, keep)
     out = ctypes.c_void_p()
     st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),
                         _stream_ptr(stream), ctypes.byref(out))

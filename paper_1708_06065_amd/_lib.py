@@ -77,6 +77,7 @@ EXPORTS = {
     "lair_level_stats_get": (c_i32, [c_vp, c_i32, c_vp]),
     "lair_export": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp]),
     "lair_free": (None, [c_vp]),
+    "lair_trim": (None, []),
     "lair_profile_begin": (c_i32, [ctypes.c_char_p]),
     "lair_profile_end": (c_i32, [ctypes.c_char_p, c_vp]),
     "lair_status_string": (ctypes.c_char_p, [c_i32]),

@@ -56,9 +56,9 @@ __device__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) 
     return r;
 }
 
-template <class F>
+template <class F, class OUT>
 __global__ void __launch_bounds__(SCAN_BS)
-k_scan_tile(F f, int64_t n, int32_t *out, int64_t *blocksum, int64_t *blockmax) {
+k_scan_tile(F f, int64_t n, OUT *out, int64_t *blocksum, int64_t *blockmax) {
     __shared__ int64_t sh[SCAN_BS];
     __shared__ int64_t smx[SCAN_BS];
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
@@ -76,7 +76,7 @@ k_scan_tile(F f, int64_t n, int32_t *out, int64_t *blocksum, int64_t *blockmax) 
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
         int64_t i = base + j;
-        if (i < n) out[i] = (int32_t)pre;
+        if (i < n) out[i] = (OUT)pre;
         pre += v[j];
         m = v[j] > m ? v[j] : m;
     }
@@ -117,15 +117,15 @@ k_scan_sums(int64_t *bs, const int64_t *bmax, int64_t nb, int64_t *total) {
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void k_scan_add(int32_t *out, int64_t n, const int64_t *bs,
-                           const int64_t *total) {
+template <class OUT>
+__global__ void k_scan_add(OUT *out, int64_t n, const int64_t *bs, const int64_t *total) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (int32_t)((int64_t)out[i] + bs[i / SCAN_TILE]);
-    if (i == 0) out[n] = (int32_t)(*total);
+    if (i < n) out[i] = (OUT)((int64_t)out[i] + bs[i / SCAN_TILE]);
+    if (i == 0) out[n] = (OUT)(*total);
 }
 
-template <class F>
-static int64_t scan_impl(F f, int32_t *out, int64_t n, hipStream_t s,
+template <class F, class OUT>
+static int64_t scan_impl(F f, OUT *out, int64_t n, hipStream_t s,
                          DevArr<int64_t> &tmp, int64_t *max_out,
                          const int32_t *flag, int32_t *flag_out) {
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -134,12 +134,12 @@ static int64_t scan_impl(F f, int32_t *out, int64_t n, hipStream_t s,
     int64_t *bs = tmp.get();
     int64_t *bmax = bs + nb;
     int64_t *tot = bmax + nb;      // tot[0] = total, tot[1] = largest value
-    hipLaunchKernelGGL(k_scan_tile<F>, dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
+    hipLaunchKernelGGL((k_scan_tile<F, OUT>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
                        f, n, out, bs, bmax);
     LAIR_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, bmax, nb, tot);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
+    hipLaunchKernelGGL(k_scan_add<OUT>, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
                        0, s, out, n, bs, tot);
     LAIR_LAUNCH_CHECK();
     int64_t h[2] = {0, 0};
@@ -147,7 +147,7 @@ static int64_t scan_impl(F f, int32_t *out, int64_t n, hipStream_t s,
     rb.add(h, tot, sizeof(h));
     if (flag && flag_out) rb.add(flag_out, flag, sizeof(int32_t));
     rb.run();
-    if (h[0] > INT32_MAX)
+    if (sizeof(OUT) == 4 && h[0] > INT32_MAX)
         fail(LAIR_EUNSUPPORTED, "offset array exceeds 2^31 entries (%lld)",
              (long long)h[0]);
     if (max_out) *max_out = h[1];
@@ -158,6 +158,11 @@ int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
                         hipStream_t s, DevArr<int64_t> &tmp, int64_t *max_out,
                         const int32_t *flag, int32_t *flag_out) {
     return scan_impl(CountsF{cnt}, out, n, s, tmp, max_out, flag, flag_out);
+}
+
+int64_t scan_counts_i64(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t s,
+                        DevArr<int64_t> &tmp, int64_t *max_out) {
+    return scan_impl(CountsF{cnt}, out, n, s, tmp, max_out, nullptr, nullptr);
 }
 
 int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
@@ -1469,125 +1474,337 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 }
 
 // ===========================================================================
-// Row-merge sparse product C = A B, symbolic pattern.  One team of T lanes
-// per row of A; the row's entries select rows of B (sorted lists) that are
-// merged in increasing column order.  List k belongs to lane k % T, slot
-// k / T (LPL slots per lane).  The value of each output column is a
-// fixed-order team sum.
+// Sparse product C = A B with the symbolic pattern, rows of C sorted.
+//
+// Row i of C has at most E_i = sum over the entries a_ik of |row k of B|
+// products.  One pass writes row i (sorted, distinct columns) into a staging
+// buffer at the row's product offset, a scan of the row lengths gives C's
+// row pointers, and a copy compacts the rows.
+//
+// Main kernel (hash accumulation): one team of T lanes per row, inside one
+// wave, with a private open-addressing table in LDS.  The products are
+// enumerated flat (the team scans the lengths of the selected rows of B;
+// each lane takes every T-th product); each product's column is found or
+// inserted in the table and a_ik b_kj added to its slot.  The adds of a
+// round are one LDS instruction of the team's wave, rounds follow in
+// program order, and no other wave touches the table, so every sum is
+// formed in the same order on every run.  The rank of each distinct column
+// among the row's columns is its output position.  Rows with more distinct
+// columns than the table holds go to a list redone by a one-team block with
+// a larger table, and beyond that by the row-merge kernel.
+//
+// Fallback (row-merge): one team per row; the row's entries select rows of
+// B (sorted lists) merged in increasing column order, list k held by lane
+// k % T, slot k / T.
 // ===========================================================================
 constexpr int GEMM_PF = 4;   // entries of each merge list held in registers
 
-template <int T, int LPL, bool FILL>
-__global__ void __launch_bounds__(256)
-k_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
-         const int32_t *bp, const int32_t *bj, const double *bx, int32_t *cnt,
-         const int32_t *cp, int32_t *cj, double *cx, int32_t *overflow) {
-    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
-    int32_t i = (int32_t)(gt / T);
-    int lane = (int)(gt % T);
+// Rows processed by a team: all rows (rows == nullptr), or the *nlist rows
+// of a list, grid-stride.
+struct RowSrc {
+    const int32_t *rows;
+    const int32_t *nlist;
+};
+
+__global__ void k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj,
+                             const int32_t *bp, int32_t *e) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    int lo = ap[i], ka = ap[i + 1] - lo;
-    if (ka > T * LPL) {
-        if (lane == 0) { atomicOr(overflow, 1); if (!FILL) cnt[i] = 0; }
-        return;
+    int64_t t = 0;
+    for (int p = ap[i]; p < ap[i + 1]; ++p) {
+        int k = aj[p];
+        t += bp[k + 1] - bp[k];
     }
-    // Each slot holds the next GEMM_PF entries of its list (columns and
-    // scaled values) as a shift register: the merge consumes from registers
-    // and reloads GEMM_PF independent entries when the window is empty.
-    int pos[LPL], end[LPL];
-    int hb[LPL][GEMM_PF];
-    double vb[LPL][GEMM_PF];
-    double mul[LPL];
-#pragma unroll
-    for (int s = 0; s < LPL; ++s) {
-        int k = lane + s * T;
-        pos[s] = 0;
-        end[s] = 0;
-        mul[s] = 0.0;
-        if (k < ka) {
-            int r = aj[lo + k];
-            pos[s] = bp[r];
-            end[s] = bp[r + 1];
-            if (FILL) mul[s] = ax[lo + k];
-        }
-#pragma unroll
-        for (int d = 0; d < GEMM_PF; ++d) {
-            int idx = pos[s] + d;
-            bool ok = idx < end[s];
-            hb[s][d] = ok ? bj[idx] : INT_MAX;
-            if (FILL) vb[s][d] = ok ? mul[s] * bx[idx] : 0.0;
-        }
-        pos[s] += GEMM_PF;
-    }
-    int o = FILL ? cp[i] : 0;
-    for (;;) {
-        int h = INT_MAX;
-#pragma unroll
-        for (int s = 0; s < LPL; ++s) h = min(h, hb[s][0]);
-        int mn = team_min<T>(h);
-        if (mn == INT_MAX) break;
-        double acc = 0.0;
-#pragma unroll
-        for (int s = 0; s < LPL; ++s) {
-            if (hb[s][0] == mn) {
-                if (FILL) acc += vb[s][0];
-#pragma unroll
-                for (int d = 0; d + 1 < GEMM_PF; ++d) {
-                    hb[s][d] = hb[s][d + 1];
-                    if (FILL) vb[s][d] = vb[s][d + 1];
-                }
-                hb[s][GEMM_PF - 1] = INT_MAX;
-                if (hb[s][0] == INT_MAX && pos[s] < end[s]) {
-#pragma unroll
-                    for (int d = 0; d < GEMM_PF; ++d) {
-                        int idx = pos[s] + d;
-                        bool ok = idx < end[s];
-                        hb[s][d] = ok ? bj[idx] : INT_MAX;
-                        if (FILL) vb[s][d] = ok ? mul[s] * bx[idx] : 0.0;
-                    }
-                    pos[s] += GEMM_PF;
-                }
-            }
-        }
-        if (FILL) {
-            acc = team_sum<T>(acc);
-            if (lane == 0) { cj[o] = mn; cx[o] = acc; }
-        }
-        ++o;
-    }
-    if (!FILL && lane == 0) cnt[i] = o;
+    e[i] = (int32_t)min<int64_t>(t, INT32_MAX);
 }
 
 template <int T, int LPL>
-static void spgemm_t(int32_t m, const int32_t *ap, const int32_t *aj,
-                     const double *ax, const int32_t *bp, const int32_t *bj,
-                     const double *bx, bool fill, int32_t *cnt,
-                     const int32_t *cp, int32_t *cj, double *cx,
-                     int32_t *overflow, hipStream_t s) {
-    dim3 g(blocks_for((int64_t)m * T, 256)), b(256);
-    if (fill)
-        hipLaunchKernelGGL((k_spgemm<T, LPL, true>), g, b, 0, s, m, ap, aj, ax, bp, bj, bx,
-                           cnt, cp, cj, cx, overflow);
-    else
-        hipLaunchKernelGGL((k_spgemm<T, LPL, false>), g, b, 0, s, m, ap, aj, ax, bp, bj, bx,
-                           cnt, cp, cj, cx, overflow);
+__global__ void __launch_bounds__(256)
+k_spgemm_merge(RowSrc src, const int32_t *ap, const int32_t *aj, const double *ax,
+               const int32_t *bp, const int32_t *bj, const double *bx, const int64_t *off,
+               int32_t *cnt, int32_t *cj, double *cx, int32_t *overflow) {
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int lane = (int)(gt % T);
+    const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / T);
+    const int64_t nr = (int64_t)*src.nlist;
+    for (int64_t t = gt / T; t < nr; t += nteams) {
+        const int32_t i = src.rows[t];
+        int lo = ap[i], ka = ap[i + 1] - lo;
+        if (ka > T * LPL) {
+            if (lane == 0) { atomicOr(overflow, 1); cnt[i] = 0; }
+            continue;
+        }
+        // Each slot holds the next GEMM_PF entries of its list (columns and
+        // scaled values) as a shift register, reloaded when empty.
+        int pos[LPL], end[LPL];
+        int hb[LPL][GEMM_PF];
+        double vb[LPL][GEMM_PF];
+        double mul[LPL];
+#pragma unroll
+        for (int s = 0; s < LPL; ++s) {
+            int k = lane + s * T;
+            pos[s] = 0;
+            end[s] = 0;
+            mul[s] = 0.0;
+            if (k < ka) {
+                int r = aj[lo + k];
+                pos[s] = bp[r];
+                end[s] = bp[r + 1];
+                mul[s] = ax[lo + k];
+            }
+#pragma unroll
+            for (int d = 0; d < GEMM_PF; ++d) {
+                int idx = pos[s] + d;
+                bool ok = idx < end[s];
+                hb[s][d] = ok ? bj[idx] : INT_MAX;
+                vb[s][d] = ok ? mul[s] * bx[idx] : 0.0;
+            }
+            pos[s] += GEMM_PF;
+        }
+        int64_t o = off[i];
+        int nout = 0;
+        for (;;) {
+            int h = INT_MAX;
+#pragma unroll
+            for (int s = 0; s < LPL; ++s) h = min(h, hb[s][0]);
+            int mn = team_min<T>(h);
+            if (mn == INT_MAX) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < LPL; ++s) {
+                if (hb[s][0] == mn) {
+                    acc += vb[s][0];
+#pragma unroll
+                    for (int d = 0; d + 1 < GEMM_PF; ++d) {
+                        hb[s][d] = hb[s][d + 1];
+                        vb[s][d] = vb[s][d + 1];
+                    }
+                    hb[s][GEMM_PF - 1] = INT_MAX;
+                    if (hb[s][0] == INT_MAX && pos[s] < end[s]) {
+#pragma unroll
+                        for (int d = 0; d < GEMM_PF; ++d) {
+                            int idx = pos[s] + d;
+                            bool ok = idx < end[s];
+                            hb[s][d] = ok ? bj[idx] : INT_MAX;
+                            vb[s][d] = ok ? mul[s] * bx[idx] : 0.0;
+                        }
+                        pos[s] += GEMM_PF;
+                    }
+                }
+            }
+            acc = team_sum<T>(acc);
+            if (lane == 0) { cj[o + nout] = mn; cx[o + nout] = acc; }
+            ++nout;
+        }
+        if (lane == 0) cnt[i] = nout;
+    }
+}
+
+__device__ __forceinline__ int gemm_hash(int32_t col, int bits) {
+    return (int)(((uint32_t)col * 0x9E3779B1u) >> (32 - bits));
+}
+
+template <int HS>
+constexpr int log2_const() { return HS <= 1 ? 0 : 1 + log2_const<HS / 2>(); }
+
+template <int T, int HS, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const double *ax,
+              const int32_t *bp, const int32_t *bj, const double *bx, const int64_t *eoff,
+              int32_t *cnt, int32_t *tcj, double *tcx, int32_t *next, int32_t *nnext) {
+    constexpr int TEAMS = BLOCK / T;
+    constexpr int HC = HS / 2;              // distinct columns a table holds
+    constexpr int BITS = log2_const<HS>();
+    __shared__ int32_t s_key[TEAMS * HS];
+    __shared__ double s_val[TEAMS * HS];
+    __shared__ int32_t s_col[TEAMS * HC];   // distinct columns, insertion order
+    __shared__ int16_t s_slot[TEAMS * HC];  // and their slots
+    __shared__ int32_t s_n[TEAMS];
+    const int team = threadIdx.x / T;
+    const int lane = threadIdx.x % T;
+    int32_t *key = s_key + team * HS;
+    double *val = s_val + team * HS;
+    int32_t *lcol = s_col + team * HC;
+    int16_t *lslot = s_slot + team * HC;
+    const int64_t gteam = (xcd_block_id() * BLOCK + threadIdx.x) / T;
+    const int64_t nteams = (int64_t)gridDim.x * TEAMS;
+    const int64_t nr = src.rows ? (int64_t)*src.nlist : (int64_t)m;
+    for (int64_t t = gteam; t < nr; t += nteams) {
+        const int32_t i = src.rows ? src.rows[t] : (int32_t)t;
+        const int lo = ap[i], ka = ap[i + 1] - lo;
+        for (int q = lane; q < HS; q += T) { key[q] = -1; val[q] = 0.0; }
+        if (lane == 0) s_n[team] = 0;
+        wave_lds_sync();
+        bool full = false;
+        for (int c0 = 0; c0 < ka && !full; c0 += T) {
+            const int p = c0 + lane;
+            int b0 = 0, len = 0;
+            double a = 0.0;
+            if (p < ka) {
+                int k = aj[lo + p];
+                b0 = bp[k];
+                len = bp[k + 1] - b0;
+                a = ax[lo + p];
+            }
+            int inc = len;
+#pragma unroll
+            for (int o = 1; o < T; o <<= 1) {
+                int u = __shfl_up(inc, o, T);
+                if (lane >= o) inc += u;
+            }
+            const int tot = __shfl(inc, T - 1, T);
+            const int exc = inc - len;
+            for (int e0 = 0; e0 < tot; e0 += T) {
+                const int e = e0 + lane;
+                // owner of product e: the last lane whose offset is <= e
+                int q = 0;
+#pragma unroll
+                for (int st = T / 2; st > 0; st >>= 1) {
+                    int ex = __shfl(exc, q + st, T);
+                    if (ex <= e) q += st;
+                }
+                const int bq = __shfl(b0, q, T);
+                const int xq = __shfl(exc, q, T);
+                const double aq = __shfl(a, q, T);
+                int h = -1;
+                double v = 0.0;
+                if (e < tot) {
+                    const int idx = bq + e - xq;
+                    const int32_t col = bj[idx];
+                    v = aq * bx[idx];
+                    h = gemm_hash(col, BITS);
+                    for (int probe = 0;; ++probe) {
+                        int old = atomicCAS(&key[h], -1, col);
+                        if (old == -1) {
+                            int ps = atomicAdd(&s_n[team], 1);
+                            if (ps < HC) { lcol[ps] = col; lslot[ps] = (int16_t)h; }
+                            break;
+                        }
+                        if (old == col) break;
+                        if (probe == HS - 1) { h = -1; break; }
+                        h = (h + 1) & (HS - 1);
+                    }
+                }
+                // one add per product, issued together by the team
+                if (h >= 0) atomicAdd(&val[h], v);
+                wave_lds_sync();
+                if (s_n[team] > HC) { full = true; break; }
+            }
+        }
+        wave_lds_sync();
+        const int n = s_n[team];
+        if (n > HC) {
+            // more distinct columns than this table holds: a larger one redoes it
+            if (lane == 0) next[atomicAdd(nnext, 1)] = i;
+            wave_lds_sync();
+            continue;
+        }
+        const int64_t o = eoff[i];
+        for (int u = lane; u < n; u += T) {
+            const int32_t c = lcol[u];
+            int r = 0;
+            for (int w = 0; w < n; ++w) r += lcol[w] < c;
+            tcj[o + r] = c;
+            tcx[o + r] = val[lslot[u]];
+        }
+        if (lane == 0) cnt[i] = n;
+        wave_lds_sync();
+    }
+}
+
+template <int T, int HS, int BLOCK>
+static void spgemm_hacc(int32_t m, RowSrc src, unsigned grid, const int32_t *ap,
+                        const int32_t *aj, const double *ax, const int32_t *bp,
+                        const int32_t *bj, const double *bx, const int64_t *eoff, int32_t *cnt,
+                        int32_t *tcj, double *tcx, int32_t *next, int32_t *nnext,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_spgemm_hacc<T, HS, BLOCK>), dim3(grid), dim3(BLOCK), 0, s, m, src,
+                       ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, next, nnext);
     LAIR_LAUNCH_CHECK();
 }
 
-// Rows of A with more than 64 * 16 = 1024 entries are rejected (overflow).
-void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
-                   const double *ax, const int32_t *bp, const int32_t *bj,
-                   const double *bx, int32_t max_row_a, bool fill,
-                   int32_t *cnt, const int32_t *cp, int32_t *cj, double *cx,
-                   int32_t *overflow, hipStream_t s) {
+// Team size from the mean number of products per row.
+static int hacc_team(double mean_e) {
+    if (mean_e <= 16.0) return 8;
+    if (mean_e <= 48.0) return 16;
+    if (mean_e <= 128.0) return 32;
+    return 64;
+}
+
+constexpr int HACC_BIG = 4096;   // table of the one-team kernel
+
+void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
+                       int32_t *e, hipStream_t s) {
     if (m == 0) return;
-    if (max_row_a <= 16) spgemm_t<4, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
-    else if (max_row_a <= 32) spgemm_t<8, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
-    else if (max_row_a <= 64) spgemm_t<16, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
-    else if (max_row_a <= 128) spgemm_t<32, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
-    else if (max_row_a <= 256) spgemm_t<64, 4>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
-    else if (max_row_a <= 512) spgemm_t<64, 8>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
-    else spgemm_t<64, 16>(m, ap, aj, ax, bp, bj, bx, fill, cnt, cp, cj, cx, overflow, s);
+    hipLaunchKernelGGL(k_prod_count, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, ap, aj,
+                       bp, e);
+    LAIR_LAUNCH_CHECK();
+}
+
+void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
+                   const int32_t *bp, const int32_t *bj, const double *bx,
+                   const int64_t *eoff, int64_t max_e, double mean_e, int32_t *cnt,
+                   int32_t *tcj, double *tcx, int32_t *work, int32_t *overflow,
+                   hipStream_t s) {
+    if (m == 0) return;
+    int32_t *n1 = work, *n2 = work + 1, *l1 = work + 2, *l2 = work + 2 + m;
+    LAIR_HIP(hipMemsetAsync(work, 0, 2 * sizeof(int32_t), s));
+    const int T = hacc_team(mean_e);
+    const RowSrc all{nullptr, nullptr};
+    const unsigned g = blocks_for((int64_t)m * T, 256);
+    // tables of 2048 slots per block (30 KB of LDS)
+    int hc = 0;
+    switch (T) {
+        case 8:
+            spgemm_hacc<8, 64, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
+            hc = 32;
+            break;
+        case 16:
+            spgemm_hacc<16, 128, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
+            hc = 64;
+            break;
+        case 32:
+            spgemm_hacc<32, 256, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
+            hc = 128;
+            break;
+        default:
+            spgemm_hacc<64, 512, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
+            hc = 256;
+            break;
+    }
+    if (max_e <= hc) return;     // no row can have more distinct columns
+    // wider rows: one 64-lane team per block with a large table, then the merge
+    spgemm_hacc<64, HACC_BIG, 64>(m, RowSrc{l1, n1}, 2048, ap, aj, ax, bp, bj, bx, eoff, cnt,
+                                  tcj, tcx, l2, n2, s);
+    if (max_e <= HACC_BIG / 2) return;
+    hipLaunchKernelGGL((k_spgemm_merge<64, 16>), dim3(256), dim3(256), 0, s, RowSrc{l2, n2},
+                       ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, overflow);
+    LAIR_LAUNCH_CHECK();
+}
+
+// Copy the staged rows (at their product offsets) to C's rows.
+__global__ void k_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
+                                 const int32_t *tcj, const double *tcx, int32_t *cj,
+                                 double *cx) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(gt / 16);
+    const int lane = (int)(gt % 16);
+    if (i >= m) return;
+    const int64_t src = eoff[i];
+    const int32_t dst = crp[i], len = crp[i + 1] - dst;
+    for (int q = lane; q < len; q += 16) {
+        cj[dst + q] = tcj[src + q];
+        cx[dst + q] = tcx[src + q];
+    }
+}
+
+void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
+                           const int32_t *tcj, const double *tcx, int32_t *cj, double *cx,
+                           hipStream_t s) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_spgemm_compact, dim3(blocks_for((int64_t)m * 16, 256)), dim3(256), 0,
+                       s, m, eoff, crp, tcj, tcx, cj, cx);
+    LAIR_LAUNCH_CHECK();
 }
 
 // ===========================================================================

@@ -174,34 +174,49 @@ __global__ void k_block_diag_csr(int32_t nblk, int32_t k, const double *dinv,
 // C = A B with the symbolic pattern.  Returns the longest row of C.
 static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
                       DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
-    C.nrows = A.nrows;
+    (void)max_row_a;
+    const int32_t m = A.nrows;
+    C.nrows = m;
     C.ncols = B.ncols;
-    DevArr<int32_t> cnt, over;
-    cnt.alloc((size_t)A.nrows + 1, s);
+    DevArr<int32_t> cnt, over, work;
+    DevArr<int64_t> eoff;
+    cnt.alloc((size_t)m + 1, s);
+    eoff.alloc((size_t)m + 1, s);
     over.alloc(1, s);
+    work.alloc(2 + 2 * (size_t)m, s);
     LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
+    int64_t etot = 0, emax = 0;
     {
-        // symbolic pass: indices of A and of the rows of B, counts out
-        ProfScope ps("spgemm_count", s, 4.0 * (A.nnz + B.nnz) + 8.0 * (A.nrows + 1) +
-                                            4.0 * (B.nrows + 1));
-        launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                      B.v.get(), max_row_a, false, cnt.get(), nullptr, nullptr, nullptr,
-                      over.get(), s);
+        // products per row: A's indices and B's row pointers
+        ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
+                                            8.0 * (B.nrows + 1) + 12.0 * m);
+        launch_prod_count(m, A.rp.get(), A.cj.get(), B.rp.get(), cnt.get(), s);
+        etot = scan_counts_i64(cnt.get(), eoff.get(), m, s, tmp, &emax);
     }
-    C.rp.alloc((size_t)A.nrows + 1, s);
+    DevArr<int32_t> tcj;
+    DevArr<double> tcx;
+    tcj.alloc((size_t)std::max<int64_t>(etot, 1), s);
+    tcx.alloc((size_t)std::max<int64_t>(etot, 1), s);
+    {
+        // A, the rows of B and the rows of C each touched once
+        ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) +
+                                           4.0 * (B.nrows + 1));
+        launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
+                      B.v.get(), eoff.get(), emax, m ? (double)etot / m : 0.0, cnt.get(),
+                      tcj.get(), tcx.get(), work.get(), over.get(), s);
+    }
+    C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
     int32_t ov = 0;
-    C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), A.nrows, s, tmp, &mx, over.get(), &ov);
+    C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), m, s, tmp, &mx, over.get(), &ov);
     if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
+    C.max_row = (int32_t)mx;
     C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     {
-        // numeric pass: A, the rows of B and C each touched once
-        ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz + C.nnz) +
-                                           8.0 * (A.nrows + 1) + 4.0 * (B.nrows + 1));
-        launch_spgemm(A.nrows, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                      B.v.get(), max_row_a, true, nullptr, C.rp.get(), C.cj.get(), C.v.get(),
-                      over.get(), s);
+        ProfScope ps("spgemm_compact", s, 24.0 * C.nnz + 8.0 * (m + 1) + 4.0 * (m + 1));
+        launch_spgemm_compact(m, eoff.get(), C.rp.get(), tcj.get(), tcx.get(), C.cj.get(),
+                              C.v.get(), s);
     }
     return (int32_t)mx;
 }
@@ -434,6 +449,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                            n, pcol.get(), has.get());
         LAIR_LAUNCH_CHECK();
         P.nnz = scan_counts_i32(has.get(), P.rp.get(), n, s, tmp);
+        P.max_row = 1;
         P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         launch_compact_one_point(n, pcol.get(), P.rp.get(), P.cj.get(), P.v.get(), s);
@@ -446,7 +462,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                                  Lv.cf.get(), Lv.cidx.get(), false, pc.get(), nullptr, nullptr,
                                  nullptr, mean, s);
         }
-        P.nnz = scan_counts_i32(pc.get(), P.rp.get(), n, s, tmp);
+        int64_t pmax = 0;
+        P.nnz = scan_counts_i32(pc.get(), P.rp.get(), n, s, tmp, &pmax);
+        P.max_row = (int32_t)pmax;
         P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         {
@@ -576,16 +594,6 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
         fail(LAIR_EDEVICE, "no HIP device available");
-    {
-        // keep freed hierarchy memory in the stream-ordered pool
-        int dev = 0;
-        LAIR_HIP(hipGetDevice(&dev));
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t thr = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-        }
-    }
     std::unique_ptr<lair_hierarchy> h(new lair_hierarchy());
     h->str = *str;
     h->opt = *opt;
@@ -634,6 +642,7 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
     LAIR_HIP(hipMemcpyAsync(A.cj.get(), Ain->col, sizeof(int32_t) * nnz, kind, s));
     LAIR_HIP(hipMemcpyAsync(A.v.get(), Ain->val, sizeof(double) * nnz, kind, s));
     L0->max_row = validate_csr(n, nnz, A.rp.get(), A.cj.get(), A.v.get(), s);
+    A.max_row = L0->max_row;
 
     if (opt->block_size > 0) {
         int32_t k = opt->block_size;
@@ -1136,9 +1145,12 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
     const int32_t ns = h->nsys;
     const int64_t n = L0.n;
     bool mixed = h->opt.precision == LAIR_MIXED;
-    h->seg_norm.alloc((size_t)ns, s);
-    h->active_dev.alloc((size_t)ns, s);
-    if (!mixed) h->e64.alloc((size_t)n, s);
+    // grow-only: captured iterations keep these addresses
+    bool moved = false;
+    if (h->seg_norm.get() == nullptr) { h->seg_norm.alloc((size_t)ns, s); moved = true; }
+    if (h->active_dev.get() == nullptr) { h->active_dev.alloc((size_t)ns, s); moved = true; }
+    if (!mixed && h->e64.get() == nullptr) { h->e64.alloc((size_t)n, s); moved = true; }
+    if (moved) h->drop_graphs();
     const double *bb = b;
     if (h->opt.block_size > 0) {
         op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
@@ -1546,10 +1558,15 @@ lair_status lair_export(const lair_hierarchy *h, int32_t level, int32_t what,
 void lair_free(lair_hierarchy *h) {
     if (!h) return;
     try {
+        // the memory goes back to the allocator's cache: wait for every
+        // launch that may still read it
+        (void)hipDeviceSynchronize();
         delete h;
     } catch (...) {
     }
 }
+
+void lair_trim(void) { dev_trim(); }
 
 const char *lair_status_string(lair_status s) {
     switch (s) {

@@ -39,6 +39,13 @@ void set_last_error(const std::string &m);
 // ---------------------------------------------------------------------------
 // Stream-ordered device array, freed on the stream it was allocated on.
 // ---------------------------------------------------------------------------
+// Caching device allocator (alloc.cpp): blocks released on a stream are
+// reused by later requests on the same stream.
+void *dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s) noexcept;
+void dev_trim() noexcept;
+size_t dev_cached_bytes() noexcept;
+
 template <class T>
 struct DevArr {
     T *p = nullptr;
@@ -61,7 +68,7 @@ struct DevArr {
         std::swap(s, o.s);
     }
     void release() noexcept {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p) dev_free(p, s);
         p = nullptr;
         n = 0;
     }
@@ -70,13 +77,12 @@ struct DevArr {
         s = stream;
         n = count;
         if (count == 0) return;
-        hipError_t e = hipMallocAsync((void **)&p, count * sizeof(T), stream);
-        if (e != hipSuccess) {
+        try {
+            p = (T *)dev_alloc(count * sizeof(T), stream);
+        } catch (...) {
             p = nullptr;
             n = 0;
-            fail(e == hipErrorOutOfMemory ? LAIR_ENOMEM : LAIR_EDEVICE,
-                 "device allocation of %zu bytes failed: %s",
-                 count * sizeof(T), hipGetErrorString(e));
+            throw;
         }
     }
     void ensure(size_t count, hipStream_t stream) {
@@ -109,6 +115,7 @@ void *pinned_staging(size_t bytes);
 struct DevCSR {
     int32_t nrows = 0, ncols = 0;
     int64_t nnz = 0;
+    int32_t max_row = -1;  // longest row when known, else -1
     DevArr<int32_t> rp, cj;
     DevArr<double> v;
     DevArr<float> v32;    // float copy of the values (mixed precision)
@@ -152,6 +159,8 @@ inline int team_for_mean(double mean_len) {
 // exclusive scan of f(i) for i < n into out[0..n], returns out[n]
 // optionally also returns the largest count and copies a device flag back
 // in the same synchronisation
+int64_t scan_counts_i64(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t s,
+                        DevArr<int64_t> &tmp, int64_t *max_out = nullptr);
 int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
                         hipStream_t s, DevArr<int64_t> &tmp,
                         int64_t *max_out = nullptr, const int32_t *flag = nullptr,
@@ -198,12 +207,21 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
                           const int8_t *cf, const int32_t *cidx, bool fill,
                           int32_t *cnt, const int32_t *prp, int32_t *pcj,
                           double *pv, double mean_len, hipStream_t s);
-// C = A B (symbolic pattern).  Count pass when fill is false.
-void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj,
-                   const double *ax, const int32_t *bp, const int32_t *bj,
-                   const double *bx, int32_t max_row_a, bool fill,
-                   int32_t *cnt, const int32_t *cp, int32_t *cj, double *cx,
-                   int32_t *overflow, hipStream_t s);
+// C = A B in three steps: launch_prod_count gives the products of every row
+// (an upper bound of its length); launch_spgemm writes each row of C,
+// sorted, at its product offset eoff[i] of the staging arrays (tcj, tcx)
+// and its length into cnt; launch_spgemm_compact copies the rows to C
+// (row pointers crp from a scan of cnt).  work: 2 + 2 m int32.
+void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
+                       int32_t *e, hipStream_t s);
+void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
+                   const int32_t *bp, const int32_t *bj, const double *bx,
+                   const int64_t *eoff, int64_t max_e, double mean_e, int32_t *cnt,
+                   int32_t *tcj, double *tcx, int32_t *work, int32_t *overflow,
+                   hipStream_t s);
+void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
+                           const int32_t *tcj, const double *tcx, int32_t *cj, double *cx,
+                           hipStream_t s);
 void launch_transpose(int32_t nrows, int32_t ncols, int64_t nnz,
                       const int32_t *rp, const int32_t *cj, const double *v,
                       int32_t *tcount, int32_t *trp, int32_t *tcj, double *tv,

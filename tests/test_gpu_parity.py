@@ -170,8 +170,11 @@ def test_multi_rhs_equals_single(lair):
 
 # ------------------------------------------------------------------- special cases
 
-def test_all_f_neighbourhood_is_ideal(lair):
-    w = W.random_ff_digraph(90, 4, 17)
+@pytest.mark.parametrize("n", [90, 300])
+def test_all_f_neighbourhood_is_ideal(lair, n):
+    # n = 300 puts ~3000 products in a row of R (A P): the product's widest
+    # staging kernel and its row-merge fallback both run
+    w = W.random_ff_digraph(n, 4, 17)
     A = O.csr(w["rowptr"], w["col"], w["val"])
     h = lair.setup(w["rowptr"], w["col"], w["val"], distance="all_f", max_coarse=8,
                    max_levels=2)
@@ -182,7 +185,7 @@ def test_all_f_neighbourhood_is_ideal(lair):
     C = np.flatnonzero(cf == 1)
     Zi = -D[np.ix_(C, F)] @ np.linalg.inv(D[np.ix_(F, F)])
     rrp, rcj, rv = (h.export(0, k) for k in ("R.rowptr", "R.col", "R.val"))
-    Rg = sp.csr_matrix((rv, rcj, rrp), shape=(C.shape[0], 90)).toarray()
+    Rg = sp.csr_matrix((rv, rcj, rrp), shape=(C.shape[0], n)).toarray()
     assert np.abs(Rg[:, F] - Zi).max() <= 1e-11 * np.abs(Zi).max()
 
 
