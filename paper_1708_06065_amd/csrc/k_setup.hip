@@ -175,20 +175,27 @@ int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
 // 4 columns not strictly increasing, 8 non-finite value, 16 zero diagonal,
 // 32 missing diagonal.  stat[1] receives the longest row.
 // ===========================================================================
+// Team of VT lanes per row (lanes take every VT-th entry); each block
+// writes its error bits and longest row to part[2 b], part[2 b + 1], and one
+// block combines the partials (no contended atomics).
+constexpr int VT = 8;
+
 __global__ void __launch_bounds__(256)
 k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cj,
-           const double *v, int32_t *stat) {
+           const double *v, int32_t *part) {
     __shared__ int se[256], sm[256];
-    int64_t i = xcd_block_id() * blockDim.x + threadIdx.x;
-    if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(stat, 1);
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int64_t i = gt / VT;
+    const int lane = (int)(gt % VT);
     int err = 0, len = 0;
+    if (gt == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) err = 1;
     if (i < n) {
         int64_t lo = rp[i], hi = rp[i + 1];
         if (lo < 0 || hi < lo || hi > nnz) {
             err = 1;
         } else {
             bool diag = false;
-            for (int64_t p = lo; p < hi; ++p) {
+            for (int64_t p = lo + lane; p < hi; p += VT) {
                 int c = cj[p];
                 if (c < 0 || c >= n) err |= 2;
                 if (p > lo && c <= cj[p - 1]) err |= 4;
@@ -196,9 +203,11 @@ k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cj,
                 if (!isfinite(a)) err |= 8;
                 if (c == i) { diag = true; if (a == 0.0) err |= 16; }
             }
-            if (!diag) err |= 32;
+            if (team_bits<VT>(diag) == 0 && lane == 0) err |= 32;
             len = (int)(hi - lo);
         }
+    } else {
+        (void)team_bits<VT>(false);
     }
     se[threadIdx.x] = err;
     sm[threadIdx.x] = len;
@@ -211,19 +220,43 @@ k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cj,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        if (se[0]) atomicOr(stat, se[0]);
-        atomicMax(stat + 1, sm[0]);
+        part[2 * blockIdx.x] = se[0];
+        part[2 * blockIdx.x + 1] = sm[0];
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_validate_final(const int32_t *part, int64_t nb, int32_t *stat) {
+    __shared__ int se[256], sm[256];
+    int e = 0, m = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) {
+        e |= part[2 * b];
+        m = max(m, part[2 * b + 1]);
+    }
+    se[threadIdx.x] = e;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            se[threadIdx.x] |= se[threadIdx.x + o];
+            sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { stat[0] = se[0]; stat[1] = sm[0]; }
 }
 
 int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
                      const int32_t *cj, const double *v, hipStream_t s) {
+    const unsigned nb = blocks_for(n * VT, 256);
     DevArr<int32_t> st;
-    st.alloc(2, s);
-    LAIR_HIP(hipMemsetAsync(st.get(), 0, 2 * sizeof(int32_t), s));
+    st.alloc(2 + 2 * (size_t)nb, s);
     ProfScope ps("validate", s, 12.0 * nnz + 4.0 * (n + 1));
-    hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       n, nnz, rp, cj, v, st.get());
+    hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, s, n, nnz, rp, cj, v,
+                       st.get() + 2);
+    LAIR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_validate_final, dim3(1), dim3(256), 0, s, st.get() + 2, (int64_t)nb,
+                       st.get());
     LAIR_LAUNCH_CHECK();
     int32_t h[2];
     {
@@ -280,7 +313,7 @@ static void strength_t(int32_t n, const int32_t *rp, const int32_t *cj,
 void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
                      const double *v, double theta, int32_t kind,
                      uint8_t *smask, double mean_len, hipStream_t s) {
-    int t = team_for_mean(mean_len);
+    int t = team_for_mean(mean_len / 2.0);
     double nnz = mean_len * n;
     ProfScope ps("strength", s, 13.0 * nnz + 4.0 * (n + 1));
     switch (t) {
@@ -327,16 +360,43 @@ k_cf_lists(int32_t n, const int8_t *cf, const int32_t *scan, const int32_t *rp,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicAdd(acc, sf[0]);
-        atomicAdd(acc + 1, sc[0]);
+        acc[2 * blockIdx.x] = sf[0];
+        acc[2 * blockIdx.x + 1] = sc[0];
     }
 }
 
+// Fixed-order sum of nb pairs of block partials into out[0], out[1].
+__global__ void __launch_bounds__(256)
+k_sum_pairs(const unsigned long long *part, int64_t nb, unsigned long long *out) {
+    __shared__ unsigned long long s0[256], s1[256];
+    unsigned long long a = 0, b = 0;
+    for (int64_t k = threadIdx.x; k < nb; k += 256) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s0[threadIdx.x] += s0[threadIdx.x + o];
+            s1[threadIdx.x] += s1[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = s0[0]; out[1] = s1[0]; }
+}
+
+// acc: 2 + 2 * ceil(n / 256) entries; acc[0], acc[1] receive the entries of
+// the F rows and of the C rows.
 void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
                      const int32_t *rp, int32_t *cidx, int32_t *clist,
                      int32_t *flist, unsigned long long *acc, hipStream_t s) {
-    hipLaunchKernelGGL(k_cf_lists, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       n, cf, cidx_scan, rp, cidx, clist, flist, acc);
+    const unsigned nb = blocks_for(n, 256);
+    hipLaunchKernelGGL(k_cf_lists, dim3(nb), dim3(256), 0, s,
+                       n, cf, cidx_scan, rp, cidx, clist, flist, acc + 2);
+    LAIR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, acc + 2, (int64_t)nb, acc);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -1506,16 +1566,20 @@ struct RowSrc {
     const int32_t *nlist;
 };
 
-__global__ void k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj,
-                             const int32_t *bp, int32_t *e) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256)
+k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp, int32_t *e) {
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(gt / 8);
+    const int lane = (int)(gt % 8);
     if (i >= m) return;
     int64_t t = 0;
-    for (int p = ap[i]; p < ap[i + 1]; ++p) {
+    for (int p = ap[i] + lane; p < ap[i + 1]; p += 8) {
         int k = aj[p];
         t += bp[k + 1] - bp[k];
     }
-    e[i] = (int32_t)min<int64_t>(t, INT32_MAX);
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) t += __shfl_xor(t, o, 8);
+    if (lane == 0) e[i] = (int32_t)min<int64_t>(t, INT32_MAX);
 }
 
 template <int T, int LPL>
@@ -1736,8 +1800,8 @@ constexpr int HACC_BIG = 4096;   // table of the one-team kernel
 void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
                        int32_t *e, hipStream_t s) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_prod_count, dim3(blocks_for(m, 256)), dim3(256), 0, s, m, ap, aj,
-                       bp, e);
+    hipLaunchKernelGGL(k_prod_count, dim3(blocks_for((int64_t)m * 8, 256)), dim3(256), 0, s, m,
+                       ap, aj, bp, e);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -1782,17 +1846,19 @@ void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double
     LAIR_LAUNCH_CHECK();
 }
 
-// Copy the staged rows (at their product offsets) to C's rows.
-__global__ void k_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
-                                 const int32_t *tcj, const double *tcx, int32_t *cj,
-                                 double *cx) {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t i = (int32_t)(gt / 16);
-    const int lane = (int)(gt % 16);
+// Copy the staged rows (at their product offsets) to C's rows, a team of T
+// lanes per row.
+template <int T>
+__global__ void __launch_bounds__(256)
+k_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp, const int32_t *tcj,
+                 const double *tcx, int32_t *cj, double *cx) {
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(gt / T);
+    const int lane = (int)(gt % T);
     if (i >= m) return;
     const int64_t src = eoff[i];
     const int32_t dst = crp[i], len = crp[i + 1] - dst;
-    for (int q = lane; q < len; q += 16) {
+    for (int q = lane; q < len; q += T) {
         cj[dst + q] = tcj[src + q];
         cx[dst + q] = tcx[src + q];
     }
@@ -1800,10 +1866,21 @@ __global__ void k_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *
 
 void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
                            const int32_t *tcj, const double *tcx, int32_t *cj, double *cx,
-                           hipStream_t s) {
+                           double mean_c, hipStream_t s) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_spgemm_compact, dim3(blocks_for((int64_t)m * 16, 256)), dim3(256), 0,
-                       s, m, eoff, crp, tcj, tcx, cj, cx);
+    const int t = team_for_mean(mean_c / 2.0);
+#define LAIR_CP(TT)                                                                      \
+    hipLaunchKernelGGL(k_spgemm_compact<TT>, dim3(blocks_for((int64_t)m * TT, 256)),     \
+                       dim3(256), 0, s, m, eoff, crp, tcj, tcx, cj, cx)
+    switch (t) {
+        case 2: LAIR_CP(2); break;
+        case 4: LAIR_CP(4); break;
+        case 8: LAIR_CP(8); break;
+        case 16: LAIR_CP(16); break;
+        case 32: LAIR_CP(32); break;
+        default: LAIR_CP(64); break;
+    }
+#undef LAIR_CP
     LAIR_LAUNCH_CHECK();
 }
 

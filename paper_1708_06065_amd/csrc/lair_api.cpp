@@ -216,7 +216,7 @@ static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
     {
         ProfScope ps("spgemm_compact", s, 24.0 * C.nnz + 8.0 * (m + 1) + 4.0 * (m + 1));
         launch_spgemm_compact(m, eoff.get(), C.rp.get(), tcj.get(), tcx.get(), C.cj.get(),
-                              C.v.get(), s);
+                              C.v.get(), m ? (double)C.nnz / m : 1.0, s);
     }
     return (int32_t)mx;
 }
@@ -369,8 +369,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.flist.alloc((size_t)std::max(Lv.nf, 1), s);
     {
         DevArr<unsigned long long> acc;
-        acc.alloc(2, s);
-        LAIR_HIP(hipMemsetAsync(acc.get(), 0, 2 * sizeof(unsigned long long), s));
+        acc.alloc(2 + 2 * (size_t)blocks_for(n, 256), s);
         ProfScope ps("cf_lists", s, 13.0 * n + 4.0 * n);
         launch_cf_lists(n, Lv.cf.get(), scan.get(), A.rp.get(), Lv.cidx.get(), Lv.clist.get(),
                         Lv.flist.get(), acc.get(), s);

@@ -221,7 +221,7 @@ void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double
                    hipStream_t s);
 void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
                            const int32_t *tcj, const double *tcx, int32_t *cj, double *cx,
-                           hipStream_t s);
+                           double mean_c, hipStream_t s);
 void launch_transpose(int32_t nrows, int32_t ncols, int64_t nnz,
                       const int32_t *rp, const int32_t *cj, const double *v,
                       int32_t *tcount, int32_t *trp, int32_t *tcj, double *tv,
