@@ -81,6 +81,151 @@ __device__ __forceinline__ void row_accM(int lo, int hi, int q, int diag_col,
     }
 }
 
+// NR interleaved right-hand sides held VW to a lane as one 16-byte vector
+// (4 floats or 2 doubles): L = NR / VW lanes per row, so a wave covers 64 / L
+// rows.  The L lanes load L consecutive entries of the row, broadcast them by
+// shuffles, and each lane gathers its VW values of every neighbour with one
+// vector load.  Pointers must be 16-byte aligned (checked by the launchers).
+template <class VT, int VW> struct VecT;
+template <> struct VecT<float, 4> { using T = float4; };
+template <> struct VecT<float, 2> { using T = float2; };
+template <> struct VecT<double, 2> { using T = double2; };
+
+template <class VT, int VW>
+struct Pack {
+    VT v[VW];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) v[k] = (VT)0;
+    }
+    __device__ __forceinline__ void load(const VT *p) {
+        typename VecT<VT, VW>::T t = *reinterpret_cast<const typename VecT<VT, VW>::T *>(p);
+        const VT *q = reinterpret_cast<const VT *>(&t);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) v[k] = q[k];
+    }
+    __device__ __forceinline__ void store(VT *p) const {
+        typename VecT<VT, VW>::T t;
+        VT *q = reinterpret_cast<VT *>(&t);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) q[k] = v[k];
+        *reinterpret_cast<typename VecT<VT, VW>::T *>(p) = t;
+    }
+};
+
+// A team of T = G L lanes per row (G a power of two chosen from the row
+// length): the team loads T consecutive entries, group g of L lanes takes
+// entries g L .. g L + L - 1 of them, and the G partial sums are added by
+// shuffles at the end.
+template <class VT, int NR, int VW, bool SEL>
+__device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_col,
+                                         const int32_t *cj, const VT *v,
+                                         const VT *xF, const VT *xC,
+                                         const int8_t *cf, Pack<VT, VW> &acc, VT &d) {
+    constexpr int L = NR / VW;
+    const int q = t % L;
+    for (int base = lo; base < hi; base += T) {
+        int p = base + t;
+        int c = -1;
+        VT a = (VT)0;
+        if (p < hi) { c = cj[p]; a = v[p]; }
+        int ce[L];
+        VT ae[L];
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+            ce[e] = __shfl(c, e, L);
+            ae[e] = __shfl(a, e, L);
+        }
+        Pack<VT, VW> xe[L];
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+            if (ce[e] >= 0) {
+                const VT *src = SEL ? (cf[ce[e]] ? xC : xF) : xF;
+                xe[e].load(src + (int64_t)ce[e] * NR + q * VW);
+            } else {
+                xe[e].zero();
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+#pragma unroll
+            for (int k = 0; k < VW; ++k) acc.v[k] += ae[e] * xe[e].v[k];
+            if (ce[e] == diag_col) d = ae[e];
+        }
+    }
+    for (int o = L; o < T; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) acc.v[k] += __shfl_xor(acc.v[k], o);
+        d += __shfl_xor(d, o);
+    }
+}
+
+template <class VT, int NR, int VW, int MODE>
+__global__ void __launch_bounds__(256)
+k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *v,
+          const VT *x, const VT *b, VT *y) {
+    constexpr int L = NR / VW;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)(gt / T);
+    int t = (int)(gt % T);
+    if (i >= nrows) return;
+    Pack<VT, VW> acc;
+    acc.zero();
+    VT d = (VT)0;
+    row_accV<VT, NR, VW, false>(rp[i], rp[i + 1], t, T, -1, cj, v, x, x, nullptr, acc, d);
+    if (t >= L) return;
+    const int64_t o = (int64_t)i * NR + t * VW;
+    Pack<VT, VW> out;
+    if (MODE == MODE_RESID) {
+        out.load(b + o);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) out.v[k] -= acc.v[k];
+    } else if (MODE == MODE_ADD) {
+        out.load(y + o);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) out.v[k] += acc.v[k];
+    } else {
+        out = acc;
+    }
+    out.store(y + o);
+}
+
+template <class VT, int NR, int VW, bool SEL>
+__global__ void __launch_bounds__(256)
+k_jacobiV(int32_t nx, int T, const int32_t *rows, const int32_t *rp, const int32_t *cj,
+          const VT *v, const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
+          VT *out, int compact, VT omega) {
+    constexpr int L = NR / VW;
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    int32_t k = (int32_t)(gt / T);
+    int t = (int)(gt % T);
+    if (k >= nx) return;
+    int32_t i = rows[k];
+    Pack<VT, VW> acc;
+    acc.zero();
+    VT d = (VT)0;
+    row_accV<VT, NR, VW, SEL>(rp[i], rp[i + 1], t, T, i, cj, v, xF, xC, cf, acc, d);
+    if (t >= L) return;
+    const int64_t oi = (int64_t)i * NR + t * VW;
+    Pack<VT, VW> xi, bi, r;
+    xi.load((SEL ? (cf[i] ? xC : xF) : xF) + oi);
+    bi.load(b + oi);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) r.v[e] = xi.v[e] + omega * (bi.v[e] - acc.v[e]) / d;
+    r.store(out + (compact ? (int64_t)k * NR + t * VW : oi));
+}
+
+// Lanes per row for the vector kernels: L = nrhs / VW, times G groups so
+// that a team covers about half of a mean row per step (team: the matrix's
+// single-vector team, a power of two >= its mean row length).
+static inline int vec_team(int L, int team) {
+    int g = 1;
+    while (g * L * 2 < team && g * L < 64) g <<= 1;
+    return g * L;
+}
+
+static inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 template <class VT, int T, int MODE>
 __global__ void __launch_bounds__(256)
 k_rowdot1(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
@@ -119,6 +264,26 @@ template <class VT, int MODE>
 static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
                    int32_t nrhs, hipStream_t s) {
     if (A.nrows == 0) return;
+    if (nrhs > 1 && aligned16(x) && aligned16(y) && (!b || aligned16(b))) {
+        constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
+#define LAIR_RV(NN, WW)                                                           \
+    {                                                                             \
+        const int T = vec_team(NN / WW, A.team);                                  \
+        hipLaunchKernelGGL((k_rowdotV<VT, NN, WW, MODE>),                         \
+                           dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, y);                 \
+    }
+        switch (nrhs) {
+            case 2: LAIR_RV(2, 2); break;
+            case 4: LAIR_RV(4, VW); break;
+            case 8: LAIR_RV(8, VW); break;
+            case 16: LAIR_RV(16, VW); break;
+            default: LAIR_RV(32, VW); break;
+        }
+#undef LAIR_RV
+        LAIR_LAUNCH_CHECK();
+        return;
+    }
     if (nrhs > 1) {
 #define LAIR_RM(NN)                                                               \
     hipLaunchKernelGGL((k_rowdotM<VT, NN, MODE>),                                 \
@@ -211,6 +376,26 @@ template <class VT, bool SEL>
 static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
                           const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
                           VT *out, int compact, VT om, int32_t nrhs, hipStream_t s) {
+    if (nrhs > 1 && aligned16(b) && aligned16(xF) && aligned16(xC) && aligned16(out)) {
+        constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
+#define LAIR_JV(NN, WW)                                                           \
+    {                                                                             \
+        const int T = vec_team(NN / WW, A.team);                                  \
+        hipLaunchKernelGGL((k_jacobiV<VT, NN, WW, SEL>),                          \
+                           dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s, \
+                           nx, T, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om); \
+    }
+        switch (nrhs) {
+            case 2: LAIR_JV(2, 2); break;
+            case 4: LAIR_JV(4, VW); break;
+            case 8: LAIR_JV(8, VW); break;
+            case 16: LAIR_JV(16, VW); break;
+            default: LAIR_JV(32, VW); break;
+        }
+#undef LAIR_JV
+        LAIR_LAUNCH_CHECK();
+        return;
+    }
     if (nrhs > 1) {
 #define LAIR_JM(NN)                                                               \
     hipLaunchKernelGGL((k_jacobiM<VT, NN, SEL>),                                  \

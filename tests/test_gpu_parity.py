@@ -166,6 +166,18 @@ def test_multi_rhs_equals_single(lair):
         assert np.abs(x1.cpu().numpy() - Xh[:, q]).max() <= 1e-9 * np.abs(Xh[:, q]).max()
         r = w["rhs"][:, q] - A @ Xh[:, q]
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(w["rhs"][:, q])
+    # right-hand sides and solution at an 8-byte offset (not 16-byte aligned):
+    # the library takes its scalar-lane kernels; same iteration, same answer
+    n = w["n"]
+    flat_b = torch.zeros(n * 16 + 1, dtype=torch.float64, device="cuda")
+    flat_x = torch.zeros(n * 16 + 1, dtype=torch.float64, device="cuda")
+    Bu = flat_b[1:].view(n, 16)
+    Xu = flat_x[1:].view(n, 16)
+    Bu.copy_(B)
+    assert Bu.data_ptr() % 16 == 8
+    _, iu = h.solve(Bu, Xu, rtol=1e-10)
+    assert iu["iters"] == info["iters"]
+    assert np.abs(Xu.cpu().numpy() - Xh).max() <= 1e-12 * np.abs(Xh).max()
 
 
 # ------------------------------------------------------------------- special cases
