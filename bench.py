@@ -222,13 +222,17 @@ def main():
             X, info = h.solve(B, rtol=1e-10, maxit=100)
         return h, X, info
 
-    # which kernel category dominates a step (one profiled, untimed step)
+    # which kernel category dominates a step: one profiled, untimed step
+    # after a warm-up step (so that first-use allocations are not in it)
+    h, X, info = step("mixed")
+    h.free()
     lair.profile_begin(None)
     h, X, info = step("mixed")
     torch.cuda.synchronize()
     prof_all = lair.profile_end()
     h.free()
     dominant = max(prof_all.items(), key=lambda kv: kv[1]["ms"])[0]
+    log("profiled step, per category:", json.dumps(prof_all))
     log("per-category GPU time of one mixed step (ms):",
         json.dumps({k: round(v["ms"], 3) for k, v in sorted(prof_all.items(),
                                                               key=lambda kv: -kv[1]["ms"])}))

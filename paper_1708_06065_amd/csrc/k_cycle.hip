@@ -87,6 +87,7 @@ __device__ __forceinline__ void row_accM(int lo, int hi, int q, int diag_col,
 // shuffles, and each lane gathers its VW values of every neighbour with one
 // vector load.  Pointers must be 16-byte aligned (checked by the launchers).
 template <class VT, int VW> struct VecT;
+template <> struct VecT<double, 1> { using T = double; };
 template <> struct VecT<float, 4> { using T = float4; };
 template <> struct VecT<float, 2> { using T = float2; };
 template <> struct VecT<double, 2> { using T = double2; };
@@ -222,6 +223,56 @@ static inline int vec_team(int L, int team) {
     int g = 1;
     while (g * L * 2 < team && g * L < 64) g <<= 1;
     return g * L;
+}
+
+// Outer residual of the double iteration fused with its norms and the
+// float copy for the cycle: r = b - A x for every row (teams as above,
+// grid-stride over a fixed grid), written as r64 and/or r32, and each
+// block's sum of r^2 per right-hand side into partial[block][nrhs]
+// (fixed order: thread sums, then a fixed walk over the block's threads).
+template <int NR, int VW, bool OUT64, bool OUT32>
+__global__ void __launch_bounds__(256)
+k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const double *v,
+             const double *x, const double *b, double *r64, float *r32, double *partial) {
+    constexpr int L = NR / VW;
+    __shared__ double sh[256 * VW];
+    const int t = (int)(threadIdx.x % T);
+    const int64_t team0 = ((int64_t)xcd_block_id() * blockDim.x + threadIdx.x) / T;
+    const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / T);
+    double sq[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) sq[k] = 0.0;
+    for (int64_t i = team0; i < nrows; i += nteams) {
+        Pack<double, VW> acc;
+        acc.zero();
+        double d = 0.0;
+        row_accV<double, NR, VW, false>(rp[i], rp[i + 1], t, T, -1, cj, v, x, x, nullptr,
+                                        acc, d);
+        if (t < L) {
+            const int64_t o = i * NR + t * VW;
+            Pack<double, VW> r;
+            r.load(b + o);
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                r.v[k] -= acc.v[k];
+                sq[k] += r.v[k] * r.v[k];
+            }
+            if (OUT64) r.store(r64 + o);
+            if (OUT32) {
+#pragma unroll
+                for (int k = 0; k < VW; ++k) r32[o + k] = (float)r.v[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < VW; ++k) sh[threadIdx.x * VW + k] = sq[k];
+    __syncthreads();
+    if ((int)threadIdx.x < NR) {
+        const int lane = threadIdx.x / VW, k = threadIdx.x % VW;
+        double a = 0.0;
+        for (int th = lane; th < (int)blockDim.x; th += T) a += sh[th * VW + k];
+        partial[(int64_t)blockIdx.x * NR + threadIdx.x] = a;
+    }
 }
 
 static inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -655,6 +706,47 @@ void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
     LAIR_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, nblk, nrhs, out);
     LAIR_LAUNCH_CHECK();
+}
+
+template <int NR, int VW>
+static void resid_norm_t(const CsrView<double> &A, const double *b, const double *x,
+                         double *r64, float *r32, double *partial, unsigned grid, int T,
+                         hipStream_t s) {
+    if (r64 && r32)
+        hipLaunchKernelGGL((k_resid_norm<NR, VW, true, true>), dim3(grid), dim3(256), 0, s,
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
+    else if (r64)
+        hipLaunchKernelGGL((k_resid_norm<NR, VW, true, false>), dim3(grid), dim3(256), 0, s,
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
+    else
+        hipLaunchKernelGGL((k_resid_norm<NR, VW, false, true>), dim3(grid), dim3(256), 0, s,
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
+    LAIR_LAUNCH_CHECK();
+}
+
+bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x,
+                      double *r64, float *r32, int32_t nrhs, double *partial,
+                      int32_t npartial, double *out, hipStream_t s) {
+    if (A.nrows == 0 || (!r64 && !r32)) return false;
+    const int VW = nrhs == 1 ? 1 : 2;
+    if (VW == 2 && !(aligned16(b) && aligned16(x) && (!r64 || aligned16(r64))))
+        return false;
+    const int L = nrhs / VW;
+    const int T = vec_team(L, A.team);
+    int64_t blocks = ((int64_t)A.nrows * T + 255) / 256;
+    unsigned grid = (unsigned)(blocks < npartial ? (blocks < 1 ? 1 : blocks) : npartial);
+    switch (nrhs) {
+        case 1: resid_norm_t<1, 1>(A, b, x, r64, r32, partial, grid, T, s); break;
+        case 2: resid_norm_t<2, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
+        case 4: resid_norm_t<4, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
+        case 8: resid_norm_t<8, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
+        case 16: resid_norm_t<16, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
+        default: resid_norm_t<32, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
+    }
+    hipLaunchKernelGGL(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, (int32_t)grid,
+                       nrhs, out);
+    LAIR_LAUNCH_CHECK();
+    return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -1057,14 +1057,26 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     CsrView<double> A0 = transpose ? view<double>(L0.At, L0.team_At)
                                    : view<double>(L0.A, L0.team_A);
     const DevCSR &M0 = transpose ? L0.At : L0.A;
+    bool mixed = h->opt.precision == LAIR_MIXED && !transpose;
+    // fused residual + norms (+ float copy in mixed precision) unless the
+    // caller's vectors are not 16-byte aligned
+    const bool fused = nrhs == 1 || (((uintptr_t)bb | (uintptr_t)x) & 15u) == 0;
     auto residual_and_norms = [&](hipStream_t st) {
+        if (fused) {
+            ProfScope ps("residual", st, ab_rowdot(M0, 8, nrhs, 1) + (mixed ? 4.0 : 8.0) *
+                         nrhs * (double)M0.nrows, 2.0 * M0.nnz * nrhs);
+            if (!op_residual_norm(A0, bb, x, mixed ? nullptr : h->r0.get(),
+                                  mixed ? h->r0_32.get() : nullptr, nrhs, h->partial.get(),
+                                  NPARTIAL, h->norms.get(), st))
+                fail(LAIR_EDEVICE, "fused residual not applicable");
+            return;
+        }
         {
             ProfScope ps("residual", st, ab_rowdot(M0, 8, nrhs, 2), 2.0 * M0.nnz * nrhs);
             op_residual<double>(A0, bb, x, h->r0.get(), nrhs, st);
         }
         sumsq_dev(h, h->r0.get(), nrhs, st);
     };
-    bool mixed = h->opt.precision == LAIR_MIXED && !transpose;
     residual_and_norms(s);
     read_norms(h->norms.get(), nrhs, s, rn);
     r_first = rn;
@@ -1094,7 +1106,7 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
             });
         } else {
             run_iteration(h, IT_MIXED, nrhs, bb, x, s, [&](hipStream_t st) {
-                {
+                if (!fused) {
                     ProfScope ps("cast", st, 12.0 * n * nrhs);
                     op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, st);
                 }

@@ -279,6 +279,12 @@ void op_dense_solve(int32_t n, const double *lu, const int32_t *piv,
                     const VT *b, VT *x, int32_t nrhs, bool transpose,
                     hipStream_t s);
 // per right-hand side sum of squares into out[0..nrhs) (double, fixed order)
+// r = b - A x with its per-column sums of squares (out, nrhs entries) in one
+// pass, written as r64 and/or r32.  Returns false (nothing launched) when the
+// vectors are not 16-byte aligned for nrhs > 1.  partial: npartial * nrhs.
+bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x,
+                      double *r64, float *r32, int32_t nrhs, double *partial,
+                      int32_t npartial, double *out, hipStream_t s);
 void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
               int32_t npartial, double *out, hipStream_t s);
 void op_axpy_f32(double *x, const float *e, int64_t n, hipStream_t s);
