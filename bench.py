@@ -39,6 +39,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 
 
+def measured_traffic(workload, category):
+    """HBM bytes per launch of a kernel category from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record, or None when there is none for
+    this workload and category or the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, category))
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    for f, sha in rec.get("source_sha256", {}).items():
+        fp = os.path.join(ROOT, f)
+        if not os.path.exists(fp) or hashlib.sha256(open(fp, "rb").read()).hexdigest() != sha:
+            return None
+    return rec["fetch"]["bytes_per_launch"] + rec["write"]["bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -280,7 +296,8 @@ def main():
     d = prof_timed.get(dominant, {"launches": 0, "ms": 1.0, "alg_bytes": 0.0})
     achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant,
                 "launches": d["launches"], "avg_launch_us": 1e3 * d["ms"] / max(d["launches"], 1),
                 "alg_bytes_per_launch": d["alg_bytes"] / max(d["launches"], 1)}
     out = {

@@ -50,7 +50,7 @@ k_union_gather(int32_t nsys, const SysCsr *sys, const int64_t *seg, const int64_
 void launch_union_gather(int32_t nsys, const SysCsr *sys, const int64_t *seg,
                          const int64_t *nzo, int32_t *rp, int32_t *cj, double *v, int32_t *bad,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_union_gather, dim3(nsys), dim3(256), 0, s, nsys, sys, seg, nzo, rp,
+    LAIR_LAUNCH(k_union_gather, dim3(nsys), dim3(256), 0, s, nsys, sys, seg, nzo, rp,
                        cj, v, bad);
     LAIR_LAUNCH_CHECK();
 }
@@ -73,7 +73,7 @@ k_seg_count_c(const int64_t *seg, const int8_t *cf, int32_t *count) {
 
 void launch_seg_count_c(int32_t nsys, const int64_t *seg, const int8_t *cf, int32_t *count,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_count_c, dim3(nsys), dim3(256), 0, s, seg, cf, count);
+    LAIR_LAUNCH(k_seg_count_c, dim3(nsys), dim3(256), 0, s, seg, cf, count);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -88,7 +88,7 @@ __global__ void k_force_c(int32_t nsys, const int64_t *seg, const uint8_t *stopp
 
 void launch_force_c(int32_t nsys, const int64_t *seg, const uint8_t *stopped, int8_t *cf,
                     int64_t nrows, hipStream_t s) {
-    hipLaunchKernelGGL(k_force_c, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_force_c, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
                        nsys, seg, stopped, cf, nrows);
     LAIR_LAUNCH_CHECK();
 }
@@ -115,12 +115,12 @@ int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
     DevArr<int32_t> scan;
     flag.alloc((size_t)std::max(nc, 1), s);
     scan.alloc((size_t)nc + 1, s);
-    hipLaunchKernelGGL(k_relax_flags, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_relax_flags, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
                        nsys, seg, stopped, clist, nc, flag.get());
     LAIR_LAUNCH_CHECK();
     int64_t cnt = scan_flags_i8(flag.get(), 1, scan.get(), nc, s, tmp);
     out.alloc((size_t)std::max<int64_t>(cnt, 1), s);
-    hipLaunchKernelGGL(k_compact_list, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_compact_list, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
                        flag.get(), scan.get(), clist, nc, out.get());
     LAIR_LAUNCH_CHECK();
     return (int32_t)cnt;
@@ -144,7 +144,7 @@ k_seg_sumsq(const int64_t *seg, const double *r, double *out) {
 
 void launch_seg_sumsq(int32_t nsys, const int64_t *seg, const double *r, double *out,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_sumsq, dim3(nsys), dim3(256), 0, s, seg, r, out);
+    LAIR_LAUNCH(k_seg_sumsq, dim3(nsys), dim3(256), 0, s, seg, r, out);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -159,7 +159,7 @@ __global__ void k_mask_rows(int32_t nsys, const int64_t *seg, const uint8_t *act
 
 void launch_mask_rows(int32_t nsys, const int64_t *seg, const uint8_t *active, double *r,
                       int64_t nrows, hipStream_t s) {
-    hipLaunchKernelGGL(k_mask_rows, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_mask_rows, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
                        nsys, seg, active, r, nrows);
     LAIR_LAUNCH_CHECK();
 }
@@ -290,21 +290,21 @@ k_block_solve(const int64_t *seg, const int64_t *doff, const double *dense,
 void launch_dense_blocks(int32_t nsys, const int64_t *seg, const int64_t *doff,
                          const int32_t *rp, const int32_t *cj, const double *v,
                          double *dense, int64_t nrows, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_blocks, dim3(blocks_for(nrows, 64)), dim3(64), 0, s,
+    LAIR_LAUNCH(k_dense_blocks, dim3(blocks_for(nrows, 64)), dim3(64), 0, s,
                        nsys, seg, doff, rp, cj, v, dense, nrows);
     LAIR_LAUNCH_CHECK();
 }
 
 void launch_block_lu(int32_t nsys, const int64_t *seg, const int64_t *doff, double *dense,
                      int32_t *piv, int32_t *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_lu, dim3(nsys), dim3(256), 0, s, seg, doff, dense, piv, info);
+    LAIR_LAUNCH(k_block_lu, dim3(nsys), dim3(256), 0, s, seg, doff, dense, piv, info);
     LAIR_LAUNCH_CHECK();
 }
 
 void launch_block_solve(int32_t nsys, const int64_t *seg, const int64_t *doff,
                         const double *dense, const int32_t *piv, const double *b, double *x,
                         bool transpose, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_solve, dim3(nsys), dim3(256), 0, s, seg, doff, dense, piv, b, x,
+    LAIR_LAUNCH(k_block_solve, dim3(nsys), dim3(256), 0, s, seg, doff, dense, piv, b, x,
                        transpose ? 1 : 0);
     LAIR_LAUNCH_CHECK();
 }

@@ -320,7 +320,7 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
 #define LAIR_RV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
-        hipLaunchKernelGGL((k_rowdotV<VT, NN, WW, MODE>),                         \
+        LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE>),                         \
                            dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
                            A.nrows, T, A.rp, A.cj, A.v, x, b, y);                 \
     }
@@ -337,7 +337,7 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
     }
     if (nrhs > 1) {
 #define LAIR_RM(NN)                                                               \
-    hipLaunchKernelGGL((k_rowdotM<VT, NN, MODE>),                                 \
+    LAIR_LAUNCH((k_rowdotM<VT, NN, MODE>),                                 \
                        dim3(blocks_for((int64_t)A.nrows * NN, 256)), dim3(256), 0, s, \
                        A.nrows, A.rp, A.cj, A.v, x, b, y)
         switch (nrhs) {
@@ -352,7 +352,7 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
         return;
     }
 #define LAIR_RD(TT)                                                              \
-    hipLaunchKernelGGL((k_rowdot1<VT, TT, MODE>),                                \
+    LAIR_LAUNCH((k_rowdot1<VT, TT, MODE>),                                \
                        dim3(blocks_for((int64_t)A.nrows * TT, 256)), dim3(256), 0, s, \
                        A.nrows, A.rp, A.cj, A.v, x, b, y)
     switch (A.team) {
@@ -432,7 +432,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
 #define LAIR_JV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
-        hipLaunchKernelGGL((k_jacobiV<VT, NN, WW, SEL>),                          \
+        LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL>),                          \
                            dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s, \
                            nx, T, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om); \
     }
@@ -449,7 +449,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
     }
     if (nrhs > 1) {
 #define LAIR_JM(NN)                                                               \
-    hipLaunchKernelGGL((k_jacobiM<VT, NN, SEL>),                                  \
+    LAIR_LAUNCH((k_jacobiM<VT, NN, SEL>),                                  \
                        dim3(blocks_for((int64_t)nx * NN, 256)), dim3(256), 0, s,  \
                        nx, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
         switch (nrhs) {
@@ -464,7 +464,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
         return;
     }
 #define LAIR_JC(TT)                                                              \
-    hipLaunchKernelGGL((k_jacobi1<VT, TT, SEL>),                                 \
+    LAIR_LAUNCH((k_jacobi1<VT, TT, SEL>),                                 \
                        dim3(blocks_for((int64_t)nx * TT, 256)), dim3(256), 0, s, \
                        nx, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
     switch (A.team) {
@@ -508,7 +508,7 @@ void op_scatter(const int32_t *rows, int32_t nx, const VT *t, VT *x,
                 int32_t nrhs, hipStream_t s) {
     if (nx == 0) return;
     int64_t total = (int64_t)nx * nrhs;
-    hipLaunchKernelGGL((k_scatter<VT>), dim3(blocks_for(total, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH((k_scatter<VT>), dim3(blocks_for(total, 256)), dim3(256), 0, s,
                        total, nrhs, rows, t, x);
     LAIR_LAUNCH_CHECK();
 }
@@ -522,7 +522,7 @@ __global__ void k_fill(VT *x, VT val, int64_t n) {
 template <class VT>
 void op_fill(VT *x, VT val, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL((k_fill<VT>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, val, n);
+    LAIR_LAUNCH((k_fill<VT>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, val, n);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -535,7 +535,7 @@ __global__ void k_copy(const VT *x, VT *y, int64_t n) {
 template <class VT>
 void op_copy(const VT *x, VT *y, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL((k_copy<VT>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, n);
+    LAIR_LAUNCH((k_copy<VT>), dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, n);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -621,7 +621,7 @@ template <class VT>
 void op_dense_solve(int32_t n, const double *lu, const int32_t *piv,
                     const VT *b, VT *x, int32_t nrhs, bool transpose,
                     hipStream_t s) {
-    hipLaunchKernelGGL((k_dense_solve<VT>), dim3(1), dim3(256), 0, s, n, lu, piv, b, x,
+    LAIR_LAUNCH((k_dense_solve<VT>), dim3(1), dim3(256), 0, s, n, lu, piv, b, x,
                        nrhs, transpose ? 1 : 0);
     LAIR_LAUNCH_CHECK();
 }
@@ -647,7 +647,7 @@ k_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x, int32_t nrhs,
 template <class VT>
 void op_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x,
                      int32_t nrhs, bool transpose, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_apply<VT>), dim3(blocks_for((int64_t)n * nrhs, 256)),
+    LAIR_LAUNCH((k_coarse_apply<VT>), dim3(blocks_for((int64_t)n * nrhs, 256)),
                        dim3(256), 0, s, n, kinv, b, x, nrhs, transpose ? 1 : 0);
     LAIR_LAUNCH_CHECK();
 }
@@ -701,10 +701,10 @@ void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
     if (chunk < NRM_BS) chunk = NRM_BS;
     int32_t nblk = (int32_t)((total + chunk - 1) / chunk);
     if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_sumsq_partial, dim3(nblk), dim3(NRM_BS), 0, s, r, total,
+    LAIR_LAUNCH(k_sumsq_partial, dim3(nblk), dim3(NRM_BS), 0, s, r, total,
                        nrhs, chunk, partial);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, nblk, nrhs, out);
+    LAIR_LAUNCH(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, nblk, nrhs, out);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -713,13 +713,13 @@ static void resid_norm_t(const CsrView<double> &A, const double *b, const double
                          double *r64, float *r32, double *partial, unsigned grid, int T,
                          hipStream_t s) {
     if (r64 && r32)
-        hipLaunchKernelGGL((k_resid_norm<NR, VW, true, true>), dim3(grid), dim3(256), 0, s,
+        LAIR_LAUNCH((k_resid_norm<NR, VW, true, true>), dim3(grid), dim3(256), 0, s,
                            A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
     else if (r64)
-        hipLaunchKernelGGL((k_resid_norm<NR, VW, true, false>), dim3(grid), dim3(256), 0, s,
+        LAIR_LAUNCH((k_resid_norm<NR, VW, true, false>), dim3(grid), dim3(256), 0, s,
                            A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
     else
-        hipLaunchKernelGGL((k_resid_norm<NR, VW, false, true>), dim3(grid), dim3(256), 0, s,
+        LAIR_LAUNCH((k_resid_norm<NR, VW, false, true>), dim3(grid), dim3(256), 0, s,
                            A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
     LAIR_LAUNCH_CHECK();
 }
@@ -743,7 +743,7 @@ bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x
         case 16: resid_norm_t<16, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
         default: resid_norm_t<32, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
     }
-    hipLaunchKernelGGL(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, (int32_t)grid,
+    LAIR_LAUNCH(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, (int32_t)grid,
                        nrhs, out);
     LAIR_LAUNCH_CHECK();
     return true;
@@ -759,7 +759,7 @@ __global__ void k_axpy_f32(double *x, const float *e, int64_t n) {
 
 void op_axpy_f32(double *x, const float *e, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_axpy_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, e, n);
+    LAIR_LAUNCH(k_axpy_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, e, n);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -770,7 +770,7 @@ __global__ void k_cast_f32(const double *in, float *out, int64_t n) {
 
 void op_cast_f32(const double *in, float *out, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_cast_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+    LAIR_LAUNCH(k_cast_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -781,7 +781,7 @@ __global__ void k_cast_f64(const float *in, double *out, int64_t n) {
 
 void op_cast_f64(const float *in, double *out, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_cast_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+    LAIR_LAUNCH(k_cast_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -803,7 +803,7 @@ __global__ void k_block_apply(int32_t nblk, int32_t k, const double *dinv,
 void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
                     const double *b, double *out, int32_t nrhs, hipStream_t s) {
     int64_t tot = (int64_t)nblk * k * nrhs;
-    hipLaunchKernelGGL(k_block_apply, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_block_apply, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
                        nblk, k, dinv, b, out, nrhs);
     LAIR_LAUNCH_CHECK();
 }

@@ -134,12 +134,12 @@ static int64_t scan_impl(F f, OUT *out, int64_t n, hipStream_t s,
     int64_t *bs = tmp.get();
     int64_t *bmax = bs + nb;
     int64_t *tot = bmax + nb;      // tot[0] = total, tot[1] = largest value
-    hipLaunchKernelGGL((k_scan_tile<F, OUT>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
+    LAIR_LAUNCH((k_scan_tile<F, OUT>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
                        f, n, out, bs, bmax);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, bmax, nb, tot);
+    LAIR_LAUNCH(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, bmax, nb, tot);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_add<OUT>, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
+    LAIR_LAUNCH(k_scan_add<OUT>, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
                        0, s, out, n, bs, tot);
     LAIR_LAUNCH_CHECK();
     int64_t h[2] = {0, 0};
@@ -252,10 +252,10 @@ int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
     DevArr<int32_t> st;
     st.alloc(2 + 2 * (size_t)nb, s);
     ProfScope ps("validate", s, 12.0 * nnz + 4.0 * (n + 1));
-    hipLaunchKernelGGL(k_validate, dim3(nb), dim3(256), 0, s, n, nnz, rp, cj, v,
+    LAIR_LAUNCH(k_validate, dim3(nb), dim3(256), 0, s, n, nnz, rp, cj, v,
                        st.get() + 2);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_validate_final, dim3(1), dim3(256), 0, s, st.get() + 2, (int64_t)nb,
+    LAIR_LAUNCH(k_validate_final, dim3(1), dim3(256), 0, s, st.get() + 2, (int64_t)nb,
                        st.get());
     LAIR_LAUNCH_CHECK();
     int32_t h[2];
@@ -305,7 +305,7 @@ template <int T>
 static void strength_t(int32_t n, const int32_t *rp, const int32_t *cj,
                        const double *v, double theta, int32_t kind,
                        uint8_t *smask, hipStream_t s) {
-    hipLaunchKernelGGL(k_strength<T>, dim3(blocks_for((int64_t)n * T, 256)),
+    LAIR_LAUNCH(k_strength<T>, dim3(blocks_for((int64_t)n * T, 256)),
                        dim3(256), 0, s, n, rp, cj, v, theta, kind, smask);
     LAIR_LAUNCH_CHECK();
 }
@@ -393,10 +393,10 @@ void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
                      const int32_t *rp, int32_t *cidx, int32_t *clist,
                      int32_t *flist, unsigned long long *acc, hipStream_t s) {
     const unsigned nb = blocks_for(n, 256);
-    hipLaunchKernelGGL(k_cf_lists, dim3(nb), dim3(256), 0, s,
+    LAIR_LAUNCH(k_cf_lists, dim3(nb), dim3(256), 0, s,
                        n, cf, cidx_scan, rp, cidx, clist, flist, acc + 2);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, acc + 2, (int64_t)nb, acc);
+    LAIR_LAUNCH(k_sum_pairs, dim3(1), dim3(256), 0, s, acc + 2, (int64_t)nb, acc);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -507,7 +507,7 @@ static void nbr_t(int32_t nc, const int32_t *clist, const int32_t *rp,
                   int32_t distance, const int32_t *flist, int32_t nf, bool fill,
                   int32_t *cnt, const int32_t *nptr, int32_t *nbr,
                   int32_t *overflow, hipStream_t s) {
-    hipLaunchKernelGGL(k_nbr<T>, dim3(blocks_for((int64_t)nc * T, 256)), dim3(256),
+    LAIR_LAUNCH(k_nbr<T>, dim3(blocks_for((int64_t)nc * T, 256)), dim3(256),
                        0, s, nc, clist, rp, cj, sm, cf, distance, flist, nf, fill,
                        cnt, nptr, nbr, overflow);
     LAIR_LAUNCH_CHECK();
@@ -1260,11 +1260,11 @@ static void small_pass(bool mixed, int32_t nlist, const int32_t *list,
                        hipStream_t s) {
     if (nlist == 0) return;
     if (mixed)
-        hipLaunchKernelGGL((k_local_small<SM, true>), dim3(blocks_for(nlist, 256)), dim3(256),
+        LAIR_LAUNCH((k_local_small<SM, true>), dim3(blocks_for(nlist, 256)), dim3(256),
                            0, s, nlist, list, list_count, clist, nptr, nbr, rp, cj, v, out.r_cj,
                            out.r_v, out.flags, defer, ndefer, sing, nsing);
     else
-        hipLaunchKernelGGL((k_local_small<SM, false>), dim3(blocks_for(nlist, 256)), dim3(256),
+        LAIR_LAUNCH((k_local_small<SM, false>), dim3(blocks_for(nlist, 256)), dim3(256),
                            0, s, nlist, list, list_count, clist, nptr, nbr, rp, cj, v, out.r_cj,
                            out.r_v, out.flags, defer, ndefer, sing, nsing);
     LAIR_LAUNCH_CHECK();
@@ -1282,7 +1282,7 @@ static void team_pass(bool mixed, int32_t nlist, const int32_t *list,
     dim3 g(blocks_for((int64_t)nlist * T, BS)), b(BS);
     if constexpr (T <= 16) {
         if (mixed) {
-            hipLaunchKernelGGL((k_local_team<T, true>), g, b, 0, s, nlist, list, list_count,
+            LAIR_LAUNCH((k_local_team<T, true>), g, b, 0, s, nlist, list, list_count,
                                clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer,
                                ndefer, sing, nsing);
             LAIR_LAUNCH_CHECK();
@@ -1291,7 +1291,7 @@ static void team_pass(bool mixed, int32_t nlist, const int32_t *list,
     }
     if (mixed) fail(LAIR_EUNSUPPORTED, "mixed 32-lane local solve");
     else
-        hipLaunchKernelGGL((k_local_team<T, false>), g, b, 0, s, nlist, list, list_count, clist,
+        LAIR_LAUNCH((k_local_team<T, false>), g, b, 0, s, nlist, list, list_count, clist,
                            nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer, ndefer,
                            sing, nsing);
     LAIR_LAUNCH_CHECK();
@@ -1318,7 +1318,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         DevArr<double> acc;
         acc.alloc(4, s);
         LAIR_HIP(hipMemsetAsync(acc.get(), 0, 4 * sizeof(double), s));
-        hipLaunchKernelGGL(k_local_cost, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
+        LAIR_LAUNCH(k_local_cost, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
                            nc, clist, nptr, nbr, rp, 32, acc.get());
         LAIR_LAUNCH_CHECK();
         Readback rb(s);
@@ -1361,11 +1361,11 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         ProfScope ps_wave("local_wave", s, cost[2], cost[3]);
         size_t lds = mixed ? wave_lds_bytes<float>(cap) : wave_lds_bytes<double>(cap);
         if (mixed)
-            hipLaunchKernelGGL((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), lds, s,
+            LAIR_LAUNCH((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), lds, s,
                                wave_list, nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
                                out.flags, sing, nS, scratch.get(), smax, cap);
         else
-            hipLaunchKernelGGL((k_local_wave<false>), dim3((unsigned)nbig), dim3(64), lds, s,
+            LAIR_LAUNCH((k_local_wave<false>), dim3((unsigned)nbig), dim3(64), lds, s,
                                wave_list, nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
                                out.flags, sing, nS, scratch.get(), smax, cap);
         LAIR_LAUNCH_CHECK();
@@ -1378,7 +1378,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         DevArr<double> scratch;
         scratch.alloc((size_t)nsing * (2 * (size_t)smax * smax + 2 * (size_t)smax), s);
         ProfScope ps_ls("local_lstsq", s, 0.0);
-        hipLaunchKernelGGL(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
+        LAIR_LAUNCH(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
                            sing, nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
                            out.r_v, scratch.get(), smax);
         LAIR_LAUNCH_CHECK();
@@ -1415,7 +1415,7 @@ void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
                              const double *v, const uint8_t *smask,
                              const int8_t *cf, const int32_t *cidx,
                              int32_t *pcol, hipStream_t s) {
-    hipLaunchKernelGGL(k_interp_1p, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_interp_1p, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        n, rp, cj, v, smask, cf, cidx, pcol);
     LAIR_LAUNCH_CHECK();
 }
@@ -1433,7 +1433,7 @@ __global__ void k_compact_1p(int32_t n, const int32_t *pcol, const int32_t *prp,
 void launch_compact_one_point(int32_t n, const int32_t *pcol,
                               const int32_t *prp, int32_t *pcj, double *pv,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_compact_1p, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_compact_1p, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        n, pcol, prp, pcj, pv);
     LAIR_LAUNCH_CHECK();
 }
@@ -1520,7 +1520,7 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
     int t = team_for_mean(mean_len);
     if (t > 16) t = 16;
 #define LAIR_ID(TT)                                                              \
-    hipLaunchKernelGGL(k_interp_direct<TT>, dim3(blocks_for((int64_t)n * TT, 256)), \
+    LAIR_LAUNCH(k_interp_direct<TT>, dim3(blocks_for((int64_t)n * TT, 256)), \
                        dim3(256), 0, s, n, rp, cj, v, smask, cf, cidx, fill, cnt, prp, \
                        pcj, pv)
     switch (t) {
@@ -1782,7 +1782,7 @@ static void spgemm_hacc(int32_t m, RowSrc src, unsigned grid, const int32_t *ap,
                         const int32_t *bj, const double *bx, const int64_t *eoff, int32_t *cnt,
                         int32_t *tcj, double *tcx, int32_t *next, int32_t *nnext,
                         hipStream_t s) {
-    hipLaunchKernelGGL((k_spgemm_hacc<T, HS, BLOCK>), dim3(grid), dim3(BLOCK), 0, s, m, src,
+    LAIR_LAUNCH((k_spgemm_hacc<T, HS, BLOCK>), dim3(grid), dim3(BLOCK), 0, s, m, src,
                        ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, next, nnext);
     LAIR_LAUNCH_CHECK();
 }
@@ -1800,7 +1800,7 @@ constexpr int HACC_BIG = 4096;   // table of the one-team kernel
 void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
                        int32_t *e, hipStream_t s) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_prod_count, dim3(blocks_for((int64_t)m * 8, 256)), dim3(256), 0, s, m,
+    LAIR_LAUNCH(k_prod_count, dim3(blocks_for((int64_t)m * 8, 256)), dim3(256), 0, s, m,
                        ap, aj, bp, e);
     LAIR_LAUNCH_CHECK();
 }
@@ -1841,7 +1841,7 @@ void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double
     spgemm_hacc<64, HACC_BIG, 64>(m, RowSrc{l1, n1}, 2048, ap, aj, ax, bp, bj, bx, eoff, cnt,
                                   tcj, tcx, l2, n2, s);
     if (max_e <= HACC_BIG / 2) return;
-    hipLaunchKernelGGL((k_spgemm_merge<64, 16>), dim3(256), dim3(256), 0, s, RowSrc{l2, n2},
+    LAIR_LAUNCH((k_spgemm_merge<64, 16>), dim3(256), dim3(256), 0, s, RowSrc{l2, n2},
                        ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, overflow);
     LAIR_LAUNCH_CHECK();
 }
@@ -1870,7 +1870,7 @@ void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
     if (m == 0) return;
     const int t = team_for_mean(mean_c / 2.0);
 #define LAIR_CP(TT)                                                                      \
-    hipLaunchKernelGGL(k_spgemm_compact<TT>, dim3(blocks_for((int64_t)m * TT, 256)),     \
+    LAIR_LAUNCH(k_spgemm_compact<TT>, dim3(blocks_for((int64_t)m * TT, 256)),     \
                        dim3(256), 0, s, m, eoff, crp, tcj, tcx, cj, cx)
     switch (t) {
         case 2: LAIR_CP(2); break;
@@ -1934,14 +1934,14 @@ void launch_transpose(int32_t nrows, int32_t ncols, int64_t nnz,
     (void)nnz;
     LAIR_HIP(hipMemsetAsync(tcount, 0, sizeof(int32_t) * (size_t)ncols, s));
     LAIR_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (size_t)ncols, s));
-    hipLaunchKernelGGL(k_tcount, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_tcount, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
                        nrows, rp, cj, tcount);
     LAIR_LAUNCH_CHECK();
     scan_counts_i32(tcount, trp, ncols, s, tmp);
-    hipLaunchKernelGGL(k_tscatter, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_tscatter, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
                        nrows, rp, cj, v, trp, cursor, tcj, tv);
     LAIR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_tsort, dim3(blocks_for(ncols, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_tsort, dim3(blocks_for(ncols, 256)), dim3(256), 0, s,
                        ncols, trp, tcj, tv);
     LAIR_LAUNCH_CHECK();
 }
@@ -1953,7 +1953,7 @@ __global__ void k_to_float(const double *in, float *out, int64_t n) {
 
 void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_to_float, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_to_float, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        in, out, n);
     LAIR_LAUNCH_CHECK();
 }
@@ -2005,7 +2005,7 @@ void launch_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
                           const int32_t *cj, const double *v, double *dinv,
                           int32_t *bad, hipStream_t s) {
     if (k > BLK_MAX) fail(LAIR_EUNSUPPORTED, "block size %d > %d", k, BLK_MAX);
-    hipLaunchKernelGGL(k_block_inverse, dim3(blocks_for(nblk, 64)), dim3(64), 0, s,
+    LAIR_LAUNCH(k_block_inverse, dim3(blocks_for(nblk, 64)), dim3(64), 0, s,
                        nblk, k, rp, cj, v, dinv, bad);
     LAIR_LAUNCH_CHECK();
 }
@@ -2024,7 +2024,7 @@ __global__ void k_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj
 
 void launch_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj,
                            const double *v, double *dense, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_from_csr, dim3(blocks_for(n, 64)), dim3(64), 0, s,
+    LAIR_LAUNCH(k_dense_from_csr, dim3(blocks_for(n, 64)), dim3(64), 0, s,
                        n, rp, cj, v, dense);
     LAIR_LAUNCH_CHECK();
 }
@@ -2149,14 +2149,14 @@ static size_t max_lds_per_block() {
 void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,
                      hipStream_t s) {
     if (n <= 128 && (size_t)n * n * sizeof(double) + 64 <= max_lds_per_block()) {
-        hipLaunchKernelGGL(k_dense_lu_lds, dim3(1), dim3(256), (size_t)n * n * sizeof(double),
+        LAIR_LAUNCH(k_dense_lu_lds, dim3(1), dim3(256), (size_t)n * n * sizeof(double),
                            s, n, lu, piv, info);
         LAIR_LAUNCH_CHECK();
         return;
     }
     int bs = 64;
     while (bs < 1024 && bs < n) bs <<= 1;
-    hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(bs), 0, s, n, lu, piv, info);
+    LAIR_LAUNCH(k_dense_lu, dim3(1), dim3(bs), 0, s, n, lu, piv, info);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -2211,7 +2211,7 @@ k_dense_inverse(int32_t n, const double *lu, const int32_t *piv, double *inv) {
 void launch_dense_inverse(int32_t n, const double *lu, const int32_t *piv,
                           double *inv, hipStream_t s) {
     int nb = (n + INV_COLS - 1) / INV_COLS;
-    hipLaunchKernelGGL(k_dense_inverse, dim3(nb), dim3(64),
+    LAIR_LAUNCH(k_dense_inverse, dim3(nb), dim3(64),
                        (size_t)n * INV_COLS * sizeof(double), s, n, lu, piv, inv);
     LAIR_LAUNCH_CHECK();
 }

@@ -418,7 +418,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     R.rp.alloc((size_t)Lv.nc + 1, s);
     R.cj.alloc((size_t)R.nnz, s);
     R.v.alloc((size_t)R.nnz, s);
-    hipLaunchKernelGGL(k_r_rowptr, dim3(blocks_for(Lv.nc + 1, 256)), dim3(256), 0, s,
+    LAIR_LAUNCH(k_r_rowptr, dim3(blocks_for(Lv.nc + 1, 256)), dim3(256), 0, s,
                        Lv.nc, Lv.nptr.get(), R.rp.get());
     LAIR_LAUNCH_CHECK();
     Lv.flags.alloc((size_t)Lv.nc, s);
@@ -444,7 +444,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         }
         DevArr<int32_t> has;
         has.alloc((size_t)n, s);
-        hipLaunchKernelGGL(k_nonneg_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+        LAIR_LAUNCH(k_nonneg_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            n, pcol.get(), has.get());
         LAIR_LAUNCH_CHECK();
         P.nnz = scan_counts_i32(has.get(), P.rp.get(), n, s, tmp);
@@ -665,7 +665,7 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         D.rp.alloc((size_t)n + 1, s);
         D.cj.alloc((size_t)D.nnz, s);
         D.v.alloc((size_t)D.nnz, s);
-        hipLaunchKernelGGL(k_block_diag_csr, dim3(blocks_for(D.nnz + 1, 256)), dim3(256), 0, s,
+        LAIR_LAUNCH(k_block_diag_csr, dim3(blocks_for(D.nnz + 1, 256)), dim3(256), 0, s,
                            nblk, k, h->dinv.get(), D.rp.get(), D.cj.get(), D.v.get());
         LAIR_LAUNCH_CHECK();
         DevCSR As;
@@ -1095,7 +1095,7 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
             // lambda <- lambda + B^T (g - A^T lambda): cycle on the residual
             DevArr<double> &e = L0.b;
             vcycle_t(h, 0, h->r0.get(), e.get(), true, nrhs, s);
-            hipLaunchKernelGGL(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
+            LAIR_LAUNCH(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
                                x, e.get(), n * nrhs);
             LAIR_LAUNCH_CHECK();
             residual_and_norms(s);
@@ -1223,7 +1223,7 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                 op_axpy_f32(x, h->e32.get(), n, st);
             } else {
                 vcycle<double>(h, 0, h->r0.get(), h->e64.get(), true, nullptr, 1, st);
-                hipLaunchKernelGGL(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, x,
+                LAIR_LAUNCH(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, x,
                                    h->e64.get(), n);
                 LAIR_LAUNCH_CHECK();
             }
@@ -1480,7 +1480,7 @@ lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g, double *lam
         int64_t n = L0.n;
         op_residual<double>(view<double>(L0.At, L0.team_At), g, lam, h->r0.get(), nrhs, s);
         vcycle_t(h, 0, h->r0.get(), L0.b.get(), true, nrhs, s);
-        hipLaunchKernelGGL(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
+        LAIR_LAUNCH(k_add, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s,
                            lam, L0.b.get(), n * nrhs);
         LAIR_LAUNCH_CHECK();
         return LAIR_OK;

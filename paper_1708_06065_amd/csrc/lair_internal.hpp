@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -132,11 +133,25 @@ struct ProfScope {
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;
-    int slot = -1;
-    hipStream_t stream = nullptr;
+    int slot = -1, prev_slot = -1;
+    hipStream_t stream = nullptr, prev_stream = nullptr;
 };
 // true while profiling is on and `category` is selected
 bool prof_selected(const char *category);
+// Start/stop events for a kernel about to be launched on s inside a
+// selected scope (false: launch without events).
+bool prof_kernel_events(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1);
+
+// Every kernel launch of the library: with the profiler on, the launch
+// carries its own start/stop events.
+#define LAIR_LAUNCH(K, G, B, SH, S, ...)                                            \
+    do {                                                                           \
+        hipEvent_t lair_e0_ = nullptr, lair_e1_ = nullptr;                         \
+        if (::lair::prof_kernel_events((S), &lair_e0_, &lair_e1_))                 \
+            hipExtLaunchKernelGGL(K, G, B, SH, S, lair_e0_, lair_e1_, 0, __VA_ARGS__); \
+        else                                                                       \
+            hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                       \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // Launch helpers

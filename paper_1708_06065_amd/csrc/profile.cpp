@@ -1,11 +1,13 @@
 // Kernel profiler behind lair_profile_begin / lair_profile_end.
 //
-// Each profiled launch records a pair of HIP events on the stream the kernel
-// runs on, so the elapsed time is that of the launch itself as the stream
-// executes it.  Records carry the algorithmic bytes and flops of the launch
-// (the data the operation must touch at least once), from which the caller
-// derives achieved bandwidth.  Process-wide; not for concurrent use from
-// several host threads.
+// A ProfScope of a selected category makes every kernel launched inside it
+// (on the scope's stream, through LAIR_LAUNCH) carry a start and a stop HIP
+// event of its own dispatch (hipExtLaunchKernelGGL), so the time is that of
+// the kernels as the stream executes them, without the dispatch latency
+// that events recorded between launches would add.  Records carry the
+// algorithmic bytes and flops of the operation (the data it must touch at
+// least once), from which the caller derives achieved bandwidth.
+// Process-wide; not for concurrent use from several host threads.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -21,8 +23,8 @@ namespace lair {
 namespace {
 struct Rec {
     std::string cat;
-    hipEvent_t e0, e1;
     double bytes, flops;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> kev;   // one pair per kernel
 };
 struct Prof {
     bool on = false;
@@ -35,6 +37,8 @@ Prof &prof() {
     static Prof p;
     return p;
 }
+thread_local int t_slot = -1;                 // record of the innermost scope
+thread_local hipStream_t t_stream = nullptr;
 hipEvent_t take_event(Prof &p) {
     if (!p.pool.empty()) {
         hipEvent_t e = p.pool.back();
@@ -72,19 +76,32 @@ ProfScope::ProfScope(const char *category, hipStream_t s, double bytes, double f
     if (!p.on) return;
     std::lock_guard<std::mutex> g(p.mu);
     if (!selected(p, category)) return;
-    Rec r{category, take_event(p), take_event(p), bytes, flops};
-    if (!r.e0 || !r.e1) return;
-    if (hipEventRecord(r.e0, s) != hipSuccess) return;
-    stream = s;
+    prev_slot = t_slot;
+    prev_stream = t_stream;
     slot = (int)p.recs.size();
-    p.recs.push_back(r);
+    stream = s;
+    p.recs.push_back(Rec{category, bytes, flops, {}});
+    t_slot = slot;
+    t_stream = s;
 }
 
 ProfScope::~ProfScope() {
     if (slot < 0) return;
+    t_slot = prev_slot;
+    t_stream = prev_stream;
+}
+
+bool prof_kernel_events(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1) {
+    if (t_slot < 0 || s != t_stream) return false;
     Prof &p = prof();
     std::lock_guard<std::mutex> g(p.mu);
-    if (slot < (int)p.recs.size()) (void)hipEventRecord(p.recs[slot].e1, stream);
+    if (!p.on || t_slot >= (int)p.recs.size()) return false;
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return false;
+    p.recs[t_slot].kev.push_back({a, b});
+    *e0 = a;
+    *e1 = b;
+    return true;
 }
 
 namespace {
@@ -142,10 +159,11 @@ extern "C" {
 lair_status lair_profile_begin(const char *categories) {
     Prof &p = prof();
     std::lock_guard<std::mutex> g(p.mu);
-    for (auto &r : p.recs) {
-        p.pool.push_back(r.e0);
-        p.pool.push_back(r.e1);
-    }
+    for (auto &r : p.recs)
+        for (auto &e : r.kev) {
+            p.pool.push_back(e.first);
+            p.pool.push_back(e.second);
+        }
     p.recs.clear();
     p.filter = categories ? categories : "";
     p.on = true;
@@ -160,14 +178,24 @@ lair_status lair_profile_end(char *json, int64_t *len) {
     std::map<std::string, Agg> agg;
     lair_status st = LAIR_OK;
     for (auto &r : p.recs) {
-        float ms = 0.f;
-        if (hipEventSynchronize(r.e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) {
+        if (r.kev.empty()) continue;          // no kernel ran in the scope
+        double ms = 0.0;
+        bool ok = true;
+        for (auto &e : r.kev) {
+            float k = 0.f;
+            if (hipEventSynchronize(e.second) != hipSuccess ||
+                hipEventElapsedTime(&k, e.first, e.second) != hipSuccess) {
+                ok = false;
+                break;
+            }
+            ms += k;
+        }
+        if (!ok) {
             st = LAIR_EDEVICE;
             continue;
         }
         Agg &a = agg[r.cat];
-        a.n += 1;
+        a.n += (long)r.kev.size();
         a.ms += ms;
         a.bytes += r.bytes;
         a.flops += r.flops;
