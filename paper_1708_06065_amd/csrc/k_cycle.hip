@@ -118,16 +118,19 @@ struct Pack {
 // length): the team loads T consecutive entries, group g of L lanes takes
 // entries g L .. g L + L - 1 of them, and the G partial sums are added by
 // shuffles at the end.
-template <class VT, int NR, int VW, bool SEL>
+// TAG: the column indices carry the point type in their sign bit (C-point
+// columns are stored as c | 2^31), which spares SEL the load of cf[c].
+template <class VT, int NR, int VW, bool SEL, bool TAG = false>
 __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_col,
                                          const int32_t *cj, const VT *v,
                                          const VT *xF, const VT *xC,
                                          const int8_t *cf, Pack<VT, VW> &acc, VT &d) {
     constexpr int L = NR / VW;
     const int q = t % L;
+    const int g0 = (t / L) * L;      // first entry of this lane's group
     for (int base = lo; base < hi; base += T) {
         int p = base + t;
-        int c = -1;
+        int c = 0;
         VT a = (VT)0;
         if (p < hi) { c = cj[p]; a = v[p]; }
         int ce[L];
@@ -140,9 +143,12 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
         Pack<VT, VW> xe[L];
 #pragma unroll
         for (int e = 0; e < L; ++e) {
-            if (ce[e] >= 0) {
-                const VT *src = SEL ? (cf[ce[e]] ? xC : xF) : xF;
-                xe[e].load(src + (int64_t)ce[e] * NR + q * VW);
+            if (base + g0 + e < hi) {
+                const int col = TAG ? (ce[e] & 0x7fffffff) : ce[e];
+                const VT *src = TAG ? (ce[e] < 0 ? xC : xF)
+                                    : (SEL ? (cf[col] ? xC : xF) : xF);
+                xe[e].load(src + (int64_t)col * NR + q * VW);
+                if (col == diag_col) d = ae[e];
             } else {
                 xe[e].zero();
             }
@@ -151,7 +157,6 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
         for (int e = 0; e < L; ++e) {
 #pragma unroll
             for (int k = 0; k < VW; ++k) acc.v[k] += ae[e] * xe[e].v[k];
-            if (ce[e] == diag_col) d = ae[e];
         }
     }
     for (int o = L; o < T; o <<= 1) {
@@ -191,7 +196,7 @@ k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *
     out.store(y + o);
 }
 
-template <class VT, int NR, int VW, bool SEL>
+template <class VT, int NR, int VW, bool SEL, bool TAG>
 __global__ void __launch_bounds__(256)
 k_jacobiV(int32_t nx, int T, const int32_t *rows, const int32_t *rp, const int32_t *cj,
           const VT *v, const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
@@ -205,7 +210,7 @@ k_jacobiV(int32_t nx, int T, const int32_t *rows, const int32_t *rp, const int32
     Pack<VT, VW> acc;
     acc.zero();
     VT d = (VT)0;
-    row_accV<VT, NR, VW, SEL>(rp[i], rp[i + 1], t, T, i, cj, v, xF, xC, cf, acc, d);
+    row_accV<VT, NR, VW, SEL, TAG>(rp[i], rp[i + 1], t, T, i, cj, v, xF, xC, cf, acc, d);
     if (t >= L) return;
     const int64_t oi = (int64_t)i * NR + t * VW;
     Pack<VT, VW> xi, bi, r;
@@ -432,9 +437,14 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
 #define LAIR_JV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
-        LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL>),                          \
-                           dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s, \
-                           nx, T, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om); \
+        if (SEL && A.cjt)                                                         \
+            LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL, true>),                       \
+                        dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s,  \
+                        nx, T, rows, A.rp, A.cjt, A.v, b, xF, xC, cf, out, compact, om); \
+        else                                                                      \
+            LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL, false>),                      \
+                        dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s,  \
+                        nx, T, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om); \
     }
         switch (nrhs) {
             case 2: LAIR_JV(2, 2); break;
@@ -747,6 +757,20 @@ bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x
                        nrhs, out);
     LAIR_LAUNCH_CHECK();
     return true;
+}
+
+__global__ void k_tag_columns(int64_t nnz, const int32_t *cj, const int8_t *cf, int32_t *cjt) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int32_t c = cj[p];
+    cjt[p] = cf[c] == 1 ? (int32_t)((uint32_t)c | 0x80000000u) : c;
+}
+
+void launch_tag_columns(int64_t nnz, const int32_t *cj, const int8_t *cf, int32_t *cjt,
+                        hipStream_t s) {
+    if (nnz == 0) return;
+    LAIR_LAUNCH(k_tag_columns, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, nnz, cj, cf, cjt);
+    LAIR_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------

@@ -1816,26 +1816,22 @@ void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double
     const int T = hacc_team(mean_e);
     const RowSrc all{nullptr, nullptr};
     const unsigned g = blocks_for((int64_t)m * T, 256);
-    // tables of 2048 slots per block (30 KB of LDS)
-    int hc = 0;
-    switch (T) {
-        case 8:
-            spgemm_hacc<8, 64, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
-            hc = 32;
-            break;
-        case 16:
-            spgemm_hacc<16, 128, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
-            hc = 64;
-            break;
-        case 32:
-            spgemm_hacc<32, 256, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
-            hc = 128;
-            break;
-        default:
-            spgemm_hacc<64, 512, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
-            hc = 256;
-            break;
-    }
+    // table: twice the mean products (a row has at most that many distinct
+    // columns in the common case), at most 2048 slots per block; smaller
+    // tables leave LDS for more resident waves
+    const int cap = 2048 / (256 / T);
+    int HS = 16;
+    while (HS < cap && HS < 2.0 * mean_e) HS <<= 1;
+    if (HS < cap / 4) HS = cap / 4;
+    const int hc = HS / 2;
+#define LAIR_HA(TT, HH)                                                                    \
+    if (T == TT && HS == HH)                                                               \
+        spgemm_hacc<TT, HH, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
+    LAIR_HA(8, 16) LAIR_HA(8, 32) LAIR_HA(8, 64)
+    LAIR_HA(16, 32) LAIR_HA(16, 64) LAIR_HA(16, 128)
+    LAIR_HA(32, 64) LAIR_HA(32, 128) LAIR_HA(32, 256)
+    LAIR_HA(64, 128) LAIR_HA(64, 256) LAIR_HA(64, 512)
+#undef LAIR_HA
     if (max_e <= hc) return;     // no row can have more distinct columns
     // wider rows: one 64-lane team per block with a large table, then the merge
     spgemm_hacc<64, HACC_BIG, 64>(m, RowSrc{l1, n1}, 2048, ap, aj, ax, bp, bj, bx, eoff, cnt,

@@ -51,6 +51,7 @@ struct Level {
     DevArr<int8_t> cf;
     DevArr<uint8_t> smask;
     DevArr<int32_t> cidx, clist, flist, nptr, nbr;
+    DevArr<int32_t> cjt;           // A's columns tagged with the C/F type
     DevArr<int8_t> flags;
     lair_level_stats st{};
     // batch of systems: row offsets of every system at this level, the
@@ -710,6 +711,11 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         h->L.push_back(std::move(nx));
     }
     finish_coarsest(h.get());
+    for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+        Level &Lv = *h->L[l];
+        Lv.cjt.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+        launch_tag_columns(Lv.A.nnz, Lv.A.cj.get(), Lv.cf.get(), Lv.cjt.get(), s);
+    }
     for (auto &lp : h->L) {
         Level &Lv = *lp;
         Lv.team_A = team_of(Lv.A);
@@ -842,7 +848,9 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, true),
                      2.0 * Lv.nnzF * nrhs);
-        op_jacobi<VT>(A, Lv.flist.get(), Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s);
+        CsrView<VT> At = A;
+        At.cjt = Lv.cjt.get();
+        op_jacobi<VT>(At, Lv.flist.get(), Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s);
     }
     const int32_t *crows = Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get();
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;

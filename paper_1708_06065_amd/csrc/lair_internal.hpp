@@ -263,7 +263,11 @@ struct CsrView {
     const int32_t *rp, *cj;
     const VT *v;
     int32_t team;      // lanes per row for single right-hand sides
+    const int32_t *cjt = nullptr;   // columns tagged with the C/F type, or null
 };
+// cjt[p] = cj[p] with bit 31 set when cf[cj[p]] = 1 (C-point)
+void launch_tag_columns(int64_t nnz, const int32_t *cj, const int8_t *cf, int32_t *cjt,
+                        hipStream_t s);
 
 template <class VT>
 void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
