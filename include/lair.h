@@ -69,6 +69,8 @@ typedef int32_t lair_status;
 #define LAIR_MIXED       1  /* float local LU + one double refinement step
                                per row of Z; float cycle under a double outer
                                iteration (residual, update, norms in double) */
+#define LAIR_MIXED_LOCAL 2  /* float local LU + one double refinement step
+                               per row of Z; the cycle in double           */
 
 /* A square CSR matrix handed to lair_setup. */
 typedef struct lair_csr {
@@ -213,6 +215,20 @@ lair_status lair_setup_batch(int32_t nsys, const lair_csr *A, const lair_cf_leve
  * lair_setup_batch. */
 lair_status lair_solve_batch(lair_hierarchy *h, const double *b, double *x, double rtol,
                              int32_t maxit, int32_t *iters, double *relres, lair_info *info,
+                             void *stream);
+
+/* Replace the diagonal of A (n values; host memory, or device memory when
+ * on_device is 1) and rebuild the hierarchy's values on its structure: the
+ * strength masks, CF splittings, neighbourhoods and every sparsity pattern
+ * are kept (at level 0 they depend only on off-diagonal entries, Sec. 4),
+ * while the local solves (Eq. (system)), the interpolation weights, the
+ * Galerkin products (Sec. 2.1) and the coarsest factors are recomputed.
+ * For a family A(c) = A0 + diag(c) this replaces a full setup when only c
+ * changes.  Synchronises `stream`.  Errors: EINVAL (NULL, or a zero or
+ * non-finite diagonal entry; the hierarchy is left unchanged),
+ * EUNSUPPORTED (block scaling on), ESINGULAR (the hierarchy is then unusable
+ * until a successful update). */
+lair_status lair_update_diag(lair_hierarchy *h, const double *diag, int32_t on_device,
                              void *stream);
 
 /* Number of systems of a hierarchy (1 for lair_setup), and for a batch the

@@ -27,6 +27,10 @@ Steps and where the paper defines them:
   solve             stationary iteration on the V-cycle to a relative
                     residual tolerance
   cycle_transpose   the exact adjoint of ``cycle`` (for gradients)
+  update_diag       a new diagonal on a kept hierarchy structure: Eq. (system)
+                    solves, interpolation weights and Sec. 2.1 Galerkin
+                    products recomputed on the same neighbourhoods, splittings
+                    and patterns
 """
 import ctypes
 import math
@@ -375,6 +379,40 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
     last = H.levels[-1]
     last.cf = None
     H.coarse_lu = sla.lu_factor(last.A.toarray())
+    H.interp = interp
+    return H
+
+
+def update_diag(H, d):
+    """Replace the diagonal of A_0 by d and recompute every value of the
+    hierarchy on its kept structure.
+
+    The strength masks, CF splittings, neighbourhoods and the sparsity
+    patterns of R, P and every A_l stay as set up.  For each level in turn
+    the local systems of Eq. (system) are solved again on the same N_i, the
+    interpolation weights are recomputed (direct interpolation; one-point
+    weights are 1 on a kept pattern), and the next operator is the Galerkin
+    product R (A P) of Sec. 2.1.  The hierarchy is modified in place.
+    """
+    A = H.levels[0].A.tocsr(copy=True)
+    d = np.asarray(d, dtype=np.float64)
+    n = A.shape[0]
+    for i in range(n):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        k = lo + int(np.searchsorted(A.indices[lo:hi], i))
+        A.data[k] = d[i]
+    for L in H.levels[:-1]:
+        L.A = A
+        cpts = L.cpts
+        L.z, L.flags = local_solves(A, cpts, L.nptr, L.nbr)
+        L.R = restriction(n, cpts, L.nptr, L.nbr, L.z)
+        if H.interp == INTERP_DIRECT:
+            L.P = interp_direct(A, L.smask, L.cf)
+        L.AP = spgemm(A, L.P)
+        A = spgemm(L.R, L.AP)
+        n = A.shape[0]
+    H.levels[-1].A = A
+    H.coarse_lu = sla.lu_factor(A.toarray())
     return H
 
 

@@ -21,7 +21,7 @@ __all__ = ["setup", "setup_batch", "Hierarchy", "LairError", "load_library",
 
 _KINDS = {"abs": L.SOC_ABS, "neg": L.SOC_NEG}
 _INTERP = {"one_point": L.P_ONE_POINT, "direct": L.P_DIRECT}
-_PREC = {"fp64": L.FP64, "mixed": L.MIXED}
+_PREC = {"fp64": L.FP64, "mixed": L.MIXED, "mixed_local": L.MIXED_LOCAL}
 _DIST = {1: 1, 2: 2, "all_f": L.DIST_ALL_F, 0: L.DIST_ALL_F}
 
 EXPORT_WHAT = {
@@ -148,6 +148,21 @@ class Hierarchy:
         d = info.as_dict()
         d["converged"] = st == L.LAIR_OK
         return x, d
+
+    def update_diag(self, diag, stream=None):
+        """New diagonal of A (NumPy array or CUDA float64 tensor of n values):
+        same structure, values rebuilt."""
+        torch = _torch()
+        if isinstance(diag, torch.Tensor) and diag.is_cuda:
+            ptr, dev = _dev_ptr(diag, torch.float64, "diag"), 1
+            keep = diag
+        else:
+            keep = np.ascontiguousarray(diag, dtype=np.float64)
+            ptr, dev = keep.ctypes.data_as(ctypes.c_void_p), 0
+        L.check(L.load().lair_update_diag(self.handle, ptr, dev, _stream_ptr(stream)),
+                "lair_update_diag")
+        del keep
+        return self
 
     @property
     def nsys(self):

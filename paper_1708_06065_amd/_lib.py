@@ -18,7 +18,7 @@ LAIR_EUNSUPPORTED = -6
 SOC_ABS, SOC_NEG = 0, 1
 DIST_ALL_F = 0
 P_ONE_POINT, P_DIRECT = 0, 1
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_LOCAL = 0, 1, 2
 FLAG_NO_GRAPH = 1
 
 
@@ -72,6 +72,7 @@ EXPORTS = {
     "lair_setup_batch": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lair_solve_batch": (c_i32, [c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "lair_num_systems": (c_i32, [c_vp]),
+    "lair_update_diag": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
     "lair_system_levels": (c_i32, [c_vp, c_vp]),
     "lair_num_levels": (c_i32, [c_vp]),
     "lair_level_stats_get": (c_i32, [c_vp, c_i32, c_vp]),

@@ -251,7 +251,8 @@ static void check_options(const lair_strength *s, const lair_options *o) {
         fail(LAIR_EINVAL, "distance must be 1, 2 or LAIR_DIST_ALL_F");
     if (o->interp != LAIR_P_ONE_POINT && o->interp != LAIR_P_DIRECT)
         fail(LAIR_EINVAL, "unknown interpolation %d", o->interp);
-    if (o->precision != LAIR_FP64 && o->precision != LAIR_MIXED)
+    if (o->precision != LAIR_FP64 && o->precision != LAIR_MIXED &&
+        o->precision != LAIR_MIXED_LOCAL)
         fail(LAIR_EINVAL, "unknown precision %d", o->precision);
     if (!(o->omega > 0.0 && o->omega <= 2.0)) fail(LAIR_EINVAL, "omega must lie in (0, 2]");
     if (o->max_levels < 1 || o->max_levels > 64) fail(LAIR_EINVAL, "max_levels must lie in [1, 64]");
@@ -425,7 +426,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.flags.alloc((size_t)Lv.nc, s);
     LocalSolveOut out{R.rp.get(), R.cj.get(), R.v.get(), Lv.flags.get()};
     int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
-                                 A.rp.get(), A.cj.get(), A.v.get(), h->opt.precision,
+                                 A.rp.get(), A.cj.get(), A.v.get(),
+                                 h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED,
                                  Lv.st.s_max, out, s);
     Lv.st.n_singular = nsing;
     h->n_singular += nsing;
@@ -1269,6 +1271,110 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
     return conv ? LAIR_OK : LAIR_ENOCONV;
 }
 
+// ---------------------------------------------------------------------------
+// New diagonal, same hierarchy structure: the strength masks, splittings,
+// neighbourhoods and every sparsity pattern are kept; the local solves, the
+// interpolation weights, the Galerkin products and the coarsest factors are
+// recomputed from the new level-0 values.
+// ---------------------------------------------------------------------------
+__global__ void k_check_diag(int32_t n, const double *d, int32_t *bad) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = d[i];
+    if (!isfinite(x) || x == 0.0) atomicOr(bad, 1);
+}
+
+__global__ void k_set_diag(int32_t n, const int32_t *rp, const int32_t *cj, double *v,
+                           const double *d) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = rp[i], hi = rp[i + 1] - 1;
+    while (lo <= hi) {                         // columns are sorted; the diagonal is stored
+        int mid = (lo + hi) >> 1;
+        int c = cj[mid];
+        if (c == i) { v[mid] = d[i]; return; }
+        if (c < i) lo = mid + 1; else hi = mid - 1;
+    }
+}
+
+static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_device,
+                             hipStream_t s) {
+    if (!h || !diag) fail(LAIR_EINVAL, "hierarchy and diag must not be NULL");
+    if (h->opt.block_size > 0)
+        fail(LAIR_EUNSUPPORTED, "a new diagonal changes the block scaling: set up again");
+    h->stream = s;
+    Level &L0 = *h->L[0];
+    const int32_t n = L0.n;
+    DevArr<double> d;
+    const double *dd = diag;
+    if (!on_device) {
+        d.alloc((size_t)n, s);
+        LAIR_HIP(hipMemcpyAsync(d.get(), diag, sizeof(double) * n, hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipStreamSynchronize(s));     // diag is pageable caller memory
+        dd = d.get();
+    }
+    DevArr<int32_t> bad;
+    bad.alloc(1, s);
+    LAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int32_t), s));
+    LAIR_LAUNCH(k_check_diag, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, dd, bad.get());
+    LAIR_LAUNCH_CHECK();
+    int32_t hb = 0;
+    {
+        Readback rb(s);
+        rb.add(&hb, bad.get(), sizeof(int32_t));
+        rb.run();
+    }
+    if (hb) fail(LAIR_EINVAL, "the new diagonal has a zero or non-finite entry");
+    LAIR_LAUNCH(k_set_diag, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, L0.A.rp.get(),
+                L0.A.cj.get(), L0.A.v.get(), dd);
+    LAIR_LAUNCH_CHECK();
+    h->drop_graphs();
+    h->have_transpose = false;
+    h->n_singular = 0;
+    DevArr<int64_t> tmp;
+    const int32_t prec = h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED;
+    for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+        Level &Lv = *h->L[l];
+        const DevCSR &A = Lv.A;
+        LocalSolveOut out{Lv.R.rp.get(), Lv.R.cj.get(), Lv.R.v.get(), Lv.flags.get()};
+        int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
+                                     A.rp.get(), A.cj.get(), A.v.get(), prec, Lv.st.s_max, out,
+                                     s);
+        Lv.st.n_singular = nsing;
+        h->n_singular += nsing;
+        if (h->opt.interp == LAIR_P_DIRECT) {
+            // one-point weights are 1 on a kept pattern; direct weights use values
+            ProfScope ps("interp", s, 14.0 * A.nnz + 13.0 * Lv.n + 12.0 * Lv.P.nnz);
+            launch_interp_direct(Lv.n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                 Lv.cf.get(), Lv.cidx.get(), true, nullptr, Lv.P.rp.get(),
+                                 Lv.P.cj.get(), Lv.P.v.get(),
+                                 Lv.n ? (double)A.nnz / Lv.n : 1.0, s);
+        }
+        DevCSR AP, K;
+        spgemm(Lv.A, Lv.max_row, Lv.P, AP, s, tmp);
+        int32_t mr = spgemm(Lv.R, Lv.st.s_max + 1, AP, K, s, tmp);
+        Level &Nx = *h->L[l + 1];
+        if (K.nnz != Nx.A.nnz)
+            fail(LAIR_EDEVICE, "coarse operator pattern changed on update (level %zu)", l + 1);
+        Nx.A = std::move(K);
+        Nx.max_row = mr;
+    }
+    finish_coarsest(h);
+    if (h->opt.precision == LAIR_MIXED) {
+        for (auto &lp : h->L) {
+            Level &Lv = *lp;
+            // the new coarse operators carry no float copy yet
+            if (Lv.A.v32.get() == nullptr)
+                Lv.A.v32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+            launch_to_float(Lv.A.v.get(), Lv.A.v32.get(), Lv.A.nnz, s);
+            if (Lv.R.nnz) launch_to_float(Lv.R.v.get(), Lv.R.v32.get(), Lv.R.nnz, s);
+            if (Lv.P.nnz) launch_to_float(Lv.P.v.get(), Lv.P.v32.get(), Lv.P.nnz, s);
+        }
+    }
+    level_stats_and_cc(h);
+    LAIR_HIP(hipStreamSynchronize(s));
+}
+
 // Union of a batch: the systems' matrices placed block-diagonally, rows of
 // system q at [seg[q], seg[q+1]).
 static lair_hierarchy *setup_batch_impl(int32_t nsys, const lair_csr *sys,
@@ -1437,6 +1543,14 @@ lair_status lair_solve_batch(lair_hierarchy *h, const double *b, double *x, doub
 }
 
 int32_t lair_num_systems(const lair_hierarchy *h) { return h ? h->nsys : 0; }
+
+lair_status lair_update_diag(lair_hierarchy *h, const double *diag, int32_t on_device,
+                             void *stream) {
+    return guarded([&]() -> lair_status {
+        update_diag_impl(h, diag, on_device, (hipStream_t)stream);
+        return LAIR_OK;
+    });
+}
 
 lair_status lair_system_levels(const lair_hierarchy *h, int32_t *levels) {
     return guarded([&]() -> lair_status {

@@ -561,3 +561,79 @@ def test_dg_reproduces_constants_and_block_scaling():
         blk = D[6 * e:6 * e + 6, 6 * e:6 * e + 6]
         assert np.abs(blk - np.eye(6)).max() <= 1e-12
     assert np.abs(As @ np.ones(A.shape[0]) - bs).max() <= 1e-12
+
+
+# ---------------------------------------------------------------- new diagonal
+
+def _with_diag(A, d):
+    B = A.tocsr(copy=True)
+    B.setdiag(d)
+    B.sort_indices()
+    return B
+
+
+def test_update_diag_satisfies_the_local_systems_and_galerkin():
+    """After a new diagonal, every row of Z solves its local system with the
+    new values on the kept N_i (Eq. (johnair): (Z A + A_cf)(i, N_i) = 0,
+    checked densely) and each coarse operator is R A P (dense products)."""
+    w = W.workload_c4(16)
+    A = (_mat(w) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    H = O.setup(A, interp=O.INTERP_DIRECT, max_coarse=20)
+    assert H.nlevels >= 3
+    d_new = A.diagonal() * (1.0 + 0.5 * np.random.default_rng(7).random(A.shape[0]))
+    O.update_diag(H, d_new)
+    A_new = _with_diag(A, d_new)
+    assert np.array_equal(H.levels[0].A.toarray(), A_new.toarray())
+    for l, L in enumerate(H.levels[:-1]):
+        D = L.A.toarray()
+        R = L.R.toarray()
+        for c, i in enumerate(L.cpts):
+            nb = L.nbr[L.nptr[c]:L.nptr[c + 1]]
+            if nb.shape[0] == 0:
+                continue
+            res = R[c] @ D[:, nb]
+            assert np.abs(res).max() <= 1e-10 * np.abs(D[i]).max(), (l, c)
+        K = R @ D @ L.P.toarray()
+        Kn = H.levels[l + 1].A.toarray()
+        assert np.abs(Kn - K).max() <= 1e-12 * np.abs(K).max()
+
+
+def test_update_diag_keeps_structure_and_identity():
+    """The same diagonal gives back the same hierarchy, bit for bit; a new
+    one keeps every pattern and the splittings."""
+    w = W.workload_c4(16)
+    A = (_mat(w) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    H = O.setup(A, interp=O.INTERP_DIRECT, max_coarse=20)
+    ref = [(L.A.copy(), L.R.copy(), L.P.copy()) for L in H.levels[:-1]]
+    O.update_diag(H, A.diagonal())
+    for (A0, R0, P0), L in zip(ref, H.levels[:-1]):
+        for X, Y in ((A0, L.A), (R0, L.R), (P0, L.P)):
+            assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+            assert np.array_equal(X.data, Y.data)
+    O.update_diag(H, 2.0 * A.diagonal())
+    for (A0, R0, P0), L in zip(ref, H.levels[:-1]):
+        for X, Y in ((A0, L.A), (R0, L.R), (P0, L.P)):
+            assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+    # direct weights are -alpha a_ik / a_ii with alpha free of the diagonal:
+    # doubling the diagonal halves the F rows of P_0 and keeps its C rows
+    P0, P1 = ref[0][2].toarray(), H.levels[0].P.toarray()
+    F = H.levels[0].cf == 0
+    assert np.abs(P1[F] - 0.5 * P0[F]).max() <= 1e-15 * np.abs(P0[F]).max()
+    assert np.array_equal(P1[~F], P0[~F])
+
+
+def test_update_diag_chain_still_solves_in_one_cycle():
+    """On the upwind chain the structure does not depend on the diagonal, so
+    after a new (positive) diagonal one V-cycle is still an exact solve."""
+    n = 129
+    A = _mat(W.chain_1d(n))
+    H = O.setup(A, max_coarse=2)
+    d = 1.0 + np.random.default_rng(3).random(n)
+    O.update_diag(H, d)
+    A_new = _with_diag(A, d)
+    b = np.random.default_rng(4).standard_normal(n)
+    x = O.cycle(H, b, np.zeros(n))
+    xs = spla.spsolve(A_new.tocsc(), b)
+    assert np.abs(x - xs).max() <= 1e-12 * np.abs(xs).max()
