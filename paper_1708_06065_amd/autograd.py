@@ -28,7 +28,10 @@ class LairSolve(torch.autograd.Function):
 
     b: (n,) or (n, nrhs) float64 CUDA tensor; c: (n,) float64 CUDA tensor
     added to the diagonal of the CSR matrix (rowptr, col, val0);
-    opts: dict of lair.setup keyword arguments plus rtol and maxit.
+    opts: dict of lair.setup keyword arguments plus rtol, maxit and
+    optionally reuse, a dict the caller keeps across calls: the first call
+    stores its hierarchy there and later calls only replace its diagonal
+    (lair_update_diag) instead of setting up again.
     """
 
     @staticmethod
@@ -36,14 +39,22 @@ class LairSolve(torch.autograd.Function):
         opts = dict(opts or {})
         rtol = opts.pop("rtol", 1e-10)
         maxit = opts.pop("maxit", 200)
+        reuse = opts.pop("reuse", None)
         pos = _diag_positions(rowptr, col)
         val = val0.clone()
         val[pos] += c
-        h = _setup(rowptr, col, val, **opts)
+        if reuse is not None and reuse.get("h") is not None:
+            h = reuse["h"]
+            h.update_diag(val[pos].contiguous())
+        else:
+            h = _setup(rowptr, col, val, **opts)
+            if reuse is not None:
+                reuse["h"] = h
         x, info = h.solve(b.contiguous(), rtol=rtol, maxit=maxit)
         if not info["converged"]:
             raise RuntimeError("lAIR forward solve did not converge: %r" % info)
         ctx.h = h
+        ctx.keep = reuse is not None
         ctx.rtol, ctx.maxit = rtol, maxit
         ctx.save_for_backward(x)
         ctx.info = info
@@ -60,5 +71,6 @@ class LairSolve(torch.autograd.Function):
         gc = None
         if ctx.needs_input_grad[1]:
             gc = -(lam * x) if lam.dim() == 1 else -(lam * x).sum(dim=1)
-        ctx.h.free()
+        if not ctx.keep:
+            ctx.h.free()
         return gb, gc, None, None, None, None

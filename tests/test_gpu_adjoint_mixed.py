@@ -144,6 +144,34 @@ def test_gradients_wrt_b_and_c(lair):
     assert worst <= 1e-5
 
 
+def test_gradients_with_reused_hierarchy(lair):
+    """Two reaction fields in a row through one kept hierarchy (the second
+    call only replaces the diagonal): gradients equal the dense adjoint's."""
+    import torch
+    from paper_1708_06065_amd.autograd import LairSolve
+    w, A0, _ = _c4(48)
+    n = A0.shape[0]
+    dev = "cuda"
+    rp = torch.as_tensor(A0.indptr.astype(np.int32), device=dev)
+    cj = torch.as_tensor(A0.indices.astype(np.int32), device=dev)
+    v0 = torch.as_tensor(A0.data, device=dev)
+    xo = torch.as_tensor(w["x_obs"], device=dev)
+    reuse = {}
+    for scale in (1.0, 1.7):
+        c = w["c"] * scale
+        bt = torch.ones(n, dtype=torch.float64, device=dev, requires_grad=True)
+        ct = torch.tensor(c, device=dev, requires_grad=True)
+        x = LairSolve.apply(bt, ct, rp, cj, v0, {"interp": "direct", "rtol": 1e-12,
+                                                 "reuse": reuse})
+        ((x - xo) ** 2).sum().backward()
+        D = (A0 + sp.diags(c)).toarray()
+        xs = np.linalg.solve(D, np.ones(n))
+        lam = np.linalg.solve(D.T, 2.0 * (xs - w["x_obs"]))
+        assert np.linalg.norm(bt.grad.cpu().numpy() - lam) <= 1e-8 * np.linalg.norm(lam)
+        assert np.linalg.norm(ct.grad.cpu().numpy() + lam * xs) <= 1e-8 * np.linalg.norm(lam * xs)
+    reuse["h"].free()
+
+
 # ------------------------------------------------------------------ mixed
 
 @pytest.mark.parametrize("case", ["euler3d", "dg"])
@@ -188,6 +216,24 @@ def test_mixed_local_solves_within_refinement_bound(lair, case):
             worst_ratio = max(worst_ratio, err / bound)
             assert err <= bound, (l, c, err, kappa)
     _say("  worst error / refinement bound:", worst_ratio)
+
+
+def test_mixed_local_precision_solve(lair):
+    """Float local solves with one double refinement, double cycle: the same
+    cycle count as FP64 (at most one more) and the FP64 residual."""
+    w = W.implicit_euler_adr_3d(m=24, nrhs=4)
+    h64 = lair.setup(w["rowptr"], w["col"], w["val"], interp="direct")
+    hml = lair.setup(w["rowptr"], w["col"], w["val"], interp="direct", precision="mixed_local")
+    B = _dev(w["rhs"])
+    x64, i64 = h64.solve(B, rtol=1e-10)
+    xml, iml = hml.solve(B, rtol=1e-10)
+    _say("  iterations fp64", i64["iters"], "mixed_local", iml["iters"])
+    assert iml["converged"] and iml["iters"] <= i64["iters"] + 1
+    A = O.csr(w["rowptr"], w["col"], w["val"])
+    X = xml.cpu().numpy()
+    for q in range(4):
+        r = w["rhs"][:, q] - A @ X[:, q]
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(w["rhs"][:, q])
 
 
 def test_mixed_solve_reaches_fp64_tolerance(lair):
