@@ -285,6 +285,12 @@ def main():
             log("residual check skipped:", e)
             rel = None
         h.free()
+        if batch:
+            its = np.asarray(infos[-1]["sys_iters"], dtype=np.float64)
+            nz = np.array([q["nnz"] for q in w["systems"]], dtype=np.float64)
+            log("%s: cycles per system min %d median %d max %d; useful share of the union's "
+                "cycle work %.3f" % (prec, its.min(), np.median(its), its.max(),
+                                     (nz * its).sum() / (nz.sum() * its.max())))
         results[prec] = dict(ms=float(np.median(times)), ms_all=times, iters=infos[-1]["iters"],
                              relres=infos[-1]["relres"], relres_check=rel,
                              setup_ms=infos[-1]["setup_ms"], solve_ms=infos[-1]["solve_ms"],

@@ -206,8 +206,8 @@ lair_status lair_setup_batch(int32_t nsys, const lair_csr *A, const lair_cf_leve
 
 /* Stationary iteration x += B (b - A x) on the union (b, x: device vectors
  * of the union's length, system q at rows [o_q, o_q + n_q)), each system
- * stopping on its own when ||b_q - A_q x_q||_2 <= rtol ||b_q||_2; the
- * residuals of stopped systems are zeroed so that their corrections vanish.
+ * stopping on its own when ||b_q - A_q x_q||_2 <= rtol ||b_q||_2; from then
+ * on the cycle skips its rows (its x is final).
  * iters[q] and relres[q] (host arrays of nsys entries, may be NULL) return
  * the cycles spent on system q and its final relative residual; info (may
  * be NULL) gets the maximum of both.  ENOCONV when a system has not

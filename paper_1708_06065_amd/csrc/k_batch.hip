@@ -126,11 +126,45 @@ int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
     return (int32_t)cnt;
 }
 
+// All active-row lists of a batch in one launch.  The outputs are laid end
+// to end in one index space; segment j covers [seg_out[j], seg_out[j+1]) of
+// it and copies `len` consecutive entries of list `lst[j]`'s source from
+// seg_src[j] (or the row ids themselves when that list has no source) to
+// its output at seg_dst[j].  No atomics: every position has one writer.
+__global__ void k_materialize(int32_t nseg, const int64_t *seg_out, const int32_t *seg_src,
+                              const int32_t *seg_dst, const int32_t *lst,
+                              const int32_t *const *srcs, int32_t *const *dsts) {
+    const int64_t total = seg_out[nseg];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (seg_out[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const int32_t off = (int32_t)(k - seg_out[lo]);
+        const int32_t *src = srcs[lst[lo]];
+        const int32_t v = src ? src[seg_src[lo] + off] : seg_src[lo] + off;
+        dsts[lst[lo]][seg_dst[lo] + off] = v;
+    }
+}
+
+void launch_materialize(int32_t nseg, int64_t total, const int64_t *seg_out,
+                        const int32_t *seg_src, const int32_t *seg_dst, const int32_t *lst,
+                        const int32_t *const *srcs, int32_t *const *dsts, hipStream_t s) {
+    if (nseg == 0 || total == 0) return;
+    const int64_t b = (total + 255) / 256;
+    LAIR_LAUNCH(k_materialize, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, nseg,
+                seg_out, seg_src, seg_dst, lst, srcs, dsts);
+    LAIR_LAUNCH_CHECK();
+}
+
 // Per-system sum of squares (one block per system, fixed order).
 __global__ void __launch_bounds__(256)
-k_seg_sumsq(const int64_t *seg, const double *r, double *out) {
+k_seg_sumsq(const int64_t *seg, const uint8_t *active, const double *r, double *out) {
     __shared__ double sh[256];
     int32_t s = blockIdx.x;
+    if (active && !active[s]) return;      // a finished system keeps its last norm
     double acc = 0.0;
     for (int64_t i = seg[s] + threadIdx.x; i < seg[s + 1]; i += 256) acc += r[i] * r[i];
     sh[threadIdx.x] = acc;
@@ -143,24 +177,8 @@ k_seg_sumsq(const int64_t *seg, const double *r, double *out) {
 }
 
 void launch_seg_sumsq(int32_t nsys, const int64_t *seg, const double *r, double *out,
-                      hipStream_t s) {
-    LAIR_LAUNCH(k_seg_sumsq, dim3(nsys), dim3(256), 0, s, seg, r, out);
-    LAIR_LAUNCH_CHECK();
-}
-
-// Zero the residual of systems that are no longer iterated, so that the
-// (block-diagonal, linear) cycle returns a zero correction for them.
-__global__ void k_mask_rows(int32_t nsys, const int64_t *seg, const uint8_t *active,
-                            double *r, int64_t nrows) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
-    if (!active[seg_of(seg, nsys, i)]) r[i] = 0.0;
-}
-
-void launch_mask_rows(int32_t nsys, const int64_t *seg, const uint8_t *active, double *r,
-                      int64_t nrows, hipStream_t s) {
-    LAIR_LAUNCH(k_mask_rows, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
-                       nsys, seg, active, r, nrows);
+                      hipStream_t s, const uint8_t *active) {
+    LAIR_LAUNCH(k_seg_sumsq, dim3(nsys), dim3(256), 0, s, seg, active, r, out);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -245,8 +263,10 @@ k_block_lu(const int64_t *seg, const int64_t *doff, double *dense, int32_t *piv,
 // and right-hand side column held in place (nrhs = 1).
 __global__ void __launch_bounds__(256)
 k_block_solve(const int64_t *seg, const int64_t *doff, const double *dense,
-              const int32_t *piv, const double *b, double *x, int transpose) {
+              const int32_t *piv, const double *b, double *x, int transpose,
+              const uint8_t *active) {
     int32_t s = blockIdx.x;
+    if (active && !active[s]) return;
     int t = threadIdx.x;
     const int n = (int)(seg[s + 1] - seg[s]);
     const double *a = dense + doff[s];
@@ -303,9 +323,9 @@ void launch_block_lu(int32_t nsys, const int64_t *seg, const int64_t *doff, doub
 
 void launch_block_solve(int32_t nsys, const int64_t *seg, const int64_t *doff,
                         const double *dense, const int32_t *piv, const double *b, double *x,
-                        bool transpose, hipStream_t s) {
+                        bool transpose, hipStream_t s, const uint8_t *active) {
     LAIR_LAUNCH(k_block_solve, dim3(nsys), dim3(256), 0, s, seg, doff, dense, piv, b, x,
-                       transpose ? 1 : 0);
+                       transpose ? 1 : 0, active);
     LAIR_LAUNCH_CHECK();
 }
 

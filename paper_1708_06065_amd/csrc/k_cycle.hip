@@ -300,6 +300,38 @@ k_rowdot1(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
     }
 }
 
+// One right-hand side over a listed subset of rows: rows[k] for k < *cnt
+// (the list and its length live on the device; the grid covers the list's
+// capacity).
+template <class VT, int T, int MODE>
+__global__ void __launch_bounds__(256)
+k_rowdot_list(const int32_t *rows, const int32_t *cnt, const int32_t *rp, const int32_t *cj,
+              const VT *v, const VT *x, const VT *b, VT *y) {
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int lane = (int)(gt % T);
+    const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / T);
+    const int32_t n = *cnt;
+    for (int64_t k = gt / T; k < n; k += nteams) {
+        const int32_t i = rows[k];
+        VT acc = (VT)0, d = (VT)0;
+        row_acc1<VT, T, false>(rp[i], rp[i + 1], lane, -1, cj, v, x, x, nullptr, acc, d);
+        acc = team_sum<T>(acc);
+        if (lane == 0) {
+            if (MODE == MODE_RESID) y[i] = b[i] - acc;
+            else if (MODE == MODE_SET) y[i] = acc;
+            else y[i] += acc;
+        }
+    }
+}
+
+// Grid for kernels that stride over a device-side count: the blocks that
+// fill every CU once (more would mostly find nothing to do).
+constexpr int64_t LIST_GRID = 2048;
+static inline unsigned list_grid(int64_t threads) {
+    const int64_t b = (threads + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b < LIST_GRID ? b : LIST_GRID));
+}
+
 template <class VT, int NR, int MODE>
 __global__ void __launch_bounds__(256)
 k_rowdotM(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
@@ -386,6 +418,34 @@ void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
     else rowdot<VT, MODE_SET>(A, x, nullptr, y, nrhs, s);
 }
 
+template <class VT, int MODE>
+static void rowdot_list_t(const CsrView<VT> &A, const int32_t *rows, const int32_t *cnt,
+                          int32_t cap, const VT *x, const VT *b, VT *y, hipStream_t s) {
+#define LAIR_RL(TT)                                                                    \
+    LAIR_LAUNCH((k_rowdot_list<VT, TT, MODE>), dim3(list_grid((int64_t)cap * TT)),     \
+                dim3(256), 0, s, rows, cnt, A.rp, A.cj, A.v, x, b, y)
+    switch (A.team) {
+        case 1: LAIR_RL(1); break;
+        case 2: LAIR_RL(2); break;
+        case 4: LAIR_RL(4); break;
+        case 8: LAIR_RL(8); break;
+        case 16: LAIR_RL(16); break;
+        case 32: LAIR_RL(32); break;
+        default: LAIR_RL(64); break;
+    }
+#undef LAIR_RL
+    LAIR_LAUNCH_CHECK();
+}
+
+template <class VT>
+void op_rowdot_list(const CsrView<VT> &A, int mode, const int32_t *rows, const int32_t *cnt,
+                    int32_t cap, const VT *x, const VT *b, VT *y, hipStream_t s) {
+    if (cap == 0) return;
+    if (mode == MODE_RESID) rowdot_list_t<VT, MODE_RESID>(A, rows, cnt, cap, x, b, y, s);
+    else if (mode == MODE_SET) rowdot_list_t<VT, MODE_SET>(A, rows, cnt, cap, x, b, y, s);
+    else rowdot_list_t<VT, MODE_ADD>(A, rows, cnt, cap, x, b, y, s);
+}
+
 // ---------------------------------------------------------------------------
 // Jacobi on a row set X:  new_i = x_i + omega (b_i - (A x)_i) / a_ii for
 // i = X[k], written to out[k] (compact) or out[i].  Every row reads the
@@ -393,21 +453,23 @@ void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
 // ---------------------------------------------------------------------------
 template <class VT, int T, bool SEL>
 __global__ void __launch_bounds__(256)
-k_jacobi1(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
-          const VT *v, const VT *b, const VT *xF, const VT *xC,
+k_jacobi1(int32_t nx, const int32_t *cnt, const int32_t *rows, const int32_t *rp,
+          const int32_t *cj, const VT *v, const VT *b, const VT *xF, const VT *xC,
           const int8_t *cf, VT *out, int compact, VT omega) {
-    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
-    int32_t k = (int32_t)(gt / T);
-    int lane = (int)(gt % T);
-    if (k >= nx) return;
-    int32_t i = rows[k];
-    VT acc = (VT)0, d = (VT)0;
-    row_acc1<VT, T, SEL>(rp[i], rp[i + 1], lane, i, cj, v, xF, xC, cf, acc, d);
-    acc = team_sum<T>(acc);
-    d = team_sum<T>(d);
-    if (lane == 0) {
-        VT xi = src_val<VT, SEL>(xF, xC, cf, i, i);
-        out[compact ? k : i] = xi + omega * (b[i] - acc) / d;
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int lane = (int)(gt % T);
+    const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / T);
+    const int32_t n = cnt ? *cnt : nx;
+    for (int64_t k = gt / T; k < n; k += nteams) {
+        int32_t i = rows[k];
+        VT acc = (VT)0, d = (VT)0;
+        row_acc1<VT, T, SEL>(rp[i], rp[i + 1], lane, i, cj, v, xF, xC, cf, acc, d);
+        acc = team_sum<T>(acc);
+        d = team_sum<T>(d);
+        if (lane == 0) {
+            VT xi = src_val<VT, SEL>(xF, xC, cf, i, i);
+            out[compact ? k : i] = xi + omega * (b[i] - acc) / d;
+        }
     }
 }
 
@@ -430,8 +492,10 @@ k_jacobiM(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
 
 template <class VT, bool SEL>
 static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
-                          const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
-                          VT *out, int compact, VT om, int32_t nrhs, hipStream_t s) {
+                          const int32_t *cnt, const VT *b, const VT *xF, const VT *xC,
+                          const int8_t *cf, VT *out, int compact, VT om, int32_t nrhs,
+                          hipStream_t s) {
+    if (cnt && nrhs != 1) fail(LAIR_EINVAL, "listed Jacobi rows take one right-hand side");
     if (nrhs > 1 && aligned16(b) && aligned16(xF) && aligned16(xC) && aligned16(out)) {
         constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
 #define LAIR_JV(NN, WW)                                                           \
@@ -475,8 +539,8 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
     }
 #define LAIR_JC(TT)                                                              \
     LAIR_LAUNCH((k_jacobi1<VT, TT, SEL>),                                 \
-                       dim3(blocks_for((int64_t)nx * TT, 256)), dim3(256), 0, s, \
-                       nx, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
+                       dim3(cnt ? list_grid((int64_t)nx * TT) : blocks_for((int64_t)nx * TT, 256)), \
+                       dim3(256), 0, s, nx, cnt, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
     switch (A.team) {
         case 1: LAIR_JC(1); break;
         case 2: LAIR_JC(2); break;
@@ -494,32 +558,36 @@ template <class VT>
 void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
                const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
                VT *out, bool compact, double omega, int32_t nrhs,
-               hipStream_t s) {
+               hipStream_t s, const int32_t *cnt) {
     if (nx == 0) return;
     VT om = (VT)omega;
     if (cf)
-        jacobi_launch<VT, true>(A, rows, nx, b, xF, xC, cf, out, compact ? 1 : 0, om, nrhs, s);
+        jacobi_launch<VT, true>(A, rows, nx, cnt, b, xF, xC, cf, out, compact ? 1 : 0, om,
+                                nrhs, s);
     else
-        jacobi_launch<VT, false>(A, rows, nx, b, xF, xF, nullptr, out, compact ? 1 : 0, om, nrhs, s);
+        jacobi_launch<VT, false>(A, rows, nx, cnt, b, xF, xF, nullptr, out, compact ? 1 : 0,
+                                 om, nrhs, s);
 }
 
 template <class VT>
 __global__ void k_scatter(int64_t total, int32_t nrhs, const int32_t *rows,
-                          const VT *t, VT *x) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    int64_t k = g / nrhs;
-    int q = (int)(g % nrhs);
-    x[(int64_t)rows[k] * nrhs + q] = t[g];
+                          const int32_t *cnt, const VT *t, VT *x) {
+    const int64_t n = cnt ? (int64_t)*cnt * nrhs : total;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = g / nrhs;
+        int q = (int)(g % nrhs);
+        x[(int64_t)rows[k] * nrhs + q] = t[g];
+    }
 }
 
 template <class VT>
 void op_scatter(const int32_t *rows, int32_t nx, const VT *t, VT *x,
-                int32_t nrhs, hipStream_t s) {
+                int32_t nrhs, hipStream_t s, const int32_t *cnt) {
     if (nx == 0) return;
     int64_t total = (int64_t)nx * nrhs;
-    LAIR_LAUNCH((k_scatter<VT>), dim3(blocks_for(total, 256)), dim3(256), 0, s,
-                       total, nrhs, rows, t, x);
+    LAIR_LAUNCH((k_scatter<VT>), dim3(cnt ? list_grid(total) : blocks_for(total, 256)),
+                dim3(256), 0, s, total, nrhs, rows, cnt, t, x);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -776,6 +844,24 @@ void launch_tag_columns(int64_t nnz, const int32_t *cj, const int8_t *cf, int32_
 // ---------------------------------------------------------------------------
 // Mixed precision helpers and block scaling of right-hand sides.
 // ---------------------------------------------------------------------------
+template <class ET>
+__global__ void k_update_list(const int32_t *rows, const int32_t *cnt, double *x, const ET *e) {
+    const int32_t n = *cnt;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = rows[k];
+        x[i] += (double)e[i];
+    }
+}
+
+template <class ET>
+void op_update_list(const int32_t *rows, const int32_t *cnt, int32_t cap, double *x,
+                    const ET *e, hipStream_t s) {
+    if (cap == 0) return;
+    LAIR_LAUNCH((k_update_list<ET>), dim3(list_grid(cap)), dim3(256), 0, s, rows, cnt, x, e);
+    LAIR_LAUNCH_CHECK();
+}
+
 __global__ void k_axpy_f32(double *x, const float *e, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] += (double)e[i];
@@ -837,12 +923,16 @@ template void op_residual<double>(const CsrView<double> &, const double *, const
 template void op_residual<float>(const CsrView<float> &, const float *, const float *, float *, int32_t, hipStream_t);
 template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t);
 template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t);
-template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t);
-template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t);
+template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t, const int32_t *);
+template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t, const int32_t *);
+template void op_rowdot_list<double>(const CsrView<double> &, int, const int32_t *, const int32_t *, int32_t, const double *, const double *, double *, hipStream_t);
+template void op_rowdot_list<float>(const CsrView<float> &, int, const int32_t *, const int32_t *, int32_t, const float *, const float *, float *, hipStream_t);
+template void op_update_list<double>(const int32_t *, const int32_t *, int32_t, double *, const double *, hipStream_t);
+template void op_update_list<float>(const int32_t *, const int32_t *, int32_t, double *, const float *, hipStream_t);
 template void op_coarse_apply<double>(int32_t, const double *, const double *, double *, int32_t, bool, hipStream_t);
 template void op_coarse_apply<float>(int32_t, const double *, const float *, float *, int32_t, bool, hipStream_t);
-template void op_scatter<double>(const int32_t *, int32_t, const double *, double *, int32_t, hipStream_t);
-template void op_scatter<float>(const int32_t *, int32_t, const float *, float *, int32_t, hipStream_t);
+template void op_scatter<double>(const int32_t *, int32_t, const double *, double *, int32_t, hipStream_t, const int32_t *);
+template void op_scatter<float>(const int32_t *, int32_t, const float *, float *, int32_t, hipStream_t, const int32_t *);
 template void op_fill<double>(double *, double, int64_t, hipStream_t);
 template void op_fill<float>(float *, float, int64_t, hipStream_t);
 template void op_copy<double>(const double *, double *, int64_t, hipStream_t);

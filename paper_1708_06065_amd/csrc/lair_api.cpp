@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -63,6 +64,9 @@ struct Level {
     DevArr<uint8_t> stopped_dev;
     DevArr<int32_t> rclist;
     int32_t nrc = -1;                 // -1: relax every C row (clist)
+    // rows of the systems still iterated (batch solve): all rows, F rows,
+    // relaxed C rows; their lengths in act_cnt[0..2] on the device
+    DevArr<int32_t> act_rows, act_f, act_c, act_cnt;
     // cycle work vectors (capacity h->nrhs_cap right-hand sides)
     DevArr<double> b, x, t, r;
     DevArr<float> b32, x32, t32, r32;
@@ -95,6 +99,7 @@ struct lair_hierarchy {
     // captured correction cycles, keyed by (precision, nrhs); replayed on a
     // private stream ordered against the caller's stream with events
     bool batch = false;                      // built by lair_setup_batch
+    bool use_act = false;                    // cycles restricted to the active rows
     std::vector<uint8_t> active;             // systems still iterated
     // captured solve iterations (cycle + residual + norms), keyed by the
     // iteration kind, the number of right-hand sides and the caller's b and
@@ -802,13 +807,14 @@ static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
                  2.0 * h->nL * (double)h->nL * nrhs);
     if (h->nsys > 1) {
         Level &Lb = *h->L.back();
+        const uint8_t *act = h->use_act ? h->active_dev.get() : nullptr;
         if constexpr (std::is_same<VT, double>::value) {
             launch_block_solve(h->nsys, Lb.seg_dev.get(), h->dense_off.get(), h->lu.get(),
-                               h->piv.get(), b, x, transpose, s);
+                               h->piv.get(), b, x, transpose, s, act);
         } else {
             op_cast_f64(b, Lb.r.get(), h->nL, s);
             launch_block_solve(h->nsys, Lb.seg_dev.get(), h->dense_off.get(), h->lu.get(),
-                               h->piv.get(), Lb.r.get(), Lb.x.get(), transpose, s);
+                               h->piv.get(), Lb.r.get(), Lb.x.get(), transpose, s, act);
             op_cast_f32(Lb.x.get(), x, h->nL, s);
         }
         return;
@@ -842,28 +848,34 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     VT *y = vec<VT>(Lv.t, Lv.t32);
     double om = h->opt.omega;
     const int w = sizeof(VT);
+    // batch solve: only the rows of the systems still iterated (device lists)
+    const bool act = h->use_act;
+    const int32_t *frows = act ? Lv.act_f.get() : Lv.flist.get();
+    const int32_t *fcnt = act ? Lv.act_cnt.get() + 1 : nullptr;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzF * nrhs);
-        op_jacobi<VT>(A, Lv.flist.get(), Lv.nf, b, x, x, nullptr, y, false, om, nrhs, s);
+        op_jacobi<VT>(A, frows, Lv.nf, b, x, x, nullptr, y, false, om, nrhs, s, fcnt);
     }
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, true),
                      2.0 * Lv.nnzF * nrhs);
         CsrView<VT> At = A;
         At.cjt = Lv.cjt.get();
-        op_jacobi<VT>(At, Lv.flist.get(), Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s);
+        op_jacobi<VT>(At, frows, Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s, fcnt);
     }
-    const int32_t *crows = Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get();
+    const int32_t *crows = act ? Lv.act_c.get()
+                               : (Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get());
+    const int32_t *ccnt = act ? Lv.act_cnt.get() + 2 : nullptr;
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, ncr, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzC * nrhs);
-        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, true, om, nrhs, s);
+        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, true, om, nrhs, s, ccnt);
     }
     {
         ProfScope ps("scatter", s, 4.0 * ncr + 2.0 * w * nrhs * ncr);
-        op_scatter<VT>(crows, ncr, y, x, nrhs, s);
+        op_scatter<VT>(crows, ncr, y, x, nrhs, s, ccnt);
     }
 }
 
@@ -895,13 +907,21 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
     VT *xc = vec<VT>(Nx.x, Nx.x32);
     {
         ProfScope ps("restrict", s, ab_rowdot(Lv.R, w, nrhs, 1), 2.0 * Lv.R.nnz * nrhs);
-        op_spmv<VT>(view<VT>(Lv.R, Lv.team_R), res, bc, nrhs, false, s);
+        if (h->use_act)
+            op_rowdot_list<VT>(view<VT>(Lv.R, Lv.team_R), 1, Nx.act_rows.get(),
+                               Nx.act_cnt.get(), Nx.n, res, nullptr, bc, s);
+        else
+            op_spmv<VT>(view<VT>(Lv.R, Lv.team_R), res, bc, nrhs, false, s);
     }
     vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s);
     {
         ProfScope ps("interpolate", s, ab_rowdot(Lv.P, w, nrhs, x_zero ? 1 : 2),
                      2.0 * Lv.P.nnz * nrhs);
-        op_spmv<VT>(view<VT>(Lv.P, Lv.team_P), xc, x, nrhs, !x_zero, s);
+        if (h->use_act)
+            op_rowdot_list<VT>(view<VT>(Lv.P, Lv.team_P), x_zero ? 1 : 2, Lv.act_rows.get(),
+                               Lv.act_cnt.get(), Lv.n, xc, nullptr, x, s);
+        else
+            op_spmv<VT>(view<VT>(Lv.P, Lv.team_P), xc, x, nrhs, !x_zero, s);
     }
     ffc<VT>(h, Lv, b, x, nrhs, s);
 }
@@ -1171,7 +1191,120 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
     if (h->seg_norm.get() == nullptr) { h->seg_norm.alloc((size_t)ns, s); moved = true; }
     if (h->active_dev.get() == nullptr) { h->active_dev.alloc((size_t)ns, s); moved = true; }
     if (!mixed && h->e64.get() == nullptr) { h->e64.alloc((size_t)n, s); moved = true; }
+    // one system: the iteration stops when it converges, no lists needed
+    const bool lists = ns > 1;
+    if (lists && L0.act_cnt.get() == nullptr) {
+        for (size_t l = 0; l < h->L.size(); ++l) {
+            Level &Lv = *h->L[l];
+            Lv.act_cnt.alloc(3, s);
+            Lv.act_rows.alloc((size_t)std::max(Lv.n, 1), s);
+            if (l + 1 < h->L.size()) {
+                Lv.act_f.alloc((size_t)std::max(Lv.nf, 1), s);
+                Lv.act_c.alloc((size_t)std::max(Lv.nrc >= 0 ? Lv.nrc : Lv.nc, 1), s);
+            }
+        }
+        moved = true;
+    }
     if (moved) h->drop_graphs();
+    // rows of the systems still iterated, on every level.  A system's rows,
+    // F rows and relaxed C rows are contiguous runs of the level's row range,
+    // F list and relaxed-C list; the host lays out the runs of the active
+    // systems and one kernel copies them (no atomics, fixed order).
+    const size_t nlev = h->L.size();
+    std::vector<std::array<std::vector<int32_t>, 3>> runs(nlev);   // per list: prefix over systems
+    for (size_t l = 0; lists && l < nlev; ++l) {
+        Level &Lv = *h->L[l];
+        for (int t = 0; t < 3; ++t) runs[l][t].assign((size_t)ns + 1, 0);
+        const bool last = l + 1 == nlev;
+        for (int32_t q = 0; q < ns; ++q) {
+            const int32_t nq = (int32_t)(Lv.seg[q + 1] - Lv.seg[q]);
+            int32_t cq = 0, rq = 0;
+            if (!last) {
+                cq = (int32_t)(Lv.next_seg[q + 1] - Lv.next_seg[q]);
+                rq = Lv.stopped[q] ? 0 : cq;     // stopped systems' C rows are not relaxed
+            }
+            runs[l][0][q + 1] = runs[l][0][q] + nq;
+            runs[l][1][q + 1] = runs[l][1][q] + (last ? 0 : nq - cq);
+            runs[l][2][q + 1] = runs[l][2][q] + rq;
+        }
+    }
+    DevArr<const int32_t *> d_src;
+    DevArr<int32_t *> d_dst;
+    DevArr<int64_t> d_out;
+    DevArr<int32_t> d_meta, d_counts;
+    if (lists) {
+        std::vector<const int32_t *> srcs(3 * nlev, nullptr);
+        std::vector<int32_t *> dsts(3 * nlev, nullptr);
+        for (size_t l = 0; l < nlev; ++l) {
+            Level &Lv = *h->L[l];
+            dsts[3 * l] = Lv.act_rows.get();
+            if (l + 1 < nlev) {
+                srcs[3 * l + 1] = Lv.flist.get();
+                dsts[3 * l + 1] = Lv.act_f.get();
+                srcs[3 * l + 2] = Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get();
+                dsts[3 * l + 2] = Lv.act_c.get();
+            }
+        }
+        d_src.alloc(3 * nlev, s);
+        d_dst.alloc(3 * nlev, s);
+        LAIR_HIP(hipMemcpyAsync(d_src.get(), srcs.data(), sizeof(void *) * 3 * nlev,
+                                hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipMemcpyAsync(d_dst.get(), dsts.data(), sizeof(void *) * 3 * nlev,
+                                hipMemcpyHostToDevice, s));
+        const size_t maxseg = 3 * nlev * (size_t)ns;
+        d_out.alloc(maxseg + 1, s);
+        d_meta.alloc(3 * maxseg, s);
+        d_counts.alloc(3 * nlev, s);
+        LAIR_HIP(hipStreamSynchronize(s));     // the pointer tables are pageable host memory
+    }
+    auto rebuild_lists = [&]() {
+        std::vector<int64_t> out{0};
+        std::vector<int32_t> src, dst, lst;
+        std::vector<int32_t> counts(3 * nlev, 0);
+        for (size_t l = 0; l < nlev; ++l)
+            for (int t = 0; t < 3; ++t) {
+                if (t > 0 && l + 1 == nlev) continue;
+                int32_t pos = 0;
+                for (int32_t q = 0; q < ns; ++q) {
+                    if (!h->active[q]) continue;
+                    const int32_t len = runs[l][t][q + 1] - runs[l][t][q];
+                    if (len == 0) continue;
+                    const int32_t start = t == 0 ? (int32_t)h->L[l]->seg[q] : runs[l][t][q];
+                    out.push_back(out.back() + len);
+                    src.push_back(start);
+                    dst.push_back(pos);
+                    lst.push_back((int32_t)(3 * l + t));
+                    pos += len;
+                }
+                counts[3 * l + t] = pos;
+            }
+        const int32_t nseg = (int32_t)lst.size();
+        // one pinned staging area, copied in stream order
+        const size_t b_out = sizeof(int64_t) * out.size(), b_i = sizeof(int32_t) * nseg;
+        char *st = (char *)pinned_staging(b_out + 3 * b_i + sizeof(int32_t) * counts.size() + 64);
+        memcpy(st, out.data(), b_out);
+        memcpy(st + b_out, src.data(), b_i);
+        memcpy(st + b_out + b_i, dst.data(), b_i);
+        memcpy(st + b_out + 2 * b_i, lst.data(), b_i);
+        memcpy(st + b_out + 3 * b_i, counts.data(), sizeof(int32_t) * counts.size());
+        LAIR_HIP(hipMemcpyAsync(d_out.get(), st, b_out, hipMemcpyHostToDevice, s));
+        if (nseg) {
+            LAIR_HIP(hipMemcpyAsync(d_meta.get(), st + b_out, 3 * b_i, hipMemcpyHostToDevice, s));
+        }
+        LAIR_HIP(hipMemcpyAsync(d_counts.get(), st + b_out + 3 * b_i,
+                                sizeof(int32_t) * counts.size(), hipMemcpyHostToDevice, s));
+        for (size_t l = 0; l < nlev; ++l)
+            LAIR_HIP(hipMemcpyAsync(h->L[l]->act_cnt.get(), d_counts.get() + 3 * l,
+                                    3 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        launch_materialize(nseg, out.back(), d_out.get(), d_meta.get(), d_meta.get() + nseg,
+                           d_meta.get() + 2 * nseg, d_src.get(), d_dst.get(), s);
+        // the staging area is reused by the next host readback: finish the copies
+        LAIR_HIP(hipStreamSynchronize(s));
+    };
+    struct ActGuard {
+        lair_hierarchy *h;
+        ~ActGuard() { h->use_act = false; }
+    } act_guard{h};
     const double *bb = b;
     if (h->opt.block_size > 0) {
         op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
@@ -1218,11 +1351,14 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
         if (upload) {
             LAIR_HIP(hipMemcpyAsync(h->active_dev.get(), h->active.data(), (size_t)ns,
                                     hipMemcpyHostToDevice, s));
+            if (lists) rebuild_lists();
             upload = false;
         }
+        // the cycle touches only the rows of systems still iterated; the
+        // others keep their x (their corrections would be zero)
+        h->use_act = lists;
         run_iteration(h, mixed ? IT_BATCH_MIXED : IT_BATCH_FP64, 1, bb, x, s,
                       [&](hipStream_t st) {
-            launch_mask_rows(ns, L0.seg_dev.get(), h->active_dev.get(), h->r0.get(), n, st);
             if (mixed) {
                 {
                     ProfScope ps("cast", st, 12.0 * n);
@@ -1230,15 +1366,35 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                 }
                 vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, 1, st);
                 ProfScope ps("cast", st, 20.0 * n);
-                op_axpy_f32(x, h->e32.get(), n, st);
+                if (lists)
+                    op_update_list<float>(L0.act_rows.get(), L0.act_cnt.get(), (int32_t)n, x,
+                                          h->e32.get(), st);
+                else
+                    op_axpy_f32(x, h->e32.get(), n, st);
             } else {
                 vcycle<double>(h, 0, h->r0.get(), h->e64.get(), true, nullptr, 1, st);
-                LAIR_LAUNCH(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, x,
-                                   h->e64.get(), n);
-                LAIR_LAUNCH_CHECK();
+                if (lists) {
+                    op_update_list<double>(L0.act_rows.get(), L0.act_cnt.get(), (int32_t)n, x,
+                                           h->e64.get(), st);
+                } else {
+                    LAIR_LAUNCH(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, x,
+                                h->e64.get(), n);
+                    LAIR_LAUNCH_CHECK();
+                }
             }
-            residual_and_norms(st);
+            {
+                ProfScope ps("residual", st, ab_rowdot(L0.A, 8, 1, 2), 2.0 * L0.A.nnz);
+                if (lists)
+                    op_rowdot_list<double>(A0, 0, L0.act_rows.get(), L0.act_cnt.get(),
+                                           (int32_t)n, x, bb, h->r0.get(), st);
+                else
+                    op_residual<double>(A0, bb, x, h->r0.get(), 1, st);
+            }
+            ProfScope ps("norm", st, 8.0 * n, 2.0 * n);
+            launch_seg_sumsq(ns, L0.seg_dev.get(), h->r0.get(), h->seg_norm.get(), st,
+                             h->active_dev.get());
         });
+        h->use_act = false;
         read_norms(h->seg_norm.get(), ns, s, rn);
         ++it;
     }

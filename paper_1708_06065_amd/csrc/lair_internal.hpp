@@ -282,13 +282,13 @@ template <class VT>
 void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nrows,
                const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
                VT *out, bool compact, double omega, int32_t nrhs,
-               hipStream_t s);
+               hipStream_t s, const int32_t *cnt = nullptr);
 template <class VT>
 void op_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x,
                      int32_t nrhs, bool transpose, hipStream_t s);
 template <class VT>
 void op_scatter(const int32_t *rows, int32_t nrows, const VT *t, VT *x,
-                int32_t nrhs, hipStream_t s);
+                int32_t nrhs, hipStream_t s, const int32_t *cnt = nullptr);
 template <class VT>
 void op_fill(VT *x, VT val, int64_t n, hipStream_t s);
 template <class VT>
@@ -298,6 +298,15 @@ void op_dense_solve(int32_t n, const double *lu, const int32_t *piv,
                     const VT *b, VT *x, int32_t nrhs, bool transpose,
                     hipStream_t s);
 // per right-hand side sum of squares into out[0..nrhs) (double, fixed order)
+// One right-hand side over the listed rows rows[k], k < *cnt (device list of
+// capacity cap): mode 0 y = b - A x, 1 y = A x, 2 y += A x.
+template <class VT>
+void op_rowdot_list(const CsrView<VT> &A, int mode, const int32_t *rows, const int32_t *cnt,
+                    int32_t cap, const VT *x, const VT *b, VT *y, hipStream_t s);
+// x[i] += e[i] for the listed rows
+template <class ET>
+void op_update_list(const int32_t *rows, const int32_t *cnt, int32_t cap, double *x,
+                    const ET *e, hipStream_t s);
 // r = b - A x with its per-column sums of squares (out, nrhs entries) in one
 // pass, written as r64 and/or r32.  Returns false (nothing launched) when the
 // vectors are not 16-byte aligned for nrhs > 1.  partial: npartial * nrhs.
@@ -332,9 +341,10 @@ int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
                    const int32_t *clist, int32_t nc, DevArr<int32_t> &out,
                    hipStream_t s, DevArr<int64_t> &tmp);
 void launch_seg_sumsq(int32_t nsys, const int64_t *seg, const double *r, double *out,
-                      hipStream_t s);
-void launch_mask_rows(int32_t nsys, const int64_t *seg, const uint8_t *active, double *r,
-                      int64_t nrows, hipStream_t s);
+                      hipStream_t s, const uint8_t *active = nullptr);
+void launch_materialize(int32_t nseg, int64_t total, const int64_t *seg_out,
+                        const int32_t *seg_src, const int32_t *seg_dst, const int32_t *lst,
+                        const int32_t *const *srcs, int32_t *const *dsts, hipStream_t s);
 void launch_dense_blocks(int32_t nsys, const int64_t *seg, const int64_t *doff,
                          const int32_t *rp, const int32_t *cj, const double *v,
                          double *dense, int64_t nrows, hipStream_t s);
@@ -342,6 +352,6 @@ void launch_block_lu(int32_t nsys, const int64_t *seg, const int64_t *doff, doub
                      int32_t *piv, int32_t *info, hipStream_t s);
 void launch_block_solve(int32_t nsys, const int64_t *seg, const int64_t *doff,
                         const double *dense, const int32_t *piv, const double *b, double *x,
-                        bool transpose, hipStream_t s);
+                        bool transpose, hipStream_t s, const uint8_t *active = nullptr);
 
 }  // namespace lair
