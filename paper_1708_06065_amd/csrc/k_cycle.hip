@@ -280,6 +280,10 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
     }
 }
 
+// Lanes per row for one right-hand side: about four entries per lane (a
+// power of two >= the mean row length gives `team`).
+static inline int scalar_team(int team) { return team >= 4 ? team / 4 : 1; }
+
 static inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <class VT, int T, int MODE>
@@ -392,7 +396,7 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
     LAIR_LAUNCH((k_rowdot1<VT, TT, MODE>),                                \
                        dim3(blocks_for((int64_t)A.nrows * TT, 256)), dim3(256), 0, s, \
                        A.nrows, A.rp, A.cj, A.v, x, b, y)
-    switch (A.team) {
+    switch (scalar_team(A.team)) {
         case 1: LAIR_RD(1); break;
         case 2: LAIR_RD(2); break;
         case 4: LAIR_RD(4); break;
@@ -424,7 +428,7 @@ static void rowdot_list_t(const CsrView<VT> &A, const int32_t *rows, const int32
 #define LAIR_RL(TT)                                                                    \
     LAIR_LAUNCH((k_rowdot_list<VT, TT, MODE>), dim3(list_grid((int64_t)cap * TT)),     \
                 dim3(256), 0, s, rows, cnt, A.rp, A.cj, A.v, x, b, y)
-    switch (A.team) {
+    switch (scalar_team(A.team)) {
         case 1: LAIR_RL(1); break;
         case 2: LAIR_RL(2); break;
         case 4: LAIR_RL(4); break;
@@ -541,7 +545,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
     LAIR_LAUNCH((k_jacobi1<VT, TT, SEL>),                                 \
                        dim3(cnt ? list_grid((int64_t)nx * TT) : blocks_for((int64_t)nx * TT, 256)), \
                        dim3(256), 0, s, nx, cnt, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
-    switch (A.team) {
+    switch (scalar_team(A.team)) {
         case 1: LAIR_JC(1); break;
         case 2: LAIR_JC(2); break;
         case 4: LAIR_JC(4); break;
