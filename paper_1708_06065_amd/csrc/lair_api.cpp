@@ -92,6 +92,13 @@ struct lair_hierarchy {
     // batch of independent systems (nsys > 1): per-system coarsest blocks
     int32_t nsys = 1;
     lair::DevArr<int64_t> dense_off;
+    lair::DevArr<double> binv;               // per-system coarsest inverses (small blocks)
+    lair::DevArr<uint8_t> use_inv;           // 1: the system's block is applied by its inverse
+    // per-system norms over several blocks per system (level-0 rows)
+    lair::DevArr<int32_t> ss_sys;
+    lair::DevArr<int64_t> ss_lo, ss_start;
+    lair::DevArr<double> ss_part;
+    int32_t ss_nblk = 0;
     std::vector<int32_t> sys_levels;
     lair::DevArr<uint8_t> active_dev;
     lair::DevArr<double> seg_norm;
@@ -509,8 +516,35 @@ static void finish_coarsest_batch(lair_hierarchy *h) {
     LAIR_HIP(hipMemsetAsync(info.get(), 0, sizeof(int32_t), s));
     launch_dense_blocks(ns, Lc.seg_dev.get(), h->dense_off.get(), Lc.A.rp.get(), Lc.A.cj.get(),
                         Lc.A.v.get(), h->lu.get(), Lc.n, s);
-    launch_block_lu(ns, Lc.seg_dev.get(), h->dense_off.get(), h->lu.get(), h->piv.get(),
-                    info.get(), s);
+    // blocks up to small_dense_max() rows: LU and inverse in LDS, one wave
+    // each; up to mid_dense_max() rows: LU, then the inverse in LDS chunks;
+    // a product with the inverse per solve.  Larger blocks: LU, and
+    // triangular solves per solve
+    const int32_t small = small_dense_max();
+    std::vector<uint8_t> ui((size_t)ns, 0);
+    int64_t mmax = 0;
+    bool any = false;
+    for (int32_t q = 0; q < ns; ++q) {
+        const int64_t m = Lc.seg[q + 1] - Lc.seg[q];
+        if (m <= mid_dense_max()) {
+            ui[q] = 1;
+            any = true;
+        }
+        mmax = std::max(mmax, m);
+    }
+    h->use_inv.alloc((size_t)ns, s);
+    LAIR_HIP(hipMemcpyAsync(h->use_inv.get(), ui.data(), (size_t)ns, hipMemcpyHostToDevice, s));
+    if (any) h->binv.alloc((size_t)std::max<int64_t>(doff[ns], 1), s);
+    else h->binv.release();
+    launch_block_lu_inv_small(ns, Lc.seg_dev.get(), h->dense_off.get(), h->lu.get(),
+                              h->piv.get(), h->binv.get(), info.get(), s);
+    if (mmax > small) {
+        launch_block_lu(ns, Lc.seg_dev.get(), h->dense_off.get(), h->lu.get(), h->piv.get(),
+                        info.get(), s, small + 1);
+        launch_block_inv_mid(ns, (int32_t)std::min<int64_t>(mmax, mid_dense_max()),
+                             Lc.seg_dev.get(), h->dense_off.get(), h->lu.get(), h->piv.get(),
+                             h->binv.get(), h->use_inv.get(), s);
+    }
     int32_t hinfo = 0;
     {
         Readback rb(s);
@@ -808,13 +842,20 @@ static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
     if (h->nsys > 1) {
         Level &Lb = *h->L.back();
         const uint8_t *act = h->use_act ? h->active_dev.get() : nullptr;
-        if constexpr (std::is_same<VT, double>::value) {
+        auto block_solve = [&](const double *bb, double *xx) {
+            if (h->binv.get())
+                launch_block_apply_inv(h->nsys, Lb.seg_dev.get(), h->dense_off.get(),
+                                       h->binv.get(), bb, xx, transpose, s, act,
+                                       h->use_inv.get());
             launch_block_solve(h->nsys, Lb.seg_dev.get(), h->dense_off.get(), h->lu.get(),
-                               h->piv.get(), b, x, transpose, s, act);
+                               h->piv.get(), bb, xx, transpose, s, act,
+                               h->binv.get() ? h->use_inv.get() : nullptr);
+        };
+        if constexpr (std::is_same<VT, double>::value) {
+            block_solve(b, x);
         } else {
             op_cast_f64(b, Lb.r.get(), h->nL, s);
-            launch_block_solve(h->nsys, Lb.seg_dev.get(), h->dense_off.get(), h->lu.get(),
-                               h->piv.get(), Lb.r.get(), Lb.x.get(), transpose, s, act);
+            block_solve(Lb.r.get(), Lb.x.get());
             op_cast_f32(Lb.x.get(), x, h->nL, s);
         }
         return;
@@ -1205,7 +1246,39 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
         }
         moved = true;
     }
+    if (h->ss_nblk == 0) {
+        // per-system norms: blocks of at most seg_sum_chunk() rows
+        const int64_t ch = seg_sum_chunk();
+        std::vector<int32_t> bsys;
+        std::vector<int64_t> blo, bstart{0};
+        for (int32_t q = 0; q < ns; ++q) {
+            for (int64_t lo = L0.seg[q]; lo < L0.seg[q + 1]; lo += ch) {
+                bsys.push_back(q);
+                blo.push_back(lo);
+            }
+            bstart.push_back((int64_t)bsys.size());
+        }
+        h->ss_nblk = (int32_t)bsys.size();
+        h->ss_sys.alloc(bsys.size(), s);
+        h->ss_lo.alloc(blo.size(), s);
+        h->ss_start.alloc(bstart.size(), s);
+        h->ss_part.alloc(bsys.size(), s);
+        LAIR_HIP(hipMemcpyAsync(h->ss_sys.get(), bsys.data(), sizeof(int32_t) * bsys.size(),
+                                hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipMemcpyAsync(h->ss_lo.get(), blo.data(), sizeof(int64_t) * blo.size(),
+                                hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipMemcpyAsync(h->ss_start.get(), bstart.data(),
+                                sizeof(int64_t) * bstart.size(), hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipStreamSynchronize(s));     // pageable sources
+        moved = true;
+    }
     if (moved) h->drop_graphs();
+    auto seg_norms = [&](const double *r, const uint8_t *act, hipStream_t st) {
+        ProfScope ps("norm", st, 8.0 * n, 2.0 * n);
+        launch_seg_sumsq_blocks(ns, h->ss_nblk, h->ss_sys.get(), h->ss_lo.get(),
+                                h->ss_start.get(), L0.seg_dev.get(), act, r,
+                                h->ss_part.get(), h->seg_norm.get(), st);
+    };
     // rows of the systems still iterated, on every level.  A system's rows,
     // F rows and relaxed C rows are contiguous runs of the level's row range,
     // F list and relaxed-C list; the host lays out the runs of the active
@@ -1279,9 +1352,10 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                 counts[3 * l + t] = pos;
             }
         const int32_t nseg = (int32_t)lst.size();
-        // one pinned staging area, copied in stream order
+        // one pinned upload area, copied in stream order; it is rewritten only
+        // at the next rebuild, after the readback that follows this iteration
         const size_t b_out = sizeof(int64_t) * out.size(), b_i = sizeof(int32_t) * nseg;
-        char *st = (char *)pinned_staging(b_out + 3 * b_i + sizeof(int32_t) * counts.size() + 64);
+        char *st = (char *)pinned_upload(b_out + 3 * b_i + sizeof(int32_t) * counts.size() + 64);
         memcpy(st, out.data(), b_out);
         memcpy(st + b_out, src.data(), b_i);
         memcpy(st + b_out + b_i, dst.data(), b_i);
@@ -1298,8 +1372,6 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                                     3 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         launch_materialize(nseg, out.back(), d_out.get(), d_meta.get(), d_meta.get() + nseg,
                            d_meta.get() + 2 * nseg, d_src.get(), d_dst.get(), s);
-        // the staging area is reused by the next host readback: finish the copies
-        LAIR_HIP(hipStreamSynchronize(s));
     };
     struct ActGuard {
         lair_hierarchy *h;
@@ -1312,10 +1384,7 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
         bb = h->bscaled.get();
     }
     std::vector<double> nb, rn, rfirst;
-    {
-        ProfScope ps("norm", s, 8.0 * n, 2.0 * n);
-        launch_seg_sumsq(ns, L0.seg_dev.get(), bb, h->seg_norm.get(), s);
-    }
+    seg_norms(bb, nullptr, s);
     read_norms(h->seg_norm.get(), ns, s, nb);
     CsrView<double> A0 = view<double>(L0.A, L0.team_A);
     auto residual_and_norms = [&](hipStream_t st) {
@@ -1323,8 +1392,7 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
             ProfScope ps("residual", st, ab_rowdot(L0.A, 8, 1, 2), 2.0 * L0.A.nnz);
             op_residual<double>(A0, bb, x, h->r0.get(), 1, st);
         }
-        ProfScope ps("norm", st, 8.0 * n, 2.0 * n);
-        launch_seg_sumsq(ns, L0.seg_dev.get(), h->r0.get(), h->seg_norm.get(), st);
+        seg_norms(h->r0.get(), nullptr, st);
     };
     residual_and_norms(s);
     read_norms(h->seg_norm.get(), ns, s, rn);
@@ -1390,9 +1458,7 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                 else
                     op_residual<double>(A0, bb, x, h->r0.get(), 1, st);
             }
-            ProfScope ps("norm", st, 8.0 * n, 2.0 * n);
-            launch_seg_sumsq(ns, L0.seg_dev.get(), h->r0.get(), h->seg_norm.get(), st,
-                             h->active_dev.get());
+            seg_norms(h->r0.get(), h->active_dev.get(), st);
         });
         h->use_act = false;
         read_norms(h->seg_norm.get(), ns, s, rn);
@@ -1602,8 +1668,10 @@ static lair_hierarchy *setup_batch_impl(int32_t nsys, const lair_csr *sys,
         LAIR_HIP(hipMemcpyAsync(dnzo.get(), nzo.data(), sizeof(int64_t) * (nsys + 1),
                                 hipMemcpyHostToDevice, s));
         LAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int32_t), s));
+        int64_t max_nnz = 0;
+        for (int32_t q = 0; q < nsys; ++q) max_nnz = std::max(max_nnz, sys[q].nnz);
         launch_union_gather(nsys, ds.get(), dseg.get(), dnzo.get(), drp.get(), dcj.get(),
-                            dv.get(), bad.get(), s);
+                            dv.get(), bad.get(), max_nnz, s);
         int32_t hb = 0;
         {
             Readback rb(s);

@@ -110,6 +110,9 @@ struct Readback {
     size_t used = 0;
 };
 // pinned host staging buffer of at least `bytes` (reused; per host thread)
+// A second pinned host buffer for host-to-device uploads that stay in
+// flight across later readbacks (the readback buffer is pinned_staging).
+void *pinned_upload(size_t bytes);
 void *pinned_staging(size_t bytes);
 
 // A square or rectangular CSR matrix on the device (int32 indices).
@@ -332,7 +335,7 @@ struct SysCsr {
 };
 void launch_union_gather(int32_t nsys, const SysCsr *sys, const int64_t *seg,
                          const int64_t *nzo, int32_t *rp, int32_t *cj, double *v, int32_t *bad,
-                         hipStream_t s);
+                         int64_t max_nnz, hipStream_t s);
 void launch_seg_count_c(int32_t nsys, const int64_t *seg, const int8_t *cf, int32_t *count,
                         hipStream_t s);
 void launch_force_c(int32_t nsys, const int64_t *seg, const uint8_t *stopped, int8_t *cf,
@@ -342,6 +345,14 @@ int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
                    hipStream_t s, DevArr<int64_t> &tmp);
 void launch_seg_sumsq(int32_t nsys, const int64_t *seg, const double *r, double *out,
                       hipStream_t s, const uint8_t *active = nullptr);
+int64_t seg_sum_chunk();
+void launch_seg_sumsq_blocks(int32_t nsys, int32_t nblk, const int32_t *bsys,
+                             const int64_t *blo, const int64_t *bstart, const int64_t *seg,
+                             const uint8_t *active, const double *r, double *part,
+                             double *out, hipStream_t s);
+void launch_block_apply_inv(int32_t nsys, const int64_t *seg, const int64_t *doff,
+                            const double *inv, const double *b, double *x, bool transpose,
+                            hipStream_t s, const uint8_t *active, const uint8_t *use_inv);
 void launch_materialize(int32_t nseg, int64_t total, const int64_t *seg_out,
                         const int32_t *seg_src, const int32_t *seg_dst, const int32_t *lst,
                         const int32_t *const *srcs, int32_t *const *dsts, hipStream_t s);
@@ -349,9 +360,20 @@ void launch_dense_blocks(int32_t nsys, const int64_t *seg, const int64_t *doff,
                          const int32_t *rp, const int32_t *cj, const double *v,
                          double *dense, int64_t nrows, hipStream_t s);
 void launch_block_lu(int32_t nsys, const int64_t *seg, const int64_t *doff, double *dense,
-                     int32_t *piv, int32_t *info, hipStream_t s);
+                     int32_t *piv, int32_t *info, hipStream_t s, int32_t min_n = 0);
+// blocks of at most small_dense_max() rows: LU and inverse in one kernel
+int32_t small_dense_max();
+// blocks of small_dense_max()+1 .. mid_dense_max() rows: inverse from the LU
+int32_t mid_dense_max();
+void launch_block_inv_mid(int32_t nsys, int32_t maxn, const int64_t *seg, const int64_t *doff,
+                          const double *lu, const int32_t *piv, double *inv,
+                          const uint8_t *use_inv, hipStream_t s);
+void launch_block_lu_inv_small(int32_t nsys, const int64_t *seg, const int64_t *doff,
+                               double *dense, int32_t *piv, double *inv, int32_t *info,
+                               hipStream_t s);
 void launch_block_solve(int32_t nsys, const int64_t *seg, const int64_t *doff,
                         const double *dense, const int32_t *piv, const double *b, double *x,
-                        bool transpose, hipStream_t s, const uint8_t *active = nullptr);
+                        bool transpose, hipStream_t s, const uint8_t *active = nullptr,
+                        const uint8_t *skip = nullptr);
 
 }  // namespace lair

@@ -114,8 +114,19 @@ struct PinnedBuf {
 };
 }  // namespace
 
+static void *pinned_grow(PinnedBuf &buf, size_t bytes);
+
 void *pinned_staging(size_t bytes) {
     static thread_local PinnedBuf buf;
+    return pinned_grow(buf, bytes);
+}
+
+void *pinned_upload(size_t bytes) {
+    static thread_local PinnedBuf buf;
+    return pinned_grow(buf, bytes);
+}
+
+static void *pinned_grow(PinnedBuf &buf, size_t bytes) {
     if (bytes > buf.n) {
         if (buf.p) (void)hipHostFree(buf.p);
         buf.p = nullptr;
