@@ -551,6 +551,8 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
 // least-squares kernel.
 // ===========================================================================
 constexpr double SING_TOL = 1e-14;
+// mean entries per row above which the local solves start with teams
+constexpr double LONG_ROW = 12.0;
 
 __device__ __forceinline__ void write_r_row(int32_t rbase, int s, int32_t i,
                                             const int32_t *l, const double *z,
@@ -762,15 +764,98 @@ k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
     r_v[rbase + ip] = 1.0;
 }
 
+// Inclusive prefix sum over a team of T consecutive lanes.
+template <int T>
+__device__ __forceinline__ int team_scan_incl(int x) {
+    const int p = threadIdx.x % T;
+#pragma unroll
+    for (int o = 1; o < T; o <<= 1) {
+        int u = __shfl_up(x, o, T);
+        if (p >= o) x += u;
+    }
+    return x;
+}
+
+// Gathers the local matrix M[k][q] = a(l_q, l_k) (row stride ldm) for the
+// sorted neighbourhood ln[0..s): the entries of the s rows l_q are numbered
+// as one flat range and each lane of the team takes every T-th of them,
+// U at a time, so a lane's loads do not wait on each other (the row-by-row
+// walk of long coarse-grid rows was bound by load latency).  off (s + 1)
+// and st (s) are the team's scratch; BLOCK selects a block barrier (the
+// one-wave kernel, whose scratch may sit in global memory) over a wave
+// fence.  Md, when given, receives the same entries in double.
+template <int T, int U, bool BLOCK, class FT>
+__device__ void gather_local(int p, int s, const int32_t *ln, int32_t *off, int32_t *st,
+                             const int32_t *rp, const int32_t *cj, const double *v,
+                             FT *M, int ldm, double *Md) {
+    int carry = 0;
+    for (int q0 = 0; q0 < s; q0 += T) {
+        const int q = q0 + p;
+        int a = 0, len = 0;
+        if (q < s) {
+            const int r = ln[q];
+            a = rp[r];
+            len = rp[r + 1] - a;
+        }
+        const int incl = team_scan_incl<T>(len);
+        if (q < s) {
+            st[q] = a;
+            off[q] = carry + incl - len;
+        }
+        carry += __shfl(incl, T - 1, T);
+    }
+    if (p == 0) off[s] = carry;
+    if (BLOCK) __syncthreads(); else wave_lds_sync();
+    const int E = carry;
+    int q = 0;
+    for (int base = p; base < E; base += U * T) {
+        int e[U], qq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * T;
+            e[u] = -1;
+            qq[u] = 0;
+            if (idx < E) {
+                while (off[q + 1] <= idx) ++q;
+                qq[u] = q;
+                e[u] = st[q] + idx - off[q];
+            }
+        }
+        int col[U];
+        double val[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            col[u] = -1;
+            val[u] = 0.0;
+            if (e[u] >= 0) {
+                col[u] = cj[e[u]];
+                val[u] = v[e[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (e[u] >= 0) {
+                const int k = bsearch_i32(ln, s, col[u]);
+                if (k >= 0) {
+                    M[(size_t)k * ldm + qq[u]] = (FT)val[u];
+                    if (Md) Md[(size_t)k * ldm + qq[u]] = val[u];
+                }
+            }
+        }
+    }
+}
+
 // One team of T lanes per system with s <= T (T = 8, 16, 32; a team is part
-// of one wave).  The gather writes M into the team's LDS tile (lane q scans
-// row l_q of A, so M[p][q] = a(l_q, l_p) lands in row p); lane p then holds
-// row p of M in registers.  Gaussian elimination with partial pivoting
-// keeps the rows in place: at step k the pivot is the not-yet-used row with
-// the largest |M[r][k]| (smallest r on ties), its row is broadcast by
-// shuffles and the other unused rows eliminate column k.  Back substitution
-// runs over the pivots in reverse order.  MIXED factorises a float copy and
-// refines once with the double rows kept in registers.
+// of one wave).  The gather writes M into the team's LDS tile; lane p then
+// holds row p of M in registers.  Gaussian elimination with partial
+// pivoting keeps the rows in place: at step k the pivot is the
+// not-yet-used row with the largest |M[r][k]| (smallest r on ties), its row
+// is broadcast by shuffles and the other unused rows eliminate column k.
+// Back substitution runs over the pivots in reverse order, column by
+// column: the pivot lane of step k yields z_k and every lane removes
+// column k from its right-hand side.  MIXED factorises a float copy and
+// refines once with the double tile kept in LDS.  list == nullptr takes
+// every C-point in order.
 template <int T, bool MIXED>
 __global__ void __launch_bounds__(T >= 32 ? 128 : 256)
 k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
@@ -784,13 +869,16 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
     __shared__ double sM[TEAMS][T * T];
     __shared__ double sf[TEAMS][T];
     __shared__ int32_t sl[TEAMS][T];
+    __shared__ int32_t soff[TEAMS][T + 1];
+    __shared__ int32_t sst[TEAMS][T];
+    __shared__ int32_t spv[TEAMS][T];
     const int team = threadIdx.x / T;
     const int p = threadIdx.x % T;                  // this lane's row / column
     int64_t gt = xcd_block_id() * BS + threadIdx.x;
     int32_t tid = (int32_t)(gt / T);
     if (tid >= nlist) return;
     if (list_count && tid >= *list_count) return;
-    const int32_t c = list[tid];
+    const int32_t c = list ? list[tid] : tid;
     const int32_t i = clist[c];
     const int32_t n0 = nptr[c];
     const int s = nptr[c + 1] - n0;
@@ -803,65 +891,57 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
     double *M = sM[team];
     double *f = sf[team];
     int32_t *ln = sl[team];
+    int32_t *pv = spv[team];
     const int32_t lp = (p < s) ? nbr[n0 + p] : INT_MAX;
     ln[p] = lp;
     f[p] = 0.0;
+    pv[p] = p;
 #pragma unroll
     for (int j = 0; j < T; ++j) M[j * T + p] = 0.0;
     wave_lds_sync();
-    if (p < s) {
-        for (int e = rp[lp]; e < rp[lp + 1]; ++e) {
-            int q = bsearch_i32(ln, s, cj[e]);
-            if (q >= 0) M[q * T + p] = v[e];
-        }
-    }
+    gather_local<T, 4, false, double>(p, s, ln, soff[team], sst[team], rp, cj, v, M, T,
+                                      nullptr);
     for (int e = rp[i] + p; e < rp[i + 1]; e += T) {
         int q = bsearch_i32(ln, s, cj[e]);
         if (q >= 0) f[q] = -v[e];
     }
     wave_lds_sync();
-    double Md[T];
     FT Mr[T];
-#pragma unroll
-    for (int j = 0; j < T; ++j) {
-        Md[j] = M[p * T + j];
-        Mr[j] = (FT)Md[j];
-    }
-    const double f0 = f[p];
     double rs = 0.0;
 #pragma unroll
-    for (int j = 0; j < T; ++j) rs += fabs(Md[j]);
+    for (int j = 0; j < T; ++j) {
+        const double a = M[p * T + j];
+        Mr[j] = (FT)a;
+        rs += fabs(a);
+    }
+    const double f0 = f[p];
     const double tol = SING_TOL * team_max<T>(p < s ? rs : 0.0);
     FT fr = (FT)f0;
     FT Lr[T];
-    int piv[T];
+    // the steps run without branches (k >= s contributes zeros), so the
+    // compiler keeps the row arrays in place instead of copying them at
+    // every join
     bool used = (p >= s);
     bool singular = false;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-        Lr[k] = (FT)0;
-        piv[k] = 0;
-        if (k < s && !singular) {
-            double cand = used ? -1.0 : fabs((double)Mr[k]);
-            int who = p;
-            team_argmax<T>(cand, who);
-            if (cand <= tol) {
-                singular = true;
-            } else {
-                piv[k] = who;
-                FT pk = __shfl(Mr[k], who, T);
-                FT fk = __shfl(fr, who, T);
-                if (p == who) used = true;
-                FT mult = used ? (FT)0 : Mr[k] / pk;
-                Lr[k] = mult;
+        const bool act = k < s;
+        double cand = (used || !act) ? -1.0 : fabs((double)Mr[k]);
+        int who = p;
+        team_argmax<T>(cand, who);
+        singular = singular || (act && cand <= tol);
+        if (p == 0 && act) pv[k] = who;
+        const FT pk = __shfl(Mr[k], who, T);
+        const FT fk = __shfl(fr, who, T);
+        used = used || (act && p == who);
+        const FT mult = (used || !act) ? (FT)0 : Mr[k] / pk;
+        Lr[k] = mult;
 #pragma unroll
-                for (int j = k + 1; j < T; ++j) {
-                    FT pj = __shfl(Mr[j], who, T);
-                    Mr[j] -= mult * pj;
-                }
-                fr -= mult * fk;
-            }
+        for (int j = k + 1; j < T; ++j) {
+            const FT pj = __shfl(Mr[j], who, T);
+            Mr[j] -= mult * pj;
         }
+        fr -= mult * fk;
     }
     if (singular) {
         if (p == 0) {
@@ -870,54 +950,41 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
         }
         return;
     }
-    // back substitution over the pivot rows, last pivot first
-    double z[T];
+    wave_lds_sync();
+    // back substitution, last pivot first, column by column: the pivot
+    // lane of step k yields z_k and every lane removes column k from its
+    // right-hand side; in MIXED the double residual r = f - M z builds up
+    // alongside from the LDS tile
+    double zq = 0.0;
+    double r = f0;
 #pragma unroll
     for (int k = T - 1; k >= 0; --k) {
-        z[k] = 0.0;
-        if (k < s) {
-            FT acc = fr;
-#pragma unroll
-            for (int j = k + 1; j < T; ++j) acc -= Mr[j] * (FT)z[j];
-            FT zk = acc / Mr[k];
-            z[k] = (double)__shfl(zk, piv[k], T);
-        }
+        const bool act = k < s;
+        const FT q = fr / Mr[k];
+        const FT zk = act ? __shfl(q, pv[k], T) : (FT)0;
+        fr -= Mr[k] * zk;
+        zq = (k == p) ? (double)zk : zq;
+        if (MIXED) r -= M[p * T + k] * (double)zk;
     }
     if (MIXED) {
-        // r_p = f_p - sum_j M[p][j] z_j in double, then the same eliminations
-        // and back substitution on r
-        double r = f0;
-#pragma unroll
-        for (int j = 0; j < T; ++j) r -= Md[j] * z[j];
+        // the same eliminations and back substitution on r
         FT rr = (FT)r;
 #pragma unroll
         for (int k = 0; k < T; ++k) {
-            if (k < s) {
-                FT rk = __shfl(rr, piv[k], T);
-                rr -= Lr[k] * rk;
-            }
+            const FT rk = __shfl(rr, pv[k], T);
+            rr -= Lr[k] * rk;
         }
-        double d[T];
 #pragma unroll
         for (int k = T - 1; k >= 0; --k) {
-            d[k] = 0.0;
-            if (k < s) {
-                FT acc = rr;
-#pragma unroll
-                for (int j = k + 1; j < T; ++j) acc -= Mr[j] * (FT)d[j];
-                FT dk = acc / Mr[k];
-                d[k] = (double)__shfl(dk, piv[k], T);
-            }
+            const bool act = k < s;
+            const FT q = rr / Mr[k];
+            const FT dk = act ? __shfl(q, pv[k], T) : (FT)0;
+            rr -= Mr[k] * dk;
+            zq = (k == p) ? zq + (double)dk : zq;
         }
-#pragma unroll
-        for (int k = 0; k < T; ++k) z[k] += d[k];
     }
     // sorted write of the R row: lane q writes entry q
     int ip = team_sum_int<T>((p < s && lp < i) ? 1 : 0);
-    double zq = 0.0;
-#pragma unroll
-    for (int k = 0; k < T; ++k)
-        if (k == p) zq = z[k];
     if (p < s) {
         int o = rbase + p + (p >= ip ? 1 : 0);
         r_cj[o] = lp;
@@ -931,15 +998,16 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
 
 // One wave per system (blockDim = 64).  M lives in dynamic LDS sized for
 // the level's largest system up to WSMAX, beyond that in a global scratch
-// slab of 3 smax^2 doubles per block.  The gather walks the rows l_p one at
-// a time with all lanes on consecutive entries (coalesced), each lane
-// locating its column in the sorted N by binary search.
+// slab of 3 smax^2 doubles per block.  The gather enumerates the entries of
+// the rows l_p as one flat range over the lanes.  MIXED keeps a double copy
+// of M for the refinement residual.
 constexpr int WSMAX = 64;
 
 template <class FT>
 __host__ __device__ constexpr size_t wave_lds_bytes(int cap) {
-    return (size_t)cap * cap * sizeof(FT) + (size_t)cap * (2 * sizeof(double) + sizeof(FT) +
-                                                           2 * sizeof(int32_t)) + 64;
+    return (size_t)cap * cap * sizeof(FT) +
+           (sizeof(FT) == sizeof(float) ? (size_t)cap * cap * sizeof(double) : 0) +
+           (size_t)cap * (2 * sizeof(double) + sizeof(FT) + 4 * sizeof(int32_t)) + 64;
 }
 
 template <bool MIXED>
@@ -960,38 +1028,26 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
     int s = nptr[c + 1] - n0;
     int32_t rbase = n0 + c;
     const int32_t *l = nbr + n0;
-    bool in_lds = (s <= cap);
-    // layout: z, f (double), M (FT), w (FT), ln, perm (int)
-    double *z, *f;
-    FT *M, *w;
-    int32_t *ln, *perm;
-    if (in_lds) {
-        z = dyn;
-        f = z + cap;
-        M = (FT *)(f + cap);
-        w = M + (size_t)cap * cap;
-        ln = (int32_t *)(w + cap);
-        perm = ln + cap;
-    } else {
-        double *g = gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3;
-        z = g;
-        f = z + smax;
-        M = (FT *)(f + smax);
-        w = (FT *)(g + (size_t)smax * smax + 2 * (size_t)smax);
-        ln = (int32_t *)(g + (size_t)smax * smax * 2);
-        perm = ln + smax;
+    const int32_t m = (s <= cap) ? cap : smax;   // capacity of this layout
+    // layout: z, f, Md (double; Md only in MIXED), M, w (FT), ln, perm,
+    // off, st (int)
+    double *z = (s <= cap) ? dyn : gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3;
+    double *f = z + m;
+    double *Md = MIXED ? f + m : nullptr;
+    FT *M = (FT *)(f + m + (MIXED ? (size_t)m * m : 0));
+    FT *w = M + (size_t)m * m;
+    int32_t *ln = (int32_t *)(w + m);
+    int32_t *perm = ln + m;
+    int32_t *off = perm + m;
+    int32_t *st = off + m + 1;
+    for (int idx = lane; idx < s * s; idx += 64) {
+        M[idx] = (FT)0;
+        if (MIXED) Md[idx] = 0.0;
     }
-    for (int idx = lane; idx < s * s; idx += 64) M[idx] = (FT)0;
     for (int p = lane; p < s; p += 64) { f[p] = 0.0; ln[p] = l[p]; perm[p] = p; }
     __syncthreads();
     // column p of M is row l_p of A restricted to N: M[q][p] = a(l_p, l_q)
-    for (int p = 0; p < s; ++p) {
-        int r = ln[p];
-        for (int e = rp[r] + lane; e < rp[r + 1]; e += 64) {
-            int q = bsearch_i32(ln, s, cj[e]);
-            if (q >= 0) M[q * s + p] = (FT)v[e];
-        }
-    }
+    gather_local<64, 4, true, FT>(lane, s, ln, off, st, rp, cj, v, M, s, Md);
     for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
         int p = bsearch_i32(ln, s, cj[e]);
         if (p >= 0) f[p] = -v[e];
@@ -1000,7 +1056,7 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
     double rs = 0.0;
     for (int p = lane; p < s; p += 64) {
         double a = 0.0;
-        for (int q = 0; q < s; ++q) a += fabs((double)M[p * s + q]);
+        for (int q = 0; q < s; ++q) a += fabs(MIXED ? Md[p * s + q] : (double)M[p * s + q]);
         rs = fmax(rs, a);
     }
     double tol = SING_TOL * team_max<64>(rs);
@@ -1057,23 +1113,13 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
         __syncthreads();
     }
     if (MIXED) {
-        // one refinement in double: r = f - M z from the rows of A (lane p
-        // owns r_p and searches column l_p in every row l_q), then
-        // z += LU^{-1} r with the float factors
+        // one refinement in double: r = f - M z from the double copy of M
+        // (rows in their original order), then z += LU^{-1} r with the
+        // float factors
         double *res = f;
         for (int p = lane; p < s; p += 64) {
             double acc = res[p];
-            int lp = ln[p];
-            for (int q = 0; q < s; ++q) {
-                int r = ln[q];
-                int lo = rp[r], hi = rp[r + 1] - 1;
-                while (lo <= hi) {
-                    int mid = (lo + hi) >> 1;
-                    int cc = cj[mid];
-                    if (cc == lp) { acc -= v[mid] * z[q]; break; }
-                    if (cc < lp) lo = mid + 1; else hi = mid - 1;
-                }
-            }
+            for (int q = 0; q < s; ++q) acc -= Md[p * s + q] * z[q];
             res[p] = acc;
         }
         __syncthreads();
@@ -1280,16 +1326,10 @@ static void team_pass(bool mixed, int32_t nlist, const int32_t *list,
     if (nlist == 0) return;
     constexpr int BS = (T >= 32) ? 128 : 256;
     dim3 g(blocks_for((int64_t)nlist * T, BS)), b(BS);
-    if constexpr (T <= 16) {
-        if (mixed) {
-            LAIR_LAUNCH((k_local_team<T, true>), g, b, 0, s, nlist, list, list_count,
-                               clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer,
-                               ndefer, sing, nsing);
-            LAIR_LAUNCH_CHECK();
-            return;
-        }
-    }
-    if (mixed) fail(LAIR_EUNSUPPORTED, "mixed 32-lane local solve");
+    if (mixed)
+        LAIR_LAUNCH((k_local_team<T, true>), g, b, 0, s, nlist, list, list_count, clist,
+                           nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer, ndefer,
+                           sing, nsing);
     else
         LAIR_LAUNCH((k_local_team<T, false>), g, b, 0, s, nlist, list, list_count, clist,
                            nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer, ndefer,
@@ -1300,9 +1340,11 @@ static void team_pass(bool mixed, int32_t nlist, const int32_t *list,
 // Size buckets: s <= 4 one lane per system (registers); s <= 8, 16, 32 one
 // team of 8, 16, 32 lanes per system; larger systems one wave each.  Each
 // pass defers the systems too large for it to a list for the next one.
+// Where rows are long (coarse Galerkin operators) one lane cannot gather a
+// system quickly, and the teams start with every system.
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
-                     const double *v, int32_t precision, int32_t smax,
+                     const double *v, int32_t precision, int32_t smax, double mean_row,
                      LocalSolveOut out, hipStream_t s) {
     if (nc == 0) return 0;
     DevArr<int32_t> lists, counters;
@@ -1328,22 +1370,28 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     int32_t h[5] = {0, 0, 0, 0, 0};
     {
         ProfScope ps_small("local_small", s, cost[0], cost[1]);
-        small_pass<4>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
-                      listA, nA, sing, nS, s);
-        if (smax > 4) {
+        const bool team_first = smax > 4 && mean_row > LONG_ROW;
+        int32_t bound = nc;
+        if (team_first) {
+            team_pass<8>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
+                         listB, nB, sing, nS, s);
+        } else {
+            small_pass<4>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
+                          listA, nA, sing, nS, s);
+        }
+        if (smax > (team_first ? 8 : 4)) {
             Readback rb(s);
             rb.add(h, counters.get(), sizeof(h));
             rb.run();
-            int32_t na = h[0];
-            team_pass<8>(mixed, na, listA, nullptr, clist, nptr, nbr, rp, cj, v, out,
-                         listB, nB, sing, nS, s);
+            bound = team_first ? h[1] : h[0];
+            if (!team_first)
+                team_pass<8>(mixed, bound, listA, nullptr, clist, nptr, nbr, rp, cj, v, out,
+                             listB, nB, sing, nS, s);
             if (smax > 8)
-                team_pass<16>(mixed, na, listB, nB, clist, nptr, nbr, rp, cj, v, out,
-                              listC, nC, sing, nS, s);
-            // the mixed 32-lane variant needs too many registers; in mixed
-            // mode systems above 16 go to the one-wave kernel
-            if (smax > 16 && !mixed)
-                team_pass<32>(mixed, na, listC, nC, clist, nptr, nbr, rp, cj, v, out,
+                team_pass<16>(mixed, bound, listB, team_first ? nullptr : nB, clist, nptr,
+                              nbr, rp, cj, v, out, listC, nC, sing, nS, s);
+            if (smax > 16)
+                team_pass<32>(mixed, bound, listC, nC, clist, nptr, nbr, rp, cj, v, out,
                               listD, nD, sing, nS, s);
         }
     }
@@ -1352,8 +1400,8 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         rb.add(h, counters.get(), sizeof(h));
         rb.run();
     }
-    const int32_t *wave_list = mixed ? listC : listD;
-    int32_t nbig = mixed ? h[2] : h[3];
+    const int32_t *wave_list = listD;
+    int32_t nbig = h[3];
     if (nbig > 0) {
         int32_t cap = smax < WSMAX ? smax : WSMAX;
         DevArr<double> scratch;

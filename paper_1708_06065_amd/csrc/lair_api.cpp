@@ -440,7 +440,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
                                  A.rp.get(), A.cj.get(), A.v.get(),
                                  h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED,
-                                 Lv.st.s_max, out, s);
+                                 Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s);
     Lv.st.n_singular = nsing;
     h->n_singular += nsing;
 
@@ -1560,8 +1560,8 @@ static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_d
         const DevCSR &A = Lv.A;
         LocalSolveOut out{Lv.R.rp.get(), Lv.R.cj.get(), Lv.R.v.get(), Lv.flags.get()};
         int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
-                                     A.rp.get(), A.cj.get(), A.v.get(), prec, Lv.st.s_max, out,
-                                     s);
+                                     A.rp.get(), A.cj.get(), A.v.get(), prec, Lv.st.s_max,
+                                     Lv.n ? (double)A.nnz / Lv.n : 0.0, out, s);
         Lv.st.n_singular = nsing;
         h->n_singular += nsing;
         if (h->opt.interp == LAIR_P_DIRECT) {

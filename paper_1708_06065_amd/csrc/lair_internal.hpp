@@ -211,7 +211,7 @@ struct LocalSolveOut {
 // returns the number of systems solved by least squares
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
-                     const double *v, int32_t precision, int32_t smax,
+                     const double *v, int32_t precision, int32_t smax, double mean_row,
                      LocalSolveOut out, hipStream_t s);
 void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
                              const double *v, const uint8_t *smask,
