@@ -553,6 +553,8 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
 constexpr double SING_TOL = 1e-14;
 // mean entries per row above which the local solves start with teams
 constexpr double LONG_ROW = 12.0;
+// number of systems at or below which the local solves start with teams
+constexpr int32_t FEW_SYSTEMS = 65536;
 
 __device__ __forceinline__ void write_r_row(int32_t rbase, int s, int32_t i,
                                             const int32_t *l, const double *z,
@@ -849,8 +851,8 @@ __device__ void gather_local(int p, int s, const int32_t *ln, int32_t *off, int3
 // of one wave).  The gather writes M into the team's LDS tile; lane p then
 // holds row p of M in registers.  Gaussian elimination with partial
 // pivoting keeps the rows in place: at step k the pivot is the
-// not-yet-used row with the largest |M[r][k]| (smallest r on ties), its row
-// is broadcast by shuffles and the other unused rows eliminate column k.
+// not-yet-used row with the largest |M[r][k]|, its row is broadcast by
+// shuffles and the other unused rows eliminate column k.
 // Back substitution runs over the pivots in reverse order, column by
 // column: the pivot lane of step k yields z_k and every lane removes
 // column k from its right-hand side.  MIXED factorises a float copy and
@@ -883,11 +885,11 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
     const int32_t n0 = nptr[c];
     const int s = nptr[c + 1] - n0;
     const int32_t rbase = n0 + c;
+    if (p == 0) flags[c] = 0;
     if (s > T) {
         if (p == 0) defer[atomicAdd(ndefer, 1)] = c;
         return;
     }
-    if (p == 0) flags[c] = 0;
     double *M = sM[team];
     double *f = sf[team];
     int32_t *ln = sl[team];
@@ -923,12 +925,19 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
     // every join
     bool used = (p >= s);
     bool singular = false;
+    // ties go to the row that partial pivoting with row exchanges would
+    // take: the one at the smallest position, positions being permuted by
+    // the exchanges of the earlier steps
+    int pos = p;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const bool act = k < s;
         double cand = (used || !act) ? -1.0 : fabs((double)Mr[k]);
-        int who = p;
-        team_argmax<T>(cand, who);
+        int key = (pos << 8) | p;
+        team_argmax<T>(cand, key);
+        const int who = key & 0xff;
+        const int wpos = key >> 8;
+        if (act) pos = (p == who) ? k : (pos == k ? wpos : pos);
         singular = singular || (act && cand <= tol);
         if (p == 0 && act) pv[k] = who;
         const FT pk = __shfl(Mr[k], who, T);
@@ -1028,6 +1037,7 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
     int s = nptr[c + 1] - n0;
     int32_t rbase = n0 + c;
     const int32_t *l = nbr + n0;
+    if (lane == 0) flags[c] = 0;
     const int32_t m = (s <= cap) ? cap : smax;   // capacity of this layout
     // layout: z, f, Md (double; Md only in MIXED), M, w (FT), ln, perm,
     // off, st (int)
@@ -1370,7 +1380,9 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     int32_t h[5] = {0, 0, 0, 0, 0};
     {
         ProfScope ps_small("local_small", s, cost[0], cost[1]);
-        const bool team_first = smax > 4 && mean_row > LONG_ROW;
+        // few systems: one lane each leaves the machine idle and waits on
+        // its loads in turn; a team per system gathers in parallel
+        const bool team_first = (smax > 4 && mean_row > LONG_ROW) || nc <= FEW_SYSTEMS;
         int32_t bound = nc;
         if (team_first) {
             team_pass<8>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
