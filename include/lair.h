@@ -109,7 +109,7 @@ typedef struct lair_options {
     double stall;            /* stop when n_c > stall * n (0.9)             */
     int32_t block_size;      /* 0, or k: solve D_B^{-1} A x = D_B^{-1} b with
                                 D_B the k x k diagonal blocks (Sec. 4.2.1) */
-    int32_t flags;           /* 0, or LAIR_FLAG_NO_GRAPH                     */
+    int32_t flags;           /* 0, or LAIR_FLAG_* bits below                */
 } lair_options;
 
 /* Solves capture one iteration (cycle, residual, norms) in a HIP graph the
@@ -119,6 +119,18 @@ typedef struct lair_options {
  * kernel eagerly instead.  Iterations are also eager while the profiler
  * times a cycle category. */
 #define LAIR_FLAG_NO_GRAPH 1
+/* A single system's cycle runs, on its large sparse levels (n >= 65536 and
+ * at most 16 entries per row on average, a prefix of the hierarchy), on
+ * copies of A_l, R_l and P_l renumbered with each level's F-points first and
+ * its C-points after them (both ascending), so that the F and C sweeps of
+ * FF C-relaxation read and write contiguous blocks; every row keeps its
+ * entries in stored order, so the cycle's sums are those of the natural
+ * ordering and the results are bitwise the same.  b and x stay in the
+ * caller's (natural) ordering.  NATURAL_ORDER runs every level on the
+ * natural matrices (batches always do); SPLIT_ALL renumbers every level but
+ * the coarsest whatever its size. */
+#define LAIR_FLAG_NATURAL_ORDER 2
+#define LAIR_FLAG_SPLIT_ALL 4
 
 typedef struct lair_info {
     int32_t iters;           /* V-cycles done                               */

@@ -22,6 +22,7 @@ __all__ = ["setup", "setup_batch", "Hierarchy", "LairError", "load_library",
 _KINDS = {"abs": L.SOC_ABS, "neg": L.SOC_NEG}
 _INTERP = {"one_point": L.P_ONE_POINT, "direct": L.P_DIRECT}
 _PREC = {"fp64": L.FP64, "mixed": L.MIXED, "mixed_local": L.MIXED_LOCAL}
+_ORDERING = {"auto": 0, "natural": L.FLAG_NATURAL_ORDER, "split": L.FLAG_SPLIT_ALL}
 _DIST = {1: 1, 2: 2, "all_f": L.DIST_ALL_F, 0: L.DIST_ALL_F}
 
 EXPORT_WHAT = {
@@ -275,16 +276,16 @@ def _cf_levels(cf_levels, keep):
 
 
 def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels,
-            max_coarse, stall, block_size, graphs):
+            max_coarse, stall, block_size, graphs, ordering="auto"):
     s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
                    _KINDS[kind], _DIST[distance])
     o = L.Options(_INTERP[interp], _PREC[precision], float(omega), int(max_levels),
                   int(max_coarse), float(stall), int(block_size),
-                  0 if graphs else L.FLAG_NO_GRAPH)
+                  (0 if graphs else L.FLAG_NO_GRAPH) | _ORDERING[ordering])
     opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
                 interp=interp, precision=precision, omega=omega,
                 max_levels=max_levels, max_coarse=max_coarse, stall=stall,
-                block_size=block_size, graphs=graphs)
+                block_size=block_size, graphs=graphs, ordering=ordering)
     return s, o, opts
 
 
@@ -319,19 +320,23 @@ def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
 def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
           kind="abs", distance=1, interp="one_point", precision="fp64",
           omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
-          graphs=True, stream=None):
+          graphs=True, ordering="auto", stream=None):
     """Build a hierarchy for the CSR matrix (rowptr, col, val).
 
     The arrays may be NumPy arrays (host) or contiguous CUDA tensors
     (int32, int32, float64).  cf_levels is an optional list of per-level
     int8 CF splittings (1 = C) in host memory.  graphs=False launches the
     solve's kernels eagerly instead of replaying captured iterations.
+    ordering: "auto" runs the cycle on F-first renumbered copies of the
+    large sparse levels, "natural" on the natural matrices everywhere,
+    "split" renumbers every level but the coarsest; the results are bitwise
+    the same.
     """
     lib = L.load()
     keep = []
     A, n = _csr(rowptr, col, val, keep)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
-                         max_levels, max_coarse, stall, block_size, graphs)
+                         max_levels, max_coarse, stall, block_size, graphs, ordering)
     cfp = _cf_levels(cf_levels, keep)
     out = ctypes.c_void_p()
     st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),

@@ -20,6 +20,8 @@ DIST_ALL_F = 0
 P_ONE_POINT, P_DIRECT = 0, 1
 FP64, MIXED, MIXED_LOCAL = 0, 1, 2
 FLAG_NO_GRAPH = 1
+FLAG_NATURAL_ORDER = 2
+FLAG_SPLIT_ALL = 4
 
 
 class Csr(ctypes.Structure):

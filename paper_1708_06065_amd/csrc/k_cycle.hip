@@ -88,6 +88,7 @@ __device__ __forceinline__ void row_accM(int lo, int hi, int q, int diag_col,
 // vector load.  Pointers must be 16-byte aligned (checked by the launchers).
 template <class VT, int VW> struct VecT;
 template <> struct VecT<double, 1> { using T = double; };
+template <> struct VecT<float, 1> { using T = float; };
 template <> struct VecT<float, 4> { using T = float4; };
 template <> struct VecT<float, 2> { using T = float2; };
 template <> struct VecT<double, 2> { using T = double2; };
@@ -238,7 +239,8 @@ static inline int vec_team(int L, int team) {
 template <int NR, int VW, bool OUT64, bool OUT32>
 __global__ void __launch_bounds__(256)
 k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const double *v,
-             const double *x, const double *b, double *r64, float *r32, double *partial) {
+             const double *x, const double *b, double *r64, float *r32, double *partial,
+             const int32_t *orow) {
     constexpr int L = NR / VW;
     __shared__ double sh[256 * VW];
     const int t = (int)(threadIdx.x % T);
@@ -255,6 +257,8 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
                                         acc, d);
         if (t < L) {
             const int64_t o = i * NR + t * VW;
+            // the residual goes to row orow[i] (another ordering) if given
+            const int64_t oo = orow ? (int64_t)orow[i] * NR + t * VW : o;
             Pack<double, VW> r;
             r.load(b + o);
 #pragma unroll
@@ -262,10 +266,10 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
                 r.v[k] -= acc.v[k];
                 sq[k] += r.v[k] * r.v[k];
             }
-            if (OUT64) r.store(r64 + o);
+            if (OUT64) r.store(r64 + oo);
             if (OUT32) {
 #pragma unroll
-                for (int k = 0; k < VW; ++k) r32[o + k] = (float)r.v[k];
+                for (int k = 0; k < VW; ++k) r32[oo + k] = (float)r.v[k];
             }
         }
     }
@@ -793,22 +797,22 @@ void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
 template <int NR, int VW>
 static void resid_norm_t(const CsrView<double> &A, const double *b, const double *x,
                          double *r64, float *r32, double *partial, unsigned grid, int T,
-                         hipStream_t s) {
+                         hipStream_t s, const int32_t *orow) {
     if (r64 && r32)
         LAIR_LAUNCH((k_resid_norm<NR, VW, true, true>), dim3(grid), dim3(256), 0, s,
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);
     else if (r64)
         LAIR_LAUNCH((k_resid_norm<NR, VW, true, false>), dim3(grid), dim3(256), 0, s,
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);
     else
         LAIR_LAUNCH((k_resid_norm<NR, VW, false, true>), dim3(grid), dim3(256), 0, s,
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial);
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);
     LAIR_LAUNCH_CHECK();
 }
 
 bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x,
                       double *r64, float *r32, int32_t nrhs, double *partial,
-                      int32_t npartial, double *out, hipStream_t s) {
+                      int32_t npartial, double *out, hipStream_t s, const int32_t *orow) {
     if (A.nrows == 0 || (!r64 && !r32)) return false;
     const int VW = nrhs == 1 ? 1 : 2;
     if (VW == 2 && !(aligned16(b) && aligned16(x) && (!r64 || aligned16(r64))))
@@ -818,12 +822,12 @@ bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x
     int64_t blocks = ((int64_t)A.nrows * T + 255) / 256;
     unsigned grid = (unsigned)(blocks < npartial ? (blocks < 1 ? 1 : blocks) : npartial);
     switch (nrhs) {
-        case 1: resid_norm_t<1, 1>(A, b, x, r64, r32, partial, grid, T, s); break;
-        case 2: resid_norm_t<2, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
-        case 4: resid_norm_t<4, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
-        case 8: resid_norm_t<8, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
-        case 16: resid_norm_t<16, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
-        default: resid_norm_t<32, 2>(A, b, x, r64, r32, partial, grid, T, s); break;
+        case 1: resid_norm_t<1, 1>(A, b, x, r64, r32, partial, grid, T, s, orow); break;
+        case 2: resid_norm_t<2, 2>(A, b, x, r64, r32, partial, grid, T, s, orow); break;
+        case 4: resid_norm_t<4, 2>(A, b, x, r64, r32, partial, grid, T, s, orow); break;
+        case 8: resid_norm_t<8, 2>(A, b, x, r64, r32, partial, grid, T, s, orow); break;
+        case 16: resid_norm_t<16, 2>(A, b, x, r64, r32, partial, grid, T, s, orow); break;
+        default: resid_norm_t<32, 2>(A, b, x, r64, r32, partial, grid, T, s, orow); break;
     }
     LAIR_LAUNCH(k_sumsq_final, dim3(nrhs), dim3(NRM_BS), 0, s, partial, (int32_t)grid,
                        nrhs, out);
@@ -869,6 +873,83 @@ void op_update_list(const int32_t *rows, const int32_t *cnt, int32_t cap, double
 __global__ void k_axpy_f32(double *x, const float *e, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] += (double)e[i];
+}
+
+// Row-mapped vector operations on n x nrhs blocks (nrhs a power of two),
+// VW consecutive entries of a row per thread; lgv = log2(nrhs / VW).
+// x[i] += e[map[i]] (e in another ordering)
+template <int VW>
+__global__ void k_axpy_f32_rows(double *x, const float *e, const int32_t *map, int64_t nv,
+                                int lgv) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nv) return;
+    const int64_t i = g >> lgv;
+    const int64_t src = (((int64_t)map[i] << lgv) | (g & ((1 << lgv) - 1))) * VW;
+    constexpr int XW = VW >= 2 ? 2 : 1;    // x in 16-byte pieces
+    Pack<float, VW> ev;
+    ev.load(e + src);
+#pragma unroll
+    for (int h = 0; h < VW / XW; ++h) {
+        Pack<double, XW> xv;
+        xv.load(x + g * VW + h * XW);
+#pragma unroll
+        for (int k = 0; k < XW; ++k) xv.v[k] += (double)ev.v[h * XW + k];
+        xv.store(x + g * VW + h * XW);
+    }
+}
+
+// out[map[i]] = (float) in[i]
+template <int VW>
+__global__ void k_cast_f32_rows(const double *in, float *out, const int32_t *map, int64_t nv,
+                                int lgv) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nv) return;
+    const int64_t i = g >> lgv;
+    const int64_t dst = (((int64_t)map[i] << lgv) | (g & ((1 << lgv) - 1))) * VW;
+    constexpr int XW = VW >= 2 ? 2 : 1;
+    Pack<float, VW> ov;
+#pragma unroll
+    for (int h = 0; h < VW / XW; ++h) {
+        Pack<double, XW> iv;
+        iv.load(in + g * VW + h * XW);
+#pragma unroll
+        for (int k = 0; k < XW; ++k) ov.v[h * XW + k] = (float)iv.v[k];
+    }
+    ov.store(out + dst);
+}
+
+static int ilog2(int32_t v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+void op_axpy_f32_rows(double *x, const float *e, const int32_t *map, int64_t n, int32_t nrhs,
+                      hipStream_t s) {
+    if (n == 0) return;
+    if (nrhs % 4 == 0 && aligned16(x)) {
+        const int64_t nv = n * nrhs / 4;
+        LAIR_LAUNCH(k_axpy_f32_rows<4>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, x, e, map,
+                    nv, ilog2(nrhs / 4));
+    } else {
+        LAIR_LAUNCH(k_axpy_f32_rows<1>, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s, x, e,
+                    map, n * nrhs, ilog2(nrhs));
+    }
+    LAIR_LAUNCH_CHECK();
+}
+
+void op_cast_f32_rows(const double *in, float *out, const int32_t *map, int64_t n,
+                      int32_t nrhs, hipStream_t s) {
+    if (n == 0) return;
+    if (nrhs % 4 == 0 && aligned16(in)) {
+        const int64_t nv = n * nrhs / 4;
+        LAIR_LAUNCH(k_cast_f32_rows<4>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, in, out,
+                    map, nv, ilog2(nrhs / 4));
+    } else {
+        LAIR_LAUNCH(k_cast_f32_rows<1>, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s, in,
+                    out, map, n * nrhs, ilog2(nrhs));
+    }
+    LAIR_LAUNCH_CHECK();
 }
 
 void op_axpy_f32(double *x, const float *e, int64_t n, hipStream_t s) {
@@ -943,5 +1024,39 @@ template void op_copy<double>(const double *, double *, int64_t, hipStream_t);
 template void op_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void op_dense_solve<double>(int32_t, const double *, const int32_t *, const double *, double *, int32_t, bool, hipStream_t);
 template void op_dense_solve<float>(int32_t, const double *, const int32_t *, const float *, float *, int32_t, bool, hipStream_t);
+
+// Row permutation of an n x nrhs block (row-major, nrhs a power of two):
+// to_split gathers out[k] = in[perm[k]], otherwise out[perm[k]] = in[k]
+// (back to natural); VW entries per thread, lgv = log2(nrhs / VW).
+template <int VW>
+__global__ void k_permute_rows(const int32_t *perm, const double *in, double *out, int64_t nv,
+                               int lgv, int to_split) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nv) return;
+    const int64_t k = g >> lgv;
+    const int64_t o = (((int64_t)perm[k] << lgv) | (g & ((1 << lgv) - 1))) * VW;
+    Pack<double, VW> v;
+    if (to_split) {
+        v.load(in + o);
+        v.store(out + g * VW);
+    } else {
+        v.load(in + g * VW);
+        v.store(out + o);
+    }
+}
+
+void op_permute_rows(int64_t n, int32_t nrhs, const int32_t *perm, const double *in,
+                     double *out, bool to_split, hipStream_t s) {
+    if (n == 0) return;
+    if (nrhs % 2 == 0 && aligned16(in) && aligned16(out)) {
+        const int64_t nv = n * nrhs / 2;
+        LAIR_LAUNCH(k_permute_rows<2>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, perm, in,
+                    out, nv, ilog2(nrhs / 2), to_split ? 1 : 0);
+    } else {
+        LAIR_LAUNCH(k_permute_rows<1>, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s, perm,
+                    in, out, n * nrhs, ilog2(nrhs), to_split ? 1 : 0);
+    }
+    LAIR_LAUNCH_CHECK();
+}
 
 }  // namespace lair

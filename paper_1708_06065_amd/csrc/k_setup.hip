@@ -39,6 +39,14 @@ struct FlagsF {
     int8_t want;
     __device__ int64_t operator()(int64_t i) const { return f[i] == want ? 1 : 0; }
 };
+// length of row map[k] of a CSR matrix (map == nullptr: row k)
+struct RowLenF {
+    const int32_t *rp, *map;
+    __device__ int64_t operator()(int64_t k) const {
+        const int64_t r = map ? map[k] : k;
+        return rp[r + 1] - rp[r];
+    }
+};
 
 __device__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) {
     int t = threadIdx.x;
@@ -124,10 +132,10 @@ __global__ void k_scan_add(OUT *out, int64_t n, const int64_t *bs, const int64_t
     if (i == 0) out[n] = (OUT)(*total);
 }
 
+// Launches only: out[0..n] and tot[0] = total, tot[1] = largest value on
+// the device.
 template <class F, class OUT>
-static int64_t scan_impl(F f, OUT *out, int64_t n, hipStream_t s,
-                         DevArr<int64_t> &tmp, int64_t *max_out,
-                         const int32_t *flag, int32_t *flag_out) {
+static int64_t *scan_launch(F f, OUT *out, int64_t n, hipStream_t s, DevArr<int64_t> &tmp) {
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
     tmp.ensure((size_t)2 * nb + 2, s);
@@ -142,6 +150,14 @@ static int64_t scan_impl(F f, OUT *out, int64_t n, hipStream_t s,
     LAIR_LAUNCH(k_scan_add<OUT>, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
                        0, s, out, n, bs, tot);
     LAIR_LAUNCH_CHECK();
+    return tot;
+}
+
+template <class F, class OUT>
+static int64_t scan_impl(F f, OUT *out, int64_t n, hipStream_t s,
+                         DevArr<int64_t> &tmp, int64_t *max_out,
+                         const int32_t *flag, int32_t *flag_out) {
+    int64_t *tot = scan_launch(f, out, n, s, tmp);
     int64_t h[2] = {0, 0};
     Readback rb(s);
     rb.add(h, tot, sizeof(h));
@@ -1741,7 +1757,7 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
     constexpr int BITS = log2_const<HS>();
     __shared__ int32_t s_key[TEAMS * HS];
     __shared__ double s_val[TEAMS * HS];
-    __shared__ int32_t s_col[TEAMS * HC];   // distinct columns, insertion order
+    __shared__ __align__(16) int32_t s_col[TEAMS * HC];   // distinct columns, insertion order
     __shared__ int16_t s_slot[TEAMS * HC];  // and their slots
     __shared__ int32_t s_n[TEAMS];
     const int team = threadIdx.x / T;
@@ -1792,6 +1808,7 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
                 const double aq = __shfl(a, q, T);
                 int h = -1;
                 double v = 0.0;
+                bool ovf = false;
                 if (e < tot) {
                     const int idx = bq + e - xq;
                     const int32_t col = bj[idx];
@@ -1802,6 +1819,7 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
                         if (old == -1) {
                             int ps = atomicAdd(&s_n[team], 1);
                             if (ps < HC) { lcol[ps] = col; lslot[ps] = (int16_t)h; }
+                            else ovf = true;
                             break;
                         }
                         if (old == col) break;
@@ -1809,10 +1827,12 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
                         h = (h + 1) & (HS - 1);
                     }
                 }
-                // one add per product, issued together by the team
+                // one add per product, issued together by the team; the
+                // wave's LDS atomics complete in issue order, so the sums do
+                // not depend on timing, and no wait is needed between steps
                 if (h >= 0) atomicAdd(&val[h], v);
-                wave_lds_sync();
-                if (s_n[team] > HC) { full = true; break; }
+                // past HC distinct columns the row goes to a larger table
+                if (team_bits<T>(ovf)) { full = true; break; }
             }
         }
         wave_lds_sync();
@@ -1824,10 +1844,24 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
             continue;
         }
         const int64_t o = eoff[i];
+        // rank of each distinct column among them (reads four at a time;
+        // lcol is 16-byte aligned, entries past n are masked)
         for (int u = lane; u < n; u += T) {
             const int32_t c = lcol[u];
+            auto rank4 = [&](int w) {
+                const int4 q = *reinterpret_cast<const int4 *>(lcol + w);
+                return (q.x < c) + (w + 1 < n && q.y < c) + (w + 2 < n && q.z < c) +
+                       (w + 3 < n && q.w < c);
+            };
             int r = 0;
-            for (int w = 0; w < n; ++w) r += lcol[w] < c;
+            if constexpr (HC >= 64) {
+                // long lists: more reads in flight (small tables keep the
+                // registers for occupancy)
+#pragma unroll 4
+                for (int w = 0; w < n; w += 4) r += rank4(w);
+            } else {
+                for (int w = 0; w < n; w += 4) r += rank4(w);
+            }
             tcj[o + r] = c;
             tcx[o + r] = val[lslot[u]];
         }
@@ -2269,6 +2303,108 @@ void launch_dense_inverse(int32_t n, const double *lu, const int32_t *piv,
     int nb = (n + INV_COLS - 1) / INV_COLS;
     LAIR_LAUNCH(k_dense_inverse, dim3(nb), dim3(64),
                        (size_t)n * INV_COLS * sizeof(double), s, n, lu, piv, inv);
+    LAIR_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Split ordering of a level for the cycle: F-points first (ascending), then
+// C-points (ascending, i.e. in coarse-index order).  A permuted copy keeps
+// every row's entries in their stored order with renumbered columns, so a
+// row's sum in the cycle runs in the same order as on the natural matrix.
+// ===========================================================================
+__global__ void k_split_perm(int32_t nf, int32_t nc, const int32_t *flist,
+                             const int32_t *clist, int32_t *perm, int32_t *iperm,
+                             int32_t *ids, int8_t *cf_split) {
+    const int32_t n = nf + nc;
+    const int32_t k = (int32_t)((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const int32_t old = k < nf ? flist[k] : clist[k - nf];
+    perm[k] = old;
+    iperm[old] = k;
+    ids[k] = k;
+    cf_split[k] = k < nf ? 0 : 1;
+}
+
+void launch_split_perm(int32_t nf, int32_t nc, const int32_t *flist, const int32_t *clist,
+                       int32_t *perm, int32_t *iperm, int32_t *ids, int8_t *cf_split,
+                       hipStream_t s) {
+    if (nf + nc == 0) return;
+    LAIR_LAUNCH(k_split_perm, dim3(blocks_for(nf + nc, 256)), dim3(256), 0, s, nf, nc, flist,
+                clist, perm, iperm, ids, cf_split);
+    LAIR_LAUNCH_CHECK();
+}
+
+// New row k is old row rowmap[k]; columns become colmap[c] (nullptr maps
+// are identities).  Values go to v_out and/or v32_out; cjt_out receives
+// the new columns tagged (sign bit) where they are >= nsplit.
+template <int T>
+__global__ void __launch_bounds__(256)
+k_permute_csr(int32_t nrows, const int32_t *rowmap, const int32_t *colmap, const int32_t *rp,
+              const int32_t *cj, const double *v, const int32_t *rp_out, int32_t *cj_out,
+              double *v_out, float *v32_out, int32_t *cjt_out, int32_t nsplit) {
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int32_t k = (int32_t)(gt / T);
+    const int t = (int)(gt % T);
+    if (k >= nrows) return;
+    const int32_t r = rowmap ? rowmap[k] : k;
+    const int32_t lo = rp[r], hi = rp[r + 1];
+    const int64_t o = (int64_t)rp_out[k] - lo;
+    // four entries per lane in flight: loads first, then the column map,
+    // then the stores
+    constexpr int U = 4;
+    for (int32_t base = lo + t; base < hi; base += U * T) {
+        int32_t c[U];
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = base + u * T;
+            c[u] = e < hi ? cj[e] : 0;
+            a[u] = e < hi ? v[e] : 0.0;
+        }
+        if (colmap) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (base + u * T < hi) c[u] = colmap[c[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = base + u * T;
+            if (e < hi) {
+                cj_out[o + e] = c[u];
+                if (v_out) v_out[o + e] = a[u];
+                if (v32_out) v32_out[o + e] = (float)a[u];
+                if (cjt_out)
+                    cjt_out[o + e] = c[u] >= nsplit ? (int32_t)((uint32_t)c[u] | 0x80000000u)
+                                                    : c[u];
+            }
+        }
+    }
+}
+
+void launch_permute_csr(int32_t nrows, int64_t nnz, double mean_row, const int32_t *rowmap,
+                        const int32_t *colmap, const int32_t *rp, const int32_t *cj,
+                        const double *v, int32_t *rp_out, int32_t *cj_out, double *v_out,
+                        float *v32_out, int32_t *cjt_out, int32_t nsplit,
+                        DevArr<int64_t> &tmp, hipStream_t s) {
+    (void)nnz;
+    scan_launch(RowLenF{rp, rowmap}, rp_out, nrows, s, tmp);
+    if (nrows == 0) return;
+    // about four entries per lane
+    const int T = mean_row > 96 ? 32 : mean_row > 48 ? 16 : mean_row > 24 ? 8
+                : mean_row > 12 ? 4 : mean_row > 6 ? 2 : 1;
+#define LAIR_PC(TT)                                                                      \
+    LAIR_LAUNCH((k_permute_csr<TT>), dim3(blocks_for((int64_t)nrows * TT, 256)), dim3(256), \
+                0, s, nrows, rowmap, colmap, rp, cj, v, rp_out, cj_out, v_out, v32_out,  \
+                cjt_out, nsplit)
+    switch (T) {
+        case 1: LAIR_PC(1); break;
+        case 2: LAIR_PC(2); break;
+        case 4: LAIR_PC(4); break;
+        case 8: LAIR_PC(8); break;
+        case 16: LAIR_PC(16); break;
+        default: LAIR_PC(32); break;
+    }
+#undef LAIR_PC
     LAIR_LAUNCH_CHECK();
 }
 

@@ -70,6 +70,15 @@ struct Level {
     // cycle work vectors (capacity h->nrhs_cap right-hand sides)
     DevArr<double> b, x, t, r;
     DevArr<float> b32, x32, t32, r32;
+    // split ordering of a single system's level for the cycle: F-points
+    // first, then C-points.  perm[new] = old, iperm[old] = new, ids[k] = k
+    // (F rows ids[0..nf), C rows ids[nf..n)), cf_split[k] = (k >= nf); As,
+    // Rs, Ps are A, R, P in the split orderings of their row and column
+    // levels, cjt_split As's columns tagged where they are C-points
+    DevArr<int32_t> perm, iperm, ids, cjt_split;
+    DevArr<int8_t> cf_split;
+    DevCSR As, Rs, Ps;
+    bool split = false;
 };
 
 }  // namespace lair
@@ -103,6 +112,10 @@ struct lair_hierarchy {
     lair::DevArr<uint8_t> active_dev;
     lair::DevArr<double> seg_norm;
     lair::DevArr<double> e64;
+    // single system: the cycle runs on split-ordered copies (Level::As ...)
+    // of the levels marked split; an FP64 solve carries b and x in level 0's
+    // split ordering
+    lair::DevArr<double> bsplit, xsplit;
     // captured correction cycles, keyed by (precision, nrhs); replayed on a
     // private stream ordered against the caller's stream with events
     bool batch = false;                      // built by lair_setup_batch
@@ -271,7 +284,10 @@ static void check_options(const lair_strength *s, const lair_options *o) {
     if (o->max_coarse < 1) fail(LAIR_EINVAL, "max_coarse must be >= 1");
     if (!(o->stall > 0.0 && o->stall <= 1.0)) fail(LAIR_EINVAL, "stall must lie in (0, 1]");
     if (o->block_size < 0 || o->block_size > 8) fail(LAIR_EINVAL, "block_size must lie in [0, 8]");
-    if (o->flags & ~LAIR_FLAG_NO_GRAPH) fail(LAIR_EINVAL, "unknown option flags 0x%x", o->flags);
+    if (o->flags & ~(LAIR_FLAG_NO_GRAPH | LAIR_FLAG_NATURAL_ORDER | LAIR_FLAG_SPLIT_ALL))
+        fail(LAIR_EINVAL, "unknown option flags 0x%x", o->flags);
+    if ((o->flags & LAIR_FLAG_NATURAL_ORDER) && (o->flags & LAIR_FLAG_SPLIT_ALL))
+        fail(LAIR_EINVAL, "NATURAL_ORDER and SPLIT_ALL exclude each other");
 }
 
 static const int32_t MAX_DENSE = 4096;
@@ -610,6 +626,113 @@ static void level_stats_and_cc(lair_hierarchy *h) {
     h->oc = sum / nnz0;
 }
 
+// Split-ordered copies of the cycle operators (single systems).  A level is
+// renumbered when it is large and sparse (its F and C sweeps then move
+// mostly vector data, half of it wasted on the other kind's rows in the
+// natural ordering); the renumbered levels form a prefix of the hierarchy
+// and the coarsest level keeps its natural ordering (its dense solve).
+// Mixed precision keeps float values only.
+constexpr int32_t SPLIT_MIN_ROWS = 65536;
+constexpr double SPLIT_MAX_MEAN_ROW = 16.0;
+
+static void build_split(lair_hierarchy *h, hipStream_t s) {
+    const size_t nL = h->L.size();
+    const bool mixed = h->opt.precision == LAIR_MIXED;
+    const bool allowed = h->nsys == 1 && nL > 1 && !(h->opt.flags & LAIR_FLAG_NATURAL_ORDER);
+    const bool all = (h->opt.flags & LAIR_FLAG_SPLIT_ALL) != 0;
+    bool prev = allowed;
+    for (size_t l = 0; l < nL; ++l) {
+        Level &Lv = *h->L[l];
+        const bool big = Lv.n >= SPLIT_MIN_ROWS &&
+                         (double)Lv.A.nnz <= SPLIT_MAX_MEAN_ROW * (double)Lv.n;
+        Lv.split = prev && l + 1 < nL && (all || big);
+        prev = Lv.split;
+    }
+    DevArr<int64_t> tmp;
+    for (size_t l = 0; l + 1 < nL; ++l) {
+        Level &Lv = *h->L[l];
+        if (!Lv.split) continue;
+        const size_t n = (size_t)std::max(Lv.n, 1);
+        Lv.perm.alloc(n, s);
+        Lv.iperm.alloc(n, s);
+        Lv.ids.alloc(n, s);
+        Lv.cf_split.alloc(n, s);
+        launch_split_perm(Lv.nf, Lv.nc, Lv.flist.get(), Lv.clist.get(), Lv.perm.get(),
+                          Lv.iperm.get(), Lv.ids.get(), Lv.cf_split.get(), s);
+    }
+    auto copy = [&](const DevCSR &M, DevCSR &O, const int32_t *rowmap, const int32_t *colmap,
+                    DevArr<int32_t> *cjt, int32_t nsplit) {
+        O.nrows = M.nrows;
+        O.ncols = M.ncols;
+        O.nnz = M.nnz;
+        O.max_row = M.max_row;
+        const size_t z = (size_t)std::max<int64_t>(M.nnz, 1);
+        O.rp.alloc((size_t)M.nrows + 1, s);
+        O.cj.alloc(z, s);
+        if (!mixed) O.v.alloc(z, s); else O.v.release();
+        if (mixed) O.v32.alloc(z, s); else O.v32.release();
+        if (cjt) cjt->alloc(z, s);
+        launch_permute_csr(M.nrows, M.nnz, M.nrows ? (double)M.nnz / M.nrows : 0.0, rowmap,
+                           colmap, M.rp.get(), M.cj.get(), M.v.get(), O.rp.get(), O.cj.get(),
+                           mixed ? nullptr : O.v.get(), mixed ? O.v32.get() : nullptr,
+                           cjt ? cjt->get() : nullptr, nsplit, tmp, s);
+    };
+    auto drop = [](DevCSR &O) {
+        O.rp.release(); O.cj.release(); O.v.release(); O.v32.release();
+        O.nrows = O.ncols = 0; O.nnz = 0;
+    };
+    for (size_t l = 0; l + 1 < nL; ++l) {
+        Level &Lv = *h->L[l];
+        Level &Nx = *h->L[l + 1];
+        const int32_t *perm = Lv.split ? Lv.perm.get() : nullptr;
+        const int32_t *iperm = Lv.split ? Lv.iperm.get() : nullptr;
+        const int32_t *nperm = Nx.split ? Nx.perm.get() : nullptr;
+        const int32_t *niperm = Nx.split ? Nx.iperm.get() : nullptr;
+        if (Lv.split) {
+            copy(Lv.A, Lv.As, perm, iperm, &Lv.cjt_split, Lv.nf);
+        } else {
+            drop(Lv.As);
+            Lv.cjt_split.release();
+        }
+        if (Lv.split || Nx.split) {
+            copy(Lv.R, Lv.Rs, nperm, iperm, nullptr, 0);
+            copy(Lv.P, Lv.Ps, perm, niperm, nullptr, 0);
+        } else {
+            drop(Lv.Rs);
+            drop(Lv.Ps);
+        }
+    }
+}
+
+// After the values of a hierarchy are set: split-ordered copies, the tagged
+// columns and float values of whatever the cycle reads in the natural
+// ordering.
+static void finish_cycle_operators(lair_hierarchy *h, hipStream_t s) {
+    build_split(h, s);
+    const bool mixed = h->opt.precision == LAIR_MIXED;
+    for (size_t l = 0; l < h->L.size(); ++l) {
+        Level &Lv = *h->L[l];
+        if (l + 1 < h->L.size() && !Lv.split && !Lv.cjt.get()) {
+            Lv.cjt.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+            launch_tag_columns(Lv.A.nnz, Lv.A.cj.get(), Lv.cf.get(), Lv.cjt.get(), s);
+        }
+        if (!mixed) continue;
+        if (!Lv.split) {
+            if (Lv.A.v32.get() == nullptr)
+                Lv.A.v32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+            launch_to_float(Lv.A.v.get(), Lv.A.v32.get(), Lv.A.nnz, s);
+        }
+        if (Lv.R.nnz && !Lv.Rs.rp.get()) {
+            if (Lv.R.v32.get() == nullptr) Lv.R.v32.alloc((size_t)Lv.R.nnz, s);
+            launch_to_float(Lv.R.v.get(), Lv.R.v32.get(), Lv.R.nnz, s);
+        }
+        if (Lv.P.nnz && !Lv.Ps.rp.get()) {
+            if (Lv.P.v32.get() == nullptr) Lv.P.v32.alloc((size_t)Lv.P.nnz, s);
+            launch_to_float(Lv.P.v.get(), Lv.P.v32.get(), Lv.P.nnz, s);
+        }
+    }
+}
+
 static void upload_seg(Level &Lv, hipStream_t s) {
     Lv.seg_dev.alloc(Lv.seg.size(), s);
     LAIR_HIP(hipMemcpyAsync(Lv.seg_dev.get(), Lv.seg.data(), sizeof(int64_t) * Lv.seg.size(),
@@ -752,29 +875,13 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         h->L.push_back(std::move(nx));
     }
     finish_coarsest(h.get());
-    for (size_t l = 0; l + 1 < h->L.size(); ++l) {
-        Level &Lv = *h->L[l];
-        Lv.cjt.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
-        launch_tag_columns(Lv.A.nnz, Lv.A.cj.get(), Lv.cf.get(), Lv.cjt.get(), s);
-    }
     for (auto &lp : h->L) {
         Level &Lv = *lp;
         Lv.team_A = team_of(Lv.A);
         Lv.team_R = team_of(Lv.R);
         Lv.team_P = team_of(Lv.P);
-        if (opt->precision == LAIR_MIXED) {
-            Lv.A.v32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
-            launch_to_float(Lv.A.v.get(), Lv.A.v32.get(), Lv.A.nnz, s);
-            if (Lv.R.nnz) {
-                Lv.R.v32.alloc((size_t)Lv.R.nnz, s);
-                launch_to_float(Lv.R.v.get(), Lv.R.v32.get(), Lv.R.nnz, s);
-            }
-            if (Lv.P.nnz) {
-                Lv.P.v32.alloc((size_t)Lv.P.nnz, s);
-                launch_to_float(Lv.P.v.get(), Lv.P.v32.get(), Lv.P.nnz, s);
-            }
-        }
     }
+    finish_cycle_operators(h.get(), s);
     level_stats_and_cc(h.get());
     LAIR_HIP(hipStreamSynchronize(s));
     h->setup_ms = ms_since(t0);
@@ -809,6 +916,10 @@ static void ensure_vectors(lair_hierarchy *h, int32_t nrhs, hipStream_t s) {
     if (mixed) {
         h->r0_32.alloc(n0, s);
         h->e32.alloc(n0, s);
+    }
+    if (h->L[0]->split && !mixed) {
+        h->bsplit.alloc(n0, s);
+        h->xsplit.alloc(n0, s);
     }
     h->partial.alloc((size_t)NPARTIAL * nrhs, s);
     h->norms.alloc((size_t)nrhs, s);
@@ -885,13 +996,14 @@ static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
 template <class VT>
 static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
                 hipStream_t s) {
-    CsrView<VT> A = view<VT>(Lv.A, Lv.team_A);
+    const bool split = Lv.split;
+    CsrView<VT> A = view<VT>(split ? Lv.As : Lv.A, Lv.team_A);
     VT *y = vec<VT>(Lv.t, Lv.t32);
     double om = h->opt.omega;
     const int w = sizeof(VT);
     // batch solve: only the rows of the systems still iterated (device lists)
     const bool act = h->use_act;
-    const int32_t *frows = act ? Lv.act_f.get() : Lv.flist.get();
+    const int32_t *frows = act ? Lv.act_f.get() : (split ? Lv.ids.get() : Lv.flist.get());
     const int32_t *fcnt = act ? Lv.act_cnt.get() + 1 : nullptr;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, false),
@@ -902,10 +1014,12 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, true),
                      2.0 * Lv.nnzF * nrhs);
         CsrView<VT> At = A;
-        At.cjt = Lv.cjt.get();
-        op_jacobi<VT>(At, frows, Lv.nf, b, y, x, Lv.cf.get(), x, false, om, nrhs, s, fcnt);
+        At.cjt = split ? Lv.cjt_split.get() : Lv.cjt.get();
+        op_jacobi<VT>(At, frows, Lv.nf, b, y, x, split ? Lv.cf_split.get() : Lv.cf.get(), x,
+                      false, om, nrhs, s, fcnt);
     }
     const int32_t *crows = act ? Lv.act_c.get()
+                               : split ? Lv.ids.get() + Lv.nf
                                : (Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get());
     const int32_t *ccnt = act ? Lv.act_cnt.get() + 2 : nullptr;
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
@@ -940,7 +1054,7 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
         } else {
             VT *rr = vec<VT>(Lv.r, Lv.r32);
             ProfScope ps("residual", s, ab_rowdot(Lv.A, w, nrhs, 2), 2.0 * Lv.A.nnz * nrhs);
-            op_residual<VT>(view<VT>(Lv.A, Lv.team_A), b, x, rr, nrhs, s);
+            op_residual<VT>(view<VT>(Lv.split ? Lv.As : Lv.A, Lv.team_A), b, x, rr, nrhs, s);
             res = rr;
         }
     }
@@ -952,7 +1066,8 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
             op_rowdot_list<VT>(view<VT>(Lv.R, Lv.team_R), 1, Nx.act_rows.get(),
                                Nx.act_cnt.get(), Nx.n, res, nullptr, bc, s);
         else
-            op_spmv<VT>(view<VT>(Lv.R, Lv.team_R), res, bc, nrhs, false, s);
+            op_spmv<VT>(view<VT>(Lv.Rs.rp.get() ? Lv.Rs : Lv.R, Lv.team_R), res, bc, nrhs, false,
+                        s);
     }
     vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s);
     {
@@ -962,7 +1077,8 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
             op_rowdot_list<VT>(view<VT>(Lv.P, Lv.team_P), x_zero ? 1 : 2, Lv.act_rows.get(),
                                Lv.act_cnt.get(), Lv.n, xc, nullptr, x, s);
         else
-            op_spmv<VT>(view<VT>(Lv.P, Lv.team_P), xc, x, nrhs, !x_zero, s);
+            op_spmv<VT>(view<VT>(Lv.Ps.rp.get() ? Lv.Ps : Lv.P, Lv.team_P), xc, x, nrhs, !x_zero,
+                        s);
     }
     ffc<VT>(h, Lv, b, x, nrhs, s);
 }
@@ -1123,12 +1239,26 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
                        h->bscaled.get(), nrhs, s);
         bb = h->bscaled.get();
     }
+    bool mixed = h->opt.precision == LAIR_MIXED && !transpose;
+    // level 0 renumbered for the cycle: the FP64 iteration carries b and x
+    // in the split ordering (x is written back at the end); the mixed one
+    // keeps them natural, writes its float residual in the split ordering
+    // and adds the correction back row by row
+    const bool split = L0.split && !transpose;
+    const bool vec_split = split && !mixed;
+    const int32_t *orow = split && mixed ? L0.iperm.get() : nullptr;
+    double *const xu = x;
+    if (vec_split) {
+        op_permute_rows(n, nrhs, L0.perm.get(), bb, h->bsplit.get(), true, s);
+        op_permute_rows(n, nrhs, L0.perm.get(), x, h->xsplit.get(), true, s);
+        bb = h->bsplit.get();
+        x = h->xsplit.get();
+    }
     std::vector<double> nb, rn, r_first;
     norms_host(h, bb, nrhs, s, nb);
     CsrView<double> A0 = transpose ? view<double>(L0.At, L0.team_At)
-                                   : view<double>(L0.A, L0.team_A);
+                                   : view<double>(vec_split ? L0.As : L0.A, L0.team_A);
     const DevCSR &M0 = transpose ? L0.At : L0.A;
-    bool mixed = h->opt.precision == LAIR_MIXED && !transpose;
     // fused residual + norms (+ float copy in mixed precision) unless the
     // caller's vectors are not 16-byte aligned
     const bool fused = nrhs == 1 || (((uintptr_t)bb | (uintptr_t)x) & 15u) == 0;
@@ -1138,7 +1268,7 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
                          nrhs * (double)M0.nrows, 2.0 * M0.nnz * nrhs);
             if (!op_residual_norm(A0, bb, x, mixed ? nullptr : h->r0.get(),
                                   mixed ? h->r0_32.get() : nullptr, nrhs, h->partial.get(),
-                                  NPARTIAL, h->norms.get(), st))
+                                  NPARTIAL, h->norms.get(), st, orow))
                 fail(LAIR_EDEVICE, "fused residual not applicable");
             return;
         }
@@ -1179,12 +1309,14 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
             run_iteration(h, IT_MIXED, nrhs, bb, x, s, [&](hipStream_t st) {
                 if (!fused) {
                     ProfScope ps("cast", st, 12.0 * n * nrhs);
-                    op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, st);
+                    if (orow) op_cast_f32_rows(h->r0.get(), h->r0_32.get(), orow, n, nrhs, st);
+                    else op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, st);
                 }
                 vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, st);
                 {
                     ProfScope ps("cast", st, 20.0 * n * nrhs);
-                    op_axpy_f32(x, h->e32.get(), n * nrhs, st);
+                    if (orow) op_axpy_f32_rows(x, h->e32.get(), orow, n, nrhs, st);
+                    else op_axpy_f32(x, h->e32.get(), n * nrhs, st);
                 }
                 residual_and_norms(st);
             });
@@ -1192,6 +1324,7 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
         read_norms(h->norms.get(), nrhs, s, rn);
         ++it;
     }
+    if (vec_split) op_permute_rows(n, nrhs, L0.perm.get(), x, xu, false, s);
     LAIR_HIP(hipStreamSynchronize(s));
     if (info) {
         info->iters = it;
@@ -1582,17 +1715,7 @@ static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_d
         Nx.max_row = mr;
     }
     finish_coarsest(h);
-    if (h->opt.precision == LAIR_MIXED) {
-        for (auto &lp : h->L) {
-            Level &Lv = *lp;
-            // the new coarse operators carry no float copy yet
-            if (Lv.A.v32.get() == nullptr)
-                Lv.A.v32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
-            launch_to_float(Lv.A.v.get(), Lv.A.v32.get(), Lv.A.nnz, s);
-            if (Lv.R.nnz) launch_to_float(Lv.R.v.get(), Lv.R.v32.get(), Lv.R.nnz, s);
-            if (Lv.P.nnz) launch_to_float(Lv.P.v.get(), Lv.P.v32.get(), Lv.P.nnz, s);
-        }
-    }
+    finish_cycle_operators(h, s);
     level_stats_and_cc(h);
     LAIR_HIP(hipStreamSynchronize(s));
 }
@@ -1800,12 +1923,20 @@ lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
                            h->bscaled.get(), nrhs, s);
             bb = h->bscaled.get();
         }
+        Level &L0 = *h->L[0];
         if (h->opt.precision == LAIR_MIXED) {
-            op_residual<double>(view<double>(h->L[0]->A, h->L[0]->team_A), bb, x,
-                                h->r0.get(), nrhs, s);
-            op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
+            op_residual<double>(view<double>(L0.A, L0.team_A), bb, x, h->r0.get(), nrhs, s);
+            if (L0.split) op_cast_f32_rows(h->r0.get(), h->r0_32.get(), L0.iperm.get(), n,
+                                           nrhs, s);
+            else op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, s);
             vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, s);
-            op_axpy_f32(x, h->e32.get(), n * nrhs, s);
+            if (L0.split) op_axpy_f32_rows(x, h->e32.get(), L0.iperm.get(), n, nrhs, s);
+            else op_axpy_f32(x, h->e32.get(), n * nrhs, s);
+        } else if (L0.split) {
+            op_permute_rows(n, nrhs, L0.perm.get(), bb, h->bsplit.get(), true, s);
+            op_permute_rows(n, nrhs, L0.perm.get(), x, h->xsplit.get(), true, s);
+            vcycle<double>(h, 0, h->bsplit.get(), h->xsplit.get(), false, nullptr, nrhs, s);
+            op_permute_rows(n, nrhs, L0.perm.get(), h->xsplit.get(), x, false, s);
         } else {
             vcycle<double>(h, 0, bb, x, false, nullptr, nrhs, s);
         }

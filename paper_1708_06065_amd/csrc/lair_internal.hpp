@@ -185,6 +185,19 @@ int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
                         int32_t *flag_out = nullptr);
 int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
                       hipStream_t s, DevArr<int64_t> &tmp);
+// split ordering (F-points, then C-points): perm[new] = old, iperm[old] =
+// new, ids[k] = k, cf_split[k] = (k >= nf)
+void launch_split_perm(int32_t nf, int32_t nc, const int32_t *flist, const int32_t *clist,
+                       int32_t *perm, int32_t *iperm, int32_t *ids, int8_t *cf_split,
+                       hipStream_t s);
+// permuted copy of a CSR matrix: row k of the copy is row rowmap[k], column
+// c becomes colmap[c] (nullptr: identity); rp_out is written on the device
+// (no synchronisation); v_out, v32_out, cjt_out optional
+void launch_permute_csr(int32_t nrows, int64_t nnz, double mean_row, const int32_t *rowmap,
+                        const int32_t *colmap, const int32_t *rp, const int32_t *cj,
+                        const double *v, int32_t *rp_out, int32_t *cj_out, double *v_out,
+                        float *v32_out, int32_t *cjt_out, int32_t nsplit,
+                        DevArr<int64_t> &tmp, hipStream_t s);
 
 int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
                      const int32_t *cj, const double *v, hipStream_t s);
@@ -315,11 +328,20 @@ void op_update_list(const int32_t *rows, const int32_t *cnt, int32_t cap, double
 // vectors are not 16-byte aligned for nrhs > 1.  partial: npartial * nrhs.
 bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x,
                       double *r64, float *r32, int32_t nrhs, double *partial,
-                      int32_t npartial, double *out, hipStream_t s);
+                      int32_t npartial, double *out, hipStream_t s,
+                      const int32_t *orow = nullptr);
 void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
               int32_t npartial, double *out, hipStream_t s);
 void op_axpy_f32(double *x, const float *e, int64_t n, hipStream_t s);
+// x[i] += e[map[i]], out[map[i]] = (float) in[i] (rows of nrhs)
+void op_axpy_f32_rows(double *x, const float *e, const int32_t *map, int64_t n, int32_t nrhs,
+                      hipStream_t s);
+void op_cast_f32_rows(const double *in, float *out, const int32_t *map, int64_t n,
+                      int32_t nrhs, hipStream_t s);
 void op_cast_f32(const double *in, float *out, int64_t n, hipStream_t s);
+// to_split: out[k] = in[perm[k]]; else out[perm[k]] = in[k] (rows of nrhs)
+void op_permute_rows(int64_t n, int32_t nrhs, const int32_t *perm, const double *in,
+                     double *out, bool to_split, hipStream_t s);
 void op_cast_f64(const float *in, double *out, int64_t n, hipStream_t s);
 void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
                     const double *b, double *out, int32_t nrhs, hipStream_t s);

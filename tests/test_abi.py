@@ -100,12 +100,13 @@ def test_batch_host_validation_without_gpu():
     assert lib.lair_setup_batch(2, arr, None, ctypes.byref(s), ctypes.byref(o), None,
                                 ctypes.byref(out)) == L.LAIR_EINVAL
     assert b"system 1" in lib.lair_last_error()
-    # unknown option flags
-    o.flags = 6
+    # unknown option flags, and the two orderings together
     arr = (L.Csr * 2)(good, good)
-    assert lib.lair_setup_batch(2, arr, None, ctypes.byref(s), ctypes.byref(o), None,
-                                ctypes.byref(out)) == L.LAIR_EINVAL
-    assert out.value is None
+    for f in (8, L.FLAG_NATURAL_ORDER | L.FLAG_SPLIT_ALL):
+        o.flags = f
+        assert lib.lair_setup_batch(2, arr, None, ctypes.byref(s), ctypes.byref(o), None,
+                                    ctypes.byref(out)) == L.LAIR_EINVAL
+        assert out.value is None
     assert lib.lair_solve_batch(None, None, None, 1e-10, 10, None, None, None,
                                 None) == L.LAIR_EINVAL
     assert lib.lair_num_systems(None) == 0
