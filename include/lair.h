@@ -248,6 +248,27 @@ lair_status lair_update_diag(lair_hierarchy *h, const double *diag, int32_t on_d
 int32_t lair_num_systems(const lair_hierarchy *h);
 lair_status lair_system_levels(const lair_hierarchy *h, int32_t *levels);
 
+/* Size buckets of the local solves (Sec. 3.1: one dense system per
+ * C-point).  Systems with S_i <= e[0] are solved one per lane in registers,
+ * S_i <= e[1] by teams of 8 lanes, S_i <= e[2] by teams of 16, S_i <= e[3]
+ * by teams of 32, larger ones by one wave each.  With e[4] = 1 the first
+ * three buckets share one persistent kernel whose blocks take tiles of
+ * systems from a queue; with e[4] = 0 each bucket has a kernel of its own.
+ * Binning and solving need no host synchronisation.  Every bucket performs
+ * the same operations in the same order, so these choices change speed,
+ * never results.  By default the library tunes them: the first time the
+ * process meets a level shape (precision, size class, mean row length,
+ * largest S_i) it times a few candidates on that level and keeps the
+ * fastest for the shape.
+ * lair_set_local_buckets fixes the choice for every later setup of the
+ * process (edges: 5 values with 0 <= e0 <= 4, e0 <= e1 <= 8, e1 <= e2 <= 16,
+ * e2 <= e3 <= 32, e4 in {0, 1}, else EINVAL); NULL returns to tuning.  Not
+ * thread-safe against concurrent setups.  lair_local_buckets reports the
+ * choice a level's local solves used (edges: 5 values; EINVAL for the
+ * coarsest level or a level out of range). */
+lair_status lair_set_local_buckets(const int32_t *edges);
+lair_status lair_local_buckets(const lair_hierarchy *h, int32_t level, int32_t *edges);
+
 /* Number of levels and per-level statistics. */
 int32_t lair_num_levels(const lair_hierarchy *h);
 lair_status lair_level_stats_get(const lair_hierarchy *h, int32_t level,

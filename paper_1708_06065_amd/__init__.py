@@ -115,6 +115,14 @@ class Hierarchy:
             return 1
         return b.shape[1]
 
+    def local_buckets(self, level):
+        """Size-bucket edges and fused flag the local solves of `level` used."""
+        e = np.zeros(5, dtype=np.int32)
+        L.check(L.load().lair_local_buckets(self.handle, int(level),
+                                            e.ctypes.data_as(ctypes.c_void_p)),
+                "lair_local_buckets")
+        return e
+
     def cycle(self, b, x, stream=None):
         """x <- x + B (b - A x): one V-cycle, in place on device tensors."""
         torch = _torch()
@@ -287,6 +295,23 @@ def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels
                 max_levels=max_levels, max_coarse=max_coarse, stall=stall,
                 block_size=block_size, graphs=graphs, ordering=ordering)
     return s, o, opts
+
+
+def set_local_buckets(edges=None):
+    """Fix the size buckets of the local solves for every later setup of the
+    process (5 ints: largest S_i per lane, per 8-, 16- and 32-lane team, and
+    1 to run the first three buckets in the shared persistent kernel), or
+    with None let the library tune them per level shape.  The choice
+    changes speed only; the results are bitwise the same."""
+    lib = L.load()
+    if edges is None:
+        L.check(lib.lair_set_local_buckets(None), "lair_set_local_buckets")
+        return
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    if e.shape != (5,):
+        raise ValueError("edges: 5 values")
+    L.check(lib.lair_set_local_buckets(e.ctypes.data_as(ctypes.c_void_p)),
+            "lair_set_local_buckets")
 
 
 def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",

@@ -76,6 +76,8 @@ EXPORTS = {
     "lair_num_systems": (c_i32, [c_vp]),
     "lair_update_diag": (c_i32, [c_vp, c_vp, c_i32, c_vp]),
     "lair_system_levels": (c_i32, [c_vp, c_vp]),
+    "lair_set_local_buckets": (c_i32, [c_vp]),
+    "lair_local_buckets": (c_i32, [c_vp, c_i32, c_vp]),
     "lair_num_levels": (c_i32, [c_vp]),
     "lair_level_stats_get": (c_i32, [c_vp, c_i32, c_vp]),
     "lair_export": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp]),

@@ -14,9 +14,16 @@
 //   sparse product          row-merge: one team per output row merges the
 //                           sorted rows of B selected by a row of A
 //   transpose, coarsest LU  support for the cycle and its adjoint
+#include <algorithm>
+#include <array>
 #include <cfloat>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "k_common.hpp"
 #include "lair_internal.hpp"
@@ -567,10 +574,6 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
 // least-squares kernel.
 // ===========================================================================
 constexpr double SING_TOL = 1e-14;
-// mean entries per row above which the local solves start with teams
-constexpr double LONG_ROW = 12.0;
-// number of systems at or below which the local solves start with teams
-constexpr int32_t FEW_SYSTEMS = 65536;
 
 __device__ __forceinline__ void write_r_row(int32_t rbase, int s, int32_t i,
                                             const int32_t *l, const double *z,
@@ -587,34 +590,34 @@ __device__ __forceinline__ void write_r_row(int32_t rbase, int s, int32_t i,
     r_v[rbase + ip] = 1.0;
 }
 
-// One lane per system, s <= SM, everything in registers.  MIXED factorises
-// in float and refines once in double: r = f - M z is -(R_i A)(N) computed
-// from the rows of A, then z += LU^{-1} r.
+// Every solver below performs the same floating-point operations in the
+// same order, so a system's z does not depend on which of them takes it
+// (the size buckets only change speed):
+//   * pivot of step k: the largest |M[r][k]| among the rows not yet used,
+//     ties to the row at the smallest position, positions being those of
+//     partial pivoting with row exchanges;
+//   * each remaining row r: m = M[r][k] / M[k][k]; M[r][j] -= m M[k][j]
+//     for j > k; f_r -= m f_k;
+//   * back substitution column by column from the last: z_k = f_k / U[k][k],
+//     then f_r -= U[r][k] z_k for the rows above;
+//   * MIXED: the factorisation runs in float; the double residual
+//     r_p = f_p - sum_k M[p][k] z_k is summed from the last column down,
+//     then the same eliminations and back substitution run on r and z += d.
+
+// One lane per system, s <= SM, everything in registers.
 template <int SM, bool MIXED>
-__global__ void __launch_bounds__(256)
-k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
-              const int32_t *clist,
-              const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
-              const int32_t *cj, const double *v, int32_t *r_cj, double *r_v,
-              int8_t *flags, int32_t *big, int32_t *nbig, int32_t *sing,
-              int32_t *nsing) {
+__device__ __forceinline__ void lane_solve(int32_t c, const int32_t *clist, const int32_t *nptr,
+                           const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+                           const double *v, int32_t *r_cj, double *r_v, int8_t *flags,
+                           int32_t *sing, int32_t *nsing) {
     using FT = typename std::conditional<MIXED, float, double>::type;
-    int32_t tid = (int32_t)xcd_block_id() * blockDim.x + threadIdx.x;
-    if (tid >= nlist) return;
-    if (list_count && tid >= *list_count) return;
-    int32_t c = list ? list[tid] : tid;
-    int32_t i = clist[c];
-    int32_t n0 = nptr[c];
-    int s = nptr[c + 1] - n0;
-    int32_t rbase = n0 + c;
-    flags[c] = 0;
+    const int32_t i = clist[c];
+    const int32_t n0 = nptr[c];
+    const int s = nptr[c + 1] - n0;
+    const int32_t rbase = n0 + c;
     if (s == 0) {
         r_cj[rbase] = i;
         r_v[rbase] = 1.0;
-        return;
-    }
-    if (s > SM) {
-        big[atomicAdd(nbig, 1)] = c;
         return;
     }
     int li[SM];
@@ -664,7 +667,7 @@ k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
         for (int q = 0; q < SM; ++q) rs += fabs(Md[p][q]);
         mnorm = fmax(mnorm, rs);
     }
-    double tol = SING_TOL * mnorm;
+    const double tol = SING_TOL * mnorm;
     int perm[SM];
 #pragma unroll
     for (int p = 0; p < SM; ++p) perm[p] = p;
@@ -694,12 +697,11 @@ k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
                         int tp = perm[k]; perm[k] = perm[r]; perm[r] = tp;
                     }
                 }
-                FT inv = (FT)1 / M[k][k];
 #pragma unroll
                 for (int r = k + 1; r < SM; ++r) {
                     if (r < s) {
-                        FT mult = M[r][k] * inv;
-                        M[r][k] = mult;               // keep L for refinement
+                        const FT mult = M[r][k] / M[k][k];
+                        M[r][k] = mult;               // kept for the refinement
 #pragma unroll
                         for (int q = k + 1; q < SM; ++q) M[r][q] -= mult * M[k][q];
                         fw[r] -= mult * fw[k];
@@ -714,29 +716,25 @@ k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
         return;
     }
     double z[SM];
+    double res[SM];
+#pragma unroll
+    for (int p = 0; p < SM; ++p) res[p] = f[p];
 #pragma unroll
     for (int k = SM - 1; k >= 0; --k) {
+        z[k] = 0.0;
         if (k < s) {
-            FT acc = fw[k];
+            const FT zk = fw[k] / M[k][k];
 #pragma unroll
-            for (int q = k + 1; q < SM; ++q)
-                if (q < s) acc -= M[k][q] * (FT)z[q];
-            z[k] = (double)(acc / M[k][k]);
-        } else {
-            z[k] = 0.0;
+            for (int r = 0; r < k; ++r) fw[r] -= M[r][k] * zk;
+            z[k] = (double)zk;
+            if (MIXED) {
+#pragma unroll
+                for (int p = 0; p < SM; ++p) res[p] -= Md[p][k] * (double)zk;
+            }
         }
     }
     if (MIXED) {
-        // residual r = f - M z in double from the unfactorised copy
-        double res[SM];
-#pragma unroll
-        for (int p = 0; p < SM; ++p) {
-            double acc = f[p];
-#pragma unroll
-            for (int q = 0; q < SM; ++q) acc -= Md[p][q] * z[q];
-            res[p] = acc;
-        }
-        // solve with the float factors: apply the row permutation, L, U
+        // the residual in pivot order, then L, then U
         FT w[SM];
 #pragma unroll
         for (int k = 0; k < SM; ++k) {
@@ -754,12 +752,10 @@ k_local_small(int32_t nlist, const int32_t *list, const int32_t *list_count,
 #pragma unroll
         for (int k = SM - 1; k >= 0; --k) {
             if (k < s) {
-                FT acc = w[k];
+                const FT dk = w[k] / M[k][k];
 #pragma unroll
-                for (int q = k + 1; q < SM; ++q)
-                    if (q < s) acc -= M[k][q] * w[q];
-                w[k] = acc / M[k][k];
-                z[k] += (double)w[k];
+                for (int r = 0; r < k; ++r) w[r] -= M[r][k] * dk;
+                z[k] += (double)dk;
             }
         }
     }
@@ -803,7 +799,7 @@ __device__ __forceinline__ int team_scan_incl(int x) {
 // one-wave kernel, whose scratch may sit in global memory) over a wave
 // fence.  Md, when given, receives the same entries in double.
 template <int T, int U, bool BLOCK, class FT>
-__device__ void gather_local(int p, int s, const int32_t *ln, int32_t *off, int32_t *st,
+__device__ __forceinline__ void gather_local(int p, int s, const int32_t *ln, int32_t *off, int32_t *st,
                              const int32_t *rp, const int32_t *cj, const double *v,
                              FT *M, int ldm, double *Md) {
     int carry = 0;
@@ -863,53 +859,25 @@ __device__ void gather_local(int p, int s, const int32_t *ln, int32_t *off, int3
     }
 }
 
-// One team of T lanes per system with s <= T (T = 8, 16, 32; a team is part
-// of one wave).  The gather writes M into the team's LDS tile; lane p then
-// holds row p of M in registers.  Gaussian elimination with partial
-// pivoting keeps the rows in place: at step k the pivot is the
-// not-yet-used row with the largest |M[r][k]|, its row is broadcast by
-// shuffles and the other unused rows eliminate column k.
-// Back substitution runs over the pivots in reverse order, column by
-// column: the pivot lane of step k yields z_k and every lane removes
-// column k from its right-hand side.  MIXED factorises a float copy and
-// refines once with the double tile kept in LDS.  list == nullptr takes
-// every C-point in order.
+// One team of T lanes (part of one wave) per system with s <= T.  The
+// gather writes M into the team's LDS tile; lane p then holds row p of M in
+// registers.  Rows stay in place: at step k the pivot row is found by an
+// arg-max over the unused lanes, broadcast by shuffles, and the other
+// unused rows eliminate column k.  Back substitution: the pivot lane of
+// step k yields z_k and every lane removes column k from its right-hand
+// side.  LDS of the team: M (T x T doubles), f (T doubles), ln, pv, st
+// (T ints each) and off (T + 1 ints), as typed LDS arrays.
 template <int T, bool MIXED>
-__global__ void __launch_bounds__(T >= 32 ? 128 : 256)
-k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
-             const int32_t *clist, const int32_t *nptr, const int32_t *nbr,
-             const int32_t *rp, const int32_t *cj, const double *v, int32_t *r_cj,
-             double *r_v, int8_t *flags, int32_t *defer, int32_t *ndefer,
-             int32_t *sing, int32_t *nsing) {
+__device__ __forceinline__ void team_solve(int p, int32_t c, const int32_t *clist, const int32_t *nptr,
+                           const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+                           const double *v, int32_t *r_cj, double *r_v, int8_t *flags,
+                           int32_t *sing, int32_t *nsing, double *M, double *f, int32_t *ln,
+                           int32_t *pv, int32_t *sst, int32_t *soff) {
     using FT = typename std::conditional<MIXED, float, double>::type;
-    constexpr int BS = (T >= 32) ? 128 : 256;
-    constexpr int TEAMS = BS / T;
-    __shared__ double sM[TEAMS][T * T];
-    __shared__ double sf[TEAMS][T];
-    __shared__ int32_t sl[TEAMS][T];
-    __shared__ int32_t soff[TEAMS][T + 1];
-    __shared__ int32_t sst[TEAMS][T];
-    __shared__ int32_t spv[TEAMS][T];
-    const int team = threadIdx.x / T;
-    const int p = threadIdx.x % T;                  // this lane's row / column
-    int64_t gt = xcd_block_id() * BS + threadIdx.x;
-    int32_t tid = (int32_t)(gt / T);
-    if (tid >= nlist) return;
-    if (list_count && tid >= *list_count) return;
-    const int32_t c = list ? list[tid] : tid;
     const int32_t i = clist[c];
     const int32_t n0 = nptr[c];
     const int s = nptr[c + 1] - n0;
     const int32_t rbase = n0 + c;
-    if (p == 0) flags[c] = 0;
-    if (s > T) {
-        if (p == 0) defer[atomicAdd(ndefer, 1)] = c;
-        return;
-    }
-    double *M = sM[team];
-    double *f = sf[team];
-    int32_t *ln = sl[team];
-    int32_t *pv = spv[team];
     const int32_t lp = (p < s) ? nbr[n0 + p] : INT_MAX;
     ln[p] = lp;
     f[p] = 0.0;
@@ -917,8 +885,7 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
 #pragma unroll
     for (int j = 0; j < T; ++j) M[j * T + p] = 0.0;
     wave_lds_sync();
-    gather_local<T, 4, false, double>(p, s, ln, soff[team], sst[team], rp, cj, v, M, T,
-                                      nullptr);
+    gather_local<T, 4, false, double>(p, s, ln, soff, sst, rp, cj, v, M, T, nullptr);
     for (int e = rp[i] + p; e < rp[i + 1]; e += T) {
         int q = bsearch_i32(ln, s, cj[e]);
         if (q >= 0) f[q] = -v[e];
@@ -941,10 +908,7 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
     // every join
     bool used = (p >= s);
     bool singular = false;
-    // ties go to the row that partial pivoting with row exchanges would
-    // take: the one at the smallest position, positions being permuted by
-    // the exchanges of the earlier steps
-    int pos = p;
+    int pos = p;          // this row's position under the row exchanges
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const bool act = k < s;
@@ -976,10 +940,6 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
         return;
     }
     wave_lds_sync();
-    // back substitution, last pivot first, column by column: the pivot
-    // lane of step k yields z_k and every lane removes column k from its
-    // right-hand side; in MIXED the double residual r = f - M z builds up
-    // alongside from the LDS tile
     double zq = 0.0;
     double r = f0;
 #pragma unroll
@@ -992,7 +952,6 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
         if (MIXED) r -= M[p * T + k] * (double)zk;
     }
     if (MIXED) {
-        // the same eliminations and back substitution on r
         FT rr = (FT)r;
 #pragma unroll
         for (int k = 0; k < T; ++k) {
@@ -1021,11 +980,143 @@ k_local_team(int32_t nlist, const int32_t *list, const int32_t *list_count,
     }
 }
 
-// One wave per system (blockDim = 64).  M lives in dynamic LDS sized for
-// the level's largest system up to WSMAX, beyond that in a global scratch
-// slab of 3 smax^2 doubles per block.  The gather enumerates the entries of
-// the rows l_p as one flat range over the lanes.  MIXED keeps a double copy
-// of M for the refinement residual.
+// Size buckets: 0 one lane (s <= e0 <= 4), 1 eight lanes (s <= e1 <= 8),
+// 2 sixteen (s <= e2 <= 16), 3 thirty-two (s <= e3 <= 32), 4 one wave.
+// fused: buckets 0-2 share the persistent kernel, else each has its own.
+struct Buckets {
+    int32_t e[4];
+    int32_t fused;
+};
+constexpr int NBUCKET = 5;
+
+// List every C-point under its bucket.  Positions come from LDS counters
+// per block and one global atomic per block and bucket (the order within a
+// bucket does not affect any result).
+__global__ void __launch_bounds__(256)
+k_local_bin(int32_t nc, const int32_t *nptr, Buckets bk, int32_t *cnt, int32_t *lists,
+            int8_t *flags) {
+    __shared__ int32_t s_cnt[NBUCKET], s_base[NBUCKET];
+    if (threadIdx.x < NBUCKET) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t c = (int32_t)(xcd_block_id() * blockDim.x + threadIdx.x);
+    int b = -1, pos = 0;
+    if (c < nc) {
+        const int s = nptr[c + 1] - nptr[c];
+        b = s <= bk.e[0] ? 0 : s <= bk.e[1] ? 1 : s <= bk.e[2] ? 2 : s <= bk.e[3] ? 3 : 4;
+        flags[c] = 0;
+        pos = atomicAdd(&s_cnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < NBUCKET)
+        s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(&cnt[threadIdx.x], s_cnt[threadIdx.x])
+                                                 : 0;
+    __syncthreads();
+    if (b >= 0) lists[(int64_t)b * nc + s_base[b] + pos] = c;
+}
+
+// The persistent local-solve kernel: every block takes tiles from one
+// queue (a ticket counter) until none is left, a tile being 32 systems of
+// the 8-lane bucket, 16 of the 16-lane bucket or 256 of the one-lane bucket
+// (larger buckets first).  Bucket lengths are read on the device, so no
+// host synchronisation separates binning from solving.  The 32-lane and
+// one-wave buckets always run as kernels of their own (their registers and
+// LDS would halve the residency of the others); whether buckets 0-2 share
+// this kernel or take one each is part of the tuned choice, since sharing
+// takes the footprint of the 16-lane path for all three.
+constexpr int PERSIST_BS = 256;
+// LDS of the shared kernel: the 8-lane (32 teams) and 16-lane (16 teams)
+// layouts over the same typed arrays
+constexpr int PSM = 16 * 16 * 16;      // M tiles (doubles), >= 32 * 8 * 8
+constexpr int PSV = 256;               // f, ln, pv, st (per team T entries)
+constexpr int PSO = 32 * 9;            // off (T + 1 per team), >= 16 * 17
+
+template <bool MIXED>
+__global__ void __launch_bounds__(PERSIST_BS)
+k_local_persist(const int32_t *cnt, const int32_t *lists, int32_t nc, int32_t *ticket,
+                const int32_t *clist, const int32_t *nptr, const int32_t *nbr,
+                const int32_t *rp, const int32_t *cj, const double *v, int32_t *r_cj,
+                double *r_v, int8_t *flags, int32_t *sing, int32_t *nsing) {
+    __shared__ double sM[PSM];
+    __shared__ double sf[PSV];
+    __shared__ int32_t sl[PSV], spv[PSV], sst[PSV], soff[PSO];
+    __shared__ int32_t s_tile;
+    const int32_t n1 = cnt[0], n8 = cnt[1], n16 = cnt[2];
+    constexpr int P16 = PERSIST_BS / 16, P8 = PERSIST_BS / 8, P1 = PERSIST_BS;
+    const int32_t t16 = (n16 + P16 - 1) / P16, t8 = (n8 + P8 - 1) / P8,
+                  t1 = (n1 + P1 - 1) / P1;
+    const int32_t total = t16 + t8 + t1;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1);
+        __syncthreads();
+        int32_t t = s_tile;
+        __syncthreads();
+        if (t >= total) break;
+        if (t < t16) {
+            const int team = threadIdx.x / 16;
+            const int32_t idx = t * P16 + team;
+            if (idx < n16)
+                team_solve<16, MIXED>(threadIdx.x % 16, lists[2 * (int64_t)nc + idx], clist, nptr,
+                                      nbr, rp, cj, v, r_cj, r_v, flags, sing, nsing,
+                                      sM + team * 256, sf + team * 16, sl + team * 16,
+                                      spv + team * 16, sst + team * 16, soff + team * 17);
+        } else if ((t -= t16) < t8) {
+            const int team = threadIdx.x / 8;
+            const int32_t idx = t * P8 + team;
+            if (idx < n8)
+                team_solve<8, MIXED>(threadIdx.x % 8, lists[(int64_t)nc + idx], clist, nptr, nbr,
+                                     rp, cj, v, r_cj, r_v, flags, sing, nsing, sM + team * 64,
+                                     sf + team * 8, sl + team * 8, spv + team * 8,
+                                     sst + team * 8, soff + team * 9);
+        } else {
+            t -= t8;
+            const int32_t idx = t * P1 + (int32_t)threadIdx.x;
+            if (idx < n1)
+                lane_solve<4, MIXED>(lists[idx], clist, nptr, nbr, rp, cj, v, r_cj, r_v, flags,
+                                     sing, nsing);
+        }
+    }
+}
+
+// One bucket on its own: teams of T lanes (bucket b); the grid covers every
+// C-point (the bucket's length is only known on the device).
+template <int T, bool MIXED>
+__global__ void __launch_bounds__(T >= 32 ? 128 : 256)
+k_local_teams(const int32_t *cnt, int b, const int32_t *list, const int32_t *clist,
+              const int32_t *nptr, const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+              const double *v, int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing,
+              int32_t *nsing) {
+    constexpr int TEAMS = (T >= 32 ? 128 : 256) / T;
+    __shared__ double sM[TEAMS][T * T];
+    __shared__ double sf[TEAMS][T];
+    __shared__ int32_t sl[TEAMS][T], spv[TEAMS][T], sst[TEAMS][T], soff[TEAMS][T + 1];
+    const int team = threadIdx.x / T;
+    const int32_t n = cnt[b];
+    // one system per team: a loop over several would keep more registers
+    // live across iterations and cost residency
+    const int64_t t = (int64_t)xcd_block_id() * TEAMS + team;
+    if (t < n)
+        team_solve<T, MIXED>(threadIdx.x % T, list[t], clist, nptr, nbr, rp, cj, v, r_cj, r_v,
+                             flags, sing, nsing, sM[team], sf[team], sl[team], spv[team],
+                             sst[team], soff[team]);
+}
+
+// The one-lane bucket on its own: one system per thread.
+template <bool MIXED>
+__global__ void __launch_bounds__(256)
+k_local_lane(const int32_t *cnt, const int32_t *list, const int32_t *clist,
+             const int32_t *nptr, const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+             const double *v, int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing,
+             int32_t *nsing) {
+    const int64_t t = xcd_block_id() * blockDim.x + threadIdx.x;
+    if (t >= cnt[0]) return;
+    lane_solve<4, MIXED>(list[t], clist, nptr, nbr, rp, cj, v, r_cj, r_v, flags, sing, nsing);
+}
+
+// One wave per system (blockDim = 64), rows exchanged in LDS.  M lives in
+// dynamic LDS sized for the level's largest system up to WSMAX, beyond that
+// in a global scratch slab of 3 smax^2 doubles per block.  The gather
+// enumerates the entries of the rows l_p as one flat range over the lanes.
+// MIXED keeps a double copy of M for the refinement residual.
 constexpr int WSMAX = 64;
 
 template <class FT>
@@ -1036,18 +1127,13 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int cap) {
 }
 
 template <bool MIXED>
-__global__ void __launch_bounds__(64)
-k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
-             const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
-             const int32_t *cj, const double *v, int32_t *r_cj, double *r_v,
-             int8_t *flags, int32_t *sing, int32_t *nsing, double *gscratch,
-             int32_t smax, int32_t cap) {
+__device__ __forceinline__ void wave_solve(int32_t c, const int32_t *clist, const int32_t *nptr,
+                           const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+                           const double *v, int32_t *r_cj, double *r_v, int8_t *flags,
+                           int32_t *sing, int32_t *nsing, double *dyn, double *slab,
+                           int32_t smax, int32_t cap) {
     using FT = typename std::conditional<MIXED, float, double>::type;
-    extern __shared__ double dyn[];
     int lane = threadIdx.x;
-    int32_t b = blockIdx.x;
-    if (b >= nlist) return;
-    int32_t c = list[b];
     int32_t i = clist[c];
     int32_t n0 = nptr[c];
     int s = nptr[c + 1] - n0;
@@ -1057,7 +1143,7 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
     const int32_t m = (s <= cap) ? cap : smax;   // capacity of this layout
     // layout: z, f, Md (double; Md only in MIXED), M, w (FT), ln, perm,
     // off, st (int)
-    double *z = (s <= cap) ? dyn : gscratch + (size_t)b * (size_t)smax * (size_t)smax * 3;
+    double *z = (s <= cap) ? dyn : slab;
     double *f = z + m;
     double *Md = MIXED ? f + m : nullptr;
     FT *M = (FT *)(f + m + (MIXED ? (size_t)m * m : 0));
@@ -1108,9 +1194,8 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
             }
         }
         __syncthreads();
-        FT inv = (FT)1 / M[k * s + k];
         for (int r = k + 1 + lane; r < s; r += 64) {
-            FT mult = M[r * s + k] * inv;
+            const FT mult = M[r * s + k] / M[k * s + k];
             M[r * s + k] = mult;
             w[r] -= mult * w[k];
         }
@@ -1145,7 +1230,7 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
         double *res = f;
         for (int p = lane; p < s; p += 64) {
             double acc = res[p];
-            for (int q = 0; q < s; ++q) acc -= Md[p * s + q] * z[q];
+            for (int q = s - 1; q >= 0; --q) acc -= Md[p * s + q] * z[q];
             res[p] = acc;
         }
         __syncthreads();
@@ -1176,6 +1261,25 @@ k_local_wave(const int32_t *list, int32_t nlist, const int32_t *clist,
     if (lane == 0) {
         r_cj[rbase + ip] = i;
         r_v[rbase + ip] = 1.0;
+    }
+}
+
+// The one-wave bucket: a fixed grid striding over the bucket's length on
+// the device, one global slab per block.
+template <bool MIXED>
+__global__ void __launch_bounds__(64)
+k_local_wave(const int32_t *cnt, const int32_t *list, const int32_t *clist,
+             const int32_t *nptr, const int32_t *nbr, const int32_t *rp, const int32_t *cj,
+             const double *v, int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing,
+             int32_t *nsing, double *gscratch, int32_t smax, int32_t cap) {
+    extern __shared__ double dyn[];
+    const int32_t n = cnt[4];
+    double *slab = gscratch ? gscratch + (size_t)blockIdx.x * (size_t)smax * (size_t)smax * 3
+                            : nullptr;
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        wave_solve<MIXED>(list[t], clist, nptr, nbr, rp, cj, v, r_cj, r_v, flags, sing, nsing,
+                          dyn, slab, smax, cap);
+        __syncthreads();
     }
 }
 
@@ -1321,66 +1425,181 @@ k_local_cost(int32_t nc, const int32_t *clist, const int32_t *nptr,
         for (int k = 0; k < 4; ++k) atomicAdd(acc + k, sh[k][0]);
 }
 
-// nlist bounds the grid; with list_count the pass reads the number of
-// listed systems on the device (no host synchronisation between passes).
-template <int SM>
-static void small_pass(bool mixed, int32_t nlist, const int32_t *list,
-                       const int32_t *list_count, const int32_t *clist,
-                       const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
-                       const int32_t *cj, const double *v, LocalSolveOut out,
-                       int32_t *defer, int32_t *ndefer, int32_t *sing, int32_t *nsing,
-                       hipStream_t s) {
-    if (nlist == 0) return;
-    if (mixed)
-        LAIR_LAUNCH((k_local_small<SM, true>), dim3(blocks_for(nlist, 256)), dim3(256),
-                           0, s, nlist, list, list_count, clist, nptr, nbr, rp, cj, v, out.r_cj,
-                           out.r_v, out.flags, defer, ndefer, sing, nsing);
-    else
-        LAIR_LAUNCH((k_local_small<SM, false>), dim3(blocks_for(nlist, 256)), dim3(256),
-                           0, s, nlist, list, list_count, clist, nptr, nbr, rp, cj, v, out.r_cj,
-                           out.r_v, out.flags, defer, ndefer, sing, nsing);
-    LAIR_LAUNCH_CHECK();
+// ---------------------------------------------------------------------------
+// Bucket edges.  Fixed by the caller (set_local_buckets), else chosen per
+// level shape (precision, size class, mean row length, largest system) by
+// timing a few candidates the first time the process meets that shape.
+// Every candidate yields the same z bit for bit; only the speed differs.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_bk_mu;
+bool g_bk_fixed = false;
+Buckets g_bk_edges{{4, 8, 16, 32}, 0};
+std::map<std::array<int32_t, 4>, Buckets> g_bk_cache;
+const Buckets BK_CANDIDATES[] = {{{4, 8, 16, 32}, 0}, {{0, 8, 16, 32}, 0},
+                                 {{4, 8, 16, 32}, 1}, {{0, 8, 16, 32}, 1},
+                                 {{2, 6, 12, 32}, 0}, {{4, 8, 12, 24}, 0},
+                                 {{4, 8, 16, 16}, 0}, {{0, 8, 16, 16}, 1}};
+
+// LAIR_TUNE_LOG=1 prints every tuning measurement to stderr
+bool tune_log() {
+    static const bool on = [] {
+        const char *e = getenv("LAIR_TUNE_LOG");
+        return e && e[0] == '1';
+    }();
+    return on;
 }
 
-template <int T>
-static void team_pass(bool mixed, int32_t nlist, const int32_t *list,
-                      const int32_t *list_count, const int32_t *clist,
-                      const int32_t *nptr, const int32_t *nbr, const int32_t *rp,
-                      const int32_t *cj, const double *v, LocalSolveOut out,
-                      int32_t *defer, int32_t *ndefer, int32_t *sing, int32_t *nsing,
-                      hipStream_t s) {
-    if (nlist == 0) return;
-    constexpr int BS = (T >= 32) ? 128 : 256;
-    dim3 g(blocks_for((int64_t)nlist * T, BS)), b(BS);
-    if (mixed)
-        LAIR_LAUNCH((k_local_team<T, true>), g, b, 0, s, nlist, list, list_count, clist,
-                           nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer, ndefer,
-                           sing, nsing);
-    else
-        LAIR_LAUNCH((k_local_team<T, false>), g, b, 0, s, nlist, list, list_count, clist,
-                           nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, defer, ndefer,
-                           sing, nsing);
-    LAIR_LAUNCH_CHECK();
+int ilog2_floor(int64_t v) {
+    int l = 0;
+    while (v > 1) { v >>= 1; ++l; }
+    return l;
 }
 
-// Size buckets: s <= 4 one lane per system (registers); s <= 8, 16, 32 one
-// team of 8, 16, 32 lanes per system; larger systems one wave each.  Each
-// pass defers the systems too large for it to a list for the next one.
-// Where rows are long (coarse Galerkin operators) one lane cannot gather a
-// system quickly, and the teams start with every system.
+// resident blocks of the persistent kernel on the current device
+unsigned persist_resident(bool mixed) {
+    static int cache[2][16] = {};
+    int dev = 0;
+    LAIR_HIP(hipGetDevice(&dev));
+    int &c = cache[mixed ? 1 : 0][dev & 15];
+    if (c == 0) {
+        int ncu = 0, per = 0;
+        LAIR_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        if (mixed)
+            LAIR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_local_persist<true>,
+                                                                  PERSIST_BS, 0));
+        else
+            LAIR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_local_persist<false>,
+                                                                  PERSIST_BS, 0));
+        c = std::max(1, ncu) * std::max(1, per);
+    }
+    return (unsigned)c;
+}
+}  // namespace
+
+void set_local_buckets(const int32_t *e) {
+    std::lock_guard<std::mutex> g(g_bk_mu);
+    if (!e) {
+        g_bk_fixed = false;
+        return;
+    }
+    if (!(e[0] >= 0 && e[0] <= 4 && e[1] >= e[0] && e[1] <= 8 && e[2] >= e[1] && e[2] <= 16 &&
+          e[3] >= e[2] && e[3] <= 32 && (e[4] == 0 || e[4] == 1)))
+        fail(LAIR_EINVAL, "bucket edges must satisfy 0 <= e0 <= 4, e0 <= e1 <= 8, "
+                          "e1 <= e2 <= 16, e2 <= e3 <= 32, and the fused flag be 0 or 1");
+    g_bk_fixed = true;
+    for (int k = 0; k < 4; ++k) g_bk_edges.e[k] = e[k];
+    g_bk_edges.fused = e[4];
+}
+
+namespace {
+struct LocalRun {
+    int32_t nc;
+    const int32_t *clist, *nptr, *nbr, *rp, *cj;
+    const double *v;
+    bool mixed;
+    int32_t smax;
+    LocalSolveOut out;
+    int32_t *cnt, *lists, *sing;          // cnt[0..4] buckets, cnt[5] ticket, cnt[6] nsing
+    double *gscratch;
+    unsigned gw;
+};
+
+// Binning, the persistent kernel, the 32-lane and one-wave buckets: no
+// host synchronisation.
+void run_buckets(const LocalRun &r, const Buckets &bk, hipStream_t s) {
+    LAIR_HIP(hipMemsetAsync(r.cnt, 0, 7 * sizeof(int32_t), s));
+    int32_t *ticket = r.cnt + 5, *nsing = r.cnt + 6;
+    LAIR_LAUNCH(k_local_bin, dim3(blocks_for(r.nc, 256)), dim3(256), 0, s, r.nc, r.nptr, bk,
+                r.cnt, r.lists, r.out.flags);
+    LAIR_LAUNCH_CHECK();
+    const int32_t *l1 = r.lists, *l8 = r.lists + (int64_t)r.nc,
+                  *l16 = r.lists + 2 * (int64_t)r.nc, *l32 = r.lists + 3 * (int64_t)r.nc;
+    // teams of T over bucket b, a team for every C-point at most
+    auto teams = [&](auto tag, int b, const int32_t *list) {
+        constexpr int T = decltype(tag)::value;
+        constexpr int BS = T >= 32 ? 128 : 256;
+        const unsigned g = (unsigned)((r.nc + BS / T - 1) / (BS / T));
+        if (r.mixed)
+            LAIR_LAUNCH((k_local_teams<T, true>), dim3(g), dim3(BS), 0, s, r.cnt, b, list,
+                        r.clist, r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj, r.out.r_v,
+                        r.out.flags, r.sing, nsing);
+        else
+            LAIR_LAUNCH((k_local_teams<T, false>), dim3(g), dim3(BS), 0, s, r.cnt, b, list,
+                        r.clist, r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj, r.out.r_v,
+                        r.out.flags, r.sing, nsing);
+        LAIR_LAUNCH_CHECK();
+    };
+    if (bk.fused) {
+        const unsigned gp = (unsigned)std::min<int64_t>(persist_resident(r.mixed),
+                                                        std::max<int64_t>(1, (r.nc + 15) / 16));
+        if (r.mixed)
+            LAIR_LAUNCH(k_local_persist<true>, dim3(gp), dim3(PERSIST_BS), 0, s, r.cnt, r.lists,
+                        r.nc, ticket, r.clist, r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj,
+                        r.out.r_v, r.out.flags, r.sing, nsing);
+        else
+            LAIR_LAUNCH(k_local_persist<false>, dim3(gp), dim3(PERSIST_BS), 0, s, r.cnt,
+                        r.lists, r.nc, ticket, r.clist, r.nptr, r.nbr, r.rp, r.cj, r.v,
+                        r.out.r_cj, r.out.r_v, r.out.flags, r.sing, nsing);
+        LAIR_LAUNCH_CHECK();
+    } else {
+        if (r.mixed)
+            LAIR_LAUNCH(k_local_lane<true>, dim3(blocks_for(r.nc, 256)), dim3(256), 0, s, r.cnt,
+                        l1, r.clist, r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj, r.out.r_v,
+                        r.out.flags, r.sing, nsing);
+        else
+            LAIR_LAUNCH(k_local_lane<false>, dim3(blocks_for(r.nc, 256)), dim3(256), 0, s,
+                        r.cnt, l1, r.clist, r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj,
+                        r.out.r_v, r.out.flags, r.sing, nsing);
+        LAIR_LAUNCH_CHECK();
+        if (r.smax > bk.e[0]) teams(std::integral_constant<int, 8>{}, 1, l8);
+        if (r.smax > bk.e[1]) teams(std::integral_constant<int, 16>{}, 2, l16);
+    }
+    if (r.smax > bk.e[2]) teams(std::integral_constant<int, 32>{}, 3, l32);
+    if (r.smax > bk.e[3]) {
+        const int32_t cap = r.smax < WSMAX ? r.smax : WSMAX;
+        const int32_t *l4 = r.lists + 4 * (int64_t)r.nc;
+        const size_t lds = r.mixed ? wave_lds_bytes<float>(cap) : wave_lds_bytes<double>(cap);
+        if (r.mixed)
+            LAIR_LAUNCH(k_local_wave<true>, dim3(r.gw), dim3(64), lds, s, r.cnt, l4, r.clist,
+                        r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj, r.out.r_v, r.out.flags,
+                        r.sing, nsing, r.gscratch, r.smax, cap);
+        else
+            LAIR_LAUNCH(k_local_wave<false>, dim3(r.gw), dim3(64), lds, s, r.cnt, l4, r.clist,
+                        r.nptr, r.nbr, r.rp, r.cj, r.v, r.out.r_cj, r.out.r_v, r.out.flags,
+                        r.sing, nsing, r.gscratch, r.smax, cap);
+        LAIR_LAUNCH_CHECK();
+    }
+}
+}  // namespace
+
+// Local solves of one level: bucket edges (fixed, cached or tuned), one
+// pass over the buckets, one readback (bucket sizes and the number of
+// singular systems), then least squares for the singular ones.
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
-                     LocalSolveOut out, hipStream_t s) {
+                     LocalSolveOut out, hipStream_t s, int32_t *edges_used) {
     if (nc == 0) return 0;
-    DevArr<int32_t> lists, counters;
-    lists.alloc((size_t)nc * 5, s);
-    int32_t *listA = lists.get(), *listB = listA + nc, *listC = listB + nc,
-            *listD = listC + nc, *sing = listD + nc;
-    counters.alloc(5, s);
-    LAIR_HIP(hipMemsetAsync(counters.get(), 0, 5 * sizeof(int32_t), s));
-    int32_t *nA = counters.get(), *nB = nA + 1, *nC = nA + 2, *nD = nA + 3, *nS = nA + 4;
-    bool mixed = (precision == LAIR_MIXED);
+    const bool mixed = (precision == LAIR_MIXED);
+    DevArr<int32_t> work;
+    work.alloc((size_t)nc * (NBUCKET + 1) + 8, s);
+    LocalRun r{nc, clist, nptr, nbr, rp, cj, v, mixed, smax, out, work.get(),
+               work.get() + 8, work.get() + 8 + (size_t)nc * NBUCKET, nullptr, 1};
+    // the one-wave bucket: a fixed grid; systems above WSMAX use a global
+    // slab per block, the grid kept small enough for 256 MB of slabs
+    DevArr<double> gscratch;
+    {
+        const int32_t cap = smax < WSMAX ? smax : WSMAX;
+        int64_t gw = std::min<int64_t>(nc, 2048);
+        if (smax > cap) {
+            const int64_t slab = 3 * (int64_t)smax * smax * (int64_t)sizeof(double);
+            gw = std::max<int64_t>(1, std::min<int64_t>(gw, ((int64_t)256 << 20) / slab));
+            gscratch.alloc((size_t)gw * 3 * (size_t)smax * smax, s);
+            r.gscratch = gscratch.get();
+        }
+        r.gw = (unsigned)gw;
+    }
     double cost[4] = {0, 0, 0, 0};
     if (prof_selected("local_small") || prof_selected("local_wave")) {
         DevArr<double> acc;
@@ -1393,69 +1612,77 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         rb.add(cost, acc.get(), sizeof(cost));
         rb.run();
     }
-    int32_t h[5] = {0, 0, 0, 0, 0};
+    Buckets bk;
+    bool tune = false;
+    const std::array<int32_t, 4> key{mixed ? 1 : 0, ilog2_floor(nc),
+                                     (int32_t)std::lround(mean_row), std::min(smax, 33)};
     {
-        ProfScope ps_small("local_small", s, cost[0], cost[1]);
-        // few systems: one lane each leaves the machine idle and waits on
-        // its loads in turn; a team per system gathers in parallel
-        const bool team_first = (smax > 4 && mean_row > LONG_ROW) || nc <= FEW_SYSTEMS;
-        int32_t bound = nc;
-        if (team_first) {
-            team_pass<8>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
-                         listB, nB, sing, nS, s);
+        std::lock_guard<std::mutex> g(g_bk_mu);
+        if (g_bk_fixed) {
+            bk = g_bk_edges;
         } else {
-            small_pass<4>(mixed, nc, nullptr, nullptr, clist, nptr, nbr, rp, cj, v, out,
-                          listA, nA, sing, nS, s);
-        }
-        if (smax > (team_first ? 8 : 4)) {
-            Readback rb(s);
-            rb.add(h, counters.get(), sizeof(h));
-            rb.run();
-            bound = team_first ? h[1] : h[0];
-            if (!team_first)
-                team_pass<8>(mixed, bound, listA, nullptr, clist, nptr, nbr, rp, cj, v, out,
-                             listB, nB, sing, nS, s);
-            if (smax > 8)
-                team_pass<16>(mixed, bound, listB, team_first ? nullptr : nB, clist, nptr,
-                              nbr, rp, cj, v, out, listC, nC, sing, nS, s);
-            if (smax > 16)
-                team_pass<32>(mixed, bound, listC, nC, clist, nptr, nbr, rp, cj, v, out,
-                              listD, nD, sing, nS, s);
+            auto it = g_bk_cache.find(key);
+            if (it != g_bk_cache.end()) bk = it->second;
+            else tune = true;
         }
     }
+    if (tune) {
+        // every candidate runs TUNE_REPS times in turn (the first pass also
+        // loads the kernels' code) and keeps its fastest time; each run
+        // overwrites the same outputs with the same values
+        constexpr int TUNE_REPS = 3;
+        const int nk = (int)(sizeof(BK_CANDIDATES) / sizeof(BK_CANDIDATES[0]));
+        std::vector<hipEvent_t> ev(2 * nk * TUNE_REPS, nullptr);
+        for (auto &e : ev) LAIR_HIP(hipEventCreate(&e));
+        for (int rep = 0; rep < TUNE_REPS; ++rep)
+            for (int k = 0; k < nk; ++k) {
+                LAIR_HIP(hipEventRecord(ev[2 * (rep * nk + k)], s));
+                run_buckets(r, BK_CANDIDATES[k], s);
+                LAIR_HIP(hipEventRecord(ev[2 * (rep * nk + k) + 1], s));
+            }
+        LAIR_HIP(hipStreamSynchronize(s));
+        float best = 0.0f;
+        int arg = 0;
+        for (int k = 0; k < nk; ++k) {
+            float mk = 0.0f;
+            for (int rep = 1; rep < TUNE_REPS; ++rep) {
+                float ms = 0.0f;
+                LAIR_HIP(hipEventElapsedTime(&ms, ev[2 * (rep * nk + k)],
+                                             ev[2 * (rep * nk + k) + 1]));
+                mk = (rep == 1) ? ms : std::min(mk, ms);
+            }
+            if (k == 0 || mk < best) { best = mk; arg = k; }
+            if (tune_log())
+                fprintf(stderr, "lair tune: nc %d mean_row %.1f smax %d %s edges %d %d %d %d "
+                        "fused %d: %.1f us\n", nc, mean_row, smax, mixed ? "mixed" : "fp64",
+                        BK_CANDIDATES[k].e[0], BK_CANDIDATES[k].e[1], BK_CANDIDATES[k].e[2],
+                        BK_CANDIDATES[k].e[3], BK_CANDIDATES[k].fused, 1e3 * mk);
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        bk = BK_CANDIDATES[arg];
+        std::lock_guard<std::mutex> g(g_bk_mu);
+        g_bk_cache[key] = bk;
+    } else {
+        ProfScope ps_small("local_small", s, cost[0] + cost[2], cost[1] + cost[3]);
+        run_buckets(r, bk, s);
+    }
+    if (edges_used) {
+        for (int k = 0; k < 4; ++k) edges_used[k] = bk.e[k];
+        edges_used[4] = bk.fused;
+    }
+    int32_t h[7] = {0, 0, 0, 0, 0, 0, 0};
     {
         Readback rb(s);
-        rb.add(h, counters.get(), sizeof(h));
+        rb.add(h, r.cnt, sizeof(h));
         rb.run();
     }
-    const int32_t *wave_list = listD;
-    int32_t nbig = h[3];
-    if (nbig > 0) {
-        int32_t cap = smax < WSMAX ? smax : WSMAX;
-        DevArr<double> scratch;
-        if (smax > cap) scratch.alloc((size_t)nbig * (size_t)smax * smax * 3 + 16, s);
-        ProfScope ps_wave("local_wave", s, cost[2], cost[3]);
-        size_t lds = mixed ? wave_lds_bytes<float>(cap) : wave_lds_bytes<double>(cap);
-        if (mixed)
-            LAIR_LAUNCH((k_local_wave<true>), dim3((unsigned)nbig), dim3(64), lds, s,
-                               wave_list, nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
-                               out.flags, sing, nS, scratch.get(), smax, cap);
-        else
-            LAIR_LAUNCH((k_local_wave<false>), dim3((unsigned)nbig), dim3(64), lds, s,
-                               wave_list, nbig, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
-                               out.flags, sing, nS, scratch.get(), smax, cap);
-        LAIR_LAUNCH_CHECK();
-        Readback rb(s);
-        rb.add(h, counters.get(), sizeof(h));
-        rb.run();
-    }
-    int32_t nsing = h[4];
+    const int32_t nsing = h[6];
     if (nsing > 0) {
         DevArr<double> scratch;
         scratch.alloc((size_t)nsing * (2 * (size_t)smax * smax + 2 * (size_t)smax), s);
         ProfScope ps_ls("local_lstsq", s, 0.0);
         LAIR_LAUNCH(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
-                           sing, nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
+                           r.sing, nsing, clist, nptr, nbr, rp, cj, v, out.r_cj,
                            out.r_v, scratch.get(), smax);
         LAIR_LAUNCH_CHECK();
         LAIR_HIP(hipStreamSynchronize(s));

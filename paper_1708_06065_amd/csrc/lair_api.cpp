@@ -79,6 +79,8 @@ struct Level {
     DevArr<int8_t> cf_split;
     DevCSR As, Rs, Ps;
     bool split = false;
+    // size-bucket edges (and the fused flag) the local solves used here
+    int32_t buckets[5] = {0, 0, 0, 0, 0};
 };
 
 }  // namespace lair
@@ -456,7 +458,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
                                  A.rp.get(), A.cj.get(), A.v.get(),
                                  h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED,
-                                 Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s);
+                                 Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s,
+                                 Lv.buckets);
     Lv.st.n_singular = nsing;
     h->n_singular += nsing;
 
@@ -1694,7 +1697,7 @@ static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_d
         LocalSolveOut out{Lv.R.rp.get(), Lv.R.cj.get(), Lv.R.v.get(), Lv.flags.get()};
         int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
                                      A.rp.get(), A.cj.get(), A.v.get(), prec, Lv.st.s_max,
-                                     Lv.n ? (double)A.nnz / Lv.n : 0.0, out, s);
+                                     Lv.n ? (double)A.nnz / Lv.n : 0.0, out, s, Lv.buckets);
         Lv.st.n_singular = nsing;
         h->n_singular += nsing;
         if (h->opt.interp == LAIR_P_DIRECT) {
@@ -1905,6 +1908,23 @@ lair_status lair_system_levels(const lair_hierarchy *h, int32_t *levels) {
         if (!h->batch) fail(LAIR_EINVAL, "the hierarchy was not built by lair_setup_batch");
         for (int32_t q = 0; q < h->nsys; ++q)
             levels[q] = h->nsys > 1 ? h->sys_levels[q] : (int32_t)h->L.size();
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_set_local_buckets(const int32_t *edges) {
+    return guarded([&]() -> lair_status {
+        set_local_buckets(edges);
+        return LAIR_OK;
+    });
+}
+
+lair_status lair_local_buckets(const lair_hierarchy *h, int32_t level, int32_t *edges) {
+    return guarded([&]() -> lair_status {
+        if (!h || !edges) fail(LAIR_EINVAL, "hierarchy and edges must not be NULL");
+        if (level < 0 || level + 1 >= (int32_t)h->L.size())
+            fail(LAIR_EINVAL, "level %d has no local solves", level);
+        for (int k = 0; k < 5; ++k) edges[k] = h->L[level]->buckets[k];
         return LAIR_OK;
     });
 }

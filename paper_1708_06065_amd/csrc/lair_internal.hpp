@@ -225,7 +225,10 @@ struct LocalSolveOut {
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
-                     LocalSolveOut out, hipStream_t s);
+                     LocalSolveOut out, hipStream_t s, int32_t *edges_used = nullptr);
+// process-wide bucket edges of the local solves and the fused flag (5
+// values; nullptr: tune per shape); edges_used receives 5 values
+void set_local_buckets(const int32_t *edges);
 void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
                              const double *v, const uint8_t *smask,
                              const int8_t *cf, const int32_t *cidx,

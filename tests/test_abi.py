@@ -110,3 +110,19 @@ def test_batch_host_validation_without_gpu():
     assert lib.lair_solve_batch(None, None, None, 1e-10, 10, None, None, None,
                                 None) == L.LAIR_EINVAL
     assert lib.lair_num_systems(None) == 0
+
+
+def test_local_bucket_edges_validation_without_gpu():
+    import numpy as np
+    """Bucket edges are checked on the host; NULL returns to tuning."""
+    lib = L.load()
+    for e in ([5, 8, 16, 32, 0], [4, 9, 16, 32, 0], [4, 8, 17, 32, 0], [4, 8, 16, 33, 0],
+              [4, 2, 16, 32, 0], [-1, 8, 16, 32, 0], [4, 8, 16, 32, 2]):
+        a = np.array(e, np.int32)
+        assert lib.lair_set_local_buckets(a.ctypes.data_as(ctypes.c_void_p)) == L.LAIR_EINVAL
+        assert b"bucket edges" in lib.lair_last_error()
+    ok = np.array([0, 8, 16, 32, 1], np.int32)
+    assert lib.lair_set_local_buckets(ok.ctypes.data_as(ctypes.c_void_p)) == L.LAIR_OK
+    assert lib.lair_set_local_buckets(None) == L.LAIR_OK
+    edges = np.zeros(5, np.int32)
+    assert lib.lair_local_buckets(None, 0, edges.ctypes.data_as(ctypes.c_void_p)) == L.LAIR_EINVAL
