@@ -44,6 +44,14 @@ def _problem(case):
     if case == "all_f":
         w = W.random_ff_digraph(120, 4, 17)
         return w, dict(distance="all_f", max_coarse=8, max_levels=2)
+    if case == "singular":
+        # C-point 0 with N = {1, 2} has a singular local matrix: the
+        # least-squares path
+        w = dict(rowptr=np.array([0, 3, 5, 8, 9], dtype=np.int32),
+                 col=np.array([0, 1, 2, 1, 3, 1, 2, 3, 3], dtype=np.int32),
+                 val=np.array([4.0, -1.0, -1.0, 1.0, -1.0, 1.0, 1e-300, -1.0, 2.0]))
+        return w, dict(cf_levels=[np.array([1, 0, 0, 1], dtype=np.int8)], max_coarse=1,
+                       max_levels=2, theta=0.0)
     w = W.workload_c1(40)
     return w, dict()
 
@@ -58,12 +66,16 @@ def _r_values(lair, w, kw):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("case", ["euler3d", "dg_d2", "all_f", "c1"])
+@pytest.mark.parametrize("case", ["euler3d", "dg_d2", "all_f", "c1", "singular"])
 def test_bucket_edges_do_not_change_r(lair, case, precision):
     _say("case: bucket edges,", case, precision)
     w, kw = _problem(case)
     kw = dict(kw, precision=precision)
     ref = None
+    if case == "singular":
+        lair.set_local_buckets(None)
+        got, _ = _r_values(lair, w, kw)
+        assert got[0][2].tolist() == [1, 0]
     try:
         for e in EDGES:
             lair.set_local_buckets(e)
