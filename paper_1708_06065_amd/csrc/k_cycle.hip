@@ -714,26 +714,35 @@ void op_dense_solve(int32_t n, const double *lu, const int32_t *piv,
 
 // Coarsest grid through its explicit inverse (small grids): x = Kinv b or
 // Kinv^T b, accumulated in double whatever the vector type.
+// x = K^{-1} b (or K^{-T} b) with the explicit inverse: a team of
+// COARSE_T lanes per output entry, each lane summing every COARSE_T-th
+// term, then a fixed shuffle tree.
+constexpr int COARSE_T = 16;
+
 template <class VT>
 __global__ void __launch_bounds__(256)
 k_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x, int32_t nrhs,
                int transpose) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / COARSE_T;
+    const int lane = threadIdx.x % COARSE_T;
     if (g >= (int64_t)n * nrhs) return;
-    int32_t i = (int32_t)(g / nrhs);
-    int q = (int)(g % nrhs);
+    const int32_t i = (int32_t)(g / nrhs);
+    const int q = (int)(g % nrhs);
     double acc = 0.0;
     if (!transpose)
-        for (int j = 0; j < n; ++j) acc += kinv[(size_t)i * n + j] * (double)b[(int64_t)j * nrhs + q];
+        for (int j = lane; j < n; j += COARSE_T)
+            acc += kinv[(size_t)i * n + j] * (double)b[(int64_t)j * nrhs + q];
     else
-        for (int j = 0; j < n; ++j) acc += kinv[(size_t)j * n + i] * (double)b[(int64_t)j * nrhs + q];
-    x[g] = (VT)acc;
+        for (int j = lane; j < n; j += COARSE_T)
+            acc += kinv[(size_t)j * n + i] * (double)b[(int64_t)j * nrhs + q];
+    acc = team_sum<COARSE_T>(acc);
+    if (lane == 0) x[g] = (VT)acc;
 }
 
 template <class VT>
 void op_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x,
                      int32_t nrhs, bool transpose, hipStream_t s) {
-    LAIR_LAUNCH((k_coarse_apply<VT>), dim3(blocks_for((int64_t)n * nrhs, 256)),
+    LAIR_LAUNCH((k_coarse_apply<VT>), dim3(blocks_for((int64_t)n * nrhs * COARSE_T, 256)),
                        dim3(256), 0, s, n, kinv, b, x, nrhs, transpose ? 1 : 0);
     LAIR_LAUNCH_CHECK();
 }

@@ -2449,6 +2449,93 @@ k_dense_lu_lds(int32_t n, double *lu, int32_t *piv, int32_t *info) {
     if (t == 0) *info = 0;
 }
 
+// Small coarsest grids (n <= 128): the explicit inverse in one workgroup by
+// Gauss-Jordan elimination in place with partial pivoting (largest |a_rk|
+// among the rows not yet used, smallest row on ties, rows exchanged), n
+// steps of one rank-1 update each; the row exchanges are undone at the end
+// as column exchanges (inv(A) = inv(PA) P).  info = k + 1 for a zero pivot
+// at step k.
+constexpr int LUI_ROWS = 128;
+constexpr int LUI_BS = 1024;
+constexpr int LUI_TPR = LUI_BS / LUI_ROWS;     // lanes per row
+
+__global__ void __launch_bounds__(LUI_BS)
+k_dense_gj_inv(int32_t n, const double *dense, double *inv, int32_t *info) {
+    extern __shared__ double a[];
+    __shared__ double s_bv[LUI_BS / 64];
+    __shared__ int s_bi[LUI_BS / 64];
+    __shared__ int s_piv[LUI_ROWS];
+    __shared__ double s_col[LUI_ROWS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int idx = tid; idx < n * n; idx += LUI_BS) a[idx] = dense[idx];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        // pivot: every wave reduces the candidates, then the per-wave
+        // results by shuffles (no serial pass over them)
+        double bv = (tid < n && tid >= k) ? fabs(a[tid * n + k]) : -1.0;
+        int bi = tid;
+        team_argmax<64>(bv, bi);
+        if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
+        __syncthreads();
+        double pv = lane < LUI_BS / 64 ? s_bv[lane] : -1.0;
+        int pr = lane < LUI_BS / 64 ? s_bi[lane] : INT_MAX;
+        team_argmax<64>(pv, pr);
+        if (pv == 0.0) {
+            if (tid == 0) *info = k + 1;
+            return;
+        }
+        if (tid == 0) s_piv[k] = pr;
+        // exchange rows k and pr; scale the pivot row (its pivot entry
+        // becomes the inverse's); keep column k of the other rows
+        // (all reads before any write of this step)
+        const double d = 1.0 / a[pr * n + k];
+        const double akk = a[k * n + k];
+        double xk = 0.0, xp = 0.0, colv = 0.0;
+        if (tid < n) {
+            xk = a[k * n + tid];
+            xp = a[pr * n + tid];
+            colv = a[tid * n + k];
+        }
+        __syncthreads();
+        if (tid < n) {
+            if (pr != k) a[pr * n + tid] = xk;
+            a[k * n + tid] = (tid == k ? 1.0 : xp) * d;
+            s_col[tid] = (tid == k) ? 0.0 : (tid == pr ? akk : colv);
+        }
+        __syncthreads();
+        // every other row: a_r -= a_rk * (pivot row), column k taking the
+        // inverse's entry -a_rk * d (lanes LUI_TPR r .. of row r take every
+        // LUI_TPR-th column)
+        {
+            const int r = tid / LUI_TPR, c = tid % LUI_TPR;
+            if (r < n && r != k) {
+                const double f = s_col[r];
+                for (int q = c; q < n; q += LUI_TPR)
+                    a[r * n + q] = (q == k) ? -f * d : a[r * n + q] - f * a[k * n + q];
+            }
+        }
+        __syncthreads();
+    }
+    // undo the row exchanges as column exchanges, last first
+    for (int r = tid; r < n; r += LUI_BS)
+        for (int j = n - 1; j >= 0; --j) {
+            const int jp = s_piv[j];
+            if (jp != j) {
+                const double x = a[r * n + j];
+                a[r * n + j] = a[r * n + jp];
+                a[r * n + jp] = x;
+            }
+        }
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += LUI_BS) inv[idx] = a[idx];
+    if (tid == 0) *info = 0;
+}
+
+// n <= 128 and the matrix fits LDS: the inverse in one kernel
+bool launch_dense_gj_inv(int32_t n, const double *dense, double *inv, int32_t *info,
+                         hipStream_t s);
+
 static size_t max_lds_per_block() {
     static size_t cached = 0;
     if (!cached) {
@@ -2461,6 +2548,16 @@ static size_t max_lds_per_block() {
             cached = 65536;
     }
     return cached;
+}
+
+bool launch_dense_gj_inv(int32_t n, const double *dense, double *inv, int32_t *info,
+                         hipStream_t s) {
+    if (n < 1 || n > LUI_ROWS || (size_t)n * n * sizeof(double) + 4096 > max_lds_per_block())
+        return false;
+    LAIR_LAUNCH(k_dense_gj_inv, dim3(1), dim3(LUI_BS), (size_t)n * n * sizeof(double), s, n,
+                dense, inv, info);
+    LAIR_LAUNCH_CHECK();
+    return true;
 }
 
 void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,

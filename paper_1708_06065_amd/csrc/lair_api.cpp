@@ -592,17 +592,26 @@ static void finish_coarsest(lair_hierarchy *h) {
     DevArr<int32_t> info;
     info.alloc(1, s);
     launch_dense_from_csr(n, Lc.A.rp.get(), Lc.A.cj.get(), Lc.A.v.get(), h->lu.get(), s);
-    launch_dense_lu(n, h->lu.get(), h->piv.get(), info.get(), s);
+    bool have_inv = false;
+    if (n <= MAX_INVERSE) h->kinv.alloc((size_t)n * n, s);
+    // small grids: the inverse directly, in one workgroup (the cycle only
+    // applies the inverse; no factors are kept)
+    if (n <= MAX_INVERSE && launch_dense_gj_inv(n, h->lu.get(), h->kinv.get(), info.get(), s))
+        have_inv = true;
+    else
+        launch_dense_lu(n, h->lu.get(), h->piv.get(), info.get(), s);
     int32_t hinfo = 0;
     {
         Readback rb(s);
         rb.add(&hinfo, info.get(), sizeof(int32_t));
         rb.run();
     }
-    if (hinfo != 0) fail(LAIR_ESINGULAR, "coarsest matrix (n = %d) is singular at pivot %d", n, hinfo);
-    if (n <= MAX_INVERSE) {
+    if (hinfo != 0) {
+        h->kinv.release();
+        fail(LAIR_ESINGULAR, "coarsest matrix (n = %d) is singular at pivot %d", n, hinfo);
+    }
+    if (n <= MAX_INVERSE && !have_inv) {
         // K^{-1} from the LU factors, eight columns of the identity per block
-        h->kinv.alloc((size_t)n * n, s);
         launch_dense_inverse(n, h->lu.get(), h->piv.get(), h->kinv.get(), s);
     }
 }

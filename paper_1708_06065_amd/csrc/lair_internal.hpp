@@ -267,6 +267,10 @@ void launch_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
 // dense coarsest factorisation
 void launch_dense_from_csr(int32_t n, const int32_t *rp, const int32_t *cj,
                            const double *v, double *dense, hipStream_t s);
+// n <= 128 and n^2 doubles fit one workgroup's LDS: the explicit inverse of
+// the dense matrix by Gauss-Jordan in one kernel; false when it does not apply
+bool launch_dense_gj_inv(int32_t n, const double *dense, double *inv, int32_t *info,
+                         hipStream_t s);
 void launch_dense_lu(int32_t n, double *lu, int32_t *piv, int32_t *info,
                      hipStream_t s);
 // inv = K^{-1} from the factors of launch_dense_lu (n <= 4096)
