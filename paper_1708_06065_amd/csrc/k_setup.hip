@@ -142,13 +142,16 @@ __global__ void k_scan_add(OUT *out, int64_t n, const int64_t *bs, const int64_t
 // Launches only: out[0..n] and tot[0] = total, tot[1] = largest value on
 // the device.
 template <class F, class OUT>
-static int64_t *scan_launch(F f, OUT *out, int64_t n, hipStream_t s, DevArr<int64_t> &tmp) {
+static int64_t *scan_launch(F f, OUT *out, int64_t n, hipStream_t s, DevArr<int64_t> &tmp,
+                            int64_t *tot_out = nullptr) {
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
     tmp.ensure((size_t)2 * nb + 2, s);
     int64_t *bs = tmp.get();
     int64_t *bmax = bs + nb;
-    int64_t *tot = bmax + nb;      // tot[0] = total, tot[1] = largest value
+    // tot[0] = total, tot[1] = largest value (in tmp, or where the caller
+    // keeps them for a later readback)
+    int64_t *tot = tot_out ? tot_out : bmax + nb;
     LAIR_LAUNCH((k_scan_tile<F, OUT>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
                        f, n, out, bs, bmax);
     LAIR_LAUNCH_CHECK();
@@ -175,6 +178,21 @@ static int64_t scan_impl(F f, OUT *out, int64_t n, hipStream_t s,
              (long long)h[0]);
     if (max_out) *max_out = h[1];
     return h[0];
+}
+
+void scan_counts_i32_to(const int32_t *cnt, int32_t *out, int64_t n, hipStream_t s,
+                        DevArr<int64_t> &tmp, int64_t *tot) {
+    scan_launch(CountsF{cnt}, out, n, s, tmp, tot);
+}
+
+void scan_counts_i64_to(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t s,
+                        DevArr<int64_t> &tmp, int64_t *tot) {
+    scan_launch(CountsF{cnt}, out, n, s, tmp, tot);
+}
+
+void scan_flags_i8_to(const int8_t *flags, int8_t want, int32_t *out, int64_t n, hipStream_t s,
+                      DevArr<int64_t> &tmp, int64_t *tot) {
+    scan_launch(FlagsF{flags, want}, out, n, s, tmp, tot);
 }
 
 int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
@@ -1579,8 +1597,12 @@ void run_buckets(const LocalRun &r, const Buckets &bk, hipStream_t s) {
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
-                     LocalSolveOut out, hipStream_t s, int32_t *edges_used) {
-    if (nc == 0) return 0;
+                     LocalSolveOut out, hipStream_t s, int32_t *edges_used,
+                     Readback *rb_extra) {
+    if (nc == 0) {
+        if (rb_extra) rb_extra->run();
+        return 0;
+    }
     const bool mixed = (precision == LAIR_MIXED);
     DevArr<int32_t> work;
     work.alloc((size_t)nc * (NBUCKET + 1) + 8, s);
@@ -1672,7 +1694,9 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     }
     int32_t h[7] = {0, 0, 0, 0, 0, 0, 0};
     {
-        Readback rb(s);
+        // the caller's pending items travel with this readback
+        Readback own(s);
+        Readback &rb = rb_extra ? *rb_extra : own;
         rb.add(h, r.cnt, sizeof(h));
         rb.run();
     }

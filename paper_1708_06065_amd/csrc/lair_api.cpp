@@ -199,27 +199,96 @@ __global__ void k_block_diag_csr(int32_t nblk, int32_t k, const double *dinv,
     v[g] = dinv[(row / k) * k * k + (row % k) * k + c];
 }
 
-// C = A B with the symbolic pattern.  Returns the longest row of C.
-static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
-                      DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
-    (void)max_row_a;
+// Sizes of a CSR matrix produced on the device (nnz, longest row, an
+// overflow flag) whose host copies wait for a later readback, so that the
+// setup does not stop for each of them.
+struct PendingSizes {
+    DevArr<int64_t> d;               // [0] nnz, [1] longest row, [2] flag (low word)
+    int64_t h[3] = {0, 0, 0};
+    DevCSR *m = nullptr;
+    const char *what = "";
+    void arm(DevCSR *mat, const char *w, hipStream_t s) {
+        d.alloc(3, s);
+        LAIR_HIP(hipMemsetAsync(d.get(), 0, 3 * sizeof(int64_t), s));
+        m = mat;
+        what = w;
+    }
+    int64_t *tot() { return d.get(); }
+    int32_t *flag() { return reinterpret_cast<int32_t *>(d.get() + 2); }
+    void add(Readback &rb) {
+        if (m) rb.add(h, d.get(), sizeof(h));
+    }
+    // after the readback that carried them
+    void apply() {
+        if (!m) return;
+        DevCSR *mat = m;
+        m = nullptr;
+        if ((int32_t)h[2]) fail(LAIR_EUNSUPPORTED, "%s", what);
+        mat->nnz = h[0];
+        mat->max_row = (int32_t)h[1];
+    }
+    void settle(hipStream_t s) {
+        if (!m) return;
+        Readback rb(s);
+        add(rb);
+        rb.run();
+        apply();
+    }
+};
+
+// The profiler attributes algorithmic bytes from host-side sizes as it
+// launches; while it times the setup categories every size is read at once.
+static bool setup_sizes_eager() {
+    return prof_selected("spgemm_fill") || prof_selected("spgemm_compact") ||
+           prof_selected("spgemm_count") || prof_selected("interp");
+}
+
+// C = A B with the symbolic pattern, in two parts: spgemm_count launches
+// the products-per-row count and its scan, leaving the total and the
+// longest count on the device (st.tot) for the caller's next readback;
+// spgemm_finish then stages, accumulates and compacts the rows.  With
+// `defer` the sizes of C stay on the device too (C's arrays are sized by
+// the number of products, an upper bound) and reach the host with a later
+// readback; otherwise they are read at once.
+struct SpgemmState {
+    int32_t m = 0;
+    DevArr<int32_t> cnt, work;
+    DevArr<int64_t> eoff, tot;       // tot: [0] products, [1] most in a row
+    int64_t h[2] = {0, 0};
+};
+
+static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipStream_t s,
+                         DevArr<int64_t> &tmp) {
     const int32_t m = A.nrows;
+    st.m = m;
+    st.cnt.alloc((size_t)m + 1, s);
+    st.eoff.alloc((size_t)m + 1, s);
+    st.work.alloc(2 + 2 * (size_t)m, s);
+    st.tot.alloc(2, s);
+    // products per row: A's indices and B's row pointers
+    ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
+                                        8.0 * (B.nrows + 1) + 12.0 * m);
+    launch_prod_count(m, A.rp.get(), A.cj.get(), B.rp.get(), st.cnt.get(), s);
+    scan_counts_i64_to(st.cnt.get(), st.eoff.get(), m, s, tmp, st.tot.get());
+}
+
+// st.h must hold the readback of st.tot.  Returns C's longest row (0 when
+// deferred).
+static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, SpgemmState &st,
+                             hipStream_t s, DevArr<int64_t> &tmp, PendingSizes *defer) {
+    const int32_t m = st.m;
+    const int64_t etot = st.h[0], emax = st.h[1];
     C.nrows = m;
     C.ncols = B.ncols;
-    DevArr<int32_t> cnt, over, work;
-    DevArr<int64_t> eoff;
-    cnt.alloc((size_t)m + 1, s);
-    eoff.alloc((size_t)m + 1, s);
-    over.alloc(1, s);
-    work.alloc(2 + 2 * (size_t)m, s);
-    LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
-    int64_t etot = 0, emax = 0;
-    {
-        // products per row: A's indices and B's row pointers
-        ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
-                                            8.0 * (B.nrows + 1) + 12.0 * m);
-        launch_prod_count(m, A.rp.get(), A.cj.get(), B.rp.get(), cnt.get(), s);
-        etot = scan_counts_i64(cnt.get(), eoff.get(), m, s, tmp, &emax);
+    DevArr<int32_t> over;
+    int32_t *ovp;
+    if (defer) {
+        defer->arm(&C, "sparse product row with more than 1024 terms", s);
+        ovp = defer->flag();
+    } else {
+        over.alloc(1, s);
+        LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
+        ovp = over.get();
     }
     DevArr<int32_t> tcj;
     DevArr<double> tcx;
@@ -230,23 +299,44 @@ static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
         ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) +
                                            4.0 * (B.nrows + 1));
         launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                      B.v.get(), eoff.get(), emax, m ? (double)etot / m : 0.0, cnt.get(),
-                      tcj.get(), tcx.get(), work.get(), over.get(), s);
+                      B.v.get(), st.eoff.get(), emax, m ? (double)etot / m : 0.0,
+                      st.cnt.get(), tcj.get(), tcx.get(), st.work.get(), ovp, s);
     }
     C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
-    int32_t ov = 0;
-    C.nnz = scan_counts_i32(cnt.get(), C.rp.get(), m, s, tmp, &mx, over.get(), &ov);
-    if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
-    C.max_row = (int32_t)mx;
+    if (defer) {
+        scan_counts_i32_to(st.cnt.get(), C.rp.get(), m, s, tmp, defer->tot());
+        C.nnz = etot;                // an upper bound until the sizes arrive
+        C.max_row = -1;
+    } else {
+        int32_t ov = 0;
+        C.nnz = scan_counts_i32(st.cnt.get(), C.rp.get(), m, s, tmp, &mx, ovp, &ov);
+        if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
+        C.max_row = (int32_t)mx;
+    }
     C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     {
         ProfScope ps("spgemm_compact", s, 24.0 * C.nnz + 8.0 * (m + 1) + 4.0 * (m + 1));
-        launch_spgemm_compact(m, eoff.get(), C.rp.get(), tcj.get(), tcx.get(), C.cj.get(),
+        launch_spgemm_compact(m, st.eoff.get(), C.rp.get(), tcj.get(), tcx.get(), C.cj.get(),
                               C.v.get(), m ? (double)C.nnz / m : 1.0, s);
     }
     return (int32_t)mx;
+}
+
+// C = A B at once (count, readback, product, sizes).  Returns the longest
+// row of C.
+static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
+                      DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
+    (void)max_row_a;
+    SpgemmState st;
+    spgemm_count(A, B, st, s, tmp);
+    {
+        Readback rb(s);
+        rb.add(st.h, st.tot.get(), sizeof(st.h));
+        rb.run();
+    }
+    return spgemm_finish(A, B, C, st, s, tmp, nullptr);
 }
 
 static void transpose(const DevCSR &M, DevCSR &T, hipStream_t s,
@@ -297,9 +387,14 @@ static const int32_t MAX_DENSE = 4096;
 // ---------------------------------------------------------------------------
 // Setup
 // ---------------------------------------------------------------------------
+// Strength, splitting, neighbourhoods, local solves, R and P of one level,
+// and the product counts of A P (left in ap for the caller's product).
+// Host synchronisations: the number of C-points with the F/C row lists,
+// the neighbourhood sizes, and one readback after the local solves that
+// also carries P's sizes and the count of products of A P.
 static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                                  const lair_cf_levels *cfl, bool &coarsest,
-                                 DevArr<int64_t> &tmp) {
+                                 DevArr<int64_t> &tmp, SpgemmState &ap) {
     hipStream_t s = h->stream;
     const int32_t n = Lv.n;
     const DevCSR &A = Lv.A;
@@ -384,21 +479,17 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
             seg_next[q + 1] = seg_next[q] + (Lv.stopped[q] ? nq : (int64_t)ncs[q]);
         }
     }
+    // coarse numbering and the F/C row lists in one pass with the count of
+    // C-points (the lists are sized for every point until it is known)
     DevArr<int32_t> scan;
     scan.alloc((size_t)n + 1, s);
-    int64_t nc = scan_flags_i8(Lv.cf.get(), 1, scan.get(), n, s, tmp);
-    if (h->nsys == 1 && (nc == 0 || (double)nc > h->opt.stall * (double)n)) {
-        coarsest = true;
-        Lv.smask.release();
-        Lv.cf.release();
-        return;
-    }
-    Lv.nc = (int32_t)nc;
-    Lv.nf = n - Lv.nc;
-    Lv.next_seg = std::move(seg_next);
+    DevArr<int64_t> nct;
+    nct.alloc(2, s);
+    scan_flags_i8_to(Lv.cf.get(), 1, scan.get(), n, s, tmp, nct.get());
     Lv.cidx.alloc((size_t)n, s);
-    Lv.clist.alloc((size_t)Lv.nc, s);
-    Lv.flist.alloc((size_t)std::max(Lv.nf, 1), s);
+    Lv.clist.alloc((size_t)std::max(n, 1), s);
+    Lv.flist.alloc((size_t)std::max(n, 1), s);
+    int64_t nc = 0;
     {
         DevArr<unsigned long long> acc;
         acc.alloc(2 + 2 * (size_t)blocks_for(n, 256), s);
@@ -406,12 +497,27 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         launch_cf_lists(n, Lv.cf.get(), scan.get(), A.rp.get(), Lv.cidx.get(), Lv.clist.get(),
                         Lv.flist.get(), acc.get(), s);
         unsigned long long hacc[2];
+        int64_t hn[2];
         Readback rb(s);
         rb.add(hacc, acc.get(), sizeof(hacc));
+        rb.add(hn, nct.get(), sizeof(hn));
         rb.run();
+        nc = hn[0];
         Lv.nnzF = (int64_t)hacc[0];
         Lv.nnzC = (int64_t)hacc[1];
     }
+    if (h->nsys == 1 && (nc == 0 || (double)nc > h->opt.stall * (double)n)) {
+        coarsest = true;
+        Lv.smask.release();
+        Lv.cf.release();
+        Lv.cidx.release();
+        Lv.clist.release();
+        Lv.flist.release();
+        return;
+    }
+    Lv.nc = (int32_t)nc;
+    Lv.nf = n - Lv.nc;
+    Lv.next_seg = std::move(seg_next);
     if (h->nsys > 1) {
         bool any = false;
         for (auto q : Lv.stopped) any = any || q;
@@ -453,21 +559,16 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     LAIR_LAUNCH(k_r_rowptr, dim3(blocks_for(Lv.nc + 1, 256)), dim3(256), 0, s,
                        Lv.nc, Lv.nptr.get(), R.rp.get());
     LAIR_LAUNCH_CHECK();
-    Lv.flags.alloc((size_t)Lv.nc, s);
-    LocalSolveOut out{R.rp.get(), R.cj.get(), R.v.get(), Lv.flags.get()};
-    int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
-                                 A.rp.get(), A.cj.get(), A.v.get(),
-                                 h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED,
-                                 Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s,
-                                 Lv.buckets);
-    Lv.st.n_singular = nsing;
-    h->n_singular += nsing;
-
-    // P
+    // P; its sizes stay on the device until the local solves' readback
+    // (arrays sized by an upper bound: a row of P has at most as many
+    // entries as the row of A)
+    const bool eager = setup_sizes_eager();
+    PendingSizes p_pend;
     DevCSR &P = Lv.P;
     P.nrows = n;
     P.ncols = Lv.nc;
     P.rp.alloc((size_t)n + 1, s);
+    p_pend.arm(&P, "", s);
     if (h->opt.interp == LAIR_P_ONE_POINT) {
         DevArr<int32_t> pcol;
         pcol.alloc((size_t)n, s);
@@ -481,8 +582,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         LAIR_LAUNCH(k_nonneg_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            n, pcol.get(), has.get());
         LAIR_LAUNCH_CHECK();
-        P.nnz = scan_counts_i32(has.get(), P.rp.get(), n, s, tmp);
-        P.max_row = 1;
+        scan_counts_i32_to(has.get(), P.rp.get(), n, s, tmp, p_pend.tot());
+        if (eager) p_pend.settle(s);
+        else P.nnz = n;
         P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         launch_compact_one_point(n, pcol.get(), P.rp.get(), P.cj.get(), P.v.get(), s);
@@ -495,9 +597,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                                  Lv.cf.get(), Lv.cidx.get(), false, pc.get(), nullptr, nullptr,
                                  nullptr, mean, s);
         }
-        int64_t pmax = 0;
-        P.nnz = scan_counts_i32(pc.get(), P.rp.get(), n, s, tmp, &pmax);
-        P.max_row = (int32_t)pmax;
+        scan_counts_i32_to(pc.get(), P.rp.get(), n, s, tmp, p_pend.tot());
+        if (eager) p_pend.settle(s);
+        else P.nnz = A.nnz;
         P.cj.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         P.v.alloc((size_t)std::max<int64_t>(P.nnz, 1), s);
         {
@@ -507,6 +609,22 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                                  P.cj.get(), P.v.get(), mean, s);
         }
     }
+    // products of A P counted now, read with the local solves
+    spgemm_count(A, P, ap, s, tmp);
+    Readback rb(s);
+    p_pend.add(rb);
+    rb.add(ap.h, ap.tot.get(), sizeof(ap.h));
+
+    Lv.flags.alloc((size_t)Lv.nc, s);
+    LocalSolveOut out{R.rp.get(), R.cj.get(), R.v.get(), Lv.flags.get()};
+    int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
+                                 A.rp.get(), A.cj.get(), A.v.get(),
+                                 h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED,
+                                 Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s,
+                                 Lv.buckets, &rb);
+    p_pend.apply();
+    Lv.st.n_singular = nsing;
+    h->n_singular += nsing;
 }
 
 static const int32_t MAX_INVERSE = 512;
@@ -869,16 +987,28 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
             if (all) break;
         }
         bool coarsest = false;
-        build_level_transfer(h.get(), Lv, lvl, cfl, coarsest, tmp);
+        SpgemmState ap_st;
+        build_level_transfer(h.get(), Lv, lvl, cfl, coarsest, tmp, ap_st);
         if (coarsest) break;
-        // Galerkin product K = R (A P)
+        // Galerkin product K = R (A P): the sizes of A P reach the host with
+        // the count of products of R (A P)
         DevCSR AP;
-        spgemm(Lv.A, Lv.max_row, Lv.P, AP, s, tmp);
+        PendingSizes ap_pend;
+        const bool eager = setup_sizes_eager();
+        spgemm_finish(Lv.A, Lv.P, AP, ap_st, s, tmp, eager ? nullptr : &ap_pend);
         std::unique_ptr<Level> nx(new Level());
         nx->n = Lv.nc;
-        int32_t rmax = Lv.st.s_max + 1;
+        SpgemmState k_st;
+        spgemm_count(Lv.R, AP, k_st, s, tmp);
+        {
+            Readback rb(s);
+            rb.add(k_st.h, k_st.tot.get(), sizeof(k_st.h));
+            ap_pend.add(rb);
+            rb.run();
+            ap_pend.apply();
+        }
         // rows of K are sorted and unique by construction of the product
-        nx->max_row = spgemm(Lv.R, rmax, AP, nx->A, s, tmp);
+        nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr);
         if (h->nsys > 1) {
             nx->seg = Lv.next_seg;
             nx->stopped = Lv.stopped;

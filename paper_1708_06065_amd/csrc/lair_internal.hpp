@@ -185,6 +185,14 @@ int64_t scan_counts_i32(const int32_t *cnt, int32_t *out, int64_t n,
                         int32_t *flag_out = nullptr);
 int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
                       hipStream_t s, DevArr<int64_t> &tmp);
+// the same scans without a readback: tot[0] = total, tot[1] = largest value
+// are written to device memory the caller reads later
+void scan_counts_i32_to(const int32_t *cnt, int32_t *out, int64_t n, hipStream_t s,
+                        DevArr<int64_t> &tmp, int64_t *tot);
+void scan_counts_i64_to(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t s,
+                        DevArr<int64_t> &tmp, int64_t *tot);
+void scan_flags_i8_to(const int8_t *flags, int8_t want, int32_t *out, int64_t n, hipStream_t s,
+                      DevArr<int64_t> &tmp, int64_t *tot);
 // split ordering (F-points, then C-points): perm[new] = old, iperm[old] =
 // new, ids[k] = k, cf_split[k] = (k >= nf)
 void launch_split_perm(int32_t nf, int32_t nc, const int32_t *flist, const int32_t *clist,
@@ -225,7 +233,8 @@ struct LocalSolveOut {
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
-                     LocalSolveOut out, hipStream_t s, int32_t *edges_used = nullptr);
+                     LocalSolveOut out, hipStream_t s, int32_t *edges_used = nullptr,
+                     Readback *rb_extra = nullptr);
 // process-wide bucket edges of the local solves and the fused flag (5
 // values; nullptr: tune per shape); edges_used receives 5 values
 void set_local_buckets(const int32_t *edges);
