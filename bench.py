@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch the solve's kernels eagerly instead of replaying captured iterations")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (for HBM counters)")
     args = ap.parse_args()
@@ -214,6 +216,9 @@ def main():
                     torch.as_tensor(q["col"], device=dev),
                     torch.as_tensor(q["val"], device=dev)) for q in w["systems"]]
     torch.cuda.synchronize()
+
+    if args.no_graphs:
+        kw = dict(kw, graphs=False)
 
     def build(cf_levels=None, precision="fp64"):
         if batch:
