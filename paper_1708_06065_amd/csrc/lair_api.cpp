@@ -65,8 +65,10 @@ struct Level {
     DevArr<int32_t> rclist;
     int32_t nrc = -1;                 // -1: relax every C row (clist)
     // rows of the systems still iterated (batch solve): all rows, F rows,
-    // relaxed C rows; their lengths in act_cnt[0..2] on the device
-    DevArr<int32_t> act_rows, act_f, act_c, act_cnt;
+    // relaxed C rows; their lengths in act_cnt[0..2] on the device (inside
+    // the hierarchy's list upload area)
+    DevArr<int32_t> act_rows, act_f, act_c;
+    int32_t *act_cnt = nullptr;
     // cycle work vectors (capacity h->nrhs_cap right-hand sides)
     DevArr<double> b, x, t, r;
     DevArr<float> b32, x32, t32, r32;
@@ -112,6 +114,10 @@ struct lair_hierarchy {
     int32_t ss_nblk = 0;
     std::vector<int32_t> sys_levels;
     lair::DevArr<uint8_t> active_dev;
+    // batch solve: the active-row list lengths of every level (3 per level,
+    // at fixed addresses read by captured iterations) followed by the
+    // segment tables of the last list rebuild, uploaded in one copy
+    lair::DevArr<char> act_upload;
     lair::DevArr<double> seg_norm;
     lair::DevArr<double> e64;
     // single system: the cycle runs on split-ordered copies (Level::As ...)
@@ -1146,7 +1152,7 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     // batch solve: only the rows of the systems still iterated (device lists)
     const bool act = h->use_act;
     const int32_t *frows = act ? Lv.act_f.get() : (split ? Lv.ids.get() : Lv.flist.get());
-    const int32_t *fcnt = act ? Lv.act_cnt.get() + 1 : nullptr;
+    const int32_t *fcnt = act ? Lv.act_cnt + 1 : nullptr;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzF * nrhs);
@@ -1163,7 +1169,7 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     const int32_t *crows = act ? Lv.act_c.get()
                                : split ? Lv.ids.get() + Lv.nf
                                : (Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get());
-    const int32_t *ccnt = act ? Lv.act_cnt.get() + 2 : nullptr;
+    const int32_t *ccnt = act ? Lv.act_cnt + 2 : nullptr;
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, ncr, Lv.n, w, nrhs, false),
@@ -1206,7 +1212,7 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
         ProfScope ps("restrict", s, ab_rowdot(Lv.R, w, nrhs, 1), 2.0 * Lv.R.nnz * nrhs);
         if (h->use_act)
             op_rowdot_list<VT>(view<VT>(Lv.R, Lv.team_R), 1, Nx.act_rows.get(),
-                               Nx.act_cnt.get(), Nx.n, res, nullptr, bc, s);
+                               Nx.act_cnt, Nx.n, res, nullptr, bc, s);
         else
             op_spmv<VT>(view<VT>(Lv.Rs.rp.get() ? Lv.Rs : Lv.R, Lv.team_R), res, bc, nrhs, false,
                         s);
@@ -1217,7 +1223,7 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
                      2.0 * Lv.P.nnz * nrhs);
         if (h->use_act)
             op_rowdot_list<VT>(view<VT>(Lv.P, Lv.team_P), x_zero ? 1 : 2, Lv.act_rows.get(),
-                               Lv.act_cnt.get(), Lv.n, xc, nullptr, x, s);
+                               Lv.act_cnt, Lv.n, xc, nullptr, x, s);
         else
             op_spmv<VT>(view<VT>(Lv.Ps.rp.get() ? Lv.Ps : Lv.P, Lv.team_P), xc, x, nrhs, !x_zero,
                         s);
@@ -1509,10 +1515,14 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
     if (!mixed && h->e64.get() == nullptr) { h->e64.alloc((size_t)n, s); moved = true; }
     // one system: the iteration stops when it converges, no lists needed
     const bool lists = ns > 1;
-    if (lists && L0.act_cnt.get() == nullptr) {
+    const size_t cnt_bytes = (3 * sizeof(int32_t) * h->L.size() + 15) & ~(size_t)15;
+    if (lists && L0.act_cnt == nullptr) {
+        const size_t maxseg = 3 * h->L.size() * (size_t)ns;
+        h->act_upload.alloc(cnt_bytes + sizeof(int64_t) * (maxseg + 1) +
+                                3 * sizeof(int32_t) * maxseg + 64, s);
         for (size_t l = 0; l < h->L.size(); ++l) {
             Level &Lv = *h->L[l];
-            Lv.act_cnt.alloc(3, s);
+            Lv.act_cnt = reinterpret_cast<int32_t *>(h->act_upload.get()) + 3 * l;
             Lv.act_rows.alloc((size_t)std::max(Lv.n, 1), s);
             if (l + 1 < h->L.size()) {
                 Lv.act_f.alloc((size_t)std::max(Lv.nf, 1), s);
@@ -1578,8 +1588,6 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
     }
     DevArr<const int32_t *> d_src;
     DevArr<int32_t *> d_dst;
-    DevArr<int64_t> d_out;
-    DevArr<int32_t> d_meta, d_counts;
     if (lists) {
         std::vector<const int32_t *> srcs(3 * nlev, nullptr);
         std::vector<int32_t *> dsts(3 * nlev, nullptr);
@@ -1599,10 +1607,6 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                                 hipMemcpyHostToDevice, s));
         LAIR_HIP(hipMemcpyAsync(d_dst.get(), dsts.data(), sizeof(void *) * 3 * nlev,
                                 hipMemcpyHostToDevice, s));
-        const size_t maxseg = 3 * nlev * (size_t)ns;
-        d_out.alloc(maxseg + 1, s);
-        d_meta.alloc(3 * maxseg, s);
-        d_counts.alloc(3 * nlev, s);
         LAIR_HIP(hipStreamSynchronize(s));     // the pointer tables are pageable host memory
     }
     auto rebuild_lists = [&]() {
@@ -1627,26 +1631,25 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                 counts[3 * l + t] = pos;
             }
         const int32_t nseg = (int32_t)lst.size();
-        // one pinned upload area, copied in stream order; it is rewritten only
-        // at the next rebuild, after the readback that follows this iteration
+        // one pinned upload area with the device layout: the list lengths
+        // (fixed addresses), then the segment offsets, sources, targets and
+        // list numbers; one copy in stream order.  It is rewritten only at
+        // the next rebuild, after the readback that follows this iteration.
         const size_t b_out = sizeof(int64_t) * out.size(), b_i = sizeof(int32_t) * nseg;
-        char *st = (char *)pinned_upload(b_out + 3 * b_i + sizeof(int32_t) * counts.size() + 64);
-        memcpy(st, out.data(), b_out);
-        memcpy(st + b_out, src.data(), b_i);
-        memcpy(st + b_out + b_i, dst.data(), b_i);
-        memcpy(st + b_out + 2 * b_i, lst.data(), b_i);
-        memcpy(st + b_out + 3 * b_i, counts.data(), sizeof(int32_t) * counts.size());
-        LAIR_HIP(hipMemcpyAsync(d_out.get(), st, b_out, hipMemcpyHostToDevice, s));
-        if (nseg) {
-            LAIR_HIP(hipMemcpyAsync(d_meta.get(), st + b_out, 3 * b_i, hipMemcpyHostToDevice, s));
-        }
-        LAIR_HIP(hipMemcpyAsync(d_counts.get(), st + b_out + 3 * b_i,
-                                sizeof(int32_t) * counts.size(), hipMemcpyHostToDevice, s));
-        for (size_t l = 0; l < nlev; ++l)
-            LAIR_HIP(hipMemcpyAsync(h->L[l]->act_cnt.get(), d_counts.get() + 3 * l,
-                                    3 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        launch_materialize(nseg, out.back(), d_out.get(), d_meta.get(), d_meta.get() + nseg,
-                           d_meta.get() + 2 * nseg, d_src.get(), d_dst.get(), s);
+        const size_t total = cnt_bytes + b_out + 3 * b_i;
+        char *st = (char *)pinned_upload(total + 64);
+        memset(st, 0, cnt_bytes);
+        memcpy(st, counts.data(), sizeof(int32_t) * counts.size());
+        memcpy(st + cnt_bytes, out.data(), b_out);
+        memcpy(st + cnt_bytes + b_out, src.data(), b_i);
+        memcpy(st + cnt_bytes + b_out + b_i, dst.data(), b_i);
+        memcpy(st + cnt_bytes + b_out + 2 * b_i, lst.data(), b_i);
+        char *dev = h->act_upload.get();
+        LAIR_HIP(hipMemcpyAsync(dev, st, total, hipMemcpyHostToDevice, s));
+        const int64_t *d_out = reinterpret_cast<const int64_t *>(dev + cnt_bytes);
+        const int32_t *d_meta = reinterpret_cast<const int32_t *>(dev + cnt_bytes + b_out);
+        launch_materialize(nseg, out.back(), d_out, d_meta, d_meta + nseg, d_meta + 2 * nseg,
+                           d_src.get(), d_dst.get(), s);
     };
     struct ActGuard {
         lair_hierarchy *h;
@@ -1710,14 +1713,14 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
                 vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, 1, st);
                 ProfScope ps("cast", st, 20.0 * n);
                 if (lists)
-                    op_update_list<float>(L0.act_rows.get(), L0.act_cnt.get(), (int32_t)n, x,
+                    op_update_list<float>(L0.act_rows.get(), L0.act_cnt, (int32_t)n, x,
                                           h->e32.get(), st);
                 else
                     op_axpy_f32(x, h->e32.get(), n, st);
             } else {
                 vcycle<double>(h, 0, h->r0.get(), h->e64.get(), true, nullptr, 1, st);
                 if (lists) {
-                    op_update_list<double>(L0.act_rows.get(), L0.act_cnt.get(), (int32_t)n, x,
+                    op_update_list<double>(L0.act_rows.get(), L0.act_cnt, (int32_t)n, x,
                                            h->e64.get(), st);
                 } else {
                     LAIR_LAUNCH(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, x,
@@ -1728,7 +1731,7 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
             {
                 ProfScope ps("residual", st, ab_rowdot(L0.A, 8, 1, 2), 2.0 * L0.A.nnz);
                 if (lists)
-                    op_rowdot_list<double>(A0, 0, L0.act_rows.get(), L0.act_cnt.get(),
+                    op_rowdot_list<double>(A0, 0, L0.act_rows.get(), L0.act_cnt,
                                            (int32_t)n, x, bb, h->r0.get(), st);
                 else
                     op_residual<double>(A0, bb, x, h->r0.get(), 1, st);
