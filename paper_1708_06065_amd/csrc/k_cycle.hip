@@ -115,13 +115,22 @@ struct Pack {
     }
 };
 
+// Row k of a row list: rows[k], or row0 + k for a contiguous range
+// (rows == nullptr).
+__device__ __forceinline__ int32_t list_row(const int32_t *rows, int32_t row0, int64_t k) {
+    return rows ? rows[k] : row0 + (int32_t)k;
+}
+
 // A team of T = G L lanes per row (G a power of two chosen from the row
 // length): the team loads T consecutive entries, group g of L lanes takes
 // entries g L .. g L + L - 1 of them, and the G partial sums are added by
 // shuffles at the end.
 // TAG: the column indices carry the point type in their sign bit (C-point
 // columns are stored as c | 2^31), which spares SEL the load of cf[c].
-template <class VT, int NR, int VW, bool SEL, bool TAG = false>
+// U: steps of T entries taken together (their loads all in flight before
+// the first product); a lane still adds its entries in increasing order, so
+// the sums do not depend on U.
+template <class VT, int NR, int VW, bool SEL, bool TAG = false, int U = 1>
 __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_col,
                                          const int32_t *cj, const VT *v,
                                          const VT *xF, const VT *xC,
@@ -129,36 +138,47 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
     constexpr int L = NR / VW;
     const int q = t % L;
     const int g0 = (t / L) * L;      // first entry of this lane's group
-    for (int base = lo; base < hi; base += T) {
-        int p = base + t;
-        int c = 0;
-        VT a = (VT)0;
-        if (p < hi) { c = cj[p]; a = v[p]; }
-        int ce[L];
-        VT ae[L];
+    for (int base = lo; base < hi; base += U * T) {
+        int c[U];
+        VT a[U];
 #pragma unroll
-        for (int e = 0; e < L; ++e) {
-            ce[e] = __shfl(c, e, L);
-            ae[e] = __shfl(a, e, L);
+        for (int u = 0; u < U; ++u) {
+            const int p = base + u * T + t;
+            c[u] = 0;
+            a[u] = (VT)0;
+            if (p < hi) { c[u] = cj[p]; a[u] = v[p]; }
         }
-        Pack<VT, VW> xe[L];
+        int ce[U][L];
+        VT ae[U][L];
 #pragma unroll
-        for (int e = 0; e < L; ++e) {
-            if (base + g0 + e < hi) {
-                const int col = TAG ? (ce[e] & 0x7fffffff) : ce[e];
-                const VT *src = TAG ? (ce[e] < 0 ? xC : xF)
-                                    : (SEL ? (cf[col] ? xC : xF) : xF);
-                xe[e].load(src + (int64_t)col * NR + q * VW);
-                if (col == diag_col) d = ae[e];
-            } else {
-                xe[e].zero();
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < L; ++e) {
+                ce[u][e] = __shfl(c[u], e, L);
+                ae[u][e] = __shfl(a[u], e, L);
             }
-        }
+        Pack<VT, VW> xe[U][L];
 #pragma unroll
-        for (int e = 0; e < L; ++e) {
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < VW; ++k) acc.v[k] += ae[e] * xe[e].v[k];
-        }
+            for (int e = 0; e < L; ++e) {
+                if (base + u * T + g0 + e < hi) {
+                    const int col = TAG ? (ce[u][e] & 0x7fffffff) : ce[u][e];
+                    const VT *src = TAG ? (ce[u][e] < 0 ? xC : xF)
+                                        : (SEL ? (cf[col] ? xC : xF) : xF);
+                    xe[u][e].load(src + (int64_t)col * NR + q * VW);
+                    if (col == diag_col) d = ae[u][e];
+                } else {
+                    xe[u][e].zero();
+                }
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < L; ++e) {
+#pragma unroll
+                for (int k = 0; k < VW; ++k) acc.v[k] += ae[u][e] * xe[u][e].v[k];
+            }
     }
     for (int o = L; o < T; o <<= 1) {
 #pragma unroll
@@ -167,7 +187,7 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
     }
 }
 
-template <class VT, int NR, int VW, int MODE>
+template <class VT, int NR, int VW, int MODE, int U>
 __global__ void __launch_bounds__(256)
 k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *v,
           const VT *x, const VT *b, VT *y) {
@@ -179,7 +199,8 @@ k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *
     Pack<VT, VW> acc;
     acc.zero();
     VT d = (VT)0;
-    row_accV<VT, NR, VW, false>(rp[i], rp[i + 1], t, T, -1, cj, v, x, x, nullptr, acc, d);
+    row_accV<VT, NR, VW, false, false, U>(rp[i], rp[i + 1], t, T, -1, cj, v, x, x, nullptr,
+                                          acc, d);
     if (t >= L) return;
     const int64_t o = (int64_t)i * NR + t * VW;
     Pack<VT, VW> out;
@@ -197,26 +218,29 @@ k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *
     out.store(y + o);
 }
 
-template <class VT, int NR, int VW, bool SEL, bool TAG>
+template <class VT, int NR, int VW, bool SEL, bool TAG, int U>
 __global__ void __launch_bounds__(256)
-k_jacobiV(int32_t nx, int T, const int32_t *rows, const int32_t *rp, const int32_t *cj,
-          const VT *v, const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
-          VT *out, int compact, VT omega) {
+k_jacobiV(int32_t nx, int T, const int32_t *rows, int32_t row0, const int32_t *rp,
+          const int32_t *cj, const VT *v, const VT *b, const VT *xF, const VT *xC,
+          const int8_t *cf, VT *out, int compact, VT omega) {
     constexpr int L = NR / VW;
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t k = (int32_t)(gt / T);
     int t = (int)(gt % T);
     if (k >= nx) return;
-    int32_t i = rows[k];
+    const int32_t i = list_row(rows, row0, k);
+    // the row's own old value and right-hand side load beside the row
+    const int64_t oi = (int64_t)i * NR + (t % L) * VW;
+    Pack<VT, VW> xi, bi, r;
+    if (t < L) {
+        xi.load((SEL ? (cf[i] ? xC : xF) : xF) + oi);
+        bi.load(b + oi);
+    }
     Pack<VT, VW> acc;
     acc.zero();
     VT d = (VT)0;
-    row_accV<VT, NR, VW, SEL, TAG>(rp[i], rp[i + 1], t, T, i, cj, v, xF, xC, cf, acc, d);
+    row_accV<VT, NR, VW, SEL, TAG, U>(rp[i], rp[i + 1], t, T, i, cj, v, xF, xC, cf, acc, d);
     if (t >= L) return;
-    const int64_t oi = (int64_t)i * NR + t * VW;
-    Pack<VT, VW> xi, bi, r;
-    xi.load((SEL ? (cf[i] ? xC : xF) : xF) + oi);
-    bi.load(b + oi);
 #pragma unroll
     for (int e = 0; e < VW; ++e) r.v[e] = xi.v[e] + omega * (bi.v[e] - acc.v[e]) / d;
     r.store(out + (compact ? (int64_t)k * NR + t * VW : oi));
@@ -229,6 +253,13 @@ static inline int vec_team(int L, int team) {
     int g = 1;
     while (g * L * 2 < team && g * L < 64) g <<= 1;
     return g * L;
+}
+
+// Steps of T entries per loop turn: two when a mean row (team) needs more
+// than one step and the doubled gathers still fit the registers.
+template <class VT>
+static inline int vec_unroll(int nrhs, int T, int team) {
+    return team > T && nrhs <= (sizeof(VT) == 4 ? 16 : 8) ? 2 : 1;
 }
 
 // Outer residual of the double iteration fused with its norms and the
@@ -362,12 +393,15 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
     if (A.nrows == 0) return;
     if (nrhs > 1 && aligned16(x) && aligned16(y) && (!b || aligned16(b))) {
         constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
+#define LAIR_RVU(NN, WW, UU)                                                      \
+        LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU>),                            \
+                           dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
+                           A.nrows, T, A.rp, A.cj, A.v, x, b, y);
 #define LAIR_RV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
-        LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE>),                         \
-                           dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, y);                 \
+        if (vec_unroll<VT>(NN, T, A.team) == 2) { LAIR_RVU(NN, WW, 2) }           \
+        else { LAIR_RVU(NN, WW, 1) }                                              \
     }
         switch (nrhs) {
             case 2: LAIR_RV(2, 2); break;
@@ -377,6 +411,7 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
             default: LAIR_RV(32, VW); break;
         }
 #undef LAIR_RV
+#undef LAIR_RVU
         LAIR_LAUNCH_CHECK();
         return;
     }
@@ -461,7 +496,7 @@ void op_rowdot_list(const CsrView<VT> &A, int mode, const int32_t *rows, const i
 // ---------------------------------------------------------------------------
 template <class VT, int T, bool SEL>
 __global__ void __launch_bounds__(256)
-k_jacobi1(int32_t nx, const int32_t *cnt, const int32_t *rows, const int32_t *rp,
+k_jacobi1(int32_t nx, const int32_t *cnt, const int32_t *rows, int32_t row0, const int32_t *rp,
           const int32_t *cj, const VT *v, const VT *b, const VT *xF, const VT *xC,
           const int8_t *cf, VT *out, int compact, VT omega) {
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
@@ -469,7 +504,7 @@ k_jacobi1(int32_t nx, const int32_t *cnt, const int32_t *rows, const int32_t *rp
     const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / T);
     const int32_t n = cnt ? *cnt : nx;
     for (int64_t k = gt / T; k < n; k += nteams) {
-        int32_t i = rows[k];
+        const int32_t i = list_row(rows, row0, k);
         VT acc = (VT)0, d = (VT)0;
         row_acc1<VT, T, SEL>(rp[i], rp[i + 1], lane, i, cj, v, xF, xC, cf, acc, d);
         acc = team_sum<T>(acc);
@@ -483,14 +518,14 @@ k_jacobi1(int32_t nx, const int32_t *cnt, const int32_t *rows, const int32_t *rp
 
 template <class VT, int NR, bool SEL>
 __global__ void __launch_bounds__(256)
-k_jacobiM(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
+k_jacobiM(int32_t nx, const int32_t *rows, int32_t row0, const int32_t *rp, const int32_t *cj,
           const VT *v, const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
           VT *out, int compact, VT omega) {
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t k = (int32_t)(gt / NR);
     int q = (int)(gt % NR);
     if (k >= nx) return;
-    int32_t i = rows[k];
+    const int32_t i = list_row(rows, row0, k);
     VT acc = (VT)0, d = (VT)0;
     row_accM<VT, NR, SEL>(rp[i], rp[i + 1], q, i, cj, v, xF, xC, cf, acc, d);
     int64_t oi = (int64_t)i * NR + q;
@@ -499,24 +534,29 @@ k_jacobiM(int32_t nx, const int32_t *rows, const int32_t *rp, const int32_t *cj,
 }
 
 template <class VT, bool SEL>
-static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
+static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t row0, int32_t nx,
                           const int32_t *cnt, const VT *b, const VT *xF, const VT *xC,
                           const int8_t *cf, VT *out, int compact, VT om, int32_t nrhs,
                           hipStream_t s) {
     if (cnt && nrhs != 1) fail(LAIR_EINVAL, "listed Jacobi rows take one right-hand side");
     if (nrhs > 1 && aligned16(b) && aligned16(xF) && aligned16(xC) && aligned16(out)) {
         constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
+#define LAIR_JVU(NN, WW, UU)                                                      \
+    {                                                                             \
+        if (SEL && A.cjt)                                                         \
+            LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL, true, UU>),                   \
+                        dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s,  \
+                        nx, T, rows, row0, A.rp, A.cjt, A.v, b, xF, xC, cf, out, compact, om); \
+        else                                                                      \
+            LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL, false, UU>),                  \
+                        dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s,  \
+                        nx, T, rows, row0, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om); \
+    }
 #define LAIR_JV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
-        if (SEL && A.cjt)                                                         \
-            LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL, true>),                       \
-                        dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s,  \
-                        nx, T, rows, A.rp, A.cjt, A.v, b, xF, xC, cf, out, compact, om); \
-        else                                                                      \
-            LAIR_LAUNCH((k_jacobiV<VT, NN, WW, SEL, false>),                      \
-                        dim3(blocks_for((int64_t)nx * T, 256)), dim3(256), 0, s,  \
-                        nx, T, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om); \
+        if (vec_unroll<VT>(NN, T, A.team) == 2) LAIR_JVU(NN, WW, 2)               \
+        else LAIR_JVU(NN, WW, 1)                                                  \
     }
         switch (nrhs) {
             case 2: LAIR_JV(2, 2); break;
@@ -526,6 +566,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
             default: LAIR_JV(32, VW); break;
         }
 #undef LAIR_JV
+#undef LAIR_JVU
         LAIR_LAUNCH_CHECK();
         return;
     }
@@ -533,7 +574,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
 #define LAIR_JM(NN)                                                               \
     LAIR_LAUNCH((k_jacobiM<VT, NN, SEL>),                                  \
                        dim3(blocks_for((int64_t)nx * NN, 256)), dim3(256), 0, s,  \
-                       nx, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
+                       nx, rows, row0, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
         switch (nrhs) {
             case 2: LAIR_JM(2); break;
             case 4: LAIR_JM(4); break;
@@ -548,7 +589,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
 #define LAIR_JC(TT)                                                              \
     LAIR_LAUNCH((k_jacobi1<VT, TT, SEL>),                                 \
                        dim3(cnt ? list_grid((int64_t)nx * TT) : blocks_for((int64_t)nx * TT, 256)), \
-                       dim3(256), 0, s, nx, cnt, rows, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
+                       dim3(256), 0, s, nx, cnt, rows, row0, A.rp, A.cj, A.v, b, xF, xC, cf, out, compact, om)
     switch (scalar_team(A.team)) {
         case 1: LAIR_JC(1); break;
         case 2: LAIR_JC(2); break;
@@ -566,36 +607,38 @@ template <class VT>
 void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nx,
                const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
                VT *out, bool compact, double omega, int32_t nrhs,
-               hipStream_t s, const int32_t *cnt) {
+               hipStream_t s, const int32_t *cnt, int32_t row0) {
     if (nx == 0) return;
+    if (!rows && cnt) fail(LAIR_EINVAL, "a counted row list needs its rows");
     VT om = (VT)omega;
     if (cf)
-        jacobi_launch<VT, true>(A, rows, nx, cnt, b, xF, xC, cf, out, compact ? 1 : 0, om,
-                                nrhs, s);
+        jacobi_launch<VT, true>(A, rows, row0, nx, cnt, b, xF, xC, cf, out, compact ? 1 : 0,
+                                om, nrhs, s);
     else
-        jacobi_launch<VT, false>(A, rows, nx, cnt, b, xF, xF, nullptr, out, compact ? 1 : 0,
-                                 om, nrhs, s);
+        jacobi_launch<VT, false>(A, rows, row0, nx, cnt, b, xF, xF, nullptr, out,
+                                 compact ? 1 : 0, om, nrhs, s);
 }
 
 template <class VT>
-__global__ void k_scatter(int64_t total, int32_t nrhs, const int32_t *rows,
+__global__ void k_scatter(int64_t total, int32_t nrhs, const int32_t *rows, int32_t row0,
                           const int32_t *cnt, const VT *t, VT *x) {
     const int64_t n = cnt ? (int64_t)*cnt * nrhs : total;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
          g += (int64_t)gridDim.x * blockDim.x) {
         int64_t k = g / nrhs;
         int q = (int)(g % nrhs);
-        x[(int64_t)rows[k] * nrhs + q] = t[g];
+        x[(int64_t)list_row(rows, row0, k) * nrhs + q] = t[g];
     }
 }
 
 template <class VT>
 void op_scatter(const int32_t *rows, int32_t nx, const VT *t, VT *x,
-                int32_t nrhs, hipStream_t s, const int32_t *cnt) {
+                int32_t nrhs, hipStream_t s, const int32_t *cnt, int32_t row0) {
     if (nx == 0) return;
+    if (!rows && cnt) fail(LAIR_EINVAL, "a counted row list needs its rows");
     int64_t total = (int64_t)nx * nrhs;
     LAIR_LAUNCH((k_scatter<VT>), dim3(cnt ? list_grid(total) : blocks_for(total, 256)),
-                dim3(256), 0, s, total, nrhs, rows, cnt, t, x);
+                dim3(256), 0, s, total, nrhs, rows, row0, cnt, t, x);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -1017,16 +1060,16 @@ template void op_residual<double>(const CsrView<double> &, const double *, const
 template void op_residual<float>(const CsrView<float> &, const float *, const float *, float *, int32_t, hipStream_t);
 template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t);
 template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t);
-template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t, const int32_t *);
-template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t, const int32_t *);
+template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t, const int32_t *, int32_t);
+template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t, const int32_t *, int32_t);
 template void op_rowdot_list<double>(const CsrView<double> &, int, const int32_t *, const int32_t *, int32_t, const double *, const double *, double *, hipStream_t);
 template void op_rowdot_list<float>(const CsrView<float> &, int, const int32_t *, const int32_t *, int32_t, const float *, const float *, float *, hipStream_t);
 template void op_update_list<double>(const int32_t *, const int32_t *, int32_t, double *, const double *, hipStream_t);
 template void op_update_list<float>(const int32_t *, const int32_t *, int32_t, double *, const float *, hipStream_t);
 template void op_coarse_apply<double>(int32_t, const double *, const double *, double *, int32_t, bool, hipStream_t);
 template void op_coarse_apply<float>(int32_t, const double *, const float *, float *, int32_t, bool, hipStream_t);
-template void op_scatter<double>(const int32_t *, int32_t, const double *, double *, int32_t, hipStream_t, const int32_t *);
-template void op_scatter<float>(const int32_t *, int32_t, const float *, float *, int32_t, hipStream_t, const int32_t *);
+template void op_scatter<double>(const int32_t *, int32_t, const double *, double *, int32_t, hipStream_t, const int32_t *, int32_t);
+template void op_scatter<float>(const int32_t *, int32_t, const float *, float *, int32_t, hipStream_t, const int32_t *, int32_t);
 template void op_fill<double>(double *, double, int64_t, hipStream_t);
 template void op_fill<float>(float *, float, int64_t, hipStream_t);
 template void op_copy<double>(const double *, double *, int64_t, hipStream_t);

@@ -1151,7 +1151,8 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     const int w = sizeof(VT);
     // batch solve: only the rows of the systems still iterated (device lists)
     const bool act = h->use_act;
-    const int32_t *frows = act ? Lv.act_f.get() : (split ? Lv.ids.get() : Lv.flist.get());
+    // split ordering: F rows are 0 .. nf-1 and C rows nf .. n-1 (no list)
+    const int32_t *frows = act ? Lv.act_f.get() : (split ? nullptr : Lv.flist.get());
     const int32_t *fcnt = act ? Lv.act_cnt + 1 : nullptr;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzF, Lv.nf, Lv.n, w, nrhs, false),
@@ -1167,18 +1168,19 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
                       false, om, nrhs, s, fcnt);
     }
     const int32_t *crows = act ? Lv.act_c.get()
-                               : split ? Lv.ids.get() + Lv.nf
+                               : split ? nullptr
                                : (Lv.nrc >= 0 ? Lv.rclist.get() : Lv.clist.get());
     const int32_t *ccnt = act ? Lv.act_cnt + 2 : nullptr;
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
+    const int32_t c0 = split ? Lv.nf : 0;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, ncr, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzC * nrhs);
-        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, true, om, nrhs, s, ccnt);
+        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, true, om, nrhs, s, ccnt, c0);
     }
     {
         ProfScope ps("scatter", s, 4.0 * ncr + 2.0 * w * nrhs * ncr);
-        op_scatter<VT>(crows, ncr, y, x, nrhs, s, ccnt);
+        op_scatter<VT>(crows, ncr, y, x, nrhs, s, ccnt, c0);
     }
 }
 

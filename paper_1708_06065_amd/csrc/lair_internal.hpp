@@ -309,18 +309,20 @@ void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
              bool accumulate, hipStream_t s);
 // Jacobi on rows X: out[k] (compact) or out[i] = x_i + omega (b - A x)_i / a_ii.
 // With cf non-null, neighbour values come from xC at C-points and from xF
-// at F-points; otherwise everything is read from xF.
+// at F-points; otherwise everything is read from xF.  rows == nullptr
+// means the contiguous rows row0 .. row0 + nrows - 1.
 template <class VT>
 void op_jacobi(const CsrView<VT> &A, const int32_t *rows, int32_t nrows,
                const VT *b, const VT *xF, const VT *xC, const int8_t *cf,
                VT *out, bool compact, double omega, int32_t nrhs,
-               hipStream_t s, const int32_t *cnt = nullptr);
+               hipStream_t s, const int32_t *cnt = nullptr, int32_t row0 = 0);
 template <class VT>
 void op_coarse_apply(int32_t n, const double *kinv, const VT *b, VT *x,
                      int32_t nrhs, bool transpose, hipStream_t s);
 template <class VT>
 void op_scatter(const int32_t *rows, int32_t nrows, const VT *t, VT *x,
-                int32_t nrhs, hipStream_t s, const int32_t *cnt = nullptr);
+                int32_t nrhs, hipStream_t s, const int32_t *cnt = nullptr,
+                int32_t row0 = 0);
 template <class VT>
 void op_fill(VT *x, VT val, int64_t n, hipStream_t s);
 template <class VT>
