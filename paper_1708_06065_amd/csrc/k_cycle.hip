@@ -255,6 +255,14 @@ static inline int vec_team(int L, int team) {
     return g * L;
 }
 
+// Jacobi sweeps on long rows (mean 32 or more): half as many lanes per row,
+// so that each lane keeps two steps of gathers in flight and twice as many
+// rows share a wavefront.
+static inline int vec_team_jacobi(int L, int team) {
+    const int T = vec_team(L, team);
+    return team >= 32 ? std::max(L, T / 2) : T;
+}
+
 // Steps of T entries per loop turn: two when a mean row (team) needs more
 // than one step and the doubled gathers still fit the registers.
 template <class VT>
@@ -554,7 +562,7 @@ static void jacobi_launch(const CsrView<VT> &A, const int32_t *rows, int32_t row
     }
 #define LAIR_JV(NN, WW)                                                           \
     {                                                                             \
-        const int T = vec_team(NN / WW, A.team);                                  \
+        const int T = vec_team_jacobi(NN / WW, A.team);                          \
         if (vec_unroll<VT>(NN, T, A.team) == 2) LAIR_JVU(NN, WW, 2)               \
         else LAIR_JVU(NN, WW, 1)                                                  \
     }

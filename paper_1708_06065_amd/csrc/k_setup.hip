@@ -2156,8 +2156,8 @@ void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double
                    int32_t *tcj, double *tcx, int32_t *work, int32_t *overflow,
                    hipStream_t s) {
     if (m == 0) return;
+    // work[0..1] (the counts of the retry lists) arrive zeroed
     int32_t *n1 = work, *n2 = work + 1, *l1 = work + 2, *l2 = work + 2 + m;
-    LAIR_HIP(hipMemsetAsync(work, 0, 2 * sizeof(int32_t), s));
     const int T = hacc_team(mean_e);
     const RowSrc all{nullptr, nullptr};
     const unsigned g = blocks_for((int64_t)m * T, 256);
@@ -2481,78 +2481,92 @@ k_dense_lu_lds(int32_t n, double *lu, int32_t *piv, int32_t *info) {
 // at step k.
 constexpr int LUI_ROWS = 128;
 constexpr int LUI_BS = 1024;
-constexpr int LUI_TPR = LUI_BS / LUI_ROWS;     // lanes per row
+constexpr int LUI_WAVES = LUI_BS / 64;
+constexpr int LUI_RPW = LUI_ROWS / LUI_WAVES;    // row positions per wave
 
+// Gauss-Jordan inverse with partial pivoting in place, in one workgroup.
+// Row positions are dealt to the waves cyclically; lane q of a wave holds
+// columns q and q + 64 of the rows it updates.  Each step: every wave finds
+// the pivot itself (same reads, same answer: no exchange) and reads the
+// pivot row and its own rows; after one barrier it writes its rows, and a
+// second barrier ends the step.  The row exchanges are undone as a column
+// permutation on the way out.
 __global__ void __launch_bounds__(LUI_BS)
 k_dense_gj_inv(int32_t n, const double *dense, double *inv, int32_t *info) {
     extern __shared__ double a[];
-    __shared__ double s_bv[LUI_BS / 64];
-    __shared__ int s_bi[LUI_BS / 64];
     __shared__ int s_piv[LUI_ROWS];
-    __shared__ double s_col[LUI_ROWS];
+    __shared__ int s_perm[LUI_ROWS];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     for (int idx = tid; idx < n * n; idx += LUI_BS) a[idx] = dense[idx];
     __syncthreads();
+    const int q0 = lane, q1 = lane + 64;
+    const bool h0 = q0 < n, h1 = q1 < n;
     for (int k = 0; k < n; ++k) {
-        // pivot: every wave reduces the candidates, then the per-wave
-        // results by shuffles (no serial pass over them)
-        double bv = (tid < n && tid >= k) ? fabs(a[tid * n + k]) : -1.0;
-        int bi = tid;
+        double bv = -1.0;
+        int bi = INT_MAX;
+        if (h0 && q0 >= k) { bv = fabs(a[q0 * n + k]); bi = q0; }
+        if (h1 && q1 >= k) {
+            const double v1 = fabs(a[q1 * n + k]);
+            if (v1 > bv) { bv = v1; bi = q1; }
+        }
         team_argmax<64>(bv, bi);
-        if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
-        __syncthreads();
-        double pv = lane < LUI_BS / 64 ? s_bv[lane] : -1.0;
-        int pr = lane < LUI_BS / 64 ? s_bi[lane] : INT_MAX;
-        team_argmax<64>(pv, pr);
-        if (pv == 0.0) {
+        if (bv == 0.0) {            // the same in every wave: all leave together
             if (tid == 0) *info = k + 1;
             return;
         }
-        if (tid == 0) s_piv[k] = pr;
-        // exchange rows k and pr; scale the pivot row (its pivot entry
-        // becomes the inverse's); keep column k of the other rows
-        // (all reads before any write of this step)
+        const int pr = bi;
         const double d = 1.0 / a[pr * n + k];
-        const double akk = a[k * n + k];
-        double xk = 0.0, xp = 0.0, colv = 0.0;
-        if (tid < n) {
-            xk = a[k * n + tid];
-            xp = a[pr * n + tid];
-            colv = a[tid * n + k];
-        }
-        __syncthreads();
-        if (tid < n) {
-            if (pr != k) a[pr * n + tid] = xk;
-            a[k * n + tid] = (tid == k ? 1.0 : xp) * d;
-            s_col[tid] = (tid == k) ? 0.0 : (tid == pr ? akk : colv);
-        }
-        __syncthreads();
-        // every other row: a_r -= a_rk * (pivot row), column k taking the
-        // inverse's entry -a_rk * d (lanes LUI_TPR r .. of row r take every
-        // LUI_TPR-th column)
-        {
-            const int r = tid / LUI_TPR, c = tid % LUI_TPR;
+        // scaled pivot row (its column k becomes the inverse's entry d)
+        const double p0 = h0 ? (q0 == k ? 1.0 : a[pr * n + q0]) * d : 0.0;
+        const double p1 = h1 ? (q1 == k ? 1.0 : a[pr * n + q1]) * d : 0.0;
+        // this wave's rows; position pr receives old row k
+        double f[LUI_RPW], s0[LUI_RPW], s1[LUI_RPW];
+#pragma unroll
+        for (int t = 0; t < LUI_RPW; ++t) {
+            const int r = wave + t * LUI_WAVES;
+            const int src = (r == pr) ? k : r;
+            f[t] = 0.0;
+            s0[t] = 0.0;
+            s1[t] = 0.0;
             if (r < n && r != k) {
-                const double f = s_col[r];
-                for (int q = c; q < n; q += LUI_TPR)
-                    a[r * n + q] = (q == k) ? -f * d : a[r * n + q] - f * a[k * n + q];
+                f[t] = a[src * n + k];
+                if (h0) s0[t] = a[src * n + q0];
+                if (h1) s1[t] = a[src * n + q1];
+            }
+        }
+        if (tid == 0) s_piv[k] = pr;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < LUI_RPW; ++t) {
+            const int r = wave + t * LUI_WAVES;
+            if (r >= n) break;
+            if (r == k) {
+                if (h0) a[k * n + q0] = p0;
+                if (h1) a[k * n + q1] = p1;
+            } else {
+                if (h0) a[r * n + q0] = (q0 == k) ? -f[t] * d : s0[t] - f[t] * p0;
+                if (h1) a[r * n + q1] = (q1 == k) ? -f[t] * d : s1[t] - f[t] * p1;
             }
         }
         __syncthreads();
     }
-    // undo the row exchanges as column exchanges, last first
-    for (int r = tid; r < n; r += LUI_BS)
+    // the row exchanges, undone last first as column exchanges, compose to
+    // one column permutation: inv[r][c] = a[r][perm[c]]
+    if (tid == 0) {
+        for (int c = 0; c < n; ++c) s_perm[c] = c;
         for (int j = n - 1; j >= 0; --j) {
             const int jp = s_piv[j];
-            if (jp != j) {
-                const double x = a[r * n + j];
-                a[r * n + j] = a[r * n + jp];
-                a[r * n + jp] = x;
-            }
+            const int t = s_perm[j];
+            s_perm[j] = s_perm[jp];
+            s_perm[jp] = t;
         }
+    }
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += LUI_BS) inv[idx] = a[idx];
+    for (int r = wave; r < n; r += LUI_WAVES) {
+        if (h0) inv[r * n + q0] = a[r * n + s_perm[q0]];
+        if (h1) inv[r * n + q1] = a[r * n + s_perm[q1]];
+    }
     if (tid == 0) *info = 0;
 }
 

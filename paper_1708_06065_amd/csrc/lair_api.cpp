@@ -210,19 +210,25 @@ __global__ void k_block_diag_csr(int32_t nblk, int32_t k, const double *dinv,
 // setup does not stop for each of them.
 struct PendingSizes {
     DevArr<int64_t> d;               // [0] nnz, [1] longest row, [2] flag (low word)
+    int64_t *dp = nullptr;           // d, or three zeroed slots of the caller
     int64_t h[3] = {0, 0, 0};
     DevCSR *m = nullptr;
     const char *what = "";
     void arm(DevCSR *mat, const char *w, hipStream_t s) {
         d.alloc(3, s);
         LAIR_HIP(hipMemsetAsync(d.get(), 0, 3 * sizeof(int64_t), s));
+        arm_at(d.get(), mat, w);
+    }
+    // slots already zeroed in stream order (no memset here)
+    void arm_at(int64_t *slots, DevCSR *mat, const char *w) {
+        dp = slots;
         m = mat;
         what = w;
     }
-    int64_t *tot() { return d.get(); }
-    int32_t *flag() { return reinterpret_cast<int32_t *>(d.get() + 2); }
+    int64_t *tot() { return dp; }
+    int32_t *flag() { return reinterpret_cast<int32_t *>(dp + 2); }
     void add(Readback &rb) {
-        if (m) rb.add(h, d.get(), sizeof(h));
+        if (m) rb.add(h, dp, sizeof(h));
     }
     // after the readback that carried them
     void apply() {
@@ -260,9 +266,13 @@ struct SpgemmState {
     int32_t m = 0;
     DevArr<int32_t> cnt, work;
     DevArr<int64_t> eoff, tot;       // tot: [0] products, [1] most in a row
+    DevArr<int64_t> ctl;             // [0..2] C's sizes or [2] the overflow flag
     int64_t h[2] = {0, 0};
 };
 
+// The counters the product needs zeroed are cleared here, while earlier
+// work still runs, rather than after the readback that spgemm_finish waits
+// for.
 static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipStream_t s,
                          DevArr<int64_t> &tmp) {
     const int32_t m = A.nrows;
@@ -271,6 +281,9 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
     st.eoff.alloc((size_t)m + 1, s);
     st.work.alloc(2 + 2 * (size_t)m, s);
     st.tot.alloc(2, s);
+    st.ctl.alloc(3, s);
+    LAIR_HIP(hipMemsetAsync(st.work.get(), 0, 2 * sizeof(int32_t), s));
+    LAIR_HIP(hipMemsetAsync(st.ctl.get(), 0, 3 * sizeof(int64_t), s));
     // products per row: A's indices and B's row pointers
     ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
                                         8.0 * (B.nrows + 1) + 12.0 * m);
@@ -286,16 +299,8 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
     const int64_t etot = st.h[0], emax = st.h[1];
     C.nrows = m;
     C.ncols = B.ncols;
-    DevArr<int32_t> over;
-    int32_t *ovp;
-    if (defer) {
-        defer->arm(&C, "sparse product row with more than 1024 terms", s);
-        ovp = defer->flag();
-    } else {
-        over.alloc(1, s);
-        LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
-        ovp = over.get();
-    }
+    int32_t *ovp = reinterpret_cast<int32_t *>(st.ctl.get() + 2);
+    if (defer) defer->arm_at(st.ctl.get(), &C, "sparse product row with more than 1024 terms");
     DevArr<int32_t> tcj;
     DevArr<double> tcx;
     tcj.alloc((size_t)std::max<int64_t>(etot, 1), s);
@@ -495,6 +500,10 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.cidx.alloc((size_t)n, s);
     Lv.clist.alloc((size_t)std::max(n, 1), s);
     Lv.flist.alloc((size_t)std::max(n, 1), s);
+    // the neighbourhoods' overflow flag, cleared before the readback below
+    DevArr<int32_t> over;
+    over.alloc(1, s);
+    LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
     int64_t nc = 0;
     {
         DevArr<unsigned long long> acc;
@@ -533,10 +542,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     }
 
     // neighbourhoods
-    DevArr<int32_t> cnt, over;
+    DevArr<int32_t> cnt;
     cnt.alloc((size_t)Lv.nc + 1, s);
-    over.alloc(1, s);
-    LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
     launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, cnt.get(),
                           nullptr, nullptr, over.get(), Lv.max_row, s);

@@ -254,7 +254,8 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 // (an upper bound of its length); launch_spgemm writes each row of C,
 // sorted, at its product offset eoff[i] of the staging arrays (tcj, tcx)
 // and its length into cnt; launch_spgemm_compact copies the rows to C
-// (row pointers crp from a scan of cnt).  work: 2 + 2 m int32.
+// (row pointers crp from a scan of cnt).  work: 2 + 2 m int32, the first
+// two zeroed by the caller; *overflow zeroed by the caller.
 void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
                        int32_t *e, hipStream_t s);
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
