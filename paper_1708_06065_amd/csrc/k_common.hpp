@@ -77,6 +77,18 @@ __device__ __forceinline__ void team_argmax(double &v, int &idx) {
     }
 }
 
+// Largest 64-bit key over a team (a packed arg-max: value bits above, an
+// index code below).
+template <int T>
+__device__ __forceinline__ uint64_t team_max_u64(uint64_t v) {
+#pragma unroll
+    for (int o = T / 2; o > 0; o >>= 1) {
+        const uint64_t ov = __shfl_xor(v, o, T);
+        v = ov > v ? ov : v;
+    }
+    return v;
+}
+
 // Make the LDS writes of the calling wave visible to its later LDS reads
 // (lanes of one wave run in lockstep; only memory ordering is needed).
 __device__ __forceinline__ void wave_lds_sync() {

@@ -639,12 +639,26 @@ __global__ void k_scatter(int64_t total, int32_t nrhs, const int32_t *rows, int3
     }
 }
 
+// A contiguous row range: a straight copy, 16 bytes per thread.
+__global__ void k_copy16(int64_t n16, const int4 *src, int4 *dst) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n16) dst[g] = src[g];
+}
+
 template <class VT>
 void op_scatter(const int32_t *rows, int32_t nx, const VT *t, VT *x,
                 int32_t nrhs, hipStream_t s, const int32_t *cnt, int32_t row0) {
     if (nx == 0) return;
     if (!rows && cnt) fail(LAIR_EINVAL, "a counted row list needs its rows");
     int64_t total = (int64_t)nx * nrhs;
+    VT *dst = x + (int64_t)row0 * nrhs;
+    if (!rows && (total * (int64_t)sizeof(VT)) % 16 == 0 && aligned16(t) && aligned16(dst)) {
+        const int64_t n16 = total * (int64_t)sizeof(VT) / 16;
+        LAIR_LAUNCH(k_copy16, dim3(blocks_for(n16, 256)), dim3(256), 0, s, n16,
+                    reinterpret_cast<const int4 *>(t), reinterpret_cast<int4 *>(dst));
+        LAIR_LAUNCH_CHECK();
+        return;
+    }
     LAIR_LAUNCH((k_scatter<VT>), dim3(cnt ? list_grid(total) : blocks_for(total, 256)),
                 dim3(256), 0, s, total, nrhs, rows, row0, cnt, t, x);
     LAIR_LAUNCH_CHECK();

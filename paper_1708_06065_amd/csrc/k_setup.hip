@@ -930,9 +930,23 @@ __device__ __forceinline__ void team_solve(int p, int32_t c, const int32_t *clis
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const bool act = k < s;
-        double cand = (used || !act) ? -1.0 : fabs((double)Mr[k]);
+        double cand;
         int key = (pos << 8) | p;
-        team_argmax<T>(cand, key);
+        if constexpr (MIXED) {
+            // the same arg-max in one 64-bit key: |pivot| bits + 1 above (0
+            // for rows out of the race, below every candidate), the
+            // complement of the key below (ties to the smallest key)
+            uint64_t pk = (uint64_t)(~(uint32_t)key);
+            if (!(used || !act))
+                pk |= (uint64_t)(__float_as_uint(fabsf(Mr[k])) + 1u) << 32;
+            pk = team_max_u64<T>(pk);
+            key = (int)~(uint32_t)pk;
+            const uint32_t hi = (uint32_t)(pk >> 32);
+            cand = hi ? (double)__uint_as_float(hi - 1u) : -1.0;
+        } else {
+            cand = (used || !act) ? -1.0 : fabs((double)Mr[k]);
+            team_argmax<T>(cand, key);
+        }
         const int who = key & 0xff;
         const int wpos = key >> 8;
         if (act) pos = (p == who) ? k : (pos == k ? wpos : pos);

@@ -176,7 +176,7 @@ static CsrView<VT> view(const DevCSR &M, int32_t team) {
     return v;
 }
 
-static const int32_t NPARTIAL = 1024;
+static const int32_t NPARTIAL = 4096;   // blocks of the fused residual (and partial sums)
 
 __global__ void k_nonneg_flag(int32_t n, const int32_t *pc, int32_t *hs) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
