@@ -1148,8 +1148,7 @@ k_local_lane(const int32_t *cnt, const int32_t *list, const int32_t *clist,
 // dynamic LDS sized for the level's largest system up to WSMAX, beyond that
 // in a global scratch slab of 3 smax^2 doubles per block.  The gather
 // enumerates the entries of the rows l_p as one flat range over the lanes.
-// MIXED keeps a double copy of M for the refinement residual.
-constexpr int WSMAX = 64;
+// MIXED keeps a double copy of M for the refinement residual.  (WSMAX: 64.)
 
 template <class FT>
 __host__ __device__ constexpr size_t wave_lds_bytes(int cap) {
@@ -2166,12 +2165,14 @@ void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const in
 
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
                    const int32_t *bp, const int32_t *bj, const double *bx,
-                   const int64_t *eoff, int64_t max_e, double mean_e, int32_t *cnt,
-                   int32_t *tcj, double *tcx, int32_t *work, int32_t *overflow,
-                   hipStream_t s) {
+                   const int64_t *eoff, int64_t max_e, double mean_e, double mean_c_hint,
+                   int32_t *cnt, int32_t *tcj, double *tcx, int32_t *work,
+                   int32_t *overflow, hipStream_t s) {
     if (m == 0) return;
-    // work[0..1] (the counts of the retry lists) arrive zeroed
-    int32_t *n1 = work, *n2 = work + 1, *l1 = work + 2, *l2 = work + 2 + m;
+    // work[0..3] (the counts of the retry lists) arrive zeroed; then three
+    // lists of m rows
+    int32_t *n1 = work, *n2 = work + 1, *n3 = work + 2;
+    int32_t *l1 = work + 4, *l2 = work + 4 + m, *l3 = work + 4 + 2 * (int64_t)m;
     const int T = hacc_team(mean_e);
     const RowSrc all{nullptr, nullptr};
     const unsigned g = blocks_for((int64_t)m * T, 256);
@@ -2182,21 +2183,49 @@ void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double
     int HS = 16;
     while (HS < cap && HS < 2.0 * mean_e) HS <<= 1;
     if (HS < cap / 4) HS = cap / 4;
-    const int hc = HS / 2;
-#define LAIR_HA(TT, HH)                                                                    \
-    if (T == TT && HS == HH)                                                               \
-        spgemm_hacc<TT, HH, 256>(m, all, g, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, l1, n1, s);
-    LAIR_HA(8, 16) LAIR_HA(8, 32) LAIR_HA(8, 64)
-    LAIR_HA(16, 32) LAIR_HA(16, 64) LAIR_HA(16, 128)
-    LAIR_HA(32, 64) LAIR_HA(32, 128) LAIR_HA(32, 256)
-    LAIR_HA(64, 128) LAIR_HA(64, 256) LAIR_HA(64, 512)
+    // with an estimate of the distinct columns per row, a large product's
+    // first pass takes a table three times that size (more waves per CU);
+    // rows that do not fit are redone by the table above, then by the large
+    // one.  Small products keep one pass (a retry costs a launch).
+    int HS1 = HS;
+    if (mean_c_hint > 0.0 && m >= 65536) {
+        HS1 = 16;
+        while (HS1 < HS && HS1 < 3.0 * mean_c_hint) HS1 <<= 1;
+        if (HS1 < cap / 4) HS1 = cap / 4;
+    }
+#define LAIR_HA(TT, HH, SRC, GRID, NL, NN)                                                 \
+    if (T == TT && hs == HH)                                                               \
+        spgemm_hacc<TT, HH, 256>(m, SRC, GRID, ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, \
+                                 NL, NN, s);
+#define LAIR_HA_ALL(SRC, GRID, NL, NN)                                                     \
+    LAIR_HA(8, 16, SRC, GRID, NL, NN) LAIR_HA(8, 32, SRC, GRID, NL, NN)                    \
+    LAIR_HA(8, 64, SRC, GRID, NL, NN) LAIR_HA(16, 32, SRC, GRID, NL, NN)                   \
+    LAIR_HA(16, 64, SRC, GRID, NL, NN) LAIR_HA(16, 128, SRC, GRID, NL, NN)                 \
+    LAIR_HA(32, 64, SRC, GRID, NL, NN) LAIR_HA(32, 128, SRC, GRID, NL, NN)                 \
+    LAIR_HA(32, 256, SRC, GRID, NL, NN) LAIR_HA(64, 128, SRC, GRID, NL, NN)                \
+    LAIR_HA(64, 256, SRC, GRID, NL, NN) LAIR_HA(64, 512, SRC, GRID, NL, NN)
+    {
+        const int hs = HS1;
+        LAIR_HA_ALL(all, g, l1, n1)
+    }
+    if (max_e <= HS1 / 2) return;     // no row can have more distinct columns
+    int32_t *lbig = l1, *nbig = n1;
+    if (HS1 < HS) {
+        const int hs = HS;
+        const RowSrc retry{l1, n1};
+        const unsigned g2 = g < 4096u ? g : 4096u;
+        LAIR_HA_ALL(retry, g2, l2, n2)
+        if (max_e <= HS / 2) return;
+        lbig = l2;
+        nbig = n2;
+    }
+#undef LAIR_HA_ALL
 #undef LAIR_HA
-    if (max_e <= hc) return;     // no row can have more distinct columns
     // wider rows: one 64-lane team per block with a large table, then the merge
-    spgemm_hacc<64, HACC_BIG, 64>(m, RowSrc{l1, n1}, 2048, ap, aj, ax, bp, bj, bx, eoff, cnt,
-                                  tcj, tcx, l2, n2, s);
+    spgemm_hacc<64, HACC_BIG, 64>(m, RowSrc{lbig, nbig}, 2048, ap, aj, ax, bp, bj, bx, eoff,
+                                  cnt, tcj, tcx, l3, n3, s);
     if (max_e <= HACC_BIG / 2) return;
-    LAIR_LAUNCH((k_spgemm_merge<64, 16>), dim3(256), dim3(256), 0, s, RowSrc{l2, n2},
+    LAIR_LAUNCH((k_spgemm_merge<64, 16>), dim3(256), dim3(256), 0, s, RowSrc{l3, n3},
                        ap, aj, ax, bp, bj, bx, eoff, cnt, tcj, tcx, overflow);
     LAIR_LAUNCH_CHECK();
 }

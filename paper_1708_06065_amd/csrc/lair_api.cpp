@@ -279,10 +279,10 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
     st.m = m;
     st.cnt.alloc((size_t)m + 1, s);
     st.eoff.alloc((size_t)m + 1, s);
-    st.work.alloc(2 + 2 * (size_t)m, s);
+    st.work.alloc(4 + 3 * (size_t)m, s);
     st.tot.alloc(2, s);
     st.ctl.alloc(3, s);
-    LAIR_HIP(hipMemsetAsync(st.work.get(), 0, 2 * sizeof(int32_t), s));
+    LAIR_HIP(hipMemsetAsync(st.work.get(), 0, 4 * sizeof(int32_t), s));
     LAIR_HIP(hipMemsetAsync(st.ctl.get(), 0, 3 * sizeof(int64_t), s));
     // products per row: A's indices and B's row pointers
     ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
@@ -293,8 +293,11 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
 
 // st.h must hold the readback of st.tot.  Returns C's longest row (0 when
 // deferred).
+// ratio: products per distinct column expected for C's rows (from a
+// similar product; 0 when unknown), which sizes the hash tables.
 static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, SpgemmState &st,
-                             hipStream_t s, DevArr<int64_t> &tmp, PendingSizes *defer) {
+                             hipStream_t s, DevArr<int64_t> &tmp, PendingSizes *defer,
+                             double ratio = 0.0) {
     const int32_t m = st.m;
     const int64_t etot = st.h[0], emax = st.h[1];
     C.nrows = m;
@@ -309,8 +312,9 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
         // A, the rows of B and the rows of C each touched once
         ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) +
                                            4.0 * (B.nrows + 1));
+        const double mean_e = m ? (double)etot / m : 0.0;
         launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                      B.v.get(), st.eoff.get(), emax, m ? (double)etot / m : 0.0,
+                      B.v.get(), st.eoff.get(), emax, mean_e, ratio > 1.0 ? mean_e / ratio : 0.0,
                       st.cnt.get(), tcj.get(), tcx.get(), st.work.get(), ovp, s);
     }
     C.rp.alloc((size_t)m + 1, s);
@@ -337,8 +341,10 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
 
 // C = A B at once (count, readback, product, sizes).  Returns the longest
 // row of C.
+// c_nnz: C's size when known beforehand (0 if not), which sizes the hash
+// tables.
 static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
-                      DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp) {
+                      DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp, int64_t c_nnz = 0) {
     (void)max_row_a;
     SpgemmState st;
     spgemm_count(A, B, st, s, tmp);
@@ -347,7 +353,8 @@ static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
         rb.add(st.h, st.tot.get(), sizeof(st.h));
         rb.run();
     }
-    return spgemm_finish(A, B, C, st, s, tmp, nullptr);
+    return spgemm_finish(A, B, C, st, s, tmp, nullptr,
+                         c_nnz > 0 ? (double)st.h[0] / (double)c_nnz : 0.0);
 }
 
 static void transpose(const DevCSR &M, DevCSR &T, hipStream_t s,
@@ -548,11 +555,23 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, cnt.get(),
                           nullptr, nullptr, over.get(), Lv.max_row, s);
     Lv.nptr.alloc((size_t)Lv.nc + 1, s);
-    int64_t smax64 = 0;
-    int32_t ov = 0;
-    int64_t nn = scan_counts_i32(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp, &smax64, over.get(),
-                                 &ov);
-    if (ov) fail(LAIR_EUNSUPPORTED, "level %d: a distance-2 neighbourhood merges more than 256 rows", lvl);
+    // distance 1: N_i lies in row i without i, so the C rows' lengths bound
+    // the lists' total and the longest row bounds each list; when that bound
+    // keeps every system within the one-wave LDS kernel, the exact sizes wait
+    // for the local solves' readback instead of a wait of their own
+    const bool defer_nbr = h->str.distance == 1 && Lv.max_row > 0 && Lv.max_row - 1 <= WSMAX;
+    DevArr<int64_t> ntot;
+    int64_t smax64 = 0, nn = 0;
+    if (defer_nbr) {
+        ntot.alloc(2, s);
+        scan_counts_i32_to(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp, ntot.get());
+        nn = std::max<int64_t>(0, Lv.nnzC - Lv.nc);
+        smax64 = Lv.max_row - 1;
+    } else {
+        int32_t ov = 0;
+        nn = scan_counts_i32(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp, &smax64, over.get(), &ov);
+        if (ov) fail(LAIR_EUNSUPPORTED, "level %d: a distance-2 neighbourhood merges more than 256 rows", lvl);
+    }
     Lv.nbr.alloc((size_t)std::max<int64_t>(nn, 1), s);
     launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, nullptr,
@@ -561,7 +580,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.st.s_mean = Lv.nc ? (double)nn / Lv.nc : 0.0;
     Lv.st.s_min = -1;   // filled on demand by lair_level_stats_get
 
-    // R = [Z I]
+    // R = [Z I] (its size an upper bound until the readback when deferred)
     DevCSR &R = Lv.R;
     R.nrows = Lv.nc;
     R.ncols = n;
@@ -627,6 +646,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Readback rb(s);
     p_pend.add(rb);
     rb.add(ap.h, ap.tot.get(), sizeof(ap.h));
+    int64_t hnt[2] = {nn, smax64};
+    if (defer_nbr) rb.add(hnt, ntot.get(), sizeof(hnt));
 
     Lv.flags.alloc((size_t)Lv.nc, s);
     LocalSolveOut out{R.rp.get(), R.cj.get(), R.v.get(), Lv.flags.get()};
@@ -636,6 +657,11 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                                  Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s,
                                  Lv.buckets, &rb);
     p_pend.apply();
+    if (defer_nbr) {
+        R.nnz = hnt[0] + Lv.nc;
+        Lv.st.s_max = (int32_t)hnt[1];
+        Lv.st.s_mean = Lv.nc ? (double)hnt[0] / Lv.nc : 0.0;
+    }
     Lv.st.n_singular = nsing;
     h->n_singular += nsing;
 }
@@ -982,6 +1008,9 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
     }
     h->L.push_back(std::move(L0));
 
+    // products per distinct column of A P and of R (A P) on the level above:
+    // the next level's hash tables are sized from them
+    double ap_ratio = 0.0, k_ratio = 0.0;
     for (int32_t lvl = 0;; ++lvl) {
         Level &Lv = *h->L.back();
         if (h->nsys == 1) {
@@ -1008,7 +1037,7 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         DevCSR AP;
         PendingSizes ap_pend;
         const bool eager = setup_sizes_eager();
-        spgemm_finish(Lv.A, Lv.P, AP, ap_st, s, tmp, eager ? nullptr : &ap_pend);
+        spgemm_finish(Lv.A, Lv.P, AP, ap_st, s, tmp, eager ? nullptr : &ap_pend, ap_ratio);
         std::unique_ptr<Level> nx(new Level());
         nx->n = Lv.nc;
         SpgemmState k_st;
@@ -1020,8 +1049,10 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
             rb.run();
             ap_pend.apply();
         }
+        if (AP.nnz > 0) ap_ratio = (double)ap_st.h[0] / (double)AP.nnz;
         // rows of K are sorted and unique by construction of the product
-        nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr);
+        nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr, k_ratio);
+        if (nx->A.nnz > 0) k_ratio = (double)k_st.h[0] / (double)nx->A.nnz;
         if (h->nsys > 1) {
             nx->seg = Lv.next_seg;
             nx->stopped = Lv.stopped;
@@ -1861,7 +1892,7 @@ static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_d
         }
         DevCSR AP, K;
         spgemm(Lv.A, Lv.max_row, Lv.P, AP, s, tmp);
-        int32_t mr = spgemm(Lv.R, Lv.st.s_max + 1, AP, K, s, tmp);
+        int32_t mr = spgemm(Lv.R, Lv.st.s_max + 1, AP, K, s, tmp, h->L[l + 1]->A.nnz);
         Level &Nx = *h->L[l + 1];
         if (K.nnz != Nx.A.nnz)
             fail(LAIR_EDEVICE, "coarse operator pattern changed on update (level %zu)", l + 1);

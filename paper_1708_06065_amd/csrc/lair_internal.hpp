@@ -229,7 +229,11 @@ struct LocalSolveOut {
     double *r_v;
     int8_t *flags;
 };
-// returns the number of systems solved by least squares
+// Largest local system the one-wave kernel keeps in LDS (larger ones use a
+// global slab).
+constexpr int32_t WSMAX = 64;
+// returns the number of systems solved by least squares.  smax may be an
+// upper bound of the largest system (it selects kernels and tables).
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
@@ -254,15 +258,17 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 // (an upper bound of its length); launch_spgemm writes each row of C,
 // sorted, at its product offset eoff[i] of the staging arrays (tcj, tcx)
 // and its length into cnt; launch_spgemm_compact copies the rows to C
-// (row pointers crp from a scan of cnt).  work: 2 + 2 m int32, the first
-// two zeroed by the caller; *overflow zeroed by the caller.
+// (row pointers crp from a scan of cnt).  work: 4 + 3 m int32, the first
+// four zeroed by the caller; *overflow zeroed by the caller.  mean_c_hint:
+// an estimate of the distinct columns per row of C (0: none), which sizes
+// the first pass's tables.
 void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
                        int32_t *e, hipStream_t s);
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
                    const int32_t *bp, const int32_t *bj, const double *bx,
-                   const int64_t *eoff, int64_t max_e, double mean_e, int32_t *cnt,
-                   int32_t *tcj, double *tcx, int32_t *work, int32_t *overflow,
-                   hipStream_t s);
+                   const int64_t *eoff, int64_t max_e, double mean_e, double mean_c_hint,
+                   int32_t *cnt, int32_t *tcj, double *tcx, int32_t *work,
+                   int32_t *overflow, hipStream_t s);
 void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
                            const int32_t *tcj, const double *tcx, int32_t *cj, double *cx,
                            double mean_c, hipStream_t s);
