@@ -139,11 +139,77 @@ __global__ void k_scan_add(OUT *out, int64_t n, const int64_t *bs, const int64_t
     if (i == 0) out[n] = (OUT)(*total);
 }
 
+// Short inputs in one launch: one block of SCAN1_BS threads, each thread
+// scanning ipt consecutive entries (read twice: sums, then offsets), the
+// waves' sums combined through LDS.
+constexpr int SCAN1_BS = 1024;
+constexpr int64_t SCAN1_MAX = 16 * SCAN1_BS;
+
+template <class F, class OUT>
+__global__ void __launch_bounds__(SCAN1_BS)
+k_scan_one(F f, int64_t n, int ipt, OUT *out, int64_t *tot) {
+    __shared__ int64_t s_sum[SCAN1_BS / 64], s_max[SCAN1_BS / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t b0 = (int64_t)t * ipt;
+    int64_t sum = 0, mx = 0;
+    for (int j = 0; j < ipt; ++j) {
+        const int64_t i = b0 + j;
+        if (i < n) {
+            const int64_t v = f(i);
+            sum += v;
+            mx = v > mx ? v : mx;
+        }
+    }
+    int64_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(inc, o);
+        if (lane >= o) inc += u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(mx, o);
+        mx = u > mx ? u : mx;
+    }
+    if (lane == 63) s_sum[w] = inc;
+    if (lane == 0) s_max[w] = mx;
+    __syncthreads();
+    int64_t pre = inc - sum, total = 0, big = 0;
+    for (int k = 0; k < SCAN1_BS / 64; ++k) {
+        if (k < w) pre += s_sum[k];
+        total += s_sum[k];
+        big = s_max[k] > big ? s_max[k] : big;
+    }
+    for (int j = 0; j < ipt; ++j) {
+        const int64_t i = b0 + j;
+        if (i < n) {
+            out[i] = (OUT)pre;
+            pre += f(i);
+        }
+    }
+    if (t == 0) {
+        out[n] = (OUT)total;
+        tot[0] = total;
+        tot[1] = big;
+    }
+}
+
 // Launches only: out[0..n] and tot[0] = total, tot[1] = largest value on
 // the device.
 template <class F, class OUT>
 static int64_t *scan_launch(F f, OUT *out, int64_t n, hipStream_t s, DevArr<int64_t> &tmp,
                             int64_t *tot_out = nullptr) {
+    if (n <= SCAN1_MAX) {
+        int64_t *tot = tot_out;
+        if (!tot) {
+            tmp.ensure(2, s);
+            tot = tmp.get();
+        }
+        const int ipt = (int)((n + SCAN1_BS - 1) / SCAN1_BS);
+        LAIR_LAUNCH((k_scan_one<F, OUT>), dim3(1), dim3(SCAN1_BS), 0, s, f, n, ipt, out, tot);
+        LAIR_LAUNCH_CHECK();
+        return tot;
+    }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
     tmp.ensure((size_t)2 * nb + 2, s);

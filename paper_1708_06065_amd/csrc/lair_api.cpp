@@ -264,9 +264,14 @@ static bool setup_sizes_eager() {
 // readback; otherwise they are read at once.
 struct SpgemmState {
     int32_t m = 0;
-    DevArr<int32_t> cnt, work;
+    DevArr<int32_t> cnt;
     DevArr<int64_t> eoff, tot;       // tot: [0] products, [1] most in a row
-    DevArr<int64_t> ctl;             // [0..2] C's sizes or [2] the overflow flag
+    // work: [0..5] three int64 slots (C's sizes, or [2] the overflow flag),
+    // then the product's retry counters and lists; the head is zeroed once
+    DevArr<int32_t> work;
+    static constexpr int HEAD = 6;
+    int64_t *ctl() { return reinterpret_cast<int64_t *>(work.get()); }
+    int32_t *lists() { return work.get() + HEAD; }
     int64_t h[2] = {0, 0};
 };
 
@@ -279,11 +284,9 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
     st.m = m;
     st.cnt.alloc((size_t)m + 1, s);
     st.eoff.alloc((size_t)m + 1, s);
-    st.work.alloc(4 + 3 * (size_t)m, s);
+    st.work.alloc(SpgemmState::HEAD + 4 + 3 * (size_t)m, s);
     st.tot.alloc(2, s);
-    st.ctl.alloc(3, s);
-    LAIR_HIP(hipMemsetAsync(st.work.get(), 0, 4 * sizeof(int32_t), s));
-    LAIR_HIP(hipMemsetAsync(st.ctl.get(), 0, 3 * sizeof(int64_t), s));
+    LAIR_HIP(hipMemsetAsync(st.work.get(), 0, (SpgemmState::HEAD + 4) * sizeof(int32_t), s));
     // products per row: A's indices and B's row pointers
     ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
                                         8.0 * (B.nrows + 1) + 12.0 * m);
@@ -302,8 +305,8 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
     const int64_t etot = st.h[0], emax = st.h[1];
     C.nrows = m;
     C.ncols = B.ncols;
-    int32_t *ovp = reinterpret_cast<int32_t *>(st.ctl.get() + 2);
-    if (defer) defer->arm_at(st.ctl.get(), &C, "sparse product row with more than 1024 terms");
+    int32_t *ovp = reinterpret_cast<int32_t *>(st.ctl() + 2);
+    if (defer) defer->arm_at(st.ctl(), &C, "sparse product row with more than 1024 terms");
     DevArr<int32_t> tcj;
     DevArr<double> tcx;
     tcj.alloc((size_t)std::max<int64_t>(etot, 1), s);
@@ -315,7 +318,7 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
         const double mean_e = m ? (double)etot / m : 0.0;
         launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
                       B.v.get(), st.eoff.get(), emax, mean_e, ratio > 1.0 ? mean_e / ratio : 0.0,
-                      st.cnt.get(), tcj.get(), tcx.get(), st.work.get(), ovp, s);
+                      st.cnt.get(), tcj.get(), tcx.get(), st.lists(), ovp, s);
     }
     C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
