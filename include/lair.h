@@ -119,8 +119,8 @@ typedef struct lair_options {
  * kernel eagerly instead.  Iterations are also eager while the profiler
  * times a cycle category. */
 #define LAIR_FLAG_NO_GRAPH 1
-/* A single system's cycle runs, on its large sparse levels (n >= 65536 and
- * at most 16 entries per row on average, a prefix of the hierarchy), on
+/* A single system's cycle runs, on its large levels (n >= 65536, a prefix
+ * of the hierarchy), on
  * copies of A_l, R_l and P_l renumbered with each level's F-points first and
  * its C-points after them (both ascending), so that the F and C sweeps of
  * FF C-relaxation read and write contiguous blocks; every row keeps its

@@ -799,13 +799,12 @@ static void level_stats_and_cc(lair_hierarchy *h) {
 }
 
 // Split-ordered copies of the cycle operators (single systems).  A level is
-// renumbered when it is large and sparse (its F and C sweeps then move
-// mostly vector data, half of it wasted on the other kind's rows in the
-// natural ordering); the renumbered levels form a prefix of the hierarchy
-// and the coarsest level keeps its natural ordering (its dense solve).
-// Mixed precision keeps float values only.
+// renumbered when it is large (in the natural ordering its F and C sweeps
+// read and write the vectors line by line for half of the data); the
+// renumbered levels form a prefix of the hierarchy and the coarsest level
+// keeps its natural ordering (its dense solve).  Mixed precision keeps
+// float values only.
 constexpr int32_t SPLIT_MIN_ROWS = 65536;
-constexpr double SPLIT_MAX_MEAN_ROW = 16.0;
 
 static void build_split(lair_hierarchy *h, hipStream_t s) {
     const size_t nL = h->L.size();
@@ -815,8 +814,7 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
     bool prev = allowed;
     for (size_t l = 0; l < nL; ++l) {
         Level &Lv = *h->L[l];
-        const bool big = Lv.n >= SPLIT_MIN_ROWS &&
-                         (double)Lv.A.nnz <= SPLIT_MAX_MEAN_ROW * (double)Lv.n;
+        const bool big = Lv.n >= SPLIT_MIN_ROWS;
         Lv.split = prev && l + 1 < nL && (all || big);
         prev = Lv.split;
     }
