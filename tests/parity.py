@@ -55,6 +55,13 @@ def compare_level(h, l, theta=0.25, kind=O.SOC_ABS, distance=1,
     cpts, nptr, nbr = O.neighbourhoods(A, sm_o, cf_o, distance)
     assert np.array_equal(nptr.astype(np.int32), h.export(l, "nbr_ptr"))
     assert np.array_equal(nbr.astype(np.int32), h.export(l, "nbr"))
+    # the level's statistics (sizes the setup may first bound, then reads)
+    st = h.level_stats(l)
+    sizes = np.diff(np.asarray(nptr, dtype=np.int64))
+    assert st["nc"] == len(cpts) and st["nnz_R"] == int(sizes.sum()) + len(cpts)
+    if len(sizes):
+        assert st["s_max"] == int(sizes.max()), "largest neighbourhood differs at level %d" % l
+        assert abs(st["s_mean"] - sizes.mean()) <= 1e-12 * max(1.0, sizes.mean())
     z, flags = O.local_solves(A, cpts, nptr, nbr)
     assert np.array_equal(flags.astype(np.int8), h.export(l, "flags"))
     R = O.restriction(n, cpts, nptr, nbr, z)

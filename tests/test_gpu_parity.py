@@ -152,6 +152,49 @@ def test_direct_interp_levelwise_and_iterations(lair, case):
     assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("m", [128, 129])
+def test_scan_size_boundary_levelwise(lair, m):
+    """n = 16,384 and 16,641 on level 0: the setup's prefix sums over n take
+    the one-launch path and the tiled path; every level against the oracle
+    and the same iteration count (direct P, a diffusive case with levels of
+    all sizes below)."""
+    _say("case: scan size boundary, m =", m)
+    w = W.adr_2d(m, 1.0, 0.7, 0.0)
+    A = O.csr(w["rowptr"], w["col"], w["val"])
+    b = np.random.default_rng(2).standard_normal(A.shape[0])
+    H = O.setup(A, interp=O.INTERP_DIRECT)
+    cfl = oracle_cf_levels(H)
+    h = lair.setup(A.indptr, A.indices, A.data, cf_levels=cfl, interp="direct")
+    assert h.nlevels == H.nlevels
+    for l in range(h.nlevels - 1):
+        compare_level(h, l, interp=O.INTERP_DIRECT, cf=cfl[l])
+    x, info, xo, ito, hist = _solve_both(lair, h, H, b)
+    assert info["converged"] and info["iters"] == ito
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    h.free()
+
+
+def test_large_levels_levelwise(lair):
+    """64^3 implicit Euler step (262,144 rows): levels 1 and 2 have 65,536
+    rows or more, so their products size the hash tables from the level
+    above and redo the rows that overflow, and levels 0 to 2 run the cycle
+    renumbered.  Every level against the oracle, same iteration count."""
+    _say("case: 64^3 levelwise")
+    w = W.implicit_euler_adr_3d(m=64, nrhs=1)
+    A = O.csr(w["rowptr"], w["col"], w["val"])
+    H = O.setup(A, interp=O.INTERP_DIRECT)
+    cfl = oracle_cf_levels(H)
+    h = lair.setup(A.indptr, A.indices, A.data, cf_levels=cfl, interp="direct")
+    assert h.nlevels == H.nlevels
+    for l in range(h.nlevels - 1):
+        compare_level(h, l, interp=O.INTERP_DIRECT, cf=cfl[l])
+    x, info, xo, ito, hist = _solve_both(lair, h, H, w["rhs"])
+    _say("  iters gpu", info["iters"], "oracle", ito)
+    assert info["converged"] and info["iters"] == ito
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    h.free()
+
+
 def test_multi_rhs_equals_single(lair):
     import torch
     w = W.implicit_euler_adr_3d(m=14, nrhs=16)
