@@ -1850,12 +1850,41 @@ void launch_compact_one_point(int32_t n, const int32_t *pcol,
 // missing from P_i is lumped into the diagonal.  Columns follow A's order,
 // which is increasing in coarse index.  One team of T lanes per row: the
 // sums are team reductions and the fill compacts in order with a ballot.
+// Direct weights of F row i in the row's order: w_ij = -(alpha or beta) a_ij / d
+// for the strong C-points j (alpha for negative entries, beta otherwise).
+template <int T>
+__device__ __forceinline__ void interp_direct_write(int32_t i, int lo, int hi, int lane,
+                                                    const int32_t *cj, const double *v,
+                                                    const uint8_t *sm, const int8_t *cf,
+                                                    const int32_t *cidx, int o, double alpha,
+                                                    double beta, double d, int32_t *pcj,
+                                                    double *pv) {
+    for (int p0 = lo; p0 < hi; p0 += T) {
+        int p = p0 + lane;
+        int j = -1;
+        double a = 0.0;
+        bool take = false;
+        if (p < hi) {
+            j = cj[p];
+            a = v[p];
+            take = (j != i) && sm[p] && cf[j] == 1;
+        }
+        uint64_t bits = team_bits<T>(take);
+        int before = __popcll(bits & ((1ull << lane) - 1ull));
+        if (take) {
+            pcj[o + before] = cidx[j];
+            pv[o + before] = -(a < 0.0 ? alpha : beta) * a / d;
+        }
+        o += __popcll(bits);
+    }
+}
+
 template <int T>
 __global__ void __launch_bounds__(256)
 k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
                 const double *v, const uint8_t *sm, const int8_t *cf,
                 const int32_t *cidx, bool fill, int32_t *cnt,
-                const int32_t *prp, int32_t *pcj, double *pv) {
+                const int32_t *prp, int32_t *pcj, double *pv, double *coef) {
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
     int lane = (int)(gt % T);
@@ -1868,6 +1897,15 @@ k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
         return;
     }
     const int lo = rp[i], hi = rp[i + 1];
+    if (fill && coef) {
+        // the sizing pass kept alpha, beta and the lumped diagonal (0: no row)
+        const double alpha = coef[3 * (int64_t)i], beta = coef[3 * (int64_t)i + 1];
+        const double d = coef[3 * (int64_t)i + 2];
+        if (d == 0.0) return;
+        interp_direct_write<T>(i, lo, hi, lane, cj, v, sm, cf, cidx, prp[i], alpha, beta, d,
+                               pcj, pv);
+        return;
+    }
     double diag = 0.0, sn = 0.0, sp = 0.0, pn = 0.0, pp = 0.0;
     int k = 0;
     for (int p = lo + lane; p < hi; p += T) {
@@ -1890,45 +1928,34 @@ k_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
     if (pn == 0.0) d += sn;
     if (pp == 0.0) d += sp;
     bool empty = (k == 0 || d == 0.0);
+    double alpha = (pn != 0.0) ? sn / pn : 0.0;
+    double beta = (pp != 0.0) ? sp / pp : 0.0;
     if (!fill) {
-        if (lane == 0) cnt[i] = empty ? 0 : k;
+        if (lane == 0) {
+            cnt[i] = empty ? 0 : k;
+            if (coef) {
+                coef[3 * (int64_t)i] = alpha;
+                coef[3 * (int64_t)i + 1] = beta;
+                coef[3 * (int64_t)i + 2] = empty ? 0.0 : d;
+            }
+        }
         return;
     }
     if (empty) return;
-    double alpha = (pn != 0.0) ? sn / pn : 0.0;
-    double beta = (pp != 0.0) ? sp / pp : 0.0;
-    int o = prp[i];
-    for (int p0 = lo; p0 < hi; p0 += T) {
-        int p = p0 + lane;
-        int j = -1;
-        double a = 0.0;
-        bool take = false;
-        if (p < hi) {
-            j = cj[p];
-            a = v[p];
-            take = (j != i) && sm[p] && cf[j] == 1;
-        }
-        uint64_t bits = team_bits<T>(take);
-        int before = __popcll(bits & ((1ull << lane) - 1ull));
-        if (take) {
-            pcj[o + before] = cidx[j];
-            pv[o + before] = -(a < 0.0 ? alpha : beta) * a / d;
-        }
-        o += __popcll(bits);
-    }
+    interp_direct_write<T>(i, lo, hi, lane, cj, v, sm, cf, cidx, prp[i], alpha, beta, d, pcj, pv);
 }
 
 void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
                           const double *v, const uint8_t *smask,
                           const int8_t *cf, const int32_t *cidx, bool fill,
                           int32_t *cnt, const int32_t *prp, int32_t *pcj,
-                          double *pv, double mean_len, hipStream_t s) {
+                          double *pv, double mean_len, hipStream_t s, double *coef) {
     int t = team_for_mean(mean_len);
     if (t > 16) t = 16;
 #define LAIR_ID(TT)                                                              \
     LAIR_LAUNCH(k_interp_direct<TT>, dim3(blocks_for((int64_t)n * TT, 256)), \
                        dim3(256), 0, s, n, rp, cj, v, smask, cf, cidx, fill, cnt, prp, \
-                       pcj, pv)
+                       pcj, pv, coef)
     switch (t) {
         case 2: LAIR_ID(2); break;
         case 4: LAIR_ID(4); break;

@@ -626,11 +626,13 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     } else {
         DevArr<int32_t> pc;
         pc.alloc((size_t)n, s);
+        DevArr<double> coef;
+        coef.alloc(3 * (size_t)std::max(n, 1), s);
         {
             ProfScope ps("interp", s, 6.0 * A.nnz + 9.0 * n);
             launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
                                  Lv.cf.get(), Lv.cidx.get(), false, pc.get(), nullptr, nullptr,
-                                 nullptr, mean, s);
+                                 nullptr, mean, s, coef.get());
         }
         scan_counts_i32_to(pc.get(), P.rp.get(), n, s, tmp, p_pend.tot());
         if (eager) p_pend.settle(s);
@@ -641,7 +643,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
             ProfScope ps("interp", s, 14.0 * A.nnz + 13.0 * n + 12.0 * P.nnz);
             launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
                                  Lv.cf.get(), Lv.cidx.get(), true, nullptr, P.rp.get(),
-                                 P.cj.get(), P.v.get(), mean, s);
+                                 P.cj.get(), P.v.get(), mean, s, coef.get());
         }
     }
     // products of A P counted now, read with the local solves

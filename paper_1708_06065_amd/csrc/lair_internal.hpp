@@ -249,11 +249,16 @@ void launch_interp_one_point(int32_t n, const int32_t *rp, const int32_t *cj,
 void launch_compact_one_point(int32_t n, const int32_t *pcol,
                               const int32_t *prp, int32_t *pcj, double *pv,
                               hipStream_t s);
+// Direct interpolation: fill = false counts each row's entries into cnt,
+// fill = true writes them.  coef (3 n doubles, optional): the counting pass
+// keeps each F row's alpha, beta and lumped diagonal there and the filling
+// pass reuses them instead of summing the row again.
 void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
                           const double *v, const uint8_t *smask,
                           const int8_t *cf, const int32_t *cidx, bool fill,
                           int32_t *cnt, const int32_t *prp, int32_t *pcj,
-                          double *pv, double mean_len, hipStream_t s);
+                          double *pv, double mean_len, hipStream_t s,
+                          double *coef = nullptr);
 // C = A B in three steps: launch_prod_count gives the products of every row
 // (an upper bound of its length); launch_spgemm writes each row of C,
 // sorted, at its product offset eoff[i] of the staging arrays (tcj, tcx)
