@@ -27,6 +27,8 @@ Steps and where the paper defines them:
   solve             stationary iteration on the V-cycle to a relative
                     residual tolerance
   cycle_transpose   the exact adjoint of ``cycle`` (for gradients)
+  fgmres            flexible GMRES(m) with one V-cycle as the right
+                    preconditioner (the outer solver of Sec. 4's results)
   update_diag       a new diagonal on a kept hierarchy structure: Eq. (system)
                     solves, interpolation weights and Sec. 2.1 Galerkin
                     products recomputed on the same neighbourhoods, splittings
@@ -494,6 +496,83 @@ def solve_transpose(H, g, rtol=1e-10, maxit=200, omega=1.0):
         it += 1
         hist.append(np.linalg.norm(g - At @ lam))
     return lam, it, np.array(hist)
+
+
+# --------------------------------------------------------------------------
+# Flexible GMRES(m), right preconditioned (Saad 1993): the Krylov solver the
+# paper wraps its cycles in.  Arnoldi by classical Gram-Schmidt applied
+# twice, the small least-squares problem by Givens rotations.
+# --------------------------------------------------------------------------
+
+def fgmres(A, b, precond, x0=None, rtol=1e-10, maxit=200, restart=20):
+    """Solve A x = b; precond(v) returns an approximation of A^{-1} v.
+
+    One iteration is one Arnoldi step (one preconditioner application).
+    Stops when the residual estimate |g_{j+1}| <= rtol ||b|| or after maxit
+    steps; after each cycle of at most ``restart`` steps the true residual
+    decides whether to restart.  Returns (x, iterations, history of true
+    residual norms at the restarts, estimates at every step).
+    """
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=float)
+    nb = np.linalg.norm(b)
+    tol = rtol * nb
+    r = b - A @ x
+    beta = np.linalg.norm(r)
+    hist = [beta]
+    est = [beta]
+    it = 0
+    while beta > tol and it < maxit:
+        m = restart
+        V = np.zeros((n, m + 1))
+        Z = np.zeros((n, m))
+        Hh = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[:, 0] = r / beta
+        k = 0
+        for j in range(m):
+            Z[:, j] = precond(V[:, j])
+            w = A @ Z[:, j]
+            h = np.zeros(j + 1)
+            for _ in range(2):                      # Gram-Schmidt, twice
+                c = V[:, :j + 1].T @ w
+                w = w - V[:, :j + 1] @ c
+                h += c
+            hn = np.linalg.norm(w)
+            Hh[:j + 1, j] = h
+            Hh[j + 1, j] = hn
+            V[:, j + 1] = w / hn if hn > 0 else 0.0
+            for i in range(j):                      # earlier rotations
+                t = cs[i] * Hh[i, j] + sn[i] * Hh[i + 1, j]
+                Hh[i + 1, j] = -sn[i] * Hh[i, j] + cs[i] * Hh[i + 1, j]
+                Hh[i, j] = t
+            d = math.hypot(Hh[j, j], Hh[j + 1, j])
+            cs[j], sn[j] = (Hh[j, j] / d, Hh[j + 1, j] / d) if d > 0 else (1.0, 0.0)
+            Hh[j, j] = d
+            Hh[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            est.append(abs(g[j + 1]))
+            if abs(g[j + 1]) <= tol or it >= maxit:
+                break
+        y = sla.solve_triangular(Hh[:k, :k], g[:k])
+        x = x + Z[:, :k] @ y
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+        hist.append(beta)
+    return x, it, np.array(hist), np.array(est)
+
+
+def fgmres_cycle(H, b, x0=None, rtol=1e-10, maxit=200, restart=20, omega=1.0):
+    """FGMRES(m) on level 0 with one V-cycle from zero as the preconditioner."""
+    A = H.levels[0].A
+    return fgmres(A, b, lambda v: cycle(H, v, np.zeros_like(v), 0, omega), x0, rtol,
+                  maxit, restart)
 
 
 def convergence_factor(hist):

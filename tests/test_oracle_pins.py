@@ -637,3 +637,74 @@ def test_update_diag_chain_still_solves_in_one_cycle():
     x = O.cycle(H, b, np.zeros(n))
     xs = spla.spsolve(A_new.tocsc(), b)
     assert np.abs(x - xs).max() <= 1e-12 * np.abs(xs).max()
+
+
+# ----------------------------------------------------------------- FGMRES
+
+def _nonsym(n, seed):
+    rng = np.random.default_rng(seed)
+    A = 4.0 * np.eye(n) + 0.6 * rng.standard_normal((n, n))
+    return A, rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fgmres_minimises_over_the_krylov_space(seed):
+    """Unpreconditioned, no restart: after k steps the residual is the least
+    one over x0 + K_k(A, r0), here found by an independent least-squares fit
+    on an orthonormal basis of the Krylov matrix."""
+    A, b = _nonsym(24, seed)
+    x0 = np.random.default_rng(seed + 10).standard_normal(24)
+    r0 = b - A @ x0
+    for k in range(1, 9):
+        xk, it, _, _ = O.fgmres(A, b, lambda v: v, x0=x0, rtol=0.0, maxit=k, restart=50)
+        assert it == k
+        K = np.empty((24, k))
+        K[:, 0] = r0
+        for j in range(1, k):
+            K[:, j] = A @ K[:, j - 1]
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(A @ Q, r0, rcond=None)
+        best = np.linalg.norm(r0 - A @ Q @ y)
+        got = np.linalg.norm(b - A @ xk)
+        assert abs(got - best) <= 1e-9 * np.linalg.norm(r0)
+
+
+def test_fgmres_estimate_is_the_true_residual():
+    A, b = _nonsym(20, 3)
+    for k in (1, 4, 9):
+        xk, _, _, est = O.fgmres(A, b, lambda v: v, rtol=0.0, maxit=k, restart=30)
+        assert abs(est[-1] - np.linalg.norm(b - A @ xk)) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_fgmres_exact_preconditioner_one_step():
+    A, b = _nonsym(16, 4)
+    x, it, hist, _ = O.fgmres(A, b, lambda v: np.linalg.solve(A, v), rtol=1e-12)
+    assert it == 1
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_fgmres_restart_is_a_fresh_start():
+    """GMRES(3) for 9 steps equals three GMRES(3) runs of 3 steps, each
+    starting from the last iterate."""
+    A, b = _nonsym(18, 5)
+    x9, it, _, _ = O.fgmres(A, b, lambda v: v, rtol=0.0, maxit=9, restart=3)
+    assert it == 9
+    x = np.zeros(18)
+    for _ in range(3):
+        x, _, _, _ = O.fgmres(A, b, lambda v: v, x0=x, rtol=0.0, maxit=3, restart=3)
+    assert np.linalg.norm(x9 - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_fgmres_cycle_no_slower_than_stationary():
+    """With the V-cycle as a fixed preconditioner B, the k-th FGMRES iterate
+    minimises the residual over x0 + B K_k(A B, r0), which holds the k-th
+    stationary iterate: never more iterations to the same tolerance."""
+    w = W.workload_c4(24)
+    A = (O.csr(w["rowptr"], w["col"], w["val"]) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    H = O.setup(A, interp=O.INTERP_DIRECT)
+    b = w["rhs"]
+    xs, its, _ = O.solve(H, b, rtol=1e-10)
+    xg, itg, hist, _ = O.fgmres_cycle(H, b, rtol=1e-10, restart=20)
+    assert itg <= its
+    assert np.linalg.norm(b - A @ xg) <= 1e-10 * np.linalg.norm(b)
