@@ -183,6 +183,24 @@ lair_status lair_solve(lair_hierarchy *h, const double *b, double *x,
                        int32_t nrhs, double rtol, int32_t maxit,
                        lair_info *info, void *stream);
 
+/* Flexible GMRES(restart) on A x = b with one V-cycle from zero as the
+ * right preconditioner: the Krylov solver around the cycle behind the
+ * paper's results (Sec. 4; flexible GMRES after Saad, 1993).  Arnoldi by
+ * classical Gram-Schmidt applied twice, the least-squares problem by Givens
+ * rotations.  Every right-hand side (nrhs in 1, 2, 4, 8, 16, 32, interleaved
+ * as for lair_solve) has its own Krylov space; it stops when its residual
+ * estimate reaches rtol ||b||_2, and each cycle of `restart` steps (1..64)
+ * ends with the true residual, which decides whether to restart.  x
+ * (device, in/out) is the initial guess.  One iteration is one Arnoldi step
+ * (one V-cycle); info->iters is the largest count over the right-hand
+ * sides, info->relres the largest true relative residual at return.  The
+ * call allocates 2 restart + 2 device vectors of n x nrhs doubles and
+ * returns them to the library's cache.  Single systems only (EUNSUPPORTED
+ * for a batch); ENOCONV when maxit is reached first (x = last iterate). */
+lair_status lair_solve_fgmres(lair_hierarchy *h, const double *b, double *x,
+                              int32_t nrhs, double rtol, int32_t maxit,
+                              int32_t restart, lair_info *info, void *stream);
+
 /* Same for the transposed system A^T lam = g with the transposed cycle
  * (pre-relaxation C, F, F on A^T; restriction P^T; interpolation R^T), the
  * exact adjoint of lair_cycle.  Used for gradients. */

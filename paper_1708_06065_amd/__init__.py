@@ -158,6 +158,24 @@ class Hierarchy:
         d["converged"] = st == L.LAIR_OK
         return x, d
 
+    def solve_fgmres(self, b, x=None, rtol=1e-10, maxit=200, restart=20, stream=None,
+                     raise_on_noconv=False):
+        """Flexible GMRES(restart) with one V-cycle as the preconditioner.
+        Returns (x, info dict); iters counts Arnoldi steps (V-cycles)."""
+        torch = _torch()
+        if x is None:
+            x = torch.zeros_like(b)
+        info = L.Info()
+        st = L.load().lair_solve_fgmres(self.handle, _dev_ptr(b, torch.float64, "b"),
+                                        _dev_ptr(x, torch.float64, "x"), self._nrhs(b),
+                                        float(rtol), int(maxit), int(restart),
+                                        ctypes.byref(info), _stream_ptr(stream))
+        if st != L.LAIR_OK and (st != L.LAIR_ENOCONV or raise_on_noconv):
+            L.check(st, "lair_solve_fgmres")
+        d = info.as_dict()
+        d["converged"] = st == L.LAIR_OK
+        return x, d
+
     def update_diag(self, diag, stream=None):
         """New diagonal of A (NumPy array or CUDA float64 tensor of n values):
         same structure, values rebuilt."""

@@ -1536,6 +1536,213 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     return relmax <= rtol ? LAIR_OK : LAIR_ENOCONV;
 }
 
+// Flexible GMRES(m), right preconditioned (Saad 1993), with one V-cycle from
+// zero as the preconditioner: the outer solver of the paper's results
+// (Sec. 4).  Each right-hand side has its own Krylov space, Hessenberg
+// matrix and Givens rotations (host), in shared device bases V (m + 1
+// vectors) and Z (m vectors) of n x nrhs doubles in the natural ordering.
+// Arnoldi: classical Gram-Schmidt applied twice.  A right-hand side whose
+// residual estimate reaches rtol ||b|| is frozen (its next basis vectors are
+// zero) and updated with its own number of steps; a cycle of m steps ends
+// with the true residual, which decides whether to restart.
+static lair_status solve_fgmres_impl(lair_hierarchy *h, const double *b, double *x,
+                                     int32_t nrhs, double rtol, int32_t maxit, int32_t m,
+                                     lair_info *info, hipStream_t s) {
+    auto t0 = Clock::now();
+    check_solve_args(h, b, x, rtol, maxit);
+    check_nrhs(h, nrhs);
+    if (h->batch) fail(LAIR_EUNSUPPORTED, "FGMRES is for a single system");
+    if (m < 1 || m > 64) fail(LAIR_EINVAL, "restart must be in [1, 64] (got %d)", m);
+    ensure_vectors(h, nrhs, s);
+    Level &L0 = *h->L[0];
+    const int64_t n = L0.n;
+    const int32_t R = nrhs;
+    const int64_t nv = n * R;
+    const bool mixed = h->opt.precision == LAIR_MIXED;
+    const bool split = L0.split;
+    const double *bb = b;
+    if (h->opt.block_size > 0) {
+        op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
+                       h->bscaled.get(), nrhs, s);
+        bb = h->bscaled.get();
+    }
+    CsrView<double> A0 = view<double>(L0.A, L0.team_A);
+    DevArr<double> V, Z, w, coef, dots, partial, scale;
+    V.alloc((size_t)(m + 1) * nv, s);
+    Z.alloc((size_t)m * nv, s);
+    w.alloc((size_t)nv, s);
+    coef.alloc((size_t)(m + 1) * R, s);
+    // dots: both Gram-Schmidt passes' coefficients, then |w|^2
+    const size_t HOFF = (size_t)(m + 1) * R;
+    dots.alloc(2 * HOFF + R, s);
+    partial.alloc((size_t)kry_dot_blocks(nv) * (m + 1) * R, s);
+    scale.alloc((size_t)R, s);
+    double *Vp = V.get(), *Zp = Z.get();
+    auto Vk = [&](int k) { return Vp + (int64_t)k * nv; };
+    auto Zk = [&](int k) { return Zp + (int64_t)k * nv; };
+    // z = B v: one V-cycle from zero, in the cycle's ordering and precision
+    auto precond = [&](const double *v, double *z) {
+        if (mixed) {
+            if (split) op_cast_f32_rows(v, h->r0_32.get(), L0.iperm.get(), n, R, s);
+            else op_cast_f32(v, h->r0_32.get(), nv, s);
+            vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, R, s);
+            op_fill<double>(z, 0.0, nv, s);
+            if (split) op_axpy_f32_rows(z, h->e32.get(), L0.iperm.get(), n, R, s);
+            else op_axpy_f32(z, h->e32.get(), nv, s);
+        } else if (split) {
+            op_permute_rows(n, R, L0.perm.get(), v, h->bsplit.get(), true, s);
+            vcycle<double>(h, 0, h->bsplit.get(), h->xsplit.get(), true, nullptr, R, s);
+            op_permute_rows(n, R, L0.perm.get(), h->xsplit.get(), z, false, s);
+        } else {
+            vcycle<double>(h, 0, v, z, true, nullptr, R, s);
+        }
+    };
+    auto upload = [&](double *dev, const std::vector<double> &hv) {
+        double *st = (double *)pinned_upload(sizeof(double) * hv.size());
+        memcpy(st, hv.data(), sizeof(double) * hv.size());
+        LAIR_HIP(hipMemcpyAsync(dev, st, sizeof(double) * hv.size(), hipMemcpyHostToDevice, s));
+        LAIR_HIP(hipStreamSynchronize(s));     // the staging area is reused
+    };
+    // r = b - A x into V_0 and its norms
+    auto true_residual = [&](std::vector<double> &beta) {
+        op_residual<double>(A0, bb, x, Vk(0), R, s);
+        op_mdot(n, R, Vk(0), nv, 1, Vk(0), partial.get(), dots.get(), s);
+        read_norms(dots.get(), R, s, beta);
+    };
+    std::vector<double> nb, beta, r_first;
+    norms_host(h, bb, R, s, nb);
+    std::vector<double> tol((size_t)R);
+    for (int32_t q = 0; q < R; ++q) tol[q] = rtol * nb[q];
+    true_residual(beta);
+    r_first = beta;
+    std::vector<int32_t> its((size_t)R, 0);
+    const size_t H1 = (size_t)m + 1;
+    std::vector<double> Hh(H1 * m * R), cs((size_t)m * R), sn((size_t)m * R), g(H1 * R);
+    std::vector<double> hc(2 * HOFF + R), sc((size_t)R), cf((size_t)(m + 1) * R);
+    std::vector<int32_t> kq((size_t)R);
+    std::vector<char> act((size_t)R);
+    int32_t it = 0;
+    for (;;) {
+        bool any = false;
+        for (int32_t q = 0; q < R; ++q) {
+            act[q] = !(beta[q] <= tol[q]);
+            any = any || act[q];
+        }
+        if (!any || it >= maxit) break;
+        // V_0 = r / beta for the right-hand sides still iterated
+        for (int32_t q = 0; q < R; ++q) {
+            sc[q] = act[q] ? 1.0 / beta[q] : 0.0;
+            kq[q] = 0;
+            g[q] = act[q] ? beta[q] : 0.0;
+            for (size_t i = 1; i < H1; ++i) g[i * R + q] = 0.0;
+        }
+        upload(scale.get(), sc);
+        op_scale_rhs(n, R, Vk(0), scale.get(), Vk(0), s);
+        for (int j = 0; j < m; ++j) {
+            precond(Vk(j), Zk(j));
+            op_spmv<double>(A0, Zk(j), w.get(), R, false, s);
+            // Gram-Schmidt twice: c = V^T w, w -= V c; h = c1 + c2
+            for (int pass = 0; pass < 2; ++pass) {
+                double *cd = dots.get() + (size_t)pass * HOFF;
+                op_mdot(n, R, Vp, nv, j + 1, w.get(), partial.get(), cd, s);
+                op_maxpy(n, R, Vp, nv, j + 1, cd, w.get(), s);
+            }
+            op_mdot(n, R, w.get(), nv, 1, w.get(), partial.get(), dots.get() + 2 * HOFF, s);
+            {
+                Readback rb(s);
+                rb.add(hc.data(), dots.get(), sizeof(double) * (j + 1) * R);
+                rb.add(hc.data() + HOFF, dots.get() + HOFF, sizeof(double) * (j + 1) * R);
+                rb.add(hc.data() + 2 * HOFF, dots.get() + 2 * HOFF, sizeof(double) * R);
+                rb.run();
+            }
+            for (int i = 0; i <= j; ++i)
+                for (int32_t q = 0; q < R; ++q)
+                    Hh[((size_t)i * m + j) * R + q] =
+                        hc[(size_t)i * R + q] + hc[HOFF + (size_t)i * R + q];
+            std::vector<double> hn((size_t)R);
+            for (int32_t q = 0; q < R; ++q) hn[q] = std::sqrt(hc[2 * HOFF + q]);
+            ++it;
+            bool still = false;
+            for (int32_t q = 0; q < R; ++q) {
+                sc[q] = 0.0;
+                if (!act[q]) continue;
+                auto H = [&](size_t i, size_t jj) -> double & { return Hh[(i * m + jj) * R + q]; };
+                H(j + 1, j) = hn[q];
+                for (int i = 0; i < j; ++i) {
+                    const double c = cs[(size_t)i * R + q], sg = sn[(size_t)i * R + q];
+                    const double t = c * H(i, j) + sg * H(i + 1, j);
+                    H(i + 1, j) = -sg * H(i, j) + c * H(i + 1, j);
+                    H(i, j) = t;
+                }
+                const double d = std::hypot(H(j, j), H(j + 1, j));
+                double c = 1.0, sg = 0.0;
+                if (d > 0) { c = H(j, j) / d; sg = H(j + 1, j) / d; }
+                cs[(size_t)j * R + q] = c;
+                sn[(size_t)j * R + q] = sg;
+                H(j, j) = d;
+                H(j + 1, j) = 0.0;
+                g[(size_t)(j + 1) * R + q] = -sg * g[(size_t)j * R + q];
+                g[(size_t)j * R + q] = c * g[(size_t)j * R + q];
+                kq[q] = j + 1;
+                its[q] += 1;
+                if (std::fabs(g[(size_t)(j + 1) * R + q]) <= tol[q]) {
+                    act[q] = 0;          // frozen: its next basis vectors are zero
+                } else {
+                    still = true;
+                    sc[q] = hn[q] > 0 ? 1.0 / hn[q] : 0.0;
+                }
+            }
+            if (!still || it >= maxit || j + 1 == m) break;
+            upload(scale.get(), sc);
+            op_scale_rhs(n, R, w.get(), scale.get(), Vk(j + 1), s);
+        }
+        // x += Z y, y from the triangular systems (each right-hand side its
+        // own number of steps; missing steps weigh zero)
+        int kmax = 0;
+        std::fill(cf.begin(), cf.end(), 0.0);
+        for (int32_t q = 0; q < R; ++q) {
+            const int k = kq[q];
+            kmax = std::max(kmax, k);
+            std::vector<double> y((size_t)k);
+            for (int i = k - 1; i >= 0; --i) {
+                double t = g[(size_t)i * R + q];
+                for (int l = i + 1; l < k; ++l) t -= Hh[((size_t)i * m + l) * R + q] * y[l];
+                y[i] = t / Hh[((size_t)i * m + i) * R + q];
+            }
+            for (int i = 0; i < k; ++i) cf[(size_t)i * R + q] = -y[i];
+        }
+        if (kmax > 0) {
+            upload(coef.get(), cf);
+            op_maxpy(n, R, Zp, nv, kmax, coef.get(), x, s);
+        }
+        true_residual(beta);
+    }
+    LAIR_HIP(hipStreamSynchronize(s));
+    double relmax = 0.0;
+    int32_t itmax = 0;
+    for (int32_t q = 0; q < R; ++q) {
+        relmax = std::max(relmax, nb[q] > 0 ? beta[q] / nb[q] : beta[q]);
+        itmax = std::max(itmax, its[q]);
+    }
+    if (info) {
+        info->iters = itmax;
+        info->nlevels = (int32_t)h->L.size();
+        info->relres = relmax;
+        double rho = 0.0;
+        if (itmax > 0)
+            for (int32_t q = 0; q < R; ++q)
+                if (r_first[q] > 0 && its[q] > 0)
+                    rho = std::max(rho, std::pow(beta[q] / r_first[q], 1.0 / its[q]));
+        info->rho = rho;
+        info->cycle_complexity = h->cc;
+        info->op_complexity = h->oc;
+        info->n_singular_local = h->n_singular;
+        info->setup_ms = h->setup_ms;
+        info->solve_ms = ms_since(t0);
+    }
+    return relmax <= rtol ? LAIR_OK : LAIR_ENOCONV;
+}
+
 // Batch of independent systems (one right-hand side each): the correction
 // form x += B (b - A x) on the union, with the residual rows of converged
 // systems zeroed so that their corrections vanish.  Each system stops at its
@@ -2183,6 +2390,15 @@ lair_status lair_solve_transpose(lair_hierarchy *h, const double *g, double *lam
         if (h && h->opt.block_size > 0)
             fail(LAIR_EUNSUPPORTED, "transposed solve with block scaling");
         return solve_impl(h, g, lam, nrhs, rtol, maxit, info, (hipStream_t)stream, true);
+    });
+}
+
+lair_status lair_solve_fgmres(lair_hierarchy *h, const double *b, double *x, int32_t nrhs,
+                              double rtol, int32_t maxit, int32_t restart, lair_info *info,
+                              void *stream) {
+    return guarded([&]() -> lair_status {
+        return solve_fgmres_impl(h, b, x, nrhs, rtol, maxit, restart, info,
+                                 (hipStream_t)stream);
     });
 }
 

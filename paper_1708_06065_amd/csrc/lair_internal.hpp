@@ -229,6 +229,20 @@ struct LocalSolveOut {
     double *r_v;
     int8_t *flags;
 };
+// Flexible GMRES kernels (vectors of n rows x R interleaved right-hand
+// sides, R a power of two up to 32; a basis: kc vectors ldv apart).
+// op_mdot: out[k R + q] = (V_k, w)_q for k < kc (partial: kry_dot_blocks(n R)
+// x kc x R doubles of scratch); op_maxpy: w -= sum_k coef[k R + q] V_k per
+// right-hand side; op_scale_rhs: out = w * s[q] per right-hand side (out may
+// be w).
+int32_t kry_dot_blocks(int64_t m);
+void op_mdot(int64_t n, int32_t R, const double *V, int64_t ldv, int32_t kc, const double *w,
+             double *partial, double *out, hipStream_t s);
+void op_maxpy(int64_t n, int32_t R, const double *V, int64_t ldv, int32_t kc,
+              const double *coef, double *w, hipStream_t s);
+void op_scale_rhs(int64_t n, int32_t R, const double *w, const double *sc, double *out,
+                  hipStream_t s);
+
 // Largest local system the one-wave kernel keeps in LDS (larger ones use a
 // global slab).
 constexpr int32_t WSMAX = 64;
