@@ -177,6 +177,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch the solve's kernels eagerly instead of replaying captured iterations")
+    ap.add_argument("--solver", choices=("stationary", "fgmres"), default="stationary",
+                    help="outer iteration: the stationary V-cycle iteration (the default "
+                         "hot path) or flexible GMRES with the V-cycle as preconditioner")
+    ap.add_argument("--restart", type=int, default=20, help="FGMRES restart length")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (for HBM counters)")
     args = ap.parse_args()
@@ -203,6 +207,12 @@ def main():
 
     t0 = time.time()
     w, kw, cfg = make_workload(args.workload)
+    if args.solver == "fgmres":
+        if "systems" in w:
+            print("--solver fgmres is for a single system", file=sys.stderr)
+            sys.exit(2)
+        cfg = dict(cfg, outer="FGMRES(%d), V-cycle as right preconditioner" % args.restart)
+        args.no_cpu_baseline = True
     log("workload %s generated in %.1fs (n=%d nnz=%d)" % (cfg["workload"], time.time() - t0,
                                                           w["n"], w["nnz"]))
     batch = "systems" in w
@@ -239,6 +249,8 @@ def main():
         h = build(cfl, precision)
         if batch:
             X, info = h.solve_batch(B, rtol=1e-10, maxit=100)
+        elif args.solver == "fgmres":
+            X, info = h.solve_fgmres(B, rtol=1e-10, maxit=100, restart=args.restart)
         else:
             X, info = h.solve(B, rtol=1e-10, maxit=100)
         return h, X, info
