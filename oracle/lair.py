@@ -21,6 +21,9 @@ Steps and where the paper defines them:
   interp_direct     classical direct interpolation (Stueben 2001) as a
                     stand-in for the classical formulas cited in Sec. 4
   galerkin          Sec. 2.1: K = R A P
+  lump              Sec. 3.3 (filtering and lumping): entries of a coarse
+                    row below theta_D times the row's largest off-diagonal
+                    magnitude move to the diagonal
   block_scale       Sec. 4.2.1: D_B^{-1} A with the element block diagonal
   cycle             Sec. 2.1 coarse-grid correction followed by F-F-C Jacobi
                     (Sec. 4, relaxation paragraph; Eq. (jacobi_err))
@@ -334,15 +337,54 @@ class Hierarchy:
         return flops / wu
 
 
+def lump_keep(K, theta_d):
+    """Entries of K that lumping keeps: the diagonal, and off-diagonal
+    entries with |k_ij| >= theta_d * max_{j != i} |k_ij| (Sec. 3.3; the row
+    maximum taken over the off-diagonal entries).  Boolean per stored entry."""
+    K = K.tocsr()
+    keep = np.ones(K.nnz, dtype=bool)
+    for i in range(K.shape[0]):
+        lo, hi = K.indptr[i], K.indptr[i + 1]
+        cols = K.indices[lo:hi]
+        off = cols != i
+        if not off.any() or not (cols == i).any():
+            continue
+        m = np.abs(K.data[lo:hi][off]).max()
+        keep[lo:hi] = ~off | (np.abs(K.data[lo:hi]) >= theta_d * m)
+    return keep
+
+
+def lump(K, theta_d):
+    """Sec. 3.3: each removed entry of row i is added to k_ii, so row sums
+    stay.  The removed entries are summed in column order, then added."""
+    K = K.tocsr()
+    keep = lump_keep(K, theta_d)
+    data = K.data.copy()
+    for i in range(K.shape[0]):
+        lo, hi = K.indptr[i], K.indptr[i + 1]
+        gone = 0.0
+        for p in range(lo, hi):
+            if not keep[p]:
+                gone += data[p]
+        if gone != 0.0 or not keep[lo:hi].all():
+            d = lo + int(np.flatnonzero(K.indices[lo:hi] == i)[0])
+            data[d] = data[d] + gone
+    rows = np.repeat(np.arange(K.shape[0]), np.diff(K.indptr))
+    L = sp.csr_matrix((data[keep], (rows[keep], K.indices[keep])), shape=K.shape)
+    L.sort_indices()
+    return L
+
+
 def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
           distance=1, interp=INTERP_ONE_POINT, max_levels=25, max_coarse=128,
-          stall=0.9):
+          stall=0.9, lump_tol=0.0):
     """Build the lAIR hierarchy.
 
     cf_levels: optional list of per-level CF splits (int8 arrays, 1 = C);
     levels beyond the list use the Ruge-Stueben first pass.
     Coarsening stops when n <= max_coarse, when max_levels is reached, when
-    no C-point is found, or when n_c > stall * n.
+    no C-point is found, or when n_c > stall * n.  lump_tol > 0 lumps every
+    coarse operator (Sec. 3.3; level 0 is the caller's matrix).
     """
     if theta_c is None:
         theta_c = theta
@@ -377,6 +419,9 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
             L.P = interp_direct(Al, L.smask, cf)
         L.AP = spgemm(Al, L.P)
         Al = spgemm(L.R, L.AP)
+        if lump_tol > 0.0:
+            L.K_full = Al
+            Al = lump(Al, lump_tol)
         lvl += 1
     last = H.levels[-1]
     last.cf = None

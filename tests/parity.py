@@ -36,8 +36,27 @@ def rows_rel_err(a_rp, a_v, b_v):
     return worst
 
 
+def _lump_scale(K, S, theta_d):
+    """The scale matrix S (|R||A||P| on K's pattern) moved like K's lumped
+    entries: kept entries keep their scale, removed ones add to the
+    diagonal's."""
+    assert np.array_equal(K.indptr, S.indptr) and np.array_equal(K.indices, S.indices)
+    keep = O.lump_keep(K, theta_d)
+    data = S.data.copy()
+    for i in range(K.shape[0]):
+        lo, hi = K.indptr[i], K.indptr[i + 1]
+        gone = data[lo:hi][~keep[lo:hi]].sum()
+        if gone:
+            d = lo + int(np.flatnonzero(K.indices[lo:hi] == i)[0])
+            data[d] += gone
+    rows = np.repeat(np.arange(K.shape[0]), np.diff(K.indptr))
+    out = sp.csr_matrix((data[keep], (rows[keep], K.indices[keep])), shape=K.shape)
+    out.sort_indices()
+    return out
+
+
 def compare_level(h, l, theta=0.25, kind=O.SOC_ABS, distance=1,
-                  interp=O.INTERP_ONE_POINT, cf=None, ztol=1e-12, ktol=1e-12):
+                  interp=O.INTERP_ONE_POINT, cf=None, ztol=1e-12, ktol=1e-12, lump_tol=0.0):
     """Check level l of the GPU hierarchy against the oracle run on the GPU's
     A_l.  Returns a dict of measured errors; asserts the bit-exact parts."""
     A = gpu_A(h, l)
@@ -80,10 +99,15 @@ def compare_level(h, l, theta=0.25, kind=O.SOC_ABS, distance=1,
     out["p_err"] = float(np.abs(P.data - pv).max()) if pv.shape[0] else 0.0
     assert np.allclose(pv, P.data, rtol=1e-13, atol=1e-15)
     K = O.galerkin(R, A, P)
+    scale = O.galerkin(abs(R), abs(A), abs(P))
+    if lump_tol > 0.0:
+        K.sort_indices()
+        scale.sort_indices()
+        scale = _lump_scale(K, scale, lump_tol)
+        K = O.lump(K, lump_tol)
     Kg = gpu_A(h, l + 1)
     assert np.array_equal(K.indptr, Kg.indptr), "K pattern (rowptr) differs at level %d" % l
     assert np.array_equal(K.indices, Kg.indices), "K pattern (col) differs at level %d" % l
-    scale = O.galerkin(abs(R), abs(A), abs(P))
     err = np.abs(Kg.data - K.data)
     bound = ktol * scale.data + 1e-300
     out["k_err"] = float((err / np.maximum(scale.data, 1e-300)).max()) if err.shape[0] else 0.0

@@ -708,3 +708,64 @@ def test_fgmres_cycle_no_slower_than_stationary():
     xg, itg, hist, _ = O.fgmres_cycle(H, b, rtol=1e-10, restart=20)
     assert itg <= its
     assert np.linalg.norm(b - A @ xg) <= 1e-10 * np.linalg.norm(b)
+
+
+# ----------------------------------------------------------------- lumping
+
+def test_lump_hand_example():
+    """Sec. 3.3 by hand, theta_D = 1e-3: each row's cut is 1e-3 times its
+    largest off-diagonal magnitude (2, 3, 2, 1); the entries below it move
+    onto the diagonal."""
+    K = sp.csr_matrix(np.array([[4.0, -1e-4, -2.0, 0.0],
+                                [-1.0, 5.0, -1e-5, -3.0],
+                                [0.0, -2.0, 6.0, -1e-3],
+                                [-1e-6, 0.0, -1.0, 2.0]]))
+    want = np.array([[4.0 - 1e-4, 0.0, -2.0, 0.0],
+                     [-1.0, 5.0 - 1e-5, 0.0, -3.0],
+                     [0.0, -2.0, 6.0 - 1e-3, 0.0],
+                     [0.0, 0.0, -1.0, 2.0 - 1e-6]])
+    L = O.lump(K, 1e-3)
+    assert np.array_equal(L.toarray(), want)
+    assert L.nnz == 9
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_lump_keeps_row_sums_and_limits(seed):
+    rng = np.random.default_rng(seed)
+    n = 40
+    K = sp.random(n, n, density=0.3, random_state=seed, format="csr") * 2.0 - \
+        sp.random(n, n, density=0.3, random_state=seed + 7, format="csr")
+    K = (K + sp.diags(5.0 + rng.random(n))).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    one = np.ones(n)
+    scale = abs(K) @ one
+    for th in (1e-3, 0.1, 0.5, 1.0):
+        L = O.lump(K, th)
+        assert np.all(np.abs(L @ one - K @ one) <= 1e-14 * scale)
+        assert L.nnz <= K.nnz
+    assert (O.lump(K, 0.0) != K).nnz == 0          # nothing below a zero cut
+    # at theta_D = 1 only each row's largest off-diagonal magnitudes stay
+    L1 = O.lump(K, 1.0)
+    for i in range(n):
+        row = K.getrow(i).toarray().ravel()
+        off = np.abs(row)
+        off[i] = 0.0
+        kept = set(L1.getrow(i).indices) - {i}
+        assert kept == set(np.flatnonzero(off == off.max())) if off.max() > 0 else not kept
+
+
+def test_lumped_hierarchy_is_smaller_and_converges():
+    """Lumping at the paper's 1e-3 lowers the operator complexity and leaves
+    convergence about where it was (Sec. 3.3)."""
+    w = W.workload_c4(32)
+    A = (O.csr(w["rowptr"], w["col"], w["val"]) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    H0 = O.setup(A, interp=O.INTERP_DIRECT)
+    H1 = O.setup(A, interp=O.INTERP_DIRECT, lump_tol=1e-3,
+                 cf_levels=[l.cf for l in H0.levels[:-1]])
+    assert H1.op_complexity() < H0.op_complexity()
+    _, i0, _ = O.solve(H0, w["rhs"], rtol=1e-10)
+    x1, i1, _ = O.solve(H1, w["rhs"], rtol=1e-10)
+    assert i1 <= i0 + 3
+    assert np.linalg.norm(w["rhs"] - A @ x1) <= 1e-10 * np.linalg.norm(w["rhs"])
