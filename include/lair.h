@@ -110,6 +110,12 @@ typedef struct lair_options {
     int32_t block_size;      /* 0, or k: solve D_B^{-1} A x = D_B^{-1} b with
                                 D_B the k x k diagonal blocks (Sec. 4.2.1) */
     int32_t flags;           /* 0, or LAIR_FLAG_* bits below                */
+    double lump_tol;         /* 0 (off), or theta_D in (0, 1]: every coarse
+                                operator drops the off-diagonal entries of a
+                                row below theta_D times the row's largest
+                                off-diagonal magnitude and adds them to the
+                                diagonal, keeping row sums (Sec. 3.3; the
+                                paper's results use 0.001)                 */
 } lair_options;
 
 /* Solves capture one iteration (cycle, residual, norms) in a HIP graph the
@@ -315,7 +321,7 @@ lair_status lair_export(const lair_hierarchy *h, int32_t level, int32_t what,
  * to query).  Categories: strength, cf_lists, nbr, local_small, local_wave,
  * local_lstsq, interp, spgemm_count, spgemm_fill, validate, coarse_setup,
  * residual, restrict, interpolate, jacobi, scatter, norm, coarse_solve,
- * cast.  Process-wide; not for concurrent use from several host threads. */
+ * cast, spgemm_compact, lump.  Process-wide; not for concurrent use from several host threads. */
 lair_status lair_profile_begin(const char *categories);
 lair_status lair_profile_end(char *json, int64_t *len);
 

@@ -302,16 +302,18 @@ def _cf_levels(cf_levels, keep):
 
 
 def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels,
-            max_coarse, stall, block_size, graphs, ordering="auto"):
+            max_coarse, stall, block_size, graphs, ordering="auto", lump_tol=0.0):
     s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
                    _KINDS[kind], _DIST[distance])
     o = L.Options(_INTERP[interp], _PREC[precision], float(omega), int(max_levels),
                   int(max_coarse), float(stall), int(block_size),
-                  (0 if graphs else L.FLAG_NO_GRAPH) | _ORDERING[ordering])
+                  (0 if graphs else L.FLAG_NO_GRAPH) | _ORDERING[ordering],
+                  float(lump_tol))
     opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
                 interp=interp, precision=precision, omega=omega,
                 max_levels=max_levels, max_coarse=max_coarse, stall=stall,
-                block_size=block_size, graphs=graphs, ordering=ordering)
+                block_size=block_size, graphs=graphs, ordering=ordering,
+                lump_tol=lump_tol)
     return s, o, opts
 
 
@@ -335,7 +337,7 @@ def set_local_buckets(edges=None):
 def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
                 distance=1, interp="one_point", precision="fp64", omega=1.0,
                 max_levels=25, max_coarse=128, stall=0.9, block_size=0, graphs=True,
-                stream=None):
+                lump_tol=0.0, stream=None):
     """One hierarchy for a batch of independent systems.
 
     systems: list of (rowptr, col, val), all NumPy (host) or all CUDA
@@ -351,7 +353,8 @@ def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
         mats.append(A)
     arr = (L.Csr * len(mats))(*mats)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
-                         max_levels, max_coarse, stall, block_size, graphs)
+                         max_levels, max_coarse, stall, block_size, graphs,
+                         lump_tol=lump_tol)
     out = ctypes.c_void_p()
     cfp = _cf_levels(cf_levels, keep)
     st = lib.lair_setup_batch(len(mats), arr, cfp, ctypes.byref(s), ctypes.byref(o),
@@ -363,7 +366,7 @@ def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
 def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
           kind="abs", distance=1, interp="one_point", precision="fp64",
           omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
-          graphs=True, ordering="auto", stream=None):
+          graphs=True, ordering="auto", lump_tol=0.0, stream=None):
     """Build a hierarchy for the CSR matrix (rowptr, col, val).
 
     The arrays may be NumPy arrays (host) or contiguous CUDA tensors
@@ -373,13 +376,14 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
     ordering: "auto" runs the cycle on F-first renumbered copies of the
     large sparse levels, "natural" on the natural matrices everywhere,
     "split" renumbers every level but the coarsest; the results are bitwise
-    the same.
+    the same.  lump_tol > 0 lumps every coarse operator (Sec. 3.3).
     """
     lib = L.load()
     keep = []
     A, n = _csr(rowptr, col, val, keep)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
-                         max_levels, max_coarse, stall, block_size, graphs, ordering)
+                         max_levels, max_coarse, stall, block_size, graphs, ordering,
+                         lump_tol)
     cfp = _cf_levels(cf_levels, keep)
     out = ctypes.c_void_p()
     st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),

@@ -41,7 +41,7 @@ class CfLevels(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("interp", c_i32), ("precision", c_i32), ("omega", c_f64),
                 ("max_levels", c_i32), ("max_coarse", c_i32), ("stall", c_f64),
-                ("block_size", c_i32), ("flags", c_i32)]
+                ("block_size", c_i32), ("flags", c_i32), ("lump_tol", c_f64)]
 
 
 class Info(ctypes.Structure):

@@ -1967,6 +1967,86 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 }
 
 // ===========================================================================
+// Lumping of a coarse operator (Sec. 3.3): in row i, an off-diagonal entry
+// with |k_ij| < theta_D max_{j != i} |k_ij| leaves the pattern and is added
+// to k_ii (the removed entries summed in column order, then added), so the
+// row sum stays.  A row without a diagonal or without off-diagonal entries
+// is kept whole.  cnt != nullptr: count the kept entries of every row;
+// otherwise write them at rp_out.  A team of T lanes per row.
+// ===========================================================================
+template <int T>
+__global__ void __launch_bounds__(256)
+k_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v, double theta,
+       int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out) {
+    const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(gt / T);
+    const int lane = (int)(gt % T);
+    if (i >= n) return;
+    const int lo = rp[i], hi = rp[i + 1];
+    double mx = 0.0;
+    int has_d = 0, has_o = 0;
+    for (int p = lo + lane; p < hi; p += T) {
+        if (cj[p] == i) { has_d = 1; continue; }
+        has_o = 1;
+        mx = fmax(mx, fabs(v[p]));
+    }
+    mx = team_max<T>(mx);
+    has_d = team_sum_int<T>(has_d);
+    has_o = team_sum_int<T>(has_o);
+    const bool whole = !has_d || !has_o;
+    const double cut = theta * mx;
+    auto kept = [&](int p) { return whole || cj[p] == i || !(fabs(v[p]) < cut); };
+    if (cnt) {
+        int k = 0;
+        for (int p = lo + lane; p < hi; p += T) k += kept(p) ? 1 : 0;
+        k = team_sum_int<T>(k);
+        if (lane == 0) cnt[i] = k;
+        return;
+    }
+    // the removed entries' sum, in column order (one lane)
+    double gone = 0.0;
+    if (lane == 0 && !whole)
+        for (int p = lo; p < hi; ++p)
+            if (!kept(p)) gone += v[p];
+    gone = __shfl(gone, 0, T);
+    int o = rp_out[i];
+    for (int p0 = lo; p0 < hi; p0 += T) {
+        const int p = p0 + lane;
+        const bool take = p < hi && kept(p);
+        const uint64_t bits = team_bits<T>(take);
+        const int before = __popcll(bits & ((1ull << lane) - 1ull));
+        if (take) {
+            const int32_t j = cj[p];
+            cj_out[o + before] = j;
+            v_out[o + before] = (j == i && !whole) ? v[p] + gone : v[p];
+        }
+        o += __popcll(bits);
+    }
+}
+
+void launch_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v,
+                 double theta, double mean_len, int32_t *cnt, const int32_t *rp_out,
+                 int32_t *cj_out, double *v_out, hipStream_t s) {
+    if (n == 0) return;
+    int t = team_for_mean(mean_len);
+    if (t > 64) t = 64;
+#define LAIR_LU(TT)                                                                        \
+    LAIR_LAUNCH(k_lump<TT>, dim3(blocks_for((int64_t)n * TT, 256)), dim3(256), 0, s, n, rp, \
+                cj, v, theta, cnt, rp_out, cj_out, v_out)
+    switch (t) {
+        case 1: LAIR_LU(1); break;
+        case 2: LAIR_LU(2); break;
+        case 4: LAIR_LU(4); break;
+        case 8: LAIR_LU(8); break;
+        case 16: LAIR_LU(16); break;
+        case 32: LAIR_LU(32); break;
+        default: LAIR_LU(64); break;
+    }
+#undef LAIR_LU
+    LAIR_LAUNCH_CHECK();
+}
+
+// ===========================================================================
 // Sparse product C = A B with the symbolic pattern, rows of C sorted.
 //
 // Row i of C has at most E_i = sum over the entries a_ik of |row k of B|

@@ -401,6 +401,8 @@ static void check_options(const lair_strength *s, const lair_options *o) {
         fail(LAIR_EINVAL, "unknown option flags 0x%x", o->flags);
     if ((o->flags & LAIR_FLAG_NATURAL_ORDER) && (o->flags & LAIR_FLAG_SPLIT_ALL))
         fail(LAIR_EINVAL, "NATURAL_ORDER and SPLIT_ALL exclude each other");
+    if (!(o->lump_tol >= 0.0 && o->lump_tol <= 1.0))
+        fail(LAIR_EINVAL, "lump_tol must lie in [0, 1]");
 }
 
 static const int32_t MAX_DENSE = 4096;
@@ -912,6 +914,37 @@ static void upload_seg(Level &Lv, hipStream_t s) {
 }
 
 // seg: row offsets of the systems of a batch (nsys + 1 entries), or NULL.
+// Sec. 3.3: the coarse operator with its small off-diagonal entries moved
+// to the diagonal (row sums kept); returns the longest row.
+static int32_t lump_coarse(DevCSR &K, double theta_d, hipStream_t s, DevArr<int64_t> &tmp) {
+    const int32_t n = K.nrows;
+    if (n == 0) return 0;
+    const double mean = (double)K.nnz / n;
+    DevArr<int32_t> cnt;
+    cnt.alloc((size_t)n + 1, s);
+    DevCSR L;
+    L.nrows = K.nrows;
+    L.ncols = K.ncols;
+    L.rp.alloc((size_t)n + 1, s);
+    {
+        ProfScope ps("lump", s, 12.0 * K.nnz + 4.0 * (n + 1) + 4.0 * n);
+        launch_lump(n, K.rp.get(), K.cj.get(), K.v.get(), theta_d, mean, cnt.get(), nullptr,
+                    nullptr, nullptr, s);
+    }
+    int64_t mx = 0;
+    L.nnz = scan_counts_i32(cnt.get(), L.rp.get(), n, s, tmp, &mx, nullptr, nullptr);
+    L.max_row = (int32_t)mx;
+    L.cj.alloc((size_t)std::max<int64_t>(L.nnz, 1), s);
+    L.v.alloc((size_t)std::max<int64_t>(L.nnz, 1), s);
+    {
+        ProfScope ps("lump", s, 12.0 * K.nnz + 4.0 * (n + 1) + 12.0 * L.nnz);
+        launch_lump(n, K.rp.get(), K.cj.get(), K.v.get(), theta_d, mean, nullptr, L.rp.get(),
+                    L.cj.get(), L.v.get(), s);
+    }
+    K = std::move(L);
+    return K.max_row;
+}
+
 static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
                                   const lair_strength *str, const lair_options *opt,
                                   hipStream_t s, const std::vector<int64_t> *seg = nullptr) {
@@ -1056,6 +1089,7 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         // rows of K are sorted and unique by construction of the product
         nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr, k_ratio);
         if (nx->A.nnz > 0) k_ratio = (double)k_st.h[0] / (double)nx->A.nnz;
+        if (opt->lump_tol > 0.0) nx->max_row = lump_coarse(nx->A, opt->lump_tol, s, tmp);
         if (h->nsys > 1) {
             nx->seg = Lv.next_seg;
             nx->stopped = Lv.stopped;
@@ -2052,6 +2086,8 @@ static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_d
     if (!h || !diag) fail(LAIR_EINVAL, "hierarchy and diag must not be NULL");
     if (h->opt.block_size > 0)
         fail(LAIR_EUNSUPPORTED, "a new diagonal changes the block scaling: set up again");
+    if (h->opt.lump_tol > 0.0)
+        fail(LAIR_EUNSUPPORTED, "lumped coarse patterns depend on the values: set up again");
     h->stream = s;
     Level &L0 = *h->L[0];
     const int32_t n = L0.n;
@@ -2250,6 +2286,7 @@ void lair_default_options(lair_strength *s, lair_options *o) {
         o->stall = 0.9;
         o->block_size = 0;
         o->flags = 0;
+        o->lump_tol = 0.0;
     }
 }
 

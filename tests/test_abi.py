@@ -41,6 +41,7 @@ def test_status_strings_and_defaults():
     lib.lair_default_options(ctypes.byref(s), ctypes.byref(o))
     assert (s.theta, s.theta_c, s.kind, s.distance) == (0.25, 0.25, 0, 1)
     assert (o.interp, o.precision, o.omega, o.max_levels, o.max_coarse) == (0, 0, 1.0, 25, 128)
+    assert o.lump_tol == 0.0
 
 
 def test_host_side_validation_without_gpu():
@@ -64,6 +65,13 @@ def test_host_side_validation_without_gpu():
     o.omega = 0.0
     assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
                           ctypes.byref(out)) == L.LAIR_EINVAL
+    o.omega = 1.0
+    o.lump_tol = 2.0
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EINVAL
+    assert b"lump_tol" in lib.lair_last_error()
+    o.lump_tol = 0.0
+    o.omega = 0.0
     assert out.value is None
     # NULL hierarchy on every entry point
     assert lib.lair_solve(None, None, None, 1, 1e-10, 10, None, None) == L.LAIR_EINVAL
