@@ -181,6 +181,8 @@ def main():
                     help="outer iteration: the stationary V-cycle iteration (the default "
                          "hot path) or flexible GMRES with the V-cycle as preconditioner")
     ap.add_argument("--restart", type=int, default=20, help="FGMRES restart length")
+    ap.add_argument("--lump", type=float, default=0.0,
+                    help="lump every coarse operator at this tolerance (the paper uses 0.001)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (for HBM counters)")
     args = ap.parse_args()
@@ -229,6 +231,10 @@ def main():
 
     if args.no_graphs:
         kw = dict(kw, graphs=False)
+    if args.lump > 0.0:
+        kw = dict(kw, lump_tol=args.lump)
+        cfg = dict(cfg, lumping=args.lump)
+        args.no_cpu_baseline = True
 
     def build(cf_levels=None, precision="fp64"):
         if batch:

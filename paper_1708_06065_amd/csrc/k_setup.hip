@@ -1976,16 +1976,19 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 // ===========================================================================
 template <int T>
 __global__ void __launch_bounds__(256)
-k_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v, double theta,
+k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
+       const int32_t *cj, const double *v, double theta,
        int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out) {
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     const int32_t i = (int32_t)(gt / T);
     const int lane = (int)(gt % T);
     if (i >= n) return;
-    const int lo = rp[i], hi = rp[i + 1];
+    // a CSR row, or a staged row (offset and length)
+    const int64_t lo = row_off ? row_off[i] : (int64_t)rp[i];
+    const int64_t hi = row_off ? lo + row_len[i] : (int64_t)rp[i + 1];
     double mx = 0.0;
     int has_d = 0, has_o = 0;
-    for (int p = lo + lane; p < hi; p += T) {
+    for (int64_t p = lo + lane; p < hi; p += T) {
         if (cj[p] == i) { has_d = 1; continue; }
         has_o = 1;
         mx = fmax(mx, fabs(v[p]));
@@ -1995,23 +1998,30 @@ k_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v, double 
     has_o = team_sum_int<T>(has_o);
     const bool whole = !has_d || !has_o;
     const double cut = theta * mx;
-    auto kept = [&](int p) { return whole || cj[p] == i || !(fabs(v[p]) < cut); };
+    auto kept = [&](int64_t p) { return whole || cj[p] == i || !(fabs(v[p]) < cut); };
     if (cnt) {
         int k = 0;
-        for (int p = lo + lane; p < hi; p += T) k += kept(p) ? 1 : 0;
+        for (int64_t p = lo + lane; p < hi; p += T) k += kept(p) ? 1 : 0;
         k = team_sum_int<T>(k);
         if (lane == 0) cnt[i] = k;
         return;
     }
-    // the removed entries' sum, in column order (one lane)
+    // the removed entries' sum in column order: each step of T entries is
+    // loaded by the team, then added entry by entry (kept ones add +0)
     double gone = 0.0;
-    if (lane == 0 && !whole)
-        for (int p = lo; p < hi; ++p)
-            if (!kept(p)) gone += v[p];
-    gone = __shfl(gone, 0, T);
+    if (!whole) {
+        for (int64_t p0 = lo; p0 < hi; p0 += T) {
+            const int64_t p = p0 + lane;
+            const bool rm = p < hi && !kept(p);
+            const double x = rm ? v[p] : 0.0;
+            if (team_bits<T>(rm) == 0) continue;
+#pragma unroll 8
+            for (int k = 0; k < T; ++k) gone += __shfl(x, k, T);
+        }
+    }
     int o = rp_out[i];
-    for (int p0 = lo; p0 < hi; p0 += T) {
-        const int p = p0 + lane;
+    for (int64_t p0 = lo; p0 < hi; p0 += T) {
+        const int64_t p = p0 + lane;
         const bool take = p < hi && kept(p);
         const uint64_t bits = team_bits<T>(take);
         const int before = __popcll(bits & ((1ull << lane) - 1ull));
@@ -2024,15 +2034,17 @@ k_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v, double 
     }
 }
 
-void launch_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v,
-                 double theta, double mean_len, int32_t *cnt, const int32_t *rp_out,
-                 int32_t *cj_out, double *v_out, hipStream_t s) {
+void launch_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
+                 const int32_t *cj, const double *v, double theta, double mean_len,
+                 int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out,
+                 hipStream_t s) {
     if (n == 0) return;
-    int t = team_for_mean(mean_len);
-    if (t > 64) t = 64;
+    // about four entries per lane: several rows share a wavefront
+    int t = team_for_mean(mean_len / 4.0);
+    if (t > 16) t = 16;
 #define LAIR_LU(TT)                                                                        \
     LAIR_LAUNCH(k_lump<TT>, dim3(blocks_for((int64_t)n * TT, 256)), dim3(256), 0, s, n, rp, \
-                cj, v, theta, cnt, rp_out, cj_out, v_out)
+                row_off, row_len, cj, v, theta, cnt, rp_out, cj_out, v_out)
     switch (t) {
         case 1: LAIR_LU(1); break;
         case 2: LAIR_LU(2); break;

@@ -298,9 +298,13 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
 // deferred).
 // ratio: products per distinct column expected for C's rows (from a
 // similar product; 0 when unknown), which sizes the hash tables.
+// lump_tol > 0 (not deferred): C is written lumped (Sec. 3.3) straight from
+// the staged rows, in place of the plain compaction.
+// *distinct receives the size C has before lumping.
 static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, SpgemmState &st,
                              hipStream_t s, DevArr<int64_t> &tmp, PendingSizes *defer,
-                             double ratio = 0.0) {
+                             double ratio = 0.0, double lump_tol = 0.0,
+                             int64_t *distinct = nullptr) {
     const int32_t m = st.m;
     const int64_t etot = st.h[0], emax = st.h[1];
     C.nrows = m;
@@ -322,6 +326,50 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
     }
     C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
+    if (lump_tol > 0.0 && !defer) {
+        DevArr<int32_t> kcnt;
+        kcnt.alloc((size_t)m + 1, s);
+        // mean row of C before lumping, from the products per distinct
+        // column of the level above when known
+        const double mean_e = m ? (double)etot / m : 1.0;
+        const double mean_c = ratio > 1.0 ? mean_e / ratio : mean_e / 2.0;
+        {
+            ProfScope ps("lump", s, 12.0 * etot + 12.0 * m);
+            launch_lump(m, nullptr, st.eoff.get(), st.cnt.get(), tcj.get(), tcx.get(), lump_tol,
+                        mean_c, kcnt.get(), nullptr, nullptr, nullptr, s);
+        }
+        // kept entries (offsets of C) and, for the hash-table estimate of
+        // the next level, the distinct columns before lumping: one readback
+        DevArr<int32_t> dscan;
+        dscan.alloc((size_t)m + 1, s);
+        DevArr<int64_t> tots;
+        tots.alloc(4, s);
+        scan_counts_i32_to(kcnt.get(), C.rp.get(), m, s, tmp, tots.get());
+        scan_counts_i32_to(st.cnt.get(), dscan.get(), m, s, tmp, tots.get() + 2);
+        int64_t ht[4] = {0, 0, 0, 0};
+        int32_t ov = 0;
+        {
+            Readback rb(s);
+            rb.add(ht, tots.get(), sizeof(ht));
+            rb.add(&ov, ovp, sizeof(ov));
+            rb.run();
+        }
+        if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
+        if (ht[0] > INT32_MAX)
+            fail(LAIR_EUNSUPPORTED, "offset array exceeds 2^31 entries (%lld)", (long long)ht[0]);
+        C.nnz = ht[0];
+        mx = ht[1];
+        if (distinct) *distinct = ht[2];
+        C.max_row = (int32_t)mx;
+        C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
+        C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
+        {
+            ProfScope ps("lump", s, 12.0 * etot + 12.0 * m + 12.0 * C.nnz);
+            launch_lump(m, nullptr, st.eoff.get(), st.cnt.get(), tcj.get(), tcx.get(), lump_tol,
+                        mean_c, nullptr, C.rp.get(), C.cj.get(), C.v.get(), s);
+        }
+        return (int32_t)mx;
+    }
     if (defer) {
         scan_counts_i32_to(st.cnt.get(), C.rp.get(), m, s, tmp, defer->tot());
         C.nnz = etot;                // an upper bound until the sizes arrive
@@ -914,37 +962,6 @@ static void upload_seg(Level &Lv, hipStream_t s) {
 }
 
 // seg: row offsets of the systems of a batch (nsys + 1 entries), or NULL.
-// Sec. 3.3: the coarse operator with its small off-diagonal entries moved
-// to the diagonal (row sums kept); returns the longest row.
-static int32_t lump_coarse(DevCSR &K, double theta_d, hipStream_t s, DevArr<int64_t> &tmp) {
-    const int32_t n = K.nrows;
-    if (n == 0) return 0;
-    const double mean = (double)K.nnz / n;
-    DevArr<int32_t> cnt;
-    cnt.alloc((size_t)n + 1, s);
-    DevCSR L;
-    L.nrows = K.nrows;
-    L.ncols = K.ncols;
-    L.rp.alloc((size_t)n + 1, s);
-    {
-        ProfScope ps("lump", s, 12.0 * K.nnz + 4.0 * (n + 1) + 4.0 * n);
-        launch_lump(n, K.rp.get(), K.cj.get(), K.v.get(), theta_d, mean, cnt.get(), nullptr,
-                    nullptr, nullptr, s);
-    }
-    int64_t mx = 0;
-    L.nnz = scan_counts_i32(cnt.get(), L.rp.get(), n, s, tmp, &mx, nullptr, nullptr);
-    L.max_row = (int32_t)mx;
-    L.cj.alloc((size_t)std::max<int64_t>(L.nnz, 1), s);
-    L.v.alloc((size_t)std::max<int64_t>(L.nnz, 1), s);
-    {
-        ProfScope ps("lump", s, 12.0 * K.nnz + 4.0 * (n + 1) + 12.0 * L.nnz);
-        launch_lump(n, K.rp.get(), K.cj.get(), K.v.get(), theta_d, mean, nullptr, L.rp.get(),
-                    L.cj.get(), L.v.get(), s);
-    }
-    K = std::move(L);
-    return K.max_row;
-}
-
 static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
                                   const lair_strength *str, const lair_options *opt,
                                   hipStream_t s, const std::vector<int64_t> *seg = nullptr) {
@@ -1087,9 +1104,12 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         }
         if (AP.nnz > 0) ap_ratio = (double)ap_st.h[0] / (double)AP.nnz;
         // rows of K are sorted and unique by construction of the product
-        nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr, k_ratio);
-        if (nx->A.nnz > 0) k_ratio = (double)k_st.h[0] / (double)nx->A.nnz;
-        if (opt->lump_tol > 0.0) nx->max_row = lump_coarse(nx->A, opt->lump_tol, s, tmp);
+        int64_t k_distinct = -1;
+        nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr, k_ratio,
+                                    opt->lump_tol, &k_distinct);
+        if (k_distinct < 0) k_distinct = nx->A.nnz;
+        if (k_distinct > 0) k_ratio = (double)k_st.h[0] / (double)k_distinct;
+
         if (h->nsys > 1) {
             nx->seg = Lv.next_seg;
             nx->stopped = Lv.stopped;

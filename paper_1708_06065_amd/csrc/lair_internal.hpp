@@ -230,10 +230,13 @@ struct LocalSolveOut {
     int8_t *flags;
 };
 // Lumping of a coarse operator (k_lump): counts of kept entries per row
-// (cnt != nullptr), or the lumped rows written at rp_out.
-void launch_lump(int32_t n, const int32_t *rp, const int32_t *cj, const double *v,
-                 double theta, double mean_len, int32_t *cnt, const int32_t *rp_out,
-                 int32_t *cj_out, double *v_out, hipStream_t s);
+// (cnt != nullptr), or the lumped rows written at rp_out.  The rows are CSR
+// rows (rp), or staged rows at row_off[i] of length row_len[i] (row_off
+// non-null; sorted columns, as the product leaves them).
+void launch_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
+                 const int32_t *cj, const double *v, double theta, double mean_len,
+                 int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out,
+                 hipStream_t s);
 
 // Flexible GMRES kernels (vectors of n rows x R interleaved right-hand
 // sides, R a power of two up to 32; a basis: kc vectors ldv apart).
