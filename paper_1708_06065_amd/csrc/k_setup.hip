@@ -1974,6 +1974,8 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 // is kept whole.  cnt != nullptr: count the kept entries of every row;
 // otherwise write them at rp_out.  A team of T lanes per row.
 // ===========================================================================
+constexpr int LUMP_E = 4;     // entries per lane held in registers
+
 template <int T>
 __global__ void __launch_bounds__(256)
 k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
@@ -1986,6 +1988,66 @@ k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_
     // a CSR row, or a staged row (offset and length)
     const int64_t lo = row_off ? row_off[i] : (int64_t)rp[i];
     const int64_t hi = row_off ? lo + row_len[i] : (int64_t)rp[i + 1];
+    if (hi - lo <= (int64_t)LUMP_E * T) {
+        // the row in registers: step e of the team holds entries
+        // lo + e T .. lo + e T + T - 1, so steps in order are column order
+        int32_t c[LUMP_E];
+        double a[LUMP_E];
+        double mx = 0.0;
+        int has_d = 0, has_o = 0;
+#pragma unroll
+        for (int e = 0; e < LUMP_E; ++e) {
+            const int64_t p = lo + e * T + lane;
+            c[e] = -1;
+            a[e] = 0.0;
+            if (p < hi) {
+                c[e] = cj[p];
+                a[e] = v[p];
+                if (c[e] == i) has_d = 1;
+                else { has_o = 1; mx = fmax(mx, fabs(a[e])); }
+            }
+        }
+        mx = team_max<T>(mx);
+        has_d = team_sum_int<T>(has_d);
+        has_o = team_sum_int<T>(has_o);
+        const bool whole = !has_d || !has_o;
+        const double cut = theta * mx;
+        bool keep[LUMP_E];
+#pragma unroll
+        for (int e = 0; e < LUMP_E; ++e)
+            keep[e] = c[e] >= 0 && (whole || c[e] == i || !(fabs(a[e]) < cut));
+        if (cnt) {
+            int k = 0;
+#pragma unroll
+            for (int e = 0; e < LUMP_E; ++e) k += keep[e] ? 1 : 0;
+            k = team_sum_int<T>(k);
+            if (lane == 0) cnt[i] = k;
+            return;
+        }
+        double gone = 0.0;
+        if (!whole) {
+#pragma unroll
+            for (int e = 0; e < LUMP_E; ++e) {
+                const bool rm = c[e] >= 0 && !keep[e];
+                const double x = rm ? a[e] : 0.0;
+                if (team_bits<T>(rm) == 0) continue;
+                for (int k = 0; k < T; ++k) gone += __shfl(x, k, T);
+            }
+        }
+        int o = rp_out[i];
+#pragma unroll
+        for (int e = 0; e < LUMP_E; ++e) {
+            const uint64_t bits = team_bits<T>(keep[e]);
+            const int before = __popcll(bits & ((1ull << lane) - 1ull));
+            if (keep[e]) {
+                cj_out[o + before] = c[e];
+                v_out[o + before] = (c[e] == i && !whole) ? a[e] + gone : a[e];
+            }
+            o += __popcll(bits);
+        }
+        return;
+    }
+    // longer rows: streamed, the same operations in the same order
     double mx = 0.0;
     int has_d = 0, has_o = 0;
     for (int64_t p = lo + lane; p < hi; p += T) {
