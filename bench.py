@@ -39,15 +39,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 
 
-def measured_traffic(workload, category):
+def measured_traffic(workload, category, lump_tol):
     """HBM bytes per launch of a kernel category from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE record, or None when there is none for
-    this workload and category or the kernel sources changed since."""
+    this workload, category and lumping tolerance or the kernel sources
+    changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, category))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if rec.get("lump_tol", 0.0) != lump_tol:
+        return None
     for f, sha in rec.get("source_sha256", {}).items():
         fp = os.path.join(ROOT, f)
         if not os.path.exists(fp) or hashlib.sha256(open(fp, "rb").read()).hexdigest() != sha:
@@ -106,14 +109,14 @@ tot = sum(w["nnz"] for w in systems)
 t0 = time.perf_counter(); done = 0; nz = 0; its = []
 for w in systems:
     A = O.csr(w["rowptr"], w["col"], w["val"])
-    H = O.setup(A, interp=O.INTERP_DIRECT)
+    H = O.setup(A, interp=O.INTERP_DIRECT, lump_tol=%r)
     x, it, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=100)
     done += 1; nz += w["nnz"]; its.append(it)
     if time.perf_counter() - t0 > %r:
         break
 el = time.perf_counter() - t0
 print(json.dumps({"s": el, "done": done, "nnz": nz, "tot": tot, "iters_max": max(its)}))
-''' % (ROOT, budget_s)
+''' % (ROOT, kw.get("lump_tol", 0.0), budget_s)
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
                        timeout=600)
@@ -143,7 +146,7 @@ w, kw, cfg = bench.make_workload(%r)
 A = O.csr(w["rowptr"], w["col"], w["val"])
 interp = O.INTERP_DIRECT if kw["interp"] == "direct" else O.INTERP_ONE_POINT
 t0 = time.perf_counter()
-H = O.setup(A, interp=interp, distance=kw["distance"])
+H = O.setup(A, interp=interp, distance=kw["distance"], lump_tol=%r)
 t1 = time.perf_counter()
 b = np.asarray(w["rhs"])
 b0 = b[:, 0] if b.ndim > 1 else b
@@ -151,7 +154,7 @@ x, it, hist = O.solve(H, b0, rtol=1e-10, maxit=100)
 t2 = time.perf_counter()
 print(json.dumps({"setup_s": t1 - t0, "solve_s": t2 - t1, "iters": it,
                   "nrhs": 1 if b.ndim == 1 else b.shape[1]}))
-''' % (ROOT, workload)
+''' % (ROOT, workload, kw.get("lump_tol", 0.0))
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
                        timeout=600)
@@ -181,8 +184,9 @@ def main():
                     help="outer iteration: the stationary V-cycle iteration (the default "
                          "hot path) or flexible GMRES with the V-cycle as preconditioner")
     ap.add_argument("--restart", type=int, default=20, help="FGMRES restart length")
-    ap.add_argument("--lump", type=float, default=0.0,
-                    help="lump every coarse operator at this tolerance (the paper uses 0.001)")
+    ap.add_argument("--lump", type=float, default=1e-3,
+                    help="lump every coarse operator at this tolerance (0: off); the paper "
+                         "lumps all its lAIR results at 0.001")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (for HBM counters)")
     args = ap.parse_args()
@@ -231,10 +235,8 @@ def main():
 
     if args.no_graphs:
         kw = dict(kw, graphs=False)
-    if args.lump > 0.0:
-        kw = dict(kw, lump_tol=args.lump)
-        cfg = dict(cfg, lumping=args.lump)
-        args.no_cpu_baseline = True
+    kw = dict(kw, lump_tol=args.lump)
+    cfg = dict(cfg, lumping=args.lump)
 
     def build(cf_levels=None, precision="fp64"):
         if batch:
@@ -326,7 +328,7 @@ def main():
     achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant,
+                "traffic": measured_traffic(args.workload, dominant, args.lump), "kernel": dominant,
                 "launches": d["launches"], "avg_launch_us": 1e3 * d["ms"] / max(d["launches"], 1),
                 "alg_bytes_per_launch": d["alg_bytes"] / max(d["launches"], 1)}
     out = {
