@@ -32,6 +32,11 @@ Steps and where the paper defines them:
   cycle_transpose   the exact adjoint of ``cycle`` (for gradients)
   fgmres            flexible GMRES(m) with one V-cycle as the right
                     preconditioner (the outer solver of Sec. 4's results)
+  setup(block=k)    nodal treatment of a k x k block structure (Sec. 3.1, the
+                    block form of Eq. (system); Sec. 4.2, treatment (iii)):
+                    strength and CF splitting on the graph of blocks, local
+                    systems by block with k right-hand sides, one-point
+                    interpolation by block, block Jacobi relaxation
   update_diag       a new diagonal on a kept hierarchy structure: Eq. (system)
                     solves, interpolation weights and Sec. 2.1 Galerkin
                     products recomputed on the same neighbourhoods, splittings
@@ -302,6 +307,174 @@ def block_scale(A, b, k):
 
 
 # --------------------------------------------------------------------------
+# Nodal (block) treatment: every step taken on the k x k blocks of A
+# (Sec. 3.1, block form of Eq. (system); Sec. 4.2, treatment (iii)).  A is
+# held as a scalar CSR matrix whose stored blocks are dense: the k rows of a
+# node store the same columns, in whole groups of k.
+# --------------------------------------------------------------------------
+
+def node_graph(A, k):
+    """The graph of blocks: node CSR (rowptr, col) and, per stored block,
+    its squared Frobenius norm summed row by row then column by column
+    (a fixed order, so that a comparison of two norms is reproducible).
+    Checks that every stored block is dense."""
+    A = A.tocsr()
+    n = A.shape[0]
+    assert n % k == 0
+    nn = n // k
+    rp, cj, vx = A.indptr, A.indices, A.data
+    nrp = np.zeros(nn + 1, dtype=np.int64)
+    ncol, nsq = [], []
+    for i in range(nn):
+        r0 = i * k
+        len0 = rp[r0 + 1] - rp[r0]
+        if len0 % k:
+            raise ValueError("node %d: a row does not store whole blocks" % i)
+        cols0 = cj[rp[r0]:rp[r0 + 1]]
+        for a in range(k):
+            ca = cj[rp[r0 + a]:rp[r0 + a + 1]]
+            if ca.shape[0] != len0 or np.any(ca != cols0):
+                raise ValueError("node %d: its rows store different columns" % i)
+        g = cols0.reshape(-1, k)
+        if np.any(g[:, 0] % k) or np.any(g - g[:, :1] != np.arange(k)):
+            raise ValueError("node %d: a stored block is not dense" % i)
+        for t in range(g.shape[0]):
+            acc = 0.0
+            for a in range(k):
+                base = rp[r0 + a] + t * k
+                for u in range(k):
+                    acc = acc + vx[base + u] * vx[base + u]
+            ncol.append(g[t, 0] // k)
+            nsq.append(acc)
+        nrp[i + 1] = nrp[i] + g.shape[0]
+    return nrp, np.array(ncol, dtype=np.int32), np.array(nsq, dtype=np.float64)
+
+
+def node_strength(nrp, ncol, nsq, theta=0.25):
+    """Strong blocks: ||A_ij||_F >= theta max_{l != i} ||A_il||_F, taken on
+    squared norms (||A_ij||^2 >= theta^2 max ||A_il||^2); a zero block or a
+    node without off-diagonal blocks has no strong connection.  uint8 per
+    stored block."""
+    nn = nrp.shape[0] - 1
+    th2 = theta * theta
+    sm = np.zeros(ncol.shape[0], dtype=np.uint8)
+    for i in range(nn):
+        lo, hi = nrp[i], nrp[i + 1]
+        off = ncol[lo:hi] != i
+        if not off.any():
+            continue
+        m = nsq[lo:hi][off].max()
+        if m <= 0.0:
+            continue
+        cut = th2 * m
+        for p in range(lo, hi):
+            if ncol[p] != i and nsq[p] > 0.0 and nsq[p] >= cut:
+                sm[p] = 1
+    return sm
+
+
+def expand_nodes(x_node, k):
+    """A per-node array repeated for each of the node's k rows."""
+    return np.repeat(np.asarray(x_node), k)
+
+
+def node_neighbourhoods(nrp, ncol, nsm, cf_node, k):
+    """N_i of every C-node (its strong F-neighbour nodes, distance one),
+    given per C-row: every row of C-node i gets the k rows of each node of
+    N_i, ascending.  Returns (cpts, nptr, nbr) over the rows of A."""
+    nn = nrp.shape[0] - 1
+    rows, lists = [], []
+    for i in range(nn):
+        if cf_node[i] != 1:
+            continue
+        nb = []
+        for p in range(nrp[i], nrp[i + 1]):
+            j = ncol[p]
+            if j != i and nsm[p] and cf_node[j] == 0:
+                nb.append(j)
+        dof = (np.repeat(np.array(sorted(nb), dtype=np.int64), k) * k +
+               np.tile(np.arange(k), len(nb))).astype(np.int32)
+        for a in range(k):
+            rows.append(i * k + a)
+            lists.append(dof)
+    cpts = np.array(rows, dtype=np.int32)
+    nptr = np.zeros(len(lists) + 1, dtype=np.int64)
+    np.cumsum([l.shape[0] for l in lists], out=nptr[1:])
+    nbr = np.concatenate(lists).astype(np.int32) if lists else np.zeros(0, np.int32)
+    return cpts, nptr, nbr
+
+
+def node_local_solves(A, k, cpts, nptr, nbr):
+    """Block form of Eq. (system): for C-node i with neighbour rows N,
+    A(N,N)^T Y = -A(i-rows, N)^T with k right-hand sides, one per row of the
+    node; row a of the block row Z_i is column a of Y.  A singular system
+    (a pivot of its LU with |u_kk| <= 1e-14 ||M||_inf) is solved for each
+    right-hand side in the minimal-norm least-squares sense.  Returns
+    (z over nbr, flags per C-row)."""
+    A = A.tocsr()
+    z = np.zeros(int(nptr[-1]), dtype=np.float64)
+    flags = np.zeros(cpts.shape[0], dtype=np.int8)
+    for q0 in range(0, cpts.shape[0], k):
+        nb = nbr[nptr[q0]:nptr[q0 + 1]]
+        if nb.shape[0] == 0:
+            continue
+        node_rows = cpts[q0:q0 + k]
+        M = A[nb][:, nb].toarray().T
+        F = -A[node_rows][:, nb].toarray().T           # (kS) x k
+        lu, piv = sla.lu_factor(M, check_finite=False)
+        if np.any(np.abs(np.diag(lu)) <= 1e-14 * np.abs(M).sum(axis=1).max()):
+            Y = np.linalg.lstsq(M, F, rcond=None)[0]
+            flags[q0:q0 + k] = 1
+        else:
+            Y = sla.lu_solve((lu, piv), F)
+        for a in range(k):
+            z[nptr[q0 + a]:nptr[q0 + a + 1]] = Y[:, a]
+    return z, flags
+
+
+def node_interp_one_point(nrp, ncol, nsq, nsm, cf_node, k):
+    """One-point interpolation by block (Sec. 4.2): an F-node takes the
+    identity block from its strong C-neighbour node with the largest block
+    norm (the first in column order on a tie); a C-node injects; an F-node
+    without a strong C-neighbour gets zero rows."""
+    nn = nrp.shape[0] - 1
+    cidx_n, cnodes = coarse_index(cf_node)
+    pick = np.full(nn, -1, dtype=np.int64)
+    for i in range(nn):
+        if cf_node[i] == 1:
+            pick[i] = cidx_n[i]
+            continue
+        best, bv = -1, -1.0
+        for p in range(nrp[i], nrp[i + 1]):
+            j = ncol[p]
+            if j == i or not nsm[p] or cf_node[j] != 1:
+                continue
+            if nsq[p] > bv:
+                bv, best = nsq[p], j
+        pick[i] = cidx_n[best] if best >= 0 else -1
+    n = nn * k
+    pcol = np.full(n, -1, dtype=np.int64)
+    for i in range(nn):
+        if pick[i] >= 0:
+            pcol[i * k:(i + 1) * k] = pick[i] * k + np.arange(k)
+    has = pcol >= 0
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(has, out=rowptr[1:])
+    return csr(rowptr, pcol[has].astype(np.int32), np.ones(int(has.sum())),
+               shape=(n, cnodes.shape[0] * k))
+
+
+def diag_blocks(A, k):
+    """The k x k diagonal blocks of A, shape (n/k, k, k)."""
+    n = A.shape[0]
+    Ac = A.tocoo()
+    D = np.zeros((n // k, k, k))
+    inb = (Ac.row // k) == (Ac.col // k)
+    D[Ac.row[inb] // k, Ac.row[inb] % k, Ac.col[inb] % k] = Ac.data[inb]
+    return D
+
+
+# --------------------------------------------------------------------------
 # Hierarchy
 # --------------------------------------------------------------------------
 
@@ -377,17 +550,22 @@ def lump(K, theta_d):
 
 def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
           distance=1, interp=INTERP_ONE_POINT, max_levels=25, max_coarse=128,
-          stall=0.9, lump_tol=0.0):
+          stall=0.9, lump_tol=0.0, block=0):
     """Build the lAIR hierarchy.
 
     cf_levels: optional list of per-level CF splits (int8 arrays, 1 = C);
     levels beyond the list use the Ruge-Stueben first pass.
     Coarsening stops when n <= max_coarse, when max_levels is reached, when
     no C-point is found, or when n_c > stall * n.  lump_tol > 0 lumps every
-    coarse operator (Sec. 3.3; level 0 is the caller's matrix).
+    coarse operator (Sec. 3.3; level 0 is the caller's matrix).  block = k
+    builds the hierarchy by k x k blocks (nodal treatment; distance one,
+    one-point interpolation by block, SOC on block norms, block Jacobi).
     """
     if theta_c is None:
         theta_c = theta
+    if block:
+        return _setup_nodal(A, block, cf_levels, theta, theta_c, max_levels,
+                            max_coarse, stall)
     H = Hierarchy()
     Al = A.tocsr()
     lvl = 0
@@ -427,6 +605,61 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
     last.cf = None
     H.coarse_lu = sla.lu_factor(last.A.toarray())
     H.interp = interp
+    return H
+
+
+def _setup_nodal(A, k, cf_levels, theta, theta_c, max_levels, max_coarse, stall):
+    H = Hierarchy()
+    H.block = k
+    Al = A.tocsr()
+    lvl = 0
+    while True:
+        L = Level()
+        L.A = Al
+        n = Al.shape[0]
+        H.levels.append(L)
+        if n <= max_coarse or lvl + 1 >= max_levels:
+            break
+        nrp, ncol, nsq = node_graph(Al, k)
+        nsm = node_strength(nrp, ncol, nsq, theta)
+        if cf_levels is not None and lvl < len(cf_levels):
+            cf = np.ascontiguousarray(cf_levels[lvl], dtype=np.int8)
+            cf_node = cf[::k].copy()
+            assert np.array_equal(expand_nodes(cf_node, k), cf)
+        else:
+            nsm_c = nsm if theta_c == theta else node_strength(nrp, ncol, nsq, theta_c)
+            G = csr(nrp.astype(np.int32), ncol, np.ones(ncol.shape[0]),
+                    shape=(n // k, n // k))
+            cf_node = rs_split(G, nsm_c)
+            cf = expand_nodes(cf_node, k).astype(np.int8)
+        nc = int((cf == 1).sum())
+        if nc == 0 or nc > stall * n:
+            break
+        L.cf = cf
+        L.node_graph = (nrp, ncol, nsq)
+        L.nsmask = nsm
+        # the strength mask over A's stored entries: every entry of a strong
+        # block
+        L.smask = np.zeros(Al.nnz, dtype=np.uint8)
+        for i in range(n // k):
+            for a in range(k):
+                lo = Al.indptr[i * k + a]
+                for t, p in enumerate(range(nrp[i], nrp[i + 1])):
+                    if nsm[p]:
+                        L.smask[lo + t * k:lo + (t + 1) * k] = 1
+        L.cidx, L.cpts = coarse_index(cf)
+        cpts, L.nptr, L.nbr = node_neighbourhoods(nrp, ncol, nsm, cf_node, k)
+        assert np.array_equal(cpts, L.cpts)
+        L.z, L.flags = node_local_solves(Al, k, cpts, L.nptr, L.nbr)
+        L.R = restriction(n, cpts, L.nptr, L.nbr, L.z)
+        L.P = node_interp_one_point(nrp, ncol, nsq, nsm, cf_node, k)
+        L.AP = spgemm(Al, L.P)
+        Al = spgemm(L.R, L.AP)
+        lvl += 1
+    last = H.levels[-1]
+    last.cf = None
+    H.coarse_lu = sla.lu_factor(last.A.toarray())
+    H.interp = INTERP_ONE_POINT
     return H
 
 
@@ -471,8 +704,20 @@ def _jacobi(A, diag, b, x, rows, omega=1.0):
     return y
 
 
+def _jacobi_block(A, D, k, b, x, rows, omega=1.0):
+    """One block Jacobi sweep over the nodes whose rows are ``rows``:
+    x_i + omega D_i^{-1} (b - A x)_i with D_i the node's diagonal block."""
+    r = b[rows] - A[rows] @ x
+    nodes = rows[::k] // k
+    c = np.linalg.solve(D[nodes], r.reshape(-1, k, 1)).reshape(-1)
+    y = x.copy()
+    y[rows] = x[rows] + omega * c
+    return y
+
+
 def cycle(H, b, x, lvl=0, omega=1.0):
-    """One V-cycle: coarse-grid correction, then F, F, C Jacobi sweeps."""
+    """One V-cycle: coarse-grid correction, then F, F, C Jacobi sweeps
+    (block Jacobi on the nodes for a nodal hierarchy)."""
     L = H.levels[lvl]
     if lvl == H.nlevels - 1:
         return sla.lu_solve(H.coarse_lu, b)
@@ -481,9 +726,16 @@ def cycle(H, b, x, lvl=0, omega=1.0):
     bc = L.R @ r
     xc = cycle(H, bc, np.zeros(bc.shape[0]), lvl + 1, omega)
     x = x + L.P @ xc
-    diag = A.diagonal()
     F = np.flatnonzero(L.cf == 0)
     C = np.flatnonzero(L.cf == 1)
+    k = getattr(H, "block", 0)
+    if k:
+        D = diag_blocks(A, k)
+        x = _jacobi_block(A, D, k, b, x, F, omega)
+        x = _jacobi_block(A, D, k, b, x, F, omega)
+        x = _jacobi_block(A, D, k, b, x, C, omega)
+        return x
+    diag = A.diagonal()
     x = _jacobi(A, diag, b, x, F, omega)
     x = _jacobi(A, diag, b, x, F, omega)
     x = _jacobi(A, diag, b, x, C, omega)

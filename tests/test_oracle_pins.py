@@ -769,3 +769,142 @@ def test_lumped_hierarchy_is_smaller_and_converges():
     x1, i1, _ = O.solve(H1, w["rhs"], rtol=1e-10)
     assert i1 <= i0 + 3
     assert np.linalg.norm(w["rhs"] - A @ x1) <= 1e-10 * np.linalg.norm(w["rhs"])
+
+
+# --------------------------------------------------------------------------
+# Nodal (block) treatment, Sec. 3.1 block form of Eq. (system), Sec. 4.2 (iii)
+# --------------------------------------------------------------------------
+
+def _adr(m):
+    w = W.workload_c4(m)
+    A = (O.csr(w["rowptr"], w["col"], w["val"]) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    return A, w["rhs"]
+
+
+def test_nodal_with_unit_blocks_is_scalar_lair():
+    """k = 1: block norms are magnitudes, so every step reduces to scalar
+    lAIR with one-point interpolation."""
+    A, b = _adr(24)
+    H = O.setup(A, interp=O.INTERP_ONE_POINT)
+    G = O.setup(A, block=1)
+    assert G.nlevels == H.nlevels
+    for l in range(H.nlevels - 1):
+        assert np.array_equal(G.levels[l].cf, H.levels[l].cf)
+        assert np.array_equal(G.levels[l].smask, H.levels[l].smask)
+        for M in ("R", "P"):
+            a, c = getattr(G.levels[l], M), getattr(H.levels[l], M)
+            assert np.array_equal(a.indptr, c.indptr) and np.array_equal(a.indices, c.indices)
+            assert np.abs(a.data - c.data).max() <= 1e-12 * np.abs(c.data).max()
+    _, it_h, _ = O.solve(H, b, rtol=1e-10)
+    x, it_g, _ = O.solve(G, b, rtol=1e-10)
+    assert it_g == it_h
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+
+
+def _kron_case(k=3, m=20, seed=0):
+    As, bs = _adr(m)
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((k, k)) + 3.0 * np.eye(k)
+    A = sp.kron(As, sp.csr_matrix(B)).tocsr()
+    A.sort_indices()
+    return As, bs, B, A
+
+
+def test_nodal_kronecker_is_scalar_times_identity():
+    """A = A_s (x) B: the block norms are |a_ij| ||B||_F, so the nodes split
+    as the scalar points of A_s; Z_il = z_il I solves the block system
+    (z (a B) summed = -a_ij B), so R = R_s (x) I, P = P_s (x) I, K = K_s (x) B,
+    and block Jacobi with D_i = a_ii B maps x_s (x) B^{-1} w as the scalar
+    sweep maps x_s: every cycle's iterate is the scalar one (x) B^{-1} w."""
+    k = 3
+    As, bs, B, A = _kron_case(k)
+    Hs = O.setup(As, interp=O.INTERP_ONE_POINT)
+    Hb = O.setup(A, block=k, max_coarse=128 * k)      # the same stop in nodes
+    assert Hb.nlevels == Hs.nlevels >= 3
+    I = sp.identity(k)
+    for l in range(Hs.nlevels - 1):
+        Ls, Lb = Hs.levels[l], Hb.levels[l]
+        assert np.array_equal(Lb.cf, np.repeat(Ls.cf, k))
+        Rk = sp.kron(Ls.R, I).toarray()
+        assert np.abs(Lb.R.toarray() - Rk).max() <= 1e-12 * np.abs(Rk).max()
+        assert (Lb.P != sp.kron(Ls.P, I)).nnz == 0
+        Kk = sp.kron(Hs.levels[l + 1].A, sp.csr_matrix(B)).toarray()
+        assert np.abs(Hb.levels[l + 1].A.toarray() - Kk).max() <= 1e-11 * np.abs(Kk).max()
+    w = np.array([1.0, -2.0, 0.5])
+    u = np.linalg.solve(B, w)
+    xs = np.zeros_like(bs)
+    xb = np.zeros(A.shape[0])
+    bb = np.kron(bs, w)
+    for _ in range(3):
+        xs = O.cycle(Hs, bs, xs)
+        xb = O.cycle(Hb, bb, xb)
+        ref = np.kron(xs, u)
+        assert np.linalg.norm(xb - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def _dense_block_case(k=2, m=16, seed=1):
+    """A dense-block matrix that is not a Kronecker product: A_s (x) B with
+    every stored entry perturbed."""
+    As, bs, B, A = _kron_case(k, m, seed)
+    rng = np.random.default_rng(seed + 10)
+    A = A.copy()
+    A.data = A.data * (1.0 + 0.3 * rng.standard_normal(A.nnz))
+    return A, np.kron(bs, np.ones(k))
+
+
+def test_nodal_strength_and_one_point_brute_force():
+    k = 2
+    A, _ = _dense_block_case(k)
+    nrp, ncol, nsq = O.node_graph(A, k)
+    nsm = O.node_strength(nrp, ncol, nsq, 0.25)
+    Ad = A.toarray()
+    nn = A.shape[0] // k
+    blk = lambda i, j: Ad[i * k:(i + 1) * k, j * k:(j + 1) * k]
+    for i in range(nn):
+        js = ncol[nrp[i]:nrp[i + 1]]
+        norms = {j: np.linalg.norm(blk(i, j)) for j in js}
+        m = max([norms[j] for j in js if j != i], default=0.0)
+        for t, j in enumerate(js):
+            want = j != i and norms[j] > 0 and m > 0 and norms[j] >= 0.25 * m
+            assert bool(nsm[nrp[i] + t]) == want
+    cf_node = O.rs_split(O.csr(nrp.astype(np.int32), ncol, np.ones(ncol.shape[0]),
+                               shape=(nn, nn)), nsm)
+    P = O.node_interp_one_point(nrp, ncol, nsq, nsm, cf_node, k).toarray()
+    cidx, _ = O.coarse_index(cf_node)
+    for i in range(nn):
+        rows = P[i * k:(i + 1) * k]
+        if cf_node[i] == 1:
+            want = cidx[i]
+        else:
+            cand = [j for t, j in enumerate(ncol[nrp[i]:nrp[i + 1]])
+                    if nsm[nrp[i] + t] and cf_node[j] == 1]
+            want = cidx[max(cand, key=lambda j: (np.linalg.norm(blk(i, j)), -j))] \
+                if cand else -1
+        if want < 0:
+            assert not rows.any()
+        else:
+            assert np.array_equal(rows[:, want * k:(want + 1) * k], np.eye(k))
+            assert rows.sum() == k
+
+
+def test_nodal_restriction_annihilates_neighbourhood_blocks():
+    """Block form of Eq. (johnair): (R A)(i, N_i) = 0 as a k x k block for
+    every C-node i and every node of N_i; the hierarchy solves."""
+    k = 2
+    A, b = _dense_block_case(k)
+    H = O.setup(A, block=k)
+    L = H.levels[0]
+    RA = (L.R @ A).toarray()
+    scale = (abs(L.R) @ abs(A)).toarray()
+    for q in range(L.cpts.shape[0]):
+        nb = L.nbr[L.nptr[q]:L.nptr[q + 1]]
+        assert np.all(np.abs(RA[q, nb]) <= 1e-12 * scale[q, nb] + 1e-300)
+    x, it, _ = O.solve(H, b, rtol=1e-10)
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_nodal_rejects_blocks_that_are_not_dense():
+    A, _ = _adr(8)
+    with pytest.raises(ValueError):
+        O.node_graph(A, 2)
