@@ -137,6 +137,24 @@ typedef struct lair_options {
  * the coarsest whatever its size. */
 #define LAIR_FLAG_NATURAL_ORDER 2
 #define LAIR_FLAG_SPLIT_ALL 4
+/* With block_size = k: build the hierarchy by k x k blocks (the nodal
+ * treatment of Sec. 4.2, with R from the block form of Eq. (system) in
+ * Sec. 3.1) instead of scaling by the block diagonal.  The k rows of node i
+ * are rows i k .. i k + k - 1; they must store the same columns in whole
+ * dense blocks (explicit zeros included), else setup fails with
+ * LAIR_EINVAL.  Block (i, j) is strong when
+ * ||A_ij||_F^2 >= theta^2 max_{l != i} ||A_il||_F^2 (the squares summed row by
+ * row, without fused multiply-adds); the first pass splits the graph of
+ * blocks, every row of a node taking the node's type (caller splittings must
+ * do the same); N_i holds every row of the strong F-neighbour nodes, so the
+ * k rows of C-node i solve the same system A(N,N)^T with k right-hand sides;
+ * an F-node takes the identity block from its strong C-neighbour with the
+ * largest block norm (one-point interpolation by block, ties to the first);
+ * the sweeps are block Jacobi, x_X + omega D_X^{-1} (b - A x)_X.  Needs
+ * interp = LAIR_P_ONE_POINT, distance 1 and no lumping; single systems only;
+ * no transposed cycle or solve and no new diagonal (LAIR_EUNSUPPORTED).
+ * Natural ordering on every level. */
+#define LAIR_FLAG_NODAL 8
 
 typedef struct lair_info {
     int32_t iters;           /* V-cycles done                               */

@@ -373,6 +373,19 @@ def node_strength(nrp, ncol, nsq, theta=0.25):
     return sm
 
 
+def node_entry_mask(A, k, nrp, nsm):
+    """The strength mask over A's stored entries: every entry of a strong
+    block (uint8 per entry)."""
+    sm = np.zeros(A.nnz, dtype=np.uint8)
+    for i in range(nrp.shape[0] - 1):
+        for a in range(k):
+            lo = A.indptr[i * k + a]
+            for t, p in enumerate(range(nrp[i], nrp[i + 1])):
+                if nsm[p]:
+                    sm[lo + t * k:lo + (t + 1) * k] = 1
+    return sm
+
+
 def expand_nodes(x_node, k):
     """A per-node array repeated for each of the node's k rows."""
     return np.repeat(np.asarray(x_node), k)
@@ -638,15 +651,7 @@ def _setup_nodal(A, k, cf_levels, theta, theta_c, max_levels, max_coarse, stall)
         L.cf = cf
         L.node_graph = (nrp, ncol, nsq)
         L.nsmask = nsm
-        # the strength mask over A's stored entries: every entry of a strong
-        # block
-        L.smask = np.zeros(Al.nnz, dtype=np.uint8)
-        for i in range(n // k):
-            for a in range(k):
-                lo = Al.indptr[i * k + a]
-                for t, p in enumerate(range(nrp[i], nrp[i + 1])):
-                    if nsm[p]:
-                        L.smask[lo + t * k:lo + (t + 1) * k] = 1
+        L.smask = node_entry_mask(Al, k, nrp, nsm)
         L.cidx, L.cpts = coarse_index(cf)
         cpts, L.nptr, L.nbr = node_neighbourhoods(nrp, ncol, nsm, cf_node, k)
         assert np.array_equal(cpts, L.cpts)

@@ -302,18 +302,20 @@ def _cf_levels(cf_levels, keep):
 
 
 def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels,
-            max_coarse, stall, block_size, graphs, ordering="auto", lump_tol=0.0):
+            max_coarse, stall, block_size, graphs, ordering="auto", lump_tol=0.0,
+            nodal=False):
     s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
                    _KINDS[kind], _DIST[distance])
     o = L.Options(_INTERP[interp], _PREC[precision], float(omega), int(max_levels),
                   int(max_coarse), float(stall), int(block_size),
-                  (0 if graphs else L.FLAG_NO_GRAPH) | _ORDERING[ordering],
+                  (0 if graphs else L.FLAG_NO_GRAPH) | _ORDERING[ordering] |
+                  (L.FLAG_NODAL if nodal else 0),
                   float(lump_tol))
     opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
                 interp=interp, precision=precision, omega=omega,
                 max_levels=max_levels, max_coarse=max_coarse, stall=stall,
                 block_size=block_size, graphs=graphs, ordering=ordering,
-                lump_tol=lump_tol)
+                lump_tol=lump_tol, nodal=nodal)
     return s, o, opts
 
 
@@ -366,7 +368,7 @@ def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
 def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
           kind="abs", distance=1, interp="one_point", precision="fp64",
           omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
-          graphs=True, ordering="auto", lump_tol=0.0, stream=None):
+          graphs=True, ordering="auto", lump_tol=0.0, nodal=False, stream=None):
     """Build a hierarchy for the CSR matrix (rowptr, col, val).
 
     The arrays may be NumPy arrays (host) or contiguous CUDA tensors
@@ -377,13 +379,15 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
     large sparse levels, "natural" on the natural matrices everywhere,
     "split" renumbers every level but the coarsest; the results are bitwise
     the same.  lump_tol > 0 lumps every coarse operator (Sec. 3.3).
+    nodal=True with block_size=k builds the hierarchy by k x k blocks (the
+    nodal treatment of Sec. 4.2) instead of scaling by the block diagonal.
     """
     lib = L.load()
     keep = []
     A, n = _csr(rowptr, col, val, keep)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
                          max_levels, max_coarse, stall, block_size, graphs, ordering,
-                         lump_tol)
+                         lump_tol, nodal)
     cfp = _cf_levels(cf_levels, keep)
     out = ctypes.c_void_p()
     st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),

@@ -22,6 +22,7 @@ FP64, MIXED, MIXED_LOCAL = 0, 1, 2
 FLAG_NO_GRAPH = 1
 FLAG_NATURAL_ORDER = 2
 FLAG_SPLIT_ALL = 4
+FLAG_NODAL = 8
 
 
 class Csr(ctypes.Structure):

@@ -83,6 +83,11 @@ struct Level {
     bool split = false;
     // size-bucket edges (and the fused flag) the local solves used here
     int32_t buckets[5] = {0, 0, 0, 0, 0};
+    // nodal hierarchy (k x k blocks): inverses of the diagonal blocks, the
+    // values of D^{-1} A on A's pattern (double and float) that the block
+    // Jacobi sweeps read, and the sweeps' right-hand side D^{-1} b
+    DevArr<double> ndinv, av, bt;
+    DevArr<float> av32, bt32;
 };
 
 }  // namespace lair
@@ -155,6 +160,13 @@ using Clock = std::chrono::steady_clock;
 static double ms_since(Clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
+
+// block_size k with the nodal flag builds the hierarchy by blocks; without
+// it the system is scaled by its block diagonal first
+static bool nodal(const lair_options &o) {
+    return o.block_size > 0 && (o.flags & LAIR_FLAG_NODAL) != 0;
+}
+static bool scaled(const lair_options &o) { return o.block_size > 0 && !nodal(o); }
 
 static int32_t team_of(const DevCSR &M) {
     double mean = M.nrows ? (double)M.nnz / (double)M.nrows : 1.0;
@@ -445,8 +457,17 @@ static void check_options(const lair_strength *s, const lair_options *o) {
     if (o->max_coarse < 1) fail(LAIR_EINVAL, "max_coarse must be >= 1");
     if (!(o->stall > 0.0 && o->stall <= 1.0)) fail(LAIR_EINVAL, "stall must lie in (0, 1]");
     if (o->block_size < 0 || o->block_size > 8) fail(LAIR_EINVAL, "block_size must lie in [0, 8]");
-    if (o->flags & ~(LAIR_FLAG_NO_GRAPH | LAIR_FLAG_NATURAL_ORDER | LAIR_FLAG_SPLIT_ALL))
+    if (o->flags & ~(LAIR_FLAG_NO_GRAPH | LAIR_FLAG_NATURAL_ORDER | LAIR_FLAG_SPLIT_ALL |
+                     LAIR_FLAG_NODAL))
         fail(LAIR_EINVAL, "unknown option flags 0x%x", o->flags);
+    if (o->flags & LAIR_FLAG_NODAL) {
+        if (o->block_size < 1) fail(LAIR_EINVAL, "the nodal treatment needs block_size >= 1");
+        if (o->interp != LAIR_P_ONE_POINT)
+            fail(LAIR_EUNSUPPORTED, "the nodal treatment interpolates by one point");
+        if (s->distance != 1) fail(LAIR_EUNSUPPORTED, "the nodal treatment uses distance 1");
+        if (o->lump_tol > 0.0)
+            fail(LAIR_EUNSUPPORTED, "lumping would break the dense blocks of a nodal hierarchy");
+    }
     if ((o->flags & LAIR_FLAG_NATURAL_ORDER) && (o->flags & LAIR_FLAG_SPLIT_ALL))
         fail(LAIR_EINVAL, "NATURAL_ORDER and SPLIT_ALL exclude each other");
     if (!(o->lump_tol >= 0.0 && o->lump_tol <= 1.0))
@@ -470,9 +491,24 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     const int32_t n = Lv.n;
     const DevCSR &A = Lv.A;
     double mean = n ? (double)A.nnz / n : 1.0;
+    const bool nod = nodal(h->opt);
+    const int32_t kb = h->opt.block_size;
+    if (nod) {
+        // every level of a nodal hierarchy stores dense blocks (the Galerkin
+        // product of dense blocks with identity-block P keeps them); the
+        // kernels below index by that layout, so it is checked first
+        if (n % kb != 0) fail(LAIR_EINVAL, "level %d: n = %d is not whole nodes", lvl, n);
+        if (!node_check(n, kb, A.rp.get(), A.cj.get(), s))
+            fail(LAIR_EINVAL, "level %d: the nodal treatment needs the k rows of a node to store "
+                 "the same whole dense blocks", lvl);
+    }
     Lv.smask.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
-    launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta, h->str.kind,
-                    Lv.smask.get(), mean, s);
+    if (nod)
+        launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta,
+                             Lv.smask.get(), s);
+    else
+        launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta, h->str.kind,
+                        Lv.smask.get(), mean, s);
     Lv.cf.alloc((size_t)n, s);
     if (cfl && lvl < cfl->nlevels) {
         int64_t lo = cfl->offs[lvl], hi = cfl->offs[lvl + 1];
@@ -488,8 +524,12 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         DevArr<uint8_t> smc;
         if (h->str.theta_c != h->str.theta) {
             smc.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
-            launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
-                            h->str.kind, smc.get(), mean, s);
+            if (nod)
+                launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
+                                     smc.get(), s);
+            else
+                launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
+                                h->str.kind, smc.get(), mean, s);
             sm_dev = smc.get();
         }
         std::vector<int32_t> hrp((size_t)n + 1), hcj((size_t)A.nnz);
@@ -501,7 +541,27 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
             LAIR_HIP(hipMemcpyAsync(hsm.data(), sm_dev, (size_t)A.nnz, hipMemcpyDeviceToHost, s));
         }
         LAIR_HIP(hipStreamSynchronize(s));
-        rs_first_pass(n, hrp.data(), hcj.data(), hsm.data(), hcf.data());
+        if (nod) {
+            // the first pass on the graph of blocks (node i's first row, one
+            // entry per block), each node's type given to its k rows
+            const int32_t nn = n / kb;
+            std::vector<int32_t> nrp((size_t)nn + 1, 0), ncj;
+            std::vector<uint8_t> nsm;
+            ncj.reserve((size_t)A.nnz / kb / kb + 1);
+            nsm.reserve((size_t)A.nnz / kb / kb + 1);
+            for (int32_t i = 0; i < nn; ++i) {
+                for (int32_t p = hrp[(size_t)i * kb]; p < hrp[(size_t)i * kb + 1]; p += kb) {
+                    ncj.push_back(hcj[p] / kb);
+                    nsm.push_back(hsm[p]);
+                }
+                nrp[i + 1] = (int32_t)ncj.size();
+            }
+            std::vector<int8_t> ncf((size_t)nn);
+            rs_first_pass(nn, nrp.data(), ncj.data(), nsm.data(), ncf.data());
+            for (int32_t r = 0; r < n; ++r) hcf[r] = ncf[r / kb];
+        } else {
+            rs_first_pass(n, hrp.data(), hcj.data(), hsm.data(), hcf.data());
+        }
         LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), hcf.data(), (size_t)n, hipMemcpyHostToDevice, s));
         LAIR_HIP(hipStreamSynchronize(s));
     }
@@ -659,8 +719,12 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         pcol.alloc((size_t)n, s);
         {
             ProfScope ps("interp", s, 13.0 * A.nnz + 9.0 * n);
-            launch_interp_one_point(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
-                                    Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
+            if (nod)
+                launch_interp_1p_node(n, kb, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                      Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
+            else
+                launch_interp_one_point(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
+                                        Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
         }
         DevArr<int32_t> has;
         has.alloc((size_t)n, s);
@@ -861,7 +925,8 @@ constexpr int32_t SPLIT_MIN_ROWS = 65536;
 static void build_split(lair_hierarchy *h, hipStream_t s) {
     const size_t nL = h->L.size();
     const bool mixed = h->opt.precision == LAIR_MIXED;
-    const bool allowed = h->nsys == 1 && nL > 1 && !(h->opt.flags & LAIR_FLAG_NATURAL_ORDER);
+    const bool allowed = h->nsys == 1 && nL > 1 && !(h->opt.flags & LAIR_FLAG_NATURAL_ORDER) &&
+                         !nodal(h->opt);
     const bool all = (h->opt.flags & LAIR_FLAG_SPLIT_ALL) != 0;
     bool prev = allowed;
     for (size_t l = 0; l < nL; ++l) {
@@ -932,6 +997,33 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
 static void finish_cycle_operators(lair_hierarchy *h, hipStream_t s) {
     build_split(h, s);
     const bool mixed = h->opt.precision == LAIR_MIXED;
+    if (nodal(h->opt)) {
+        // block Jacobi: D^{-1} of every level's diagonal blocks and the
+        // values of D^{-1} A, read by the sweeps as a scalar Jacobi on them
+        const int32_t k = h->opt.block_size;
+        DevArr<int32_t> bad;
+        bad.alloc(1, s);
+        LAIR_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int32_t), s));
+        for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+            Level &Lv = *h->L[l];
+            const int32_t nblk = Lv.n / k;
+            Lv.ndinv.alloc((size_t)std::max(nblk, 1) * k * k, s);
+            launch_block_inverse(nblk, k, Lv.A.rp.get(), Lv.A.cj.get(), Lv.A.v.get(),
+                                 Lv.ndinv.get(), bad.get(), s);
+            Lv.av.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+            launch_node_scale(Lv.n, k, Lv.A.rp.get(), Lv.A.v.get(), Lv.ndinv.get(), Lv.av.get(),
+                              s);
+            if (mixed) {
+                Lv.av32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
+                launch_to_float(Lv.av.get(), Lv.av32.get(), Lv.A.nnz, s);
+            }
+        }
+        int32_t hb = 0;
+        Readback rb(s);
+        rb.add(&hb, bad.get(), sizeof(int32_t));
+        rb.run();
+        if (hb) fail(LAIR_ESINGULAR, "a %dx%d diagonal block of a nodal level is singular", k, k);
+    }
     for (size_t l = 0; l < h->L.size(); ++l) {
         Level &Lv = *h->L[l];
         if (l + 1 < h->L.size() && !Lv.split && !Lv.cjt.get()) {
@@ -1030,7 +1122,18 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
     L0->max_row = validate_csr(n, nnz, A.rp.get(), A.cj.get(), A.v.get(), s);
     A.max_row = L0->max_row;
 
-    if (opt->block_size > 0) {
+    if (nodal(*opt) && cfl && cfl->nlevels > 0) {
+        // the caller's splittings must give the k rows of a node one type
+        const int32_t k = opt->block_size;
+        for (int32_t l = 0; l < cfl->nlevels; ++l) {
+            const int64_t lo = cfl->offs[l], hi = cfl->offs[l + 1];
+            if ((hi - lo) % k) fail(LAIR_EINVAL, "CF splitting of level %d is not whole nodes", l);
+            for (int64_t q = lo; q < hi; ++q)
+                if (cfl->cf[q] != cfl->cf[lo + (q - lo) / k * k])
+                    fail(LAIR_EINVAL, "CF splitting of level %d splits a node", l);
+        }
+    }
+    if (scaled(*opt)) {
         int32_t k = opt->block_size;
         int32_t nblk = n / k;
         h->dinv.alloc((size_t)nblk * k * k, s);
@@ -1155,7 +1258,14 @@ static void ensure_vectors(lair_hierarchy *h, int32_t nrhs, hipStream_t s) {
     }
     size_t n0 = (size_t)h->L[0]->n * nrhs;
     h->r0.alloc(n0, s);
-    if (h->opt.block_size > 0) h->bscaled.alloc(n0, s);
+    if (scaled(h->opt)) h->bscaled.alloc(n0, s);
+    if (nodal(h->opt))
+        for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+            Level &Lv = *h->L[l];
+            size_t n = (size_t)std::max(Lv.n, 1) * nrhs;
+            Lv.bt.alloc(n, s);
+            if (mixed) Lv.bt32.alloc(n, s);
+        }
     if (mixed) {
         h->r0_32.alloc(n0, s);
         h->e32.alloc(n0, s);
@@ -1241,6 +1351,20 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
                 hipStream_t s) {
     const bool split = Lv.split;
     CsrView<VT> A = view<VT>(split ? Lv.As : Lv.A, Lv.team_A);
+    if (nodal(h->opt)) {
+        // block Jacobi x_X + D_X^{-1} (b - A x)_X is the scalar Jacobi sweep
+        // on D^{-1} A (unit diagonal blocks) with right-hand side D^{-1} b
+        VT *bt = vec<VT>(Lv.bt, Lv.bt32);
+        {
+            ProfScope ps("jacobi", s, 8.0 * Lv.n * h->opt.block_size +
+                                          2.0 * sizeof(VT) * nrhs * Lv.n,
+                         2.0 * Lv.n * h->opt.block_size * nrhs);
+            op_node_rhs<VT>(Lv.n, h->opt.block_size, nrhs, Lv.ndinv.get(), b, bt, s);
+        }
+        b = bt;
+        if constexpr (std::is_same<VT, double>::value) A.v = Lv.av.get();
+        else A.v = Lv.av32.get();
+    }
     VT *y = vec<VT>(Lv.t, Lv.t32);
     double om = h->opt.omega;
     const int w = sizeof(VT);
@@ -1479,7 +1603,7 @@ static lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     Level &L0 = *h->L[0];
     const int64_t n = L0.n;
     const double *bb = b;
-    if (h->opt.block_size > 0 && !transpose) {
+    if (scaled(h->opt) && !transpose) {
         op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
                        h->bscaled.get(), nrhs, s);
         bb = h->bscaled.get();
@@ -1615,7 +1739,7 @@ static lair_status solve_fgmres_impl(lair_hierarchy *h, const double *b, double 
     const bool mixed = h->opt.precision == LAIR_MIXED;
     const bool split = L0.split;
     const double *bb = b;
-    if (h->opt.block_size > 0) {
+    if (scaled(h->opt)) {
         op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
                        h->bscaled.get(), nrhs, s);
         bb = h->bscaled.get();
@@ -1960,7 +2084,7 @@ static lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *
         ~ActGuard() { h->use_act = false; }
     } act_guard{h};
     const double *bb = b;
-    if (h->opt.block_size > 0) {
+    if (scaled(h->opt)) {
         op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
                        h->bscaled.get(), 1, s);
         bb = h->bscaled.get();
@@ -2104,8 +2228,10 @@ __global__ void k_set_diag(int32_t n, const int32_t *rp, const int32_t *cj, doub
 static void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_device,
                              hipStream_t s) {
     if (!h || !diag) fail(LAIR_EINVAL, "hierarchy and diag must not be NULL");
-    if (h->opt.block_size > 0)
+    if (scaled(h->opt))
         fail(LAIR_EUNSUPPORTED, "a new diagonal changes the block scaling: set up again");
+    if (nodal(h->opt))
+        fail(LAIR_EUNSUPPORTED, "a new diagonal on a nodal hierarchy: set up again");
     if (h->opt.lump_tol > 0.0)
         fail(LAIR_EUNSUPPORTED, "lumped coarse patterns depend on the values: set up again");
     h->stream = s;
@@ -2179,6 +2305,7 @@ static lair_hierarchy *setup_batch_impl(int32_t nsys, const lair_csr *sys,
     if (nsys < 1) fail(LAIR_EINVAL, "nsys must be >= 1");
     if (!sys) fail(LAIR_EINVAL, "the system array must not be NULL");
     check_options(str, opt);
+    if (nodal(*opt)) fail(LAIR_EUNSUPPORTED, "batches are not built by nodes");
     std::vector<int64_t> seg((size_t)nsys + 1, 0), nzo((size_t)nsys + 1, 0);
     const int32_t dev = sys[0].on_device;
     for (int32_t q = 0; q < nsys; ++q) {
@@ -2387,7 +2514,7 @@ lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
         ensure_vectors(h, nrhs, s);
         const double *bb = b;
         int64_t n = h->L[0]->n;
-        if (h->opt.block_size > 0) {
+        if (scaled(h->opt)) {
             op_block_apply(n / h->opt.block_size, h->opt.block_size, h->dinv.get(), b,
                            h->bscaled.get(), nrhs, s);
             bb = h->bscaled.get();
@@ -2419,6 +2546,7 @@ lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g, double *lam
         if (!h || !g || !lam) fail(LAIR_EINVAL, "NULL argument");
         check_nrhs(h, nrhs);
         hipStream_t s = (hipStream_t)stream;
+        if (nodal(h->opt)) fail(LAIR_EUNSUPPORTED, "transposed cycle on a nodal hierarchy");
         ensure_vectors(h, nrhs, s);
         ensure_transposes(h);
         // lam <- lam + B^T (g - A^T lam)
@@ -2444,8 +2572,10 @@ lair_status lair_solve_transpose(lair_hierarchy *h, const double *g, double *lam
                                  int32_t nrhs, double rtol, int32_t maxit,
                                  lair_info *info, void *stream) {
     return guarded([&]() -> lair_status {
-        if (h && h->opt.block_size > 0)
+        if (h && scaled(h->opt))
             fail(LAIR_EUNSUPPORTED, "transposed solve with block scaling");
+        if (h && nodal(h->opt))
+            fail(LAIR_EUNSUPPORTED, "transposed solve on a nodal hierarchy");
         return solve_impl(h, g, lam, nrhs, rtol, maxit, info, (hipStream_t)stream, true);
     });
 }

@@ -400,6 +400,29 @@ void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
                     const double *b, double *out, int32_t nrhs, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Nodal treatment of k x k blocks (k_nodal.hip).  The matrix is scalar CSR
+// whose k rows of a node store the same whole dense blocks.
+// ---------------------------------------------------------------------------
+// true when every row of every node stores its node's whole dense blocks
+// (waits for the answer)
+bool node_check(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj, hipStream_t s);
+// smask over A's entries: every entry of a block with
+// ||A_ij||_F^2 >= theta^2 max_{l != i} ||A_il||_F^2 (nonzero)
+void launch_node_strength(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj,
+                          const double *v, double theta, uint8_t *smask, hipStream_t s);
+// one-point interpolation by block: pcol[r] = coarse column of row r or -1
+void launch_interp_1p_node(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj,
+                           const double *v, const uint8_t *smask, const int8_t *cf,
+                           const int32_t *cidx, int32_t *pcol, hipStream_t s);
+// out = D^{-1} A on A's pattern (dinv: the inverse diagonal blocks)
+void launch_node_scale(int32_t n, int32_t k, const int32_t *rp, const double *v,
+                       const double *dinv, double *out, hipStream_t s);
+// out = D^{-1} b for nrhs interleaved right-hand sides
+template <class VT>
+void op_node_rhs(int32_t n, int32_t k, int32_t nrhs, const double *dinv, const VT *b, VT *out,
+                 hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Batch kernels (k_batch.hip)
 // ---------------------------------------------------------------------------
 struct SysCsr {

@@ -1,0 +1,185 @@
+"""GPU: nodal (block) lAIR (LAIR_FLAG_NODAL, Sec. 3.1 block form of
+Eq. (system), Sec. 4.2 treatment (iii)) against the oracle's nodal setup.
+
+Level by level on the GPU's own A_l: strength masks, node splittings,
+neighbourhoods, fallback flags and the R, P and K patterns bit-exact; each
+row of Z within 1e-12 of its largest entry; K within 1e-12 of the scale of
+the terms summed; the same number of cycles to 1e-10 and the solution
+within 1e-8.  Cases: a Kronecker product ADR (x) B (k = 3), a perturbed
+dense-block matrix (k = 2), and P2 upwind DG along a curved field (k = 6).
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import lair as O
+from tests.parity import gpu_A, gpu_level_csr, rows_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lair():
+    import torch
+    import paper_1708_06065_amd as lair
+    assert torch.cuda.is_available()
+    lair.load_library()
+    return lair
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _adr(m):
+    w = W.workload_c4(m)
+    A = (O.csr(w["rowptr"], w["col"], w["val"]) + sp.diags(w["c"])).tocsr()
+    A.sort_indices()
+    return A, w["rhs"]
+
+
+def _case(name):
+    if name == "kron3":
+        As, bs = _adr(20)
+        B = np.random.default_rng(0).standard_normal((3, 3)) + 3.0 * np.eye(3)
+        A = sp.kron(As, sp.csr_matrix(B)).tocsr()
+        A.sort_indices()
+        return A, np.kron(bs, [1.0, -2.0, 0.5]), 3
+    if name == "perturbed2":
+        As, bs = _adr(24)
+        rng = np.random.default_rng(1)
+        B = rng.standard_normal((2, 2)) + 3.0 * np.eye(2)
+        A = sp.kron(As, sp.csr_matrix(B)).tocsr()
+        A.sort_indices()
+        A.data = A.data * (1.0 + 0.3 * rng.standard_normal(A.nnz))
+        return A, np.kron(bs, [1.0, 1.0]), 2
+    w = W.workload_dg_curved(16)
+    return O.csr(w["rowptr"], w["col"], w["val"]), w["rhs"], 6
+
+
+def compare_nodal_level(h, l, k, theta=0.25, cf=None):
+    A = gpu_A(h, l)
+    n = A.shape[0]
+    nrp, ncol, nsq = O.node_graph(A, k)
+    nsm = O.node_strength(nrp, ncol, nsq, theta)
+    assert np.array_equal(O.node_entry_mask(A, k, nrp, nsm), h.export(l, "smask")), \
+        "strength mask differs at level %d" % l
+    if cf is None:
+        G = O.csr(nrp.astype(np.int32), ncol, np.ones(ncol.shape[0]), shape=(n // k,) * 2)
+        cf_node = O.rs_split(G, nsm)
+    else:
+        cf_node = np.asarray(cf, dtype=np.int8)[::k]
+    cf_o = O.expand_nodes(cf_node, k).astype(np.int8)
+    assert np.array_equal(cf_o, h.export(l, "cf")), "CF splitting differs at level %d" % l
+    cpts, nptr, nbr = O.node_neighbourhoods(nrp, ncol, nsm, cf_node, k)
+    assert np.array_equal(nptr.astype(np.int32), h.export(l, "nbr_ptr"))
+    assert np.array_equal(nbr.astype(np.int32), h.export(l, "nbr"))
+    z, flags = O.node_local_solves(A, k, cpts, nptr, nbr)
+    assert np.array_equal(flags.astype(np.int8), h.export(l, "flags"))
+    R = O.restriction(n, cpts, nptr, nbr, z)
+    rrp, rcj, rv = gpu_level_csr(h, l, "R")
+    assert np.array_equal(R.indptr.astype(np.int32), rrp)
+    assert np.array_equal(R.indices.astype(np.int32), rcj)
+    z_err = rows_rel_err(rrp, rv, R.data)
+    assert z_err <= 1e-12, "R values differ by %g at level %d" % (z_err, l)
+    P = O.node_interp_one_point(nrp, ncol, nsq, nsm, cf_node, k)
+    prp, pcj, pv = gpu_level_csr(h, l, "P")
+    assert np.array_equal(P.indptr.astype(np.int32), prp)
+    assert np.array_equal(P.indices.astype(np.int32), pcj)
+    assert np.array_equal(pv, P.data)
+    K = O.galerkin(R, A, P)
+    scale = O.galerkin(abs(R), abs(A), abs(P))
+    Kg = gpu_A(h, l + 1)
+    assert np.array_equal(K.indptr, Kg.indptr) and np.array_equal(K.indices, Kg.indices)
+    assert np.all(np.abs(Kg.data - K.data) <= 1e-12 * scale.data + 1e-300)
+    return z_err
+
+
+@pytest.mark.parametrize("name", ["kron3", "perturbed2", "dg_curved"])
+@pytest.mark.parametrize("own_split", [False, True])
+def test_nodal_levels_and_iterations(lair, name, own_split):
+    _say("case: nodal", name, "own split" if own_split else "oracle split")
+    A, b, k = _case(name)
+    H = O.setup(A, block=k)
+    cfl = None if own_split else [L.cf for L in H.levels[:-1]]
+    h = lair.setup(A.indptr, A.indices, A.data, cf_levels=cfl, block_size=k, nodal=True)
+    assert h.nlevels == H.nlevels
+    for l in range(h.nlevels - 1):
+        compare_nodal_level(h, l, k, cf=None if cfl is None else cfl[l])
+    x, info = h.solve(_dev(b), rtol=1e-10)
+    xo, ito, _ = O.solve(H, b, rtol=1e-10)
+    _say("  levels", h.nlevels, "iters", info["iters"], ito)
+    assert info["converged"] and info["iters"] == ito
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    h.free()
+
+
+def test_nodal_cycle_matches_oracle(lair):
+    """Single cycles from a nonzero iterate, 4 right-hand sides at once."""
+    A, b, k = _case("dg_curved")
+    H = O.setup(A, block=k)
+    h = lair.setup(A.indptr, A.indices, A.data, cf_levels=[L.cf for L in H.levels[:-1]],
+                   block_size=k, nodal=True)
+    rng = np.random.default_rng(5)
+    n = A.shape[0]
+    B = rng.standard_normal((n, 4))
+    X0 = rng.standard_normal((n, 4))
+    X = _dev(X0)
+    h.cycle(_dev(B), X)
+    X = X.cpu().numpy()
+    for q in range(4):
+        xo = O.cycle(H, B[:, q], X0[:, q].copy())
+        assert np.linalg.norm(X[:, q] - xo) <= 1e-11 * np.linalg.norm(xo)
+    h.free()
+
+
+def test_nodal_mixed_and_fgmres(lair):
+    A, b, k = _case("dg_curved")
+    H = O.setup(A, block=k)
+    cfl = [L.cf for L in H.levels[:-1]]
+    _, ito, _ = O.solve(H, b, rtol=1e-10)
+    hm = lair.setup(A.indptr, A.indices, A.data, cf_levels=cfl, block_size=k, nodal=True,
+                    precision="mixed")
+    x, info = hm.solve(_dev(b), rtol=1e-10)
+    _say("  mixed iters", info["iters"], "oracle", ito)
+    assert info["converged"] and ito <= info["iters"] <= ito + 1
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+    hm.free()
+    h = lair.setup(A.indptr, A.indices, A.data, cf_levels=cfl, block_size=k, nodal=True)
+    xo, itg, _, _ = O.fgmres_cycle(H, b, rtol=1e-10, restart=20)
+    x, info = h.solve_fgmres(_dev(b), rtol=1e-10, restart=20)
+    _say("  fgmres steps", info["iters"], "oracle", itg)
+    assert info["converged"] and info["iters"] == itg
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    h.free()
+
+
+def test_nodal_argument_errors(lair):
+    A, b, k = _case("perturbed2")
+    with pytest.raises(Exception):      # one-point interpolation only
+        lair.setup(A.indptr, A.indices, A.data, block_size=k, nodal=True, interp="direct")
+    with pytest.raises(Exception):      # no lumping
+        lair.setup(A.indptr, A.indices, A.data, block_size=k, nodal=True, lump_tol=1e-3)
+    Ad, _ = _adr(12)                     # scalar ADR: rows do not store whole 2 x 2 blocks
+    with pytest.raises(Exception):
+        lair.setup(Ad.indptr, Ad.indices, Ad.data, block_size=2, nodal=True)
+    H = O.setup(A, block=k)
+    cf = H.levels[0].cf.copy()
+    cf[1] = 1 - cf[1]                    # splits node 0
+    with pytest.raises(Exception):
+        lair.setup(A.indptr, A.indices, A.data, cf_levels=[cf], block_size=k, nodal=True)
+    h = lair.setup(A.indptr, A.indices, A.data, block_size=k, nodal=True)
+    with pytest.raises(Exception):
+        h.update_diag(A.diagonal())
+    with pytest.raises(Exception):
+        h.solve_transpose(_dev(b))
+    h.free()

@@ -218,3 +218,27 @@ def workload_c2(m=256):
     w = upwind_dg_p2(m)
     w["name"] = "dg_p2_recirculating_%dx%dx2" % (m, m)
     return w
+
+
+def dense_blocks(w, k=6):
+    """The same system stored with whole dense k x k blocks (explicit zeros
+    where a coupling block has structural zeros): the layout a nodal
+    hierarchy reads."""
+    A = sp.csr_matrix((w["val"], w["col"], w["rowptr"]), shape=(w["n"],) * 2)
+    B = sp.bsr_matrix(A, blocksize=(k, k)).tocsr()
+    B.sort_indices()
+    return dict(w, rowptr=B.indptr.astype(np.int32), col=B.indices.astype(np.int32),
+                val=B.data.astype(np.float64), nnz=int(B.nnz))
+
+
+def workload_dg_curved(m=256):
+    """Pure advection along the curved, divergence-free field
+    b = (y^2, cos^2(pi x / 2)) (the advective field of the paper's DGu
+    problem, Sec. 4.2, without its diffusion), P2 upwind DG on m x m x 2
+    triangles, stored in dense 6 x 6 blocks.  Every streamline enters at
+    x = 0 or y = 0 and leaves, so the steady problem is well posed."""
+    def velocity(x, y):
+        return y * y, np.cos(0.5 * np.pi * x) ** 2
+    w = dense_blocks(upwind_dg_p2(m, velocity=velocity))
+    w["name"] = "dg_p2_curved_%dx%dx2" % (m, m)
+    return w
