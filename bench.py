@@ -92,6 +92,12 @@ def make_workload(name):
         return w, dict(interp="direct", distance=1), \
             {"workload": "adr_reaction_64x64", "n": w["n"], "nnz": w["nnz"], "nrhs": 1,
              "distance": 1, "interp": "direct", "rtol": 1e-10}
+    if name == "dg":
+        w = W.workload_dg_curved(256)
+        return w, dict(interp="one_point", distance=1, block_size=6, nodal=True), \
+            {"workload": w["name"], "n": w["n"], "nnz": w["nnz"], "nrhs": 1, "block": 6,
+             "treatment": "nodal", "interp": "one_point by block", "distance": 1,
+             "relaxation": "FFC block Jacobi", "rtol": 1e-10}
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -235,6 +241,10 @@ def main():
 
     if args.no_graphs:
         kw = dict(kw, graphs=False)
+    if kw.get("nodal"):
+        # lumping would break the dense blocks a nodal hierarchy keeps
+        args.lump = 0.0
+        args.no_cpu_baseline = True
     kw = dict(kw, lump_tol=args.lump)
     cfg = dict(cfg, lumping=args.lump)
 
@@ -253,14 +263,17 @@ def main():
     h0.free()
     log("library CF split + setup: %.1f ms, %d levels" % (t_full_setup, nlev))
 
+    # the nodal DG workload needs about a hundred cycles at 256 x 256 x 2
+    maxit = 300 if kw.get("nodal") else 100
+
     def step(precision):
         h = build(cfl, precision)
         if batch:
-            X, info = h.solve_batch(B, rtol=1e-10, maxit=100)
+            X, info = h.solve_batch(B, rtol=1e-10, maxit=maxit)
         elif args.solver == "fgmres":
-            X, info = h.solve_fgmres(B, rtol=1e-10, maxit=100, restart=args.restart)
+            X, info = h.solve_fgmres(B, rtol=1e-10, maxit=maxit, restart=args.restart)
         else:
-            X, info = h.solve(B, rtol=1e-10, maxit=100)
+            X, info = h.solve(B, rtol=1e-10, maxit=maxit)
         return h, X, info
 
     # which kernel category dominates a step: one profiled, untimed step
