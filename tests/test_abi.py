@@ -71,6 +71,29 @@ def test_host_side_validation_without_gpu():
                           ctypes.byref(out)) == L.LAIR_EINVAL
     assert b"lump_tol" in lib.lair_last_error()
     o.lump_tol = 0.0
+    # the nodal treatment: block_size >= 1, one-point interpolation by block,
+    # distance 1, no lumping
+    o.omega = 1.0
+    o.flags = L.FLAG_NODAL
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EINVAL
+    assert b"block_size" in lib.lair_last_error()
+    o.block_size = 2
+    o.interp = 1
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
+    o.interp = 0
+    s.distance = 2
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
+    s.distance = 1
+    o.lump_tol = 1e-3
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
+    assert b"lumping" in lib.lair_last_error()
+    o.lump_tol = 0.0
+    o.flags = 0
+    o.block_size = 0
     o.omega = 0.0
     assert out.value is None
     # NULL hierarchy on every entry point
