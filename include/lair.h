@@ -146,12 +146,13 @@ typedef struct lair_options {
  * ||A_ij||_F^2 >= theta^2 max_{l != i} ||A_il||_F^2 (the squares summed row by
  * row, without fused multiply-adds); the first pass splits the graph of
  * blocks, every row of a node taking the node's type (caller splittings must
- * do the same); N_i holds every row of the strong F-neighbour nodes, so the
+ * do the same); N_i holds every row of the strong F-neighbour nodes (and of
+ * theirs at distance 2, F-F-C paths on the graph of blocks), so the
  * k rows of C-node i solve the same system A(N,N)^T with k right-hand sides;
  * an F-node takes the identity block from its strong C-neighbour with the
  * largest block norm (one-point interpolation by block, ties to the first);
  * the sweeps are block Jacobi, x_X + omega D_X^{-1} (b - A x)_X.  Needs
- * interp = LAIR_P_ONE_POINT, distance 1 and no lumping; single systems only;
+ * interp = LAIR_P_ONE_POINT, distance 1 or 2 and no lumping; single systems only;
  * no transposed cycle or solve and no new diagonal (LAIR_EUNSUPPORTED).
  * Natural ordering on every level. */
 #define LAIR_FLAG_NODAL 8

@@ -391,20 +391,24 @@ def expand_nodes(x_node, k):
     return np.repeat(np.asarray(x_node), k)
 
 
-def node_neighbourhoods(nrp, ncol, nsm, cf_node, k):
-    """N_i of every C-node (its strong F-neighbour nodes, distance one),
+def node_neighbourhoods(nrp, ncol, nsm, cf_node, k, distance=1):
+    """N_i of every C-node on the graph of blocks: its strong F-neighbour
+    nodes, and at distance two also theirs (F-F-C paths only, Sec. 4),
     given per C-row: every row of C-node i gets the k rows of each node of
     N_i, ascending.  Returns (cpts, nptr, nbr) over the rows of A."""
     nn = nrp.shape[0] - 1
+
+    def strong_f(i):
+        return [int(ncol[p]) for p in range(nrp[i], nrp[i + 1])
+                if ncol[p] != i and nsm[p] and cf_node[ncol[p]] == 0]
     rows, lists = [], []
     for i in range(nn):
         if cf_node[i] != 1:
             continue
-        nb = []
-        for p in range(nrp[i], nrp[i + 1]):
-            j = ncol[p]
-            if j != i and nsm[p] and cf_node[j] == 0:
-                nb.append(j)
+        nb = set(strong_f(i))
+        if distance == 2:
+            for j in list(nb):
+                nb.update(strong_f(j))
         dof = (np.repeat(np.array(sorted(nb), dtype=np.int64), k) * k +
                np.tile(np.arange(k), len(nb))).astype(np.int32)
         for a in range(k):
@@ -571,14 +575,15 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
     Coarsening stops when n <= max_coarse, when max_levels is reached, when
     no C-point is found, or when n_c > stall * n.  lump_tol > 0 lumps every
     coarse operator (Sec. 3.3; level 0 is the caller's matrix).  block = k
-    builds the hierarchy by k x k blocks (nodal treatment; distance one,
-    one-point interpolation by block, SOC on block norms, block Jacobi).
+    builds the hierarchy by k x k blocks (nodal treatment; distance one or
+    two on the graph of blocks, one-point interpolation by block, SOC on
+    block norms, block Jacobi).
     """
     if theta_c is None:
         theta_c = theta
     if block:
         return _setup_nodal(A, block, cf_levels, theta, theta_c, max_levels,
-                            max_coarse, stall)
+                            max_coarse, stall, distance)
     H = Hierarchy()
     Al = A.tocsr()
     lvl = 0
@@ -621,7 +626,7 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
     return H
 
 
-def _setup_nodal(A, k, cf_levels, theta, theta_c, max_levels, max_coarse, stall):
+def _setup_nodal(A, k, cf_levels, theta, theta_c, max_levels, max_coarse, stall, distance=1):
     H = Hierarchy()
     H.block = k
     Al = A.tocsr()
@@ -653,7 +658,7 @@ def _setup_nodal(A, k, cf_levels, theta, theta_c, max_levels, max_coarse, stall)
         L.nsmask = nsm
         L.smask = node_entry_mask(Al, k, nrp, nsm)
         L.cidx, L.cpts = coarse_index(cf)
-        cpts, L.nptr, L.nbr = node_neighbourhoods(nrp, ncol, nsm, cf_node, k)
+        cpts, L.nptr, L.nbr = node_neighbourhoods(nrp, ncol, nsm, cf_node, k, distance)
         assert np.array_equal(cpts, L.cpts)
         L.z, L.flags = node_local_solves(Al, k, cpts, L.nptr, L.nbr)
         L.R = restriction(n, cpts, L.nptr, L.nbr, L.z)

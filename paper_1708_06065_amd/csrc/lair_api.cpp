@@ -464,7 +464,8 @@ static void check_options(const lair_strength *s, const lair_options *o) {
         if (o->block_size < 1) fail(LAIR_EINVAL, "the nodal treatment needs block_size >= 1");
         if (o->interp != LAIR_P_ONE_POINT)
             fail(LAIR_EUNSUPPORTED, "the nodal treatment interpolates by one point");
-        if (s->distance != 1) fail(LAIR_EUNSUPPORTED, "the nodal treatment uses distance 1");
+        if (s->distance != 1 && s->distance != 2)
+            fail(LAIR_EUNSUPPORTED, "the nodal treatment uses distance 1 or 2");
         if (o->lump_tol > 0.0)
             fail(LAIR_EUNSUPPORTED, "lumping would break the dense blocks of a nodal hierarchy");
     }

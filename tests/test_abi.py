@@ -72,7 +72,7 @@ def test_host_side_validation_without_gpu():
     assert b"lump_tol" in lib.lair_last_error()
     o.lump_tol = 0.0
     # the nodal treatment: block_size >= 1, one-point interpolation by block,
-    # distance 1, no lumping
+    # distance 1 or 2, no lumping
     o.omega = 1.0
     o.flags = L.FLAG_NODAL
     assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
@@ -83,7 +83,7 @@ def test_host_side_validation_without_gpu():
     assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
                           ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
     o.interp = 0
-    s.distance = 2
+    s.distance = 0                       # all F-points: not by nodes
     assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
                           ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
     s.distance = 1

@@ -66,7 +66,7 @@ def _case(name):
     return O.csr(w["rowptr"], w["col"], w["val"]), w["rhs"], 6
 
 
-def compare_nodal_level(h, l, k, theta=0.25, cf=None):
+def compare_nodal_level(h, l, k, theta=0.25, cf=None, distance=1):
     A = gpu_A(h, l)
     n = A.shape[0]
     nrp, ncol, nsq = O.node_graph(A, k)
@@ -80,7 +80,7 @@ def compare_nodal_level(h, l, k, theta=0.25, cf=None):
         cf_node = np.asarray(cf, dtype=np.int8)[::k]
     cf_o = O.expand_nodes(cf_node, k).astype(np.int8)
     assert np.array_equal(cf_o, h.export(l, "cf")), "CF splitting differs at level %d" % l
-    cpts, nptr, nbr = O.node_neighbourhoods(nrp, ncol, nsm, cf_node, k)
+    cpts, nptr, nbr = O.node_neighbourhoods(nrp, ncol, nsm, cf_node, k, distance)
     assert np.array_equal(nptr.astype(np.int32), h.export(l, "nbr_ptr"))
     assert np.array_equal(nbr.astype(np.int32), h.export(l, "nbr"))
     z, flags = O.node_local_solves(A, k, cpts, nptr, nbr)
@@ -118,6 +118,26 @@ def test_nodal_levels_and_iterations(lair, name, own_split):
     x, info = h.solve(_dev(b), rtol=1e-10)
     xo, ito, _ = O.solve(H, b, rtol=1e-10)
     _say("  levels", h.nlevels, "iters", info["iters"], ito)
+    assert info["converged"] and info["iters"] == ito
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    h.free()
+
+
+@pytest.mark.parametrize("name", ["perturbed2", "dg_curved"])
+def test_nodal_distance_two(lair, name):
+    """F-F-C paths on the graph of blocks: the node-expanded strength mask
+    makes the scalar distance-two merge give the nodal sets."""
+    _say("case: nodal distance 2", name)
+    A, b, k = _case(name)
+    H = O.setup(A, block=k, distance=2)
+    h = lair.setup(A.indptr, A.indices, A.data, block_size=k, nodal=True, distance=2)
+    assert h.nlevels == H.nlevels
+    for l in range(h.nlevels - 1):
+        compare_nodal_level(h, l, k, distance=2)
+    x, info = h.solve(_dev(b), rtol=1e-10)
+    xo, ito, _ = O.solve(H, b, rtol=1e-10)
+    _say("  levels", h.nlevels, "iters", info["iters"], ito, "s_max",
+         max(h.level_stats(l)["s_max"] for l in range(h.nlevels - 1)))
     assert info["converged"] and info["iters"] == ito
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
     h.free()

@@ -782,12 +782,13 @@ def _adr(m):
     return A, w["rhs"]
 
 
-def test_nodal_with_unit_blocks_is_scalar_lair():
+@pytest.mark.parametrize("distance", [1, 2])
+def test_nodal_with_unit_blocks_is_scalar_lair(distance):
     """k = 1: block norms are magnitudes, so every step reduces to scalar
-    lAIR with one-point interpolation."""
+    lAIR with one-point interpolation, at distance one and two."""
     A, b = _adr(24)
-    H = O.setup(A, interp=O.INTERP_ONE_POINT)
-    G = O.setup(A, block=1)
+    H = O.setup(A, interp=O.INTERP_ONE_POINT, distance=distance)
+    G = O.setup(A, block=1, distance=distance)
     assert G.nlevels == H.nlevels
     for l in range(H.nlevels - 1):
         assert np.array_equal(G.levels[l].cf, H.levels[l].cf)
@@ -811,7 +812,8 @@ def _kron_case(k=3, m=20, seed=0):
     return As, bs, B, A
 
 
-def test_nodal_kronecker_is_scalar_times_identity():
+@pytest.mark.parametrize("distance", [1, 2])
+def test_nodal_kronecker_is_scalar_times_identity(distance):
     """A = A_s (x) B: the block norms are |a_ij| ||B||_F, so the nodes split
     as the scalar points of A_s; Z_il = z_il I solves the block system
     (z (a B) summed = -a_ij B), so R = R_s (x) I, P = P_s (x) I, K = K_s (x) B,
@@ -819,8 +821,8 @@ def test_nodal_kronecker_is_scalar_times_identity():
     sweep maps x_s: every cycle's iterate is the scalar one (x) B^{-1} w."""
     k = 3
     As, bs, B, A = _kron_case(k)
-    Hs = O.setup(As, interp=O.INTERP_ONE_POINT)
-    Hb = O.setup(A, block=k, max_coarse=128 * k)      # the same stop in nodes
+    Hs = O.setup(As, interp=O.INTERP_ONE_POINT, distance=distance)
+    Hb = O.setup(A, block=k, max_coarse=128 * k, distance=distance)   # the same stop in nodes
     assert Hb.nlevels == Hs.nlevels >= 3
     I = sp.identity(k)
     for l in range(Hs.nlevels - 1):
