@@ -137,6 +137,41 @@ print(json.dumps({"s": el, "done": done, "nnz": nz, "tot": tot, "iters_max": max
                       % (d["done"], d["s"], 100.0 / scale, scale)}
 
 
+def cpu_baseline_nodal(kw, n_full, m_sample=96):
+    """The oracle's nodal setup + solve to 1e-10 on the same DG problem at
+    m_sample x m_sample x 2 triangles (its Python loops over nodes would
+    take minutes at full size), scaled to the full problem by rows.  Child
+    process, one OpenMP thread."""
+    code = r'''
+import json, sys, time
+sys.path.insert(0, %r)
+import workloads as W
+from oracle import lair as O
+w = W.workload_dg_curved(%d)
+A = O.csr(w["rowptr"], w["col"], w["val"])
+t0 = time.perf_counter()
+H = O.setup(A, block=6, distance=%d)
+t1 = time.perf_counter()
+x, it, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=300)
+t2 = time.perf_counter()
+print(json.dumps({"setup_s": t1 - t0, "solve_s": t2 - t1, "iters": it, "n": w["n"]}))
+''' % (ROOT, m_sample, kw["distance"])
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        log("cpu baseline failed:", r.stderr[-2000:])
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    scale = n_full / d["n"]
+    return {"value": 1e3 * (d["setup_s"] + d["solve_s"]) * scale, "unit": "ms", "cores": 1,
+            "kind": "oracle",
+            "sample": "oracle nodal setup (%.1f s) + solve to 1e-10 (%.1f s, %d cycles) of the "
+                      "same problem on %dx%dx2 triangles (%d rows), scaled x%.0f by rows"
+                      % (d["setup_s"], d["solve_s"], d["iters"], m_sample, m_sample, d["n"],
+                         scale)}
+
+
 def cpu_baseline(workload, kw):
     """Time the CPU oracle on a bounded sample: the full setup of the
     workload plus the solve of its first right-hand side; the solve time is
@@ -250,7 +285,6 @@ def main():
     if kw.get("nodal"):
         # lumping would break the dense blocks a nodal hierarchy keeps
         args.lump = 0.0
-        args.no_cpu_baseline = True
     kw = dict(kw, lump_tol=args.lump)
     cfg = dict(cfg, lumping=args.lump)
 
@@ -380,7 +414,12 @@ def main():
         out["speedup_mixed_vs_fp64"] = results["fp64"]["ms"] / r["ms"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        cb = cpu_baseline_batch(kw) if batch else cpu_baseline(args.workload, kw)
+        if batch:
+            cb = cpu_baseline_batch(kw)
+        elif kw.get("nodal"):
+            cb = cpu_baseline_nodal(kw, w["n"])
+        else:
+            cb = cpu_baseline(args.workload, kw)
         if cb:
             out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
