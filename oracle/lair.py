@@ -135,6 +135,50 @@ def rs_split(A, smask):
     return cf
 
 
+def hash32(i):
+    """MurmurHash3's 32-bit finalizer (fmix32, A. Appleby) of the indices:
+    the deterministic tie-breaking weight of the parallel splitting."""
+    h = np.asarray(i, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
+    m = np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    h = (h * np.uint64(0x85EBCA6B)) & m
+    h ^= h >> np.uint64(13)
+    h = (h * np.uint64(0xC2B2AE35)) & m
+    h ^= h >> np.uint64(16)
+    return h
+
+
+def pmis_split(A, smask):
+    """A parallel CF splitting of the PMIS type (De Sterck, Yang and Heys,
+    2006), an alternative to the Ruge-Stueben first pass of Sec. 4 that
+    needs no sequential greedy step.  Weight of point i: the number of
+    points that strongly depend on it, then hash32(i), then i.  Points on
+    which no point strongly depends are F.  Each round, every undecided
+    point whose weight exceeds that of every undecided point it is strongly
+    connected to (either direction) becomes C, then every undecided point
+    that strongly depends on a C-point becomes F.  int8[n], 1 = C, 0 = F."""
+    A = A.tocsr()
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    sm = np.asarray(smask).astype(bool) & (A.indices != rows)
+    sj, si = rows[sm], A.indices[sm]            # j strongly depends on i
+    cnt = np.bincount(si, minlength=n).astype(np.uint64)
+    key = (cnt << np.uint64(32)) | hash32(np.arange(n))
+    state = np.where(cnt == 0, 0, -1).astype(np.int8)
+    while (state == -1).any():
+        und = state == -1
+        cand = und.copy()
+        live = und[sj] & und[si]
+        a, b = sj[live], si[live]
+        b_wins = (key[b] > key[a]) | ((key[b] == key[a]) & (b > a))
+        cand[a[b_wins]] = False
+        cand[b[~b_wins]] = False
+        state[cand] = 1
+        hit = (state[sj] == -1) & (state[si] == 1)
+        state[sj[hit]] = 0
+    return state
+
+
 def coarse_index(cf):
     """C-points numbered in increasing fine index; -1 for F-points."""
     cf = np.asarray(cf)
@@ -567,7 +611,7 @@ def lump(K, theta_d):
 
 def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
           distance=1, interp=INTERP_ONE_POINT, max_levels=25, max_coarse=128,
-          stall=0.9, lump_tol=0.0, block=0):
+          stall=0.9, lump_tol=0.0, block=0, split="rs"):
     """Build the lAIR hierarchy.
 
     cf_levels: optional list of per-level CF splits (int8 arrays, 1 = C);
@@ -577,7 +621,8 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
     coarse operator (Sec. 3.3; level 0 is the caller's matrix).  block = k
     builds the hierarchy by k x k blocks (nodal treatment; distance one or
     two on the graph of blocks, one-point interpolation by block, SOC on
-    block norms, block Jacobi).
+    block norms, block Jacobi).  split="pmis" takes the parallel splitting
+    of pmis_split instead of the Ruge-Stueben first pass.
     """
     if theta_c is None:
         theta_c = theta
@@ -599,7 +644,7 @@ def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,
             cf = np.ascontiguousarray(cf_levels[lvl], dtype=np.int8)
         else:
             sm_c = L.smask if theta_c == theta else strength(Al, theta_c, kind)
-            cf = rs_split(Al, sm_c)
+            cf = pmis_split(Al, sm_c) if split == "pmis" else rs_split(Al, sm_c)
         nc = int((cf == 1).sum())
         if nc == 0 or nc > stall * n:
             del L.smask

@@ -910,3 +910,78 @@ def test_nodal_rejects_blocks_that_are_not_dense():
     A, _ = _adr(8)
     with pytest.raises(ValueError):
         O.node_graph(A, 2)
+
+
+# --------------------------------------------------------------------------
+# Parallel (PMIS-type) CF splitting
+# --------------------------------------------------------------------------
+
+def test_hash32_published_values():
+    """fmix32 of MurmurHash3: 0 maps to 0; the finalizer is a bijection on
+    32-bit words (no two of 2^16 inputs collide); a hand-worked value."""
+    assert int(O.hash32(0)) == 0
+    h = O.hash32(np.arange(1 << 16))
+    assert np.unique(h).shape[0] == 1 << 16
+    x = 1
+    x ^= x >> 16
+    x = (x * 0x85EBCA6B) & 0xFFFFFFFF
+    x ^= x >> 13
+    x = (x * 0xC2B2AE35) & 0xFFFFFFFF
+    x ^= x >> 16
+    assert int(O.hash32(1)) == x
+
+
+def _strong_pairs(A, sm):
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    s = sm.astype(bool) & (A.indices != rows)
+    return rows[s], A.indices[s]                  # j strongly depends on i
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pmis_split_dominates_and_takes_local_maxima(seed):
+    """Points on which nothing strongly depends are F; every other F-point
+    strongly depends on a C-point; a point whose weight (count of
+    dependants, hash, index) beats every point it is strongly connected to
+    is C (it wins the first round); some points are C, some F."""
+    A, _ = _adr(20 + 4 * seed)
+    rng = np.random.default_rng(seed)
+    A = A.copy()
+    A.data = A.data * (1.0 + 0.5 * rng.random(A.nnz))
+    sm = O.strength(A, 0.25)
+    cf = O.pmis_split(A, sm)
+    n = A.shape[0]
+    j, i = _strong_pairs(A, sm)
+    cnt = np.bincount(i, minlength=n)
+    assert np.all(cf[cnt == 0] == 0)
+    hasc = np.zeros(n, bool)
+    hasc[j[cf[i] == 1]] = True
+    assert np.all((cf == 1) | (cnt == 0) | hasc)
+    key = [(int(cnt[q]), int(O.hash32(q)), q) for q in range(n)]
+    nbrs = [set() for _ in range(n)]
+    for a, b in zip(j, i):
+        nbrs[a].add(b)
+        nbrs[b].add(a)
+    for q in range(n):
+        if cnt[q] > 0 and all(key[q] > key[r] for r in nbrs[q] if cnt[r] > 0):
+            assert cf[q] == 1
+    assert 0 < (cf == 1).sum() < n
+
+
+def test_pmis_split_on_a_chain_and_the_hierarchy_solves():
+    """Upwind chain: point i strongly depends on i - 1 only.  The last point
+    influences nothing and is F; every other F-point has its upwind
+    neighbour as C.  The lAIR hierarchy built on the parallel splitting
+    solves ADR to 1e-10."""
+    n = 50
+    A = sp.diags([np.ones(n), -np.ones(n - 1)], [0, -1], format="csr")
+    A.sort_indices()
+    cf = O.pmis_split(A, O.strength(A, 0.25))
+    assert cf[-1] == 0
+    for q in range(1, n):
+        if cf[q] == 0 and q < n - 1:
+            assert cf[q - 1] == 1
+    B, b = _adr(24)
+    H = O.setup(B, interp=O.INTERP_DIRECT, split="pmis")
+    x, it, _ = O.solve(H, b, rtol=1e-10)
+    assert H.nlevels >= 3 and np.linalg.norm(b - B @ x) <= 1e-10 * np.linalg.norm(b)
