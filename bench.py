@@ -217,6 +217,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c5")
+    ap.add_argument("--split", choices=("rs", "pmis"), default="rs",
+                    help="rs: the paper's first pass on the host, computed once untimed and "
+                         "passed in; pmis: the parallel splitting on the device, inside the "
+                         "timed setup")
     ap.add_argument("--distance", type=int, choices=(1, 2), default=None,
                     help="neighbourhood distance instead of the workload's own")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -278,6 +282,10 @@ def main():
 
     if args.no_graphs:
         kw = dict(kw, graphs=False)
+    if args.split == "pmis":
+        kw = dict(kw, split="pmis")
+        cfg = dict(cfg, splitting="PMIS on the device, timed")
+        args.no_cpu_baseline = True
     if args.distance is not None:
         kw = dict(kw, distance=args.distance)
         cfg = dict(cfg, distance=args.distance)
@@ -307,7 +315,7 @@ def main():
     maxit = 300 if kw.get("nodal") else 100
 
     def step(precision):
-        h = build(cfl, precision)
+        h = build(None if args.split == "pmis" else cfl, precision)
         if batch:
             X, info = h.solve_batch(B, rtol=1e-10, maxit=maxit)
         elif args.solver == "fgmres":

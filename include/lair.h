@@ -156,6 +156,17 @@ typedef struct lair_options {
  * no transposed cycle or solve and no new diagonal (LAIR_EUNSUPPORTED).
  * Natural ordering on every level. */
 #define LAIR_FLAG_NODAL 8
+/* Levels without a caller splitting are split on the device by a parallel
+ * splitting of the PMIS type (De Sterck, Yang and Heys, 2006) instead of the
+ * sequential Ruge-Stueben first pass of Sec. 4 on the host.  Weight of point
+ * i: the number of points that strongly depend on it, then MurmurHash3's
+ * 32-bit finalizer of i, then i.  Points on which nothing strongly depends
+ * are F; each round, every undecided point that beats every undecided point
+ * it is strongly connected to (either direction) becomes C, then every
+ * undecided point that strongly depends on a C-point becomes F.  The result
+ * does not depend on thread order.  It is a different coarsening from the
+ * paper's, usually coarser.  Not with LAIR_FLAG_NODAL (LAIR_EUNSUPPORTED). */
+#define LAIR_FLAG_PMIS 16
 
 typedef struct lair_info {
     int32_t iters;           /* V-cycles done                               */

@@ -301,21 +301,24 @@ def _cf_levels(cf_levels, keep):
     return ctypes.byref(cfl)
 
 
+_SPLIT = {"rs": 0, "pmis": L.FLAG_PMIS}
+
+
 def _params(theta, theta_c, kind, distance, interp, precision, omega, max_levels,
             max_coarse, stall, block_size, graphs, ordering="auto", lump_tol=0.0,
-            nodal=False):
+            nodal=False, split="rs"):
     s = L.Strength(float(theta), float(theta if theta_c is None else theta_c),
                    _KINDS[kind], _DIST[distance])
     o = L.Options(_INTERP[interp], _PREC[precision], float(omega), int(max_levels),
                   int(max_coarse), float(stall), int(block_size),
                   (0 if graphs else L.FLAG_NO_GRAPH) | _ORDERING[ordering] |
-                  (L.FLAG_NODAL if nodal else 0),
+                  (L.FLAG_NODAL if nodal else 0) | _SPLIT[split],
                   float(lump_tol))
     opts = dict(theta=theta, theta_c=theta_c, kind=kind, distance=distance,
                 interp=interp, precision=precision, omega=omega,
                 max_levels=max_levels, max_coarse=max_coarse, stall=stall,
                 block_size=block_size, graphs=graphs, ordering=ordering,
-                lump_tol=lump_tol, nodal=nodal)
+                lump_tol=lump_tol, nodal=nodal, split=split)
     return s, o, opts
 
 
@@ -339,7 +342,7 @@ def set_local_buckets(edges=None):
 def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
                 distance=1, interp="one_point", precision="fp64", omega=1.0,
                 max_levels=25, max_coarse=128, stall=0.9, block_size=0, graphs=True,
-                lump_tol=0.0, stream=None):
+                lump_tol=0.0, split="rs", stream=None):
     """One hierarchy for a batch of independent systems.
 
     systems: list of (rowptr, col, val), all NumPy (host) or all CUDA
@@ -356,7 +359,7 @@ def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
     arr = (L.Csr * len(mats))(*mats)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
                          max_levels, max_coarse, stall, block_size, graphs,
-                         lump_tol=lump_tol)
+                         lump_tol=lump_tol, split=split)
     out = ctypes.c_void_p()
     cfp = _cf_levels(cf_levels, keep)
     st = lib.lair_setup_batch(len(mats), arr, cfp, ctypes.byref(s), ctypes.byref(o),
@@ -368,7 +371,7 @@ def setup_batch(systems, cf_levels=None, theta=0.25, theta_c=None, kind="abs",
 def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
           kind="abs", distance=1, interp="one_point", precision="fp64",
           omega=1.0, max_levels=25, max_coarse=128, stall=0.9, block_size=0,
-          graphs=True, ordering="auto", lump_tol=0.0, nodal=False, stream=None):
+          graphs=True, ordering="auto", lump_tol=0.0, nodal=False, split="rs", stream=None):
     """Build a hierarchy for the CSR matrix (rowptr, col, val).
 
     The arrays may be NumPy arrays (host) or contiguous CUDA tensors
@@ -381,13 +384,15 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
     the same.  lump_tol > 0 lumps every coarse operator (Sec. 3.3).
     nodal=True with block_size=k builds the hierarchy by k x k blocks (the
     nodal treatment of Sec. 4.2) instead of scaling by the block diagonal.
+    split="pmis" splits the levels without a given splitting on the device
+    by a parallel PMIS-type splitting instead of the host first pass.
     """
     lib = L.load()
     keep = []
     A, n = _csr(rowptr, col, val, keep)
     s, o, opts = _params(theta, theta_c, kind, distance, interp, precision, omega,
                          max_levels, max_coarse, stall, block_size, graphs, ordering,
-                         lump_tol, nodal)
+                         lump_tol, nodal, split)
     cfp = _cf_levels(cf_levels, keep)
     out = ctypes.c_void_p()
     st = lib.lair_setup(ctypes.byref(A), cfp, ctypes.byref(s), ctypes.byref(o),

@@ -23,6 +23,7 @@ FLAG_NO_GRAPH = 1
 FLAG_NATURAL_ORDER = 2
 FLAG_SPLIT_ALL = 4
 FLAG_NODAL = 8
+FLAG_PMIS = 16
 
 
 class Csr(ctypes.Structure):

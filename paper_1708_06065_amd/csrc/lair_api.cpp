@@ -458,7 +458,7 @@ static void check_options(const lair_strength *s, const lair_options *o) {
     if (!(o->stall > 0.0 && o->stall <= 1.0)) fail(LAIR_EINVAL, "stall must lie in (0, 1]");
     if (o->block_size < 0 || o->block_size > 8) fail(LAIR_EINVAL, "block_size must lie in [0, 8]");
     if (o->flags & ~(LAIR_FLAG_NO_GRAPH | LAIR_FLAG_NATURAL_ORDER | LAIR_FLAG_SPLIT_ALL |
-                     LAIR_FLAG_NODAL))
+                     LAIR_FLAG_NODAL | LAIR_FLAG_PMIS))
         fail(LAIR_EINVAL, "unknown option flags 0x%x", o->flags);
     if (o->flags & LAIR_FLAG_NODAL) {
         if (o->block_size < 1) fail(LAIR_EINVAL, "the nodal treatment needs block_size >= 1");
@@ -468,6 +468,8 @@ static void check_options(const lair_strength *s, const lair_options *o) {
             fail(LAIR_EUNSUPPORTED, "the nodal treatment uses distance 1 or 2");
         if (o->lump_tol > 0.0)
             fail(LAIR_EUNSUPPORTED, "lumping would break the dense blocks of a nodal hierarchy");
+        if (o->flags & LAIR_FLAG_PMIS)
+            fail(LAIR_EUNSUPPORTED, "a nodal hierarchy splits the graph of blocks on the host");
     }
     if ((o->flags & LAIR_FLAG_NATURAL_ORDER) && (o->flags & LAIR_FLAG_SPLIT_ALL))
         fail(LAIR_EINVAL, "NATURAL_ORDER and SPLIT_ALL exclude each other");
@@ -519,6 +521,18 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         // the splittings were uploaded (and checked) at the start of setup
         LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), h->cf_dev.get() + lo, (size_t)n,
                                 hipMemcpyDeviceToDevice, s));
+    } else if (h->opt.flags & LAIR_FLAG_PMIS) {
+        // the parallel splitting on the device
+        const uint8_t *sm_dev = Lv.smask.get();
+        DevArr<uint8_t> smc;
+        if (h->str.theta_c != h->str.theta) {
+            smc.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
+            launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
+                            h->str.kind, smc.get(), mean, s);
+            sm_dev = smc.get();
+        }
+        ProfScope ps("split", s, 13.0 * A.nnz + 4.0 * n);
+        launch_pmis_split(n, A.rp.get(), A.cj.get(), sm_dev, Lv.cf.get(), s);
     } else {
         // library's own classical first pass on a host copy of the pattern
         const uint8_t *sm_dev = Lv.smask.get();

@@ -417,6 +417,10 @@ void launch_interp_1p_node(int32_t n, int32_t k, const int32_t *rp, const int32_
 // out = D^{-1} A on A's pattern (dinv: the inverse diagonal blocks)
 void launch_node_scale(int32_t n, int32_t k, const int32_t *rp, const double *v,
                        const double *dinv, double *out, hipStream_t s);
+// parallel PMIS-type CF splitting on the device (k_split.hip): cf[i] = 1
+// for C, 0 for F
+void launch_pmis_split(int32_t n, const int32_t *rp, const int32_t *cj, const uint8_t *smask,
+                       int8_t *cf, hipStream_t s);
 // out = D^{-1} b for nrhs interleaved right-hand sides
 template <class VT>
 void op_node_rhs(int32_t n, int32_t k, int32_t nrhs, const double *dinv, const VT *b, VT *out,
