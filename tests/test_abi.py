@@ -92,6 +92,12 @@ def test_host_side_validation_without_gpu():
                           ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
     assert b"lumping" in lib.lair_last_error()
     o.lump_tol = 0.0
+    o.flags = L.FLAG_NODAL | L.FLAG_PMIS          # nodal splits the graph of blocks
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EUNSUPPORTED
+    o.flags = 32                                   # no such flag
+    assert lib.lair_setup(ctypes.byref(A), None, ctypes.byref(s), ctypes.byref(o), None,
+                          ctypes.byref(out)) == L.LAIR_EINVAL
     o.flags = 0
     o.block_size = 0
     o.omega = 0.0
