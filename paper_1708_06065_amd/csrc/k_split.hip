@@ -39,26 +39,20 @@ k_pmis_count(int32_t n, const int32_t *rp, const int32_t *cj, const uint8_t *sma
 
 // weights and the first states; every undecided point starts a candidate
 __global__ void __launch_bounds__(SPLIT_BS)
-k_pmis_init(int32_t n, const int32_t *cnt, uint64_t *key, int8_t *state) {
+k_pmis_init(int32_t n, const int32_t *cnt, uint64_t *key, int8_t *state, uint8_t *cand) {
     const int32_t i = blockIdx.x * SPLIT_BS + threadIdx.x;
     if (i >= n) return;
     key[i] = ((uint64_t)(uint32_t)cnt[i] << 32) | fmix32((uint32_t)i);
     state[i] = cnt[i] == 0 ? ST_F : ST_U;
+    cand[i] = cnt[i] == 0 ? 0 : 1;
 }
 
 __device__ __forceinline__ bool pmis_beats(const uint64_t *key, int32_t a, int32_t b) {
     return key[a] > key[b] || (key[a] == key[b] && a > b);
 }
 
-// cand[i] = 1 for undecided points; then the loser of every strong pair of
-// undecided points is cleared (stores of 0 only)
-__global__ void __launch_bounds__(SPLIT_BS)
-k_pmis_cand(int32_t n, const int8_t *state, uint8_t *cand) {
-    const int32_t i = blockIdx.x * SPLIT_BS + threadIdx.x;
-    if (i >= n) return;
-    cand[i] = state[i] == ST_U ? 1 : 0;
-}
-
+// cand[i] is 1 for the undecided points at the start of a round; the loser
+// of every strong pair of undecided points is cleared (stores of 0 only)
 __global__ void __launch_bounds__(SPLIT_BS)
 k_pmis_compete(int32_t n, const int32_t *rp, const int32_t *cj, const uint8_t *smask,
                const uint64_t *key, const int8_t *state, uint8_t *cand) {
@@ -80,19 +74,26 @@ k_pmis_select(int32_t n, const uint8_t *cand, int8_t *state) {
 }
 
 // undecided points that strongly depend on a C-point become F; the points
-// still undecided are counted
+// still undecided are counted and are the next round's candidates (a
+// thread writes only its own point's state and candidate flag)
 __global__ void __launch_bounds__(SPLIT_BS)
 k_pmis_fpass(int32_t n, const int32_t *rp, const int32_t *cj, const uint8_t *smask,
-             int8_t *state, int32_t *left) {
+             int8_t *state, uint8_t *cand, int32_t *left) {
     const int32_t j = blockIdx.x * SPLIT_BS + threadIdx.x;
-    if (j >= n || state[j] != ST_U) return;
+    if (j >= n) return;
+    if (state[j] != ST_U) {
+        cand[j] = 0;
+        return;
+    }
     for (int32_t p = rp[j]; p < rp[j + 1]; ++p) {
         const int32_t i = cj[p];
         if (smask[p] && i != j && state[i] == ST_C) {
             state[j] = ST_F;
+            cand[j] = 0;
             return;
         }
     }
+    cand[j] = 1;
     atomicAdd(left, 1);
 }
 
@@ -107,12 +108,12 @@ void launch_pmis_split(int32_t n, const int32_t *rp, const int32_t *cj, const ui
     key.alloc((size_t)n, s);
     cand.alloc((size_t)n, s);
     // one counter per round of a batch of rounds
-    constexpr int ROUNDS = 4;
+    constexpr int ROUNDS = 8;
     left.alloc(ROUNDS, s);
     LAIR_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * n, s));
     LAIR_LAUNCH(k_pmis_count, grid, blk, 0, s, n, rp, cj, smask, cnt.get());
     LAIR_LAUNCH_CHECK();
-    LAIR_LAUNCH(k_pmis_init, grid, blk, 0, s, n, cnt.get(), key.get(), cf);
+    LAIR_LAUNCH(k_pmis_init, grid, blk, 0, s, n, cnt.get(), key.get(), cf, cand.get());
     LAIR_LAUNCH_CHECK();
     // every round turns at least the undecided point of largest weight into
     // a C-point, so n rounds always suffice; rounds are launched in batches
@@ -120,14 +121,13 @@ void launch_pmis_split(int32_t n, const int32_t *rp, const int32_t *cj, const ui
     for (int64_t done = 0; done < n; done += ROUNDS) {
         LAIR_HIP(hipMemsetAsync(left.get(), 0, sizeof(int32_t) * ROUNDS, s));
         for (int r = 0; r < ROUNDS; ++r) {
-            LAIR_LAUNCH(k_pmis_cand, grid, blk, 0, s, n, cf, cand.get());
-            LAIR_LAUNCH_CHECK();
             LAIR_LAUNCH(k_pmis_compete, grid, blk, 0, s, n, rp, cj, smask, key.get(), cf,
                         cand.get());
             LAIR_LAUNCH_CHECK();
             LAIR_LAUNCH(k_pmis_select, grid, blk, 0, s, n, cand.get(), cf);
             LAIR_LAUNCH_CHECK();
-            LAIR_LAUNCH(k_pmis_fpass, grid, blk, 0, s, n, rp, cj, smask, cf, left.get() + r);
+            LAIR_LAUNCH(k_pmis_fpass, grid, blk, 0, s, n, rp, cj, smask, cf, cand.get(),
+                        left.get() + r);
             LAIR_LAUNCH_CHECK();
         }
         int32_t hl[ROUNDS];
