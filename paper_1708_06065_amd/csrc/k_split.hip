@@ -74,27 +74,28 @@ k_pmis_select(int32_t n, const uint8_t *cand, int8_t *state) {
 }
 
 // undecided points that strongly depend on a C-point become F; the points
-// still undecided are counted and are the next round's candidates (a
-// thread writes only its own point's state and candidate flag)
+// still undecided are the next round's candidates (a thread writes only its
+// own point's state and candidate flag) and are counted, one atomic per
+// wavefront (every lane reaches the ballot: no early return)
 __global__ void __launch_bounds__(SPLIT_BS)
 k_pmis_fpass(int32_t n, const int32_t *rp, const int32_t *cj, const uint8_t *smask,
              int8_t *state, uint8_t *cand, int32_t *left) {
     const int32_t j = blockIdx.x * SPLIT_BS + threadIdx.x;
-    if (j >= n) return;
-    if (state[j] != ST_U) {
-        cand[j] = 0;
-        return;
-    }
-    for (int32_t p = rp[j]; p < rp[j + 1]; ++p) {
-        const int32_t i = cj[p];
-        if (smask[p] && i != j && state[i] == ST_C) {
-            state[j] = ST_F;
-            cand[j] = 0;
-            return;
+    bool und = false;
+    if (j < n) {
+        if (state[j] == ST_U) {
+            bool to_f = false;
+            for (int32_t p = rp[j]; p < rp[j + 1] && !to_f; ++p) {
+                const int32_t i = cj[p];
+                to_f = smask[p] && i != j && state[i] == ST_C;
+            }
+            if (to_f) state[j] = ST_F;
+            und = !to_f;
         }
+        cand[j] = und ? 1 : 0;
     }
-    cand[j] = 1;
-    atomicAdd(left, 1);
+    const unsigned long long m = __ballot(und);
+    if ((threadIdx.x & 63) == 0 && m != 0ull) atomicAdd(left, (int32_t)__popcll(m));
 }
 
 void launch_pmis_split(int32_t n, const int32_t *rp, const int32_t *cj, const uint8_t *smask,
