@@ -22,8 +22,8 @@ Steps and where the paper defines them:
                     stand-in for the classical formulas cited in Sec. 4
   galerkin          Sec. 2.1: K = R A P
   lump              Sec. 3.3 (filtering and lumping): entries of a coarse
-                    row below theta_D times the row's largest off-diagonal
-                    magnitude move to the diagonal
+                    row below theta_D times the row's largest magnitude
+                    (diagonal included) move to the diagonal
   block_scale       Sec. 4.2.1: D_B^{-1} A with the element block diagonal
   cycle             Sec. 2.1 coarse-grid correction followed by F-F-C Jacobi
                     (Sec. 4, relaxation paragraph; Eq. (jacobi_err))
@@ -84,6 +84,8 @@ def lib():
         L.orc_spgemm_count.restype = i32
         L.orc_spgemm_fill.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P]
         L.orc_spgemm_fill.restype = i32
+        L.orc_lump.argtypes = [i64, P, P, P, f64, i32, P, P, P, P, P]
+        L.orc_lump.restype = None
         _lib = L
     return _lib
 
@@ -571,42 +573,44 @@ class Hierarchy:
         return flops / wu
 
 
+def _lump_pass(K, theta_d):
+    K = K.tocsr()
+    rp, cj, vx = _arrays(K)
+    m = K.shape[0]
+    keep = np.zeros(max(cj.shape[0], 1), dtype=np.uint8)
+    cnt = np.zeros(m, dtype=np.int64)
+    dummy_i = np.zeros(1, np.int64)
+    lib().orc_lump(m, _p(rp), _p(cj), _p(vx), float(theta_d), 0, _p(keep),
+                   _p(cnt), _p(dummy_i), _p(np.zeros(1, np.int32)),
+                   _p(np.zeros(1)))
+    return K, rp, cj, vx, keep[:cj.shape[0]], cnt
+
+
 def lump_keep(K, theta_d):
     """Entries of K that lumping keeps: the diagonal, and off-diagonal
-    entries with |k_ij| >= theta_d * max_{j != i} |k_ij| (Sec. 3.3; the row
-    maximum taken over the off-diagonal entries).  Boolean per stored entry."""
-    K = K.tocsr()
-    keep = np.ones(K.nnz, dtype=bool)
-    for i in range(K.shape[0]):
-        lo, hi = K.indptr[i], K.indptr[i + 1]
-        cols = K.indices[lo:hi]
-        off = cols != i
-        if not off.any() or not (cols == i).any():
-            continue
-        m = np.abs(K.data[lo:hi][off]).max()
-        keep[lo:hi] = ~off | (np.abs(K.data[lo:hi]) >= theta_d * m)
-    return keep
+    entries with |k_ij| >= theta_d * max_j |k_ij|, the maximum taken over
+    the whole row, diagonal included (Sec. 3.3 and the caption of its
+    filtering table).  Rows without a stored diagonal or without an
+    off-diagonal entry are kept whole.  Boolean per stored entry."""
+    return _lump_pass(K, theta_d)[4].astype(bool)
 
 
 def lump(K, theta_d):
     """Sec. 3.3: each removed entry of row i is added to k_ii, so row sums
     stay.  The removed entries are summed in column order, then added."""
-    K = K.tocsr()
-    keep = lump_keep(K, theta_d)
-    data = K.data.copy()
-    for i in range(K.shape[0]):
-        lo, hi = K.indptr[i], K.indptr[i + 1]
-        gone = 0.0
-        for p in range(lo, hi):
-            if not keep[p]:
-                gone += data[p]
-        if gone != 0.0 or not keep[lo:hi].all():
-            d = lo + int(np.flatnonzero(K.indices[lo:hi] == i)[0])
-            data[d] = data[d] + gone
-    rows = np.repeat(np.arange(K.shape[0]), np.diff(K.indptr))
-    L = sp.csr_matrix((data[keep], (rows[keep], K.indices[keep])), shape=K.shape)
-    L.sort_indices()
-    return L
+    K, rp, cj, vx, keep, cnt = _lump_pass(K, theta_d)
+    m = K.shape[0]
+    optr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(cnt, out=optr[1:])
+    nnz = int(optr[-1])
+    ocj = np.zeros(max(nnz, 1), np.int32)
+    ov = np.zeros(max(nnz, 1), np.float64)
+    if cj.shape[0] == 0:
+        keep = np.zeros(1, np.uint8)
+    lib().orc_lump(m, _p(rp), _p(cj), _p(vx), float(theta_d), 1,
+                   _p(np.ascontiguousarray(keep, np.uint8)), _p(cnt), _p(optr),
+                   _p(ocj), _p(ov))
+    return csr(optr.astype(np.int32), ocj[:nnz], ov[:nnz], shape=K.shape)
 
 
 def setup(A, cf_levels=None, theta=0.25, theta_c=None, kind=SOC_ABS,

@@ -27,6 +27,9 @@
  *                     classical formulas the paper cites but does not state)
  *   orc_spgemm_*      sparse product for the Galerkin operator K = R A P
  *                     (Sec. 2.1), symbolic pattern, nothing dropped
+ *   orc_lump          lumping of a coarse operator (Sec. 3.3 and the caption
+ *                     of its filtering table): small entries of a row move
+ *                     onto the diagonal
  *
  * All arrays are caller-owned.  Indices are int32 (CSR rowptr/col), values
  * double.  Rows of every input CSR have sorted, unique column indices.
@@ -470,4 +473,50 @@ int32_t orc_spgemm_fill(int64_t m, int64_t ncol_b, const int64_t *ap,
     }
     free(pos); free(acc);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lumping (Sec. 3.3).  In row i, an off-diagonal entry with                 */
+/*   |k_ij| < theta_D max_j |k_ij|   (the maximum over the whole row, the    */
+/*                                    diagonal included)                     */
+/* is removed and added to k_ii, so the row sum is kept.  The removed        */
+/* entries are summed in column order first, then added to k_ii.  A row      */
+/* without a stored diagonal, or without an off-diagonal entry, is kept      */
+/* whole.  keep[p] = 1 for every entry that stays; pass 1 (fill == 0)        */
+/* writes keep and the kept count of row i into cnt[i]; pass 2 writes the    */
+/* lumped row at out_ptr[i].                                                 */
+/* ------------------------------------------------------------------------ */
+void orc_lump(int64_t m, const int32_t *rp, const int32_t *cj, const double *v,
+              double theta, int32_t fill, uint8_t *keep, int64_t *cnt,
+              const int64_t *out_ptr, int32_t *out_cj, double *out_v)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        if (!fill) {
+            double mx = 0.0;
+            int has_d = 0, has_o = 0;
+            for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+                if (cj[p] == i) has_d = 1; else has_o = 1;
+                if (fabs(v[p]) > mx) mx = fabs(v[p]);
+            }
+            int64_t c = 0;
+            for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+                int k = 1;
+                if (has_d && has_o && cj[p] != i && fabs(v[p]) < theta * mx) k = 0;
+                keep[p] = (uint8_t)k;
+                c += k;
+            }
+            cnt[i] = c;
+            continue;
+        }
+        double gone = 0.0;
+        for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (!keep[p]) gone += v[p];
+        int64_t o = out_ptr[i];
+        for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (!keep[p]) continue;
+            out_cj[o] = cj[p];
+            out_v[o] = (cj[p] == i) ? v[p] + gone : v[p];
+            o++;
+        }
+    }
 }

@@ -345,6 +345,31 @@ def test_direct_interp_reproduces_constants():
     assert np.allclose(p1[rows], 1.0, rtol=0, atol=1e-12)
 
 
+def _golden_direct():
+    g = _read_golden("direct_interp7.txt")
+    A = O.csr(np.array(g["A_rowptr"], np.int32), np.array(g["A_col"], np.int32),
+              np.array(g["A_val"], np.float64))
+    P = O.csr(np.array(g["P_rowptr"], np.int32), np.array(g["P_col"], np.int32),
+              np.array(g["P_val"], np.float64), shape=(A.shape[0], 3))
+    return g, A, P
+
+
+def test_direct_interp_hand_worked_rows():
+    """Direct interpolation (Stueben 2001) worked by hand on rows with both
+    sign classes (beta weights for positive couplings, a weak positive
+    neighbour in N_i but not in P_i), with no positive interpolatory
+    coupling (their sum goes to the diagonal), with no negative one, and
+    with no strong C-neighbour (zero row)."""
+    g, A, Pw = _golden_direct()
+    sm = O.strength(A, 0.25, O.SOC_ABS)
+    assert np.array_equal(sm, np.array(g["strong"], np.uint8))
+    cf = np.array(g["cf"], np.int8)
+    P = O.interp_direct(A, sm, cf)
+    assert np.array_equal(P.indptr, Pw.indptr)
+    assert np.array_equal(P.indices, Pw.indices)
+    assert np.allclose(P.data, Pw.data, rtol=4e-16, atol=0.0)
+
+
 def test_galerkin_matches_dense_products():
     A = _mat(W.adr_2d(10, 1e-2, 1.1, 0.2))
     H = O.setup(A, interp=O.INTERP_DIRECT, max_coarse=10)
@@ -713,20 +738,27 @@ def test_fgmres_cycle_no_slower_than_stationary():
 # ----------------------------------------------------------------- lumping
 
 def test_lump_hand_example():
-    """Sec. 3.3 by hand, theta_D = 1e-3: each row's cut is 1e-3 times its
-    largest off-diagonal magnitude (2, 3, 2, 1); the entries below it move
-    onto the diagonal."""
-    K = sp.csr_matrix(np.array([[4.0, -1e-4, -2.0, 0.0],
+    """Sec. 3.3 by hand, theta_D = 1e-3: each row's cut is 1e-3 times the
+    largest magnitude of the row, diagonal included (10, 5, 6, 3: cuts 0.01,
+    0.005, 0.006, 0.003); the off-diagonal entries below it move onto the
+    diagonal.  Rows 0 and 2 hold an entry (-0.005, -0.004) that a maximum
+    over the off-diagonal entries alone (2, 2) would keep."""
+    K = sp.csr_matrix(np.array([[10.0, -0.005, -2.0, 0.0],
                                 [-1.0, 5.0, -1e-5, -3.0],
-                                [0.0, -2.0, 6.0, -1e-3],
-                                [-1e-6, 0.0, -1.0, 2.0]]))
-    want = np.array([[4.0 - 1e-4, 0.0, -2.0, 0.0],
+                                [0.0, -2.0, 6.0, -0.004],
+                                [-0.0015, 0.0, -3.0, 1.0]]))
+    want = np.array([[10.0 - 0.005, 0.0, -2.0, 0.0],
                      [-1.0, 5.0 - 1e-5, 0.0, -3.0],
-                     [0.0, -2.0, 6.0 - 1e-3, 0.0],
-                     [0.0, 0.0, -1.0, 2.0 - 1e-6]])
+                     [0.0, -2.0, 6.0 - 0.004, 0.0],
+                     [0.0, 0.0, -3.0, 1.0 - 0.0015]])
     L = O.lump(K, 1e-3)
     assert np.array_equal(L.toarray(), want)
     assert L.nnz == 9
+    # a row without its diagonal, or without an off-diagonal entry, stays whole
+    K2 = sp.csr_matrix((np.array([1e-9, 4.0, 7.0]), np.array([1, 2, 1]),
+                        np.array([0, 2, 3])), shape=(2, 3))
+    L2 = O.lump(K2, 1e-3)
+    assert L2.nnz == 3 and np.array_equal(L2.toarray(), K2.toarray())
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -745,14 +777,17 @@ def test_lump_keeps_row_sums_and_limits(seed):
         assert np.all(np.abs(L @ one - K @ one) <= 1e-14 * scale)
         assert L.nnz <= K.nnz
     assert (O.lump(K, 0.0) != K).nnz == 0          # nothing below a zero cut
-    # at theta_D = 1 only each row's largest off-diagonal magnitudes stay
+    # at theta_D = 1 an off-diagonal entry stays only when its magnitude is
+    # the row's largest, diagonal included
     L1 = O.lump(K, 1.0)
     for i in range(n):
         row = K.getrow(i).toarray().ravel()
-        off = np.abs(row)
+        mag = np.abs(row)
+        off = mag.copy()
         off[i] = 0.0
         kept = set(L1.getrow(i).indices) - {i}
-        assert kept == set(np.flatnonzero(off == off.max())) if off.max() > 0 else not kept
+        want = set(np.flatnonzero(off == mag.max())) - {i} if off.max() > 0 else set()
+        assert kept == want
 
 
 def test_lumped_hierarchy_is_smaller_and_converges():
