@@ -108,14 +108,17 @@ typedef struct lair_options {
     int32_t max_coarse;      /* stop coarsening at n <= max_coarse (128)    */
     double stall;            /* stop when n_c > stall * n (0.9)             */
     int32_t block_size;      /* 0, or k: solve D_B^{-1} A x = D_B^{-1} b with
-                                D_B the k x k diagonal blocks (Sec. 4.2.1) */
+                                D_B the k x k diagonal blocks (Sec. 4.2.1);
+                                the diagonal blocks of D_B^{-1} A are stored
+                                as the exact identity                      */
     int32_t flags;           /* 0, or LAIR_FLAG_* bits below                */
     double lump_tol;         /* 0 (off), or theta_D in (0, 1]: every coarse
                                 operator drops the off-diagonal entries of a
                                 row below theta_D times the row's largest
-                                off-diagonal magnitude and adds them to the
-                                diagonal, keeping row sums (Sec. 3.3; the
-                                paper's results use 0.001)                 */
+                                magnitude (diagonal included) and adds them
+                                to the diagonal, keeping row sums (Sec. 3.3
+                                and its filtering table; the paper's results
+                                use 0.001)                                 */
 } lair_options;
 
 /* Solves capture one iteration (cycle, residual, norms) in a HIP graph the

@@ -333,7 +333,11 @@ def block_scale(A, b, k):
 
     Each block row is multiplied by the inverse of its diagonal block; the
     product keeps the symbolic pattern, so every row of a block carries the
-    union of that block row's columns.
+    union of that block row's columns.  The diagonal blocks of D_B^{-1} A
+    are the identity by definition; they are stored as exact ones and zeros
+    instead of the rounded products, whose noise (about 1e-17) would
+    otherwise decide the strength of connection in rows without other
+    couplings.
     """
     n = A.shape[0]
     assert n % k == 0
@@ -349,7 +353,11 @@ def block_scale(A, b, k):
            np.tile(np.arange(k), nb * k)).astype(np.int32)
     Bd = csr(rowptr, col, Dinv.reshape(-1), shape=(n, n))
     bs = np.einsum("eij,ej->ei", Dinv, np.asarray(b).reshape(nb, k)).ravel()
-    return spgemm(Bd, A), bs
+    S = spgemm(Bd, A)
+    rows = np.repeat(np.arange(n), np.diff(S.indptr))
+    inb = (rows // k) == (S.indices // k)
+    S.data[inb] = np.where(S.indices[inb] == rows[inb], 1.0, 0.0)
+    return S, bs
 
 
 # --------------------------------------------------------------------------

@@ -31,7 +31,11 @@ class LairSolve(torch.autograd.Function):
     opts: dict of lair.setup keyword arguments plus rtol, maxit and
     optionally reuse, a dict the caller keeps across calls: the first call
     stores its hierarchy there and later calls only replace its diagonal
-    (lair_update_diag) instead of setting up again.
+    (lair_update_diag) instead of setting up again.  The shared hierarchy
+    remembers whose diagonal it holds; a backward pass whose forward
+    diagonal has since been replaced puts that diagonal back first (the
+    same diagonal rebuilds the same hierarchy), so forward, forward,
+    backward, backward gives each backward its own A(c)^T.
     """
 
     @staticmethod
@@ -43,18 +47,26 @@ class LairSolve(torch.autograd.Function):
         pos = _diag_positions(rowptr, col)
         val = val0.clone()
         val[pos] += c
+        diag = val[pos].contiguous()
         if reuse is not None and reuse.get("h") is not None:
             h = reuse["h"]
-            h.update_diag(val[pos].contiguous())
+            h.update_diag(diag)
         else:
             h = _setup(rowptr, col, val, **opts)
             if reuse is not None:
                 reuse["h"] = h
+        token = None
+        if reuse is not None:
+            token = reuse.get("count", 0) + 1
+            reuse["count"] = token
+            reuse["current"] = token
         x, info = h.solve(b.contiguous(), rtol=rtol, maxit=maxit)
         if not info["converged"]:
             raise RuntimeError("lAIR forward solve did not converge: %r" % info)
         ctx.h = h
         ctx.keep = reuse is not None
+        ctx.reuse, ctx.token = reuse, token
+        ctx.diag = diag if reuse is not None else None
         ctx.rtol, ctx.maxit = rtol, maxit
         ctx.save_for_backward(x)
         ctx.info = info
@@ -63,6 +75,10 @@ class LairSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
+        if ctx.reuse is not None and ctx.reuse.get("current") != ctx.token:
+            # a later forward replaced the diagonal: restore this one's
+            ctx.h.update_diag(ctx.diag)
+            ctx.reuse["current"] = ctx.token
         lam, info = ctx.h.solve_transpose(gx.contiguous(), rtol=ctx.rtol * 1e-2,
                                           maxit=ctx.maxit)
         if not info["converged"]:

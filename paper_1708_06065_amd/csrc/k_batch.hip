@@ -100,6 +100,22 @@ void launch_force_c(int32_t nsys, const int64_t *seg, const uint8_t *stopped, in
     LAIR_LAUNCH_CHECK();
 }
 
+// flag[r] = 1 for the rows of the systems that have stopped coarsening.
+__global__ void k_stopped_rows(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
+                               int8_t *flag, int64_t nrows) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    flag[r] = stopped[seg_of(seg, nsys, r)] ? 1 : 0;
+}
+
+void launch_stopped_rows(int32_t nsys, const int64_t *seg, const uint8_t *stopped, int8_t *flag,
+                         int64_t nrows, hipStream_t s) {
+    if (nrows == 0) return;
+    LAIR_LAUNCH(k_stopped_rows, dim3(blocks_for(nrows, 256)), dim3(256), 0, s,
+                nsys, seg, stopped, flag, nrows);
+    LAIR_LAUNCH_CHECK();
+}
+
 // flag[k] = 1 when C-point clist[k] belongs to a system still coarsening
 // (the only C rows that are relaxed).
 __global__ void k_relax_flags(int32_t nsys, const int64_t *seg, const uint8_t *stopped,

@@ -1967,19 +1967,21 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 }
 
 // ===========================================================================
-// Lumping of a coarse operator (Sec. 3.3): in row i, an off-diagonal entry
-// with |k_ij| < theta_D max_{j != i} |k_ij| leaves the pattern and is added
-// to k_ii (the removed entries summed in column order, then added), so the
+// Lumping of a coarse operator (Sec. 3.3 and the caption of its filtering
+// table): in row i, an off-diagonal entry with |k_ij| < theta_D max_j |k_ij|
+// (the maximum over the whole row, diagonal included) leaves the pattern and
+// is added to k_ii (the removed entries summed in column order, then added), so the
 // row sum stays.  A row without a diagonal or without off-diagonal entries
-// is kept whole.  cnt != nullptr: count the kept entries of every row;
-// otherwise write them at rp_out.  A team of T lanes per row.
+// is kept whole, and so is row i when whole_rows[i] != 0 (whole_rows may be
+// null).  cnt != nullptr: count the kept entries of every row; otherwise
+// write them at rp_out.  A team of T lanes per row.
 // ===========================================================================
 constexpr int LUMP_E = 4;     // entries per lane held in registers
 
 template <int T>
 __global__ void __launch_bounds__(256)
 k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
-       const int32_t *cj, const double *v, double theta,
+       const int32_t *cj, const double *v, double theta, const int8_t *whole_rows,
        int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out) {
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     const int32_t i = (int32_t)(gt / T);
@@ -2004,13 +2006,14 @@ k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_
                 c[e] = cj[p];
                 a[e] = v[p];
                 if (c[e] == i) has_d = 1;
-                else { has_o = 1; mx = fmax(mx, fabs(a[e])); }
+                else has_o = 1;
+                mx = fmax(mx, fabs(a[e]));
             }
         }
         mx = team_max<T>(mx);
         has_d = team_sum_int<T>(has_d);
         has_o = team_sum_int<T>(has_o);
-        const bool whole = !has_d || !has_o;
+        const bool whole = !has_d || !has_o || (whole_rows && whole_rows[i]);
         const double cut = theta * mx;
         bool keep[LUMP_E];
 #pragma unroll
@@ -2051,14 +2054,14 @@ k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_
     double mx = 0.0;
     int has_d = 0, has_o = 0;
     for (int64_t p = lo + lane; p < hi; p += T) {
-        if (cj[p] == i) { has_d = 1; continue; }
-        has_o = 1;
+        if (cj[p] == i) has_d = 1;
+        else has_o = 1;
         mx = fmax(mx, fabs(v[p]));
     }
     mx = team_max<T>(mx);
     has_d = team_sum_int<T>(has_d);
     has_o = team_sum_int<T>(has_o);
-    const bool whole = !has_d || !has_o;
+    const bool whole = !has_d || !has_o || (whole_rows && whole_rows[i]);
     const double cut = theta * mx;
     auto kept = [&](int64_t p) { return whole || cj[p] == i || !(fabs(v[p]) < cut); };
     if (cnt) {
@@ -2097,16 +2100,16 @@ k_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_
 }
 
 void launch_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
-                 const int32_t *cj, const double *v, double theta, double mean_len,
-                 int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out,
-                 hipStream_t s) {
+                 const int32_t *cj, const double *v, double theta, const int8_t *whole_rows,
+                 double mean_len, int32_t *cnt, const int32_t *rp_out, int32_t *cj_out,
+                 double *v_out, hipStream_t s) {
     if (n == 0) return;
     // about four entries per lane: several rows share a wavefront
     int t = team_for_mean(mean_len / 4.0);
     if (t > 16) t = 16;
 #define LAIR_LU(TT)                                                                        \
     LAIR_LAUNCH(k_lump<TT>, dim3(blocks_for((int64_t)n * TT, 256)), dim3(256), 0, s, n, rp, \
-                row_off, row_len, cj, v, theta, cnt, rp_out, cj_out, v_out)
+                row_off, row_len, cj, v, theta, whole_rows, cnt, rp_out, cj_out, v_out)
     switch (t) {
         case 1: LAIR_LU(1); break;
         case 2: LAIR_LU(2); break;

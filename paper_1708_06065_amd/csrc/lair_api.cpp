@@ -217,6 +217,22 @@ __global__ void k_block_diag_csr(int32_t nblk, int32_t k, const double *dinv,
     v[g] = dinv[(row / k) * k * k + (row % k) * k + c];
 }
 
+// The diagonal blocks of D_B^{-1} A are the identity by definition: store
+// exact ones and zeros there instead of the rounded products, whose noise
+// would otherwise decide the strength of connection in rows that have no
+// other coupling.  A team of 8 lanes per row.
+__global__ void k_unit_diag_blocks(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj,
+                                   double *v) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t r = (int32_t)(g / 8);
+    if (r >= n) return;
+    const int32_t blk = r / k;
+    for (int32_t p = rp[r] + (int32_t)(g % 8); p < rp[r + 1]; p += 8) {
+        const int32_t c = cj[p];
+        if (c / k == blk) v[p] = (c == r) ? 1.0 : 0.0;
+    }
+}
+
 // Sizes of a CSR matrix produced on the device (nnz, longest row, an
 // overflow flag) whose host copies wait for a later readback, so that the
 // setup does not stop for each of them.
@@ -316,7 +332,7 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
 static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, SpgemmState &st,
                              hipStream_t s, DevArr<int64_t> &tmp, PendingSizes *defer,
                              double ratio = 0.0, double lump_tol = 0.0,
-                             int64_t *distinct = nullptr) {
+                             int64_t *distinct = nullptr, const int8_t *whole_rows = nullptr) {
     const int32_t m = st.m;
     const int64_t etot = st.h[0], emax = st.h[1];
     C.nrows = m;
@@ -345,10 +361,15 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
         // column of the level above when known
         const double mean_e = m ? (double)etot / m : 1.0;
         const double mean_c = ratio > 1.0 ? mean_e / ratio : mean_e / 2.0;
+        // algorithmic bytes: the distinct entries of each staged row (column
+        // and value), its offset and length, and the count written; the
+        // number of distinct entries reaches the host with the readback below
+        int count_slot = -1;
         {
-            ProfScope ps("lump", s, 12.0 * etot + 12.0 * m);
+            ProfScope ps("lump", s, 12.0 * etot + 16.0 * m);
             launch_lump(m, nullptr, st.eoff.get(), st.cnt.get(), tcj.get(), tcx.get(), lump_tol,
-                        mean_c, kcnt.get(), nullptr, nullptr, nullptr, s);
+                        whole_rows, mean_c, kcnt.get(), nullptr, nullptr, nullptr, s);
+            count_slot = ps.slot;
         }
         // kept entries (offsets of C) and, for the hash-table estimate of
         // the next level, the distinct columns before lumping: one readback
@@ -372,13 +393,15 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
         C.nnz = ht[0];
         mx = ht[1];
         if (distinct) *distinct = ht[2];
+        prof_set_bytes(count_slot, 12.0 * ht[2] + 16.0 * m);
         C.max_row = (int32_t)mx;
         C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
         C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
         {
-            ProfScope ps("lump", s, 12.0 * etot + 12.0 * m + 12.0 * C.nnz);
+            // the distinct entries read again, C's offsets read, C written
+            ProfScope ps("lump", s, 12.0 * ht[2] + 20.0 * m + 12.0 * C.nnz);
             launch_lump(m, nullptr, st.eoff.get(), st.cnt.get(), tcj.get(), tcx.get(), lump_tol,
-                        mean_c, nullptr, C.rp.get(), C.cj.get(), C.v.get(), s);
+                        whole_rows, mean_c, nullptr, C.rp.get(), C.cj.get(), C.v.get(), s);
         }
         return (int32_t)mx;
     }
@@ -1175,6 +1198,9 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         LAIR_LAUNCH_CHECK();
         DevCSR As;
         L0->max_row = spgemm(D, k, A, As, s, tmp);
+        LAIR_LAUNCH(k_unit_diag_blocks, dim3(blocks_for((int64_t)n * 8, 256)), dim3(256), 0, s,
+                    n, k, As.rp.get(), As.cj.get(), As.v.get());
+        LAIR_LAUNCH_CHECK();
         L0->A = std::move(As);
     }
     h->L.push_back(std::move(L0));
@@ -1211,6 +1237,20 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         spgemm_finish(Lv.A, Lv.P, AP, ap_st, s, tmp, eager ? nullptr : &ap_pend, ap_ratio);
         std::unique_ptr<Level> nx(new Level());
         nx->n = Lv.nc;
+        if (h->nsys > 1) {
+            nx->seg = Lv.next_seg;
+            nx->stopped = Lv.stopped;
+            upload_seg(*nx, s);
+        }
+        // a batch keeps the blocks of its stopped systems as they are: the
+        // single-system hierarchy lumps a coarse operator once, when it is
+        // formed, and never the coarsest level again
+        DevArr<int8_t> whole;
+        if (h->nsys > 1 && opt->lump_tol > 0.0) {
+            whole.alloc((size_t)std::max(Lv.nc, 1), s);
+            launch_stopped_rows(h->nsys, nx->seg_dev.get(), Lv.stopped_dev.get(), whole.get(),
+                                Lv.nc, s);
+        }
         SpgemmState k_st;
         spgemm_count(Lv.R, AP, k_st, s, tmp);
         {
@@ -1224,15 +1264,9 @@ static lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl
         // rows of K are sorted and unique by construction of the product
         int64_t k_distinct = -1;
         nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr, k_ratio,
-                                    opt->lump_tol, &k_distinct);
+                                    opt->lump_tol, &k_distinct, whole.get());
         if (k_distinct < 0) k_distinct = nx->A.nnz;
         if (k_distinct > 0) k_ratio = (double)k_st.h[0] / (double)k_distinct;
-
-        if (h->nsys > 1) {
-            nx->seg = Lv.next_seg;
-            nx->stopped = Lv.stopped;
-            upload_seg(*nx, s);
-        }
         h->L.push_back(std::move(nx));
     }
     finish_coarsest(h.get());

@@ -141,6 +141,10 @@ struct ProfScope {
 };
 // true while profiling is on and `category` is selected
 bool prof_selected(const char *category);
+// Replace the algorithmic bytes of a closed scope's record (slot from
+// ProfScope::slot; ignored when negative or profiling has restarted), for
+// sizes that reach the host only after the scope's launches.
+void prof_set_bytes(int slot, double bytes);
 // Start/stop events for a kernel about to be launched on s inside a
 // selected scope (false: launch without events).
 bool prof_kernel_events(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1);
@@ -232,11 +236,12 @@ struct LocalSolveOut {
 // Lumping of a coarse operator (k_lump): counts of kept entries per row
 // (cnt != nullptr), or the lumped rows written at rp_out.  The rows are CSR
 // rows (rp), or staged rows at row_off[i] of length row_len[i] (row_off
-// non-null; sorted columns, as the product leaves them).
+// non-null; sorted columns, as the product leaves them).  Rows with
+// whole_rows[i] != 0 are kept whole (whole_rows may be null).
 void launch_lump(int32_t n, const int32_t *rp, const int64_t *row_off, const int32_t *row_len,
-                 const int32_t *cj, const double *v, double theta, double mean_len,
-                 int32_t *cnt, const int32_t *rp_out, int32_t *cj_out, double *v_out,
-                 hipStream_t s);
+                 const int32_t *cj, const double *v, double theta, const int8_t *whole_rows,
+                 double mean_len, int32_t *cnt, const int32_t *rp_out, int32_t *cj_out,
+                 double *v_out, hipStream_t s);
 
 // Flexible GMRES kernels (vectors of n rows x R interleaved right-hand
 // sides, R a power of two up to 32; a basis: kc vectors ldv apart).
@@ -442,6 +447,9 @@ void launch_seg_count_c(int32_t nsys, const int64_t *seg, const int8_t *cf, int3
                         hipStream_t s);
 void launch_force_c(int32_t nsys, const int64_t *seg, const uint8_t *stopped, int8_t *cf,
                     int64_t nrows, hipStream_t s);
+// flag[r] = 1 for the rows (seg: nsys + 1 offsets) of the stopped systems
+void launch_stopped_rows(int32_t nsys, const int64_t *seg, const uint8_t *stopped, int8_t *flag,
+                         int64_t nrows, hipStream_t s);
 int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
                    const int32_t *clist, int32_t nc, DevArr<int32_t> &out,
                    hipStream_t s, DevArr<int64_t> &tmp);

@@ -85,6 +85,14 @@ ProfScope::ProfScope(const char *category, hipStream_t s, double bytes, double f
     t_stream = s;
 }
 
+void prof_set_bytes(int slot, double bytes) {
+    if (slot < 0) return;
+    Prof &p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!p.on || slot >= (int)p.recs.size()) return;
+    p.recs[slot].bytes = bytes;
+}
+
 ProfScope::~ProfScope() {
     if (slot < 0) return;
     t_slot = prev_slot;

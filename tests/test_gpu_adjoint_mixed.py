@@ -172,6 +172,37 @@ def test_gradients_with_reused_hierarchy(lair):
     reuse["h"].free()
 
 
+def test_reused_hierarchy_two_forwards_before_backward(lair):
+    """forward(c1), forward(c2), backward(c1), backward(c2) on one kept
+    hierarchy: each backward uses its own forward's A(c)^T."""
+    import torch
+    from paper_1708_06065_amd.autograd import LairSolve
+    w, A0, _ = _c4(40)
+    n = A0.shape[0]
+    dev = "cuda"
+    rp = torch.as_tensor(A0.indptr.astype(np.int32), device=dev)
+    cj = torch.as_tensor(A0.indices.astype(np.int32), device=dev)
+    v0 = torch.as_tensor(A0.data, device=dev)
+    xo = torch.as_tensor(w["x_obs"], device=dev)
+    reuse = {}
+    runs = []
+    for scale in (1.0, 2.5):
+        c = w["c"] * scale
+        bt = torch.ones(n, dtype=torch.float64, device=dev, requires_grad=True)
+        ct = torch.tensor(c, device=dev, requires_grad=True)
+        x = LairSolve.apply(bt, ct, rp, cj, v0, {"interp": "direct", "rtol": 1e-12,
+                                                 "reuse": reuse})
+        runs.append((c, bt, ct, ((x - xo) ** 2).sum()))
+    for c, bt, ct, J in runs:
+        J.backward()
+        D = (A0 + sp.diags(c)).toarray()
+        xs = np.linalg.solve(D, np.ones(n))
+        lam = np.linalg.solve(D.T, 2.0 * (xs - w["x_obs"]))
+        assert np.linalg.norm(bt.grad.cpu().numpy() - lam) <= 1e-8 * np.linalg.norm(lam)
+        assert np.linalg.norm(ct.grad.cpu().numpy() + lam * xs) <= 1e-8 * np.linalg.norm(lam * xs)
+    reuse["h"].free()
+
+
 # ------------------------------------------------------------------ mixed
 
 @pytest.mark.parametrize("case", ["euler3d", "dg"])

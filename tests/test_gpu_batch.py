@@ -23,7 +23,7 @@ import scipy.sparse as sp
 
 import workloads as W
 from oracle import lair as O
-from tests.parity import gpu_A, rows_rel_err
+from tests.parity import _lump_scale, gpu_A, rows_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -82,7 +82,7 @@ def _identity_check(B):
     assert np.all(B.data == 1.0)
 
 
-def _check_member_levels(h, systems, segs, interp):
+def _check_member_levels(h, systems, segs, interp, lump_tol=0.0):
     nl = h.nlevels
     sys_levels = h.system_levels()
     worst = {"z": 0.0, "k": 0.0}
@@ -134,8 +134,14 @@ def _check_member_levels(h, systems, segs, interp):
             assert np.array_equal(Po.indptr, Pq.indptr) and np.array_equal(Po.indices, Pq.indices)
             assert np.allclose(Pq.data, Po.data, rtol=1e-13, atol=1e-15)
             Ko = O.galerkin(Ro, Aq, Po)
+            S = O.galerkin(abs(Ro), abs(Aq), abs(Po))
+            if lump_tol > 0.0:
+                Ko.sort_indices()
+                S.sort_indices()
+                S = _lump_scale(Ko, S, lump_tol)
+                Ko = O.lump(Ko, lump_tol)
             assert np.array_equal(Ko.indptr, Kq.indptr) and np.array_equal(Ko.indices, Kq.indices)
-            scale = O.galerkin(abs(Ro), abs(Aq), abs(Po)).data
+            scale = S.data
             ke = float((np.abs(Kq.data - Ko.data) / np.maximum(scale, 1e-300)).max()) \
                 if scale.shape[0] else 0.0
             assert ke <= 1e-12, (l, q, ke)
@@ -174,6 +180,60 @@ def test_batch_members_equal_single_runs(lair, interp):
         assert np.linalg.norm(w["rhs"] - Aq @ xq) <= 1e-10 * np.linalg.norm(w["rhs"])
         assert info["sys_relres"][q] <= 1e-10
     _say("  iterations per system:", list(info["sys_iters"]))
+
+
+def _c3_sample():
+    """The first 24 systems of the 512-system workload (seed 3, drawn in
+    order) plus its largest and its smallest system."""
+    allsys = W.adr_batch(512, seed=3)
+    sizes = np.array([w["n"] for w in allsys])
+    pick = list(range(24))
+    for q in (int(np.argmax(sizes)), int(np.argmin(sizes))):
+        if q not in pick:
+            pick.append(q)
+    return [allsys[q] for q in pick]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c3_recipe_batch_members_against_oracle(lair, precision):
+    """Systems of the 512-system workload at their own sizes (N from 32 to
+    320), set up and solved as the benchmark does (direct interpolation,
+    coarse operators lumped at 0.001, default coarsest size): every member's
+    levels against the oracle's single-system run on the GPU's member
+    blocks, pass-through blocks unchanged, and each member's cycle count
+    equal to the oracle's (mixed precision: at most one more), its solution
+    within 1e-8 of the oracle's."""
+    systems = _c3_sample()
+    seg0 = np.concatenate([[0], np.cumsum([w["n"] for w in systems])])
+    _say("case: C3 recipe batch, %d systems, N %s, %s" %
+         (len(systems), [int(round(np.sqrt(w["n"]))) for w in systems], precision))
+    h = lair.setup_batch([(w["rowptr"], w["col"], w["val"]) for w in systems],
+                         interp="direct", lump_tol=1e-3, precision=precision)
+    Hs = [O.setup(O.csr(w["rowptr"], w["col"], w["val"]), interp=O.INTERP_DIRECT,
+                  lump_tol=1e-3) for w in systems]
+    assert list(h.system_levels()) == [H.nlevels for H in Hs]
+    if precision == "fp64":
+        segs = _level_segs(h, seg0)
+        worst = _check_member_levels(h, systems, segs, "direct", lump_tol=1e-3)
+        _say("  worst R row error %.2e, worst K error %.2e" % (worst["z"], worst["k"]))
+    b = np.concatenate([w["rhs"] for w in systems])
+    x, info = h.solve_batch(_dev(b), rtol=1e-10, maxit=100)
+    assert info["converged"]
+    X = x.cpu().numpy()
+    worst_err = 0.0
+    for q, (w, H) in enumerate(zip(systems, Hs)):
+        xo, ito, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=100)
+        it = int(info["sys_iters"][q])
+        if precision == "fp64":
+            assert it == ito, (q, it, ito)
+        else:
+            assert it <= ito + 1, (q, it, ito)
+        xq = X[seg0[q]:seg0[q + 1]]
+        err = np.linalg.norm(xq - xo) / np.linalg.norm(xo)
+        worst_err = max(worst_err, err)
+        assert err <= 1e-8, (q, err)
+    _say("  cycles per system:", list(info["sys_iters"]),
+         "max rel err vs FP64 oracle %.2e" % worst_err)
 
 
 def test_batch_mixed_precision(lair):

@@ -4,7 +4,7 @@ LAIR_FLAG_PMIS) against the oracle's pmis_split.
 Level by level on the GPU's own A_l: the splitting bit-exact, and the rest
 of the level (neighbourhoods, R, P, K) to the usual parity bar; the same
 number of cycles to 1e-10 as the oracle's hierarchy on the same splitting
-rule; a batch's level-0 splitting equals the oracle's on the union.
+rule; a batch's splitting of every level equals the oracle's on the union.
 """
 import sys
 
@@ -70,14 +70,32 @@ def test_pmis_levels_and_iterations(lair, name):
     h.free()
 
 
-def test_pmis_batch_level0(lair):
+def test_pmis_batch_every_level(lair):
+    """A batch split in parallel: on every level, each system still
+    coarsening has the oracle's splitting of the GPU's union A_l on its rows
+    (the weights' hash takes union indices, so the union is split as one
+    matrix), and a system that has stopped has all its points as C-points."""
     systems = W.adr_batch(6, seed=11)
     mats = [(q["rowptr"], q["col"], q["val"]) for q in systems]
-    hb = lair.setup_batch(mats, interp="direct", split="pmis")
+    hb = lair.setup_batch(mats, interp="direct", split="pmis", max_coarse=40)
+    sys_levels = hb.system_levels()
+    _say("  batch levels", hb.nlevels, "per system", list(sys_levels))
+    assert hb.nlevels >= 3
+    seg = np.concatenate([[0], np.cumsum([q["n"] for q in systems])]).astype(np.int64)
+    for l in range(hb.nlevels - 1):
+        Ul = gpu_A(hb, l)
+        cf_o = O.pmis_split(Ul, O.strength(Ul, 0.25))
+        cf_g = hb.export(l, "cf")
+        for q in range(len(systems)):
+            s0, s1 = seg[q], seg[q + 1]
+            if l >= sys_levels[q] - 1:
+                assert np.all(cf_g[s0:s1] == 1), (l, q)
+            else:
+                assert np.array_equal(cf_g[s0:s1], cf_o[s0:s1]), (l, q)
+        c = np.concatenate([[0], np.cumsum(cf_g.astype(np.int64))])
+        seg = c[seg]
     U = sp.block_diag([O.csr(*m) for m in mats]).tocsr()
     U.sort_indices()
-    cf = O.pmis_split(U, O.strength(U, 0.25))
-    assert np.array_equal(hb.export(0, "cf"), cf)
     b = np.concatenate([q["rhs"] for q in systems])
     x, info = hb.solve_batch(_dev(b), rtol=1e-10)
     assert info["converged"]

@@ -582,9 +582,16 @@ def test_dg_reproduces_constants_and_block_scaling():
     assert np.abs(A @ np.ones(A.shape[0]) - w["rhs"]).max() <= 1e-14
     As, bs = O.block_scale(A, w["rhs"], 6)
     D = As.toarray()
+    Ad = A.toarray()
     for e in range(A.shape[0] // 6):
-        blk = D[6 * e:6 * e + 6, 6 * e:6 * e + 6]
-        assert np.abs(blk - np.eye(6)).max() <= 1e-12
+        sl = slice(6 * e, 6 * e + 6)
+        # the identity exactly, whatever the rounding of D_B^{-1} D_B
+        assert np.array_equal(D[sl, sl], np.eye(6))
+        # the rest of the block row: D_B^{-1} times A's block row (dense)
+        want = np.linalg.solve(Ad[sl, sl], Ad[sl, :])
+        off = np.ones(A.shape[0], bool)
+        off[sl] = False
+        assert np.abs(D[sl][:, off] - want[:, off]).max() <= 1e-12 * np.abs(want).max()
     assert np.abs(As @ np.ones(A.shape[0]) - bs).max() <= 1e-12
 
 
