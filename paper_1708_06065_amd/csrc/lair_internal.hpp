@@ -52,6 +52,7 @@ struct DevArr {
     T *p = nullptr;
     size_t n = 0;
     hipStream_t s = nullptr;
+    bool own = true;       // false: a view of memory the array does not free
 
     DevArr() = default;
     DevArr(const DevArr &) = delete;
@@ -67,11 +68,20 @@ struct DevArr {
         std::swap(p, o.p);
         std::swap(n, o.n);
         std::swap(s, o.s);
+        std::swap(own, o.own);
     }
     void release() noexcept {
-        if (p) dev_free(p, s);
+        if (p && own) dev_free(p, s);
         p = nullptr;
         n = 0;
+        own = true;
+    }
+    // view `count` elements at `ptr` (memory owned elsewhere)
+    void borrow(T *ptr, size_t count) noexcept {
+        release();
+        p = ptr;
+        n = count;
+        own = false;
     }
     void alloc(size_t count, hipStream_t stream) {
         release();
