@@ -214,6 +214,29 @@ lair_status lair_setup(const lair_csr *A, const lair_cf_levels *cf,
 lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
                        int32_t nrhs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * operation of lair_cycle, x <- x + B (b - A x) on device vectors, with the
+ * cycle's work vectors in a fixed device array of the library instead of
+ * memory it allocates.  The call allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine; the kernel profiler must be off,
+ * since it creates events).  The array holds LAIR_NOALLOC_MAX_BYTES on every
+ * GPU the library runs on, for the life of the process; the first call on a
+ * device looks its address up.  The cycle needs, in 256-byte aligned pieces,
+ * for every level l four vectors of n_l * nrhs doubles (plus four of floats
+ * in LAIR_MIXED), and at level 0 up to two more (block scaling, mixed
+ * precision or the F-first ordering); a hierarchy and nrhs whose vectors do
+ * not fit give LAIR_EUNSUPPORTED before any device work, leaving x
+ * unchanged.  The result is bitwise that of lair_cycle.  Every call on one
+ * GPU shares its array, which keeps the last call's contents (the cycle
+ * writes every work vector before reading it, so nothing needs clearing):
+ * calls that overlap on one GPU, on any streams or hierarchies, race and
+ * must not be issued.  Asynchronous on `stream`; the current device's array
+ * is used.  Errors otherwise as lair_cycle. */
+#define LAIR_NOALLOC_MAX_BYTES (32 << 20)
+lair_status lair_cycle_noalloc(lair_hierarchy *h, const double *b, double *x,
+                               int32_t nrhs, void *stream);
+
 /* Stationary V-cycle iteration from the given x (device, in/out) until
  * every right-hand side has ||b - A x||_2 <= rtol ||b||_2, or maxit cycles.
  * info may be NULL.  Returns ENOCONV (info filled, x = last iterate) when

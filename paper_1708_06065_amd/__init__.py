@@ -132,6 +132,16 @@ class Hierarchy:
                                     _stream_ptr(stream)), "lair_cycle")
         return x
 
+    def cycle_noalloc(self, b, x, stream=None):
+        """The same cycle with the work vectors in the library's fixed device
+        array (lair_cycle_noalloc): no device allocation in the call."""
+        torch = _torch()
+        nr = self._nrhs(b)
+        L.check(L.load().lair_cycle_noalloc(self.handle, _dev_ptr(b, torch.float64, "b"),
+                                            _dev_ptr(x, torch.float64, "x"), nr,
+                                            _stream_ptr(stream)), "lair_cycle_noalloc")
+        return x
+
     def cycle_transpose(self, g, lam, stream=None):
         torch = _torch()
         nr = self._nrhs(g)

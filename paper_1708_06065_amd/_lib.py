@@ -70,6 +70,7 @@ EXPORTS = {
     "lair_default_options": (None, [c_vp, c_vp]),
     "lair_setup": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lair_cycle": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "lair_cycle_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
     "lair_solve": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
     "lair_solve_transpose": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
     "lair_solve_fgmres": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_i32, c_vp, c_vp]),

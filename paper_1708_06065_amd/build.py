@@ -18,7 +18,7 @@ LIB = os.path.join(LIBDIR, "liblair.so")
 ARCH = os.environ.get("LAIR_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["k_setup.hip", "k_cycle.hip", "k_batch.hip", "k_krylov.hip", "k_nodal.hip", "k_split.hip", "lair_api.cpp",
-               "setup.cpp", "solve.cpp",
+               "setup.cpp", "solve.cpp", "noalloc.cpp",
                "profile.cpp", "alloc.cpp"]
 CXX_SOURCES = ["rs_split.cpp"]
 

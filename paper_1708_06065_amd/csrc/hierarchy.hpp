@@ -250,6 +250,10 @@ void for_each_cycle_vector(lair_hierarchy *h, int32_t nrhs, F &&f) {
         f(h->xsplit, n0);
     }
 }
+// lair_cycle_noalloc: cycle_body with the work vectors in the fixed device
+// array of noalloc.cpp
+void cycle_noalloc_impl(lair_hierarchy *h, const double *b, double *x, int32_t nrhs,
+                        hipStream_t s);
 // lam <- lam + B^T (g - A^T lam)
 void cycle_transpose_impl(lair_hierarchy *h, const double *g, double *lam, int32_t nrhs,
                           hipStream_t s);

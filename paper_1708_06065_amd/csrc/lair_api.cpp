@@ -158,6 +158,14 @@ lair_status lair_cycle(lair_hierarchy *h, const double *b, double *x,
     });
 }
 
+lair_status lair_cycle_noalloc(lair_hierarchy *h, const double *b, double *x,
+                               int32_t nrhs, void *stream) {
+    return guarded([&]() -> lair_status {
+        cycle_noalloc_impl(h, b, x, nrhs, (hipStream_t)stream);
+        return LAIR_OK;
+    });
+}
+
 lair_status lair_cycle_transpose(lair_hierarchy *h, const double *g, double *lam,
                                  int32_t nrhs, void *stream) {
     return guarded([&]() -> lair_status {

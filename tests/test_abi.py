@@ -105,6 +105,7 @@ def test_host_side_validation_without_gpu():
     # NULL hierarchy on every entry point
     assert lib.lair_solve(None, None, None, 1, 1e-10, 10, None, None) == L.LAIR_EINVAL
     assert lib.lair_cycle(None, None, None, 1, None) == L.LAIR_EINVAL
+    assert lib.lair_cycle_noalloc(None, None, None, 1, None) == L.LAIR_EINVAL
     assert lib.lair_num_levels(None) == 0
     lib.lair_free(None)
 
