@@ -171,6 +171,8 @@ typedef struct lair_options {
  * paper's, usually coarser.  Not with LAIR_FLAG_NODAL (LAIR_EUNSUPPORTED). */
 #define LAIR_FLAG_PMIS 16
 
+#define LAIR_HIST_MAX 256
+
 typedef struct lair_info {
     int32_t iters;           /* V-cycles done                               */
     int32_t nlevels;
@@ -182,6 +184,21 @@ typedef struct lair_info {
     int64_t n_singular_local;/* local systems solved by least squares       */
     double setup_ms;         /* wall time of lair_setup                     */
     double solve_ms;         /* wall time of the last solve                 */
+    double split_ms;         /* host wall time lair_setup spent in the
+                                library's own sequential CF splittings (the
+                                classical first pass, with the copies of
+                                the pattern it needs); 0 when every level's
+                                splitting was given or split on the device */
+    double wpd;              /* work units per digit of accuracy,
+                                -cycle_complexity / log10(rho) (Sec. 4, the
+                                solver-efficiency measure); 0 when rho is 0
+                                or rho >= 1                                */
+    int32_t hist_len;        /* entries of relres_hist: min(iters + 1,
+                                LAIR_HIST_MAX); 0 for lair_solve_fgmres    */
+    double relres_hist[LAIR_HIST_MAX]; /* largest relative residual over the
+                                right-hand sides (over the systems of a
+                                batch) before the first cycle, then after
+                                each cycle                                 */
 } lair_info;
 
 /* Per-level statistics (host copy). */
@@ -390,6 +407,14 @@ void lair_free(lair_hierarchy *h);
  * device synchronisation).  The library keeps released blocks for reuse by
  * later calls on the same stream; this call gives the memory back. */
 void lair_trim(void);
+/* Device memory of the library in bytes (host variables, may be NULL):
+ * *in_use held by hierarchies and calls in progress, *cached released and
+ * kept for reuse (lair_trim returns it).  For leak checks: after a failed
+ * call the bytes in use are what they were before it.  Allocation failures
+ * can be forced for such checks by setting the environment variable
+ * LAIR_DEBUG_MAX_BYTES to a positive number of bytes: a request that would
+ * raise the bytes in use above it fails with LAIR_ENOMEM. */
+void lair_memory(int64_t *in_use, int64_t *cached);
 const char *lair_status_string(lair_status s);
 const char *lair_last_error(void);
 

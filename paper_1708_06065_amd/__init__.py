@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import LairError  # noqa: F401
 
 __all__ = ["setup", "setup_batch", "Hierarchy", "LairError", "load_library",
-           "profile_begin", "profile_end"]
+           "memory", "profile_begin", "profile_end"]
 
 _KINDS = {"abs": L.SOC_ABS, "neg": L.SOC_NEG}
 _INTERP = {"one_point": L.P_ONE_POINT, "direct": L.P_DIRECT}
@@ -251,6 +251,13 @@ class Hierarchy:
         d = info.as_dict()
         d["converged"] = st == L.LAIR_OK
         return lam, d
+
+
+def memory():
+    """(bytes in use, bytes cached) of the library's device memory."""
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    L.load().lair_memory(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def profile_begin(categories=None):

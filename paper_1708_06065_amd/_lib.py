@@ -46,14 +46,21 @@ class Options(ctypes.Structure):
                 ("block_size", c_i32), ("flags", c_i32), ("lump_tol", c_f64)]
 
 
+HIST_MAX = 256
+
+
 class Info(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("nlevels", c_i32), ("relres", c_f64),
                 ("rho", c_f64), ("cycle_complexity", c_f64),
                 ("op_complexity", c_f64), ("n_singular_local", c_i64),
-                ("setup_ms", c_f64), ("solve_ms", c_f64)]
+                ("setup_ms", c_f64), ("solve_ms", c_f64), ("split_ms", c_f64),
+                ("wpd", c_f64), ("hist_len", c_i32),
+                ("relres_hist", c_f64 * HIST_MAX)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "relres_hist"}
+        d["relres_hist"] = list(self.relres_hist[:max(0, min(self.hist_len, HIST_MAX))])
+        return d
 
 
 class LevelStats(ctypes.Structure):
@@ -71,6 +78,7 @@ EXPORTS = {
     "lair_setup": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lair_cycle": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
     "lair_cycle_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "lair_memory": (None, [c_vp, c_vp]),
     "lair_solve": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
     "lair_solve_transpose": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_vp, c_vp]),
     "lair_solve_fgmres": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f64, c_i32, c_i32, c_vp, c_vp]),

@@ -6,8 +6,13 @@
 // that use them.  Released blocks are kept per device and per stream and
 // handed out again to requests on the same stream, where stream order makes
 // the reuse safe.  lair_trim returns the cached blocks to the runtime.
+//
+// Failure testing: when the environment variable LAIR_DEBUG_MAX_BYTES holds a
+// positive number, a request that would raise the bytes in use by the
+// library above it fails with LAIR_ENOMEM, as a real shortage would.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -28,6 +33,7 @@ struct Cache {
     std::unordered_map<void *, Block> live;
     std::multimap<size_t, std::pair<void *, Block>> idle;   // by size
     size_t cached = 0;
+    size_t in_use = 0;       // bytes of the live blocks
 };
 
 Cache &cache() {
@@ -58,6 +64,15 @@ void release_idle(Cache &c, int device) {
     }
 }
 
+// LAIR_DEBUG_MAX_BYTES, read at every request (0: no cap)
+size_t debug_cap() {
+    const char *e = std::getenv("LAIR_DEBUG_MAX_BYTES");
+    if (!e || !*e) return 0;
+    char *end = nullptr;
+    unsigned long long v = std::strtoull(e, &end, 10);
+    return (end && *end == 0) ? (size_t)v : 0;
+}
+
 }  // namespace
 
 void *dev_alloc(size_t bytes, hipStream_t s) {
@@ -67,6 +82,10 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
     const size_t want = round_size(bytes);
     Cache &c = cache();
     std::lock_guard<std::mutex> g(c.mu);
+    const size_t cap = debug_cap();
+    if (cap && c.in_use + want > cap)
+        fail(LAIR_ENOMEM, "device allocation of %zu bytes refused: %zu bytes in use, "
+             "LAIR_DEBUG_MAX_BYTES = %zu", bytes, c.in_use, cap);
     // smallest idle block of this device and stream that fits without
     // wasting more than half of it
     for (auto it = c.idle.lower_bound(want); it != c.idle.end() && it->first <= 2 * want; ++it) {
@@ -75,6 +94,7 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
             void *p = it->second.first;
             c.live[p] = b;
             c.cached -= b.size;
+            c.in_use += b.size;
             c.idle.erase(it);
             return p;
         }
@@ -92,6 +112,7 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
              "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     }
     c.live[p] = Block{want, dev, s};
+    c.in_use += want;
     return p;
 }
 
@@ -104,6 +125,7 @@ void dev_free(void *p, hipStream_t s) noexcept {
     Block b = it->second;
     b.stream = s;
     c.live.erase(it);
+    c.in_use -= b.size;
     c.idle.emplace(b.size, std::make_pair(p, b));
     c.cached += b.size;
 }
@@ -119,6 +141,12 @@ size_t dev_cached_bytes() noexcept {
     Cache &c = cache();
     std::lock_guard<std::mutex> g(c.mu);
     return c.cached;
+}
+
+size_t dev_in_use_bytes() noexcept {
+    Cache &c = cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    return c.in_use;
 }
 
 }  // namespace lair

@@ -129,6 +129,7 @@ struct lair_hierarchy {
     }
     int64_t n_singular = 0;
     double setup_ms = 0.0;
+    double split_ms = 0.0;                   // host first-pass splittings in setup
     double cc = 0.0, oc = 0.0;
 };
 
@@ -202,6 +203,9 @@ lair_status solve_fgmres_impl(lair_hierarchy *h, const double *b, double *x, int
 lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *x, double rtol,
                              int32_t maxit, int32_t *iters, double *relres, lair_info *info,
                              hipStream_t s);
+// The fields of lair_info every solve fills the same way: level count,
+// complexities, setup figures, and the work units per digit from rho.
+void info_common(const lair_hierarchy *h, lair_info *info);
 // x <- x + B (b - A x), the work vectors taken from the hierarchy
 void cycle_impl(lair_hierarchy *h, const double *b, double *x, int32_t nrhs, hipStream_t s);
 // the same with the arguments checked and the work vectors in place (the

@@ -277,6 +277,11 @@ void lair_free(lair_hierarchy *h) {
 
 void lair_trim(void) { dev_trim(); }
 
+void lair_memory(int64_t *in_use, int64_t *cached) {
+    if (in_use) *in_use = (int64_t)dev_in_use_bytes();
+    if (cached) *cached = (int64_t)dev_cached_bytes();
+}
+
 const char *lair_status_string(lair_status s) {
     switch (s) {
         case LAIR_OK: return "LAIR_OK";

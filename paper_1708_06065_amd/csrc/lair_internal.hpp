@@ -46,6 +46,7 @@ void *dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s) noexcept;
 void dev_trim() noexcept;
 size_t dev_cached_bytes() noexcept;
+size_t dev_in_use_bytes() noexcept;
 
 template <class T>
 struct DevArr {

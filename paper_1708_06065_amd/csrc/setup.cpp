@@ -383,6 +383,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         launch_pmis_split(n, A.rp.get(), A.cj.get(), sm_dev, Lv.cf.get(), s);
     } else {
         // library's own classical first pass on a host copy of the pattern
+        // (timed from the moment the device has produced the mask)
+        LAIR_HIP(hipStreamSynchronize(s));
+        const auto t_split = Clock::now();
         const uint8_t *sm_dev = Lv.smask.get();
         DevArr<uint8_t> smc;
         if (h->str.theta_c != h->str.theta) {
@@ -427,6 +430,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         }
         LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), hcf.data(), (size_t)n, hipMemcpyHostToDevice, s));
         LAIR_HIP(hipStreamSynchronize(s));
+        h->split_ms += ms_since(t_split);
     }
     std::vector<int64_t> seg_next;
     if (h->nsys > 1) {

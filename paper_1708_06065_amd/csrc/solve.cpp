@@ -28,6 +28,9 @@ __global__ void k_add(double *x, const double *e, int64_t m) {
 static void ensure_vectors(lair_hierarchy *h, int32_t nrhs, hipStream_t s) {
     if (nrhs <= h->nrhs_cap) return;
     h->drop_graphs();     // captured iterations refer to the old buffers
+    // a failed allocation below leaves no capacity claimed, so the next call
+    // allocates every vector again
+    h->nrhs_cap = 0;
     for_each_cycle_vector(h, nrhs, [&](auto &a, size_t count) { a.alloc(count, s); });
     h->partial.alloc((size_t)NPARTIAL * nrhs, s);
     h->norms.alloc((size_t)nrhs, s);
@@ -341,6 +344,25 @@ static void check_solve_args(lair_hierarchy *h, const double *b, double *x, doub
     if (!(rtol > 0.0) || maxit < 0) fail(LAIR_EINVAL, "need rtol > 0 and maxit >= 0");
 }
 
+void info_common(const lair_hierarchy *h, lair_info *info) {
+    info->nlevels = (int32_t)h->L.size();
+    info->cycle_complexity = h->cc;
+    info->op_complexity = h->oc;
+    info->n_singular_local = h->n_singular;
+    info->setup_ms = h->setup_ms;
+    info->split_ms = h->split_ms;
+    // Sec. 4: work units per digit of accuracy, -CC / log10(rho)
+    info->wpd = (info->rho > 0.0 && info->rho < 1.0)
+                    ? -h->cc / std::log10(info->rho) : 0.0;
+    info->hist_len = 0;
+}
+
+static void set_history(lair_info *info, const std::vector<double> &hist) {
+    const size_t m = std::min(hist.size(), (size_t)LAIR_HIST_MAX);
+    for (size_t k = 0; k < m; ++k) info->relres_hist[k] = hist[k];
+    info->hist_len = (int32_t)m;
+}
+
 lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
                        int32_t nrhs, double rtol, int32_t maxit,
                        lair_info *info, hipStream_t s, bool transpose) {
@@ -401,6 +423,7 @@ lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     r_first = rn;
     int32_t it = 0;
     double relmax = 0.0;
+    std::vector<double> hist;
     for (;;) {
         relmax = 0.0;
         bool done = true;
@@ -409,6 +432,7 @@ lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
             relmax = std::max(relmax, rel);
             if (!(rel <= rtol)) done = false;
         }
+        hist.push_back(relmax);
         if (done || it >= maxit) break;
         if (transpose) {
             // lambda <- lambda + B^T (g - A^T lambda): cycle on the residual
@@ -446,7 +470,6 @@ lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
     LAIR_HIP(hipStreamSynchronize(s));
     if (info) {
         info->iters = it;
-        info->nlevels = (int32_t)h->L.size();
         info->relres = relmax;
         double rho = 0.0;
         if (it > 0 && !r_first.empty()) {
@@ -454,10 +477,8 @@ lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
                 if (r_first[q] > 0) rho = std::max(rho, std::pow(rn[q] / r_first[q], 1.0 / it));
         }
         info->rho = rho;
-        info->cycle_complexity = h->cc;
-        info->op_complexity = h->oc;
-        info->n_singular_local = h->n_singular;
-        info->setup_ms = h->setup_ms;
+        info_common(h, info);
+        set_history(info, hist);
         info->solve_ms = ms_since(t0);
     }
     return relmax <= rtol ? LAIR_OK : LAIR_ENOCONV;
@@ -653,7 +674,6 @@ lair_status solve_fgmres_impl(lair_hierarchy *h, const double *b, double *x,
     }
     if (info) {
         info->iters = itmax;
-        info->nlevels = (int32_t)h->L.size();
         info->relres = relmax;
         double rho = 0.0;
         if (itmax > 0)
@@ -661,10 +681,7 @@ lair_status solve_fgmres_impl(lair_hierarchy *h, const double *b, double *x,
                 if (r_first[q] > 0 && its[q] > 0)
                     rho = std::max(rho, std::pow(beta[q] / r_first[q], 1.0 / its[q]));
         info->rho = rho;
-        info->cycle_complexity = h->cc;
-        info->op_complexity = h->oc;
-        info->n_singular_local = h->n_singular;
-        info->setup_ms = h->setup_ms;
+        info_common(h, info);
         info->solve_ms = ms_since(t0);
     }
     return relmax <= rtol ? LAIR_OK : LAIR_ENOCONV;
@@ -857,6 +874,7 @@ lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *x,
     std::vector<double> rel((size_t)ns, 0.0);
     bool upload = true;
     int32_t it = 0;
+    std::vector<double> hist;
     for (;;) {
         int32_t nact = 0;
         for (int32_t q = 0; q < ns; ++q) {
@@ -870,6 +888,7 @@ lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *x,
                 ++nact;
             }
         }
+        hist.push_back(*std::max_element(rel.begin(), rel.end()));
         if (nact == 0 || it >= maxit) break;
         if (upload) {
             LAIR_HIP(hipMemcpyAsync(h->active_dev.get(), h->active.data(), (size_t)ns,
@@ -932,17 +951,14 @@ lair_status solve_batch_impl(lair_hierarchy *h, const double *b, double *x,
     }
     if (info) {
         info->iters = itmax;
-        info->nlevels = (int32_t)h->L.size();
         info->relres = relmax;
         double rho = 0.0;
         for (int32_t q = 0; q < ns; ++q)
             if (its[q] > 0 && rfirst[q] > 0)
                 rho = std::max(rho, std::pow(rel[q] * nb[q] / rfirst[q], 1.0 / its[q]));
         info->rho = rho;
-        info->cycle_complexity = h->cc;
-        info->op_complexity = h->oc;
-        info->n_singular_local = h->n_singular;
-        info->setup_ms = h->setup_ms;
+        info_common(h, info);
+        set_history(info, hist);
         info->solve_ms = ms_since(t0);
     }
     return conv ? LAIR_OK : LAIR_ENOCONV;

@@ -92,17 +92,25 @@ def euler64():
     A = O.csr(w["rowptr"], w["col"], w["val"])
     H = O.setup(A, interp=O.INTERP_DIRECT, lump_tol=1e-3)
     cfl = oracle_cf_levels(H)
-    cols = []
+    cols, hists = [], []
     for q in range(16):
         xo, ito, hist = O.solve(H, np.ascontiguousarray(w["rhs"][:, q]), rtol=1e-10, maxit=100)
         cols.append((xo, ito))
-    return w, H, cfl, cols
+        hists.append(hist)
+    # the GPU cycles every column until the last one converges: the
+    # oracle's histories over the same number of cycles
+    ito_max = max(it for _, it in cols)
+    for q in range(16):
+        if cols[q][1] < ito_max:
+            hists[q] = O.solve(H, np.ascontiguousarray(w["rhs"][:, q]), rtol=0.0,
+                               maxit=ito_max)[2]
+    return w, H, cfl, cols, hists
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_headline_path_every_rhs_against_oracle(lair, euler64, precision):
     import torch
-    w, H, cfl, cols = euler64
+    w, H, cfl, cols, hists = euler64
     _say("case: 64^3 implicit Euler, 16 rhs, lumped 1e-3, split ordering, graphs,", precision)
     n = w["n"]
     rp = torch.as_tensor(w["rowptr"], device="cuda")
@@ -140,6 +148,16 @@ def test_headline_path_every_rhs_against_oracle(lair, euler64, precision):
         if precision == "fp64":
             assert info["iters"] == ito_max
             assert err <= 1e-8, errs
+            # residual history (largest relative residual over the columns)
+            # and work units per digit against the oracle's
+            ho = np.max(np.stack([hq[:info["iters"] + 1] / np.linalg.norm(w["rhs"][:, q])
+                                  for q, hq in enumerate(hists)]), axis=0)
+            hg = np.array(info["relres_hist"])
+            assert info["hist_len"] == info["iters"] + 1
+            assert np.all(np.abs(hg - ho) <= 1e-6 * ho), (hg, ho)
+            cc_o = H.cycle_complexity()
+            assert abs(info["cycle_complexity"] - cc_o) <= 1e-12 * cc_o
+            assert abs(info["wpd"] + cc_o / np.log10(info["rho"])) <= 1e-12 * info["wpd"]
         else:
             assert info["iters"] <= ito_max + 1
             # both solutions have relative residuals below 1e-10; A = I + dt S
