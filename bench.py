@@ -12,9 +12,11 @@ matrix and right-hand sides are resident in HBM before the timed region.  The
 CF splitting (the classical first pass, a sequential host algorithm) is
 computed once by the library before timing and reported separately.
 
-During the timed steps the library's profiler brackets every launch of the
-dominant kernel category with HIP events on its stream; the roofline entry is
-that category's algorithmic bytes divided by its measured time.
+The timed steps run as a caller would run them (iterations replayed from HIP
+graphs, no profiler).  As many steps again follow with the library's
+profiler bracketing every launch of the dominant kernel category with HIP
+events on its stream (those cycles run eagerly); the roofline entry is that
+category's algorithmic bytes divided by its measured kernel time.
 
 Workload c3: a batch of 512 independent 2-D advection-diffusion-reaction
 systems of uneven size (N x N grids, N log-uniform in [32, 320], 10.8 M
@@ -538,8 +540,6 @@ def main():
             h.free()
         torch.cuda.synchronize()
         times, infos = [], []
-        if prec == main_prec:
-            lair.profile_begin([dominant])
         for k in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -550,8 +550,19 @@ def main():
             if k < args.steps - 1:
                 h.free()
         if prec == main_prec:
-            prof_timed = lair.profile_end()
             x_main = (X[:, 0] if X.dim() > 1 else X).cpu().numpy()
+            # the dominant category's kernels timed with HIP events on their
+            # streams over as many steps again (the profiler launches a
+            # profiled cycle's kernels one by one, so it stays out of the
+            # timed steps above)
+            h.free()
+            lair.profile_begin([dominant])
+            for k in range(args.steps):
+                h, X, info = step(prec)
+                if k < args.steps - 1:
+                    h.free()
+            torch.cuda.synchronize()
+            prof_timed = lair.profile_end()
         # independent FP64 check of the last step's solution
         try:
             A = torch.sparse_csr_tensor(rp.long(), cj.long(), vv, size=(w["n"], w["n"]))

@@ -77,6 +77,8 @@ struct lair_hierarchy {
     lair_options opt{};
     hipStream_t stream = nullptr;
     int32_t nL = 0;                          // coarsest size
+    double coarse_entries = 0.0;             // entries of the coarsest dense factors:
+                                             // nL^2, or the sum of the systems' n_q^2
     lair::DevArr<double> lu;
     lair::DevArr<int32_t> piv;
     lair::DevArr<double> kinv;               // explicit inverse when nL <= 512

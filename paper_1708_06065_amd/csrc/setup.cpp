@@ -668,6 +668,7 @@ static void finish_coarsest_batch(lair_hierarchy *h) {
     }
     ProfScope ps("coarse_setup", s, 8.0 * (double)doff[ns], 0.0);
     h->nL = Lc.n;
+    h->coarse_entries = (double)doff[ns];
     h->dense_off.alloc((size_t)ns + 1, s);
     LAIR_HIP(hipMemcpyAsync(h->dense_off.get(), doff.data(), sizeof(int64_t) * (ns + 1),
                             hipMemcpyHostToDevice, s));
@@ -730,6 +731,7 @@ static void finish_coarsest(lair_hierarchy *h) {
              n, MAX_DENSE);
     ProfScope ps("coarse_setup", s, 8.0 * n * (double)n, 2.0 / 3.0 * n * (double)n * n);
     h->nL = n;
+    h->coarse_entries = (double)n * (double)n;
     h->lu.alloc((size_t)n * n, s);
     h->piv.alloc((size_t)std::max(n, 1), s);
     DevArr<int32_t> info;
@@ -775,8 +777,8 @@ static void level_stats_and_cc(lair_hierarchy *h) {
         flops += 2.0 * Lv.A.nnz + 2.0 * Lv.R.nnz + 2.0 * Lv.P.nnz;
         flops += 2.0 * (2.0 * (double)Lv.nnzF + (double)Lv.nnzC);
     }
-    double nl = (double)h->L.back()->n;
-    flops += 2.0 * nl * nl;
+    // the coarsest dense solve(s): one per system of a batch
+    flops += 2.0 * h->coarse_entries;
     h->cc = flops / (2.0 * nnz0);
     h->oc = sum / nnz0;
 }

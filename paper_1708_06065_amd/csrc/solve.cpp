@@ -53,8 +53,8 @@ template <class VT>
 static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
                          bool transpose, hipStream_t s) {
     const int w = sizeof(VT);
-    ProfScope ps("coarse_solve", s, 8.0 * h->nL * (double)h->nL + 2.0 * w * nrhs * h->nL,
-                 2.0 * h->nL * (double)h->nL * nrhs);
+    ProfScope ps("coarse_solve", s, 8.0 * h->coarse_entries + 2.0 * w * nrhs * h->nL,
+                 2.0 * h->coarse_entries * nrhs);
     if (h->nsys > 1) {
         Level &Lb = *h->L.back();
         const uint8_t *act = h->use_act ? h->active_dev.get() : nullptr;
