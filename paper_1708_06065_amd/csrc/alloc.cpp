@@ -149,4 +149,65 @@ size_t dev_in_use_bytes() noexcept {
     return c.in_use;
 }
 
+// ---------------------------------------------------------------------------
+// Zeroed counter slots.  Flags, sizes and queue counters of the setup must
+// start at zero; instead of a memset for each, they are handed out from a
+// block per device and stream that one memset clears, each slot once.
+// zeroed_slots_reserve (at the start of a setup) clears the block again when
+// fewer slots than asked remain: every slot handed out before belongs to an
+// earlier call whose work and readbacks are complete in stream order.  A
+// block that runs out within a call is replaced by a fresh one.  The blocks
+// are held until the process ends and are not counted as memory in use.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t ZBLOCK = (size_t)1 << 16;   // slots (int64) per block
+
+struct ZArena {
+    int64_t *block = nullptr;
+    size_t next = ZBLOCK;
+};
+
+std::mutex g_zmu;
+std::map<std::pair<int, hipStream_t>, ZArena> g_zarena;
+
+ZArena &zarena(hipStream_t s) {
+    int dev = 0;
+    LAIR_HIP(hipGetDevice(&dev));
+    return g_zarena[{dev, s}];
+}
+
+void zfresh(ZArena &a, hipStream_t s) {
+    if (!a.block) {
+        void *p = nullptr;
+        if (hipMalloc(&p, ZBLOCK * sizeof(int64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(LAIR_ENOMEM, "device allocation of the counter slots failed");
+        }
+        a.block = (int64_t *)p;
+    }
+    LAIR_HIP(hipMemsetAsync(a.block, 0, ZBLOCK * sizeof(int64_t), s));
+    a.next = 0;
+}
+}  // namespace
+
+void zeroed_slots_reserve(size_t count, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_zmu);
+    ZArena &a = zarena(s);
+    if (!a.block || ZBLOCK - a.next < count) zfresh(a, s);
+}
+
+int64_t *zeroed_slots(size_t count, hipStream_t s) {
+    if (count > ZBLOCK) fail(LAIR_EUNSUPPORTED, "too many counter slots (%zu)", count);
+    std::lock_guard<std::mutex> g(g_zmu);
+    ZArena &a = zarena(s);
+    if (!a.block || ZBLOCK - a.next < count) {
+        // mid-call: a new block, so that slots still to be read stay intact
+        a.block = nullptr;
+        zfresh(a, s);
+    }
+    int64_t *p = a.block + a.next;
+    a.next += count;
+    return p;
+}
+
 }  // namespace lair

@@ -25,6 +25,7 @@ struct Level {
     DevCSR At, Rt, Pt;         // transposes for the adjoint cycle
     int32_t n = 0, nc = 0, nf = 0;
     int64_t nnzF = 0, nnzC = 0;     // stored entries in the F rows / C rows
+    DevArr<unsigned long long> fc_acc;   // their device sums until read at the end of setup
     int32_t max_row = 0;
     int32_t team_A = 8, team_R = 8, team_P = 2;
     int32_t team_At = 8, team_Rt = 2, team_Pt = 8;
@@ -83,6 +84,7 @@ struct lair_hierarchy {
     lair::DevArr<int32_t> piv;
     lair::DevArr<double> kinv;               // explicit inverse when nL <= 512
     lair::DevArr<int8_t> cf_dev;             // caller's CF splittings (all levels)
+    std::vector<int64_t> cf_count;           // their numbers of C-points
     lair::DevArr<double> dinv;               // block scaling (block_size > 0)
     int32_t nrhs_cap = 0;
     lair::DevArr<double> bscaled, r0, partial, norms;

@@ -34,7 +34,7 @@ namespace lair {
 // Scan: out[i] = sum_{j<i} f(j), out[n] = total.
 // ===========================================================================
 constexpr int SCAN_BS = 256;
-constexpr int SCAN_IPT = 4;
+constexpr int SCAN_IPT = 8;
 constexpr int SCAN_TILE = SCAN_BS * SCAN_IPT;
 
 struct CountsF {
@@ -55,88 +55,121 @@ struct RowLenF {
     }
 };
 
-__device__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t &total) {
-    int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int o = 1; o < SCAN_BS; o <<= 1) {
-        int64_t add = (t >= o) ? sh[t - o] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+// Longer inputs in two launches.  k_scan_reduce writes the sum and the
+// largest value of every tile of SCAN_TILE entries; k_scan_down gives each
+// tile its offset by summing the sums of the tiles before it (the block's
+// threads share the reads) and writes the tile's offsets.  The last tile
+// also writes out[n], the total and the largest value.
+__device__ __forceinline__ int64_t block_scan_threads(int64_t v, int64_t *s_w, int64_t &total) {
+    // exclusive scan of one value per thread over a block of SCAN_BS threads
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(inc, o);
+        if (lane >= o) inc += u;
     }
-    total = sh[SCAN_BS - 1];
-    int64_t r = sh[t] - v;
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    int64_t pre = inc - v;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_BS / 64; ++k) {
+        if (k < w) pre += s_w[k];
+        total += s_w[k];
+    }
+    __syncthreads();
+    return pre;
+}
+
+__device__ __forceinline__ int64_t block_sum_threads(int64_t v, int64_t *s_w) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) s_w[w] = v;
+    __syncthreads();
+    int64_t r = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_BS / 64; ++k) r += s_w[k];
     __syncthreads();
     return r;
 }
 
+__device__ __forceinline__ int64_t block_max_threads(int64_t v, int64_t *s_w) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    if (lane == 0) s_w[w] = v;
+    __syncthreads();
+    int64_t r = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_BS / 64; ++k) r = s_w[k] > r ? s_w[k] : r;
+    __syncthreads();
+    return r;
+}
+
+template <class F>
+__global__ void __launch_bounds__(SCAN_BS)
+k_scan_reduce(F f, int64_t n, int64_t *blocksum, int64_t *blockmax) {
+    __shared__ int64_t s_w[SCAN_BS / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int64_t sum = 0, mx = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        const int64_t i = base + j;
+        const int64_t v = (i < n) ? f(i) : 0;
+        sum += v;
+        mx = v > mx ? v : mx;
+    }
+    sum = block_sum_threads(sum, s_w);
+    mx = block_max_threads(mx, s_w);
+    if (threadIdx.x == 0) {
+        blocksum[blockIdx.x] = sum;
+        blockmax[blockIdx.x] = mx;
+    }
+}
+
 template <class F, class OUT>
 __global__ void __launch_bounds__(SCAN_BS)
-k_scan_tile(F f, int64_t n, OUT *out, int64_t *blocksum, int64_t *blockmax) {
-    __shared__ int64_t sh[SCAN_BS];
-    __shared__ int64_t smx[SCAN_BS];
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+k_scan_down(F f, int64_t n, int64_t nb, const int64_t *blocksum, const int64_t *blockmax,
+            OUT *out, int64_t *tot) {
+    __shared__ int64_t s_w[SCAN_BS / 64];
+    const int64_t b = blockIdx.x;
+    // this tile's offset: the sums of the tiles before it
+    int64_t part = 0;
+    for (int64_t k = threadIdx.x; k < b; k += SCAN_BS) part += blocksum[k];
+    const int64_t off = block_sum_threads(part, s_w);
+    const int64_t base = b * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int64_t v[SCAN_IPT];
-    int64_t s = 0;
+    int64_t sum = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t i = base + j;
+        const int64_t i = base + j;
         v[j] = (i < n) ? f(i) : 0;
-        s += v[j];
+        sum += v[j];
     }
-    int64_t total;
-    int64_t pre = block_exclusive_scan(s, sh, total);
-    int64_t m = 0;
+    int64_t tile_total;
+    int64_t pre = off + block_scan_threads(sum, s_w, tile_total);
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t i = base + j;
+        const int64_t i = base + j;
         if (i < n) out[i] = (OUT)pre;
         pre += v[j];
-        m = v[j] > m ? v[j] : m;
     }
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
-    smx[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = SCAN_BS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o && smx[threadIdx.x + o] > smx[threadIdx.x])
-            smx[threadIdx.x] = smx[threadIdx.x + o];
-        __syncthreads();
+    if (b == nb - 1) {
+        int64_t mx = 0;
+        for (int64_t k = threadIdx.x; k < nb; k += SCAN_BS)
+            mx = blockmax[k] > mx ? blockmax[k] : mx;
+        mx = block_max_threads(mx, s_w);
+        if (threadIdx.x == 0) {
+            out[n] = (OUT)(off + tile_total);
+            tot[0] = off + tile_total;
+            tot[1] = mx;
+        }
     }
-    if (threadIdx.x == 0) blockmax[blockIdx.x] = smx[0];
-}
-
-__global__ void __launch_bounds__(SCAN_BS)
-k_scan_sums(int64_t *bs, const int64_t *bmax, int64_t nb, int64_t *total) {
-    __shared__ int64_t sh[SCAN_BS];
-    int64_t carry = 0;
-    int64_t m = 0;
-    for (int64_t i = threadIdx.x; i < nb; i += SCAN_BS) m = bmax[i] > m ? bmax[i] : m;
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = SCAN_BS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o && sh[threadIdx.x + o] > sh[threadIdx.x])
-            sh[threadIdx.x] = sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) total[1] = sh[0];
-    __syncthreads();
-    for (int64_t base = 0; base < nb; base += SCAN_BS) {
-        int64_t i = base + threadIdx.x;
-        int64_t v = (i < nb) ? bs[i] : 0;
-        int64_t tot;
-        int64_t pre = block_exclusive_scan(v, sh, tot);
-        if (i < nb) bs[i] = pre + carry;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *total = carry;
-}
-
-template <class OUT>
-__global__ void k_scan_add(OUT *out, int64_t n, const int64_t *bs, const int64_t *total) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (OUT)((int64_t)out[i] + bs[i / SCAN_TILE]);
-    if (i == 0) out[n] = (OUT)(*total);
 }
 
 // Short inputs in one launch: one block of SCAN1_BS threads, each thread
@@ -218,13 +251,10 @@ static int64_t *scan_launch(F f, OUT *out, int64_t n, hipStream_t s, DevArr<int6
     // tot[0] = total, tot[1] = largest value (in tmp, or where the caller
     // keeps them for a later readback)
     int64_t *tot = tot_out ? tot_out : bmax + nb;
-    LAIR_LAUNCH((k_scan_tile<F, OUT>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s,
-                       f, n, out, bs, bmax);
+    LAIR_LAUNCH((k_scan_reduce<F>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s, f, n, bs, bmax);
     LAIR_LAUNCH_CHECK();
-    LAIR_LAUNCH(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, s, bs, bmax, nb, tot);
-    LAIR_LAUNCH_CHECK();
-    LAIR_LAUNCH(k_scan_add<OUT>, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256),
-                       0, s, out, n, bs, tot);
+    LAIR_LAUNCH((k_scan_down<F, OUT>), dim3((unsigned)nb), dim3(SCAN_BS), 0, s, f, n, nb, bs,
+                bmax, out, tot);
     LAIR_LAUNCH_CHECK();
     return tot;
 }
@@ -1604,8 +1634,8 @@ struct LocalRun {
 
 // Binning, the persistent kernel, the 32-lane and one-wave buckets: no
 // host synchronisation.
-void run_buckets(const LocalRun &r, const Buckets &bk, hipStream_t s) {
-    LAIR_HIP(hipMemsetAsync(r.cnt, 0, 7 * sizeof(int32_t), s));
+void run_buckets(LocalRun &r, const Buckets &bk, hipStream_t s) {
+    r.cnt = reinterpret_cast<int32_t *>(zeroed_slots(4, s));   // 7 zeroed counters
     int32_t *ticket = r.cnt + 5, *nsing = r.cnt + 6;
     LAIR_LAUNCH(k_local_bin, dim3(blocks_for(r.nc, 256)), dim3(256), 0, s, r.nc, r.nptr, bk,
                 r.cnt, r.lists, r.out.flags);
@@ -1685,7 +1715,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
     const bool mixed = (precision == LAIR_MIXED);
     DevArr<int32_t> work;
     work.alloc((size_t)nc * (NBUCKET + 1) + 8, s);
-    LocalRun r{nc, clist, nptr, nbr, rp, cj, v, mixed, smax, out, work.get(),
+    LocalRun r{nc, clist, nptr, nbr, rp, cj, v, mixed, smax, out, nullptr,
                work.get() + 8, work.get() + 8 + (size_t)nc * NBUCKET, nullptr, 1};
     // the one-wave bucket: a fixed grid; systems above WSMAX use a global
     // slab per block, the grid kept small enough for 256 MB of slabs
@@ -2416,13 +2446,13 @@ void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const in
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
                    const int32_t *bp, const int32_t *bj, const double *bx,
                    const int64_t *eoff, int64_t max_e, double mean_e, double mean_c_hint,
-                   int32_t *cnt, int32_t *tcj, double *tcx, int32_t *work,
+                   int32_t *cnt, int32_t *tcj, double *tcx, int32_t *counts, int32_t *lists,
                    int32_t *overflow, hipStream_t s) {
     if (m == 0) return;
-    // work[0..3] (the counts of the retry lists) arrive zeroed; then three
-    // lists of m rows
-    int32_t *n1 = work, *n2 = work + 1, *n3 = work + 2;
-    int32_t *l1 = work + 4, *l2 = work + 4 + m, *l3 = work + 4 + 2 * (int64_t)m;
+    // counts[0..2] (the lengths of the retry lists) arrive zeroed; lists
+    // holds three lists of m rows
+    int32_t *n1 = counts, *n2 = counts + 1, *n3 = counts + 2;
+    int32_t *l1 = lists, *l2 = lists + m, *l3 = lists + 2 * (int64_t)m;
     const int T = hacc_team(mean_e);
     const RowSrc all{nullptr, nullptr};
     const unsigned g = blocks_for((int64_t)m * T, 256);

@@ -47,6 +47,11 @@ void dev_free(void *p, hipStream_t s) noexcept;
 void dev_trim() noexcept;
 size_t dev_cached_bytes() noexcept;
 size_t dev_in_use_bytes() noexcept;
+// `count` int64 slots of device memory that are zero in stream order on s,
+// each handed out once (flags, sizes and counters of the setup); reserve at
+// the start of a call so that its slots come from one cleared block.
+int64_t *zeroed_slots(size_t count, hipStream_t s);
+void zeroed_slots_reserve(size_t count, hipStream_t s);
 
 template <class T>
 struct DevArr {
@@ -311,7 +316,7 @@ void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const in
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
                    const int32_t *bp, const int32_t *bj, const double *bx,
                    const int64_t *eoff, int64_t max_e, double mean_e, double mean_c_hint,
-                   int32_t *cnt, int32_t *tcj, double *tcx, int32_t *work,
+                   int32_t *cnt, int32_t *tcj, double *tcx, int32_t *counts, int32_t *lists,
                    int32_t *overflow, hipStream_t s);
 void launch_spgemm_compact(int32_t m, const int64_t *eoff, const int32_t *crp,
                            const int32_t *tcj, const double *tcx, int32_t *cj, double *cx,

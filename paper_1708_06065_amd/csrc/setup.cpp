@@ -63,15 +63,12 @@ __global__ void k_unit_diag_blocks(int32_t n, int32_t k, const int32_t *rp, cons
 // overflow flag) whose host copies wait for a later readback, so that the
 // setup does not stop for each of them.
 struct PendingSizes {
-    DevArr<int64_t> d;               // [0] nnz, [1] longest row, [2] flag (low word)
-    int64_t *dp = nullptr;           // d, or three zeroed slots of the caller
+    int64_t *dp = nullptr;           // three zeroed slots: [0] nnz, [1] longest row, [2] flag
     int64_t h[3] = {0, 0, 0};
     DevCSR *m = nullptr;
     const char *what = "";
     void arm(DevCSR *mat, const char *w, hipStream_t s) {
-        d.alloc(3, s);
-        LAIR_HIP(hipMemsetAsync(d.get(), 0, 3 * sizeof(int64_t), s));
-        arm_at(d.get(), mat, w);
+        arm_at(zeroed_slots(3, s), mat, w);
     }
     // slots already zeroed in stream order (no memset here)
     void arm_at(int64_t *slots, DevCSR *mat, const char *w) {
@@ -120,12 +117,14 @@ struct SpgemmState {
     int32_t m = 0;
     DevArr<int32_t> cnt;
     DevArr<int64_t> eoff, tot;       // tot: [0] products, [1] most in a row
-    // work: [0..5] three int64 slots (C's sizes, or [2] the overflow flag),
-    // then the product's retry counters and lists; the head is zeroed once
-    DevArr<int32_t> work;
-    static constexpr int HEAD = 6;
-    int64_t *ctl() { return reinterpret_cast<int64_t *>(work.get()); }
-    int32_t *lists() { return work.get() + HEAD; }
+    // ctl: five zeroed int64 slots: [0..2] C's sizes (or [2] the overflow
+    // flag), then the product's four retry-list counters (int32); lists:
+    // the retry lists
+    int64_t *ctl_ = nullptr;
+    DevArr<int32_t> lists_;
+    int64_t *ctl() { return ctl_; }
+    int32_t *counts() { return reinterpret_cast<int32_t *>(ctl_ + 3); }
+    int32_t *lists() { return lists_.get(); }
     int64_t h[2] = {0, 0};
 };
 
@@ -138,9 +137,9 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
     st.m = m;
     st.cnt.alloc((size_t)m + 1, s);
     st.eoff.alloc((size_t)m + 1, s);
-    st.work.alloc(SpgemmState::HEAD + 4 + 3 * (size_t)m, s);
+    st.ctl_ = zeroed_slots(5, s);
+    st.lists_.alloc(3 * (size_t)std::max(m, 1), s);
     st.tot.alloc(2, s);
-    LAIR_HIP(hipMemsetAsync(st.work.get(), 0, (SpgemmState::HEAD + 4) * sizeof(int32_t), s));
     // products per row: A's indices and B's row pointers
     ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
                                         8.0 * (B.nrows + 1) + 12.0 * m);
@@ -176,7 +175,7 @@ static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, Spgemm
         const double mean_e = m ? (double)etot / m : 0.0;
         launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
                       B.v.get(), st.eoff.get(), emax, mean_e, ratio > 1.0 ? mean_e / ratio : 0.0,
-                      st.cnt.get(), tcj.get(), tcx.get(), st.lists(), ovp, s);
+                      st.cnt.get(), tcj.get(), tcx.get(), st.counts(), st.lists(), ovp, s);
     }
     C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
@@ -487,26 +486,35 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.cidx.alloc((size_t)n, s);
     Lv.clist.alloc((size_t)std::max(n, 1), s);
     Lv.flist.alloc((size_t)std::max(n, 1), s);
-    // the neighbourhoods' overflow flag, cleared before the readback below
-    DevArr<int32_t> over;
-    over.alloc(1, s);
-    LAIR_HIP(hipMemsetAsync(over.get(), 0, sizeof(int32_t), s));
+    // the neighbourhoods' overflow flag
+    struct { int32_t *p; int32_t *get() const { return p; } } over{
+        reinterpret_cast<int32_t *>(zeroed_slots(1, s))};
     int64_t nc = 0;
+    // a caller's splitting gives the count of C-points on the host: the
+    // entries of the F and C rows (for the cycle's accounting) then wait on
+    // the device until the end of the setup instead of a wait here
+    const bool nc_known = h->nsys == 1 && cfl && lvl < cfl->nlevels;
     {
         DevArr<unsigned long long> acc;
         acc.alloc(2 + 2 * (size_t)blocks_for(n, 256), s);
         ProfScope ps("cf_lists", s, 13.0 * n + 4.0 * n);
         launch_cf_lists(n, Lv.cf.get(), scan.get(), A.rp.get(), Lv.cidx.get(), Lv.clist.get(),
                         Lv.flist.get(), acc.get(), s);
-        unsigned long long hacc[2];
-        int64_t hn[2];
-        Readback rb(s);
-        rb.add(hacc, acc.get(), sizeof(hacc));
-        rb.add(hn, nct.get(), sizeof(hn));
-        rb.run();
-        nc = hn[0];
-        Lv.nnzF = (int64_t)hacc[0];
-        Lv.nnzC = (int64_t)hacc[1];
+        if (nc_known) {
+            nc = h->cf_count[(size_t)lvl];
+            Lv.nnzF = Lv.nnzC = -1;
+            Lv.fc_acc = std::move(acc);
+        } else {
+            unsigned long long hacc[2];
+            int64_t hn[2];
+            Readback rb(s);
+            rb.add(hacc, acc.get(), sizeof(hacc));
+            rb.add(hn, nct.get(), sizeof(hn));
+            rb.run();
+            nc = hn[0];
+            Lv.nnzF = (int64_t)hacc[0];
+            Lv.nnzC = (int64_t)hacc[1];
+        }
     }
     if (h->nsys == 1 && (nc == 0 || (double)nc > h->opt.stall * (double)n)) {
         coarsest = true;
@@ -545,7 +553,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     if (defer_nbr) {
         ntot.alloc(2, s);
         scan_counts_i32_to(cnt.get(), Lv.nptr.get(), Lv.nc, s, tmp, ntot.get());
-        nn = std::max<int64_t>(0, Lv.nnzC - Lv.nc);
+        // N_i holds at most the entries of row i but its diagonal
+        nn = std::max<int64_t>(0, (Lv.nnzC >= 0 ? Lv.nnzC : A.nnz) - Lv.nc);
         smax64 = Lv.max_row - 1;
     } else {
         int32_t ov = 0;
@@ -762,6 +771,24 @@ static void finish_coarsest(lair_hierarchy *h) {
 }
 
 static void level_stats_and_cc(lair_hierarchy *h) {
+    // the F/C row entries left on the device, in one readback
+    {
+        std::vector<unsigned long long> v(2 * h->L.size(), 0);
+        Readback rb(h->stream);
+        bool any = false;
+        for (size_t l = 0; l < h->L.size(); ++l)
+            if (h->L[l]->fc_acc.get()) {
+                rb.add(&v[2 * l], h->L[l]->fc_acc.get(), 2 * sizeof(unsigned long long));
+                any = true;
+            }
+        if (any) rb.run();
+        for (size_t l = 0; l < h->L.size(); ++l)
+            if (h->L[l]->fc_acc.get()) {
+                h->L[l]->nnzF = (int64_t)v[2 * l];
+                h->L[l]->nnzC = (int64_t)v[2 * l + 1];
+                h->L[l]->fc_acc.release();
+            }
+    }
     double nnz0 = (double)h->L[0]->A.nnz;
     double flops = 0.0, sum = 0.0;
     for (size_t l = 0; l < h->L.size(); ++l) {
@@ -945,6 +972,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
     h->str = *str;
     h->opt = *opt;
     h->stream = s;
+    zeroed_slots_reserve(4096, s);
     DevArr<int64_t> tmp;
 
     const int32_t n = (int32_t)Ain->n;
@@ -957,7 +985,15 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
             if (cfl->offs[l + 1] < cfl->offs[l]) fail(LAIR_EINVAL, "bad CF level offsets");
         uint8_t bad = 0;
         const uint8_t *cfb = (const uint8_t *)cfl->cf;
-        for (int64_t k = 0; k < total; ++k) bad |= cfb[k] & 0xFE;
+        h->cf_count.assign((size_t)cfl->nlevels, 0);
+        for (int32_t l = 0; l < cfl->nlevels; ++l) {
+            int64_t c = 0;
+            for (int64_t k = cfl->offs[l]; k < cfl->offs[l + 1]; ++k) {
+                bad |= cfb[k] & 0xFE;
+                c += cfb[k] & 1;
+            }
+            h->cf_count[(size_t)l] = c;
+        }
         if (bad) fail(LAIR_EINVAL, "a CF splitting holds a value other than 0/1");
         if (total > 0) {
             int8_t *stage = (int8_t *)pinned_staging((size_t)total);
@@ -1150,6 +1186,7 @@ void update_diag_impl(lair_hierarchy *h, const double *diag, int32_t on_device,
     if (h->opt.lump_tol > 0.0)
         fail(LAIR_EUNSUPPORTED, "lumped coarse patterns depend on the values: set up again");
     h->stream = s;
+    zeroed_slots_reserve(4096, s);
     Level &L0 = *h->L[0];
     const int32_t n = L0.n;
     DevArr<double> d;
