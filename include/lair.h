@@ -90,14 +90,16 @@ typedef struct lair_strength {
     int32_t distance;        /* 1, 2 or LAIR_DIST_ALL_F                     */
 } lair_strength;
 
-/* Optional per-level CF splittings (host memory).  Level l uses
- * cf[offs[l] .. offs[l+1]) with 1 = C-point, 0 = F-point; its length must
- * equal that level's size.  Levels beyond nlevels use the library's own
- * classical first-pass splitting on the host. */
+/* Optional per-level CF splittings.  Level l uses cf[offs[l] .. offs[l+1])
+ * with 1 = C-point, 0 = F-point; its length must equal that level's size.
+ * Levels beyond nlevels use the library's own splitting.  offs is host
+ * memory; cf is host memory, or device memory when on_device is 1 (then
+ * checked and counted on the device, with no host pass over it). */
 typedef struct lair_cf_levels {
     int32_t nlevels;
-    const int64_t *offs;     /* nlevels + 1 entries                          */
+    const int64_t *offs;     /* nlevels + 1 entries (host)                   */
     const int8_t *cf;
+    int32_t on_device;       /* 1: cf is a device pointer                    */
 } lair_cf_levels;
 
 typedef struct lair_options {
@@ -193,6 +195,14 @@ typedef struct lair_info {
                                 -cycle_complexity / log10(rho) (Sec. 4, the
                                 solver-efficiency measure); 0 when rho is 0
                                 or rho >= 1                                */
+    double setup_phase_ms[8];/* host wall time of lair_setup by phase (the
+                                waits for the device included): [0] copy,
+                                checks and block scaling of A, [1] strength
+                                and splitting, [2] neighbourhoods,
+                                interpolation and local solves, [3]
+                                Galerkin products and lumping, [4] coarsest
+                                factors, [5] the cycle's operators and
+                                statistics, [6..7] 0                       */
     int32_t hist_len;        /* entries of relres_hist: min(iters + 1,
                                 LAIR_HIST_MAX); 0 for lair_solve_fgmres    */
     double relres_hist[LAIR_HIST_MAX]; /* largest relative residual over the

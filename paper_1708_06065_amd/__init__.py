@@ -304,16 +304,27 @@ def _csr(rowptr, col, val, keep):
 
 
 def _cf_levels(cf_levels, keep):
-    """lair_cf_levels pointer (or None) for a list of per-level splittings."""
+    """lair_cf_levels pointer (or None) for a list of per-level splittings:
+    NumPy arrays (host), or CUDA int8 tensors (device, concatenated on the
+    device)."""
     if cf_levels is None:
         return None
-    arrs = [np.ascontiguousarray(x, dtype=np.int8) for x in cf_levels]
-    offs = np.zeros(len(arrs) + 1, dtype=np.int64)
-    offs[1:] = np.cumsum([x.shape[0] for x in arrs])
-    flat = np.concatenate(arrs) if arrs else np.zeros(1, np.int8)
+    torch = _torch()
+    on_dev = len(cf_levels) > 0 and all(isinstance(x, torch.Tensor) and x.is_cuda
+                                        for x in cf_levels)
+    sizes = [int(x.shape[0]) for x in cf_levels]
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    if on_dev:
+        flat = torch.cat([x.to(torch.int8).contiguous() for x in cf_levels])
+        ptr = ctypes.c_void_p(flat.data_ptr())
+    else:
+        arrs = [np.ascontiguousarray(x, dtype=np.int8) for x in cf_levels]
+        flat = np.concatenate(arrs) if arrs else np.zeros(1, np.int8)
+        ptr = flat.ctypes.data_as(ctypes.c_void_p)
     keep += [offs, flat]
-    cfl = L.CfLevels(len(arrs), offs.ctypes.data_as(ctypes.c_void_p),
-                     flat.ctypes.data_as(ctypes.c_void_p))
+    cfl = L.CfLevels(len(sizes), offs.ctypes.data_as(ctypes.c_void_p), ptr,
+                     1 if on_dev else 0)
     keep.append(cfl)
     return ctypes.byref(cfl)
 
@@ -393,7 +404,8 @@ def setup(rowptr, col, val, cf_levels=None, theta=0.25, theta_c=None,
 
     The arrays may be NumPy arrays (host) or contiguous CUDA tensors
     (int32, int32, float64).  cf_levels is an optional list of per-level
-    int8 CF splittings (1 = C) in host memory.  graphs=False launches the
+    int8 CF splittings (1 = C): NumPy arrays, or CUDA tensors (checked and
+    counted on the device).  graphs=False launches the
     solve's kernels eagerly instead of replaying captured iterations.
     ordering: "auto" runs the cycle on F-first renumbered copies of the
     large sparse levels, "natural" on the natural matrices everywhere,

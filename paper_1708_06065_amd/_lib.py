@@ -37,7 +37,7 @@ class Strength(ctypes.Structure):
 
 
 class CfLevels(ctypes.Structure):
-    _fields_ = [("nlevels", c_i32), ("offs", c_vp), ("cf", c_vp)]
+    _fields_ = [("nlevels", c_i32), ("offs", c_vp), ("cf", c_vp), ("on_device", c_i32)]
 
 
 class Options(ctypes.Structure):
@@ -54,11 +54,13 @@ class Info(ctypes.Structure):
                 ("rho", c_f64), ("cycle_complexity", c_f64),
                 ("op_complexity", c_f64), ("n_singular_local", c_i64),
                 ("setup_ms", c_f64), ("solve_ms", c_f64), ("split_ms", c_f64),
-                ("wpd", c_f64), ("hist_len", c_i32),
+                ("wpd", c_f64), ("setup_phase_ms", c_f64 * 8), ("hist_len", c_i32),
                 ("relres_hist", c_f64 * HIST_MAX)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "relres_hist"}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("relres_hist", "setup_phase_ms")}
+        d["setup_phase_ms"] = list(self.setup_phase_ms)
         d["relres_hist"] = list(self.relres_hist[:max(0, min(self.hist_len, HIST_MAX))])
         return d
 

@@ -134,6 +134,14 @@ struct lair_hierarchy {
     int64_t n_singular = 0;
     double setup_ms = 0.0;
     double split_ms = 0.0;                   // host first-pass splittings in setup
+    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // setup wall time by phase
+    std::chrono::steady_clock::time_point phase_t0;
+    // charge the wall time since the last mark to phase k
+    void phase_mark(int k) {
+        const auto t = std::chrono::steady_clock::now();
+        phase_ms[k] += std::chrono::duration<double, std::milli>(t - phase_t0).count();
+        phase_t0 = t;
+    }
     double cc = 0.0, oc = 0.0;
 };
 

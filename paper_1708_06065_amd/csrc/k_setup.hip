@@ -172,6 +172,68 @@ k_scan_down(F f, int64_t n, int64_t nb, const int64_t *blocksum, const int64_t *
     }
 }
 
+// ===========================================================================
+// Caller's CF splittings in device memory: every value 0 or 1 (else bad[0]
+// is set), with k > 1 every node's k entries alike (else bad[0]), and the
+// C-points of every level counted into cnt[l] (int64).  offs: nlevels + 1
+// level offsets.  The lanes of a wave that lie in the level of the wave's
+// first entry add their count with one atomic; the others (a wave across a
+// level boundary) add one by one.
+// ===========================================================================
+constexpr int CF_LDS_LEVELS = 64;
+
+__global__ void __launch_bounds__(256)
+k_cf_check(int32_t nlevels, const int64_t *offs, const int8_t *cf, int32_t k, int64_t *cnt,
+           int32_t *bad) {
+    __shared__ unsigned long long s_cnt[CF_LDS_LEVELS];
+    for (int l = threadIdx.x; l < CF_LDS_LEVELS; l += blockDim.x) s_cnt[l] = 0;
+    __syncthreads();
+    const int64_t total = offs[nlevels];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t rounds = (total + stride - 1) / stride;
+    int any_bad = 0;
+    for (int64_t r = 0; r < rounds; ++r) {
+        const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + r * stride;
+        const bool in = q < total;
+        int lev = 0;
+        int8_t v = 0;
+        if (in) {
+            while (lev + 1 < nlevels && offs[lev + 1] <= q) ++lev;
+            v = cf[q];
+            bool b = (v & ~1) != 0;
+            if (k > 1) {
+                const int64_t lo = offs[lev];
+                b = b || v != cf[lo + (q - lo) / k * k];
+            }
+            any_bad |= b ? 1 : 0;
+        }
+        // the lanes in the level of the wave's first entry: one LDS add
+        const int first = __shfl(lev, 0);
+        const bool same = in && lev == first;
+        const uint64_t ones = __ballot(same && v == 1);
+        if ((threadIdx.x & (WAVE - 1)) == 0 && ones) {
+            if (first < CF_LDS_LEVELS) atomicAdd(&s_cnt[first], (unsigned long long)__popcll(ones));
+            else atomicAdd((unsigned long long *)&cnt[first], (unsigned long long)__popcll(ones));
+        }
+        if (in && !same && v == 1) {
+            if (lev < CF_LDS_LEVELS) atomicAdd(&s_cnt[lev], 1ull);
+            else atomicAdd((unsigned long long *)&cnt[lev], 1ull);
+        }
+    }
+    if (any_bad) atomicOr(bad, 1);
+    __syncthreads();
+    for (int l = threadIdx.x; l < CF_LDS_LEVELS && l < nlevels; l += blockDim.x)
+        if (s_cnt[l]) atomicAdd((unsigned long long *)&cnt[l], s_cnt[l]);
+}
+
+void launch_cf_check(int32_t nlevels, const int64_t *offs_dev, int64_t total, const int8_t *cf,
+                     int32_t k, int64_t *cnt, int32_t *bad, hipStream_t s) {
+    if (total <= 0) return;
+    const unsigned grid = std::min<unsigned>(blocks_for(total, 256), 1024u);
+    LAIR_LAUNCH(k_cf_check, dim3(grid), dim3(256), 0, s, nlevels, offs_dev, cf, k, cnt, bad);
+    LAIR_LAUNCH_CHECK();
+}
+
 // Short inputs in one launch: one block of SCAN1_BS threads, each thread
 // scanning ipt consecutive entries (read twice: sums, then offsets), the
 // waves' sums combined through LDS.
@@ -321,30 +383,36 @@ __global__ void __launch_bounds__(256)
 k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cj,
            const double *v, int32_t *part) {
     __shared__ int se[256], sm[256];
+    // a fixed grid, rows taken grid-stride (few partial results to combine)
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
-    const int64_t i = gt / VT;
     const int lane = (int)(gt % VT);
+    const int64_t nteam = (int64_t)gridDim.x * blockDim.x / VT;
     int err = 0, len = 0;
     if (gt == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) err = 1;
-    if (i < n) {
-        int64_t lo = rp[i], hi = rp[i + 1];
-        if (lo < 0 || hi < lo || hi > nnz) {
-            err = 1;
-        } else {
-            bool diag = false;
-            for (int64_t p = lo + lane; p < hi; p += VT) {
-                int c = cj[p];
-                if (c < 0 || c >= n) err |= 2;
-                if (p > lo && c <= cj[p - 1]) err |= 4;
-                double a = v[p];
-                if (!isfinite(a)) err |= 8;
-                if (c == i) { diag = true; if (a == 0.0) err |= 16; }
+    const int64_t rounds = (n + nteam - 1) / nteam;
+    for (int64_t k = 0; k < rounds; ++k) {
+        const int64_t i = gt / VT + k * nteam;
+        bool diag = false;
+        if (i < n) {
+            int64_t lo = rp[i], hi = rp[i + 1];
+            if (lo < 0 || hi < lo || hi > nnz) {
+                err |= 1;
+                diag = true;        // reported as bad row pointers only
+            } else {
+                for (int64_t p = lo + lane; p < hi; p += VT) {
+                    int c = cj[p];
+                    if (c < 0 || c >= n) err |= 2;
+                    if (p > lo && c <= cj[p - 1]) err |= 4;
+                    double a = v[p];
+                    if (!isfinite(a)) err |= 8;
+                    if (c == i) { diag = true; if (a == 0.0) err |= 16; }
+                }
+                len = max(len, (int)(hi - lo));
             }
-            if (team_bits<VT>(diag) == 0 && lane == 0) err |= 32;
-            len = (int)(hi - lo);
+        } else {
+            diag = true;
         }
-    } else {
-        (void)team_bits<VT>(false);
+        if (team_bits<VT>(diag) == 0 && lane == 0) err |= 32;
     }
     se[threadIdx.x] = err;
     sm[threadIdx.x] = len;
@@ -385,7 +453,7 @@ k_validate_final(const int32_t *part, int64_t nb, int32_t *stat) {
 
 int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
                      const int32_t *cj, const double *v, hipStream_t s) {
-    const unsigned nb = blocks_for(n * VT, 256);
+    const unsigned nb = std::min<unsigned>(blocks_for(n * VT, 256), 2048u);
     DevArr<int32_t> st;
     st.alloc(2 + 2 * (size_t)nb, s);
     ProfScope ps("validate", s, 12.0 * nnz + 4.0 * (n + 1));

@@ -207,6 +207,11 @@ int64_t scan_flags_i8(const int8_t *flags, int8_t want, int32_t *out, int64_t n,
                       hipStream_t s, DevArr<int64_t> &tmp);
 // the same scans without a readback: tot[0] = total, tot[1] = largest value
 // are written to device memory the caller reads later
+// Check a caller's device CF splittings (0/1 values, whole nodes of k) and
+// count each level's C-points into cnt[0..nlevels) (zeroed int64); bad[0]
+// (zeroed) becomes nonzero on a bad value.  offs_dev: device level offsets.
+void launch_cf_check(int32_t nlevels, const int64_t *offs_dev, int64_t total, const int8_t *cf,
+                     int32_t k, int64_t *cnt, int32_t *bad, hipStream_t s);
 void scan_counts_i32_to(const int32_t *cnt, int32_t *out, int64_t n, hipStream_t s,
                         DevArr<int64_t> &tmp, int64_t *tot);
 void scan_counts_i64_to(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t s,

@@ -516,6 +516,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
             Lv.nnzC = (int64_t)hacc[1];
         }
     }
+    h->phase_mark(1);
     if (h->nsys == 1 && (nc == 0 || (double)nc > h->opt.stall * (double)n)) {
         coarsest = true;
         Lv.smask.release();
@@ -972,6 +973,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
     h->str = *str;
     h->opt = *opt;
     h->stream = s;
+    h->phase_t0 = t0;
     zeroed_slots_reserve(4096, s);
     DevArr<int64_t> tmp;
 
@@ -983,19 +985,50 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         if (cfl->offs[0] != 0 || total < 0) fail(LAIR_EINVAL, "bad CF level offsets");
         for (int32_t l = 0; l < cfl->nlevels; ++l)
             if (cfl->offs[l + 1] < cfl->offs[l]) fail(LAIR_EINVAL, "bad CF level offsets");
+        h->cf_count.assign((size_t)cfl->nlevels, 0);
+        if (cfl->on_device) {
+            // copied, checked and counted on the device; one readback
+            const int32_t nl = cfl->nlevels;
+            h->cf_dev.alloc((size_t)std::max<int64_t>(total, 1), s);
+            if (total > 0)
+                LAIR_HIP(hipMemcpyAsync(h->cf_dev.get(), cfl->cf, (size_t)total,
+                                        hipMemcpyDeviceToDevice, s));
+            int64_t *stage = (int64_t *)pinned_upload(sizeof(int64_t) * (nl + 1));
+            memcpy(stage, cfl->offs, sizeof(int64_t) * (nl + 1));
+            DevArr<int64_t> doffs;
+            doffs.alloc((size_t)nl + 1, s);
+            LAIR_HIP(hipMemcpyAsync(doffs.get(), stage, sizeof(int64_t) * (nl + 1),
+                                    hipMemcpyHostToDevice, s));
+            int64_t *cnt = zeroed_slots((size_t)nl + 1, s);
+            int32_t *badp = reinterpret_cast<int32_t *>(cnt + nl);
+            launch_cf_check(nl, doffs.get(), total, h->cf_dev.get(),
+                            nodal(*opt) ? opt->block_size : 1, cnt, badp, s);
+            std::vector<int64_t> hc((size_t)nl + 1, 0);
+            {
+                Readback rb(s);
+                rb.add(hc.data(), cnt, sizeof(int64_t) * (nl + 1));
+                rb.run();
+            }
+            if ((int32_t)hc[(size_t)nl])
+                fail(LAIR_EINVAL, nodal(*opt) ? "a CF splitting holds a value other than 0/1 "
+                                                "or splits a node"
+                                              : "a CF splitting holds a value other than 0/1");
+            for (int32_t l = 0; l < nl; ++l) h->cf_count[(size_t)l] = hc[(size_t)l];
+        }
         uint8_t bad = 0;
         const uint8_t *cfb = (const uint8_t *)cfl->cf;
-        h->cf_count.assign((size_t)cfl->nlevels, 0);
-        for (int32_t l = 0; l < cfl->nlevels; ++l) {
-            int64_t c = 0;
-            for (int64_t k = cfl->offs[l]; k < cfl->offs[l + 1]; ++k) {
-                bad |= cfb[k] & 0xFE;
-                c += cfb[k] & 1;
+        if (!cfl->on_device) {
+            for (int32_t l = 0; l < cfl->nlevels; ++l) {
+                int64_t c = 0;
+                for (int64_t k = cfl->offs[l]; k < cfl->offs[l + 1]; ++k) {
+                    bad |= cfb[k] & 0xFE;
+                    c += cfb[k] & 1;
+                }
+                h->cf_count[(size_t)l] = c;
             }
-            h->cf_count[(size_t)l] = c;
         }
         if (bad) fail(LAIR_EINVAL, "a CF splitting holds a value other than 0/1");
-        if (total > 0) {
+        if (total > 0 && !cfl->on_device) {
             int8_t *stage = (int8_t *)pinned_staging((size_t)total);
             memcpy(stage, cfl->cf, (size_t)total);
             h->cf_dev.alloc((size_t)total, s);
@@ -1027,7 +1060,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
     L0->max_row = validate_csr(n, nnz, A.rp.get(), A.cj.get(), A.v.get(), s);
     A.max_row = L0->max_row;
 
-    if (nodal(*opt) && cfl && cfl->nlevels > 0) {
+    if (nodal(*opt) && cfl && cfl->nlevels > 0 && !cfl->on_device) {
         // the caller's splittings must give the k rows of a node one type
         const int32_t k = opt->block_size;
         for (int32_t l = 0; l < cfl->nlevels; ++l) {
@@ -1094,7 +1127,9 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         }
         bool coarsest = false;
         SpgemmState ap_st;
+        h->phase_mark(lvl == 0 ? 0 : 3);
         build_level_transfer(h.get(), Lv, lvl, cfl, coarsest, tmp, ap_st);
+        h->phase_mark(2);
         if (coarsest) break;
         // Galerkin product K = R (A P): the sizes of A P reach the host with
         // the count of products of R (A P)
@@ -1136,7 +1171,9 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         if (k_distinct > 0) k_ratio = (double)k_st.h[0] / (double)k_distinct;
         h->L.push_back(std::move(nx));
     }
+    h->phase_mark(h->L.size() == 1 ? 0 : 3);
     finish_coarsest(h.get());
+    h->phase_mark(4);
     for (auto &lp : h->L) {
         Level &Lv = *lp;
         Lv.team_A = team_of(Lv.A);
@@ -1146,6 +1183,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
     finish_cycle_operators(h.get(), s);
     level_stats_and_cc(h.get());
     LAIR_HIP(hipStreamSynchronize(s));
+    h->phase_mark(5);
     h->setup_ms = ms_since(t0);
     return h.release();
 }

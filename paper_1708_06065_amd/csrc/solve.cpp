@@ -351,6 +351,7 @@ void info_common(const lair_hierarchy *h, lair_info *info) {
     info->n_singular_local = h->n_singular;
     info->setup_ms = h->setup_ms;
     info->split_ms = h->split_ms;
+    for (int k = 0; k < 8; ++k) info->setup_phase_ms[k] = h->phase_ms[k];
     // Sec. 4: work units per digit of accuracy, -CC / log10(rho)
     info->wpd = (info->rho > 0.0 && info->rho < 1.0)
                     ? -h->cc / std::log10(info->rho) : 0.0;

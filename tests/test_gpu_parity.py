@@ -69,6 +69,39 @@ def test_c1_levelwise_and_iterations(lair):
     h.free()
 
 
+def test_device_cf_levels_equal_host(lair):
+    """Splittings handed over in device memory (checked and counted on the
+    device) give the hierarchy the host arrays give; a bad value or a
+    wrong length is refused."""
+    import torch
+    from paper_1708_06065_amd import LairError
+    w = W.implicit_euler_adr_3d(m=24, nrhs=1)
+    A = O.csr(w["rowptr"], w["col"], w["val"])
+    H = O.setup(A, interp=O.INTERP_DIRECT, max_coarse=16)
+    cfl = oracle_cf_levels(H)
+    hh = lair.setup(w["rowptr"], w["col"], w["val"], cf_levels=cfl, interp="direct",
+                    max_coarse=16)
+    dcf = [torch.as_tensor(c, device="cuda") for c in cfl]
+    hd = lair.setup(w["rowptr"], w["col"], w["val"], cf_levels=dcf, interp="direct",
+                    max_coarse=16)
+    assert hh.nlevels == hd.nlevels == H.nlevels
+    for l in range(hh.nlevels):
+        for what in ("A.rowptr", "A.col", "A.val"):
+            assert np.array_equal(hh.export(l, what), hd.export(l, what)), (l, what)
+    bad = [c.clone() for c in dcf]
+    bad[1][3] = 2
+    with pytest.raises(LairError) as e:
+        lair.setup(w["rowptr"], w["col"], w["val"], cf_levels=bad, interp="direct",
+                   max_coarse=16)
+    assert e.value.status == -1
+    short = [dcf[0], dcf[1][:-1]]
+    with pytest.raises(LairError):
+        lair.setup(w["rowptr"], w["col"], w["val"], cf_levels=short, interp="direct",
+                   max_coarse=16)
+    hh.free()
+    hd.free()
+
+
 def test_c1_library_rs_split(lair):
     """No CF given: the library's own first-pass splitting equals the oracle's."""
     w = W.workload_c1()
