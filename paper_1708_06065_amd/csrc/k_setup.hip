@@ -1585,7 +1585,6 @@ k_local_lstsq(const int32_t *list, int32_t nlist, const int32_t *clist,
     }
 }
 
-constexpr int SMALL_SM = 8;
 
 // Algorithmic cost of the local solves, split at s <= lim / s > lim:
 // bytes = (|row i| + sum_{j in N_i} |row j|) 12 + (s + 1) 12 (gather and R
@@ -2255,7 +2254,7 @@ struct RowSrc {
 };
 
 __global__ void __launch_bounds__(256)
-k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp, int32_t *e) {
+k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, BRows bp, int32_t *e) {
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     const int32_t i = (int32_t)(gt / 8);
     const int lane = (int)(gt % 8);
@@ -2263,7 +2262,7 @@ k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
     int64_t t = 0;
     for (int p = ap[i] + lane; p < ap[i + 1]; p += 8) {
         int k = aj[p];
-        t += bp[k + 1] - bp[k];
+        t += bp.length(k);
     }
 #pragma unroll
     for (int o = 4; o > 0; o >>= 1) t += __shfl_xor(t, o, 8);
@@ -2273,7 +2272,7 @@ k_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
 template <int T, int LPL>
 __global__ void __launch_bounds__(256)
 k_spgemm_merge(RowSrc src, const int32_t *ap, const int32_t *aj, const double *ax,
-               const int32_t *bp, const int32_t *bj, const double *bx, const int64_t *off,
+               BRows bp, const int32_t *bj, const double *bx, const int64_t *off,
                int32_t *cnt, int32_t *cj, double *cx, int32_t *overflow) {
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     const int lane = (int)(gt % T);
@@ -2300,8 +2299,8 @@ k_spgemm_merge(RowSrc src, const int32_t *ap, const int32_t *aj, const double *a
             mul[s] = 0.0;
             if (k < ka) {
                 int r = aj[lo + k];
-                pos[s] = bp[r];
-                end[s] = bp[r + 1];
+                pos[s] = bp.start(r);
+                end[s] = pos[s] + bp.length(r);
                 mul[s] = ax[lo + k];
             }
 #pragma unroll
@@ -2362,7 +2361,7 @@ constexpr int log2_const() { return HS <= 1 ? 0 : 1 + log2_const<HS / 2>(); }
 template <int T, int HS, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const double *ax,
-              const int32_t *bp, const int32_t *bj, const double *bx, const int64_t *eoff,
+              BRows bp, const int32_t *bj, const double *bx, const int64_t *eoff,
               int32_t *cnt, int32_t *tcj, double *tcx, int32_t *next, int32_t *nnext) {
     constexpr int TEAMS = BLOCK / T;
     constexpr int HC = HS / 2;              // distinct columns a table holds
@@ -2394,8 +2393,8 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
             double a = 0.0;
             if (p < ka) {
                 int k = aj[lo + p];
-                b0 = bp[k];
-                len = bp[k + 1] - b0;
+                b0 = bp.start(k);
+                len = bp.length(k);
                 a = ax[lo + p];
             }
             int inc = len;
@@ -2484,7 +2483,7 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
 
 template <int T, int HS, int BLOCK>
 static void spgemm_hacc(int32_t m, RowSrc src, unsigned grid, const int32_t *ap,
-                        const int32_t *aj, const double *ax, const int32_t *bp,
+                        const int32_t *aj, const double *ax, BRows bp,
                         const int32_t *bj, const double *bx, const int64_t *eoff, int32_t *cnt,
                         int32_t *tcj, double *tcx, int32_t *next, int32_t *nnext,
                         hipStream_t s) {
@@ -2503,7 +2502,7 @@ static int hacc_team(double mean_e) {
 
 constexpr int HACC_BIG = 4096;   // table of the one-team kernel
 
-void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
+void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, BRows bp,
                        int32_t *e, hipStream_t s) {
     if (m == 0) return;
     LAIR_LAUNCH(k_prod_count, dim3(blocks_for((int64_t)m * 8, 256)), dim3(256), 0, s, m,
@@ -2512,7 +2511,7 @@ void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const in
 }
 
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
-                   const int32_t *bp, const int32_t *bj, const double *bx,
+                   BRows bp, const int32_t *bj, const double *bx,
                    const int64_t *eoff, int64_t max_e, double mean_e, double mean_c_hint,
                    int32_t *cnt, int32_t *tcj, double *tcx, int32_t *counts, int32_t *lists,
                    int32_t *overflow, hipStream_t s) {

@@ -316,10 +316,22 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
 // four zeroed by the caller; *overflow zeroed by the caller.  mean_c_hint:
 // an estimate of the distinct columns per row of C (0: none), which sizes
 // the first pass's tables.
-void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, const int32_t *bp,
+// Rows of the right factor B of a sparse product: CSR (rp), or rows staged
+// by an earlier product at offsets off[k] with lengths len[k] (rp null;
+// offsets below 2^31).
+struct BRows {
+    const int32_t *rp = nullptr;
+    const int64_t *off = nullptr;
+    const int32_t *len = nullptr;
+    __device__ __forceinline__ int start(int k) const { return rp ? rp[k] : (int)off[k]; }
+    __device__ __forceinline__ int length(int k) const {
+        return rp ? rp[k + 1] - rp[k] : len[k];
+    }
+};
+void launch_prod_count(int32_t m, const int32_t *ap, const int32_t *aj, BRows bp,
                        int32_t *e, hipStream_t s);
 void launch_spgemm(int32_t m, const int32_t *ap, const int32_t *aj, const double *ax,
-                   const int32_t *bp, const int32_t *bj, const double *bx,
+                   BRows bp, const int32_t *bj, const double *bx,
                    const int64_t *eoff, int64_t max_e, double mean_e, double mean_c_hint,
                    int32_t *cnt, int32_t *tcj, double *tcx, int32_t *counts, int32_t *lists,
                    int32_t *overflow, hipStream_t s);

@@ -65,33 +65,38 @@ __global__ void k_unit_diag_blocks(int32_t n, int32_t k, const int32_t *rp, cons
 struct PendingSizes {
     int64_t *dp = nullptr;           // three zeroed slots: [0] nnz, [1] longest row, [2] flag
     int64_t h[3] = {0, 0, 0};
-    DevCSR *m = nullptr;
+    int64_t *nnz = nullptr;          // where the sizes go (null: nothing pending)
+    int32_t *max_row = nullptr;
     const char *what = "";
     void arm(DevCSR *mat, const char *w, hipStream_t s) {
         arm_at(zeroed_slots(3, s), mat, w);
     }
     // slots already zeroed in stream order (no memset here)
     void arm_at(int64_t *slots, DevCSR *mat, const char *w) {
+        arm_sizes(slots, &mat->nnz, &mat->max_row, w);
+    }
+    void arm_sizes(int64_t *slots, int64_t *n, int32_t *mx, const char *w) {
         dp = slots;
-        m = mat;
+        nnz = n;
+        max_row = mx;
         what = w;
     }
     int64_t *tot() { return dp; }
     int32_t *flag() { return reinterpret_cast<int32_t *>(dp + 2); }
     void add(Readback &rb) {
-        if (m) rb.add(h, dp, sizeof(h));
+        if (nnz) rb.add(h, dp, sizeof(h));
     }
     // after the readback that carried them
     void apply() {
-        if (!m) return;
-        DevCSR *mat = m;
-        m = nullptr;
+        if (!nnz) return;
+        int64_t *n = nnz;
+        nnz = nullptr;
         if ((int32_t)h[2]) fail(LAIR_EUNSUPPORTED, "%s", what);
-        mat->nnz = h[0];
-        mat->max_row = (int32_t)h[1];
+        *n = h[0];
+        *max_row = (int32_t)h[1];
     }
     void settle(hipStream_t s) {
-        if (!m) return;
+        if (!nnz) return;
         Readback rb(s);
         add(rb);
         rb.run();
@@ -113,6 +118,45 @@ static bool setup_sizes_eager() {
 // `defer` the sizes of C stay on the device too (C's arrays are sized by
 // the number of products, an upper bound) and reach the host with a later
 // readback; otherwise they are read at once.
+// The right factor of a product: a CSR matrix, or the rows an earlier
+// product left staged (at their product offsets, with their lengths).
+struct StagedB {
+    DevArr<int64_t> off;
+    DevArr<int32_t> len, cj;
+    DevArr<double> v;
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;                 // distinct entries (once read back)
+    int32_t max_row = -1;
+};
+struct BSrc {
+    BRows rows;
+    const int32_t *cj = nullptr;
+    const double *v = nullptr;
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    static BSrc of(const DevCSR &B) {
+        BSrc b;
+        b.rows.rp = B.rp.get();
+        b.cj = B.cj.get();
+        b.v = B.v.get();
+        b.nrows = B.nrows;
+        b.ncols = B.ncols;
+        b.nnz = B.nnz;
+        return b;
+    }
+    static BSrc of(const StagedB &B) {
+        BSrc b;
+        b.rows.off = B.off.get();
+        b.rows.len = B.len.get();
+        b.cj = B.cj.get();
+        b.v = B.v.get();
+        b.nrows = B.nrows;
+        b.ncols = B.ncols;
+        b.nnz = B.nnz;
+        return b;
+    }
+};
+
 struct SpgemmState {
     int32_t m = 0;
     DevArr<int32_t> cnt;
@@ -131,7 +175,7 @@ struct SpgemmState {
 // The counters the product needs zeroed are cleared here, while earlier
 // work still runs, rather than after the readback that spgemm_finish waits
 // for.
-static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipStream_t s,
+static void spgemm_count(const DevCSR &A, const BSrc &B, SpgemmState &st, hipStream_t s,
                          DevArr<int64_t> &tmp) {
     const int32_t m = A.nrows;
     st.m = m;
@@ -143,7 +187,7 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
     // products per row: A's indices and B's row pointers
     ProfScope ps("spgemm_count", s, 4.0 * A.nnz + 4.0 * (A.nrows + 1) +
                                         8.0 * (B.nrows + 1) + 12.0 * m);
-    launch_prod_count(m, A.rp.get(), A.cj.get(), B.rp.get(), st.cnt.get(), s);
+    launch_prod_count(m, A.rp.get(), A.cj.get(), B.rows, st.cnt.get(), s);
     scan_counts_i64_to(st.cnt.get(), st.eoff.get(), m, s, tmp, st.tot.get());
 }
 
@@ -154,29 +198,62 @@ static void spgemm_count(const DevCSR &A, const DevCSR &B, SpgemmState &st, hipS
 // lump_tol > 0 (not deferred): C is written lumped (Sec. 3.3) straight from
 // the staged rows, in place of the plain compaction.
 // *distinct receives the size C has before lumping.
-static int32_t spgemm_finish(const DevCSR &A, const DevCSR &B, DevCSR &C, SpgemmState &st,
+// The hash pass of C = A B: C's rows sorted at their product offsets in the
+// staging arrays tcj, tcx (sized here by st.h), their lengths in st.cnt.
+static void spgemm_hash(const DevCSR &A, const BSrc &B, SpgemmState &st, hipStream_t s,
+                        double ratio, DevArr<int32_t> &tcj, DevArr<double> &tcx) {
+    const int32_t m = st.m;
+    const int64_t etot = st.h[0], emax = st.h[1];
+    if (etot > INT32_MAX)
+        fail(LAIR_EUNSUPPORTED, "sparse product with more than 2^31 terms (%lld)", (long long)etot);
+    int32_t *ovp = reinterpret_cast<int32_t *>(st.ctl() + 2);
+    tcj.alloc((size_t)std::max<int64_t>(etot, 1), s);
+    tcx.alloc((size_t)std::max<int64_t>(etot, 1), s);
+    // A, the rows of B and the rows of C each touched once
+    ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) +
+                                       4.0 * (B.nrows + 1));
+    const double mean_e = m ? (double)etot / m : 0.0;
+    launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rows, B.cj, B.v, st.eoff.get(),
+                  emax, mean_e, ratio > 1.0 ? mean_e / ratio : 0.0, st.cnt.get(), tcj.get(),
+                  tcx.get(), st.counts(), st.lists(), ovp, s);
+}
+
+// C = A B left staged for a following product (no compaction): its sizes
+// (distinct entries, longest row, the overflow flag) wait in `pend` for a
+// later readback.
+static void spgemm_to_staged(const DevCSR &A, const BSrc &B, StagedB &C, SpgemmState &st,
+                             hipStream_t s, DevArr<int64_t> &tmp, PendingSizes &pend,
+                             double ratio) {
+    DevArr<int32_t> tcj;
+    DevArr<double> tcx;
+    spgemm_hash(A, B, st, s, ratio, tcj, tcx);
+    C.nrows = st.m;
+    C.ncols = B.ncols;
+    C.nnz = st.h[0];                 // an upper bound until the sizes arrive
+    // the totals of the lengths (a scratch scan)
+    DevArr<int32_t> rp;
+    rp.alloc((size_t)st.m + 1, s);
+    pend.arm_sizes(st.ctl(), &C.nnz, &C.max_row, "sparse product row with more than 1024 terms");
+    scan_counts_i32_to(st.cnt.get(), rp.get(), st.m, s, tmp, pend.tot());
+    C.off = std::move(st.eoff);
+    C.len = std::move(st.cnt);
+    C.cj = std::move(tcj);
+    C.v = std::move(tcx);
+}
+
+static int32_t spgemm_finish(const DevCSR &A, const BSrc &B, DevCSR &C, SpgemmState &st,
                              hipStream_t s, DevArr<int64_t> &tmp, PendingSizes *defer,
                              double ratio = 0.0, double lump_tol = 0.0,
                              int64_t *distinct = nullptr, const int8_t *whole_rows = nullptr) {
     const int32_t m = st.m;
-    const int64_t etot = st.h[0], emax = st.h[1];
+    const int64_t etot = st.h[0];
     C.nrows = m;
     C.ncols = B.ncols;
     int32_t *ovp = reinterpret_cast<int32_t *>(st.ctl() + 2);
     if (defer) defer->arm_at(st.ctl(), &C, "sparse product row with more than 1024 terms");
     DevArr<int32_t> tcj;
     DevArr<double> tcx;
-    tcj.alloc((size_t)std::max<int64_t>(etot, 1), s);
-    tcx.alloc((size_t)std::max<int64_t>(etot, 1), s);
-    {
-        // A, the rows of B and the rows of C each touched once
-        ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) +
-                                           4.0 * (B.nrows + 1));
-        const double mean_e = m ? (double)etot / m : 0.0;
-        launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rp.get(), B.cj.get(),
-                      B.v.get(), st.eoff.get(), emax, mean_e, ratio > 1.0 ? mean_e / ratio : 0.0,
-                      st.cnt.get(), tcj.get(), tcx.get(), st.counts(), st.lists(), ovp, s);
-    }
+    spgemm_hash(A, B, st, s, ratio, tcj, tcx);
     C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
     if (lump_tol > 0.0 && !defer) {
@@ -258,13 +335,13 @@ static int32_t spgemm(const DevCSR &A, int32_t max_row_a, const DevCSR &B,
                       DevCSR &C, hipStream_t s, DevArr<int64_t> &tmp, int64_t c_nnz = 0) {
     (void)max_row_a;
     SpgemmState st;
-    spgemm_count(A, B, st, s, tmp);
+    spgemm_count(A, BSrc::of(B), st, s, tmp);
     {
         Readback rb(s);
         rb.add(st.h, st.tot.get(), sizeof(st.h));
         rb.run();
     }
-    return spgemm_finish(A, B, C, st, s, tmp, nullptr,
+    return spgemm_finish(A, BSrc::of(B), C, st, s, tmp, nullptr,
                          c_nnz > 0 ? (double)st.h[0] / (double)c_nnz : 0.0);
 }
 
@@ -638,7 +715,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         }
     }
     // products of A P counted now, read with the local solves
-    spgemm_count(A, P, ap, s, tmp);
+    spgemm_count(A, BSrc::of(P), ap, s, tmp);
     Readback rb(s);
     p_pend.add(rb);
     rb.add(ap.h, ap.tot.get(), sizeof(ap.h));
@@ -1133,10 +1210,12 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         if (coarsest) break;
         // Galerkin product K = R (A P): the sizes of A P reach the host with
         // the count of products of R (A P)
-        DevCSR AP;
+        // A P stays in the product's staging arrays (rows at their product
+        // offsets): R (A P) reads it there, so it is never compacted
+        StagedB AP;
         PendingSizes ap_pend;
-        const bool eager = setup_sizes_eager();
-        spgemm_finish(Lv.A, Lv.P, AP, ap_st, s, tmp, eager ? nullptr : &ap_pend, ap_ratio);
+        spgemm_to_staged(Lv.A, BSrc::of(Lv.P), AP, ap_st, s, tmp, ap_pend, ap_ratio);
+        if (setup_sizes_eager()) ap_pend.settle(s);
         std::unique_ptr<Level> nx(new Level());
         nx->n = Lv.nc;
         if (h->nsys > 1) {
@@ -1154,7 +1233,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
                                 Lv.nc, s);
         }
         SpgemmState k_st;
-        spgemm_count(Lv.R, AP, k_st, s, tmp);
+        spgemm_count(Lv.R, BSrc::of(AP), k_st, s, tmp);
         {
             Readback rb(s);
             rb.add(k_st.h, k_st.tot.get(), sizeof(k_st.h));
@@ -1165,7 +1244,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         if (AP.nnz > 0) ap_ratio = (double)ap_st.h[0] / (double)AP.nnz;
         // rows of K are sorted and unique by construction of the product
         int64_t k_distinct = -1;
-        nx->max_row = spgemm_finish(Lv.R, AP, nx->A, k_st, s, tmp, nullptr, k_ratio,
+        nx->max_row = spgemm_finish(Lv.R, BSrc::of(AP), nx->A, k_st, s, tmp, nullptr, k_ratio,
                                     opt->lump_tol, &k_distinct, whole.get());
         if (k_distinct < 0) k_distinct = nx->A.nnz;
         if (k_distinct > 0) k_ratio = (double)k_st.h[0] / (double)k_distinct;
