@@ -23,6 +23,14 @@ __device__ __forceinline__ int64_t xcd_block_id() {
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Streaming (non-temporal) loads for data that a kernel reads once and
+// that is far larger than the caches: the lines are not kept, so the caches
+// stay with the gathered vectors.
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <class T, int N>
+using ExtVec = T __attribute__((ext_vector_type(N)));
+
 // Butterfly reductions over a team of T consecutive lanes (T a power of two
 // dividing 64).  Every lane of the team receives the result; the order of
 // the additions is fixed, so results are reproducible run to run.

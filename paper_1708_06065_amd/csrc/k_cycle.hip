@@ -113,6 +113,16 @@ struct Pack {
         for (int k = 0; k < VW; ++k) q[k] = v[k];
         *reinterpret_cast<typename VecT<VT, VW>::T *>(p) = t;
     }
+    // streaming load (data read once, far larger than the caches)
+    __device__ __forceinline__ void load_nt(const VT *p) {
+        if constexpr (VW == 1) {
+            v[0] = ld_stream(p);
+        } else {
+            const ExtVec<VT, VW> t = ld_stream(reinterpret_cast<const ExtVec<VT, VW> *>(p));
+#pragma unroll
+            for (int k = 0; k < VW; ++k) v[k] = t[k];
+        }
+    }
 };
 
 // Row k of a row list: rows[k], or row0 + k for a contiguous range
@@ -130,11 +140,16 @@ __device__ __forceinline__ int32_t list_row(const int32_t *rows, int32_t row0, i
 // U: steps of T entries taken together (their loads all in flight before
 // the first product); a lane still adds its entries in increasing order, so
 // the sums do not depend on U.
-template <class VT, int NR, int VW, bool SEL, bool TAG = false, int U = 1>
+// NTA: the row's entries are streamed (read once).
+// RNG: columns >= csplit are read from xC, the others from xF (a vector
+// whose rows from csplit on were left in another buffer).
+template <class VT, int NR, int VW, bool SEL, bool TAG = false, int U = 1, bool NTA = false,
+          bool RNG = false>
 __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_col,
                                          const int32_t *cj, const VT *v,
                                          const VT *xF, const VT *xC,
-                                         const int8_t *cf, Pack<VT, VW> &acc, VT &d) {
+                                         const int8_t *cf, Pack<VT, VW> &acc, VT &d,
+                                         int csplit = 0) {
     constexpr int L = NR / VW;
     const int q = t % L;
     const int g0 = (t / L) * L;      // first entry of this lane's group
@@ -146,7 +161,10 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
             const int p = base + u * T + t;
             c[u] = 0;
             a[u] = (VT)0;
-            if (p < hi) { c[u] = cj[p]; a[u] = v[p]; }
+            if (p < hi) {
+                c[u] = NTA ? ld_stream(cj + p) : cj[p];
+                a[u] = NTA ? ld_stream(v + p) : v[p];
+            }
         }
         int ce[U][L];
         VT ae[U][L];
@@ -165,7 +183,9 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
                 if (base + u * T + g0 + e < hi) {
                     const int col = TAG ? (ce[u][e] & 0x7fffffff) : ce[u][e];
                     const VT *src = TAG ? (ce[u][e] < 0 ? xC : xF)
-                                        : (SEL ? (cf[col] ? xC : xF) : xF);
+                                  : SEL ? (cf[col] ? xC : xF)
+                                  : RNG ? (col >= csplit ? xC : xF)
+                                        : xF;
                     xe[u][e].load(src + (int64_t)col * NR + q * VW);
                     if (col == diag_col) d = ae[u][e];
                 } else {
@@ -187,10 +207,10 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
     }
 }
 
-template <class VT, int NR, int VW, int MODE, int U>
+template <class VT, int NR, int VW, int MODE, int U, bool RNG>
 __global__ void __launch_bounds__(256)
 k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *v,
-          const VT *x, const VT *b, VT *y) {
+          const VT *x, const VT *xhi, int32_t csplit, const VT *b, VT *y) {
     constexpr int L = NR / VW;
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
@@ -199,8 +219,8 @@ k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *
     Pack<VT, VW> acc;
     acc.zero();
     VT d = (VT)0;
-    row_accV<VT, NR, VW, false, false, U>(rp[i], rp[i + 1], t, T, -1, cj, v, x, x, nullptr,
-                                          acc, d);
+    row_accV<VT, NR, VW, false, false, U, false, RNG>(rp[i], rp[i + 1], t, T, -1, cj, v, x,
+                                                      RNG ? xhi : x, nullptr, acc, d, csplit);
     if (t >= L) return;
     const int64_t o = (int64_t)i * NR + t * VW;
     Pack<VT, VW> out;
@@ -292,14 +312,15 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
         Pack<double, VW> acc;
         acc.zero();
         double d = 0.0;
-        row_accV<double, NR, VW, false>(rp[i], rp[i + 1], t, T, -1, cj, v, x, x, nullptr,
-                                        acc, d);
+        // the matrix and b are streamed (read once), x is gathered
+        row_accV<double, NR, VW, false, false, 1, true>(ld_stream(rp + i), ld_stream(rp + i + 1),
+                                                        t, T, -1, cj, v, x, x, nullptr, acc, d);
         if (t < L) {
             const int64_t o = i * NR + t * VW;
             // the residual goes to row orow[i] (another ordering) if given
             const int64_t oo = orow ? (int64_t)orow[i] * NR + t * VW : o;
             Pack<double, VW> r;
-            r.load(b + o);
+            r.load_nt(b + o);
 #pragma unroll
             for (int k = 0; k < VW; ++k) {
                 r.v[k] -= acc.v[k];
@@ -307,8 +328,10 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
             }
             if (OUT64) r.store(r64 + oo);
             if (OUT32) {
+                Pack<float, VW> rf;
 #pragma unroll
-                for (int k = 0; k < VW; ++k) r32[oo + k] = (float)r.v[k];
+                for (int k = 0; k < VW; ++k) rf.v[k] = (float)r.v[k];
+                rf.store(r32 + oo);
             }
         }
     }
@@ -395,16 +418,24 @@ k_rowdotM(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
     else y[o] += acc;
 }
 
+// x_hi (optional): the rows of x from csplit on are read there instead
+// (only on the vector path, see op_spmv_split_ok).
 template <class VT, int MODE>
 static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
-                   int32_t nrhs, hipStream_t s) {
+                   int32_t nrhs, hipStream_t s, const VT *x_hi = nullptr, int32_t csplit = 0) {
     if (A.nrows == 0) return;
-    if (nrhs > 1 && aligned16(x) && aligned16(y) && (!b || aligned16(b))) {
+    if (nrhs > 1 && aligned16(x) && aligned16(y) && (!b || aligned16(b)) &&
+        (!x_hi || aligned16(x_hi))) {
         constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
 #define LAIR_RVU(NN, WW, UU)                                                      \
-        LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU>),                            \
-                           dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, y);
+        if (x_hi)                                                                 \
+            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, true>),                  \
+                        dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
+                        A.nrows, T, A.rp, A.cj, A.v, x, x_hi, csplit, b, y);      \
+        else                                                                      \
+            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, false>),                 \
+                        dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
+                        A.nrows, T, A.rp, A.cj, A.v, x, x, 0, b, y);
 #define LAIR_RV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
@@ -423,6 +454,7 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
         LAIR_LAUNCH_CHECK();
         return;
     }
+    if (x_hi) fail(LAIR_EINVAL, "a vector split over two buffers needs aligned multi-vectors");
     if (nrhs > 1) {
 #define LAIR_RM(NN)                                                               \
     LAIR_LAUNCH((k_rowdotM<VT, NN, MODE>),                                 \
@@ -464,9 +496,13 @@ void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
 
 template <class VT>
 void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
-             bool accumulate, hipStream_t s) {
-    if (accumulate) rowdot<VT, MODE_ADD>(A, x, nullptr, y, nrhs, s);
-    else rowdot<VT, MODE_SET>(A, x, nullptr, y, nrhs, s);
+             bool accumulate, hipStream_t s, const VT *x_hi, int32_t csplit) {
+    if (accumulate) rowdot<VT, MODE_ADD>(A, x, nullptr, y, nrhs, s, x_hi, csplit);
+    else rowdot<VT, MODE_SET>(A, x, nullptr, y, nrhs, s, x_hi, csplit);
+}
+
+bool op_spmv_split_ok(int32_t nrhs, const void *x, const void *x_hi, const void *y) {
+    return nrhs > 1 && aligned16(x) && aligned16(x_hi) && aligned16(y);
 }
 
 template <class VT, int MODE>
@@ -953,12 +989,14 @@ __global__ void k_axpy_f32(double *x, const float *e, int64_t n) {
 // VW consecutive entries of a row per thread; lgv = log2(nrhs / VW).
 // x[i] += e[map[i]] (e in another ordering)
 template <int VW>
-__global__ void k_axpy_f32_rows(double *x, const float *e, const int32_t *map, int64_t nv,
-                                int lgv) {
+__global__ void k_axpy_f32_rows(double *x, const float *e, const float *e_hi, int32_t split,
+                                const int32_t *map, int64_t nv, int lgv) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nv) return;
     const int64_t i = g >> lgv;
-    const int64_t src = (((int64_t)map[i] << lgv) | (g & ((1 << lgv) - 1))) * VW;
+    const int32_t m = map[i];
+    if (e_hi && m >= split) e = e_hi;
+    const int64_t src = (((int64_t)m << lgv) | (g & ((1 << lgv) - 1))) * VW;
     constexpr int XW = VW >= 2 ? 2 : 1;    // x in 16-byte pieces
     Pack<float, VW> ev;
     ev.load(e + src);
@@ -999,15 +1037,15 @@ static int ilog2(int32_t v) {
 }
 
 void op_axpy_f32_rows(double *x, const float *e, const int32_t *map, int64_t n, int32_t nrhs,
-                      hipStream_t s) {
+                      hipStream_t s, const float *e_hi, int32_t split) {
     if (n == 0) return;
-    if (nrhs % 4 == 0 && aligned16(x)) {
+    if (nrhs % 4 == 0 && aligned16(x) && aligned16(e) && (!e_hi || aligned16(e_hi))) {
         const int64_t nv = n * nrhs / 4;
-        LAIR_LAUNCH(k_axpy_f32_rows<4>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, x, e, map,
-                    nv, ilog2(nrhs / 4));
+        LAIR_LAUNCH(k_axpy_f32_rows<4>, dim3(blocks_for(nv, 256)), dim3(256), 0, s, x, e, e_hi,
+                    split, map, nv, ilog2(nrhs / 4));
     } else {
         LAIR_LAUNCH(k_axpy_f32_rows<1>, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, s, x, e,
-                    map, n * nrhs, ilog2(nrhs));
+                    e_hi, split, map, n * nrhs, ilog2(nrhs));
     }
     LAIR_LAUNCH_CHECK();
 }
@@ -1080,8 +1118,8 @@ void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
 // explicit instantiations
 template void op_residual<double>(const CsrView<double> &, const double *, const double *, double *, int32_t, hipStream_t);
 template void op_residual<float>(const CsrView<float> &, const float *, const float *, float *, int32_t, hipStream_t);
-template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t);
-template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t);
+template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t, const double *, int32_t);
+template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t, const float *, int32_t);
 template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t, const int32_t *, int32_t);
 template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t, const int32_t *, int32_t);
 template void op_rowdot_list<double>(const CsrView<double> &, int, const int32_t *, const int32_t *, int32_t, const double *, const double *, double *, hipStream_t);

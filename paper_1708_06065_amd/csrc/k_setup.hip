@@ -1459,6 +1459,217 @@ __device__ __forceinline__ void wave_solve(int32_t c, const int32_t *clist, cons
     }
 }
 
+// Block form of the local systems (Sec. 3.1): the k rows of a C-node share
+// their neighbourhood, so the k systems A(N,N)^T z_a = -A(i_a,N)^T have one
+// matrix and k right-hand sides.  One wave per node factors M once (the
+// pivoting of wave_solve) and carries the k right-hand sides through the
+// elimination, the back substitution and, in MIXED, the refinement; every
+// right-hand side sees exactly the operations wave_solve applies to it, so
+// the rows of R equal those of k separate solves bit for bit.  The node's
+// rows are clist[c0 .. c0 + k - 1] = i0 .. i0 + k - 1 with c0 = node k;
+// a node whose rows do not have that form or whose lists differ in length
+// is counted in *bad and left alone.  Systems up to `cap` rows (<= WSMAX).
+constexpr size_t NODE_LDS_MAX = 64 * 1024;   // dynamic LDS of one workgroup
+
+template <class FT>
+__host__ __device__ constexpr size_t node_lds_bytes(int cap, int k) {
+    return (size_t)cap * cap * sizeof(FT) +
+           (sizeof(FT) == sizeof(float) ? (size_t)cap * cap * sizeof(double) : 0) +
+           (size_t)k * cap * (2 * sizeof(double) + sizeof(FT)) +
+           (size_t)cap * 4 * sizeof(int32_t) + 64;
+}
+
+// q / d for 0 <= q < 2^13 and 1 <= d <= 64 by a float reciprocal: the
+// product's error stays below 2^13 2^-22 / d < 0.5 / d, the distance of
+// (q + 1/2) / d to the nearest integer, so the floor is exact (the loops
+// below would otherwise spend most of their instructions on divisions).
+struct SmallDiv {
+    float inv;
+    int d;
+    __device__ explicit SmallDiv(int dd) : inv(1.0f / (float)dd), d(dd) {}
+    __device__ int quot(int q) const { return (int)(((float)q + 0.5f) * inv); }
+};
+
+template <bool MIXED>
+__global__ void __launch_bounds__(64)
+k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr,
+             const int32_t *nbr, const int32_t *rp, const int32_t *cj, const double *v,
+             int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing, int32_t *nsing,
+             int32_t *bad, int32_t cap) {
+    using FT = typename std::conditional<MIXED, float, double>::type;
+    extern __shared__ double dyn[];
+    const int lane = threadIdx.x;
+    const int32_t m = cap;
+    // layout: z[k][m], f[k][m], Md[m][m] (MIXED), M[m][m], w[k][m] (FT),
+    // ln, perm, off, st (int)
+    double *z = dyn;
+    double *f = z + (size_t)k * m;
+    double *Md = MIXED ? f + (size_t)k * m : nullptr;
+    FT *M = (FT *)(f + (size_t)k * m + (MIXED ? (size_t)m * m : 0));
+    FT *w = M + (size_t)m * m;
+    int32_t *ln = (int32_t *)(w + (size_t)k * m);
+    int32_t *perm = ln + m;
+    int32_t *off = perm + m;
+    int32_t *st = off + m + 1;
+    for (int64_t node = blockIdx.x; node < nnode; node += gridDim.x) {
+        const int32_t c0 = (int32_t)(node * k);
+        const int32_t i0 = clist[c0];
+        const int32_t n0 = nptr[c0];
+        const int s = nptr[c0 + 1] - n0;
+        bool ok = s <= cap;
+        for (int a = 1; a < k; ++a)
+            ok = ok && clist[c0 + a] == i0 + a && nptr[c0 + a + 1] - nptr[c0 + a] == s;
+        if (!ok) {
+            if (lane == 0) atomicAdd(bad, 1);
+            continue;
+        }
+        const int32_t *l = nbr + n0;
+        const SmallDiv ds(s > 0 ? s : 1);
+        if (lane < k) flags[c0 + lane] = 0;
+        __syncthreads();
+        for (int idx = lane; idx < s * s; idx += 64) {
+            M[idx] = (FT)0;
+            if (MIXED) Md[idx] = 0.0;
+        }
+        for (int idx = lane; idx < k * s; idx += 64) f[idx] = 0.0;
+        for (int p = lane; p < s; p += 64) { ln[p] = l[p]; perm[p] = p; }
+        __syncthreads();
+        gather_local<64, 4, true, FT>(lane, s, ln, off, st, rp, cj, v, M, s, Md);
+        // right-hand side a: -A(i_a, N)^T
+        for (int a = 0; a < k; ++a)
+            for (int e = rp[i0 + a] + lane; e < rp[i0 + a + 1]; e += 64) {
+                int p = bsearch_i32(ln, s, cj[e]);
+                if (p >= 0) f[a * s + p] = -v[e];
+            }
+        __syncthreads();
+        double rs = 0.0;
+        for (int p = lane; p < s; p += 64) {
+            double acc = 0.0;
+            for (int q = 0; q < s; ++q) acc += fabs(MIXED ? Md[p * s + q] : (double)M[p * s + q]);
+            rs = fmax(rs, acc);
+        }
+        const double tol = SING_TOL * team_max<64>(rs);
+        for (int idx = lane; idx < k * s; idx += 64) w[idx] = (FT)f[idx];
+        __syncthreads();
+        bool singular = false;
+        for (int kk = 0; kk < s; ++kk) {
+            double pv = -1.0;
+            int pr = INT_MAX;
+            for (int r = kk + lane; r < s; r += 64) {
+                double av = fabs((double)M[r * s + kk]);
+                if (av > pv) { pv = av; pr = r; }
+            }
+            team_argmax<64>(pv, pr);
+            if (pv <= tol) { singular = true; break; }
+            if (pr != kk) {
+                for (int q = lane; q < s; q += 64) {
+                    FT t = M[kk * s + q]; M[kk * s + q] = M[pr * s + q]; M[pr * s + q] = t;
+                }
+                if (lane < k) {
+                    FT t = w[lane * s + kk]; w[lane * s + kk] = w[lane * s + pr];
+                    w[lane * s + pr] = t;
+                }
+                if (lane == 0) { int tp = perm[kk]; perm[kk] = perm[pr]; perm[pr] = tp; }
+            }
+            __syncthreads();
+            // multipliers, then every right-hand side (its pivot entry is
+            // final: the multipliers of this step only touch rows below)
+            for (int r = kk + 1 + lane; r < s; r += 64) M[r * s + kk] = M[r * s + kk] / M[kk * s + kk];
+            __syncthreads();
+            const int below = s - kk - 1;
+            if (below > 0) {
+                const SmallDiv db(below);
+                for (int idx = lane; idx < k * below; idx += 64) {
+                    const int a = db.quot(idx), r = kk + 1 + idx - a * below;
+                    w[a * s + r] -= M[r * s + kk] * w[a * s + kk];
+                }
+                for (int idx = lane; idx < below * below; idx += 64) {
+                    const int rr = db.quot(idx);
+                    const int r = kk + 1 + rr, q = kk + 1 + idx - rr * below;
+                    M[r * s + q] -= M[r * s + kk] * M[kk * s + q];
+                }
+            }
+            __syncthreads();
+        }
+        if (singular) {
+            if (lane == 0) {
+                const int32_t o = atomicAdd(nsing, k);
+                for (int a = 0; a < k; ++a) {
+                    flags[c0 + a] = 1;
+                    sing[o + a] = c0 + a;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        // back substitution, column oriented for each right-hand side
+        for (int kk = s - 1; kk >= 0; --kk) {
+            const int rows = kk + 1;
+            const SmallDiv dr(rows);
+            for (int idx = lane; idx < k * rows; idx += 64) {
+                const int a = dr.quot(idx), r = idx - a * rows;
+                const FT zk = w[a * s + kk] / M[kk * s + kk];
+                if (r == kk) z[a * s + kk] = (double)zk;
+                else w[a * s + r] -= M[r * s + kk] * zk;
+            }
+            __syncthreads();
+        }
+        if (MIXED) {
+            // one refinement per right-hand side in double (as wave_solve)
+            for (int idx = lane; idx < k * s; idx += 64) {
+                const int a = ds.quot(idx), p = idx - a * s;
+                double acc = f[a * s + p];
+                for (int q = s - 1; q >= 0; --q) acc -= Md[p * s + q] * z[a * s + q];
+                f[a * s + p] = acc;
+            }
+            __syncthreads();
+            for (int idx = lane; idx < k * s; idx += 64) {
+                const int a = ds.quot(idx), kk = idx - a * s;
+                w[a * s + kk] = (FT)f[a * s + perm[kk]];
+            }
+            __syncthreads();
+            for (int kk = 0; kk < s; ++kk) {
+                const int below = s - kk - 1;
+                if (below > 0) {
+                    const SmallDiv db(below);
+                    for (int idx = lane; idx < k * below; idx += 64) {
+                        const int a = db.quot(idx), r = kk + 1 + idx - a * below;
+                        w[a * s + r] -= M[r * s + kk] * w[a * s + kk];
+                    }
+                }
+                __syncthreads();
+            }
+            for (int kk = s - 1; kk >= 0; --kk) {
+                const int rows = kk + 1;
+                const SmallDiv dr(rows);
+                for (int idx = lane; idx < k * rows; idx += 64) {
+                    const int a = dr.quot(idx), r = idx - a * rows;
+                    const FT zk = w[a * s + kk] / M[kk * s + kk];
+                    if (r == kk) z[a * s + kk] += (double)zk;
+                    else w[a * s + r] -= M[r * s + kk] * zk;
+                }
+                __syncthreads();
+            }
+        }
+        // rows of R: N with the identity entry at the row's place
+        int ip = 0;
+        for (int q = lane; q < s; q += 64) ip += (ln[q] < i0) ? 1 : 0;
+        ip = team_sum_int<64>(ip);
+        for (int idx = lane; idx < k * s; idx += 64) {
+            const int a = ds.quot(idx), q = idx - a * s;
+            const int64_t o = (int64_t)nptr[c0 + a] + c0 + a + q + (q >= ip ? 1 : 0);
+            r_cj[o] = ln[q];
+            r_v[o] = z[a * s + q];
+        }
+        if (lane < k) {
+            const int64_t o = (int64_t)nptr[c0 + lane] + c0 + lane + ip;
+            r_cj[o] = i0 + lane;
+            r_v[o] = 1.0;
+        }
+        __syncthreads();
+    }
+}
+
 // The one-wave bucket: a fixed grid striding over the bucket's length on
 // the device, one global slab per block.
 template <bool MIXED>
@@ -1591,11 +1802,19 @@ k_local_lstsq(const int32_t *list, int32_t nlist, const int32_t *clist,
 // row), flops = 2 s^3 / 3 + 2 s^2 (LU and triangular solves).
 __global__ void __launch_bounds__(256)
 k_local_cost(int32_t nc, const int32_t *clist, const int32_t *nptr,
-             const int32_t *nbr, const int32_t *rp, int32_t lim, double *acc) {
+             const int32_t *nbr, const int32_t *rp, int32_t lim, double *acc,
+             int32_t knode) {
     __shared__ double sh[4][256];
     int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (c < nc) {
+    if (c < nc && knode > 1 && c % knode != 0) {
+        // a node's later rows: their right-hand side, substitutions and row
+        // of R (the gather and the factorisation are the first row's)
+        int32_t i = clist[c];
+        double ds = (double)(nptr[c + 1] - nptr[c]);
+        v[0] = 12.0 * (double)(rp[i + 1] - rp[i]) + 12.0 * (ds + 1);
+        v[1] = 2.0 * ds * ds;
+    } else if (c < nc) {
         int32_t i = clist[c];
         int s = nptr[c + 1] - nptr[c];
         double rows = (double)(rp[i + 1] - rp[i]);
@@ -1770,16 +1989,84 @@ void run_buckets(LocalRun &r, const Buckets &bk, hipStream_t s) {
 // Local solves of one level: bucket edges (fixed, cached or tuned), one
 // pass over the buckets, one readback (bucket sizes and the number of
 // singular systems), then least squares for the singular ones.
+bool node_solves_fit(int32_t k, int32_t smax, int32_t precision) {
+    if (k < 2 || smax > WSMAX) return false;
+    const int cap = std::max(1, smax);
+    const size_t b = precision == LAIR_MIXED ? node_lds_bytes<float>(cap, k)
+                                             : node_lds_bytes<double>(cap, k);
+    return b <= NODE_LDS_MAX;
+}
+
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
                      LocalSolveOut out, hipStream_t s, int32_t *edges_used,
-                     Readback *rb_extra) {
+                     Readback *rb_extra, int32_t knode) {
     if (nc == 0) {
         if (rb_extra) rb_extra->run();
         return 0;
     }
     const bool mixed = (precision == LAIR_MIXED);
+    if (knode > 1) {
+        // one factorisation per node, k right-hand sides (the caller checked
+        // node_solves_fit)
+        if (nc % knode != 0 || !node_solves_fit(knode, smax, precision))
+            fail(LAIR_EINVAL, "node local solves: %d C-rows, nodes of %d, systems up to %d",
+                 nc, knode, smax);
+        DevArr<int32_t> sing;
+        sing.alloc((size_t)nc, s);
+        int32_t *cnt = reinterpret_cast<int32_t *>(zeroed_slots(4, s));   // [0] bad, [6] nsing
+        const int32_t nnode = nc / knode;
+        const int cap = std::max(1, smax);
+        const unsigned g = (unsigned)std::min<int64_t>(nnode, 8192);
+        double cost[4] = {0, 0, 0, 0};
+        if (prof_selected("local_node")) {
+            DevArr<double> acc;
+            acc.alloc(4, s);
+            LAIR_HIP(hipMemsetAsync(acc.get(), 0, 4 * sizeof(double), s));
+            LAIR_LAUNCH(k_local_cost, dim3(blocks_for(nc, 256)), dim3(256), 0, s, nc, clist,
+                        nptr, nbr, rp, WSMAX, acc.get(), knode);
+            LAIR_LAUNCH_CHECK();
+            Readback rb(s);
+            rb.add(cost, acc.get(), sizeof(cost));
+            rb.run();
+        }
+        {
+            ProfScope ps("local_node", s, cost[0], cost[1]);
+            if (mixed)
+                LAIR_LAUNCH(k_local_node<true>, dim3(g), dim3(64),
+                            node_lds_bytes<float>(cap, knode), s, nnode, knode, clist, nptr, nbr,
+                            rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(), cnt + 6, cnt,
+                            cap);
+            else
+                LAIR_LAUNCH(k_local_node<false>, dim3(g), dim3(64),
+                            node_lds_bytes<double>(cap, knode), s, nnode, knode, clist, nptr,
+                            nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(), cnt + 6,
+                            cnt, cap);
+            LAIR_LAUNCH_CHECK();
+        }
+        int32_t h[7] = {0, 0, 0, 0, 0, 0, 0};
+        {
+            Readback own(s);
+            Readback &rb = rb_extra ? *rb_extra : own;
+            rb.add(h, cnt, sizeof(h));
+            rb.run();
+        }
+        if (h[0] > 0)
+            fail(LAIR_EINVAL, "%d C-node(s) whose rows do not share one neighbourhood", h[0]);
+        const int32_t nsing = h[6];
+        if (nsing > 0) {
+            DevArr<double> scratch;
+            scratch.alloc((size_t)nsing * (2 * (size_t)smax * smax + 2 * (size_t)smax), s);
+            ProfScope ps_ls("local_lstsq", s, 0.0);
+            LAIR_LAUNCH(k_local_lstsq, dim3((unsigned)nsing), dim3(64), 0, s,
+                        sing.get(), nsing, clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v,
+                        scratch.get(), smax);
+            LAIR_LAUNCH_CHECK();
+            LAIR_HIP(hipStreamSynchronize(s));
+        }
+        return nsing;
+    }
     DevArr<int32_t> work;
     work.alloc((size_t)nc * (NBUCKET + 1) + 8, s);
     LocalRun r{nc, clist, nptr, nbr, rp, cj, v, mixed, smax, out, nullptr,
@@ -1804,7 +2091,7 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         acc.alloc(4, s);
         LAIR_HIP(hipMemsetAsync(acc.get(), 0, 4 * sizeof(double), s));
         LAIR_LAUNCH(k_local_cost, dim3(blocks_for(nc, 256)), dim3(256), 0, s,
-                           nc, clist, nptr, nbr, rp, 32, acc.get());
+                           nc, clist, nptr, nbr, rp, 32, acc.get(), 1);
         LAIR_LAUNCH_CHECK();
         Readback rb(s);
         rb.add(cost, acc.get(), sizeof(cost));

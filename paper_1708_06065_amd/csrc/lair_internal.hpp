@@ -283,11 +283,15 @@ void op_scale_rhs(int64_t n, int32_t R, const double *w, const double *sc, doubl
 constexpr int32_t WSMAX = 64;
 // returns the number of systems solved by least squares.  smax may be an
 // upper bound of the largest system (it selects kernels and tables).
+// knode > 1: the C-rows form nodes of knode consecutive rows that share
+// one neighbourhood (the nodal treatment), solved as one system with knode
+// right-hand sides each; needs node_solves_fit(knode, smax, precision).
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                      const int32_t *nbr, const int32_t *rp, const int32_t *cj,
                      const double *v, int32_t precision, int32_t smax, double mean_row,
                      LocalSolveOut out, hipStream_t s, int32_t *edges_used = nullptr,
-                     Readback *rb_extra = nullptr);
+                     Readback *rb_extra = nullptr, int32_t knode = 1);
+bool node_solves_fit(int32_t k, int32_t smax, int32_t precision);
 // process-wide bucket edges of the local solves and the fused flag (5
 // values; nullptr: tune per shape); edges_used receives 5 values
 void set_local_buckets(const int32_t *edges);
@@ -377,9 +381,13 @@ void launch_tag_columns(int64_t nnz, const int32_t *cj, const int8_t *cf, int32_
 template <class VT>
 void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
                  int32_t nrhs, hipStream_t s);
+// y = A x (or y += A x).  With x_hi, the entries of x at rows >= csplit are
+// read from x_hi instead (a vector whose upper rows were left in another
+// buffer); that needs the aligned multi-vector path (op_spmv_split_ok).
 template <class VT>
 void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
-             bool accumulate, hipStream_t s);
+             bool accumulate, hipStream_t s, const VT *x_hi = nullptr, int32_t csplit = 0);
+bool op_spmv_split_ok(int32_t nrhs, const void *x, const void *x_hi, const void *y);
 // Jacobi on rows X: out[k] (compact) or out[i] = x_i + omega (b - A x)_i / a_ii.
 // With cf non-null, neighbour values come from xC at C-points and from xF
 // at F-points; otherwise everything is read from xF.  rows == nullptr
@@ -424,9 +432,10 @@ bool op_residual_norm(const CsrView<double> &A, const double *b, const double *x
 void op_sumsq(const double *r, int64_t n, int32_t nrhs, double *partial,
               int32_t npartial, double *out, hipStream_t s);
 void op_axpy_f32(double *x, const float *e, int64_t n, hipStream_t s);
-// x[i] += e[map[i]], out[map[i]] = (float) in[i] (rows of nrhs)
+// x[i] += e[map[i]], out[map[i]] = (float) in[i] (rows of nrhs); with e_hi
+// the rows map[i] >= split of e are read from e_hi
 void op_axpy_f32_rows(double *x, const float *e, const int32_t *map, int64_t n, int32_t nrhs,
-                      hipStream_t s);
+                      hipStream_t s, const float *e_hi = nullptr, int32_t split = 0);
 void op_cast_f32_rows(const double *in, float *out, const int32_t *map, int64_t n,
                       int32_t nrhs, hipStream_t s);
 void op_cast_f32(const double *in, float *out, int64_t n, hipStream_t s);

@@ -11,6 +11,7 @@
 #include <array>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -106,6 +107,12 @@ struct PendingSizes {
 
 // The profiler attributes algorithmic bytes from host-side sizes as it
 // launches; while it times the setup categories every size is read at once.
+// An environment switch: set and not "0".
+static bool env_flag(const char *name) {
+    const char *e = std::getenv(name);
+    return e && *e && std::strcmp(e, "0") != 0;
+}
+
 static bool setup_sizes_eager() {
     return prof_selected("spgemm_fill") || prof_selected("spgemm_compact") ||
            prof_selected("spgemm_count") || prof_selected("interp");
@@ -724,11 +731,16 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
 
     Lv.flags.alloc((size_t)Lv.nc, s);
     LocalSolveOut out{R.rp.get(), R.cj.get(), R.v.get(), Lv.flags.get()};
+    const int32_t lprec = h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED;
+    // nodal: the k rows of a C-node share N, one factorisation per node
+    // (LAIR_NODAL_ROW_SOLVES=1 solves every row on its own instead, the
+    // same numbers; for checks)
+    const int32_t knode = nod && node_solves_fit(kb, Lv.st.s_max, lprec) &&
+                                  !env_flag("LAIR_NODAL_ROW_SOLVES") ? kb : 1;
     int64_t nsing = local_solves(Lv.nc, Lv.clist.get(), Lv.nptr.get(), Lv.nbr.get(),
-                                 A.rp.get(), A.cj.get(), A.v.get(),
-                                 h->opt.precision == LAIR_FP64 ? LAIR_FP64 : LAIR_MIXED,
+                                 A.rp.get(), A.cj.get(), A.v.get(), lprec,
                                  Lv.st.s_max, n ? (double)A.nnz / n : 0.0, out, s,
-                                 Lv.buckets, &rb);
+                                 Lv.buckets, &rb, knode);
     p_pend.apply();
     if (defer_nbr) {
         R.nnz = hnt[0] + Lv.nc;

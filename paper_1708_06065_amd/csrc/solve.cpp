@@ -98,9 +98,12 @@ static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
 //   F sweep 2 reads Y at F-points and X at C-points, writes X at the F rows
 //     (X's F entries are not read by this sweep);
 //   C sweep reads X, writes a compact buffer that is then scattered to X.
+// With leave_c on a split-ordered level (C rows nf .. n-1) the C sweep
+// writes Y's C rows instead and nothing is copied: the result is X's rows
+// below nf and Y's rows from nf on.  Returns whether it did so.
 template <class VT>
-static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
-                hipStream_t s) {
+static bool ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
+                hipStream_t s, bool leave_c) {
     const bool split = Lv.split;
     CsrView<VT> A = view<VT>(split ? Lv.As : Lv.A, Lv.team_A);
     if (nodal(h->opt)) {
@@ -144,28 +147,33 @@ static void ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     const int32_t *ccnt = act ? Lv.act_cnt + 2 : nullptr;
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
     const int32_t c0 = split ? Lv.nf : 0;
+    leave_c = leave_c && split && !act && Lv.nrc < 0;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, ncr, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzC * nrhs);
-        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, true, om, nrhs, s, ccnt, c0);
+        op_jacobi<VT>(A, crows, ncr, b, x, x, nullptr, y, !leave_c, om, nrhs, s, ccnt, c0);
     }
+    if (leave_c) return true;
     {
         ProfScope ps("scatter", s, 4.0 * ncr + 2.0 * w * nrhs * ncr);
         op_scatter<VT>(crows, ncr, y, x, nrhs, s, ccnt, c0);
     }
+    return false;
 }
 
 // V-cycle from level l.  With x_zero the incoming iterate is zero: the
 // residual is b itself and the interpolated correction is assigned.  When
-// r is non-null it already holds b - A x.
+// r is non-null it already holds b - A x.  With split_out the result may be
+// left split (see ffc): the return value is then the buffer that holds its
+// rows from the level's nf on, otherwise nullptr (x holds all of it).
 template <class VT>
-static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
-                   const VT *r, int32_t nrhs, hipStream_t s) {
+static const VT *vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
+                        const VT *r, int32_t nrhs, hipStream_t s, bool split_out = false) {
     Level &Lv = *h->L[l];
     const int w = sizeof(VT);
     if (l + 1 == h->L.size()) {
         coarse_solve<VT>(h, b, x, nrhs, false, s);
-        return;
+        return nullptr;
     }
     Level &Nx = *h->L[l + 1];
     const VT *res = b;
@@ -190,7 +198,11 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
             op_spmv<VT>(view<VT>(Lv.Rs.rp.get() ? Lv.Rs : Lv.R, Lv.team_R), res, bc, nrhs, false,
                         s);
     }
-    vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s);
+    // the coarse correction may come back split when the interpolation
+    // reads its split-ordered columns through the aligned vector path
+    const bool coarse_split = !h->use_act && Lv.Ps.rp.get() &&
+                              op_spmv_split_ok(nrhs, xc, vec<VT>(Nx.t, Nx.t32), x);
+    const VT *xc_hi = vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s, coarse_split);
     {
         ProfScope ps("interpolate", s, ab_rowdot(Lv.P, w, nrhs, x_zero ? 1 : 2),
                      2.0 * Lv.P.nnz * nrhs);
@@ -199,9 +211,9 @@ static void vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
                                Lv.act_cnt, Lv.n, xc, nullptr, x, s);
         else
             op_spmv<VT>(view<VT>(Lv.Ps.rp.get() ? Lv.Ps : Lv.P, Lv.team_P), xc, x, nrhs, !x_zero,
-                        s);
+                        s, xc_hi, Nx.nf);
     }
-    ffc<VT>(h, Lv, b, x, nrhs, s);
+    return ffc<VT>(h, Lv, b, x, nrhs, s, split_out) ? vec<VT>(Lv.t, Lv.t32) : nullptr;
 }
 
 // Transposed cycle: C, F, F Jacobi on A^T, restriction with P^T, recursion
@@ -455,10 +467,12 @@ lair_status solve_impl(lair_hierarchy *h, const double *b, double *x,
                     if (orow) op_cast_f32_rows(h->r0.get(), h->r0_32.get(), orow, n, nrhs, st);
                     else op_cast_f32(h->r0.get(), h->r0_32.get(), n * nrhs, st);
                 }
-                vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true, nullptr, nrhs, st);
+                // the split-ordered correction may come back in two pieces
+                const float *e_hi = vcycle<float>(h, 0, h->r0_32.get(), h->e32.get(), true,
+                                                  nullptr, nrhs, st, orow != nullptr);
                 {
                     ProfScope ps("cast", st, 20.0 * n * nrhs);
-                    if (orow) op_axpy_f32_rows(x, h->e32.get(), orow, n, nrhs, st);
+                    if (orow) op_axpy_f32_rows(x, h->e32.get(), orow, n, nrhs, st, e_hi, L0.nf);
                     else op_axpy_f32(x, h->e32.get(), n * nrhs, st);
                 }
                 residual_and_norms(st);

@@ -203,3 +203,39 @@ def test_nodal_argument_errors(lair):
     with pytest.raises(Exception):
         h.solve_transpose(_dev(b))
     h.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,distance", [("kron3", 1), ("dg_curved", 1), ("dg_curved", 2),
+                                           ("perturbed2", 2)])
+def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precision):
+    """The nodal local systems of a C-node (one matrix A(N,N)^T, one
+    right-hand side per row of the node; Sec. 3.1, block form of
+    Eq. (system)) solved as one factorisation with k right-hand sides give
+    the same R, bit for bit, as k separate solves of the scalar rows; the
+    node path is the one that ran (its profiler category)."""
+    _say("case: node solves", name, "distance", distance, precision)
+    A, b, k = _case(name)
+    Rs = {}
+    for rows in (True, False):
+        if rows:
+            monkeypatch.setenv("LAIR_NODAL_ROW_SOLVES", "1")
+        else:
+            monkeypatch.delenv("LAIR_NODAL_ROW_SOLVES", raising=False)
+        lair.profile_begin(["local_node", "local_small"])
+        h = lair.setup(A.indptr, A.indices, A.data, block_size=k, nodal=True,
+                       distance=distance, precision=precision)
+        prof = lair.profile_end()
+        Rs[rows] = [gpu_level_csr(h, l, "R") for l in range(h.nlevels - 1)]
+        smax = max(h.level_stats(l)["s_max"] for l in range(h.nlevels - 1))
+        _say("  rows" if rows else "  nodes", "levels", h.nlevels, "s_max", smax,
+             {c: (round(v["ms"], 3), v["launches"]) for c, v in prof.items()})
+        if rows:
+            assert "local_node" not in prof
+        else:
+            assert prof.get("local_node", {}).get("launches", 0) > 0
+        h.free()
+    assert len(Rs[True]) == len(Rs[False])
+    for l, (a, c) in enumerate(zip(Rs[True], Rs[False])):
+        for u, w in zip(a, c):
+            assert np.array_equal(u, w), "R differs at level %d" % l
