@@ -2977,54 +2977,88 @@ void launch_to_float(const double *in, float *out, int64_t n, hipStream_t s) {
 }
 
 // ===========================================================================
-// Block-diagonal inverse (Sec. 4.2.1): one lane per k x k diagonal block,
+// Block-diagonal inverse (Sec. 4.2.1): the k x k diagonal blocks by
 // Gauss-Jordan with partial pivoting.  bad = 1 for a singular block.
 // ===========================================================================
 constexpr int BLK_MAX = 8;
 
-__global__ void k_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
-                                const int32_t *cj, const double *v,
-                                double *dinv, int32_t *bad) {
-    int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+// A team of BLK_MAX lanes per block, lane r holding row r of [D_e | I] in
+// registers (every index below is a compile-time one, so nothing spills):
+// lane r finds the block's entries in its row by a binary search for
+// column e k; the Gauss-Jordan steps are those of a serial elimination
+// (pivot: the largest magnitude in the column, the first row on a tie; the
+// pivot row scaled by 1 / pivot, then every other row with a nonzero
+// multiplier updated), one row per lane.
+__global__ void __launch_bounds__(256)
+k_block_inverse(int32_t nblk, int32_t k, const int32_t *rp, const int32_t *cj,
+                const double *v, double *dinv, int32_t *bad) {
+    constexpr int B = BLK_MAX;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t e = (int32_t)(g / B);
+    const int r = (int)(g % B);
     if (e >= nblk) return;
-    double a[BLK_MAX][2 * BLK_MAX];
-    for (int r = 0; r < k; ++r)
-        for (int q = 0; q < 2 * k; ++q) a[r][q] = (q == k + r) ? 1.0 : 0.0;
-    int b0 = e * k;
-    for (int r = 0; r < k; ++r) {
-        int row = b0 + r;
-        for (int p = rp[row]; p < rp[row + 1]; ++p) {
-            int c = cj[p] - b0;
-            if (c >= 0 && c < k) a[r][c] = v[p];
+    const int32_t b0 = e * k;
+    double a[2 * B];
+#pragma unroll
+    for (int q = 0; q < 2 * B; ++q) a[q] = (r < k && q == k + r) ? 1.0 : 0.0;
+    if (r < k) {
+        const int32_t row = b0 + r;
+        int32_t lo = rp[row], hi = rp[row + 1];
+        while (lo < hi) {                       // first column >= b0
+            const int32_t mid = (lo + hi) >> 1;
+            if (cj[mid] < b0) lo = mid + 1; else hi = mid;
+        }
+        for (int32_t p = lo; p < rp[row + 1] && cj[p] < b0 + k; ++p) {
+            const int c = cj[p] - b0;
+            const double val = v[p];
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                if (q == c) a[q] = val;
         }
     }
-    for (int col = 0; col < k; ++col) {
-        int pr = col;
-        double pv = fabs(a[col][col]);
-        for (int r = col + 1; r < k; ++r)
-            if (fabs(a[r][col]) > pv) { pv = fabs(a[r][col]); pr = r; }
-        if (pv == 0.0) { atomicOr(bad, 1); return; }
-        if (pr != col)
-            for (int q = 0; q < 2 * k; ++q) { double t = a[col][q]; a[col][q] = a[pr][q]; a[pr][q] = t; }
-        double inv = 1.0 / a[col][col];
-        for (int q = 0; q < 2 * k; ++q) a[col][q] *= inv;
-        for (int r = 0; r < k; ++r) {
-            if (r == col) continue;
-            double f = a[r][col];
-            if (f == 0.0) continue;
-            for (int q = 0; q < 2 * k; ++q) a[r][q] -= f * a[col][q];
+    bool singular = false;
+#pragma unroll
+    for (int col = 0; col < B; ++col) {
+        if (col >= k) break;
+        double cand = (r >= col && r < k) ? fabs(a[col]) : -1.0;
+        int pr = r;
+        team_argmax<B>(cand, pr);
+        if (cand == 0.0) { singular = true; break; }
+        const int src = (r == col) ? pr : (r == pr ? col : r);
+#pragma unroll
+        for (int q = 0; q < 2 * B; ++q) a[q] = __shfl(a[q], src, B);
+        const double inv = 1.0 / __shfl(a[col], col, B);
+        if (r == col) {
+#pragma unroll
+            for (int q = 0; q < 2 * B; ++q)
+                if (q < 2 * k) a[q] *= inv;
+        }
+        const double f = a[col];
+#pragma unroll
+        for (int q = 0; q < 2 * B; ++q) {
+            const double pq = __shfl(a[q], col, B);
+            if (r != col && r < k && f != 0.0 && q < 2 * k) a[q] -= f * pq;
         }
     }
-    for (int r = 0; r < k; ++r)
-        for (int q = 0; q < k; ++q) dinv[(size_t)e * k * k + r * k + q] = a[r][k + q];
+    if (singular) {
+        if (r == 0) atomicOr(bad, 1);
+        return;
+    }
+    if (r < k) {
+        double *out = dinv + (size_t)e * k * k + (size_t)r * k;
+#pragma unroll
+        for (int q = 0; q < 2 * B; ++q)
+            if (q >= k && q < 2 * k) out[q - k] = a[q];
+    }
 }
 
 void launch_block_inverse(int32_t nblk, int32_t k, const int32_t *rp,
                           const int32_t *cj, const double *v, double *dinv,
                           int32_t *bad, hipStream_t s) {
     if (k > BLK_MAX) fail(LAIR_EUNSUPPORTED, "block size %d > %d", k, BLK_MAX);
-    LAIR_LAUNCH(k_block_inverse, dim3(blocks_for(nblk, 64)), dim3(64), 0, s,
-                       nblk, k, rp, cj, v, dinv, bad);
+    if (nblk == 0) return;
+    LAIR_LAUNCH(k_block_inverse, dim3(blocks_for((int64_t)nblk * BLK_MAX, 256)), dim3(256), 0, s,
+                nblk, k, rp, cj, v, dinv, bad);
     LAIR_LAUNCH_CHECK();
 }
 

@@ -452,17 +452,19 @@ void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
 // ---------------------------------------------------------------------------
 // true when every row of every node stores its node's whole dense blocks
 // (waits for the answer)
-bool node_check(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj, hipStream_t s);
+bool node_check(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj, int64_t nnz,
+                hipStream_t s);
 // smask over A's entries: every entry of a block with
 // ||A_ij||_F^2 >= theta^2 max_{l != i} ||A_il||_F^2 (nonzero)
 void launch_node_strength(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj,
-                          const double *v, double theta, uint8_t *smask, hipStream_t s);
+                          const double *v, int64_t nnz, double theta, uint8_t *smask,
+                          hipStream_t s);
 // one-point interpolation by block: pcol[r] = coarse column of row r or -1
 void launch_interp_1p_node(int32_t n, int32_t k, const int32_t *rp, const int32_t *cj,
-                           const double *v, const uint8_t *smask, const int8_t *cf,
+                           const double *v, int64_t nnz, const uint8_t *smask, const int8_t *cf,
                            const int32_t *cidx, int32_t *pcol, hipStream_t s);
 // out = D^{-1} A on A's pattern (dinv: the inverse diagonal blocks)
-void launch_node_scale(int32_t n, int32_t k, const int32_t *rp, const double *v,
+void launch_node_scale(int32_t n, int32_t k, const int32_t *rp, const double *v, int64_t nnz,
                        const double *dinv, double *out, hipStream_t s);
 // parallel PMIS-type CF splitting on the device (k_split.hip): cf[i] = 1
 // for C, 0 for F

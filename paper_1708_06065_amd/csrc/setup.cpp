@@ -432,13 +432,13 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         // product of dense blocks with identity-block P keeps them); the
         // kernels below index by that layout, so it is checked first
         if (n % kb != 0) fail(LAIR_EINVAL, "level %d: n = %d is not whole nodes", lvl, n);
-        if (!node_check(n, kb, A.rp.get(), A.cj.get(), s))
+        if (!node_check(n, kb, A.rp.get(), A.cj.get(), A.nnz, s))
             fail(LAIR_EINVAL, "level %d: the nodal treatment needs the k rows of a node to store "
                  "the same whole dense blocks", lvl);
     }
     Lv.smask.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
     if (nod)
-        launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta,
+        launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), A.nnz, h->str.theta,
                              Lv.smask.get(), s);
     else
         launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta, h->str.kind,
@@ -474,8 +474,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         if (h->str.theta_c != h->str.theta) {
             smc.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
             if (nod)
-                launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
-                                     smc.get(), s);
+                launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), A.nnz,
+                                     h->str.theta_c, smc.get(), s);
             else
                 launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta_c,
                                 h->str.kind, smc.get(), mean, s);
@@ -681,8 +681,8 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         {
             ProfScope ps("interp", s, 13.0 * A.nnz + 9.0 * n);
             if (nod)
-                launch_interp_1p_node(n, kb, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
-                                      Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
+                launch_interp_1p_node(n, kb, A.rp.get(), A.cj.get(), A.v.get(), A.nnz,
+                                      Lv.smask.get(), Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
             else
                 launch_interp_one_point(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
                                         Lv.cf.get(), Lv.cidx.get(), pcol.get(), s);
@@ -997,8 +997,8 @@ static void finish_cycle_operators(lair_hierarchy *h, hipStream_t s) {
             launch_block_inverse(nblk, k, Lv.A.rp.get(), Lv.A.cj.get(), Lv.A.v.get(),
                                  Lv.ndinv.get(), bad.get(), s);
             Lv.av.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
-            launch_node_scale(Lv.n, k, Lv.A.rp.get(), Lv.A.v.get(), Lv.ndinv.get(), Lv.av.get(),
-                              s);
+            launch_node_scale(Lv.n, k, Lv.A.rp.get(), Lv.A.v.get(), Lv.A.nnz, Lv.ndinv.get(),
+                              Lv.av.get(), s);
             if (mixed) {
                 Lv.av32.alloc((size_t)std::max<int64_t>(Lv.A.nnz, 1), s);
                 launch_to_float(Lv.av.get(), Lv.av32.get(), Lv.A.nnz, s);
