@@ -53,6 +53,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 FP64_VALU_PEAK_TFS = 78.6      # MI355X FP64 vector peak, TFLOP/s
 C2_CYCLES = 20                 # fixed cycles per step on the non-converging DG problem
+DGU_KAPPA = 1e-3               # diffusion of the DGu workload (one of the paper's values)
 
 
 CSRC = os.path.join("paper_1708_06065_amd", "csrc")
@@ -154,6 +155,14 @@ def make_workload(name):
             {"workload": w["name"], "n": w["n"], "nnz": w["nnz"], "nrhs": 1, "block": 6,
              "treatment": "nodal", "interp": "one_point by block", "distance": 2,
              "relaxation": "FFC block Jacobi", "rtol": 1e-10}
+    if name == "dgu":
+        w = W.workload_dgu(256, DGU_KAPPA)
+        return w, dict(interp="one_point", distance=2, block_size=6, nodal=True), \
+            {"workload": w["name"], "n": w["n"], "nnz": w["nnz"], "nrhs": 1, "block": 6,
+             "kappa": DGU_KAPPA, "gamma": "1e4 in (0.25,0.75)^2, 1e-4 elsewhere",
+             "beta": "(y^2, cos^2(pi x/2))", "diffusion": "symmetric interior penalty",
+             "treatment": "nodal", "interp": "one_point by block", "distance": 2,
+             "relaxation": "FFC block Jacobi", "rtol": 1e-10}
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -217,17 +226,18 @@ print(json.dumps({"s": el, "done": done, "nnz": nz, "tot": tot, "iters_max": max
     return _both_thread_counts(code, to_ms, describe)
 
 
-def cpu_baseline_nodal(kw, n_full, m_sample=96):
+def cpu_baseline_nodal(kw, n_full, gen, m_sample=96):
     """The oracle's nodal setup + solve to 1e-10 on the same DG problem at
     m_sample x m_sample x 2 triangles (its Python loops over nodes would
-    take minutes at full size), scaled to the full problem by rows."""
+    take minutes at full size), scaled to the full problem by rows.  gen:
+    the workload call with %d for the mesh size."""
     def code(_first):
-        return r"""
+        return (r"""
 import json, sys, time
 sys.path.insert(0, %r)
 import workloads as W
 from oracle import lair as O
-w = W.workload_dg_curved(%d)
+w = W.""" + gen + r"""
 A = O.csr(w["rowptr"], w["col"], w["val"])
 t0 = time.perf_counter()
 H = O.setup(A, block=6, distance=%d)
@@ -235,7 +245,7 @@ t1 = time.perf_counter()
 x, it, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=300)
 t2 = time.perf_counter()
 print(json.dumps({"setup_s": t1 - t0, "solve_s": t2 - t1, "iters": it, "n": w["n"]}))
-""" % (ROOT, m_sample, kw["distance"])
+""") % (ROOT, m_sample, kw["distance"])
 
     def to_ms(d):
         return 1e3 * (d["setup_s"] + d["solve_s"]) * n_full / d["n"]
@@ -673,7 +683,9 @@ def main():
         if batch:
             cb = cpu_baseline_batch(kw)
         elif kw.get("nodal"):
-            cb = cpu_baseline_nodal(kw, w["n"])
+            gen = ("workload_dgu(%%d, %r)" % DGU_KAPPA if args.workload == "dgu"
+                   else "workload_dg_curved(%d)")
+            cb = cpu_baseline_nodal(kw, w["n"], gen)
         else:
             cb = cpu_baseline(args.workload, kw, xp, cycles=C2_CYCLES if c2 else None)
         if cb:

@@ -1468,7 +1468,8 @@ __device__ __forceinline__ void wave_solve(int32_t c, const int32_t *clist, cons
 // the rows of R equal those of k separate solves bit for bit.  The node's
 // rows are clist[c0 .. c0 + k - 1] = i0 .. i0 + k - 1 with c0 = node k;
 // a node whose rows do not have that form or whose lists differ in length
-// is counted in *bad and left alone.  Systems up to `cap` rows (<= WSMAX).
+// is counted in *bad and left alone.  Systems up to `cap` rows (<= WSMAX)
+// work in LDS, larger ones (up to smax) in a global slab per block.
 constexpr size_t NODE_LDS_MAX = 64 * 1024;   // dynamic LDS of one workgroup
 
 template <class FT>
@@ -1479,15 +1480,19 @@ __host__ __device__ constexpr size_t node_lds_bytes(int cap, int k) {
            (size_t)cap * 4 * sizeof(int32_t) + 64;
 }
 
-// q / d for 0 <= q < 2^13 and 1 <= d <= 64 by a float reciprocal: the
-// product's error stays below 2^13 2^-22 / d < 0.5 / d, the distance of
-// (q + 1/2) / d to the nearest integer, so the floor is exact (the loops
-// below would otherwise spend most of their instructions on divisions).
+// q / d for 0 <= q < 2^22, d >= 1 by a float reciprocal and one correction
+// step (the estimate is off by at most one): the loops below would
+// otherwise spend most of their instructions on integer divisions.
 struct SmallDiv {
     float inv;
     int d;
     __device__ explicit SmallDiv(int dd) : inv(1.0f / (float)dd), d(dd) {}
-    __device__ int quot(int q) const { return (int)(((float)q + 0.5f) * inv); }
+    __device__ int quot(int q) const {
+        int r = (int)(((float)q + 0.5f) * inv);
+        if (r * d > q) --r;
+        else if ((r + 1) * d <= q) ++r;
+        return r;
+    }
 };
 
 template <bool MIXED>
@@ -1495,28 +1500,31 @@ __global__ void __launch_bounds__(64)
 k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr,
              const int32_t *nbr, const int32_t *rp, const int32_t *cj, const double *v,
              int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing, int32_t *nsing,
-             int32_t *bad, int32_t cap) {
+             int32_t *bad, int32_t cap, double *gscratch, int64_t slab, int32_t smax) {
     using FT = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ double dyn[];
     const int lane = threadIdx.x;
-    const int32_t m = cap;
-    // layout: z[k][m], f[k][m], Md[m][m] (MIXED), M[m][m], w[k][m] (FT),
-    // ln, perm, off, st (int)
-    double *z = dyn;
-    double *f = z + (size_t)k * m;
-    double *Md = MIXED ? f + (size_t)k * m : nullptr;
-    FT *M = (FT *)(f + (size_t)k * m + (MIXED ? (size_t)m * m : 0));
-    FT *w = M + (size_t)m * m;
-    int32_t *ln = (int32_t *)(w + (size_t)k * m);
-    int32_t *perm = ln + m;
-    int32_t *off = perm + m;
-    int32_t *st = off + m + 1;
     for (int64_t node = blockIdx.x; node < nnode; node += gridDim.x) {
         const int32_t c0 = (int32_t)(node * k);
         const int32_t i0 = clist[c0];
         const int32_t n0 = nptr[c0];
         const int s = nptr[c0 + 1] - n0;
-        bool ok = s <= cap;
+        // systems up to cap rows live in LDS, larger ones (up to smax) in
+        // this block's slab of global scratch
+        const int32_t m = (s <= cap) ? cap : smax;
+        double *base = (s <= cap) ? dyn : gscratch + blockIdx.x * slab;
+        // layout: z[k][m], f[k][m], Md[m][m] (MIXED), M[m][m], w[k][m] (FT),
+        // ln, perm, off, st (int)
+        double *z = base;
+        double *f = z + (size_t)k * m;
+        double *Md = MIXED ? f + (size_t)k * m : nullptr;
+        FT *M = (FT *)(f + (size_t)k * m + (MIXED ? (size_t)m * m : 0));
+        FT *w = M + (size_t)m * m;
+        int32_t *ln = (int32_t *)(w + (size_t)k * m);
+        int32_t *perm = ln + m;
+        int32_t *off = perm + m;
+        int32_t *st = off + m + 1;
+        bool ok = s <= cap || (gscratch && s <= smax);
         for (int a = 1; a < k; ++a)
             ok = ok && clist[c0 + a] == i0 + a && nptr[c0 + a + 1] - nptr[c0 + a] == s;
         if (!ok) {
@@ -1990,8 +1998,8 @@ void run_buckets(LocalRun &r, const Buckets &bk, hipStream_t s) {
 // pass over the buckets, one readback (bucket sizes and the number of
 // singular systems), then least squares for the singular ones.
 bool node_solves_fit(int32_t k, int32_t smax, int32_t precision) {
-    if (k < 2 || smax > WSMAX) return false;
-    const int cap = std::max(1, smax);
+    if (k < 2) return false;
+    const int cap = std::max(1, std::min(smax, WSMAX));
     const size_t b = precision == LAIR_MIXED ? node_lds_bytes<float>(cap, k)
                                              : node_lds_bytes<double>(cap, k);
     return b <= NODE_LDS_MAX;
@@ -2017,8 +2025,20 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         sing.alloc((size_t)nc, s);
         int32_t *cnt = reinterpret_cast<int32_t *>(zeroed_slots(4, s));   // [0] bad, [6] nsing
         const int32_t nnode = nc / knode;
-        const int cap = std::max(1, smax);
-        const unsigned g = (unsigned)std::min<int64_t>(nnode, 8192);
+        const int cap = std::max(1, std::min(smax, WSMAX));
+        unsigned g = (unsigned)std::min<int64_t>(nnode, 8192);
+        // systems above WSMAX rows: a global slab per block, the grid kept
+        // small enough for 256 MB of slabs
+        DevArr<double> gscratch;
+        int64_t slab = 0;
+        if (smax > cap) {
+            const size_t sb = mixed ? node_lds_bytes<float>(smax, knode)
+                                    : node_lds_bytes<double>(smax, knode);
+            slab = (int64_t)((sb + 255) / 256 * 256 / sizeof(double));
+            g = (unsigned)std::max<int64_t>(
+                1, std::min<int64_t>(g, ((int64_t)256 << 20) / (slab * (int64_t)sizeof(double))));
+            gscratch.alloc((size_t)g * slab, s);
+        }
         double cost[4] = {0, 0, 0, 0};
         if (prof_selected("local_node")) {
             DevArr<double> acc;
@@ -2037,12 +2057,12 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
                 LAIR_LAUNCH(k_local_node<true>, dim3(g), dim3(64),
                             node_lds_bytes<float>(cap, knode), s, nnode, knode, clist, nptr, nbr,
                             rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(), cnt + 6, cnt,
-                            cap);
+                            cap, gscratch.get(), slab, smax);
             else
                 LAIR_LAUNCH(k_local_node<false>, dim3(g), dim3(64),
                             node_lds_bytes<double>(cap, knode), s, nnode, knode, clist, nptr,
                             nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(), cnt + 6,
-                            cnt, cap);
+                            cnt, cap, gscratch.get(), slab, smax);
             LAIR_LAUNCH_CHECK();
         }
         int32_t h[7] = {0, 0, 0, 0, 0, 0, 0};

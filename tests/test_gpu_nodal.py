@@ -6,7 +6,9 @@ neighbourhoods, fallback flags and the R, P and K patterns bit-exact; each
 row of Z within 1e-12 of its largest entry; K within 1e-12 of the scale of
 the terms summed; the same number of cycles to 1e-10 and the solution
 within 1e-8.  Cases: a Kronecker product ADR (x) B (k = 3), a perturbed
-dense-block matrix (k = 2), and P2 upwind DG along a curved field (k = 6).
+dense-block matrix (k = 2), P2 upwind DG along a curved field (k = 6), and
+the DGu problem of Sec. 4.2 (gamma jump, interior-penalty diffusion kappa
+in {0, 1e-3, 1}; k = 6).
 """
 import sys
 
@@ -62,6 +64,11 @@ def _case(name):
         A.sort_indices()
         A.data = A.data * (1.0 + 0.3 * rng.standard_normal(A.nnz))
         return A, np.kron(bs, [1.0, 1.0]), 2
+    if name.startswith("dgu"):
+        # the DGu problem of Sec. 4.2 (gamma jump, curved field) with
+        # diffusion kappa = the number after "dgu"
+        w = W.workload_dgu(16, float(name[3:]))
+        return O.csr(w["rowptr"], w["col"], w["val"]), w["rhs"], 6
     w = W.workload_dg_curved(16)
     return O.csr(w["rowptr"], w["col"], w["val"]), w["rhs"], 6
 
@@ -104,7 +111,8 @@ def compare_nodal_level(h, l, k, theta=0.25, cf=None, distance=1):
     return z_err
 
 
-@pytest.mark.parametrize("name", ["kron3", "perturbed2", "dg_curved"])
+@pytest.mark.parametrize("name", ["kron3", "perturbed2", "dg_curved", "dgu0", "dgu0.001",
+                                  "dgu1"])
 @pytest.mark.parametrize("own_split", [False, True])
 def test_nodal_levels_and_iterations(lair, name, own_split):
     _say("case: nodal", name, "own split" if own_split else "oracle split")
@@ -123,7 +131,7 @@ def test_nodal_levels_and_iterations(lair, name, own_split):
     h.free()
 
 
-@pytest.mark.parametrize("name", ["perturbed2", "dg_curved"])
+@pytest.mark.parametrize("name", ["perturbed2", "dg_curved", "dgu0", "dgu0.001", "dgu1"])
 def test_nodal_distance_two(lair, name):
     """F-F-C paths on the graph of blocks: the node-expanded strength mask
     makes the scalar distance-two merge give the nodal sets."""
@@ -162,8 +170,10 @@ def test_nodal_cycle_matches_oracle(lair):
     h.free()
 
 
-def test_nodal_mixed_and_fgmres(lair):
-    A, b, k = _case("dg_curved")
+@pytest.mark.parametrize("name", ["dg_curved", "dgu0.001"])
+def test_nodal_mixed_and_fgmres(lair, name):
+    _say("case: nodal mixed + fgmres", name)
+    A, b, k = _case(name)
     H = O.setup(A, block=k)
     cfl = [L.cf for L in H.levels[:-1]]
     _, ito, _ = O.solve(H, b, rtol=1e-10)
@@ -207,7 +217,7 @@ def test_nodal_argument_errors(lair):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name,distance", [("kron3", 1), ("dg_curved", 1), ("dg_curved", 2),
-                                           ("perturbed2", 2)])
+                                           ("perturbed2", 2), ("dgu0.001", 2)])
 def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precision):
     """The nodal local systems of a C-node (one matrix A(N,N)^T, one
     right-hand side per row of the node; Sec. 3.1, block form of

@@ -13,11 +13,13 @@ Every generator returns a plain dict of NumPy arrays:
 from .fd import (upwind_transport_2d, adr_2d, adr_batch, reaction_field_2d,
                  implicit_euler_adr_3d, chain_1d, random_ff_digraph,
                  workload_c1, workload_c3, workload_c4, workload_c5)
-from .dg import dense_blocks, upwind_dg_p2, workload_c2, workload_dg_curved
+from .dg import (dense_blocks, upwind_dg_p2, diffusion_reaction_dg_p2, workload_c2,
+                 workload_dg_curved, workload_dgu)
 
 __all__ = [
     "upwind_transport_2d", "adr_2d", "adr_batch", "reaction_field_2d",
     "implicit_euler_adr_3d", "chain_1d", "random_ff_digraph",
     "workload_c1", "workload_c2", "workload_c3", "workload_c4", "workload_c5",
-    "upwind_dg_p2", "dense_blocks", "workload_dg_curved",
+    "upwind_dg_p2", "dense_blocks", "workload_dg_curved", "diffusion_reaction_dg_p2",
+    "workload_dgu",
 ]

@@ -242,3 +242,173 @@ def workload_dg_curved(m=256):
     w = dense_blocks(upwind_dg_p2(m, velocity=velocity))
     w["name"] = "dg_p2_curved_%dx%dx2" % (m, m)
     return w
+
+
+def _dgu_gamma(x, y):
+    """Total cross section of the DGu problem (Sec. 4.2): 1e4 in the
+    square (0.25, 0.75)^2, 1e-4 elsewhere."""
+    inside = (x > 0.25) & (x < 0.75) & (y > 0.25) & (y < 0.75)
+    return np.where(inside, 1e4, 1e-4)
+
+
+def _dgu_velocity(x, y):
+    return y * y, np.cos(0.5 * np.pi * x) ** 2
+
+
+def diffusion_reaction_dg_p2(m, kappa, gamma, jitter=0.2, seed=2, g=1.0, penalty=20.0,
+                             dirichlet=None):
+    """Diffusion and reaction parts of a P2 DG discretisation on the mesh of
+    upwind_dg_p2 (same m, jitter, seed, so the DoF numbering matches).
+
+    Reaction: int_K gamma_K u v with gamma_K = gamma(centroid of K).
+    Diffusion: symmetric interior penalty,
+        sum_K int_K kappa grad u . grad v
+      - sum_F int_F ({kappa grad u} . [v] + {kappa grad v} . [u])
+      + sum_F int_F (penalty kappa / |F|) [u] . [v]
+    over interior faces F and the Dirichlet faces (where the jump is the
+    trace minus g, moved to the right-hand side: Nitsche's method); the
+    other boundary faces carry the natural (zero flux) condition.  g is
+    the Dirichlet value, a number or a function g(x, y).
+    ``dirichlet(xm, ym) -> bool`` selects Dirichlet boundary faces by their
+    midpoint (default: the south and west sides, y = 0 or x = 0).
+    Returns (A, rhs) as a scipy CSR matrix and a vector."""
+    if dirichlet is None:
+        def dirichlet(xm, ym):
+            return (ym < 1e-12) | (xm < 1e-12)
+    xy, tri = jittered_mesh(m, jitter, seed)
+    ne = tri.shape[0]
+    n = 6 * ne
+    P = xy[tri]
+    J = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]], axis=2)
+    det = J[:, 0, 0] * J[:, 1, 1] - J[:, 0, 1] * J[:, 1, 0]
+    area = 0.5 * det
+    glam = np.empty((ne, 3, 2))
+    glam[:, 1, 0], glam[:, 1, 1] = J[:, 1, 1] / det, -J[:, 0, 1] / det
+    glam[:, 2, 0], glam[:, 2, 1] = -J[:, 1, 0] / det, J[:, 0, 0] / det
+    glam[:, 0] = -glam[:, 1] - glam[:, 2]
+    base = 6 * np.arange(ne)
+    li, lj = np.meshgrid(np.arange(6), np.arange(6), indexing="ij")
+    rows, cols, vals = [], [], []
+    rhs = np.zeros(n)
+
+    def add_blocks(ti, tj, blk):
+        # blk[o, i, j]: test function i of element ti, trial j of element tj
+        rows.append((6 * ti[:, None, None] + li[None]).ravel())
+        cols.append((6 * tj[:, None, None] + lj[None]).ravel())
+        vals.append(blk.ravel())
+
+    # ---- volume: kappa stiffness + gamma mass ----
+    phi = _p2_values(TRI_Q)                          # [Q, 6]
+    gphi = _p2_grads(TRI_Q, glam)                    # [E, Q, 6, 2]
+    cen = P.mean(axis=1)
+    gam = gamma(cen[:, 0], cen[:, 1])
+    stiff = kappa * np.einsum("q,e,eqik,eqjk->eij", TRI_W, area, gphi, gphi)
+    mass = np.einsum("q,e,qi,qj->eij", TRI_W, area * gam, phi, phi)
+    add_blocks(np.arange(ne), np.arange(ne), stiff + mass)
+
+    if kappa > 0.0:
+        # ---- faces ----
+        occ_t = np.repeat(np.arange(ne), 3)
+        occ_e = np.tile(np.arange(3), ne)
+        ea = np.array([_EDGES[e][0] for e in occ_e])
+        eb = np.array([_EDGES[e][1] for e in occ_e])
+        va, vb = tri[occ_t, ea], tri[occ_t, eb]
+        key = np.minimum(va, vb) * xy.shape[0] + np.maximum(va, vb)
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        first = np.ones(ks.shape[0], dtype=bool)
+        first[1:] = ks[1:] != ks[:-1]
+        grp = np.cumsum(first) - 1
+        counts = np.bincount(grp)
+        pair_start = np.flatnonzero(first)
+        two = counts == 2
+        o1 = order[pair_start[two]]
+        o2 = order[pair_start[two] + 1]
+        ob = order[pair_start[~two]]
+        pa, pb = xy[va], xy[vb]
+        d = pb - pa
+        length = np.sqrt((d ** 2).sum(axis=1))
+        nrm = np.stack([d[:, 1], -d[:, 0]], axis=1) / length[:, None]
+
+        def face_basis(o, s):
+            """Values [O, q, 6] and gradients [O, q, 6, 2] of the basis of
+            occurrence o's element at parameter s along its edge a -> b."""
+            nq = s.shape[0]
+            lam = np.zeros((o.shape[0], nq, 3))
+            lam[np.arange(o.shape[0])[:, None], np.arange(nq)[None], ea[o][:, None]] = 1.0 - s
+            lam[np.arange(o.shape[0])[:, None], np.arange(nq)[None], eb[o][:, None]] = s
+            val = _p2_values(lam)
+            Lm = lam[..., None]                      # [O, q, 3, 1]
+            G = glam[occ_t[o]][:, None]              # [O, 1, 3, 2]
+            gv = (4.0 * Lm - 1.0) * G
+            mids = [4.0 * (Lm[:, :, a] * G[:, :, b] + Lm[:, :, b] * G[:, :, a])
+                    for a, b in _EDGES]
+            grad = np.concatenate([gv, np.stack(mids, axis=2)], axis=2)
+            return val, grad
+
+        # interior faces: o1 runs a -> b, o2 the same edge b -> a
+        w = EDGE_W[None, :] * length[o1][:, None]                    # [F, q]
+        n1 = nrm[o1]
+        v1, g1 = face_basis(o1, EDGE_S)
+        v2, g2 = face_basis(o2, 1.0 - EDGE_S)
+        dn1 = np.einsum("fqik,fk->fqi", g1, n1)                       # grad . n1
+        dn2 = np.einsum("fqik,fk->fqi", g2, n1)
+        sig = penalty * kappa / length[o1]
+        t1, t2 = occ_t[o1], occ_t[o2]
+        # test i, trial j; [u] = (u1 - u2) n1, {grad u} . n1 = (dn_u1 + dn_u2) / 2
+        for (ti, vi, di, si), (tj, vj, dj, sj) in (
+                ((t1, v1, dn1, 1.0), (t1, v1, dn1, 1.0)),
+                ((t1, v1, dn1, 1.0), (t2, v2, dn2, -1.0)),
+                ((t2, v2, dn2, -1.0), (t1, v1, dn1, 1.0)),
+                ((t2, v2, dn2, -1.0), (t2, v2, dn2, -1.0))):
+            blk = (-0.5 * kappa * si * np.einsum("fq,fqi,fqj->fij", w, vi, dj)
+                   - 0.5 * kappa * sj * np.einsum("fq,fqi,fqj->fij", w, di, vj)
+                   + si * sj * np.einsum("f,fq,fqi,fqj->fij", sig, w, vi, vj))
+            add_blocks(ti, tj, blk)
+        # Dirichlet boundary faces (Nitsche): trace u, outward normal
+        mid = 0.5 * (pa[ob] + pb[ob])
+        od = ob[dirichlet(mid[:, 0], mid[:, 1])]
+        if od.shape[0]:
+            w = EDGE_W[None, :] * length[od][:, None]
+            vb_, gb_ = face_basis(od, EDGE_S)
+            dnb = np.einsum("fqik,fk->fqi", gb_, nrm[od])
+            sigb = penalty * kappa / length[od]
+            blk = (-kappa * np.einsum("fq,fqi,fqj->fij", w, vb_, dnb)
+                   - kappa * np.einsum("fq,fqi,fqj->fij", w, dnb, vb_)
+                   + np.einsum("f,fq,fqi,fqj->fij", sigb, w, vb_, vb_))
+            tb = occ_t[od]
+            add_blocks(tb, tb, blk)
+            if callable(g):
+                xq = pa[od][:, None, :] + EDGE_S[None, :, None] * d[od][:, None, :]
+                gq = g(xq[..., 0], xq[..., 1])                   # [F, q]
+            else:
+                gq = np.full(w.shape, float(g))
+            rb = (-kappa * np.einsum("fq,fq,fqi->fi", w, gq, dnb)
+                  + np.einsum("f,fq,fq,fqi->fi", sigb, w, gq, vb_))
+            np.add.at(rhs, (6 * tb[:, None] + np.arange(6)[None]).ravel(), rb.ravel())
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    return A, rhs
+
+
+def workload_dgu(m=256, kappa=1e-3, jitter=0.2, seed=2):
+    """The DGu problem of Sec. 4.2: div(-kappa grad u + beta u) + gamma u = 0
+    on (0,1)^2 with beta = (y^2, cos^2(pi x / 2)), gamma = 1e4 in
+    (0.25, 0.75)^2 and 1e-4 elsewhere, u = 1 on the inflow sides (south and
+    west), zero diffusive flux on the outflow sides (north and east).  P2
+    upwind DG for the advection, symmetric interior penalty for the
+    diffusion (kappa = 0: advection-reaction only), m x m x 2 jittered
+    triangles, stored in dense 6 x 6 blocks."""
+    adv = upwind_dg_p2(m, velocity=_dgu_velocity, g=1.0, jitter=jitter, seed=seed)
+    Aa = sp.csr_matrix((adv["val"], adv["col"], adv["rowptr"]), shape=(adv["n"],) * 2)
+    Ad, rd = diffusion_reaction_dg_p2(m, kappa, _dgu_gamma, jitter=jitter, seed=seed)
+    A = (Aa + Ad).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    w = dict(adv, rowptr=A.indptr.astype(np.int32), col=A.indices.astype(np.int32),
+             val=A.data.astype(np.float64), nnz=int(A.nnz), rhs=adv["rhs"] + rd,
+             kappa=kappa)
+    w = dense_blocks(w)
+    w["name"] = "dgu_p2_%dx%dx2_kappa%g" % (m, m, kappa)
+    return w
