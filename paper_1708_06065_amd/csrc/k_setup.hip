@@ -1468,16 +1468,27 @@ __device__ __forceinline__ void wave_solve(int32_t c, const int32_t *clist, cons
 // the rows of R equal those of k separate solves bit for bit.  The node's
 // rows are clist[c0 .. c0 + k - 1] = i0 .. i0 + k - 1 with c0 = node k;
 // a node whose rows do not have that form or whose lists differ in length
-// is counted in *bad and left alone.  Systems up to `cap` rows (<= WSMAX)
-// work in LDS, larger ones (up to smax) in a global slab per block.
-constexpr size_t NODE_LDS_MAX = 64 * 1024;   // dynamic LDS of one workgroup
+// is counted in *bad and left alone.  The work arrays of a system live in
+// LDS when they fit, else partly (the double copy of M) or wholly in a
+// global slab per block.
+constexpr size_t NODE_LDS_MAX = 64 * 1024;   // LDS of one node's block
 
+// Bytes of one node's work arrays for systems up to `cap` rows: with_md
+// includes the double copy of M that MIXED keeps for the refinement.
 template <class FT>
-__host__ __device__ constexpr size_t node_lds_bytes(int cap, int k) {
+__host__ __device__ constexpr size_t node_lds_bytes(int cap, int k, bool with_md = true) {
     return (size_t)cap * cap * sizeof(FT) +
-           (sizeof(FT) == sizeof(float) ? (size_t)cap * cap * sizeof(double) : 0) +
+           (sizeof(FT) == sizeof(float) && with_md ? (size_t)cap * cap * sizeof(double) : 0) +
            (size_t)k * cap * (2 * sizeof(double) + sizeof(FT)) +
            (size_t)cap * 4 * sizeof(int32_t) + 64;
+}
+
+// Largest system size whose work arrays fit `bytes` (0 if none).
+template <class FT>
+static int node_cap_for(size_t bytes, int k, bool with_md, int limit) {
+    int c = 0;
+    while (c < limit && node_lds_bytes<FT>(c + 1, k, with_md) <= bytes) ++c;
+    return c;
 }
 
 // q / d for 0 <= q < 2^22, d >= 1 by a float reciprocal and one correction
@@ -1500,31 +1511,38 @@ __global__ void __launch_bounds__(64)
 k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr,
              const int32_t *nbr, const int32_t *rp, const int32_t *cj, const double *v,
              int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing, int32_t *nsing,
-             int32_t *bad, int32_t cap, double *gscratch, int64_t slab, int32_t smax) {
+             int32_t *bad, int32_t cap, int32_t cap_nomd, double *gscratch, int64_t slab,
+             int32_t smax, int32_t s_lo, int32_t s_hi) {
     using FT = typename std::conditional<MIXED, float, double>::type;
     extern __shared__ double dyn[];
     const int lane = threadIdx.x;
+    double *gslab = gscratch ? gscratch + blockIdx.x * slab : nullptr;
     for (int64_t node = blockIdx.x; node < nnode; node += gridDim.x) {
         const int32_t c0 = (int32_t)(node * k);
         const int32_t i0 = clist[c0];
         const int32_t n0 = nptr[c0];
         const int s = nptr[c0 + 1] - n0;
-        // systems up to cap rows live in LDS, larger ones (up to smax) in
-        // this block's slab of global scratch
-        const int32_t m = (s <= cap) ? cap : smax;
-        double *base = (s <= cap) ? dyn : gscratch + blockIdx.x * slab;
-        // layout: z[k][m], f[k][m], Md[m][m] (MIXED), M[m][m], w[k][m] (FT),
-        // ln, perm, off, st (int)
+        if (s < s_lo || s > s_hi) continue;      // outside this launch's size range
+        // where the work arrays live: all in LDS (s <= cap); in LDS but the
+        // double copy of M in this block's global slab (MIXED, s <= cap_nomd);
+        // all in the slab (s <= smax)
+        const bool all_lds = s <= cap;
+        const bool md_out = MIXED && !all_lds && s <= cap_nomd;
+        const int32_t m = all_lds ? cap : md_out ? cap_nomd : smax;
+        double *base = (all_lds || md_out) ? dyn : gslab;
+        // layout: z[k][m], f[k][m], Md[m][m] (MIXED, unless md_out), M[m][m],
+        // w[k][m] (FT), ln, perm, off, st (int)
         double *z = base;
         double *f = z + (size_t)k * m;
-        double *Md = MIXED ? f + (size_t)k * m : nullptr;
-        FT *M = (FT *)(f + (size_t)k * m + (MIXED ? (size_t)m * m : 0));
+        const bool md_here = MIXED && !md_out;
+        double *Md = !MIXED ? nullptr : md_out ? gslab : f + (size_t)k * m;
+        FT *M = (FT *)(f + (size_t)k * m + (md_here ? (size_t)m * m : 0));
         FT *w = M + (size_t)m * m;
         int32_t *ln = (int32_t *)(w + (size_t)k * m);
         int32_t *perm = ln + m;
         int32_t *off = perm + m;
         int32_t *st = off + m + 1;
-        bool ok = s <= cap || (gscratch && s <= smax);
+        bool ok = all_lds || md_out || (gslab && s <= smax);
         for (int a = 1; a < k; ++a)
             ok = ok && clist[c0 + a] == i0 + a && nptr[c0 + a + 1] - nptr[c0 + a] == s;
         if (!ok) {
@@ -1999,10 +2017,10 @@ void run_buckets(LocalRun &r, const Buckets &bk, hipStream_t s) {
 // singular systems), then least squares for the singular ones.
 bool node_solves_fit(int32_t k, int32_t smax, int32_t precision) {
     if (k < 2) return false;
-    const int cap = std::max(1, std::min(smax, WSMAX));
-    const size_t b = precision == LAIR_MIXED ? node_lds_bytes<float>(cap, k)
-                                             : node_lds_bytes<double>(cap, k);
-    return b <= NODE_LDS_MAX;
+    // the smallest systems must fit in LDS; larger ones go to the slab
+    const size_t b = precision == LAIR_MIXED ? node_lds_bytes<float>(1, k)
+                                             : node_lds_bytes<double>(1, k);
+    return b <= NODE_LDS_MAX && smax >= 0;
 }
 
 int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
@@ -2025,20 +2043,6 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         sing.alloc((size_t)nc, s);
         int32_t *cnt = reinterpret_cast<int32_t *>(zeroed_slots(4, s));   // [0] bad, [6] nsing
         const int32_t nnode = nc / knode;
-        const int cap = std::max(1, std::min(smax, WSMAX));
-        unsigned g = (unsigned)std::min<int64_t>(nnode, 8192);
-        // systems above WSMAX rows: a global slab per block, the grid kept
-        // small enough for 256 MB of slabs
-        DevArr<double> gscratch;
-        int64_t slab = 0;
-        if (smax > cap) {
-            const size_t sb = mixed ? node_lds_bytes<float>(smax, knode)
-                                    : node_lds_bytes<double>(smax, knode);
-            slab = (int64_t)((sb + 255) / 256 * 256 / sizeof(double));
-            g = (unsigned)std::max<int64_t>(
-                1, std::min<int64_t>(g, ((int64_t)256 << 20) / (slab * (int64_t)sizeof(double))));
-            gscratch.alloc((size_t)g * slab, s);
-        }
         double cost[4] = {0, 0, 0, 0};
         if (prof_selected("local_node")) {
             DevArr<double> acc;
@@ -2051,18 +2055,44 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
             rb.add(cost, acc.get(), sizeof(cost));
             rb.run();
         }
+        // Work arrays in at most 64 KB of LDS (several blocks per CU): all of
+        // them up to `cap` rows, all but the double copy of M (MIXED) up to
+        // `cap_nomd`; larger systems use a global slab per block, the grid
+        // then kept small enough for 256 MB of slabs.  (Blocks with the
+        // whole LDS of a CU for the large systems ran slower: one wave per
+        // CU leaves the elimination's latency exposed.)
+        const int sm1 = std::max(1, smax);
+        const int cap = mixed ? node_cap_for<float>(NODE_LDS_MAX, knode, true, sm1)
+                              : node_cap_for<double>(NODE_LDS_MAX, knode, true, sm1);
+        const int cap_nomd = mixed ? node_cap_for<float>(NODE_LDS_MAX, knode, false, sm1) : cap;
+        const size_t lds = mixed ? std::max(node_lds_bytes<float>(cap, knode),
+                                            node_lds_bytes<float>(cap_nomd, knode, false))
+                                 : node_lds_bytes<double>(cap, knode);
+        unsigned g = (unsigned)std::min<int64_t>(nnode, 8192);
+        DevArr<double> gscratch;
+        int64_t slab = 0;
+        if (smax > cap_nomd) {
+            const size_t sb = mixed ? node_lds_bytes<float>(smax, knode)
+                                    : node_lds_bytes<double>(smax, knode);
+            slab = (int64_t)((sb + 255) / 256 * 256 / sizeof(double));
+        } else if (smax > cap) {
+            slab = ((int64_t)smax * smax + 31) / 32 * 32;   // the double copies of M only
+        }
+        if (slab) {
+            g = (unsigned)std::max<int64_t>(
+                1, std::min<int64_t>(g, ((int64_t)256 << 20) / (slab * (int64_t)sizeof(double))));
+            gscratch.alloc((size_t)g * slab, s);
+        }
         {
             ProfScope ps("local_node", s, cost[0], cost[1]);
             if (mixed)
-                LAIR_LAUNCH(k_local_node<true>, dim3(g), dim3(64),
-                            node_lds_bytes<float>(cap, knode), s, nnode, knode, clist, nptr, nbr,
-                            rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(), cnt + 6, cnt,
-                            cap, gscratch.get(), slab, smax);
+                LAIR_LAUNCH(k_local_node<true>, dim3(g), dim3(64), lds, s, nnode, knode, clist,
+                            nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(),
+                            cnt + 6, cnt, cap, cap_nomd, gscratch.get(), slab, smax, 0, smax);
             else
-                LAIR_LAUNCH(k_local_node<false>, dim3(g), dim3(64),
-                            node_lds_bytes<double>(cap, knode), s, nnode, knode, clist, nptr,
-                            nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(), cnt + 6,
-                            cnt, cap, gscratch.get(), slab, smax);
+                LAIR_LAUNCH(k_local_node<false>, dim3(g), dim3(64), lds, s, nnode, knode, clist,
+                            nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(),
+                            cnt + 6, cnt, cap, cap_nomd, gscratch.get(), slab, smax, 0, smax);
             LAIR_LAUNCH_CHECK();
         }
         int32_t h[7] = {0, 0, 0, 0, 0, 0, 0};
