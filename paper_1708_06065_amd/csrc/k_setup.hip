@@ -3462,14 +3462,16 @@ void launch_split_perm(int32_t nf, int32_t nc, const int32_t *flist, const int32
 // the new columns tagged (sign bit) where they are >= nsplit.
 template <int T>
 __global__ void __launch_bounds__(256)
-k_permute_csr(int32_t nrows, const int32_t *rowmap, const int32_t *colmap, const int32_t *rp,
+k_permute_csr(int32_t nrows, const int32_t *irowmap, const int32_t *colmap, const int32_t *rp,
               const int32_t *cj, const double *v, const int32_t *rp_out, int32_t *cj_out,
               double *v_out, float *v32_out, int32_t *cjt_out, int32_t nsplit) {
+    // teams walk the input rows in order (reads stream; output row
+    // k = irowmap[r] is written at its place)
     const int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
-    const int32_t k = (int32_t)(gt / T);
+    const int32_t r = (int32_t)(gt / T);
     const int t = (int)(gt % T);
-    if (k >= nrows) return;
-    const int32_t r = rowmap ? rowmap[k] : k;
+    if (r >= nrows) return;
+    const int32_t k = irowmap ? irowmap[r] : r;
     const int32_t lo = rp[r], hi = rp[r + 1];
     const int64_t o = (int64_t)rp_out[k] - lo;
     // four entries per lane in flight: loads first, then the column map,
@@ -3505,10 +3507,12 @@ k_permute_csr(int32_t nrows, const int32_t *rowmap, const int32_t *colmap, const
 }
 
 void launch_permute_csr(int32_t nrows, int64_t nnz, double mean_row, const int32_t *rowmap,
-                        const int32_t *colmap, const int32_t *rp, const int32_t *cj,
-                        const double *v, int32_t *rp_out, int32_t *cj_out, double *v_out,
-                        float *v32_out, int32_t *cjt_out, int32_t nsplit,
+                        const int32_t *irowmap, const int32_t *colmap, const int32_t *rp,
+                        const int32_t *cj, const double *v, int32_t *rp_out, int32_t *cj_out,
+                        double *v_out, float *v32_out, int32_t *cjt_out, int32_t nsplit,
                         DevArr<int64_t> &tmp, hipStream_t s) {
+    if ((rowmap == nullptr) != (irowmap == nullptr))
+        fail(LAIR_EINVAL, "a row permutation needs its inverse");
     (void)nnz;
     scan_launch(RowLenF{rp, rowmap}, rp_out, nrows, s, tmp);
     if (nrows == 0) return;
@@ -3517,7 +3521,7 @@ void launch_permute_csr(int32_t nrows, int64_t nnz, double mean_row, const int32
                 : mean_row > 12 ? 4 : mean_row > 6 ? 2 : 1;
 #define LAIR_PC(TT)                                                                      \
     LAIR_LAUNCH((k_permute_csr<TT>), dim3(blocks_for((int64_t)nrows * TT, 256)), dim3(256), \
-                0, s, nrows, rowmap, colmap, rp, cj, v, rp_out, cj_out, v_out, v32_out,  \
+                0, s, nrows, irowmap, colmap, rp, cj, v, rp_out, cj_out, v_out, v32_out, \
                 cjt_out, nsplit)
     switch (T) {
         case 1: LAIR_PC(1); break;

@@ -227,9 +227,9 @@ void launch_split_perm(int32_t nf, int32_t nc, const int32_t *flist, const int32
 // c becomes colmap[c] (nullptr: identity); rp_out is written on the device
 // (no synchronisation); v_out, v32_out, cjt_out optional
 void launch_permute_csr(int32_t nrows, int64_t nnz, double mean_row, const int32_t *rowmap,
-                        const int32_t *colmap, const int32_t *rp, const int32_t *cj,
-                        const double *v, int32_t *rp_out, int32_t *cj_out, double *v_out,
-                        float *v32_out, int32_t *cjt_out, int32_t nsplit,
+                        const int32_t *irowmap, const int32_t *colmap, const int32_t *rp,
+                        const int32_t *cj, const double *v, int32_t *rp_out, int32_t *cj_out,
+                        double *v_out, float *v32_out, int32_t *cjt_out, int32_t nsplit,
                         DevArr<int64_t> &tmp, hipStream_t s);
 
 int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,

@@ -933,8 +933,8 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
         launch_split_perm(Lv.nf, Lv.nc, Lv.flist.get(), Lv.clist.get(), Lv.perm.get(),
                           Lv.iperm.get(), Lv.ids.get(), Lv.cf_split.get(), s);
     }
-    auto copy = [&](const DevCSR &M, DevCSR &O, const int32_t *rowmap, const int32_t *colmap,
-                    DevArr<int32_t> *cjt, int32_t nsplit) {
+    auto copy = [&](const DevCSR &M, DevCSR &O, const int32_t *rowmap, const int32_t *irowmap,
+                    const int32_t *colmap, DevArr<int32_t> *cjt, int32_t nsplit) {
         O.nrows = M.nrows;
         O.ncols = M.ncols;
         O.nnz = M.nnz;
@@ -946,7 +946,8 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
         if (mixed) O.v32.alloc(z, s); else O.v32.release();
         if (cjt) cjt->alloc(z, s);
         launch_permute_csr(M.nrows, M.nnz, M.nrows ? (double)M.nnz / M.nrows : 0.0, rowmap,
-                           colmap, M.rp.get(), M.cj.get(), M.v.get(), O.rp.get(), O.cj.get(),
+                           irowmap, colmap, M.rp.get(), M.cj.get(), M.v.get(), O.rp.get(),
+                           O.cj.get(),
                            mixed ? nullptr : O.v.get(), mixed ? O.v32.get() : nullptr,
                            cjt ? cjt->get() : nullptr, nsplit, tmp, s);
     };
@@ -962,14 +963,14 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
         const int32_t *nperm = Nx.split ? Nx.perm.get() : nullptr;
         const int32_t *niperm = Nx.split ? Nx.iperm.get() : nullptr;
         if (Lv.split) {
-            copy(Lv.A, Lv.As, perm, iperm, &Lv.cjt_split, Lv.nf);
+            copy(Lv.A, Lv.As, perm, iperm, iperm, &Lv.cjt_split, Lv.nf);
         } else {
             drop(Lv.As);
             Lv.cjt_split.release();
         }
         if (Lv.split || Nx.split) {
-            copy(Lv.R, Lv.Rs, nperm, iperm, nullptr, 0);
-            copy(Lv.P, Lv.Ps, perm, niperm, nullptr, 0);
+            copy(Lv.R, Lv.Rs, nperm, niperm, iperm, nullptr, 0);
+            copy(Lv.P, Lv.Ps, perm, iperm, niperm, nullptr, 0);
         } else {
             drop(Lv.Rs);
             drop(Lv.Ps);
