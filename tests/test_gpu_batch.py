@@ -350,3 +350,46 @@ def test_batch_graph_replays_equal_eager(lair):
         torch.cuda.synchronize()
         assert np.array_equal(ig["sys_iters"], ie["sys_iters"])
         assert torch.equal(Xg, Xe), "batch replay %d differs from eager" % rep
+
+
+def test_c3_full_batch_sampled_members(lair):
+    """The whole 512-system workload in one batch, as the benchmark runs it
+    (direct interpolation, lumped at 0.001, mixed precision): every member
+    converges with its own residual below 1e-10 (checked independently),
+    and sampled members (the largest, the smallest and ten seeded picks)
+    have the oracle's level count, at most one cycle more than the oracle's
+    single-system solve, and its solution to 1e-8."""
+    allsys = W.adr_batch(512, seed=3)
+    sizes = np.array([w["n"] for w in allsys])
+    seg0 = np.concatenate([[0], np.cumsum(sizes)])
+    _say("case: C3 full batch, 512 systems, %d rows" % seg0[-1])
+    h = lair.setup_batch([(w["rowptr"], w["col"], w["val"]) for w in allsys],
+                         interp="direct", lump_tol=1e-3, precision="mixed")
+    b = np.concatenate([w["rhs"] for w in allsys])
+    x, info = h.solve_batch(_dev(b), rtol=1e-10, maxit=100)
+    assert info["converged"]
+    X = x.cpu().numpy()
+    worst_res = 0.0
+    for q, w in enumerate(allsys):
+        A = O.csr(w["rowptr"], w["col"], w["val"])
+        xq = X[seg0[q]:seg0[q + 1]]
+        worst_res = max(worst_res, np.linalg.norm(w["rhs"] - A @ xq) / np.linalg.norm(w["rhs"]))
+    _say("  largest member relative residual %.2e, cycles %d" % (worst_res, info["iters"]))
+    assert worst_res <= 1e-10 * (1 + 1e-6)
+    rng = np.random.default_rng(11)
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} |
+                  set(int(q) for q in rng.choice(512, size=10, replace=False)))
+    levels = h.system_levels()
+    for q in pick:
+        w = allsys[q]
+        H = O.setup(O.csr(w["rowptr"], w["col"], w["val"]), interp=O.INTERP_DIRECT,
+                    lump_tol=1e-3)
+        assert levels[q] == H.nlevels, (q, levels[q], H.nlevels)
+        xo, ito, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=100)
+        it = int(info["sys_iters"][q])
+        err = np.linalg.norm(X[seg0[q]:seg0[q + 1]] - xo) / np.linalg.norm(xo)
+        _say("  system %d (N = %d): cycles gpu %d oracle %d, rel. error %.2e"
+             % (q, int(round(np.sqrt(w["n"]))), it, ito, err))
+        assert ito <= it <= ito + 1
+        assert err <= 1e-8
+    h.free()
