@@ -207,10 +207,12 @@ __device__ __forceinline__ void row_accV(int lo, int hi, int t, int T, int diag_
     }
 }
 
-template <class VT, int NR, int VW, int MODE, int U, bool RNG>
+// SRC: 0 one source; 1 columns >= csplit read from xhi; 2 columns with
+// cf[c] = 1 read from xhi.
+template <class VT, int NR, int VW, int MODE, int U, int SRC>
 __global__ void __launch_bounds__(256)
 k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *v,
-          const VT *x, const VT *xhi, int32_t csplit, const VT *b, VT *y) {
+          const VT *x, const VT *xhi, int32_t csplit, const int8_t *cf, const VT *b, VT *y) {
     constexpr int L = NR / VW;
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
@@ -219,8 +221,9 @@ k_rowdotV(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const VT *
     Pack<VT, VW> acc;
     acc.zero();
     VT d = (VT)0;
-    row_accV<VT, NR, VW, false, false, U, false, RNG>(rp[i], rp[i + 1], t, T, -1, cj, v, x,
-                                                      RNG ? xhi : x, nullptr, acc, d, csplit);
+    row_accV<VT, NR, VW, SRC == 2, false, U, false, SRC == 1>(rp[i], rp[i + 1], t, T, -1, cj, v,
+                                                             x, SRC ? xhi : x, cf, acc, d,
+                                                             csplit);
     if (t >= L) return;
     const int64_t o = (int64_t)i * NR + t * VW;
     Pack<VT, VW> out;
@@ -352,16 +355,18 @@ static inline int scalar_team(int team) { return team >= 4 ? team / 4 : 1; }
 
 static inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-template <class VT, int T, int MODE>
+// SEL: the source is split by point type (x at F columns, xC where
+// cf[c] = 1).
+template <class VT, int T, int MODE, bool SEL>
 __global__ void __launch_bounds__(256)
 k_rowdot1(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
-          const VT *x, const VT *b, VT *y) {
+          const VT *x, const VT *xC, const int8_t *cf, const VT *b, VT *y) {
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(gt / T);
     int lane = (int)(gt % T);
     if (i >= nrows) return;
     VT acc = (VT)0, d = (VT)0;
-    row_acc1<VT, T, false>(rp[i], rp[i + 1], lane, -1, cj, v, x, x, nullptr, acc, d);
+    row_acc1<VT, T, SEL>(rp[i], rp[i + 1], lane, -1, cj, v, x, SEL ? xC : x, cf, acc, d);
     acc = team_sum<T>(acc);
     if (lane == 0) {
         if (MODE == MODE_RESID) y[i] = b[i] - acc;
@@ -418,24 +423,32 @@ k_rowdotM(int32_t nrows, const int32_t *rp, const int32_t *cj, const VT *v,
     else y[o] += acc;
 }
 
-// x_hi (optional): the rows of x from csplit on are read there instead
-// (only on the vector path, see op_spmv_split_ok).
+// x_hi (optional): a source vector left in two buffers.  With csplit >= 0
+// its rows from csplit on are read from x_hi, else the rows with
+// cf_hi[c] = 1 (the vector path takes either, the one-right-hand-side path
+// the point types; see op_spmv_split_ok).
 template <class VT, int MODE>
 static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
-                   int32_t nrhs, hipStream_t s, const VT *x_hi = nullptr, int32_t csplit = 0) {
+                   int32_t nrhs, hipStream_t s, const VT *x_hi = nullptr, int32_t csplit = -1,
+                   const int8_t *cf_hi = nullptr) {
     if (A.nrows == 0) return;
+    if (x_hi && csplit < 0 && !cf_hi) fail(LAIR_EINVAL, "a split source needs its split");
     if (nrhs > 1 && aligned16(x) && aligned16(y) && (!b || aligned16(b)) &&
         (!x_hi || aligned16(x_hi))) {
         constexpr int VW = sizeof(VT) == 4 ? 4 : 2;
 #define LAIR_RVU(NN, WW, UU)                                                      \
-        if (x_hi)                                                                 \
-            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, true>),                  \
+        if (x_hi && csplit >= 0)                                                  \
+            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, 1>),                     \
                         dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
-                        A.nrows, T, A.rp, A.cj, A.v, x, x_hi, csplit, b, y);      \
+                        A.nrows, T, A.rp, A.cj, A.v, x, x_hi, csplit, nullptr, b, y); \
+        else if (x_hi)                                                            \
+            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, 2>),                     \
+                        dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
+                        A.nrows, T, A.rp, A.cj, A.v, x, x_hi, 0, cf_hi, b, y);    \
         else                                                                      \
-            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, false>),                 \
+            LAIR_LAUNCH((k_rowdotV<VT, NN, WW, MODE, UU, 0>),                     \
                         dim3(blocks_for((int64_t)A.nrows * T, 256)), dim3(256), 0, s, \
-                        A.nrows, T, A.rp, A.cj, A.v, x, x, 0, b, y);
+                        A.nrows, T, A.rp, A.cj, A.v, x, x, 0, nullptr, b, y);
 #define LAIR_RV(NN, WW)                                                           \
     {                                                                             \
         const int T = vec_team(NN / WW, A.team);                                  \
@@ -454,7 +467,9 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
         LAIR_LAUNCH_CHECK();
         return;
     }
-    if (x_hi) fail(LAIR_EINVAL, "a vector split over two buffers needs aligned multi-vectors");
+    if (x_hi && (nrhs > 1 || !cf_hi))
+        fail(LAIR_EINVAL, "a vector split over two buffers needs aligned multi-vectors or "
+             "point types");
     if (nrhs > 1) {
 #define LAIR_RM(NN)                                                               \
     LAIR_LAUNCH((k_rowdotM<VT, NN, MODE>),                                 \
@@ -472,9 +487,14 @@ static void rowdot(const CsrView<VT> &A, const VT *x, const VT *b, VT *y,
         return;
     }
 #define LAIR_RD(TT)                                                              \
-    LAIR_LAUNCH((k_rowdot1<VT, TT, MODE>),                                \
-                       dim3(blocks_for((int64_t)A.nrows * TT, 256)), dim3(256), 0, s, \
-                       A.nrows, A.rp, A.cj, A.v, x, b, y)
+    if (x_hi)                                                                    \
+        LAIR_LAUNCH((k_rowdot1<VT, TT, MODE, true>),                             \
+                    dim3(blocks_for((int64_t)A.nrows * TT, 256)), dim3(256), 0, s, \
+                    A.nrows, A.rp, A.cj, A.v, x, x_hi, cf_hi, b, y);             \
+    else                                                                         \
+        LAIR_LAUNCH((k_rowdot1<VT, TT, MODE, false>),                            \
+                    dim3(blocks_for((int64_t)A.nrows * TT, 256)), dim3(256), 0, s, \
+                    A.nrows, A.rp, A.cj, A.v, x, x, nullptr, b, y)
     switch (scalar_team(A.team)) {
         case 1: LAIR_RD(1); break;
         case 2: LAIR_RD(2); break;
@@ -496,13 +516,14 @@ void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
 
 template <class VT>
 void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
-             bool accumulate, hipStream_t s, const VT *x_hi, int32_t csplit) {
-    if (accumulate) rowdot<VT, MODE_ADD>(A, x, nullptr, y, nrhs, s, x_hi, csplit);
-    else rowdot<VT, MODE_SET>(A, x, nullptr, y, nrhs, s, x_hi, csplit);
+             bool accumulate, hipStream_t s, const VT *x_hi, int32_t csplit,
+             const int8_t *cf_hi) {
+    if (accumulate) rowdot<VT, MODE_ADD>(A, x, nullptr, y, nrhs, s, x_hi, csplit, cf_hi);
+    else rowdot<VT, MODE_SET>(A, x, nullptr, y, nrhs, s, x_hi, csplit, cf_hi);
 }
 
 bool op_spmv_split_ok(int32_t nrhs, const void *x, const void *x_hi, const void *y) {
-    return nrhs > 1 && aligned16(x) && aligned16(x_hi) && aligned16(y);
+    return nrhs == 1 || (aligned16(x) && aligned16(x_hi) && aligned16(y));
 }
 
 template <class VT, int MODE>
@@ -1118,8 +1139,8 @@ void op_block_apply(int32_t nblk, int32_t k, const double *dinv,
 // explicit instantiations
 template void op_residual<double>(const CsrView<double> &, const double *, const double *, double *, int32_t, hipStream_t);
 template void op_residual<float>(const CsrView<float> &, const float *, const float *, float *, int32_t, hipStream_t);
-template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t, const double *, int32_t);
-template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t, const float *, int32_t);
+template void op_spmv<double>(const CsrView<double> &, const double *, double *, int32_t, bool, hipStream_t, const double *, int32_t, const int8_t *);
+template void op_spmv<float>(const CsrView<float> &, const float *, float *, int32_t, bool, hipStream_t, const float *, int32_t, const int8_t *);
 template void op_jacobi<double>(const CsrView<double> &, const int32_t *, int32_t, const double *, const double *, const double *, const int8_t *, double *, bool, double, int32_t, hipStream_t, const int32_t *, int32_t);
 template void op_jacobi<float>(const CsrView<float> &, const int32_t *, int32_t, const float *, const float *, const float *, const int8_t *, float *, bool, double, int32_t, hipStream_t, const int32_t *, int32_t);
 template void op_rowdot_list<double>(const CsrView<double> &, int, const int32_t *, const int32_t *, int32_t, const double *, const double *, double *, hipStream_t);

@@ -381,12 +381,14 @@ void launch_tag_columns(int64_t nnz, const int32_t *cj, const int8_t *cf, int32_
 template <class VT>
 void op_residual(const CsrView<VT> &A, const VT *b, const VT *x, VT *r,
                  int32_t nrhs, hipStream_t s);
-// y = A x (or y += A x).  With x_hi, the entries of x at rows >= csplit are
-// read from x_hi instead (a vector whose upper rows were left in another
-// buffer); that needs the aligned multi-vector path (op_spmv_split_ok).
+// y = A x (or y += A x).  With x_hi, some rows of x are read from x_hi
+// instead (a vector left in two buffers): the rows >= csplit when csplit >= 0
+// (aligned multi-vectors only), else the rows with cf_hi[c] = 1; see
+// op_spmv_split_ok.
 template <class VT>
 void op_spmv(const CsrView<VT> &A, const VT *x, VT *y, int32_t nrhs,
-             bool accumulate, hipStream_t s, const VT *x_hi = nullptr, int32_t csplit = 0);
+             bool accumulate, hipStream_t s, const VT *x_hi = nullptr, int32_t csplit = -1,
+             const int8_t *cf_hi = nullptr);
 bool op_spmv_split_ok(int32_t nrhs, const void *x, const void *x_hi, const void *y);
 // Jacobi on rows X: out[k] (compact) or out[i] = x_i + omega (b - A x)_i / a_ii.
 // With cf non-null, neighbour values come from xC at C-points and from xF

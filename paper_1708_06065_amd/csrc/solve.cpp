@@ -98,9 +98,9 @@ static void coarse_solve(lair_hierarchy *h, const VT *b, VT *x, int32_t nrhs,
 //   F sweep 2 reads Y at F-points and X at C-points, writes X at the F rows
 //     (X's F entries are not read by this sweep);
 //   C sweep reads X, writes a compact buffer that is then scattered to X.
-// With leave_c on a split-ordered level (C rows nf .. n-1) the C sweep
-// writes Y's C rows instead and nothing is copied: the result is X's rows
-// below nf and Y's rows from nf on.  Returns whether it did so.
+// With leave_c the C sweep writes Y's C rows instead and nothing is copied:
+// the result is X at the F rows and Y at the C rows (on a split-ordered
+// level, X below nf and Y from nf on).  Returns whether it did so.
 template <class VT>
 static bool ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
                 hipStream_t s, bool leave_c) {
@@ -147,7 +147,7 @@ static bool ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
     const int32_t *ccnt = act ? Lv.act_cnt + 2 : nullptr;
     const int32_t ncr = Lv.nrc >= 0 ? Lv.nrc : Lv.nc;
     const int32_t c0 = split ? Lv.nf : 0;
-    leave_c = leave_c && split && !act && Lv.nrc < 0;
+    leave_c = leave_c && !act && Lv.nrc < 0;
     {
         ProfScope ps("jacobi", s, ab_jacobi(Lv.nnzC, ncr, Lv.n, w, nrhs, false),
                      2.0 * Lv.nnzC * nrhs);
@@ -165,7 +165,7 @@ static bool ffc(lair_hierarchy *h, Level &Lv, const VT *b, VT *x, int32_t nrhs,
 // residual is b itself and the interpolated correction is assigned.  When
 // r is non-null it already holds b - A x.  With split_out the result may be
 // left split (see ffc): the return value is then the buffer that holds its
-// rows from the level's nf on, otherwise nullptr (x holds all of it).
+// C rows, otherwise nullptr (x holds all of it).
 template <class VT>
 static const VT *vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_zero,
                         const VT *r, int32_t nrhs, hipStream_t s, bool split_out = false) {
@@ -198,9 +198,9 @@ static const VT *vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_
             op_spmv<VT>(view<VT>(Lv.Rs.rp.get() ? Lv.Rs : Lv.R, Lv.team_R), res, bc, nrhs, false,
                         s);
     }
-    // the coarse correction may come back split when the interpolation
-    // reads its split-ordered columns through the aligned vector path
-    const bool coarse_split = !h->use_act && Lv.Ps.rp.get() &&
+    // the coarse correction may come back in two buffers (its C rows in the
+    // level's work buffer); the interpolation then reads those columns there
+    const bool coarse_split = !h->use_act &&
                               op_spmv_split_ok(nrhs, xc, vec<VT>(Nx.t, Nx.t32), x);
     const VT *xc_hi = vcycle<VT>(h, l + 1, bc, xc, true, nullptr, nrhs, s, coarse_split);
     {
@@ -211,7 +211,8 @@ static const VT *vcycle(lair_hierarchy *h, size_t l, const VT *b, VT *x, bool x_
                                Lv.act_cnt, Lv.n, xc, nullptr, x, s);
         else
             op_spmv<VT>(view<VT>(Lv.Ps.rp.get() ? Lv.Ps : Lv.P, Lv.team_P), xc, x, nrhs, !x_zero,
-                        s, xc_hi, Nx.nf);
+                        s, xc_hi, Nx.split && nrhs > 1 ? Nx.nf : -1,
+                        Nx.split ? Nx.cf_split.get() : Nx.cf.get());
     }
     return ffc<VT>(h, Lv, b, x, nrhs, s, split_out) ? vec<VT>(Lv.t, Lv.t32) : nullptr;
 }
