@@ -30,7 +30,13 @@ stationary iteration does not reach 1e-10 on this problem (closed
 streamlines: the paper calls the steady limit ill-posed), so one step is the
 setup plus a fixed number of cycles, and the line says so.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c5|c3|c2|c4|c1|dg]
+Workload dg: nodal (block) lAIR at distance 2 on P2 upwind DG along the
+curved field b = (y^2, cos^2(pi x/2)), 256 x 256 x 2 triangles, dense 6 x 6
+blocks.  Workload dgu: the same with the DGu problem's total cross section
+(1e4 in the central square, 1e-4 outside) and interior-penalty diffusion
+kappa = 1e-3.  Both solve to 1e-10.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c5|c3|c2|c4|c1|dg|dgu]
 
 Summaries of rocprofv3 runs (written under profiles/):
 
@@ -667,6 +673,13 @@ def main():
         "roofline": roofline,
         "step_roofline": step_roof,
         "gpu_ms_by_category": {k: round(v["ms"], 3) for k, v in prof_all.items()},
+        # per category of the profiled step: launches, algorithmic bytes and
+        # the fraction of the HBM peak they reach
+        "category_roofline": {k: {"launches": v["launches"],
+                                  "alg_gb": round(v["alg_bytes"] * 1e-9, 4),
+                                  "frac": round(v["alg_bytes"] / (max(v["ms"], 1e-9) * 1e-3)
+                                                * 1e-9 / HBM_PEAK_GBS, 4)}
+                              for k, v in prof_all.items()},
     }
     if c2:
         out["converged"] = False
