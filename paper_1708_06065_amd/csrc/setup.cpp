@@ -84,6 +84,10 @@ struct PendingSizes {
     }
     int64_t *tot() { return dp; }
     int32_t *flag() { return reinterpret_cast<int32_t *>(dp + 2); }
+    // a profiled launch whose algorithmic bytes include 12 per entry of the
+    // matrix whose size is pending (set when the size arrives)
+    int prof_slot = -1;
+    double prof_base = 0.0;
     void add(Readback &rb) {
         if (nnz) rb.add(h, dp, sizeof(h));
     }
@@ -95,6 +99,8 @@ struct PendingSizes {
         if ((int32_t)h[2]) fail(LAIR_EUNSUPPORTED, "%s", what);
         *n = h[0];
         *max_row = (int32_t)h[1];
+        if (prof_slot >= 0) prof_set_bytes(prof_slot, prof_base + 12.0 * (double)h[0]);
+        prof_slot = -1;
     }
     void settle(hipStream_t s) {
         if (!nnz) return;
@@ -207,8 +213,12 @@ static void spgemm_count(const DevCSR &A, const BSrc &B, SpgemmState &st, hipStr
 // *distinct receives the size C has before lumping.
 // The hash pass of C = A B: C's rows sorted at their product offsets in the
 // staging arrays tcj, tcx (sized here by st.h), their lengths in st.cnt.
+// *slot / *base: the profiler slot of the pass and its algorithmic bytes
+// before C's entries (12 per distinct entry written, added by the caller
+// once the number is known).
 static void spgemm_hash(const DevCSR &A, const BSrc &B, SpgemmState &st, hipStream_t s,
-                        double ratio, DevArr<int32_t> &tcj, DevArr<double> &tcx) {
+                        double ratio, DevArr<int32_t> &tcj, DevArr<double> &tcx,
+                        int *slot = nullptr, double *base = nullptr) {
     const int32_t m = st.m;
     const int64_t etot = st.h[0], emax = st.h[1];
     if (etot > INT32_MAX)
@@ -217,8 +227,10 @@ static void spgemm_hash(const DevCSR &A, const BSrc &B, SpgemmState &st, hipStre
     tcj.alloc((size_t)std::max<int64_t>(etot, 1), s);
     tcx.alloc((size_t)std::max<int64_t>(etot, 1), s);
     // A, the rows of B and the rows of C each touched once
-    ProfScope ps("spgemm_fill", s, 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) +
-                                       4.0 * (B.nrows + 1));
+    const double bytes = 12.0 * (A.nnz + B.nnz) + 4.0 * (A.nrows + 1) + 4.0 * (B.nrows + 1);
+    ProfScope ps("spgemm_fill", s, bytes);
+    if (slot) *slot = ps.slot;
+    if (base) *base = bytes;
     const double mean_e = m ? (double)etot / m : 0.0;
     launch_spgemm(m, A.rp.get(), A.cj.get(), A.v.get(), B.rows, B.cj, B.v, st.eoff.get(),
                   emax, mean_e, ratio > 1.0 ? mean_e / ratio : 0.0, st.cnt.get(), tcj.get(),
@@ -233,7 +245,9 @@ static void spgemm_to_staged(const DevCSR &A, const BSrc &B, StagedB &C, SpgemmS
                              double ratio) {
     DevArr<int32_t> tcj;
     DevArr<double> tcx;
-    spgemm_hash(A, B, st, s, ratio, tcj, tcx);
+    int slot = -1;
+    double base = 0.0;
+    spgemm_hash(A, B, st, s, ratio, tcj, tcx, &slot, &base);
     C.nrows = st.m;
     C.ncols = B.ncols;
     C.nnz = st.h[0];                 // an upper bound until the sizes arrive
@@ -241,6 +255,8 @@ static void spgemm_to_staged(const DevCSR &A, const BSrc &B, StagedB &C, SpgemmS
     DevArr<int32_t> rp;
     rp.alloc((size_t)st.m + 1, s);
     pend.arm_sizes(st.ctl(), &C.nnz, &C.max_row, "sparse product row with more than 1024 terms");
+    pend.prof_slot = slot;
+    pend.prof_base = base;
     scan_counts_i32_to(st.cnt.get(), rp.get(), st.m, s, tmp, pend.tot());
     C.off = std::move(st.eoff);
     C.len = std::move(st.cnt);
@@ -260,7 +276,13 @@ static int32_t spgemm_finish(const DevCSR &A, const BSrc &B, DevCSR &C, SpgemmSt
     if (defer) defer->arm_at(st.ctl(), &C, "sparse product row with more than 1024 terms");
     DevArr<int32_t> tcj;
     DevArr<double> tcx;
-    spgemm_hash(A, B, st, s, ratio, tcj, tcx);
+    int fill_slot = -1;
+    double fill_base = 0.0;
+    spgemm_hash(A, B, st, s, ratio, tcj, tcx, &fill_slot, &fill_base);
+    if (defer) {
+        defer->prof_slot = fill_slot;
+        defer->prof_base = fill_base;
+    }
     C.rp.alloc((size_t)m + 1, s);
     int64_t mx = 0;
     if (lump_tol > 0.0 && !defer) {
@@ -303,6 +325,7 @@ static int32_t spgemm_finish(const DevCSR &A, const BSrc &B, DevCSR &C, SpgemmSt
         mx = ht[1];
         if (distinct) *distinct = ht[2];
         prof_set_bytes(count_slot, 12.0 * ht[2] + 16.0 * m);
+        prof_set_bytes(fill_slot, fill_base + 12.0 * ht[2]);
         C.max_row = (int32_t)mx;
         C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
         C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
@@ -323,6 +346,7 @@ static int32_t spgemm_finish(const DevCSR &A, const BSrc &B, DevCSR &C, SpgemmSt
         C.nnz = scan_counts_i32(st.cnt.get(), C.rp.get(), m, s, tmp, &mx, ovp, &ov);
         if (ov) fail(LAIR_EUNSUPPORTED, "sparse product row with more than 1024 terms");
         C.max_row = (int32_t)mx;
+        prof_set_bytes(fill_slot, fill_base + 12.0 * C.nnz);
     }
     C.cj.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
     C.v.alloc((size_t)std::max<int64_t>(C.nnz, 1), s);
