@@ -31,9 +31,15 @@ DEVICE = ["-x", "hip", "--offload-arch=" + ARCH,
           "-munsafe-fp-atomics"]
 
 
+# Per-file device flags.  The register-tiled node solves unroll their step
+# loops over 9 column slots; past the default size limit the unrolling stops
+# and the register tiles fall back to scratch memory.
+FILE_FLAGS = {"k_setup.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+
+
 def _compile(src, hip):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + (DEVICE if hip else []) + \
+    cmd = [HIPCC] + COMMON + (DEVICE + FILE_FLAGS.get(src, []) if hip else []) + \
         ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -1472,6 +1472,7 @@ __device__ __forceinline__ void wave_solve(int32_t c, const int32_t *clist, cons
 // LDS when they fit, else partly (the double copy of M) or wholly in a
 // global slab per block.
 constexpr size_t NODE_LDS_MAX = 64 * 1024;   // LDS of one node's block
+constexpr size_t NODE_LDS_CU = 152 * 1024;   // at most, when one block takes a CU
 
 // Bytes of one node's work arrays for systems up to `cap` rows: with_md
 // includes the double copy of M that MIXED keeps for the refinement.
@@ -1609,10 +1610,26 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
                     const int a = db.quot(idx), r = kk + 1 + idx - a * below;
                     w[a * s + r] -= M[r * s + kk] * w[a * s + kk];
                 }
-                for (int idx = lane; idx < below * below; idx += 64) {
-                    const int rr = db.quot(idx);
-                    const int r = kk + 1 + rr, q = kk + 1 + idx - rr * below;
-                    M[r * s + q] -= M[r * s + kk] * M[kk * s + q];
+                // four entries per lane at a time, every load before any
+                // store (the entries of a step are independent), so their
+                // LDS latencies overlap
+                const int nb = below * below;
+                for (int base = lane; base < nb; base += 4 * 64) {
+                    int o[4];
+                    FT a[4], b[4], c[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int idx = min(base + u * 64, nb - 1);
+                        const int rr = db.quot(idx);
+                        const int r = kk + 1 + rr, q = kk + 1 + idx - rr * below;
+                        o[u] = r * s + q;
+                        a[u] = M[o[u]];
+                        b[u] = M[r * s + kk];
+                        c[u] = M[kk * s + q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (base + u * 64 < nb) M[o[u]] = a[u] - b[u] * c[u];
                 }
             }
             __syncthreads();
@@ -1686,6 +1703,396 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
             const int64_t o = (int64_t)nptr[c0 + a] + c0 + a + q + (q >= ip ? 1 : 0);
             r_cj[o] = ln[q];
             r_v[o] = z[a * s + q];
+        }
+        if (lane < k) {
+            const int64_t o = (int64_t)nptr[c0 + lane] + c0 + lane + ip;
+            r_cj[o] = i0 + lane;
+            r_v[o] = 1.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Fixed-length binary searches over a sorted int array of at most 128
+// entries: no data-dependent trip count, so a lane's searches for several
+// keys proceed side by side.  Entries of a[0..n) below key, and at or below.
+__device__ __forceinline__ int count_below(const int32_t *a, int n, int key) {
+    int p = 0;
+    if (n <= 0) return 0;
+#pragma unroll
+    for (int step = 64; step > 0; step >>= 1) {
+        const int t = p + step;
+        const int x = a[min(t, n) - 1];
+        if (t <= n && x < key) p = t;
+    }
+    return p;
+}
+__device__ __forceinline__ int count_upto(const int32_t *a, int n, int key) {
+    int p = 0;
+    if (n <= 0) return 0;
+#pragma unroll
+    for (int step = 64; step > 0; step >>= 1) {
+        const int t = p + step;
+        const int x = a[min(t, n) - 1];
+        if (t <= n && x <= key) p = t;
+    }
+    return p;
+}
+
+// The gather of gather_local for one wave and systems up to 128 rows:
+// M[k][q] = a(l_q, l_k) (row stride ldm).  Each entry's row in the flat
+// range and its column's place in N come from fixed-length searches, so the
+// U entries of a lane are found side by side instead of one walk after
+// another.
+template <int U>
+__device__ __forceinline__ void gather_wave(int lane, int s, const int32_t *ln, int32_t *off,
+                                            int32_t *st, const int32_t *rp, const int32_t *cj,
+                                            const double *v, double *M, int ldm) {
+    int carry = 0;
+    for (int q0 = 0; q0 < s; q0 += 64) {
+        const int q = q0 + lane;
+        int a = 0, len = 0;
+        if (q < s) {
+            const int r = ln[q];
+            a = rp[r];
+            len = rp[r + 1] - a;
+        }
+        const int incl = team_scan_incl<64>(len);
+        if (q < s) {
+            st[q] = a;
+            off[q] = carry + incl - len;
+        }
+        carry += __shfl(incl, 63);
+    }
+    if (lane == 0) off[s] = carry;
+    __syncthreads();
+    const int E = carry;
+    for (int base = lane; base < E; base += U * 64) {
+        int qq[U], e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = min(base + u * 64, E - 1);
+            qq[u] = count_upto(off + 1, s - 1, idx);     // off[qq] <= idx < off[qq + 1]
+            e[u] = st[qq[u]] + idx - off[qq[u]];
+        }
+        int col[U];
+        double val[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            col[u] = cj[e[u]];
+            val[u] = v[e[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kp = count_below(ln, s, col[u]);
+            if (base + u * 64 < E && kp < s && ln[kp] == col[u])
+                M[(size_t)kp * ldm + qq[u]] = val[u];
+        }
+    }
+}
+
+// The node solve with M in registers, for systems up to 8R rows.  The wave
+// is an 8 x 8 grid of lanes: lane (lr, lq) keeps the entries (r, q) of M
+// with r = lr + 8i, q = lq + 8j in m[i][j], and in column slot R the entry
+// of right-hand side lq (lq < k) at row r.  Rows never move: each keeps its
+// position under the row exchanges beside it, and the pivot of step kk is
+// the arg-max of |M[r][kk]| over the rows at positions >= kk, ties to the
+// smallest position, as in the LDS form.  Every lane of a row of lanes
+// holds column kk of its rows (cur), so the arg-max needs only a reduction
+// across the rows of lanes and every lane forms its rows' multipliers; the
+// pivot row goes through LDS from its row of lanes, and after the update the
+// next column is shared along each row of lanes.  The substitutions
+// take the column of U or L the same way; in MIXED the refinement's
+// residual f - M z comes from the double matrix in LDS, summed in the order
+// of the LDS form.  Every
+// entry sees the operations of the LDS form in the same order, so the rows
+// of R are the same bit for bit.  LDS holds the gathered matrix in double,
+// the right-hand sides and the neighbourhood.
+template <int R>
+__host__ __device__ constexpr size_t node_reg_lds_bytes(int k, bool mg_in_lds = true) {
+    return (mg_in_lds ? (size_t)64 * R * R * sizeof(double) : 0) +
+           2 * (size_t)k * 8 * R * sizeof(double) +
+           2 * (size_t)8 * (R + 1) * sizeof(double) + (4 * (size_t)8 * R + 1) * sizeof(int32_t) +
+           64;
+}
+
+template <int R, bool MIXED, bool GMG>
+__global__ void __launch_bounds__(64)
+k_local_node_reg(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr,
+                 const int32_t *nbr, const int32_t *rp, const int32_t *cj, const double *v,
+                 int32_t *r_cj, double *r_v, int8_t *flags, int32_t *sing, int32_t *nsing,
+                 int32_t *bad, int32_t s_lo, int32_t s_hi, double *gslab) {
+    using FT = typename std::conditional<MIXED, float, double>::type;
+    constexpr int SC = 8 * R, C = R + 1;
+    extern __shared__ double dyn[];
+    const int lane = threadIdx.x, lr = lane >> 3, lq = lane & 7;
+    // layout: Mg[s][s] (in this block's global slab when GMG: LDS then
+    // leaves room for more waves per CU), f[k][s] and zs[k][s] (double), two
+    // pivot-row buffers of 8C (FT), ln, off, st, rowat (int)
+    double *Mg = GMG ? gslab + (size_t)blockIdx.x * SC * SC : dyn;
+    double *f = GMG ? dyn : dyn + (size_t)SC * SC;
+    double *zs = f + (size_t)k * SC;
+    FT *prow = (FT *)(zs + (size_t)k * SC);
+    int32_t *ln = (int32_t *)(prow + 2 * 8 * C);
+    int32_t *off = ln + SC;
+    int32_t *st = off + SC + 1;
+    int32_t *rowat = st + SC;
+    for (int64_t node = blockIdx.x; node < nnode; node += gridDim.x) {
+        const int32_t c0 = (int32_t)(node * k);
+        const int32_t i0 = clist[c0];
+        const int32_t n0 = nptr[c0];
+        const int s = nptr[c0 + 1] - n0;
+        if (s < s_lo || s > s_hi) continue;      // outside this launch's size range
+        bool ok = s <= SC;
+        for (int a = 1; a < k; ++a)
+            ok = ok && clist[c0 + a] == i0 + a && nptr[c0 + a + 1] - nptr[c0 + a] == s;
+        if (!ok) {
+            if (lane == 0) atomicAdd(bad, 1);
+            continue;
+        }
+        const int32_t *l = nbr + n0;
+        if (lane < k) flags[c0 + lane] = 0;
+        __syncthreads();
+        for (int idx = lane; idx < s * s; idx += 64) Mg[idx] = 0.0;
+        for (int idx = lane; idx < k * s; idx += 64) f[idx] = 0.0;
+        for (int p = lane; p < s; p += 64) ln[p] = l[p];
+        __syncthreads();
+        gather_wave<8>(lane, s, ln, off, st, rp, cj, v, Mg, s);
+        for (int a = 0; a < k; ++a)
+            for (int e = rp[i0 + a] + lane; e < rp[i0 + a + 1]; e += 64) {
+                int p = bsearch_i32(ln, s, cj[e]);
+                if (p >= 0) f[a * s + p] = -v[e];
+            }
+        __syncthreads();
+        double rs = 0.0;
+        for (int p = lane; p < s; p += 64) {
+            double acc = 0.0;
+            for (int q = 0; q < s; ++q) acc += fabs(Mg[p * s + q]);
+            rs = fmax(rs, acc);
+        }
+        const double tol = SING_TOL * team_max<64>(rs);
+        FT m[R][C];
+        FT cur[R];
+        int pos[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lr + 8 * i;
+            pos[i] = r < s ? r : -1;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int q = lq + 8 * j;
+                m[i][j] = (r < s && q < s) ? (FT)Mg[r * s + q] : (FT)0;
+            }
+            m[i][R] = (r < s && lq < k) ? (FT)f[lq * s + r] : (FT)0;
+            cur[i] = r < s ? (FT)Mg[r * s] : (FT)0;
+        }
+        bool singular = false;
+#pragma unroll
+        for (int jb = 0; jb < R; ++jb) {
+#pragma unroll 1
+            for (int kl = 0; kl < 8; ++kl) {
+                const int kk = 8 * jb + kl;
+                if (kk >= s) break;
+                // arg-max over the unused rows, then across the rows of lanes
+                double pv = -1.0;
+                int key = INT_MAX;
+                FT pval = (FT)0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const double a = fabs((double)cur[i]);
+                    const int ki = pos[i] * 256 + lr + 8 * i;
+                    if (pos[i] >= kk && (a > pv || (a == pv && ki < key))) {
+                        pv = a;
+                        key = ki;
+                        pval = cur[i];
+                    }
+                }
+#pragma unroll
+                for (int o = 8; o < 64; o <<= 1) {
+                    const double ov = __shfl_xor(pv, o);
+                    const int ok2 = __shfl_xor(key, o);
+                    const FT oval = __shfl_xor(pval, o);
+                    if (ov > pv || (ov == pv && ok2 < key)) { pv = ov; key = ok2; pval = oval; }
+                }
+                key = __builtin_amdgcn_readfirstlane(key);
+                // (no candidate at all, key INT_MAX, only with a NaN norm)
+                if (__builtin_amdgcn_readfirstlane(pv <= tol || key == INT_MAX ? 1 : 0)) {
+                    singular = true;
+                    break;
+                }
+                const int pp = key >> 8;
+                // exchange positions kk and pp
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    pos[i] = pos[i] == kk ? pp : (pos[i] == pp ? kk : pos[i]);
+                FT mult[R];
+#pragma unroll
+                for (int i = 0; i < R; ++i) mult[i] = cur[i] / pval;
+                // the pivot row through LDS: its row of lanes writes it (the
+                // pivot is the row now at position kk; selecting its slot by
+                // a test on each slot keeps m out of indexed memory)
+                FT *pb = prow + (kk & 1) * 8 * C;
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (pos[i] == kk) {
+#pragma unroll
+                        for (int j = 0; j < C; ++j)
+                            if (j >= jb) pb[j * 8 + lq] = m[i][j];
+                    }
+                wave_lds_sync();
+                FT pj[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) pj[j] = j >= jb ? pb[j * 8 + lq] : (FT)0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    if (pos[i] > kk) {
+                        const FT mu = mult[i];
+                        m[i][jb] = lq > kl ? m[i][jb] - mu * pj[jb]
+                                           : (lq == kl ? mu : m[i][jb]);
+#pragma unroll
+                        for (int j = 0; j < R; ++j)
+                            if (j > jb) m[i][j] -= mu * pj[j];
+                        m[i][R] = lq < k ? m[i][R] - mu * pj[R] : m[i][R];
+                    }
+                }
+                // the next column along each row of lanes
+                if (kl < 7) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) cur[i] = __shfl(m[i][jb], lr * 8 + kl + 1);
+                } else if (jb + 1 < R) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) cur[i] = __shfl(m[i][jb + 1 < R ? jb + 1 : jb], lr * 8);
+                }
+            }
+            if (singular) break;
+        }
+        if (singular) {
+            if (lane == 0) {
+                const int32_t o = atomicAdd(nsing, k);
+                for (int a = 0; a < k; ++a) {
+                    flags[c0 + a] = 1;
+                    sing[o + a] = c0 + a;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        // the row at each position, read per step by readlane
+        if (lq == 0) {
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (pos[i] >= 0) rowat[pos[i]] = lr + 8 * i;
+        }
+        wave_lds_sync();
+        const int ra0 = lane < s ? rowat[lane] : 0;
+        const int ra1 = (SC > 64 && 64 + lane < s) ? rowat[64 + lane] : 0;
+        // solution entries q = lr + 8i of right-hand side lq (lanes lq < k)
+        double zr[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) zr[i] = 0.0;
+        for (int pass = 0; pass < (MIXED && s > 0 ? 2 : 1); ++pass) {
+            if (pass == 1) {
+                // residual f - M z in double from the gathered matrix, each
+                // entry summed over the columns from the last down; a lane
+                // runs its entries side by side
+                if (lq < k) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const int q = lr + 8 * i;
+                        if (q < s) zs[lq * s + q] = zr[i];
+                    }
+                }
+                wave_lds_sync();
+                constexpr int NT = (8 * SC + 63) / 64;     // entries per lane, k <= 8
+                const SmallDiv ds(s > 0 ? s : 1);
+                double acc[NT];
+                int bm[NT], bz[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int idx = min(lane + 64 * t, k * s - 1);
+                    const int a = ds.quot(idx), p = idx - a * s;
+                    bm[t] = p * s;
+                    bz[t] = a * s;
+                    acc[t] = f[idx];
+                }
+                for (int q = s - 1; q >= 0; --q) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[t] -= Mg[bm[t] + q] * zs[bz[t] + q];
+                }
+                wave_lds_sync();
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    if (lane + 64 * t < k * s) f[lane + 64 * t] = acc[t];
+                wave_lds_sync();
+                // the residual as right-hand side (row r takes residual r:
+                // rows never moved), then forward substitution with L
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int r = lr + 8 * i;
+                    m[i][R] = (r < s && lq < k) ? (FT)f[lq * s + r] : (FT)0;
+                }
+#pragma unroll
+                for (int jb = 0; jb < R; ++jb) {
+#pragma unroll 1
+                    for (int kl = 0; kl < 8; ++kl) {
+                        const int kk = 8 * jb + kl;
+                        if (kk >= s) break;
+                        const int ph = __builtin_amdgcn_readlane(kk < 64 ? ra0 : ra1, kk & 63);
+                        FT wl = (FT)0;
+#pragma unroll
+                        for (int i = 0; i < R; ++i) wl = pos[i] == kk ? m[i][R] : wl;
+                        const FT wk = __shfl(wl, (ph & 7) * 8 + lq);
+#pragma unroll
+                        for (int i = 0; i < R; ++i) {
+                            const FT lv = __shfl(m[i][jb], lr * 8 + kl);
+                            const FT t = m[i][R] - lv * wk;
+                            m[i][R] = (lq < k && pos[i] > kk) ? t : m[i][R];
+                        }
+                    }
+                }
+            }
+            // back substitution: z_kk = w(row at kk) / U(kk, kk), then the
+            // rows above remove column kk
+#pragma unroll
+            for (int jb = R - 1; jb >= 0; --jb) {
+#pragma unroll 1
+                for (int kl = 7; kl >= 0; --kl) {
+                    const int kk = 8 * jb + kl;
+                    if (kk >= s) continue;
+                    const int ph = __builtin_amdgcn_readlane(kk < 64 ? ra0 : ra1, kk & 63);
+                    FT ucol[R];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) ucol[i] = __shfl(m[i][jb], lr * 8 + kl);
+                    FT num = (FT)0, den = (FT)1;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        num = pos[i] == kk ? m[i][R] : num;
+                        den = pos[i] == kk ? ucol[i] : den;
+                    }
+                    const FT zk = __shfl(num / den, (ph & 7) * 8 + lq);
+                    if (lr == kl) zr[jb] = pass == 0 ? (double)zk : zr[jb] + (double)zk;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const FT t = m[i][R] - ucol[i] * zk;
+                        m[i][R] = (lq < k && pos[i] >= 0 && pos[i] < kk) ? t : m[i][R];
+                    }
+                }
+            }
+        }
+        // rows of R: N with the identity entry at the row's place
+        int ip = 0;
+        for (int q = lane; q < s; q += 64) ip += (ln[q] < i0) ? 1 : 0;
+        ip = team_sum_int<64>(ip);
+        if (lq < k) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int q = lr + 8 * i;
+                if (q < s) {
+                    const int64_t o = (int64_t)nptr[c0 + lq] + c0 + lq + q + (q >= ip ? 1 : 0);
+                    r_cj[o] = ln[q];
+                    r_v[o] = zr[i];
+                }
+            }
         }
         if (lane < k) {
             const int64_t o = (int64_t)nptr[c0 + lane] + c0 + lane + ip;
@@ -2055,16 +2462,35 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
             rb.add(cost, acc.get(), sizeof(cost));
             rb.run();
         }
-        // Work arrays in at most 64 KB of LDS (several blocks per CU): all of
-        // them up to `cap` rows, all but the double copy of M (MIXED) up to
-        // `cap_nomd`; larger systems use a global slab per block, the grid
-        // then kept small enough for 256 MB of slabs.  (Blocks with the
-        // whole LDS of a CU for the large systems ran slower: one wave per
-        // CU leaves the elimination's latency exposed.)
+        // Systems up to 72 rows run with M in registers, in three size
+        // classes (the smaller tiles leave more waves per CU); the LDS form
+        // takes the rest.  Its work arrays: in at most 64 KB of LDS (several
+        // blocks per CU) when it takes every system, all of them up to `cap`
+        // rows, all but the double copy of M (MIXED) up to `cap_nomd`; larger
+        // systems use a global slab per block, the grid then kept small
+        // enough for 256 MB of slabs.  When it takes only the few systems
+        // above 72 rows it gets the LDS of a whole CU, which keeps them out
+        // of the slab.  (For the bulk, blocks with the whole LDS of a CU ran
+        // slower: one wave per CU leaves the elimination's latency exposed.)
+        const bool reg = knode <= 8 && !env_flag("LAIR_NODE_LDS_SOLVES");
+        size_t budget = NODE_LDS_MAX;
+        if (reg && smax > 72) {
+            const size_t big = mixed ? std::max(node_lds_bytes<float>(smax, knode),
+                                                node_lds_bytes<float>(smax, knode, false))
+                                     : node_lds_bytes<double>(smax, knode);
+            const size_t want = std::min<size_t>(big, NODE_LDS_CU);
+            const void *kern = mixed ? (const void *)k_local_node<true>
+                                     : (const void *)k_local_node<false>;
+            if (want > NODE_LDS_MAX &&
+                hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)want) == hipSuccess)
+                budget = want;
+            (void)hipGetLastError();
+        }
         const int sm1 = std::max(1, smax);
-        const int cap = mixed ? node_cap_for<float>(NODE_LDS_MAX, knode, true, sm1)
-                              : node_cap_for<double>(NODE_LDS_MAX, knode, true, sm1);
-        const int cap_nomd = mixed ? node_cap_for<float>(NODE_LDS_MAX, knode, false, sm1) : cap;
+        const int cap = mixed ? node_cap_for<float>(budget, knode, true, sm1)
+                              : node_cap_for<double>(budget, knode, true, sm1);
+        const int cap_nomd = mixed ? node_cap_for<float>(budget, knode, false, sm1) : cap;
         const size_t lds = mixed ? std::max(node_lds_bytes<float>(cap, knode),
                                             node_lds_bytes<float>(cap_nomd, knode, false))
                                  : node_lds_bytes<double>(cap, knode);
@@ -2085,15 +2511,59 @@ int64_t local_solves(int32_t nc, const int32_t *clist, const int32_t *nptr,
         }
         {
             ProfScope ps("local_node", s, cost[0], cost[1]);
-            if (mixed)
-                LAIR_LAUNCH(k_local_node<true>, dim3(g), dim3(64), lds, s, nnode, knode, clist,
-                            nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(),
-                            cnt + 6, cnt, cap, cap_nomd, gscratch.get(), slab, smax, 0, smax);
-            else
-                LAIR_LAUNCH(k_local_node<false>, dim3(g), dim3(64), lds, s, nnode, knode, clist,
-                            nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(),
-                            cnt + 6, cnt, cap, cap_nomd, gscratch.get(), slab, smax, 0, smax);
-            LAIR_LAUNCH_CHECK();
+            const unsigned gr = (unsigned)std::min<int64_t>(nnode, 8192);
+            int lo = 0;
+            if (reg) {
+                auto run = [&](auto kern, int hi, size_t bytes, unsigned grid, double *slabs) {
+                    if (lo > smax) return;
+                    LAIR_LAUNCH(kern, dim3(grid), dim3(64), bytes, s, nnode, knode, clist, nptr,
+                                nbr, rp, cj, v, out.r_cj, out.r_v, out.flags, sing.get(),
+                                cnt + 6, cnt, lo, hi, slabs);
+                    LAIR_LAUNCH_CHECK();
+                    lo = hi + 1;
+                };
+                if (mixed) {
+                    run(k_local_node_reg<3, true, false>, 24, node_reg_lds_bytes<3>(knode), gr,
+                        nullptr);
+                    run(k_local_node_reg<5, true, false>, 40, node_reg_lds_bytes<5>(knode), gr,
+                        nullptr);
+                    if (lo <= smax) {
+                        // the largest class keeps its double matrix in a
+                        // global slab per block (then registers, not LDS,
+                        // bound the waves per CU)
+                        const unsigned g9 = (unsigned)std::min<int64_t>(nnode, 2048);
+                        DevArr<double> slabs;
+                        slabs.alloc((size_t)g9 * 72 * 72, s);
+                        run(k_local_node_reg<9, true, true>, 72,
+                            node_reg_lds_bytes<9>(knode, false), g9, slabs.get());
+                    }
+                } else {
+                    run(k_local_node_reg<3, false, false>, 24, node_reg_lds_bytes<3>(knode), gr,
+                        nullptr);
+                    run(k_local_node_reg<5, false, false>, 40, node_reg_lds_bytes<5>(knode), gr,
+                        nullptr);
+                    if (lo <= smax) {
+                        const unsigned g9 = (unsigned)std::min<int64_t>(nnode, 2048);
+                        DevArr<double> slabs;
+                        slabs.alloc((size_t)g9 * 72 * 72, s);
+                        run(k_local_node_reg<9, false, true>, 72,
+                            node_reg_lds_bytes<9>(knode, false), g9, slabs.get());
+                    }
+                }
+            }
+            if (lo <= smax) {
+                if (mixed)
+                    LAIR_LAUNCH(k_local_node<true>, dim3(g), dim3(64), lds, s, nnode, knode,
+                                clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
+                                sing.get(), cnt + 6, cnt, cap, cap_nomd, gscratch.get(), slab,
+                                smax, lo, smax);
+                else
+                    LAIR_LAUNCH(k_local_node<false>, dim3(g), dim3(64), lds, s, nnode, knode,
+                                clist, nptr, nbr, rp, cj, v, out.r_cj, out.r_v, out.flags,
+                                sing.get(), cnt + 6, cnt, cap, cap_nomd, gscratch.get(), slab,
+                                smax, lo, smax);
+                LAIR_LAUNCH_CHECK();
+            }
         }
         int32_t h[7] = {0, 0, 0, 0, 0, 0, 0};
         {

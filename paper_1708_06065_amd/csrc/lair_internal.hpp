@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -175,6 +177,12 @@ bool prof_kernel_events(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1);
         else                                                                       \
             hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                       \
     } while (0)
+
+// An environment switch: set and not "0".
+inline bool env_flag(const char *name) {
+    const char *e = std::getenv(name);
+    return e && *e && std::strcmp(e, "0") != 0;
+}
 
 // ---------------------------------------------------------------------------
 // Launch helpers

@@ -113,12 +113,6 @@ struct PendingSizes {
 
 // The profiler attributes algorithmic bytes from host-side sizes as it
 // launches; while it times the setup categories every size is read at once.
-// An environment switch: set and not "0".
-static bool env_flag(const char *name) {
-    const char *e = std::getenv(name);
-    return e && *e && std::strcmp(e, "0") != 0;
-}
-
 static bool setup_sizes_eager() {
     return prof_selected("spgemm_fill") || prof_selected("spgemm_compact") ||
            prof_selected("spgemm_count") || prof_selected("interp");

@@ -222,30 +222,37 @@ def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precisi
     """The nodal local systems of a C-node (one matrix A(N,N)^T, one
     right-hand side per row of the node; Sec. 3.1, block form of
     Eq. (system)) solved as one factorisation with k right-hand sides give
-    the same R, bit for bit, as k separate solves of the scalar rows; the
-    node path is the one that ran (its profiler category)."""
+    the same R, bit for bit, as k separate solves of the scalar rows, with
+    the node's matrix in registers or in LDS; the node path is the one that
+    ran (its profiler category)."""
     _say("case: node solves", name, "distance", distance, precision)
     A, b, k = _case(name)
     Rs = {}
-    for rows in (True, False):
-        if rows:
+    # scalar rows; nodes with M in registers (systems up to 72 rows) and in
+    # LDS above; nodes all in LDS
+    for mode in ("rows", "nodes", "nodes_lds"):
+        monkeypatch.delenv("LAIR_NODAL_ROW_SOLVES", raising=False)
+        monkeypatch.delenv("LAIR_NODE_LDS_SOLVES", raising=False)
+        if mode == "rows":
             monkeypatch.setenv("LAIR_NODAL_ROW_SOLVES", "1")
-        else:
-            monkeypatch.delenv("LAIR_NODAL_ROW_SOLVES", raising=False)
+        if mode == "nodes_lds":
+            monkeypatch.setenv("LAIR_NODE_LDS_SOLVES", "1")
         lair.profile_begin(["local_node", "local_small"])
         h = lair.setup(A.indptr, A.indices, A.data, block_size=k, nodal=True,
                        distance=distance, precision=precision)
         prof = lair.profile_end()
-        Rs[rows] = [gpu_level_csr(h, l, "R") for l in range(h.nlevels - 1)]
+        Rs[mode] = [gpu_level_csr(h, l, "R") for l in range(h.nlevels - 1)]
         smax = max(h.level_stats(l)["s_max"] for l in range(h.nlevels - 1))
-        _say("  rows" if rows else "  nodes", "levels", h.nlevels, "s_max", smax,
+        _say("  " + mode, "levels", h.nlevels, "s_max", smax,
              {c: (round(v["ms"], 3), v["launches"]) for c, v in prof.items()})
-        if rows:
+        if mode == "rows":
             assert "local_node" not in prof
         else:
             assert prof.get("local_node", {}).get("launches", 0) > 0
         h.free()
-    assert len(Rs[True]) == len(Rs[False])
-    for l, (a, c) in enumerate(zip(Rs[True], Rs[False])):
-        for u, w in zip(a, c):
-            assert np.array_equal(u, w), "R differs at level %d" % l
+    monkeypatch.delenv("LAIR_NODE_LDS_SOLVES", raising=False)
+    for mode in ("nodes", "nodes_lds"):
+        assert len(Rs["rows"]) == len(Rs[mode])
+        for l, (a, c) in enumerate(zip(Rs["rows"], Rs[mode])):
+            for u, w in zip(a, c):
+                assert np.array_equal(u, w), "R differs at level %d (%s)" % (l, mode)
