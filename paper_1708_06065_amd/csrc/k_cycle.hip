@@ -306,12 +306,21 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
     constexpr int L = NR / VW;
     __shared__ double sh[256 * VW];
     const int t = (int)(threadIdx.x % T);
-    const int64_t team0 = ((int64_t)xcd_block_id() * blockDim.x + threadIdx.x) / T;
-    const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / T);
+    // the blocks of one XCD (consecutive ids under xcd_block_id) take one
+    // contiguous share of the rows, their teams striding through it: a
+    // row's neighbours a few strides away then stay in that XCD's L2
+    // instead of being fetched again by another XCD
+    const int64_t nb = gridDim.x, xb = blockIdx.x % NXCD;
+    const int64_t q = nb / NXCD, rr = nb % NXCD;
+    const int64_t nbx = q + (xb < rr ? 1 : 0);
+    const int64_t b0 = xb < rr ? xb * (q + 1) : rr * (q + 1) + (xb - rr) * q;
+    const int64_t tpb = blockDim.x / T;
+    const int64_t tl = (xcd_block_id() - b0) * tpb + threadIdx.x / T;
+    const int64_t lo = b0 * (int64_t)nrows / nb, hi = (b0 + nbx) * (int64_t)nrows / nb;
     double sq[VW];
 #pragma unroll
     for (int k = 0; k < VW; ++k) sq[k] = 0.0;
-    for (int64_t i = team0; i < nrows; i += nteams) {
+    for (int64_t i = lo + tl; i < hi; i += nbx * tpb) {
         Pack<double, VW> acc;
         acc.zero();
         double d = 0.0;
