@@ -64,6 +64,11 @@ def _case(name):
         A.sort_indices()
         A.data = A.data * (1.0 + 0.3 * rng.standard_normal(A.nnz))
         return A, np.kron(bs, [1.0, 1.0]), 2
+    if name == "dgu24":
+        # 24 x 24 x 2 triangles, kappa 1e-3: at distance 2 level 1 holds
+        # systems of up to 78 rows, past the register form's 72
+        w = W.workload_dgu(24, 1e-3)
+        return O.csr(w["rowptr"], w["col"], w["val"]), w["rhs"], 6
     if name.startswith("dgu"):
         # the DGu problem of Sec. 4.2 (gamma jump, curved field) with
         # diffusion kappa = the number after "dgu"
@@ -131,7 +136,8 @@ def test_nodal_levels_and_iterations(lair, name, own_split):
     h.free()
 
 
-@pytest.mark.parametrize("name", ["perturbed2", "dg_curved", "dgu0", "dgu0.001", "dgu1"])
+@pytest.mark.parametrize("name", ["perturbed2", "dg_curved", "dgu0", "dgu0.001", "dgu1",
+                                  "dgu24"])
 def test_nodal_distance_two(lair, name):
     """F-F-C paths on the graph of blocks: the node-expanded strength mask
     makes the scalar distance-two merge give the nodal sets."""
@@ -217,7 +223,7 @@ def test_nodal_argument_errors(lair):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name,distance", [("kron3", 1), ("dg_curved", 1), ("dg_curved", 2),
-                                           ("perturbed2", 2), ("dgu0.001", 2)])
+                                           ("perturbed2", 2), ("dgu0.001", 2), ("dgu24", 2)])
 def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precision):
     """The nodal local systems of a C-node (one matrix A(N,N)^T, one
     right-hand side per row of the node; Sec. 3.1, block form of
@@ -245,6 +251,8 @@ def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precisi
         smax = max(h.level_stats(l)["s_max"] for l in range(h.nlevels - 1))
         _say("  " + mode, "levels", h.nlevels, "s_max", smax,
              {c: (round(v["ms"], 3), v["launches"]) for c, v in prof.items()})
+        if name == "dgu24":
+            assert smax > 72        # the LDS form takes the largest systems
         if mode == "rows":
             assert "local_node" not in prof
         else:
