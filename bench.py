@@ -197,29 +197,34 @@ def _both_thread_counts(make_code, to_ms, describe):
             "sample": describe(allc) + "; the same on one core: %.1f ms" % to_ms(one)}
 
 
-def cpu_baseline_batch(kw, budget_s=15.0):
+def cpu_baseline_batch(kw, budget_s=15.0, x_path=None):
     """Oracle on a bounded sample of the batch: setup + solve of the systems
     in order until budget_s seconds have been spent, scaled to the whole
-    batch by stored entries."""
-    def code(_first):
+    batch by stored entries.  The one-core run also writes the oracle's
+    solutions of the systems it solved, one after another, to x_path."""
+    def code(first):
         return r"""
 import json, sys, time
 sys.path.insert(0, %r)
+import numpy as np
 import workloads as W
 from oracle import lair as O
 systems = W.adr_batch(512, seed=3)
 tot = sum(w["nnz"] for w in systems)
-t0 = time.perf_counter(); done = 0; nz = 0; its = []
+t0 = time.perf_counter(); done = 0; nz = 0; its = []; xs = []
 for w in systems:
     A = O.csr(w["rowptr"], w["col"], w["val"])
     H = O.setup(A, interp=O.INTERP_DIRECT, lump_tol=%r)
     x, it, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=100)
-    done += 1; nz += w["nnz"]; its.append(it)
+    done += 1; nz += w["nnz"]; its.append(it); xs.append(x)
     if time.perf_counter() - t0 > %r:
         break
 el = time.perf_counter() - t0
+xp = %r
+if xp:
+    np.save(xp, np.concatenate(xs))
 print(json.dumps({"s": el, "done": done, "nnz": nz, "tot": tot, "iters_max": max(its)}))
-""" % (ROOT, kw.get("lump_tol", 0.0), budget_s)
+""" % (ROOT, kw.get("lump_tol", 0.0), budget_s, x_path if first else None)
 
     def to_ms(d):
         return 1e3 * d["s"] * d["tot"] / d["nnz"]
@@ -232,15 +237,20 @@ print(json.dumps({"s": el, "done": done, "nnz": nz, "tot": tot, "iters_max": max
     return _both_thread_counts(code, to_ms, describe)
 
 
-def cpu_baseline_nodal(kw, n_full, gen, m_sample=96):
+DG_ORACLE_SAMPLE = 96     # mesh of the nodal workloads' oracle sample
+
+
+def cpu_baseline_nodal(kw, n_full, gen, m_sample=DG_ORACLE_SAMPLE, x_path=None):
     """The oracle's nodal setup + solve to 1e-10 on the same DG problem at
     m_sample x m_sample x 2 triangles (its Python loops over nodes would
     take minutes at full size), scaled to the full problem by rows.  gen:
-    the workload call with %d for the mesh size."""
-    def code(_first):
+    the workload call with %d for the mesh size.  The one-core run also
+    writes the oracle's solution to x_path."""
+    def code(first):
         return (r"""
 import json, sys, time
 sys.path.insert(0, %r)
+import numpy as np
 import workloads as W
 from oracle import lair as O
 w = W.""" + gen + r"""
@@ -250,8 +260,11 @@ H = O.setup(A, block=6, distance=%d)
 t1 = time.perf_counter()
 x, it, _ = O.solve(H, w["rhs"], rtol=1e-10, maxit=300)
 t2 = time.perf_counter()
+xp = %r
+if xp:
+    np.save(xp, x)
 print(json.dumps({"setup_s": t1 - t0, "solve_s": t2 - t1, "iters": it, "n": w["n"]}))
-""") % (ROOT, m_sample, kw["distance"])
+""") % (ROOT, m_sample, kw["distance"], x_path if first else None)
 
     def to_ms(d):
         return 1e3 * (d["setup_s"] + d["solve_s"]) * n_full / d["n"]
@@ -694,16 +707,52 @@ def main():
         import tempfile
         xp = os.path.join(tempfile.mkdtemp(prefix="lair_bench_"), "x0.npy")
         if batch:
-            cb = cpu_baseline_batch(kw)
+            cb = cpu_baseline_batch(kw, x_path=xp)
         elif kw.get("nodal"):
             gen = ("workload_dgu(%%d, %r)" % DGU_KAPPA if args.workload == "dgu"
                    else "workload_dg_curved(%d)")
-            cb = cpu_baseline_nodal(kw, w["n"], gen)
+            cb = cpu_baseline_nodal(kw, w["n"], gen, x_path=xp)
         else:
             cb = cpu_baseline(args.workload, kw, xp, cycles=C2_CYCLES if c2 else None)
         if cb:
             out["cpu_baseline"] = cb
-        if x_main is not None and os.path.exists(xp):
+        if x_main is not None and os.path.exists(xp) and batch:
+            # every system the oracle solved (the first ones of the union)
+            xo = np.load(xp)
+            sys_n = [q["n"] for q in w["systems"]]
+            errs, lo = [], 0
+            for nq in sys_n:
+                if lo + nq > xo.size:
+                    break
+                xq = xo[lo:lo + nq]
+                errs.append(float(np.linalg.norm(x_main[lo:lo + nq] - xq) /
+                                  max(np.linalg.norm(xq), 1e-300)))
+                lo += nq
+            out["err_vs_fp64_oracle"] = {"max_rel": max(errs), "median_rel": float(np.median(errs)),
+                                         "systems": len(errs),
+                                         "sample": "the first %d of 512 systems, each against the "
+                                                   "oracle's FP64 solve to 1e-10" % len(errs)}
+        elif kw.get("nodal") and os.path.exists(xp):
+            # the full-size oracle would take minutes: the GPU solves the
+            # oracle's sample problem in the timed precision and is
+            # compared there
+            import workloads as W
+            m = DG_ORACLE_SAMPLE
+            ws = (W.workload_dgu(m, DGU_KAPPA) if args.workload == "dgu"
+                  else W.workload_dg_curved(m))
+            hs = lair.setup(torch.as_tensor(ws["rowptr"], device=dev),
+                            torch.as_tensor(ws["col"], device=dev),
+                            torch.as_tensor(ws["val"], device=dev), precision=main_prec, **kw)
+            bs = torch.as_tensor(np.ascontiguousarray(np.asarray(ws["rhs"], dtype=np.float64)),
+                                 device=dev)
+            xs, _ = hs.solve(bs, rtol=1e-10, maxit=maxit)
+            hs.free()
+            xo = np.load(xp)
+            out["err_vs_fp64_oracle"] = {
+                "rel": float(np.linalg.norm(xs.cpu().numpy() - xo) / np.linalg.norm(xo)),
+                "sample": "the same problem on %dx%dx2 triangles (%d rows), GPU in the timed "
+                          "precision against the oracle's FP64 solve to 1e-10" % (m, m, ws["n"])}
+        elif x_main is not None and os.path.exists(xp):
             xo = np.load(xp)
             out["err_vs_fp64_oracle_rhs0"] = float(np.linalg.norm(x_main - xo) /
                                                    np.linalg.norm(xo))
