@@ -1459,6 +1459,84 @@ __device__ __forceinline__ void wave_solve(int32_t c, const int32_t *clist, cons
     }
 }
 
+// Binary searches of a trip count fixed by n alone (steps from the largest
+// power of two <= n down), so a lane's searches for several keys proceed
+// side by side.  Entries of a[0..n) below key, and at or below.
+__device__ __forceinline__ int count_below(const int32_t *a, int n, int key) {
+    int p = 0;
+    if (n <= 0) return 0;
+    for (int step = 1 << (31 - __clz(n)); step > 0; step >>= 1) {
+        const int t = p + step;
+        const int x = a[min(t, n) - 1];
+        if (t <= n && x < key) p = t;
+    }
+    return p;
+}
+__device__ __forceinline__ int count_upto(const int32_t *a, int n, int key) {
+    int p = 0;
+    if (n <= 0) return 0;
+    for (int step = 1 << (31 - __clz(n)); step > 0; step >>= 1) {
+        const int t = p + step;
+        const int x = a[min(t, n) - 1];
+        if (t <= n && x <= key) p = t;
+    }
+    return p;
+}
+
+// The gather of gather_local for one wave (a block of 64 threads):
+// M[k][q] = a(l_q, l_k) (row stride ldm), and the same entries in double in
+// Md when given.  Each entry's row in the flat range and its column's place
+// in N come from the searches above, so the U entries of a lane are found
+// side by side instead of one walk after another.
+template <int U, class FT>
+__device__ __forceinline__ void gather_wave(int lane, int s, const int32_t *ln, int32_t *off,
+                                            int32_t *st, const int32_t *rp, const int32_t *cj,
+                                            const double *v, FT *M, int ldm, double *Md) {
+    int carry = 0;
+    for (int q0 = 0; q0 < s; q0 += 64) {
+        const int q = q0 + lane;
+        int a = 0, len = 0;
+        if (q < s) {
+            const int r = ln[q];
+            a = rp[r];
+            len = rp[r + 1] - a;
+        }
+        const int incl = team_scan_incl<64>(len);
+        if (q < s) {
+            st[q] = a;
+            off[q] = carry + incl - len;
+        }
+        carry += __shfl(incl, 63);
+    }
+    if (lane == 0) off[s] = carry;
+    __syncthreads();
+    const int E = carry;
+    for (int base = lane; base < E; base += U * 64) {
+        int qq[U], e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = min(base + u * 64, E - 1);
+            qq[u] = count_upto(off + 1, s - 1, idx);     // off[qq] <= idx < off[qq + 1]
+            e[u] = st[qq[u]] + idx - off[qq[u]];
+        }
+        int col[U];
+        double val[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            col[u] = cj[e[u]];
+            val[u] = v[e[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kp = count_below(ln, s, col[u]);
+            if (base + u * 64 < E && kp < s && ln[kp] == col[u]) {
+                M[(size_t)kp * ldm + qq[u]] = (FT)val[u];
+                if (Md) Md[(size_t)kp * ldm + qq[u]] = val[u];
+            }
+        }
+    }
+}
+
 // Block form of the local systems (Sec. 3.1): the k rows of a C-node share
 // their neighbourhood, so the k systems A(N,N)^T z_a = -A(i_a,N)^T have one
 // matrix and k right-hand sides.  One wave per node factors M once (the
@@ -1561,7 +1639,7 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
         for (int idx = lane; idx < k * s; idx += 64) f[idx] = 0.0;
         for (int p = lane; p < s; p += 64) { ln[p] = l[p]; perm[p] = p; }
         __syncthreads();
-        gather_local<64, 4, true, FT>(lane, s, ln, off, st, rp, cj, v, M, s, Md);
+        gather_wave<8, FT>(lane, s, ln, off, st, rp, cj, v, M, s, Md);
         // right-hand side a: -A(i_a, N)^T
         for (int a = 0; a < k; ++a)
             for (int e = rp[i0 + a] + lane; e < rp[i0 + a + 1]; e += 64) {
@@ -1603,33 +1681,27 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
             // final: the multipliers of this step only touch rows below)
             for (int r = kk + 1 + lane; r < s; r += 64) M[r * s + kk] = M[r * s + kk] / M[kk * s + kk];
             __syncthreads();
-            const int below = s - kk - 1;
-            if (below > 0) {
-                const SmallDiv db(below);
-                for (int idx = lane; idx < k * below; idx += 64) {
-                    const int a = db.quot(idx), r = kk + 1 + idx - a * below;
-                    w[a * s + r] -= M[r * s + kk] * w[a * s + kk];
-                }
-                // four entries per lane at a time, every load before any
-                // store (the entries of a step are independent), so their
-                // LDS latencies overlap
-                const int nb = below * below;
-                for (int base = lane; base < nb; base += 4 * 64) {
-                    int o[4];
-                    FT a[4], b[4], c[4];
+            // the right-hand sides' rows below, then the trailing matrix:
+            // each lane takes columns, runs down the rows eight at a time,
+            // every load of a batch before its stores (the entries of a step
+            // are independent), so their LDS latencies overlap
+            for (int a = 0; a < k; ++a) {
+                const FT wk = w[a * s + kk];
+                for (int r = kk + 1 + lane; r < s; r += 64) w[a * s + r] -= M[r * s + kk] * wk;
+            }
+            for (int q = kk + 1 + lane; q < s; q += 64) {
+                const FT pq = M[kk * s + q];
+                for (int r0 = kk + 1; r0 < s; r0 += 8) {
+                    FT mb[8], mx[8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int idx = min(base + u * 64, nb - 1);
-                        const int rr = db.quot(idx);
-                        const int r = kk + 1 + rr, q = kk + 1 + idx - rr * below;
-                        o[u] = r * s + q;
-                        a[u] = M[o[u]];
-                        b[u] = M[r * s + kk];
-                        c[u] = M[kk * s + q];
+                    for (int u = 0; u < 8; ++u) {
+                        const int r = min(r0 + u, s - 1);
+                        mb[u] = M[r * s + kk];
+                        mx[u] = M[r * s + q];
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (base + u * 64 < nb) M[o[u]] = a[u] - b[u] * c[u];
+                    for (int u = 0; u < 8; ++u)
+                        if (r0 + u < s) M[(r0 + u) * s + q] = mx[u] - mb[u] * pq;
                 }
             }
             __syncthreads();
@@ -1645,25 +1717,38 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
             __syncthreads();
             continue;
         }
-        // back substitution, column oriented for each right-hand side
+        // back substitution, column oriented for each right-hand side: z_kk
+        // (every lane forms the same quotient), then the rows above
         for (int kk = s - 1; kk >= 0; --kk) {
-            const int rows = kk + 1;
-            const SmallDiv dr(rows);
-            for (int idx = lane; idx < k * rows; idx += 64) {
-                const int a = dr.quot(idx), r = idx - a * rows;
+            for (int a = 0; a < k; ++a) {
                 const FT zk = w[a * s + kk] / M[kk * s + kk];
-                if (r == kk) z[a * s + kk] = (double)zk;
-                else w[a * s + r] -= M[r * s + kk] * zk;
+                if (lane == 0) z[a * s + kk] = (double)zk;
+                for (int r = lane; r < kk; r += 64) w[a * s + r] -= M[r * s + kk] * zk;
             }
             __syncthreads();
         }
         if (MIXED) {
-            // one refinement per right-hand side in double (as wave_solve)
-            for (int idx = lane; idx < k * s; idx += 64) {
-                const int a = ds.quot(idx), p = idx - a * s;
-                double acc = f[a * s + p];
-                for (int q = s - 1; q >= 0; --q) acc -= Md[p * s + q] * z[a * s + q];
-                f[a * s + p] = acc;
+            // one refinement per right-hand side in double (as wave_solve):
+            // each residual entry summed over the columns from the last down,
+            // a lane's entries eight side by side
+            for (int base = lane; base < k * s; base += 8 * 64) {
+                double acc[8];
+                int bm[8], bz[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = min(base + u * 64, k * s - 1);
+                    const int a = ds.quot(idx), p = idx - a * s;
+                    bm[u] = p * s;
+                    bz[u] = a * s;
+                    acc[u] = f[idx];
+                }
+                for (int q = s - 1; q >= 0; --q) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[u] -= Md[bm[u] + q] * z[bz[u] + q];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (base + u * 64 < k * s) f[base + u * 64] = acc[u];
             }
             __syncthreads();
             for (int idx = lane; idx < k * s; idx += 64) {
@@ -1672,24 +1757,18 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
             }
             __syncthreads();
             for (int kk = 0; kk < s; ++kk) {
-                const int below = s - kk - 1;
-                if (below > 0) {
-                    const SmallDiv db(below);
-                    for (int idx = lane; idx < k * below; idx += 64) {
-                        const int a = db.quot(idx), r = kk + 1 + idx - a * below;
-                        w[a * s + r] -= M[r * s + kk] * w[a * s + kk];
-                    }
+                for (int a = 0; a < k; ++a) {
+                    const FT wk = w[a * s + kk];
+                    for (int r = kk + 1 + lane; r < s; r += 64)
+                        w[a * s + r] -= M[r * s + kk] * wk;
                 }
                 __syncthreads();
             }
             for (int kk = s - 1; kk >= 0; --kk) {
-                const int rows = kk + 1;
-                const SmallDiv dr(rows);
-                for (int idx = lane; idx < k * rows; idx += 64) {
-                    const int a = dr.quot(idx), r = idx - a * rows;
+                for (int a = 0; a < k; ++a) {
                     const FT zk = w[a * s + kk] / M[kk * s + kk];
-                    if (r == kk) z[a * s + kk] += (double)zk;
-                    else w[a * s + r] -= M[r * s + kk] * zk;
+                    if (lane == 0) z[a * s + kk] += (double)zk;
+                    for (int r = lane; r < kk; r += 64) w[a * s + r] -= M[r * s + kk] * zk;
                 }
                 __syncthreads();
             }
@@ -1710,84 +1789,6 @@ k_local_node(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *nptr
             r_v[o] = 1.0;
         }
         __syncthreads();
-    }
-}
-
-// Fixed-length binary searches over a sorted int array of at most 128
-// entries: no data-dependent trip count, so a lane's searches for several
-// keys proceed side by side.  Entries of a[0..n) below key, and at or below.
-__device__ __forceinline__ int count_below(const int32_t *a, int n, int key) {
-    int p = 0;
-    if (n <= 0) return 0;
-#pragma unroll
-    for (int step = 64; step > 0; step >>= 1) {
-        const int t = p + step;
-        const int x = a[min(t, n) - 1];
-        if (t <= n && x < key) p = t;
-    }
-    return p;
-}
-__device__ __forceinline__ int count_upto(const int32_t *a, int n, int key) {
-    int p = 0;
-    if (n <= 0) return 0;
-#pragma unroll
-    for (int step = 64; step > 0; step >>= 1) {
-        const int t = p + step;
-        const int x = a[min(t, n) - 1];
-        if (t <= n && x <= key) p = t;
-    }
-    return p;
-}
-
-// The gather of gather_local for one wave and systems up to 128 rows:
-// M[k][q] = a(l_q, l_k) (row stride ldm).  Each entry's row in the flat
-// range and its column's place in N come from fixed-length searches, so the
-// U entries of a lane are found side by side instead of one walk after
-// another.
-template <int U>
-__device__ __forceinline__ void gather_wave(int lane, int s, const int32_t *ln, int32_t *off,
-                                            int32_t *st, const int32_t *rp, const int32_t *cj,
-                                            const double *v, double *M, int ldm) {
-    int carry = 0;
-    for (int q0 = 0; q0 < s; q0 += 64) {
-        const int q = q0 + lane;
-        int a = 0, len = 0;
-        if (q < s) {
-            const int r = ln[q];
-            a = rp[r];
-            len = rp[r + 1] - a;
-        }
-        const int incl = team_scan_incl<64>(len);
-        if (q < s) {
-            st[q] = a;
-            off[q] = carry + incl - len;
-        }
-        carry += __shfl(incl, 63);
-    }
-    if (lane == 0) off[s] = carry;
-    __syncthreads();
-    const int E = carry;
-    for (int base = lane; base < E; base += U * 64) {
-        int qq[U], e[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int idx = min(base + u * 64, E - 1);
-            qq[u] = count_upto(off + 1, s - 1, idx);     // off[qq] <= idx < off[qq + 1]
-            e[u] = st[qq[u]] + idx - off[qq[u]];
-        }
-        int col[U];
-        double val[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            col[u] = cj[e[u]];
-            val[u] = v[e[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kp = count_below(ln, s, col[u]);
-            if (base + u * 64 < E && kp < s && ln[kp] == col[u])
-                M[(size_t)kp * ldm + qq[u]] = val[u];
-        }
     }
 }
 
@@ -1857,7 +1858,7 @@ k_local_node_reg(int32_t nnode, int32_t k, const int32_t *clist, const int32_t *
         for (int idx = lane; idx < k * s; idx += 64) f[idx] = 0.0;
         for (int p = lane; p < s; p += 64) ln[p] = l[p];
         __syncthreads();
-        gather_wave<8>(lane, s, ln, off, st, rp, cj, v, Mg, s);
+        gather_wave<8, double>(lane, s, ln, off, st, rp, cj, v, Mg, s, nullptr);
         for (int a = 0; a < k; ++a)
             for (int e = rp[i0 + a] + lane; e < rp[i0 + a + 1]; e += 64) {
                 int p = bsearch_i32(ln, s, cj[e]);
