@@ -6,9 +6,11 @@ neighbourhoods, fallback flags and the R, P and K patterns bit-exact; each
 row of Z within 1e-12 of its largest entry; K within 1e-12 of the scale of
 the terms summed; the same number of cycles to 1e-10 and the solution
 within 1e-8.  Cases: a Kronecker product ADR (x) B (k = 3), a perturbed
-dense-block matrix (k = 2), P2 upwind DG along a curved field (k = 6), and
-the DGu problem of Sec. 4.2 (gamma jump, interior-penalty diffusion kappa
-in {0, 1e-3, 1}; k = 6).
+dense-block matrix (k = 2), P2 upwind DG along a curved field (k = 6), the
+DGu problem of Sec. 4.2 (gamma jump, interior-penalty diffusion kappa in
+{0, 1e-3, 1}; k = 6; on 24 x 24 x 2 triangles its systems pass 72 rows),
+and a random sparse graph (x) 3 x 3 blocks whose distance-2 systems pass
+128 rows.
 """
 import sys
 
@@ -64,6 +66,15 @@ def _case(name):
         A.sort_indices()
         A.data = A.data * (1.0 + 0.3 * rng.standard_normal(A.nnz))
         return A, np.kron(bs, [1.0, 1.0]), 2
+    if name == "rand8k3":
+        # a random sparse graph (8 couplings per row) (x) 3 x 3 blocks: at
+        # distance 2 the first level's systems reach 141 rows
+        As = W.random_ff_digraph(300, 8, seed=1)
+        As = O.csr(As["rowptr"], As["col"], As["val"])
+        B = np.random.default_rng(0).standard_normal((3, 3)) + 3.0 * np.eye(3)
+        A = sp.kron(As, sp.csr_matrix(B)).tocsr()
+        A.sort_indices()
+        return A, np.kron(np.ones(300), [1.0, -1.0, 0.5]), 3
     if name == "dgu24":
         # 24 x 24 x 2 triangles, kappa 1e-3: at distance 2 level 1 holds
         # systems of up to 78 rows, past the register form's 72
@@ -137,7 +148,7 @@ def test_nodal_levels_and_iterations(lair, name, own_split):
 
 
 @pytest.mark.parametrize("name", ["perturbed2", "dg_curved", "dgu0", "dgu0.001", "dgu1",
-                                  "dgu24"])
+                                  "dgu24", "rand8k3"])
 def test_nodal_distance_two(lair, name):
     """F-F-C paths on the graph of blocks: the node-expanded strength mask
     makes the scalar distance-two merge give the nodal sets."""
@@ -223,7 +234,8 @@ def test_nodal_argument_errors(lair):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name,distance", [("kron3", 1), ("dg_curved", 1), ("dg_curved", 2),
-                                           ("perturbed2", 2), ("dgu0.001", 2), ("dgu24", 2)])
+                                           ("perturbed2", 2), ("dgu0.001", 2), ("dgu24", 2),
+                                           ("rand8k3", 2)])
 def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precision):
     """The nodal local systems of a C-node (one matrix A(N,N)^T, one
     right-hand side per row of the node; Sec. 3.1, block form of
@@ -253,6 +265,8 @@ def test_node_solves_equal_row_solves(lair, monkeypatch, name, distance, precisi
              {c: (round(v["ms"], 3), v["launches"]) for c, v in prof.items()})
         if name == "dgu24":
             assert smax > 72        # the LDS form takes the largest systems
+        if name == "rand8k3":
+            assert smax > 128       # past the searches' first power of two
         if mode == "rows":
             assert "local_node" not in prof
         else:
