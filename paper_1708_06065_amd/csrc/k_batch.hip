@@ -4,6 +4,7 @@
 //
 // Segments: system s owns rows [seg[s], seg[s+1]) of a level; seg has
 // nsys + 1 entries (int64).  The system of a row is found by binary search.
+#include <algorithm>
 #include <cmath>
 
 #include "k_common.hpp"
@@ -154,21 +155,22 @@ int32_t relax_list(int32_t nsys, const int64_t *seg, const uint8_t *stopped,
 // it and copies `len` consecutive entries of list `lst[j]`'s source from
 // seg_src[j] (or the row ids themselves when that list has no source) to
 // its output at seg_dst[j].  No atomics: every position has one writer.
-__global__ void k_materialize(int32_t nseg, const int64_t *seg_out, const int32_t *seg_src,
-                              const int32_t *seg_dst, const int32_t *lst,
-                              const int32_t *const *srcs, int32_t *const *dsts) {
-    const int64_t total = seg_out[nseg];
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (seg_out[mid] <= k) lo = mid; else hi = mid - 1;
+__global__ void __launch_bounds__(256)
+k_materialize(int32_t nseg, const int64_t *seg_out, const int32_t *seg_src,
+              const int32_t *seg_dst, const int32_t *lst, const int32_t *const *srcs,
+              int32_t *const *dsts) {
+    // one block per segment (grid-stride over segments): a straight copy of
+    // its run, coalesced, with no search per entry
+    for (int32_t g = blockIdx.x; g < nseg; g += gridDim.x) {
+        const int64_t len = seg_out[g + 1] - seg_out[g];
+        const int32_t *src = srcs[lst[g]];
+        int32_t *dst = dsts[lst[g]] + seg_dst[g];
+        const int32_t s0 = seg_src[g];
+        if (src) {
+            for (int64_t o = threadIdx.x; o < len; o += blockDim.x) dst[o] = src[s0 + o];
+        } else {
+            for (int64_t o = threadIdx.x; o < len; o += blockDim.x) dst[o] = s0 + (int32_t)o;
         }
-        const int32_t off = (int32_t)(k - seg_out[lo]);
-        const int32_t *src = srcs[lst[lo]];
-        const int32_t v = src ? src[seg_src[lo] + off] : seg_src[lo] + off;
-        dsts[lst[lo]][seg_dst[lo] + off] = v;
     }
 }
 
@@ -176,8 +178,7 @@ void launch_materialize(int32_t nseg, int64_t total, const int64_t *seg_out,
                         const int32_t *seg_src, const int32_t *seg_dst, const int32_t *lst,
                         const int32_t *const *srcs, int32_t *const *dsts, hipStream_t s) {
     if (nseg == 0 || total == 0) return;
-    const int64_t b = (total + 255) / 256;
-    LAIR_LAUNCH(k_materialize, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, nseg,
+    LAIR_LAUNCH(k_materialize, dim3((unsigned)std::min(nseg, 8192)), dim3(256), 0, s, nseg,
                 seg_out, seg_src, seg_dst, lst, srcs, dsts);
     LAIR_LAUNCH_CHECK();
 }
