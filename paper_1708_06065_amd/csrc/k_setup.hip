@@ -624,17 +624,21 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
                       const int32_t *cj, const uint8_t *sm, const int8_t *cf,
                       int32_t distance, const int32_t *flist, int32_t nf,
                       bool fill, int32_t *cnt, const int32_t *nptr,
-                      int32_t *nbr, int32_t *overflow) {
+                      int32_t *nbr, int32_t *overflow, int32_t knode) {
+    // knode > 1 (nodal levels): the knode consecutive C rows of a C-node
+    // share their neighbourhood (the strength mask is node-expanded), so one
+    // team merges it once, from the node's first row, and writes it for each
     int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
-    int32_t c = (int32_t)(gt / T);
+    int32_t c = (int32_t)(gt / T) * knode;
     int lane = (int)(gt % T);
     if (c >= nc) return;
-    int32_t base = fill ? nptr[c] : 0;
     if (distance == LAIR_DIST_ALL_F) {
-        if (fill)
-            for (int q = lane; q < nf; q += T) nbr[base + q] = flist[q];
-        else if (lane == 0)
-            cnt[c] = nf;
+        for (int32_t a = 0; a < knode; ++a) {
+            if (fill)
+                for (int q = lane; q < nf; q += T) nbr[nptr[c + a] + q] = flist[q];
+            else if (lane == 0)
+                cnt[c + a] = nf;
+        }
         return;
     }
     int32_t i = clist[c];
@@ -646,10 +650,12 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
             bool q = (p < hi) && nbr_ok(sm, cf, cj, p);
             uint64_t bits = team_bits<T>(q);
             int before = __popcll(bits & ((1ull << lane) - 1ull));
-            if (fill && q) nbr[base + o + before] = cj[p];
+            if (fill && q)
+                for (int32_t a = 0; a < knode; ++a) nbr[nptr[c + a] + o + before] = cj[p];
             o += __popcll(bits);
         }
-        if (!fill && lane == 0) cnt[c] = o;
+        if (!fill && lane == 0)
+            for (int32_t a = 0; a < knode; ++a) cnt[c + a] = o;
         return;
     }
     // distance 2: assign lists to (lane, slot)
@@ -676,7 +682,8 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
     }
     if (k > T * NBR_LPL) {
         if (lane == 0) atomicOr(overflow, 1);
-        if (!fill && lane == 0) cnt[c] = 0;
+        if (!fill && lane == 0)
+            for (int32_t a = 0; a < knode; ++a) cnt[c + a] = 0;
         return;
     }
     (void)over;
@@ -685,6 +692,8 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
         while (pos[m] < end[m] && !nbr_ok(sm, cf, cj, pos[m])) ++pos[m];
         head[m] = (pos[m] < end[m]) ? cj[pos[m]] : INT_MAX;
     }
+    // lanes a < knode write copy a of each merged entry
+    const int32_t base = (fill && lane < knode) ? nptr[c + lane] : 0;
     int o = 0;
     for (;;) {
         int h = INT_MAX;
@@ -692,7 +701,10 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
         for (int m = 0; m < NBR_LPL; ++m) h = min(h, head[m]);
         int mn = team_min<T>(h);
         if (mn == INT_MAX) break;
-        if (fill && lane == 0) nbr[base + o] = mn;
+        if (fill) {
+            if (lane < knode) nbr[base + o] = mn;
+            for (int32_t a = T + lane; a < knode; a += T) nbr[nptr[c + a] + o] = mn;
+        }
         ++o;
 #pragma unroll
         for (int m = 0; m < NBR_LPL; ++m) {
@@ -703,7 +715,8 @@ __global__ void k_nbr(int32_t nc, const int32_t *clist, const int32_t *rp,
             }
         }
     }
-    if (!fill && lane == 0) cnt[c] = o;
+    if (!fill && lane == 0)
+        for (int32_t a = 0; a < knode; ++a) cnt[c + a] = o;
 }
 
 template <int T>
@@ -711,10 +724,10 @@ static void nbr_t(int32_t nc, const int32_t *clist, const int32_t *rp,
                   const int32_t *cj, const uint8_t *sm, const int8_t *cf,
                   int32_t distance, const int32_t *flist, int32_t nf, bool fill,
                   int32_t *cnt, const int32_t *nptr, int32_t *nbr,
-                  int32_t *overflow, hipStream_t s) {
-    LAIR_LAUNCH(k_nbr<T>, dim3(blocks_for((int64_t)nc * T, 256)), dim3(256),
+                  int32_t *overflow, int32_t knode, hipStream_t s) {
+    LAIR_LAUNCH(k_nbr<T>, dim3(blocks_for((int64_t)(nc / knode) * T, 256)), dim3(256),
                        0, s, nc, clist, rp, cj, sm, cf, distance, flist, nf, fill,
-                       cnt, nptr, nbr, overflow);
+                       cnt, nptr, nbr, overflow, knode);
     LAIR_LAUNCH_CHECK();
 }
 
@@ -724,9 +737,11 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
                            int32_t distance, const int32_t *flist, int32_t nf,
                            int32_t *cnt, const int32_t *nptr, int32_t *nbr,
                            int32_t *overflow, int32_t max_row,
-                           hipStream_t s) {
+                           hipStream_t s, int32_t knode) {
     (void)n;
     if (nc == 0) return;
+    if (knode < 1 || nc % knode != 0)
+        fail(LAIR_EINVAL, "neighbourhoods: %d C rows in nodes of %d", nc, knode);
     bool fill = (nbr != nullptr);
     ProfScope ps("nbr", s, 4.0 * nc);
     int t;
@@ -739,12 +754,12 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
         if (t > 16 && distance == 1) t = 16;
     }
     switch (t) {
-        case 2: nbr_t<2>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
-        case 4: nbr_t<4>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
-        case 8: nbr_t<8>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
-        case 16: nbr_t<16>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
-        case 32: nbr_t<32>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
-        default: nbr_t<64>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, s); break;
+        case 2: nbr_t<2>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, knode, s); break;
+        case 4: nbr_t<4>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, knode, s); break;
+        case 8: nbr_t<8>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, knode, s); break;
+        case 16: nbr_t<16>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, knode, s); break;
+        case 32: nbr_t<32>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, knode, s); break;
+        default: nbr_t<64>(nc, clist, rp, cj, smask, cf, distance, flist, nf, fill, cnt, nptr, nbr, overflow, knode, s); break;
     }
 }
 

@@ -256,7 +256,7 @@ void launch_neighbourhoods(int32_t nc, int32_t n, const int32_t *clist,
                            int32_t distance, const int32_t *flist, int32_t nf,
                            int32_t *cnt, const int32_t *nptr, int32_t *nbr,
                            int32_t *overflow, int32_t max_row_strong,
-                           hipStream_t s);
+                           hipStream_t s, int32_t knode = 1);
 struct LocalSolveOut {
     int32_t *r_rp, *r_cj;
     double *r_v;

@@ -642,9 +642,11 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     // neighbourhoods
     DevArr<int32_t> cnt;
     cnt.alloc((size_t)Lv.nc + 1, s);
+    // nodal levels: the rows of a C-node share one neighbourhood, merged once
+    const int32_t knbr = nodal(h->opt) ? h->opt.block_size : 1;
     launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, cnt.get(),
-                          nullptr, nullptr, over.get(), Lv.max_row, s);
+                          nullptr, nullptr, over.get(), Lv.max_row, s, knbr);
     Lv.nptr.alloc((size_t)Lv.nc + 1, s);
     // distance 1: N_i lies in row i without i, so the C rows' lengths bound
     // the lists' total and the longest row bounds each list; when that bound
@@ -667,7 +669,7 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
     Lv.nbr.alloc((size_t)std::max<int64_t>(nn, 1), s);
     launch_neighbourhoods(Lv.nc, n, Lv.clist.get(), A.rp.get(), A.cj.get(), Lv.smask.get(),
                           Lv.cf.get(), h->str.distance, Lv.flist.get(), Lv.nf, nullptr,
-                          Lv.nptr.get(), Lv.nbr.get(), over.get(), Lv.max_row, s);
+                          Lv.nptr.get(), Lv.nbr.get(), over.get(), Lv.max_row, s, knbr);
     Lv.st.s_max = (int32_t)smax64;
     Lv.st.s_mean = Lv.nc ? (double)nn / Lv.nc : 0.0;
     Lv.st.s_min = -1;   // filled on demand by lair_level_stats_get
