@@ -26,17 +26,34 @@ __device__ __forceinline__ VT src_val(const VT *xF, const VT *xC, const int8_t *
 }
 
 // One right-hand side, a team of T lanes per row (lanes take every T-th
-// entry of the row).
+// entry of the row).  A lane loads four of its entries, then their four
+// gathers, before it sums them in entry order, so the loads of a row are in
+// flight together (the sums are those of the plain loop).
 template <class VT, int T, bool SEL>
 __device__ __forceinline__ void row_acc1(int lo, int hi, int lane, int diag_col,
                                          const int32_t *cj, const VT *v,
                                          const VT *xF, const VT *xC,
                                          const int8_t *cf, VT &acc, VT &d) {
-    for (int p = lo + lane; p < hi; p += T) {
-        int c = cj[p];
-        VT a = v[p];
-        acc += a * src_val<VT, SEL>(xF, xC, cf, c, c);
-        if (c == diag_col) d = a;
+    constexpr int U = 4;
+    for (int p0 = lo + lane; p0 < hi; p0 += U * T) {
+        int c[U];
+        VT a[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u * T;
+            c[u] = p < hi ? cj[p] : -1;
+            a[u] = p < hi ? v[p] : (VT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            xv[u] = c[u] >= 0 ? src_val<VT, SEL>(xF, xC, cf, c[u], c[u]) : (VT)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c[u] >= 0) {
+                acc += a[u] * xv[u];
+                if (c[u] == diag_col) d = a[u];
+            }
+        }
     }
 }
 
