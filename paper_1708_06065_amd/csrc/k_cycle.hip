@@ -315,7 +315,7 @@ static inline int vec_unroll(int nrhs, int T, int team) {
 // grid-stride over a fixed grid), written as r64 and/or r32, and each
 // block's sum of r^2 per right-hand side into partial[block][nrhs]
 // (fixed order: thread sums, then a fixed walk over the block's threads).
-template <int NR, int VW, bool OUT64, bool OUT32>
+template <int NR, int VW, bool OUT64, bool OUT32, int U>
 __global__ void __launch_bounds__(256)
 k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const double *v,
              const double *x, const double *b, double *r64, float *r32, double *partial,
@@ -342,7 +342,7 @@ k_resid_norm(int32_t nrows, int T, const int32_t *rp, const int32_t *cj, const d
         acc.zero();
         double d = 0.0;
         // the matrix and b are streamed (read once), x is gathered
-        row_accV<double, NR, VW, false, false, 1, true>(ld_stream(rp + i), ld_stream(rp + i + 1),
+        row_accV<double, NR, VW, false, false, U, true>(ld_stream(rp + i), ld_stream(rp + i + 1),
                                                         t, T, -1, cj, v, x, x, nullptr, acc, d);
         if (t < L) {
             const int64_t o = i * NR + t * VW;
@@ -955,15 +955,22 @@ template <int NR, int VW>
 static void resid_norm_t(const CsrView<double> &A, const double *b, const double *x,
                          double *r64, float *r32, double *partial, unsigned grid, int T,
                          hipStream_t s, const int32_t *orow) {
-    if (r64 && r32)
-        LAIR_LAUNCH((k_resid_norm<NR, VW, true, true>), dim3(grid), dim3(256), 0, s,
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);
-    else if (r64)
-        LAIR_LAUNCH((k_resid_norm<NR, VW, true, false>), dim3(grid), dim3(256), 0, s,
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);
-    else
-        LAIR_LAUNCH((k_resid_norm<NR, VW, false, true>), dim3(grid), dim3(256), 0, s,
-                           A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);
+    // two steps of a row's gathers in flight where a row needs more than one
+    // (the sums keep their order)
+    const bool u2 = vec_unroll<double>(NR, T, A.team) == 2;
+#define LAIR_RN(O64, O32)                                                                  \
+    {                                                                                      \
+        if (u2)                                                                            \
+            LAIR_LAUNCH((k_resid_norm<NR, VW, O64, O32, 2>), dim3(grid), dim3(256), 0, s,  \
+                        A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);       \
+        else                                                                               \
+            LAIR_LAUNCH((k_resid_norm<NR, VW, O64, O32, 1>), dim3(grid), dim3(256), 0, s,  \
+                        A.nrows, T, A.rp, A.cj, A.v, x, b, r64, r32, partial, orow);       \
+    }
+    if (r64 && r32) LAIR_RN(true, true)
+    else if (r64) LAIR_RN(true, false)
+    else LAIR_RN(false, true)
+#undef LAIR_RN
     LAIR_LAUNCH_CHECK();
 }
 
