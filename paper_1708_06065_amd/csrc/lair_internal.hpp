@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -127,6 +128,12 @@ struct Readback {
     std::vector<std::pair<const void *, size_t>> src;
     size_t used = 0;
 };
+// Install (or, with null, remove) a hook that every Readback::run of this
+// host thread calls after queueing its copies and before waiting for them:
+// the hook may queue work on the readback's stream that does not feed the
+// values read back, and the wait then covers the readback alone.  Returns
+// the hook it replaces.
+const std::function<void()> *set_readback_fill(const std::function<void()> *fill);
 // pinned host staging buffer of at least `bytes` (reused; per host thread)
 // A second pinned host buffer for host-to-device uploads that stay in
 // flight across later readbacks (the readback buffer is pinned_staging).
@@ -159,6 +166,8 @@ struct ProfScope {
 };
 // true while profiling is on and `category` is selected
 bool prof_selected(const char *category);
+// true while profiling is on
+bool prof_active();
 // Replace the algorithmic bytes of a closed scope's record (slot from
 // ProfScope::slot; ignored when negative or profiling has restarted), for
 // sizes that reach the host only after the scope's launches.

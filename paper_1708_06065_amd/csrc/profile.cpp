@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -196,6 +197,45 @@ void *gather_buffer() {
 }
 }  // namespace
 
+namespace {
+thread_local const std::function<void()> *t_fill = nullptr;
+hipEvent_t readback_event() {
+    thread_local hipEvent_t e = nullptr;
+    if (!e) LAIR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return e;
+}
+// Wait for everything queued on s so far.  With a fill hook installed, the
+// hook first queues independent work behind the readback, which the device
+// runs while this thread waits for the readback alone (an event recorded
+// before the hook's work).
+void wait_readback(hipStream_t s) {
+    if (t_fill && *t_fill) {
+        hipEvent_t e = readback_event();
+        LAIR_HIP(hipEventRecord(e, s));
+        const std::function<void()> *f = t_fill;
+        t_fill = nullptr;                    // no hook inside the hook
+        try {
+            (*f)();
+        } catch (...) {
+            t_fill = f;
+            throw;
+        }
+        t_fill = f;
+        LAIR_HIP(hipEventSynchronize(e));
+        return;
+    }
+    LAIR_HIP(hipStreamSynchronize(s));
+}
+}  // namespace
+
+const std::function<void()> *set_readback_fill(const std::function<void()> *fill) {
+    const std::function<void()> *prev = t_fill;
+    t_fill = fill;
+    return prev;
+}
+
+bool prof_active() { return prof().on; }
+
 void Readback::run() {
     bool small = src.size() <= (size_t)GATHER_MAX && used <= GATHER_BYTES;
     for (size_t k = 0; k < src.size() && small; ++k)
@@ -212,7 +252,7 @@ void Readback::run() {
         // (not a profiled operation: launched without the profiler's events)
         hipLaunchKernelGGL(k_gather_host, dim3(1), dim3(256), 0, stream, a, (uint32_t *)stage);
         LAIR_LAUNCH_CHECK();
-        LAIR_HIP(hipStreamSynchronize(stream));
+        wait_readback(stream);
         for (size_t k = 0; k < src.size(); ++k)
             memcpy(dst[k].first, stage + dst[k].second, src[k].second);
         dst.clear();
@@ -224,7 +264,7 @@ void Readback::run() {
     for (size_t k = 0; k < src.size(); ++k)
         LAIR_HIP(hipMemcpyAsync(stage + dst[k].second, src[k].first, src[k].second,
                                 hipMemcpyDeviceToHost, stream));
-    LAIR_HIP(hipStreamSynchronize(stream));
+    wait_readback(stream);
     for (size_t k = 0; k < src.size(); ++k)
         memcpy(dst[k].first, stage + dst[k].second, src[k].second);
     dst.clear();

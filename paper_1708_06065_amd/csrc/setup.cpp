@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -928,23 +930,29 @@ static void level_stats_and_cc(lair_hierarchy *h) {
 // float values only.
 constexpr int32_t SPLIT_MIN_ROWS = 65536;
 
-static void build_split(lair_hierarchy *h, hipStream_t s) {
-    const size_t nL = h->L.size();
-    const bool mixed = h->opt.precision == LAIR_MIXED;
-    const bool allowed = h->nsys == 1 && nL > 1 && !(h->opt.flags & LAIR_FLAG_NATURAL_ORDER) &&
-                         !nodal(h->opt);
-    const bool all = (h->opt.flags & LAIR_FLAG_SPLIT_ALL) != 0;
-    bool prev = allowed;
-    for (size_t l = 0; l < nL; ++l) {
-        Level &Lv = *h->L[l];
-        const bool big = Lv.n >= SPLIT_MIN_ROWS;
-        Lv.split = prev && l + 1 < nL && (all || big);
-        prev = Lv.split;
-    }
+// The work level by level: whether level l is renumbered (decide, once the
+// level is known not to be the coarsest), its permutation and its copy of A
+// (once its splitting exists), and its copies of R and P (once the next
+// level is decided and permuted).
+struct SplitCopies {
+    lair_hierarchy *h;
+    hipStream_t s;
+    bool mixed, allowed, all;
     DevArr<int64_t> tmp;
-    for (size_t l = 0; l + 1 < nL; ++l) {
+    SplitCopies(lair_hierarchy *h_, hipStream_t s_) : h(h_), s(s_) {
+        mixed = h->opt.precision == LAIR_MIXED;
+        allowed = h->nsys == 1 && !(h->opt.flags & LAIR_FLAG_NATURAL_ORDER) && !nodal(h->opt);
+        all = (h->opt.flags & LAIR_FLAG_SPLIT_ALL) != 0;
+    }
+    // renumbered levels form a prefix of the hierarchy, the coarsest excluded
+    void decide(size_t l, bool coarsest) {
         Level &Lv = *h->L[l];
-        if (!Lv.split) continue;
+        const bool prev = l == 0 ? allowed : h->L[l - 1]->split;
+        Lv.split = prev && !coarsest && (all || Lv.n >= SPLIT_MIN_ROWS);
+    }
+    void perm(size_t l) {
+        Level &Lv = *h->L[l];
+        if (!Lv.split) return;
         const size_t n = (size_t)std::max(Lv.n, 1);
         Lv.perm.alloc(n, s);
         Lv.iperm.alloc(n, s);
@@ -953,8 +961,8 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
         launch_split_perm(Lv.nf, Lv.nc, Lv.flist.get(), Lv.clist.get(), Lv.perm.get(),
                           Lv.iperm.get(), Lv.ids.get(), Lv.cf_split.get(), s);
     }
-    auto copy = [&](const DevCSR &M, DevCSR &O, const int32_t *rowmap, const int32_t *irowmap,
-                    const int32_t *colmap, DevArr<int32_t> *cjt, int32_t nsplit) {
+    void copy(const DevCSR &M, DevCSR &O, const int32_t *rowmap, const int32_t *irowmap,
+              const int32_t *colmap, DevArr<int32_t> *cjt, int32_t nsplit) {
         O.nrows = M.nrows;
         O.ncols = M.ncols;
         O.nnz = M.nnz;
@@ -970,25 +978,29 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
                            O.cj.get(),
                            mixed ? nullptr : O.v.get(), mixed ? O.v32.get() : nullptr,
                            cjt ? cjt->get() : nullptr, nsplit, tmp, s);
-    };
-    auto drop = [](DevCSR &O) {
+    }
+    static void drop(DevCSR &O) {
         O.rp.release(); O.cj.release(); O.v.release(); O.v32.release();
         O.nrows = O.ncols = 0; O.nnz = 0;
-    };
-    for (size_t l = 0; l + 1 < nL; ++l) {
+    }
+    void copy_A(size_t l) {
         Level &Lv = *h->L[l];
-        Level &Nx = *h->L[l + 1];
-        const int32_t *perm = Lv.split ? Lv.perm.get() : nullptr;
-        const int32_t *iperm = Lv.split ? Lv.iperm.get() : nullptr;
-        const int32_t *nperm = Nx.split ? Nx.perm.get() : nullptr;
-        const int32_t *niperm = Nx.split ? Nx.iperm.get() : nullptr;
         if (Lv.split) {
-            copy(Lv.A, Lv.As, perm, iperm, iperm, &Lv.cjt_split, Lv.nf);
+            copy(Lv.A, Lv.As, Lv.perm.get(), Lv.iperm.get(), Lv.iperm.get(), &Lv.cjt_split,
+                 Lv.nf);
         } else {
             drop(Lv.As);
             Lv.cjt_split.release();
         }
+    }
+    void copy_RP(size_t l) {
+        Level &Lv = *h->L[l];
+        Level &Nx = *h->L[l + 1];
         if (Lv.split || Nx.split) {
+            const int32_t *perm = Lv.split ? Lv.perm.get() : nullptr;
+            const int32_t *iperm = Lv.split ? Lv.iperm.get() : nullptr;
+            const int32_t *nperm = Nx.split ? Nx.perm.get() : nullptr;
+            const int32_t *niperm = Nx.split ? Nx.iperm.get() : nullptr;
             copy(Lv.R, Lv.Rs, nperm, niperm, iperm, nullptr, 0);
             copy(Lv.P, Lv.Ps, perm, iperm, niperm, nullptr, 0);
         } else {
@@ -996,13 +1008,25 @@ static void build_split(lair_hierarchy *h, hipStream_t s) {
             drop(Lv.Ps);
         }
     }
+};
+
+// Every level at once (a hierarchy whose values have changed).
+static void build_split(lair_hierarchy *h, hipStream_t s) {
+    const size_t nL = h->L.size();
+    SplitCopies sc(h, s);
+    for (size_t l = 0; l < nL; ++l) sc.decide(l, l + 1 == nL);
+    for (size_t l = 0; l + 1 < nL; ++l) sc.perm(l);
+    for (size_t l = 0; l + 1 < nL; ++l) {
+        sc.copy_A(l);
+        sc.copy_RP(l);
+    }
 }
 
 // After the values of a hierarchy are set: split-ordered copies, the tagged
 // columns and float values of whatever the cycle reads in the natural
 // ordering.
-static void finish_cycle_operators(lair_hierarchy *h, hipStream_t s) {
-    build_split(h, s);
+static void finish_cycle_operators(lair_hierarchy *h, hipStream_t s, bool split_built = false) {
+    if (!split_built) build_split(h, s);
     const bool mixed = h->opt.precision == LAIR_MIXED;
     if (nodal(h->opt)) {
         // block Jacobi: D^{-1} of every level's diagonal blocks and the
@@ -1218,6 +1242,23 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
     // products per distinct column of A P and of R (A P) on the level above:
     // the next level's hash tables are sized from them
     double ap_ratio = 0.0, k_ratio = 0.0;
+    // The split-ordered copies of a level wait in a queue once their inputs
+    // exist; every readback of the levels below takes one item and queues its
+    // kernels behind the readback, so the device copies while the host waits
+    // for the sizes (not while profiling: the profiler times categories
+    // launch by launch).
+    SplitCopies sc(h.get(), s);
+    std::deque<std::function<void()>> fillq;
+    const std::function<void()> fill = [&fillq]() {
+        if (fillq.empty()) return;
+        std::function<void()> f = std::move(fillq.front());
+        fillq.pop_front();
+        f();
+    };
+    struct FillGuard {
+        const std::function<void()> *prev;
+        ~FillGuard() { set_readback_fill(prev); }
+    } fill_guard{set_readback_fill(prof_active() ? nullptr : &fill)};
     for (int32_t lvl = 0;; ++lvl) {
         Level &Lv = *h->L.back();
         if (h->nsys == 1) {
@@ -1241,6 +1282,14 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         build_level_transfer(h.get(), Lv, lvl, cfl, coarsest, tmp, ap_st);
         h->phase_mark(2);
         if (coarsest) break;
+        // level lvl is not the coarsest: its permutation and copy of A, then
+        // the copies of the transfer operators of the level above it
+        sc.decide((size_t)lvl, false);
+        fillq.push_back([&sc, lvl] {
+            sc.perm((size_t)lvl);
+            sc.copy_A((size_t)lvl);
+        });
+        if (lvl > 0) fillq.push_back([&sc, lvl] { sc.copy_RP((size_t)lvl - 1); });
         // Galerkin product K = R (A P): the sizes of A P reach the host with
         // the count of products of R (A P)
         // A P stays in the product's staging arrays (rows at their product
@@ -1285,6 +1334,14 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
     }
     h->phase_mark(h->L.size() == 1 ? 0 : 3);
     finish_coarsest(h.get());
+    // what the readbacks have not taken
+    set_readback_fill(fill_guard.prev);
+    while (!fillq.empty()) fill();
+    {
+        const size_t nL = h->L.size();
+        sc.decide(nL - 1, true);
+        if (nL >= 2) sc.copy_RP(nL - 2);
+    }
     h->phase_mark(4);
     for (auto &lp : h->L) {
         Level &Lv = *lp;
@@ -1292,7 +1349,7 @@ lair_hierarchy *setup_impl(const lair_csr *Ain, const lair_cf_levels *cfl,
         Lv.team_R = team_of(Lv.R);
         Lv.team_P = team_of(Lv.P);
     }
-    finish_cycle_operators(h.get(), s);
+    finish_cycle_operators(h.get(), s, true);
     level_stats_and_cc(h.get());
     LAIR_HIP(hipStreamSynchronize(s));
     h->phase_mark(5);

@@ -312,9 +312,12 @@ static bool use_graphs(const lair_hierarchy *h) {
 
 static const size_t MAX_GRAPHS = 8;
 
-// Run body(stream) on s: replay its captured graph, capturing it first on
-// the hierarchy's private stream.  body must launch kernels only (no
-// allocation, no host synchronisation, no memset).
+// Run body(stream) on s: replay its captured graph.  The first iteration of
+// a kind is launched directly on s and then captured on the hierarchy's
+// private stream, so that the capture and the instantiation (host work of
+// a few hundred microseconds for a deep cycle) run while the device executes
+// that first iteration; later ones replay the graph.  body must launch
+// kernels only (no allocation, no host synchronisation, no memset).
 template <class Body>
 static void run_iteration(lair_hierarchy *h, int kind, int32_t nrhs, const void *b, void *x,
                           hipStream_t s, Body &&body) {
@@ -327,6 +330,7 @@ static void run_iteration(lair_hierarchy *h, int kind, int32_t nrhs, const void 
             LAIR_HIP(hipGraphLaunch(g.exec, s));
             return;
         }
+    body(s);
     if (!h->gstream) LAIR_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     LAIR_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
@@ -347,7 +351,6 @@ static void run_iteration(lair_hierarchy *h, int kind, int32_t nrhs, const void 
         h->graphs.erase(h->graphs.begin());
     }
     h->graphs.push_back({kind, nrhs, b, x, exec});
-    LAIR_HIP(hipGraphLaunch(exec, s));
 }
 
 static void check_solve_args(lair_hierarchy *h, const double *b, double *x, double rtol,
