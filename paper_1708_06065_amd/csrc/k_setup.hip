@@ -3182,7 +3182,7 @@ template <int HS>
 constexpr int log2_const() { return HS <= 1 ? 0 : 1 + log2_const<HS / 2>(); }
 
 template <int T, int HS, int BLOCK>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
 k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const double *ax,
               BRows bp, const int32_t *bj, const double *bx, const int64_t *eoff,
               int32_t *cnt, int32_t *tcj, double *tcx, int32_t *next, int32_t *nnext) {
@@ -3279,25 +3279,56 @@ k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const
         }
         const int64_t o = eoff[i];
         // rank of each distinct column among them (reads four at a time;
-        // lcol is 16-byte aligned, entries past n are masked)
-        for (int u = lane; u < n; u += T) {
-            const int32_t c = lcol[u];
-            auto rank4 = [&](int w) {
-                const int4 q = *reinterpret_cast<const int4 *>(lcol + w);
-                return (q.x < c) + (w + 1 < n && q.y < c) + (w + 2 < n && q.z < c) +
-                       (w + 3 < n && q.w < c);
-            };
-            int r = 0;
-            if constexpr (HC >= 64) {
-                // long lists: more reads in flight (small tables keep the
-                // registers for occupancy)
-#pragma unroll 4
-                for (int w = 0; w < n; w += 4) r += rank4(w);
-            } else {
-                for (int w = 0; w < n; w += 4) r += rank4(w);
+        // lcol is 16-byte aligned, entries past n are masked).  A lane holds
+        // at most HC / T columns; up to four of them are ranked in one pass
+        // over the list, each read compared with all of them.
+        constexpr int KR = HC / T;
+        if constexpr (KR <= 4) {
+            int cc[KR], rk[KR];
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int u = lane + k * T;
+                cc[k] = u < n ? lcol[u] : INT_MAX;
+                rk[k] = 0;
             }
-            tcj[o + r] = c;
-            tcx[o + r] = val[lslot[u]];
+            for (int w = 0; w < n; w += 4) {
+                int4 q = *reinterpret_cast<const int4 *>(lcol + w);
+                // entries past n rank below nothing
+                q.y = w + 1 < n ? q.y : INT_MAX;
+                q.z = w + 2 < n ? q.z : INT_MAX;
+                q.w = w + 3 < n ? q.w : INT_MAX;
+#pragma unroll
+                for (int k = 0; k < KR; ++k)
+                    rk[k] += (q.x < cc[k]) + (q.y < cc[k]) + (q.z < cc[k]) + (q.w < cc[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const int u = lane + k * T;
+                if (u < n) {
+                    tcj[o + rk[k]] = cc[k];
+                    tcx[o + rk[k]] = val[lslot[u]];
+                }
+            }
+        } else {
+            for (int u = lane; u < n; u += T) {
+                const int32_t c = lcol[u];
+                auto rank4 = [&](int w) {
+                    const int4 q = *reinterpret_cast<const int4 *>(lcol + w);
+                    return (q.x < c) + (w + 1 < n && q.y < c) + (w + 2 < n && q.z < c) +
+                           (w + 3 < n && q.w < c);
+                };
+                int r = 0;
+                if constexpr (HC >= 64) {
+                    // long lists: more reads in flight (small tables keep the
+                    // registers for occupancy)
+#pragma unroll 4
+                    for (int w = 0; w < n; w += 4) r += rank4(w);
+                } else {
+                    for (int w = 0; w < n; w += 4) r += rank4(w);
+                }
+                tcj[o + r] = c;
+                tcx[o + r] = val[lslot[u]];
+            }
         }
         if (lane == 0) cnt[i] = n;
         wave_lds_sync();
