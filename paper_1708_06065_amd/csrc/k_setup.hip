@@ -3181,6 +3181,9 @@ __device__ __forceinline__ int gemm_hash(int32_t col, int bits) {
 template <int HS>
 constexpr int log2_const() { return HS <= 1 ? 0 : 1 + log2_const<HS / 2>(); }
 
+// Eight waves per SIMD asked for: the ranking below holds up to four columns
+// per lane, whose scalar registers would otherwise lower the occupancy of the
+// tables that fit eight (a few scalars then live in vector lanes).
 template <int T, int HS, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
 k_spgemm_hacc(int32_t m, RowSrc src, const int32_t *ap, const int32_t *aj, const double *ax,
