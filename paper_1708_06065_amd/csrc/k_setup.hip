@@ -2886,6 +2886,88 @@ void launch_interp_direct(int32_t n, const int32_t *rp, const int32_t *cj,
     LAIR_LAUNCH_CHECK();
 }
 
+// The strength of k_strength and the counting pass of k_interp_direct in one
+// pass over each row, for a splitting known beforehand: the team shape, the
+// loop over the row and the team sums are those of k_interp_direct, so cnt
+// and coef are its values bit for bit (the strength does not depend on the
+// team: a maximum and comparisons).
+template <int T>
+__global__ void __launch_bounds__(256)
+k_strength_interp(int32_t n, const int32_t *rp, const int32_t *cj, const double *v,
+                  double theta, int32_t kind, const int8_t *cf, uint8_t *smask,
+                  int32_t *cnt, double *coef) {
+    int64_t gt = xcd_block_id() * blockDim.x + threadIdx.x;
+    int32_t i = (int32_t)(gt / T);
+    int lane = (int)(gt % T);
+    if (i >= n) return;
+    const int lo = rp[i], hi = rp[i + 1];
+    double m = 0.0;
+    for (int p = lo + lane; p < hi; p += T)
+        if (cj[p] != i) m = fmax(m, fabs(v[p]));
+    m = team_max<T>(m);
+    const double thr = theta * m;
+    const bool frow = cf[i] != 1;
+    double diag = 0.0, sn = 0.0, sp = 0.0, pn = 0.0, pp = 0.0;
+    int k = 0;
+    for (int p = lo + lane; p < hi; p += T) {
+        const int j = cj[p];
+        const double a = v[p];
+        const bool st = (j != i) && (a != 0.0) && (m > 0.0) &&
+                        (((kind == LAIR_SOC_NEG) ? -a : fabs(a)) >= thr);
+        smask[p] = st ? 1 : 0;
+        if (!frow) continue;
+        if (j == i) { diag = a; continue; }
+        if (a < 0.0) sn += a; else sp += a;
+        if (st && cf[j] == 1) {
+            if (a < 0.0) pn += a; else pp += a;
+            ++k;
+        }
+    }
+    if (!frow) {
+        if (lane == 0) cnt[i] = 1;
+        return;
+    }
+    diag = team_sum<T>(diag);
+    sn = team_sum<T>(sn);
+    sp = team_sum<T>(sp);
+    pn = team_sum<T>(pn);
+    pp = team_sum<T>(pp);
+    k = team_sum_int<T>(k);
+    double d = diag;
+    if (pn == 0.0) d += sn;
+    if (pp == 0.0) d += sp;
+    const bool empty = (k == 0 || d == 0.0);
+    if (lane == 0) {
+        cnt[i] = empty ? 0 : k;
+        coef[3 * (int64_t)i] = (pn != 0.0) ? sn / pn : 0.0;
+        coef[3 * (int64_t)i + 1] = (pp != 0.0) ? sp / pp : 0.0;
+        coef[3 * (int64_t)i + 2] = empty ? 0.0 : d;
+    }
+}
+
+void launch_strength_interp(int32_t n, const int32_t *rp, const int32_t *cj,
+                            const double *v, double theta, int32_t kind, const int8_t *cf,
+                            uint8_t *smask, int32_t *cnt, double *coef, double mean_len,
+                            hipStream_t s) {
+    if (n == 0) return;
+    // the team of launch_interp_direct
+    int t = team_for_mean(mean_len);
+    if (t > 16) t = 16;
+    const double nnz = mean_len * n;
+    ProfScope ps("strength", s, 13.0 * nnz + 4.0 * (n + 1) + 1.0 * n + 16.0 * n);
+#define LAIR_SI(TT)                                                                      \
+    LAIR_LAUNCH(k_strength_interp<TT>, dim3(blocks_for((int64_t)n * TT, 256)), dim3(256), \
+                0, s, n, rp, cj, v, theta, kind, cf, smask, cnt, coef)
+    switch (t) {
+        case 2: LAIR_SI(2); break;
+        case 4: LAIR_SI(4); break;
+        case 8: LAIR_SI(8); break;
+        default: LAIR_SI(16); break;
+    }
+#undef LAIR_SI
+    LAIR_LAUNCH_CHECK();
+}
+
 // ===========================================================================
 // Lumping of a coarse operator (Sec. 3.3 and the caption of its filtering
 // table): in row i, an off-diagonal entry with |k_ij| < theta_D max_j |k_ij|

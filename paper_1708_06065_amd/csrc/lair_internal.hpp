@@ -254,6 +254,14 @@ int32_t validate_csr(int64_t n, int64_t nnz, const int32_t *rp,
 void launch_strength(int32_t n, const int32_t *rp, const int32_t *cj,
                      const double *v, double theta, int32_t kind,
                      uint8_t *smask, double mean_len, hipStream_t s);
+// launch_strength and, on the same reads of each row, the counting pass of
+// launch_interp_direct (cnt, coef: the same values, bit for bit), for a
+// splitting cf known before the strength (the counting pass then need not
+// read the matrix again).
+void launch_strength_interp(int32_t n, const int32_t *rp, const int32_t *cj,
+                            const double *v, double theta, int32_t kind, const int8_t *cf,
+                            uint8_t *smask, int32_t *cnt, double *coef, double mean_len,
+                            hipStream_t s);
 // cidx, C and F row lists; acc[0] += nnz of F rows, acc[1] += nnz of C rows
 void launch_cf_lists(int32_t n, const int8_t *cf, const int32_t *cidx_scan,
                      const int32_t *rp, int32_t *cidx, int32_t *clist,

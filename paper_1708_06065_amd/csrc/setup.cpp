@@ -457,14 +457,9 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
                  "the same whole dense blocks", lvl);
     }
     Lv.smask.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
-    if (nod)
-        launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), A.nnz, h->str.theta,
-                             Lv.smask.get(), s);
-    else
-        launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta, h->str.kind,
-                        Lv.smask.get(), mean, s);
     Lv.cf.alloc((size_t)n, s);
-    if (cfl && lvl < cfl->nlevels) {
+    const bool given = cfl && lvl < cfl->nlevels;
+    if (given) {
         int64_t lo = cfl->offs[lvl], hi = cfl->offs[lvl + 1];
         if (hi - lo != n)
             fail(LAIR_EINVAL, "CF splitting of level %d has %lld entries, level size is %d",
@@ -472,6 +467,28 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         // the splittings were uploaded (and checked) at the start of setup
         LAIR_HIP(hipMemcpyAsync(Lv.cf.get(), h->cf_dev.get() + lo, (size_t)n,
                                 hipMemcpyDeviceToDevice, s));
+    }
+    // a given splitting of one system (not changed after the strength) lets
+    // the strength pass also take the counting pass of direct interpolation
+    const bool strength_interp = given && !nod && h->nsys == 1 &&
+                                 h->opt.interp == LAIR_P_DIRECT;
+    DevArr<int32_t> pc_early;
+    DevArr<double> coef_early;
+    if (nod) {
+        launch_node_strength(n, kb, A.rp.get(), A.cj.get(), A.v.get(), A.nnz, h->str.theta,
+                             Lv.smask.get(), s);
+    } else if (strength_interp) {
+        pc_early.alloc((size_t)n, s);
+        coef_early.alloc(3 * (size_t)std::max(n, 1), s);
+        launch_strength_interp(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta,
+                               h->str.kind, Lv.cf.get(), Lv.smask.get(), pc_early.get(),
+                               coef_early.get(), mean, s);
+    } else {
+        launch_strength(n, A.rp.get(), A.cj.get(), A.v.get(), h->str.theta, h->str.kind,
+                        Lv.smask.get(), mean, s);
+    }
+    if (given) {
+        // copied above, before the strength pass
     } else if (h->opt.flags & LAIR_FLAG_PMIS) {
         // the parallel splitting on the device
         const uint8_t *sm_dev = Lv.smask.get();
@@ -722,10 +739,14 @@ static void build_level_transfer(lair_hierarchy *h, Level &Lv, int32_t lvl,
         launch_compact_one_point(n, pcol.get(), P.rp.get(), P.cj.get(), P.v.get(), s);
     } else {
         DevArr<int32_t> pc;
-        pc.alloc((size_t)n, s);
         DevArr<double> coef;
-        coef.alloc(3 * (size_t)std::max(n, 1), s);
-        {
+        if (strength_interp) {
+            // counted by the strength pass
+            pc = std::move(pc_early);
+            coef = std::move(coef_early);
+        } else {
+            pc.alloc((size_t)n, s);
+            coef.alloc(3 * (size_t)std::max(n, 1), s);
             ProfScope ps("interp", s, 6.0 * A.nnz + 9.0 * n);
             launch_interp_direct(n, A.rp.get(), A.cj.get(), A.v.get(), Lv.smask.get(),
                                  Lv.cf.get(), Lv.cidx.get(), false, pc.get(), nullptr, nullptr,
