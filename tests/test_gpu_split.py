@@ -122,3 +122,31 @@ def test_split_levels_export_natural(lair):
     xo, ito, _ = O.solve(H, w["rhs"], rtol=1e-10)
     assert info["iters"] == ito
     assert np.abs(x.cpu().numpy() - xo).max() <= 1e-9 * np.abs(xo).max()
+
+
+@pytest.mark.parametrize("ordering", ["auto", "split"])
+def test_copies_behind_readbacks_equal_copies_at_the_end(lair, ordering):
+    """The split-ordered copies are queued behind the setup's readbacks, level
+    by level as their inputs appear; with the profiler on they are all made
+    at the end of setup instead.  The two hierarchies must solve alike, bit
+    for bit (the profiler also runs the cycles without graphs, which the
+    graph tests pin to the captured cycles).  48^3, 16 right-hand sides,
+    lumped, mixed precision: the timed configuration at a smaller size."""
+    _say("case: copies behind readbacks vs at the end,", ordering)
+    w = W.implicit_euler_adr_3d(m=48, nrhs=16)
+    kw = dict(interp="direct", precision="mixed", lump_tol=1e-3, ordering=ordering)
+    b = _dev(w["rhs"])
+    hq = lair.setup(w["rowptr"], w["col"], w["val"], **kw)
+    xq, iq = hq.solve(b, rtol=1e-10)
+    lair.profile_begin(None)
+    try:
+        he = lair.setup(w["rowptr"], w["col"], w["val"], **kw)
+        xe, ie = he.solve(b, rtol=1e-10)
+    finally:
+        lair.profile_end()
+    _say("  levels", hq.nlevels, he.nlevels, "iterations", iq["iters"], ie["iters"])
+    assert hq.nlevels == he.nlevels
+    assert iq["converged"] and iq["iters"] == ie["iters"]
+    assert np.array_equal(xq.cpu().numpy(), xe.cpu().numpy())
+    hq.free()
+    he.free()
